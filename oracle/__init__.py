@@ -1,0 +1,206 @@
+"""FP64 CPU oracle for the batched lens log-likelihood (test infrastructure).
+
+Only the tests, the smoke check and the CPU-baseline leg of ``bench.py`` use
+this package.  The GPU library never imports it; the two share no code.  The
+arithmetic lives in ``lens_oracle.c`` (plain C, FP64, libm, OpenMP across
+proposals); this module only marshals numpy arrays through ctypes.
+
+``Oracle(path)`` binds one compiled copy of the C file, so that tests can also
+load deliberately broken copies (planted mistakes) and check that the pins
+catch them.  The module-level functions use the default build.
+
+Sections and equations cited refer to Cao et al. (2025), "CSST Strong Lensing
+Preparation: Fast Modelling of Galaxy-Galaxy Strong Lenses in the Big Data Era".
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(_HERE, "lens_oracle.c")
+LIB_PATH = os.path.join(_HERE, "liblens_oracle.so")
+NPARAM_STRIDE = 20
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+def compile_oracle(src: str, out: str) -> str:
+    """gcc the oracle source ``src`` into the shared library ``out``."""
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-D_GNU_SOURCE", "-fopenmp", "-ffp-contract=off",
+           "-fPIC", "-shared", "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def build(force: bool = True) -> str:
+    """Compile lens_oracle.c into liblens_oracle.so next to it."""
+    if force or not os.path.exists(LIB_PATH):
+        compile_oracle(SRC, LIB_PATH)
+    return LIB_PATH
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _ptr(a, t=_dp):
+    return a.ctypes.data_as(t)
+
+
+class Oracle:
+    """ctypes view of one compiled oracle library."""
+
+    def __init__(self, path: str = LIB_PATH):
+        if path == LIB_PATH and not os.path.exists(path):
+            build(force=False)
+        lib = ctypes.CDLL(path)
+        d, i, i64 = ctypes.c_double, ctypes.c_int, ctypes.c_int64
+        sig = {
+            "oracle_gammainc_lower_reg": ([d, d], d),
+            "oracle_bn": ([d], d),
+            "oracle_sersic": ([d] * 10, d),
+            "oracle_sie_deflection": ([d] * 7 + [_dp, _dp], None),
+            "oracle_shear_deflection": ([d, d, d, d, _dp, _dp], None),
+            "oracle_deflection": ([_dp, d, d, _dp, _dp], None),
+            "oracle_params_valid": ([_dp], i),
+            "oracle_subpixel_xy": ([i, i, d, i, i, i, i, i, _dp, _dp], None),
+            "oracle_convolve_same": ([_dp, i, i, _dp, i, _dp], None),
+            "oracle_model_image": ([i, i, d, i, i, _dp, _dp, i, _dp], i),
+            "oracle_loglike_norm": ([i64, _dp, _u8p], d),
+            "oracle_loglike": ([i, i, d, i, i, _dp, _dp, _dp, _u8p, _dp, i64, _dp, _dp, i], i),
+            "oracle_num_threads": ([], i),
+        }
+        for name, (args, res) in sig.items():
+            fn = getattr(lib, name)
+            fn.argtypes = args
+            fn.restype = res
+        self.lib = lib
+        self.path = path
+
+    # -- scalar pieces -------------------------------------------------------
+    def gammainc_lower_reg(self, a: float, x: float) -> float:
+        """Regularised lower incomplete gamma P(a, x) (enters Sec. 2.4, Eq. 9)."""
+        return self.lib.oracle_gammainc_lower_reg(float(a), float(x))
+
+    def bn(self, n: float) -> float:
+        """Sersic b_n: the root of Gamma(2n) = 2 gamma(2n, b_n) (Sec. 2.4, Eq. 9)."""
+        return self.lib.oracle_bn(float(n))
+
+    def sersic(self, I_e, R_e, n, b_n, q, phi, xc, yc, x, y) -> float:
+        """Elliptical Sersic surface brightness at (x, y) (Sec. 2.4, Eqs. 8, 10)."""
+        return self.lib.oracle_sersic(*[float(v) for v in (I_e, R_e, n, b_n, q, phi, xc, yc, x, y)])
+
+    def sie_deflection(self, theta_E, q, phi, xm, ym, x, y):
+        """SIE deflection (Sec. 2.4: elliptical power law at slope 2) at one point."""
+        ax, ay = ctypes.c_double(), ctypes.c_double()
+        self.lib.oracle_sie_deflection(float(theta_E), float(q), float(phi), float(xm), float(ym),
+                                       float(x), float(y), ctypes.byref(ax), ctypes.byref(ay))
+        return ax.value, ay.value
+
+    def shear_deflection(self, g1, g2, x, y):
+        """External-shear deflection (Sec. 2.4, Eqs. 13-14) at one point."""
+        ax, ay = ctypes.c_double(), ctypes.c_double()
+        self.lib.oracle_shear_deflection(float(g1), float(g2), float(x), float(y),
+                                         ctypes.byref(ax), ctypes.byref(ay))
+        return ax.value, ay.value
+
+    def deflection(self, params, x, y):
+        """SIE + shear deflection of one proposal at one point."""
+        p = _f64(params)
+        assert p.size >= 19
+        ax, ay = ctypes.c_double(), ctypes.c_double()
+        self.lib.oracle_deflection(_ptr(p), float(x), float(y), ctypes.byref(ax), ctypes.byref(ay))
+        return ax.value, ay.value
+
+    def params_valid(self, params) -> bool:
+        p = _f64(params)
+        return bool(self.lib.oracle_params_valid(_ptr(p)))
+
+    def subpixel_xy(self, ny, nx, dpix, s, i, j, v, u):
+        """Image-plane position of sub-pixel (v, u) of pixel (i, j)."""
+        x, y = ctypes.c_double(), ctypes.c_double()
+        self.lib.oracle_subpixel_xy(ny, nx, float(dpix), s, i, j, v, u, ctypes.byref(x), ctypes.byref(y))
+        return x.value, y.value
+
+    # -- images ----------------------------------------------------------------
+    def convolve_same(self, img, psf):
+        """Zero-padded 'same' true convolution (Sec. 2.1, Eq. 3)."""
+        img = _f64(img)
+        psf = _f64(psf)
+        ny, nx = img.shape
+        k = psf.shape[0]
+        assert psf.shape == (k, k) and k % 2 == 1
+        out = np.empty_like(img)
+        self.lib.oracle_convolve_same(_ptr(img), ny, nx, _ptr(psf), k, _ptr(out))
+        return out
+
+    def model_image(self, ny, nx, dpix, s, psf, params, stage=1):
+        """Model image of one proposal: stage 0 binned, 1 convolved, 2 supersampled."""
+        psf = _f64(psf)
+        k = psf.shape[0]
+        p = _f64(params).reshape(-1)
+        if p.size == 19:
+            p = np.concatenate([p, [0.0]])
+        shape = (ny * s, nx * s) if stage == 2 else (ny, nx)
+        out = np.empty(shape, dtype=np.float64)
+        rc = self.lib.oracle_model_image(ny, nx, float(dpix), s, k, _ptr(psf), _ptr(p), stage, _ptr(out))
+        if rc == -2:
+            raise ValueError("proposal outside the parameter domain")
+        if rc != 0:
+            raise ValueError("bad argument to oracle_model_image")
+        return out
+
+    # -- likelihood --------------------------------------------------------------
+    def loglike_norm(self, sigma, mask) -> float:
+        """C = -1/2 sum over the mask of ln(2 pi sigma^2) (Sec. 2.2, Eq. 5)."""
+        sigma = _f64(sigma).reshape(-1)
+        mask = np.ascontiguousarray(mask, dtype=np.uint8).reshape(-1)
+        return self.lib.oracle_loglike_norm(sigma.size, _ptr(sigma), _ptr(mask, _u8p))
+
+    def loglike(self, geom, psf, data, sigma, mask, params, nthreads=0, return_chi2=False):
+        """lnL of every proposal row of ``params`` ([n, 20] float64), Sec. 2.2, Eq. 5.
+
+        ``geom`` is (ny, nx, pixel_scale, supersample)."""
+        ny, nx, dpix, s = geom
+        psf = _f64(psf)
+        k = psf.shape[0]
+        data = _f64(data)
+        sigma = _f64(sigma)
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert data.shape == (ny, nx) and sigma.shape == (ny, nx) and mask.shape == (ny, nx)
+        p = _f64(params).reshape(-1, NPARAM_STRIDE)
+        n = p.shape[0]
+        out = np.empty(n, dtype=np.float64)
+        chi2 = np.empty(n, dtype=np.float64)
+        rc = self.lib.oracle_loglike(ny, nx, float(dpix), s, k, _ptr(psf), _ptr(data), _ptr(sigma),
+                                     _ptr(mask, _u8p), _ptr(p), n, _ptr(out), _ptr(chi2), int(nthreads))
+        if rc != 0:
+            raise ValueError("bad argument to oracle_loglike")
+        return (out, chi2) if return_chi2 else out
+
+    def num_threads(self) -> int:
+        return self.lib.oracle_num_threads()
+
+
+_default = None
+
+
+def default() -> Oracle:
+    global _default
+    if _default is None:
+        _default = Oracle(LIB_PATH)
+    return _default
+
+
+def __getattr__(name):
+    # module-level access to the default oracle's methods: oracle.bn(...), oracle.loglike(...)
+    if name.startswith("_"):
+        raise AttributeError(name)
+    return getattr(default(), name)

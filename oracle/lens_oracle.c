@@ -1,0 +1,358 @@
+/*
+ * lens_oracle.c -- plain FP64 CPU oracle for the batched lens log-likelihood.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * definition that the GPU path is checked against.  It is called only from
+ * tests/, from the smoke check and from the CPU-baseline leg of bench.py.
+ * It shares no code, header, table or constant with the GPU library, and the
+ * GPU library never calls it.
+ *
+ * What it computes (Cao et al. 2025, "CSST Strong Lensing Preparation: Fast
+ * Modelling of Galaxy-Galaxy Strong Lenses in the Big Data Era"):
+ *   - lens equation beta = theta - alpha(theta)               (Sec. 2.1, Eq. 1)
+ *   - image = lens light at theta + source light at beta       (Sec. 2.1, Eq. 2)
+ *   - s x s supersampling, binned by the pixel mean            (Sec. 2.1, text after Eq. 2)
+ *   - PSF convolution of the binned image                       (Sec. 2.1, Eq. 3)
+ *   - Gaussian pixel likelihood over the fitting region         (Sec. 2.2, Eq. 5; mask: App. A)
+ *   - elliptical Sersic light                                   (Sec. 2.4, Eqs. 8-10)
+ *   - SIE mass = elliptical power law at slope 2                (Sec. 2.4, Eq. 12 and text)
+ *   - external shear                                            (Sec. 2.4, Eqs. 13-14)
+ *
+ * Everything is FP64, scalar loops, libm only, on the full supersampled grid
+ * (no skipping outside the mask), with a full-image direct convolution.
+ *
+ * Readings where the paper is silent (each one is listed in the design notes):
+ *   R1  SIE convergence kappa = theta_E / (2 R_p) with the paper's elliptical
+ *       radius R_p = sqrt(q x1^2 + x2^2/q) of Eq. 10; its deflection is the
+ *       closed form of Kormann et al. (1994) rewritten for this normalisation.
+ *   R2  q = 1 uses the circular form alpha = theta_E x/|x|; alpha = 0 at the
+ *       mass centre.
+ *   R3  shear follows the sign printed in Eq. 13,
+ *       psi = -1/2 [g1 (x^2 - y^2) + 2 g2 x y], so
+ *       alpha_sh = -(g1 x + g2 y, g2 x - g1 y), with origin at (0, 0).
+ *   R5  position angles are counter-clockwise from +x1 (the rotation in
+ *       Eq. 10); x1 grows with the column index, x2 with the row index.
+ *   R6  the image centre is at pixel ((nx-1)/2, (ny-1)/2).
+ *   R7  sub-pixels are the centres of an s x s equal split of each pixel; the
+ *       binned value is their arithmetic mean; lens light is supersampled too.
+ *   R8  lens light centre = mass centre (Table 1).
+ *   R9  b_n is the exact root of Gamma(2n) = 2 gamma(2n, b_n) (Eq. 9).
+ *   R11 the PSF is a true convolution (kernel flipped), k odd, centred at
+ *       (k-1)/2, zero outside the image, output of the image's size.
+ *   R12 supersample -> bin -> convolve.
+ *   R13 lnL = -1/2 chi^2 - 1/2 sum_mask ln(2 pi sigma^2), sums over the mask.
+ *
+ * Parameter vector of one proposal: 20 doubles (slot 19 unused, must be 0):
+ *   0 theta_E  1 q_m  2 phi_m  3 x_m  4 y_m  5 g1  6 g2
+ *   7 I_l  8 R_l  9 n_l  10 q_l  11 phi_l
+ *   12 I_s 13 R_s 14 n_s 15 q_s 16 phi_s 17 x_s 18 y_s
+ * Angles in radians, positions and radii in arcsec.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_NP 20
+
+/* ------------------------------------------------------------------------ */
+/* Regularised lower incomplete gamma P(a, x) = gamma(a, x) / Gamma(a).      */
+/* Series for x < a + 1, continued fraction for Q = 1 - P otherwise          */
+/* (the standard pair of expansions, e.g. Numerical Recipes 3rd ed. 6.2).    */
+/* ------------------------------------------------------------------------ */
+static double orc_gser(double a, double x)
+{
+    /* P(a,x) = e^{-x} x^a / Gamma(a+1) * sum_{k>=0} x^k / ((a+1)...(a+k)) */
+    double term = 1.0, sum = 1.0, ap = a;
+    for (int k = 1; k < 100000; ++k) {
+        ap += 1.0;
+        term *= x / ap;
+        sum += term;
+        if (term < sum * 1e-17) break;
+    }
+    return sum * exp(a * log(x) - x - lgamma(a + 1.0));
+}
+
+static double orc_gcf(double a, double x)
+{
+    /* Q(a,x) by the modified Lentz evaluation of the Legendre continued fraction */
+    const double tiny = 1e-300;
+    double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
+    for (int i = 1; i < 100000; ++i) {
+        double an = -i * (i - a);
+        b += 2.0;
+        d = an * d + b;
+        if (fabs(d) < tiny) d = tiny;
+        c = b + an / c;
+        if (fabs(c) < tiny) c = tiny;
+        d = 1.0 / d;
+        double del = d * c;
+        h *= del;
+        if (fabs(del - 1.0) < 1e-16) break;
+    }
+    return exp(a * log(x) - x - lgamma(a)) * h;
+}
+
+double oracle_gammainc_lower_reg(double a, double x)
+{
+    if (!(a > 0.0) || !(x >= 0.0)) return NAN;
+    if (x == 0.0) return 0.0;
+    if (x < a + 1.0) return orc_gser(a, x);
+    return 1.0 - orc_gcf(a, x);
+}
+
+/* b_n: root of P(2n, b) = 1/2 (Sec. 2.4, Eq. 9), by plain bisection to the
+ * last bit.  P is increasing in b, P(2n, 0) = 0 and P(2n, 2n + 1) > 1/2. */
+double oracle_bn(double n)
+{
+    if (!(n > 0.0) || !isfinite(n)) return NAN;
+    double a = 2.0 * n, lo = 0.0, hi = a + 1.0;
+    while (oracle_gammainc_lower_reg(a, hi) < 0.5) hi *= 2.0;
+    for (int it = 0; it < 2000; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (mid <= lo || mid >= hi) break;
+        if (oracle_gammainc_lower_reg(a, mid) < 0.5) lo = mid; else hi = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Light: elliptical Sersic (Sec. 2.4, Eqs. 8 and 10)                        */
+/* ------------------------------------------------------------------------ */
+double oracle_sersic(double I_e, double R_e, double n, double b_n, double q,
+                     double phi, double xc, double yc, double x, double y)
+{
+    double dx = x - xc, dy = y - yc;
+    double x1 = dx * cos(phi) + dy * sin(phi);       /* Eq. 10, first row  */
+    double x2 = -dx * sin(phi) + dy * cos(phi);      /* Eq. 10, second row */
+    double R = sqrt(x1 * x1 * q + x2 * x2 / q);      /* Eq. 10, third row  */
+    return I_e * exp(-b_n * (pow(R / R_e, 1.0 / n) - 1.0));   /* Eq. 8 */
+}
+
+/* ------------------------------------------------------------------------ */
+/* Mass: SIE (reading R1/R2) and external shear (reading R3)                 */
+/* ------------------------------------------------------------------------ */
+void oracle_sie_deflection(double theta_E, double q, double phi, double xm,
+                           double ym, double x, double y, double *ax, double *ay)
+{
+    double dx = x - xm, dy = y - ym;
+    double c = cos(phi), s = sin(phi);
+    double x1 = c * dx + s * dy;          /* frame of the mass ellipse (Eq. 10) */
+    double x2 = -s * dx + c * dy;
+    double a1, a2;
+    if (x1 == 0.0 && x2 == 0.0) { *ax = 0.0; *ay = 0.0; return; }
+    if (q == 1.0) {
+        double r = sqrt(x1 * x1 + x2 * x2);
+        a1 = theta_E * x1 / r;
+        a2 = theta_E * x2 / r;
+    } else {
+        double e = sqrt(1.0 - q * q);
+        double psi = sqrt(q * q * x1 * x1 + x2 * x2);
+        double b = theta_E * sqrt(q);
+        a1 = b / e * atan(e * x1 / psi);
+        a2 = b / e * atanh(e * x2 / psi);
+    }
+    *ax = c * a1 - s * a2;                /* rotate back to the image frame */
+    *ay = s * a1 + c * a2;
+}
+
+void oracle_shear_deflection(double g1, double g2, double x, double y,
+                             double *ax, double *ay)
+{
+    /* gradient of psi = -1/2 [g1 (x^2 - y^2) + 2 g2 x y]  (Eq. 13 with Eq. 14) */
+    *ax = -(g1 * x + g2 * y);
+    *ay = -(g2 * x - g1 * y);
+}
+
+/* Total deflection of one proposal at (x, y). */
+void oracle_deflection(const double *p, double x, double y, double *ax, double *ay)
+{
+    double sx, sy, hx, hy;
+    oracle_sie_deflection(p[0], p[1], p[2], p[3], p[4], x, y, &sx, &sy);
+    oracle_shear_deflection(p[5], p[6], x, y, &hx, &hy);
+    *ax = sx + hx;
+    *ay = sy + hy;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Proposal domain                                                           */
+/* ------------------------------------------------------------------------ */
+#define ORC_N_MIN 0.1
+#define ORC_N_MAX 20.0
+
+int oracle_params_valid(const double *p)
+{
+    for (int i = 0; i < 19; ++i)
+        if (!isfinite(p[i])) return 0;
+    if (p[0] < 0.0) return 0;
+    const int qs[3] = {1, 10, 15};
+    for (int i = 0; i < 3; ++i)
+        if (!(p[qs[i]] > 0.0 && p[qs[i]] <= 1.0)) return 0;
+    if (!(p[8] > 0.0) || !(p[13] > 0.0)) return 0;
+    if (!(p[9] >= ORC_N_MIN && p[9] <= ORC_N_MAX)) return 0;
+    if (!(p[14] >= ORC_N_MIN && p[14] <= ORC_N_MAX)) return 0;
+    return 1;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Image grid (readings R6, R7)                                              */
+/* ------------------------------------------------------------------------ */
+void oracle_subpixel_xy(int ny, int nx, double dpix, int s, int i, int j,
+                        int v, int u, double *x, double *y)
+{
+    *x = ((double)j - 0.5 * (nx - 1) + ((double)u + 0.5) / s - 0.5) * dpix;
+    *y = ((double)i - 0.5 * (ny - 1) + ((double)v + 0.5) / s - 0.5) * dpix;
+}
+
+/* Surface brightness of the lensed scene at one image-plane point (Eq. 2). */
+static double orc_scene(const double *p, double bl, double bs, double x, double y)
+{
+    double ax, ay;
+    oracle_deflection(p, x, y, &ax, &ay);
+    double bx = x - ax, by = y - ay;                                   /* Eq. 1 */
+    double lens = oracle_sersic(p[7], p[8], p[9], bl, p[10], p[11], p[3], p[4], x, y);
+    double src = oracle_sersic(p[12], p[13], p[14], bs, p[15], p[16], p[17], p[18], bx, by);
+    return lens + src;
+}
+
+/* 'same'-size true convolution with zero padding (Eq. 3, reading R11):
+ *   out[i][j] = sum_{a,b} K[a][b] * img[i + r - a][j + r - b],  r = (k-1)/2 */
+void oracle_convolve_same(const double *img, int ny, int nx, const double *psf,
+                          int k, double *out)
+{
+    int r = (k - 1) / 2;
+    for (int i = 0; i < ny; ++i)
+        for (int j = 0; j < nx; ++j) {
+            double acc = 0.0;
+            for (int a = 0; a < k; ++a) {
+                int ii = i + r - a;
+                if (ii < 0 || ii >= ny) continue;
+                for (int b = 0; b < k; ++b) {
+                    int jj = j + r - b;
+                    if (jj < 0 || jj >= nx) continue;
+                    acc += psf[a * k + b] * img[ii * nx + jj];
+                }
+            }
+            out[i * nx + j] = acc;
+        }
+}
+
+static int orc_geom_ok(int ny, int nx, double dpix, int s, int k)
+{
+    return ny > 0 && nx > 0 && s > 0 && k > 0 && (k & 1) && dpix > 0.0 && isfinite(dpix);
+}
+
+/* Model image of one proposal.
+ *   stage 0: binned, unconvolved          [ny][nx]
+ *   stage 1: binned and PSF-convolved     [ny][nx]
+ *   stage 2: the supersampled grid        [ny*s][nx*s], fine row i*s+v, col j*s+u
+ * Returns 0 on success, -1 on a bad argument, -2 for a proposal outside the
+ * domain (out is then untouched). */
+int oracle_model_image(int ny, int nx, double dpix, int s, int k, const double *psf,
+                       const double *p, int stage, double *out)
+{
+    if (!orc_geom_ok(ny, nx, dpix, s, k) || !p || !out) return -1;
+    if (stage == 1 && !psf) return -1;
+    if (stage < 0 || stage > 2) return -1;
+    if (!oracle_params_valid(p)) return -2;
+    double bl = oracle_bn(p[9]), bs = oracle_bn(p[14]);
+    if (stage == 2) {
+        int fx = nx * s;
+        for (int i = 0; i < ny; ++i)
+            for (int v = 0; v < s; ++v)
+                for (int j = 0; j < nx; ++j)
+                    for (int u = 0; u < s; ++u) {
+                        double x, y;
+                        oracle_subpixel_xy(ny, nx, dpix, s, i, j, v, u, &x, &y);
+                        out[(i * s + v) * fx + j * s + u] = orc_scene(p, bl, bs, x, y);
+                    }
+        return 0;
+    }
+    double *img = (double *)malloc(sizeof(double) * (size_t)ny * nx);
+    if (!img) return -1;
+    for (int i = 0; i < ny; ++i)
+        for (int j = 0; j < nx; ++j) {
+            double acc = 0.0;
+            for (int v = 0; v < s; ++v)
+                for (int u = 0; u < s; ++u) {
+                    double x, y;
+                    oracle_subpixel_xy(ny, nx, dpix, s, i, j, v, u, &x, &y);
+                    acc += orc_scene(p, bl, bs, x, y);
+                }
+            img[i * nx + j] = acc / ((double)s * s);
+        }
+    if (stage == 0) memcpy(out, img, sizeof(double) * (size_t)ny * nx);
+    else oracle_convolve_same(img, ny, nx, psf, k, out);
+    free(img);
+    return 0;
+}
+
+/* C = -1/2 sum_mask ln(2 pi sigma^2), the likelihood's normalisation (Eq. 5). */
+double oracle_loglike_norm(int64_t npix, const double *sigma, const uint8_t *mask)
+{
+    double c = 0.0;
+    for (int64_t i = 0; i < npix; ++i)
+        if (mask[i]) c += -0.5 * log(2.0 * M_PI * sigma[i] * sigma[i]);
+    return c;
+}
+
+/* lnL of n proposals (Eq. 5 over the fitting region).  out_chi2 may be NULL.
+ * Proposals outside the domain give lnL = -inf and chi2 = +inf.
+ * nthreads <= 0 uses the OpenMP default.  Returns 0, or -1 on a bad argument. */
+int oracle_loglike(int ny, int nx, double dpix, int s, int k, const double *psf,
+                   const double *data, const double *sigma, const uint8_t *mask,
+                   const double *params, int64_t n, double *out, double *out_chi2,
+                   int nthreads)
+{
+    if (!orc_geom_ok(ny, nx, dpix, s, k) || !psf || !data || !sigma || !mask ||
+        (n > 0 && (!params || !out)) || n < 0)
+        return -1;
+    int64_t npix = (int64_t)ny * nx;
+    for (int64_t i = 0; i < npix; ++i)
+        if (mask[i] && !(sigma[i] > 0.0 && isfinite(sigma[i]) && isfinite(data[i]))) return -1;
+    double C = oracle_loglike_norm(npix, sigma, mask);
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads) reduction(| : bad)
+#endif
+    {
+        double *m = (double *)malloc(sizeof(double) * (size_t)npix);
+        if (!m) bad = 1;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int64_t t = 0; t < n; ++t) {
+            if (!m) continue;
+            const double *p = params + t * ORC_NP;
+            if (!oracle_params_valid(p)) {
+                out[t] = -INFINITY;
+                if (out_chi2) out_chi2[t] = INFINITY;
+                continue;
+            }
+            oracle_model_image(ny, nx, dpix, s, k, psf, p, 1, m);
+            double chi2 = 0.0;
+            for (int64_t i = 0; i < npix; ++i)
+                if (mask[i]) {
+                    double r = (data[i] - m[i]) / sigma[i];
+                    chi2 += r * r;
+                }
+            out[t] = C - 0.5 * chi2;
+            if (out_chi2) out_chi2[t] = chi2;
+        }
+        free(m);
+    }
+    return bad ? -1 : 0;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,69 @@
+"""Planted mistakes in copies of the oracle must each fail at least one pin.
+
+Each mutant is the oracle's C source with one plausible slip (a sign, a
+dropped term, a transposed index, a misplaced offset) rebuilt in a temporary
+directory; the real oracle source is never touched.  Passing here shows that
+the pins in oracle_pins.py constrain every step of the computation.
+"""
+import os
+
+import pytest
+
+import oracle
+import oracle_pins
+
+MUTANTS = {
+    "shear_sign": [("*ax = -(g1 * x + g2 * y);", "*ax = (g1 * x + g2 * y);"),
+                   ("*ay = -(g2 * x - g1 * y);", "*ay = (g2 * x - g1 * y);")],
+    "psf_not_flipped": [("int ii = i + r - a;", "int ii = i - r + a;"),
+                        ("int jj = j + r - b;", "int jj = j - r + b;")],
+    "psf_periodic_edges": [("if (ii < 0 || ii >= ny) continue;", "ii = (ii + ny) % ny;"),
+                           ("if (jj < 0 || jj >= nx) continue;", "jj = (jj + nx) % nx;")],
+    "subpixel_offset": [("((double)u + 0.5) / s - 0.5", "(double)u / s - 0.5"),
+                        ("((double)v + 0.5) / s - 0.5", "(double)v / s - 0.5")],
+    "bin_sum_not_mean": [("acc / ((double)s * s)", "acc / (double)s")],
+    "drop_normalisation": [("out[t] = C - 0.5 * chi2;", "out[t] = -0.5 * chi2;")],
+    "chi2_whole_image": [("if (mask[i]) {\n                    double r", "{\n                    double r")],
+    "sie_normalisation": [("double b = theta_E * sqrt(q);", "double b = theta_E;")],
+    "sie_axes_swapped": [("sqrt(q * q * x1 * x1 + x2 * x2)", "sqrt(x1 * x1 + q * q * x2 * x2)")],
+    "sie_atanh_atan": [("a2 = b / e * atanh(e * x2 / psi);", "a2 = b / e * atan(e * x2 / psi);")],
+    "sersic_rotation_sense": [("double x1 = dx * cos(phi) + dy * sin(phi);", "double x1 = dx * cos(phi) - dy * sin(phi);"),
+                              ("double x2 = -dx * sin(phi) + dy * cos(phi);", "double x2 = dx * sin(phi) + dy * cos(phi);")],
+    "sersic_q_inverted": [("sqrt(x1 * x1 * q + x2 * x2 / q)", "sqrt(x1 * x1 / q + x2 * x2 * q)")],
+    "sersic_drop_minus_one": [("exp(-b_n * (pow(R / R_e, 1.0 / n) - 1.0))", "exp(-b_n * pow(R / R_e, 1.0 / n))")],
+    "bn_wrong_quantile": [("if (oracle_gammainc_lower_reg(a, mid) < 0.5) lo = mid;",
+                           "if (oracle_gammainc_lower_reg(a, mid) < 0.55) lo = mid;")],
+    "gamma_series_term": [("term *= x / ap;", "term *= x / (ap + 1.0);")],
+    "lens_equation_sign": [("double bx = x - ax, by = y - ay;", "double bx = x + ax, by = y + ay;")],
+    "lens_light_off_mass_centre": [("p[10], p[11], p[3], p[4], x, y)", "p[10], p[11], p[17], p[18], x, y)")],
+    "scene_xy_transposed": [("p[10], p[11], p[3], p[4], x, y)", "p[10], p[11], p[3], p[4], y, x)"),
+                            ("p[17], p[18], bx, by)", "p[17], p[18], by, bx)")],
+    "lens_light_not_supersampled": [("acc += orc_scene(p, bl, bs, x, y);",
+                                     "acc += orc_scene(p, bl, bs, x, y) - oracle_sersic(p[7], p[8], p[9], bl, p[10], p[11], p[3], p[4], x, y) + oracle_sersic(p[7], p[8], p[9], bl, p[10], p[11], p[3], p[4], ((double)j - 0.5 * (nx - 1)) * dpix, ((double)i - 0.5 * (ny - 1)) * dpix);")],
+}
+
+
+@pytest.fixture(scope="module")
+def src():
+    with open(oracle.SRC) as f:
+        return f.read()
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_mutant_is_caught(name, src, tmp_path):
+    text = src
+    for old, new in MUTANTS[name]:
+        assert text.count(old) >= 1, (name, old)
+        text = text.replace(old, new)
+    path = os.path.join(str(tmp_path), "mutant_%s.c" % name)
+    with open(path, "w") as f:
+        f.write(text)
+    lib = oracle.compile_oracle(path, os.path.join(str(tmp_path), "libmutant_%s.so" % name))
+    orc = oracle.Oracle(lib)
+    caught = []
+    for pin in oracle_pins.ALL_PINS:
+        try:
+            pin(orc)
+        except (AssertionError, ValueError):
+            caught.append(pin.__name__)
+    assert caught, "planted mistake %r passed every pin" % name
