@@ -1,0 +1,195 @@
+/*
+ * lens_api.h -- C ABI of the MI355X batched lens log-likelihood library.
+ *
+ * The library evaluates, for many proposed parameter vectors at once, the
+ * Gaussian log-likelihood of a galaxy-galaxy strong-lens image under the
+ * forward model of Cao et al. (2025), "CSST Strong Lensing Preparation: Fast
+ * Modelling of Galaxy-Galaxy Strong Lenses in the Big Data Era":
+ *   - lens equation beta = theta - alpha(theta)                 (Sec. 2.1, Eq. 1)
+ *   - image = lens light(theta) + source light(beta)             (Sec. 2.1, Eq. 2)
+ *   - s x s supersampling, binned by the pixel mean               (Sec. 2.1, after Eq. 2)
+ *   - PSF convolution of the binned image                         (Sec. 2.1, Eq. 3)
+ *   - lnL = sum over the fitting region of ln N(d_i; I_i, sigma_i)  (Sec. 2.2, Eq. 5)
+ *   - SIE mass (the elliptical power law at slope 2) + external shear (Sec. 2.4, Eqs. 12-14)
+ *   - elliptical Sersic light for lens and source                 (Sec. 2.4, Eqs. 8-10)
+ * The light amplitudes are explicit parameters here; the paper's linear
+ * (NNLS) amplitude solve of Sec. 2.3 is not part of this call.
+ *
+ * Conventions (each is a reading of a passage the paper leaves open):
+ *   - SIE convergence kappa = theta_E / (2 R_p), R_p = sqrt(q x1^2 + x2^2/q)
+ *     the elliptical radius of Eq. 10; alpha = 0 at the mass centre.
+ *   - shear potential with the sign printed in Eq. 13:
+ *     alpha_shear = -(g1 x + g2 y, g2 x - g1 y), origin at the image centre.
+ *   - position angles counter-clockwise from +x; x grows with the column
+ *     index, y with the row index; the image centre is pixel ((nx-1)/2, (ny-1)/2).
+ *   - sub-pixels are the centres of an s x s split of each pixel; the
+ *     binned value is their mean; the lens light is centred on the mass.
+ *   - b_n is the exact root of Gamma(2n) = 2 gamma(2n, b_n) (Eq. 9).
+ *   - the PSF is a true convolution (kernel flipped), k odd, centred at
+ *     (k-1)/2, zero outside the image, output of the image's size.
+ *   - lnL = -1/2 chi^2 - 1/2 sum_mask ln(2 pi sigma^2), sums over mask pixels.
+ *
+ * Parameter vector: LENS_PARAM_STRIDE doubles per proposal, row-major
+ * [n][20], arcsec and radians; slot 19 is ignored:
+ *   0 theta_E  1 q_m  2 phi_m  3 x_m  4 y_m  5 g1  6 g2
+ *   7 I_l  8 R_l  9 n_l  10 q_l  11 phi_l
+ *   12 I_s 13 R_s 14 n_s 15 q_s 16 phi_s 17 x_s 18 y_s
+ * A proposal outside the domain is not a call error: its lnL is -INFINITY.
+ * The domain is: every slot 0..18 finite, theta_E >= 0, each axis ratio in
+ * (0, 1], R_l > 0, R_s > 0, n_l and n_s in [0.1, 20].
+ *
+ * Arithmetic: ray tracing and light in FP32, the PSF convolution in FP32
+ * (LENS_PREC_FP32) or as a BF16 matrix-core contraction (the other
+ * precisions), the chi-square reduction and the result in FP64.
+ *
+ * Threading: every entry point is thread-safe.  Errors: every call returns a
+ * lens_status; on a call error nothing is written to the outputs and
+ * lens_last_error() holds a message.  A HIP runtime error is sticky: the
+ * context then answers LENS_EDEVICE to every call but lens_shutdown.
+ */
+#ifndef LENS_API_H
+#define LENS_API_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lens_status;
+#define LENS_OK 0
+#define LENS_PENDING 1         /* lens_poll: the request has not finished */
+#define LENS_EINVAL (-1)       /* bad argument */
+#define LENS_ENOMEM (-2)       /* device memory or the HBM budget is exhausted */
+#define LENS_ENOENT (-3)       /* unknown lens id or request id */
+#define LENS_EBUSY (-4)        /* lens has requests in flight */
+#define LENS_EAGAIN (-5)       /* non-blocking submit: no room right now */
+#define LENS_EDEVICE (-6)      /* HIP runtime error (sticky) */
+#define LENS_ECANCELED (-7)    /* request was cancelled */
+#define LENS_ETIMEDOUT (-8)    /* lens_wait timed out; the request is still pending */
+
+#define LENS_PARAM_STRIDE 20
+#define LENS_NPARAM 19
+
+/* PSF-convolution arithmetic, chosen per lens at load. */
+#define LENS_PREC_FP32 0          /* FP32 direct convolution on the vector ALUs */
+#define LENS_PREC_BF16_SPLIT 1    /* BF16 MFMA, image and PSF split hi+lo, 3 products */
+#define LENS_PREC_BF16 2          /* BF16 MFMA, single product */
+#define LENS_PREC_BF16_SPLIT3 3   /* BF16 MFMA, hi+mid+lo split, 6 products */
+
+typedef struct lens_ctx lens_ctx;
+typedef int64_t lens_id;
+typedef int64_t lens_req;
+
+/* Device-memory hooks.  alloc returns a device pointer or NULL; both are
+ * called with the context's device current. */
+typedef void *(*lens_dev_alloc_fn)(size_t bytes, void *stream, void *user);
+typedef void (*lens_dev_free_fn)(void *ptr, void *stream, void *user);
+
+typedef struct lens_init_opts {
+    int32_t device;             /* HIP device ordinal */
+    int64_t hbm_budget_bytes;   /* cap on library-held device memory; <= 0: 90% of free memory at init */
+    int32_t max_inflight;       /* serving: requests resident on the device at once; <= 0: 8 */
+    int32_t nonblocking_submit; /* 1: lens_submit answers LENS_EAGAIN when no slot is free */
+    lens_dev_alloc_fn dev_alloc;/* NULL: hipMalloc / hipFree */
+    lens_dev_free_fn dev_free;
+    void *alloc_user;
+    void *stream;               /* hipStream_t for the blocking calls; NULL: a library-owned stream */
+} lens_init_opts;
+
+/* One observed lens image.  All arrays are host memory, row-major, copied by
+ * lens_load_data; the caller may free them when it returns. */
+typedef struct lens_data_desc {
+    int32_t ny, nx;             /* image rows, columns (1..4096) */
+    double pixel_scale;         /* arcsec per pixel, > 0 */
+    int32_t supersample;        /* s >= 1 (paper: 4), at most 8 */
+    int32_t psf_size;           /* k, odd, 1..63 */
+    const double *psf;          /* k*k, used as given (not renormalised) */
+    const double *data;         /* ny*nx observed image */
+    const double *sigma;        /* ny*nx noise; > 0 and finite where mask = 1 */
+    const uint8_t *mask;        /* ny*nx; nonzero = pixel enters the likelihood */
+    int32_t precision;          /* LENS_PREC_* */
+} lens_data_desc;
+
+typedef struct lens_info {
+    int32_t ny, nx, supersample, psf_size, precision;
+    int64_t masked_pixels;      /* M */
+    int64_t needed_pixels;      /* pixels inside the mask dilated by the PSF footprint */
+    int64_t device_bytes;       /* device memory held for this lens */
+    double norm;                /* C = -1/2 sum_mask ln(2 pi sigma^2) */
+} lens_info;
+
+typedef struct lens_stats {
+    int64_t requests_submitted, requests_done, requests_failed, requests_canceled;
+    int64_t proposals_done;
+    int64_t queued, inflight;
+    int64_t hbm_budget_bytes, hbm_used_bytes;
+    int64_t launches;
+} lens_stats;
+
+/* Context.  lens_init creates the context on opts->device (NULL opts: all
+ * defaults).  lens_shutdown waits for in-flight work, cancels queued
+ * requests and frees everything; the pointer is invalid afterwards. */
+lens_status lens_init(const lens_init_opts *opts, lens_ctx **out);
+void lens_shutdown(lens_ctx *ctx);
+
+/* Copy one lens to the device (data, sigma -> weight mask/sigma, PSF, the
+ * pixel lists of the mask and of its PSF-dilated footprint).  Charged to the
+ * HBM budget: LENS_ENOMEM if it does not fit.  LENS_EINVAL for a bad
+ * descriptor (see the field comments). */
+lens_status lens_load_data(lens_ctx *ctx, const lens_data_desc *desc, lens_id *out_id);
+/* Free a lens.  LENS_EBUSY while requests on it are queued or running. */
+lens_status lens_unload(lens_ctx *ctx, lens_id id);
+lens_status lens_get_info(lens_ctx *ctx, lens_id id, lens_info *out);
+
+/* lnL of n proposals (host buffers, params [n][20], out [n]).  Blocks until
+ * the results are in out.  n = 0 is a no-op. */
+lens_status lens_loglike_batch(lens_ctx *ctx, lens_id id, const double *params, int64_t n,
+                               double *out_loglike);
+
+/* Same on device buffers: d_params [n][20] and d_out [n] in device memory,
+ * enqueued on the hipStream_t `stream` (NULL: the context's stream) and not
+ * waited for.  The caller keeps both buffers alive until the stream passes
+ * the call.  Calls on one stream run in order; the library keeps a separate
+ * scratch buffer per stream. */
+lens_status lens_loglike_batch_device(lens_ctx *ctx, lens_id id, const double *d_params,
+                                      int64_t n, double *d_out, void *stream);
+
+/* Many lenses in one persistent launch.  ids[i] with counts[i] proposals;
+ * params holds the proposals of lens 0, then lens 1, ... ([sum counts][20]),
+ * out the results in the same order.  Blocking, host buffers. */
+lens_status lens_loglike_multi(lens_ctx *ctx, int32_t nlens, const lens_id *ids,
+                               const int64_t *counts, const double *params, double *out);
+
+/* Serving.  lens_submit copies params before it returns; out must stay valid
+ * until lens_poll / lens_wait report a final status or lens_cancel returns.
+ * Requests are batched continuously with others on the device.  When all
+ * max_inflight slots are busy the request queues, or with nonblocking_submit
+ * the call answers LENS_EAGAIN. */
+lens_status lens_submit(lens_ctx *ctx, lens_id id, const double *params, int64_t n,
+                        double *out_loglike, lens_req *out_req);
+/* LENS_PENDING, LENS_OK when out is written, or the request's error.  A
+ * request id is forgotten after the first final answer (then LENS_ENOENT). */
+lens_status lens_poll(lens_ctx *ctx, lens_req req);
+/* Waits up to timeout_us (< 0: forever); LENS_ETIMEDOUT if still pending. */
+lens_status lens_wait(lens_ctx *ctx, lens_req req, int64_t timeout_us);
+/* Cancels a queued request (LENS_OK) or waits for a running one to finish
+ * and discards it; out is then not written.  The id is forgotten. */
+lens_status lens_cancel(lens_ctx *ctx, lens_req req);
+lens_status lens_get_stats(lens_ctx *ctx, lens_stats *out);
+
+/* Debug/test: the model image of one proposal (params1: 20 doubles) into
+ * out_img [ny][nx]: stage 0 binned and unconvolved, stage 1 PSF-convolved.
+ * A proposal outside the domain gives LENS_EINVAL. */
+lens_status lens_model_image(lens_ctx *ctx, lens_id id, const double *params1, int32_t stage,
+                             double *out_img);
+
+const char *lens_strerror(lens_status st);
+/* Last error message of the calling thread on this context ("" if none). */
+const char *lens_last_error(lens_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LENS_API_H */

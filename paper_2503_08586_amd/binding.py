@@ -1,0 +1,404 @@
+"""ctypes binding of the lens likelihood C ABI (include/lens_api.h).
+
+Argument marshalling only: every step of the likelihood runs in the HIP
+kernels of liblens_mi355x.so.  The module-level functions carry the C names;
+``LensContext`` wraps them for convenience.  torch is imported first so that
+its HIP runtime is the one the library binds to; device memory for the
+library can come from torch's caching allocator, and the device-buffer entry
+point takes torch tensors and streams.
+
+If the library has not been built, ``load()`` raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library links against)
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblens_mi355x.so")
+STRIDE = 20
+NPARAM = 19
+
+LENS_OK = 0
+LENS_PENDING = 1
+LENS_EINVAL = -1
+LENS_ENOMEM = -2
+LENS_ENOENT = -3
+LENS_EBUSY = -4
+LENS_EAGAIN = -5
+LENS_EDEVICE = -6
+LENS_ECANCELED = -7
+LENS_ETIMEDOUT = -8
+
+LENS_PREC_FP32 = 0
+LENS_PREC_BF16_SPLIT = 1
+LENS_PREC_BF16 = 2
+LENS_PREC_BF16_SPLIT3 = 3
+
+EXPORTED = [
+    "lens_init", "lens_shutdown", "lens_load_data", "lens_unload", "lens_get_info",
+    "lens_loglike_batch", "lens_loglike_batch_device", "lens_loglike_multi",
+    "lens_submit", "lens_poll", "lens_wait", "lens_cancel", "lens_get_stats",
+    "lens_model_image", "lens_strerror", "lens_last_error",
+]
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class lens_init_opts(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32),
+        ("hbm_budget_bytes", ctypes.c_int64),
+        ("max_inflight", ctypes.c_int32),
+        ("nonblocking_submit", ctypes.c_int32),
+        ("dev_alloc", ALLOC_FN),
+        ("dev_free", FREE_FN),
+        ("alloc_user", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class lens_data_desc(ctypes.Structure):
+    _fields_ = [
+        ("ny", ctypes.c_int32),
+        ("nx", ctypes.c_int32),
+        ("pixel_scale", ctypes.c_double),
+        ("supersample", ctypes.c_int32),
+        ("psf_size", ctypes.c_int32),
+        ("psf", ctypes.POINTER(ctypes.c_double)),
+        ("data", ctypes.POINTER(ctypes.c_double)),
+        ("sigma", ctypes.POINTER(ctypes.c_double)),
+        ("mask", ctypes.POINTER(ctypes.c_uint8)),
+        ("precision", ctypes.c_int32),
+    ]
+
+
+class lens_info(ctypes.Structure):
+    _fields_ = [
+        ("ny", ctypes.c_int32), ("nx", ctypes.c_int32), ("supersample", ctypes.c_int32),
+        ("psf_size", ctypes.c_int32), ("precision", ctypes.c_int32),
+        ("masked_pixels", ctypes.c_int64), ("needed_pixels", ctypes.c_int64),
+        ("device_bytes", ctypes.c_int64), ("norm", ctypes.c_double),
+    ]
+
+
+class lens_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "requests_submitted", "requests_done", "requests_failed", "requests_canceled",
+        "proposals_done", "queued", "inflight", "hbm_budget_bytes", "hbm_used_bytes", "launches")]
+
+
+class LensError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (_strerror(status), status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Load liblens_mi355x.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("liblens_mi355x.so is not built; run __graft_entry__.build() "
+                           "or python paper_2503_08586_amd/build.py")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    sig = {
+        "lens_init": ([ctypes.POINTER(lens_init_opts), ctypes.POINTER(vp)], i32),
+        "lens_shutdown": ([vp], None),
+        "lens_load_data": ([vp, ctypes.POINTER(lens_data_desc), i64p], i32),
+        "lens_unload": ([vp, i64], i32),
+        "lens_get_info": ([vp, i64, ctypes.POINTER(lens_info)], i32),
+        "lens_loglike_batch": ([vp, i64, dp, i64, dp], i32),
+        "lens_loglike_batch_device": ([vp, i64, vp, i64, vp, vp], i32),
+        "lens_loglike_multi": ([vp, i32, i64p, i64p, dp, dp], i32),
+        "lens_submit": ([vp, i64, dp, i64, dp, i64p], i32),
+        "lens_poll": ([vp, i64], i32),
+        "lens_wait": ([vp, i64, i64], i32),
+        "lens_cancel": ([vp, i64], i32),
+        "lens_get_stats": ([vp, ctypes.POINTER(lens_stats)], i32),
+        "lens_model_image": ([vp, i64, dp, i32, dp], i32),
+        "lens_strerror": ([i32], ctypes.c_char_p),
+        "lens_last_error": ([vp], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _strerror(st):
+    try:
+        return load().lens_strerror(st).decode()
+    except Exception:
+        return "status"
+
+
+def _check(ctx, st, ok=(LENS_OK,)):
+    if st in ok:
+        return st
+    msg = load().lens_last_error(ctx).decode() if ctx else ""
+    raise LensError(st, msg)
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _params(params) -> np.ndarray:
+    p = np.ascontiguousarray(params, dtype=np.float64)
+    if p.ndim == 1:
+        p = p[None, :]
+    if p.shape[1] == NPARAM:
+        p = np.concatenate([p, np.zeros((p.shape[0], 1))], axis=1)
+    if p.ndim != 2 or p.shape[1] != STRIDE:
+        raise ValueError("params must be [n, 19] or [n, 20]")
+    return np.ascontiguousarray(p)
+
+
+# ---------------------------------------------------------------------------
+# the C entry points, one Python function each
+# ---------------------------------------------------------------------------
+class _Hooks:
+    """torch caching-allocator hooks handed to lens_init (kept alive with the context)."""
+
+    def __init__(self, device):
+        self.device = device
+
+        def _alloc(size, stream, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(size), self.device, int(stream or 0))
+            except Exception:
+                return None
+
+        def _free(ptr, stream, user):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        self.alloc = ALLOC_FN(_alloc)
+        self.free = FREE_FN(_free)
+
+
+_hooks_by_ctx = {}
+
+
+def lens_init(device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 0,
+              nonblocking_submit: bool = False, use_torch_allocator: bool = True,
+              stream: Optional[int] = None):
+    lib = load()
+    o = lens_init_opts()
+    o.device = device
+    o.hbm_budget_bytes = hbm_budget_bytes
+    o.max_inflight = max_inflight
+    o.nonblocking_submit = 1 if nonblocking_submit else 0
+    hooks = None
+    if use_torch_allocator:
+        hooks = _Hooks(device)
+        o.dev_alloc = hooks.alloc
+        o.dev_free = hooks.free
+    o.stream = stream
+    ctx = ctypes.c_void_p()
+    st = lib.lens_init(ctypes.byref(o), ctypes.byref(ctx))
+    if st != LENS_OK:
+        raise LensError(st, "lens_init failed")
+    _hooks_by_ctx[ctx.value] = hooks
+    return ctx.value
+
+
+def lens_shutdown(ctx):
+    load().lens_shutdown(ctx)
+    _hooks_by_ctx.pop(ctx, None)
+
+
+def lens_load_data(ctx, ny, nx, pixel_scale, supersample, psf, data, sigma, mask,
+                   precision=LENS_PREC_FP32) -> int:
+    psf = np.ascontiguousarray(psf, dtype=np.float64)
+    data = np.ascontiguousarray(data, dtype=np.float64)
+    sigma = np.ascontiguousarray(sigma, dtype=np.float64)
+    mask = np.ascontiguousarray(mask, dtype=np.uint8)
+    k = psf.shape[0]
+    if psf.shape != (k, k) or data.shape != (ny, nx) or sigma.shape != (ny, nx) or mask.shape != (ny, nx):
+        raise ValueError("array shapes do not match ny, nx, psf_size")
+    d = lens_data_desc()
+    d.ny, d.nx, d.pixel_scale, d.supersample, d.psf_size = ny, nx, pixel_scale, supersample, k
+    d.psf, d.data, d.sigma = _dptr(psf), _dptr(data), _dptr(sigma)
+    d.mask = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+    d.precision = precision
+    lid = ctypes.c_int64()
+    _check(ctx, load().lens_load_data(ctx, ctypes.byref(d), ctypes.byref(lid)))
+    return lid.value
+
+
+def lens_unload(ctx, lens_id):
+    _check(ctx, load().lens_unload(ctx, lens_id))
+
+
+def lens_get_info(ctx, lens_id) -> dict:
+    info = lens_info()
+    _check(ctx, load().lens_get_info(ctx, lens_id, ctypes.byref(info)))
+    return {f: getattr(info, f) for f, _ in lens_info._fields_}
+
+
+def lens_loglike_batch(ctx, lens_id, params) -> np.ndarray:
+    p = _params(params)
+    out = np.empty(p.shape[0], dtype=np.float64)
+    _check(ctx, load().lens_loglike_batch(ctx, lens_id, _dptr(p), p.shape[0], _dptr(out)))
+    return out
+
+
+def lens_loglike_batch_device(ctx, lens_id, params_dev: "torch.Tensor", out_dev: "torch.Tensor",
+                              stream: Optional["torch.cuda.Stream"] = None):
+    """Device-buffer entry point: params_dev [n, 20] float64 and out_dev [n] float64 on the GPU."""
+    if params_dev.dtype != torch.float64 or out_dev.dtype != torch.float64:
+        raise TypeError("float64 tensors expected")
+    if not (params_dev.is_cuda and out_dev.is_cuda and params_dev.is_contiguous() and out_dev.is_contiguous()):
+        raise ValueError("contiguous device tensors expected")
+    n = params_dev.shape[0]
+    if params_dev.shape != (n, STRIDE) or out_dev.shape != (n,):
+        raise ValueError("shapes must be [n, 20] and [n]")
+    s = stream if stream is not None else torch.cuda.current_stream(params_dev.device)
+    _check(ctx, load().lens_loglike_batch_device(ctx, lens_id, params_dev.data_ptr(), n,
+                                                 out_dev.data_ptr(), s.cuda_stream))
+
+
+def lens_loglike_multi(ctx, lens_ids: Sequence[int], params_list: Sequence[np.ndarray]) -> list:
+    ps = [_params(p) for p in params_list]
+    counts = np.array([p.shape[0] for p in ps], dtype=np.int64)
+    ids = np.array(lens_ids, dtype=np.int64)
+    allp = np.ascontiguousarray(np.concatenate(ps, axis=0)) if ps else np.zeros((0, STRIDE))
+    out = np.empty(int(counts.sum()), dtype=np.float64)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    _check(ctx, load().lens_loglike_multi(ctx, len(ids), ids.ctypes.data_as(i64p), counts.ctypes.data_as(i64p),
+                                          _dptr(allp), _dptr(out)))
+    return np.split(out, np.cumsum(counts)[:-1])
+
+
+class Request:
+    """A submitted serving request: keeps its output buffer alive."""
+
+    def __init__(self, ctx, req_id, out):
+        self.ctx, self.id, self.out = ctx, req_id, out
+
+
+def lens_submit(ctx, lens_id, params) -> Request:
+    p = _params(params)
+    out = np.empty(p.shape[0], dtype=np.float64)
+    rid = ctypes.c_int64()
+    _check(ctx, load().lens_submit(ctx, lens_id, _dptr(p), p.shape[0], _dptr(out), ctypes.byref(rid)))
+    return Request(ctx, rid.value, out)
+
+
+def lens_poll(ctx, req: Request) -> int:
+    st = load().lens_poll(ctx, req.id)
+    return _check(ctx, st, ok=(LENS_OK, LENS_PENDING))
+
+
+def lens_wait(ctx, req: Request, timeout_us: int = -1) -> int:
+    st = load().lens_wait(ctx, req.id, timeout_us)
+    return _check(ctx, st, ok=(LENS_OK, LENS_ETIMEDOUT))
+
+
+def lens_cancel(ctx, req: Request):
+    _check(ctx, load().lens_cancel(ctx, req.id))
+
+
+def lens_get_stats(ctx) -> dict:
+    s = lens_stats()
+    _check(ctx, load().lens_get_stats(ctx, ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in lens_stats._fields_}
+
+
+def lens_model_image(ctx, lens_id, params1, stage: int, ny: int, nx: int) -> np.ndarray:
+    p = _params(params1)[0].copy()
+    out = np.empty((ny, nx), dtype=np.float64)
+    _check(ctx, load().lens_model_image(ctx, lens_id, _dptr(p), stage, _dptr(out)))
+    return out
+
+
+def lens_strerror(st: int) -> str:
+    return load().lens_strerror(st).decode()
+
+
+def lens_last_error(ctx) -> str:
+    return load().lens_last_error(ctx).decode()
+
+
+# ---------------------------------------------------------------------------
+# convenience wrapper
+# ---------------------------------------------------------------------------
+class LensContext:
+    """One library context on one GPU."""
+
+    def __init__(self, device: int = 0, **kw):
+        self.ctx = lens_init(device=device, **kw)
+        self.geom = {}
+
+    def close(self):
+        if self.ctx:
+            lens_shutdown(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def load(self, spec, precision=LENS_PREC_FP32, data=None) -> int:
+        """Load a synth.LensSpec (its data, or ``data`` if given)."""
+        d = spec.data if data is None else data
+        lid = lens_load_data(self.ctx, spec.ny, spec.nx, spec.dpix, spec.s, spec.psf, d, spec.sigma,
+                             spec.mask, precision)
+        self.geom[lid] = (spec.ny, spec.nx)
+        return lid
+
+    def load_raw(self, ny, nx, dpix, s, psf, data, sigma, mask, precision=LENS_PREC_FP32) -> int:
+        lid = lens_load_data(self.ctx, ny, nx, dpix, s, psf, data, sigma, mask, precision)
+        self.geom[lid] = (ny, nx)
+        return lid
+
+    def unload(self, lid):
+        lens_unload(self.ctx, lid)
+        self.geom.pop(lid, None)
+
+    def loglike(self, lid, params) -> np.ndarray:
+        return lens_loglike_batch(self.ctx, lid, params)
+
+    def loglike_device(self, lid, params_dev, out_dev, stream=None):
+        lens_loglike_batch_device(self.ctx, lid, params_dev, out_dev, stream)
+
+    def loglike_multi(self, lids, params_list):
+        return lens_loglike_multi(self.ctx, lids, params_list)
+
+    def model_image(self, lid, params1, stage=1) -> np.ndarray:
+        ny, nx = self.geom[lid]
+        return lens_model_image(self.ctx, lid, params1, stage, ny, nx)
+
+    def info(self, lid) -> dict:
+        return lens_get_info(self.ctx, lid)
+
+    def submit(self, lid, params) -> Request:
+        return lens_submit(self.ctx, lid, params)
+
+    def poll(self, req) -> int:
+        return lens_poll(self.ctx, req)
+
+    def wait(self, req, timeout_us=-1) -> int:
+        return lens_wait(self.ctx, req, timeout_us)
+
+    def cancel(self, req):
+        lens_cancel(self.ctx, req)
+
+    def stats(self) -> dict:
+        return lens_get_stats(self.ctx)

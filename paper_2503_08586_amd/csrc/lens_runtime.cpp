@@ -1,0 +1,1112 @@
+// lens_runtime.cpp -- host runtime behind include/lens_api.h.
+//
+// Context, resident lens registry with HBM-budget accounting, per-stream
+// scratch, the blocking and device-buffer likelihood calls, the multi-lens
+// call, and the serving scheduler (continuous batching of proposal tiles from
+// many concurrent requests onto several HIP streams).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <condition_variable>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "lens_api.h"
+#include "lens_internal.h"
+
+using lensk::LensGeom;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+constexpr int kServeStreams = 4;
+constexpr int64_t kTileMax = 8192;           // proposals per serving launch
+constexpr size_t kBytesPerProposal = lensk::kStride * sizeof(double) + lensk::kPC * sizeof(float) + sizeof(double);
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Lens {
+    lens_id id = 0;
+    LensGeom g{};
+    int precision = 0;
+    int64_t masked = 0, needed = 0;
+    void *slab = nullptr;   // one device allocation holding every array
+    size_t bytes = 0;
+    int users = 0;          // blocking calls in progress
+    int requests = 0;       // serving requests queued or running
+};
+
+struct Scratch {            // per-stream device scratch of the device-buffer entry point
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+enum class RState { Queued, Running, Done, Error, Canceled };
+
+struct Request {
+    lens_req id = 0;
+    Lens *lens = nullptr;
+    int64_t n = 0;
+    std::vector<double> params;   // host copy taken at submit
+    double *out = nullptr;        // caller's buffer
+    RState state = RState::Queued;
+    lens_status status = LENS_PENDING;
+    int64_t next_tile = 0;        // first proposal not yet launched
+    int64_t done = 0;             // proposals finished
+    int tiles_running = 0;
+    bool cancel = false;
+    std::vector<double> result;   // assembled here, copied to out when complete
+};
+
+struct Tile {
+    Request *req = nullptr;
+    int64_t off = 0, n = 0;
+    size_t arena_off = 0, arena_bytes = 0;
+    hipEvent_t ev = nullptr;
+    int stream = 0;
+};
+
+// First-fit arena over one device slab and one pinned host slab of equal size.
+struct Arena {
+    size_t size = 0;
+    std::map<size_t, size_t> free_;   // offset -> length
+    void reset(size_t s)
+    {
+        size = s;
+        free_.clear();
+        if (s) free_[0] = s;
+    }
+    bool alloc(size_t len, size_t *off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= len) {
+                *off = it->first;
+                size_t rest = it->second - len;
+                size_t noff = it->first + len;
+                free_.erase(it);
+                if (rest) free_[noff] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t len)
+    {
+        auto it = free_.emplace(off, len).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+thread_local std::unordered_map<const void *, std::string> t_err;
+
+}  // namespace
+
+struct lens_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    lens_dev_alloc_fn alloc = nullptr;
+    lens_dev_free_fn dfree = nullptr;
+    void *user = nullptr;
+    int64_t budget = 0;
+    std::atomic<int64_t> used{0};
+    std::atomic<int> dev_error{0};
+
+    std::mutex mu;                        // registry, scratch, budget
+    std::map<lens_id, Lens *> lenses;
+    lens_id next_id = 1;
+    std::unordered_map<hipStream_t, Scratch> scratch;
+
+    std::mutex sync_mu;                   // staging of the blocking calls
+    double *h_params = nullptr, *h_out = nullptr;
+    size_t h_cap = 0;                     // proposals
+    void *d_sync = nullptr;               // params | pc | out for the blocking calls
+    size_t d_sync_bytes = 0;
+
+    // serving
+    int max_inflight = 8;
+    bool nonblocking = false;
+    std::mutex smu;
+    std::condition_variable scv;          // wakes the scheduler
+    std::condition_variable dcv;          // request finished
+    std::deque<Request *> queue;          // requests with tiles still to launch
+    std::map<lens_req, Request *> reqs;
+    lens_req next_req = 1;
+    std::vector<Tile> running;
+    Arena arena;
+    void *d_arena = nullptr;
+    char *h_arena = nullptr;
+    hipStream_t sstreams[kServeStreams] = {};
+    std::thread sched;
+    bool stop = false;
+    lens_stats stats{};
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+lens_status fail(lens_ctx *c, lens_status st, const std::string &msg)
+{
+    t_err[c] = msg;
+    return st;
+}
+
+lens_status hip_fail(lens_ctx *c, hipError_t e, const char *what)
+{
+    c->dev_error.store(1);
+    char buf[256];
+    snprintf(buf, sizeof(buf), "%s: %s", what, hipGetErrorString(e));
+    return fail(c, LENS_EDEVICE, buf);
+}
+
+#define HIPCHK(ctx, expr)                                   \
+    do {                                                    \
+        hipError_t _e = (expr);                             \
+        if (_e != hipSuccess) return hip_fail(ctx, _e, #expr); \
+    } while (0)
+
+void *dev_alloc(lens_ctx *c, size_t bytes)
+{
+    if (c->alloc) return c->alloc(bytes, (void *)c->stream, c->user);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+}
+
+void dev_free(lens_ctx *c, void *p)
+{
+    if (!p) return;
+    if (c->dfree) c->dfree(p, (void *)c->stream, c->user);
+    else (void)hipFree(p);
+}
+
+bool charge(lens_ctx *c, int64_t bytes)
+{
+    int64_t cur = c->used.load();
+    while (true) {
+        if (cur + bytes > c->budget) return false;
+        if (c->used.compare_exchange_weak(cur, cur + bytes)) return true;
+    }
+}
+
+void uncharge(lens_ctx *c, int64_t bytes) { c->used.fetch_sub(bytes); }
+
+Lens *acquire(lens_ctx *c, lens_id id)
+{
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->lenses.find(id);
+    if (it == c->lenses.end()) return nullptr;
+    it->second->users++;
+    return it->second;
+}
+
+void release(lens_ctx *c, Lens *L)
+{
+    std::lock_guard<std::mutex> lk(c->mu);
+    L->users--;
+}
+
+lens_status check_ctx(lens_ctx *c)
+{
+    if (!c) return LENS_EINVAL;
+    if (c->dev_error.load()) return fail(c, LENS_EDEVICE, "context is in the device-error state");
+    return LENS_OK;
+}
+
+// Device scratch of at least `bytes` private to `stream` (grown by re-allocation
+// after the stream has drained).
+lens_status stream_scratch(lens_ctx *c, hipStream_t st, size_t bytes, void **out)
+{
+    std::lock_guard<std::mutex> lk(c->mu);
+    Scratch &s = c->scratch[st];
+    if (s.bytes >= bytes) {
+        *out = s.p;
+        return LENS_OK;
+    }
+    size_t want = align_up(std::max(bytes, s.bytes * 3 / 2), 1 << 20);
+    if (s.p) {
+        HIPCHK(c, hipStreamSynchronize(st));
+        dev_free(c, s.p);
+        uncharge(c, (int64_t)s.bytes);
+        s.p = nullptr;
+        s.bytes = 0;
+    }
+    if (!charge(c, (int64_t)want)) return fail(c, LENS_ENOMEM, "HBM budget exhausted (scratch)");
+    s.p = dev_alloc(c, want);
+    if (!s.p) {
+        uncharge(c, (int64_t)want);
+        return fail(c, LENS_ENOMEM, "device allocation failed (scratch)");
+    }
+    s.bytes = want;
+    *out = s.p;
+    return LENS_OK;
+}
+
+struct ScratchLayout {
+    double *params;
+    float *pc;
+    double *out;
+};
+
+size_t scratch_bytes(int64_t n, bool with_params_out)
+{
+    size_t b = align_up((size_t)n * lensk::kPC * sizeof(float), kAlign);
+    if (with_params_out)
+        b += align_up((size_t)n * lensk::kStride * sizeof(double), kAlign) + align_up((size_t)n * sizeof(double), kAlign);
+    return b;
+}
+
+ScratchLayout carve(void *base, int64_t n, bool with_params_out)
+{
+    ScratchLayout L{};
+    char *p = (char *)base;
+    L.pc = (float *)p;
+    p += align_up((size_t)n * lensk::kPC * sizeof(float), kAlign);
+    if (with_params_out) {
+        L.params = (double *)p;
+        p += align_up((size_t)n * lensk::kStride * sizeof(double), kAlign);
+        L.out = (double *)p;
+    }
+    return L;
+}
+
+hipError_t launch_lens(const Lens *L, const double *d_params, float *d_pc, int64_t n, double *d_out,
+                       hipStream_t st)
+{
+    hipError_t e = lensk::launch_prep(d_params, n, d_pc, st);
+    if (e != hipSuccess) return e;
+    return lensk::launch_loglike_fp32(L->g, d_pc, n, d_out, st);
+}
+
+void scheduler_main(lens_ctx *c);
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------
+extern "C" lens_status lens_init(const lens_init_opts *opts, lens_ctx **out)
+{
+    if (!out) return LENS_EINVAL;
+    *out = nullptr;
+    lens_init_opts o{};
+    if (opts) o = *opts;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return LENS_EDEVICE;
+    if (o.device < 0 || o.device >= ndev) return LENS_EINVAL;
+    if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr)) return LENS_EINVAL;
+    auto c = std::make_unique<lens_ctx>();
+    c->device = o.device;
+    DeviceGuard dg(c->device);
+    c->alloc = o.dev_alloc;
+    c->dfree = o.dev_free;
+    c->user = o.alloc_user;
+    size_t fre = 0, tot = 0;
+    if (hipMemGetInfo(&fre, &tot) != hipSuccess) return LENS_EDEVICE;
+    c->budget = o.hbm_budget_bytes > 0 ? o.hbm_budget_bytes : (int64_t)(fre * 0.9);
+    c->max_inflight = o.max_inflight > 0 ? o.max_inflight : 8;
+    c->nonblocking = o.nonblocking_submit != 0;
+    if (o.stream) {
+        c->stream = (hipStream_t)o.stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) return LENS_EDEVICE;
+        c->own_stream = true;
+    }
+    for (int i = 0; i < kServeStreams; ++i)
+        if (hipStreamCreateWithFlags(&c->sstreams[i], hipStreamNonBlocking) != hipSuccess) return LENS_EDEVICE;
+    c->stats.hbm_budget_bytes = c->budget;
+    lens_ctx *raw = c.release();
+    raw->sched = std::thread(scheduler_main, raw);
+    *out = raw;
+    return LENS_OK;
+}
+
+extern "C" void lens_shutdown(lens_ctx *c)
+{
+    if (!c) return;
+    {
+        std::unique_lock<std::mutex> lk(c->smu);
+        for (Request *r : c->queue) {
+            if (r->tiles_running == 0 && r->state == RState::Queued) {
+                r->state = RState::Canceled;
+                r->status = LENS_ECANCELED;
+            }
+            r->cancel = true;
+        }
+        c->stop = true;
+    }
+    c->scv.notify_all();
+    if (c->sched.joinable()) c->sched.join();
+    DeviceGuard dg(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    for (int i = 0; i < kServeStreams; ++i)
+        if (c->sstreams[i]) {
+            (void)hipStreamSynchronize(c->sstreams[i]);
+            (void)hipStreamDestroy(c->sstreams[i]);
+        }
+    for (auto &kv : c->reqs) delete kv.second;
+    c->reqs.clear();
+    for (auto &kv : c->lenses) {
+        dev_free(c, kv.second->slab);
+        delete kv.second;
+    }
+    c->lenses.clear();
+    for (auto &kv : c->scratch) {
+        (void)hipStreamSynchronize(kv.first);
+        dev_free(c, kv.second.p);
+    }
+    c->scratch.clear();
+    if (c->d_sync) dev_free(c, c->d_sync);
+    if (c->d_arena) dev_free(c, c->d_arena);
+    if (c->h_params) (void)hipHostFree(c->h_params);
+    if (c->h_out) (void)hipHostFree(c->h_out);
+    if (c->h_arena) (void)hipHostFree(c->h_arena);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    t_err.erase(c);
+    delete c;
+}
+
+extern "C" const char *lens_strerror(lens_status st)
+{
+    switch (st) {
+    case LENS_OK: return "ok";
+    case LENS_PENDING: return "pending";
+    case LENS_EINVAL: return "invalid argument";
+    case LENS_ENOMEM: return "out of device memory or HBM budget";
+    case LENS_ENOENT: return "no such lens or request";
+    case LENS_EBUSY: return "lens has requests in flight";
+    case LENS_EAGAIN: return "no free slot, try again";
+    case LENS_EDEVICE: return "HIP device error";
+    case LENS_ECANCELED: return "request cancelled";
+    case LENS_ETIMEDOUT: return "timed out";
+    default: return "unknown status";
+    }
+}
+
+extern "C" const char *lens_last_error(lens_ctx *c)
+{
+    auto it = t_err.find(c);
+    return it == t_err.end() ? "" : it->second.c_str();
+}
+
+// ---------------------------------------------------------------------------
+// lens registry
+// ---------------------------------------------------------------------------
+extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens_id *out_id)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (!d || !out_id) return fail(c, LENS_EINVAL, "null descriptor or output");
+    const int ny = d->ny, nx = d->nx, s = d->supersample, k = d->psf_size;
+    if (ny < 1 || nx < 1 || ny > 4096 || nx > 4096) return fail(c, LENS_EINVAL, "ny, nx must be in 1..4096");
+    if (!(d->pixel_scale > 0.0) || !std::isfinite(d->pixel_scale)) return fail(c, LENS_EINVAL, "pixel_scale must be > 0");
+    if (s < 1 || s > 8) return fail(c, LENS_EINVAL, "supersample must be in 1..8");
+    if (k < 1 || k > lensk::kMaxK || (k & 1) == 0) return fail(c, LENS_EINVAL, "psf_size must be odd, 1..63");
+    if (!d->psf || !d->data || !d->sigma || !d->mask) return fail(c, LENS_EINVAL, "null array in descriptor");
+    if (d->precision != LENS_PREC_FP32) return fail(c, LENS_EINVAL, "precision mode not available");
+    const int64_t npix = (int64_t)ny * nx;
+    for (int i = 0; i < k * k; ++i)
+        if (!std::isfinite(d->psf[i])) return fail(c, LENS_EINVAL, "non-finite PSF value");
+    int64_t masked = 0;
+    double norm = 0.0;
+    for (int64_t i = 0; i < npix; ++i) {
+        if (!d->mask[i]) continue;
+        const double sg = d->sigma[i];
+        if (!(sg > 0.0) || !std::isfinite(sg) || !std::isfinite(d->data[i]))
+            return fail(c, LENS_EINVAL, "sigma must be finite and > 0 and data finite on masked pixels");
+        norm += -0.5 * std::log(2.0 * M_PI * sg * sg);
+        ++masked;
+    }
+    const int r = (k - 1) / 2;
+    const int kc = lensk::choose_kc(k);
+    const int pitch = (int)align_up((size_t)nx, 4);
+    // masked column range of each row
+    std::vector<int> mlo(ny, INT_MAX), mhi(ny, INT_MIN);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x)
+            if (d->mask[(int64_t)y * nx + x]) {
+                mlo[y] = std::min(mlo[y], x);
+                mhi[y] = x + 1;
+            }
+    // needed range: the masked ranges of rows within r, widened by r, clipped
+    std::vector<int2> evr(ny);
+    std::vector<uint32_t> evl, cvl;
+    std::vector<int> evpre(ny + 1, 0), cvpre(ny + 1, 0);
+    for (int y = 0; y < ny; ++y) {
+        int lo = INT_MAX, hi = INT_MIN;
+        for (int yy = std::max(0, y - r); yy <= std::min(ny - 1, y + r); ++yy)
+            if (mhi[yy] > mlo[yy]) {
+                lo = std::min(lo, mlo[yy] - r);
+                hi = std::max(hi, mhi[yy] + r);
+            }
+        lo = std::max(lo, 0);
+        hi = std::min(hi, nx);
+        if (hi <= lo) lo = hi = 0;
+        evr[y] = make_int2(lo, hi);
+        evpre[y] = (int)evl.size();
+        for (int x = lo; x < hi; ++x) evl.push_back(((uint32_t)y << 16) | (uint32_t)x);
+        cvpre[y] = (int)cvl.size();
+        if (mhi[y] > mlo[y])
+            for (int x0 = mlo[y] & ~3; x0 < mhi[y]; x0 += 4) cvl.push_back(((uint32_t)y << 16) | (uint32_t)x0);
+    }
+    evpre[ny] = (int)evl.size();
+    cvpre[ny] = (int)cvl.size();
+    // strip height: as tall as fits 64 KB of LDS, at most 16 rows
+    LensGeom g{};
+    g.ny = ny; g.nx = nx; g.s = s; g.k = k; g.r = r; g.pitch = pitch; g.kc = kc;
+    g.ring_w = (int)align_up((size_t)nx, 4) + 4 * kc;
+    int H = 16;
+    while (H > 1 && (size_t)(H + 2 * r) * g.ring_w * 4 > 65536) --H;
+    if ((size_t)(H + 2 * r) * g.ring_w * 4 > 65536)
+        return fail(c, LENS_EINVAL, "image too wide for the LDS line buffer at this PSF size");
+    g.strip_h = H;
+    g.ring_rows = H + 2 * r;
+    g.sd = (float)(d->pixel_scale / s);
+    g.cfx = (float)(0.5 * ((double)nx * s - 1.0));
+    g.cfy = (float)(0.5 * ((double)ny * s - 1.0));
+    g.inv_s2 = (float)(1.0 / ((double)s * s));
+    g.norm = norm;
+    // host images
+    std::vector<float> hd((size_t)ny * pitch, 0.0f), hw((size_t)ny * pitch, 0.0f), hk((size_t)k * k);
+    for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+            const int64_t i = (int64_t)y * nx + x;
+            if (!d->mask[i]) continue;
+            hd[(size_t)y * pitch + x] = (float)d->data[i];
+            hw[(size_t)y * pitch + x] = (float)(1.0 / d->sigma[i]);
+        }
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) hk[(size_t)a * k + b] = (float)d->psf[(size_t)(k - 1 - a) * k + (k - 1 - b)];
+    // one slab
+    size_t off = 0;
+    auto place = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + std::max<size_t>(bytes, 4), kAlign);
+        return o;
+    };
+    const size_t o_psf = place(hk.size() * 4), o_d = place(hd.size() * 4), o_w = place(hw.size() * 4);
+    const size_t o_evl = place(evl.size() * 4), o_evpre = place(evpre.size() * 4), o_evr = place(evr.size() * 8);
+    const size_t o_cvl = place(cvl.size() * 4), o_cvpre = place(cvpre.size() * 4);
+    const size_t total = off;
+    DeviceGuard dg(c->device);
+    if (!charge(c, (int64_t)total)) return fail(c, LENS_ENOMEM, "HBM budget exhausted");
+    void *slab = dev_alloc(c, total);
+    if (!slab) {
+        uncharge(c, (int64_t)total);
+        return fail(c, LENS_ENOMEM, "device allocation failed");
+    }
+    char *b = (char *)slab;
+    struct {
+        size_t o;
+        const void *src;
+        size_t n;
+    } cp[] = {{o_psf, hk.data(), hk.size() * 4},     {o_d, hd.data(), hd.size() * 4},
+              {o_w, hw.data(), hw.size() * 4},       {o_evl, evl.data(), evl.size() * 4},
+              {o_evpre, evpre.data(), evpre.size() * 4}, {o_evr, evr.data(), evr.size() * 8},
+              {o_cvl, cvl.data(), cvl.size() * 4},   {o_cvpre, cvpre.data(), cvpre.size() * 4}};
+    for (auto &e : cp) {
+        if (!e.n) continue;
+        hipError_t he = hipMemcpyAsync(b + e.o, e.src, e.n, hipMemcpyHostToDevice, c->stream);
+        if (he != hipSuccess) {
+            dev_free(c, slab);
+            uncharge(c, (int64_t)total);
+            return hip_fail(c, he, "hipMemcpyAsync (load)");
+        }
+    }
+    hipError_t he = hipStreamSynchronize(c->stream);
+    if (he != hipSuccess) {
+        dev_free(c, slab);
+        uncharge(c, (int64_t)total);
+        return hip_fail(c, he, "hipStreamSynchronize (load)");
+    }
+    g.psf = (const float *)(b + o_psf);
+    g.data = (const float *)(b + o_d);
+    g.wgt = (const float *)(b + o_w);
+    g.evl = (const uint32_t *)(b + o_evl);
+    g.evpre = (const int *)(b + o_evpre);
+    g.evr = (const int2 *)(b + o_evr);
+    g.cvl = (const uint32_t *)(b + o_cvl);
+    g.cvpre = (const int *)(b + o_cvpre);
+    Lens *L = new Lens();
+    L->g = g;
+    L->precision = d->precision;
+    L->masked = masked;
+    L->needed = (int64_t)evl.size();
+    L->slab = slab;
+    L->bytes = total;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        L->id = c->next_id++;
+        c->lenses[L->id] = L;
+    }
+    *out_id = L->id;
+    return LENS_OK;
+}
+
+extern "C" lens_status lens_unload(lens_ctx *c, lens_id id)
+{
+    if (!c) return LENS_EINVAL;
+    Lens *L = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto it = c->lenses.find(id);
+        if (it == c->lenses.end()) return fail(c, LENS_ENOENT, "unknown lens id");
+        L = it->second;
+        if (L->users > 0) return fail(c, LENS_EBUSY, "lens is in use by a running call");
+        {
+            std::lock_guard<std::mutex> sl(c->smu);
+            if (L->requests > 0) return fail(c, LENS_EBUSY, "lens has serving requests in flight");
+        }
+        c->lenses.erase(it);
+    }
+    DeviceGuard dg(c->device);
+    // every launch that read the lens has completed: blocking calls synchronise,
+    // serving requests are finished; device-buffer calls are ordered on their streams
+    (void)hipDeviceSynchronize();
+    dev_free(c, L->slab);
+    uncharge(c, (int64_t)L->bytes);
+    delete L;
+    return LENS_OK;
+}
+
+extern "C" lens_status lens_get_info(lens_ctx *c, lens_id id, lens_info *out)
+{
+    if (!c || !out) return LENS_EINVAL;
+    Lens *L = acquire(c, id);
+    if (!L) return fail(c, LENS_ENOENT, "unknown lens id");
+    out->ny = L->g.ny;
+    out->nx = L->g.nx;
+    out->supersample = L->g.s;
+    out->psf_size = L->g.k;
+    out->precision = L->precision;
+    out->masked_pixels = L->masked;
+    out->needed_pixels = L->needed;
+    out->device_bytes = (int64_t)L->bytes;
+    out->norm = L->g.norm;
+    release(c, L);
+    return LENS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// likelihood calls
+// ---------------------------------------------------------------------------
+namespace {
+
+// pinned staging + device buffers of the blocking calls, for n proposals
+lens_status sync_buffers(lens_ctx *c, int64_t n)
+{
+    if ((size_t)n > c->h_cap) {
+        size_t cap = std::max<size_t>((size_t)n, c->h_cap * 3 / 2);
+        if (c->h_params) (void)hipHostFree(c->h_params);
+        if (c->h_out) (void)hipHostFree(c->h_out);
+        c->h_params = c->h_out = nullptr;
+        c->h_cap = 0;
+        HIPCHK(c, hipHostMalloc((void **)&c->h_params, cap * lensk::kStride * sizeof(double), hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->h_out, cap * sizeof(double), hipHostMallocDefault));
+        c->h_cap = cap;
+    }
+    const size_t need = scratch_bytes((int64_t)c->h_cap, true);
+    if (need > c->d_sync_bytes) {
+        if (c->d_sync) {
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+            dev_free(c, c->d_sync);
+            uncharge(c, (int64_t)c->d_sync_bytes);
+            c->d_sync = nullptr;
+            c->d_sync_bytes = 0;
+        }
+        if (!charge(c, (int64_t)need)) return fail(c, LENS_ENOMEM, "HBM budget exhausted (staging)");
+        c->d_sync = dev_alloc(c, need);
+        if (!c->d_sync) {
+            uncharge(c, (int64_t)need);
+            return fail(c, LENS_ENOMEM, "device allocation failed (staging)");
+        }
+        c->d_sync_bytes = need;
+    }
+    return LENS_OK;
+}
+
+}  // namespace
+
+extern "C" lens_status lens_loglike_batch(lens_ctx *c, lens_id id, const double *params, int64_t n,
+                                          double *out)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (n < 0 || (n > 0 && (!params || !out))) return fail(c, LENS_EINVAL, "bad params/out/n");
+    if (n > INT_MAX) return fail(c, LENS_EINVAL, "n too large for one call");
+    Lens *L = acquire(c, id);
+    if (!L) return fail(c, LENS_ENOENT, "unknown lens id");
+    if (n == 0) {
+        release(c, L);
+        return LENS_OK;
+    }
+    DeviceGuard dg(c->device);
+    lens_status rs = LENS_OK;
+    {
+        std::lock_guard<std::mutex> lk(c->sync_mu);
+        rs = sync_buffers(c, n);
+        if (rs == LENS_OK) {
+            ScratchLayout S = carve(c->d_sync, (int64_t)c->h_cap, true);
+            memcpy(c->h_params, params, (size_t)n * lensk::kStride * sizeof(double));
+            hipError_t e = hipMemcpyAsync(S.params, c->h_params, (size_t)n * lensk::kStride * sizeof(double),
+                                          hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = launch_lens(L, S.params, S.pc, n, S.out, c->stream);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->h_out, S.out, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) rs = hip_fail(c, e, "lens_loglike_batch");
+            else memcpy(out, c->h_out, (size_t)n * sizeof(double));
+        }
+    }
+    release(c, L);
+    return rs;
+}
+
+extern "C" lens_status lens_loglike_batch_device(lens_ctx *c, lens_id id, const double *d_params, int64_t n,
+                                                 double *d_out, void *stream)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (n < 0 || (n > 0 && (!d_params || !d_out))) return fail(c, LENS_EINVAL, "bad params/out/n");
+    if (n > INT_MAX) return fail(c, LENS_EINVAL, "n too large for one call");
+    Lens *L = acquire(c, id);
+    if (!L) return fail(c, LENS_ENOENT, "unknown lens id");
+    if (n == 0) {
+        release(c, L);
+        return LENS_OK;
+    }
+    DeviceGuard dg(c->device);
+    hipStream_t hs = stream ? (hipStream_t)stream : c->stream;
+    void *scr = nullptr;
+    lens_status rs = stream_scratch(c, hs, scratch_bytes(n, false), &scr);
+    if (rs == LENS_OK) {
+        ScratchLayout S = carve(scr, n, false);
+        hipError_t e = launch_lens(L, d_params, S.pc, n, d_out, hs);
+        if (e != hipSuccess) rs = hip_fail(c, e, "lens_loglike_batch_device");
+    }
+    release(c, L);
+    return rs;
+}
+
+extern "C" lens_status lens_loglike_multi(lens_ctx *c, int32_t nlens, const lens_id *ids, const int64_t *counts,
+                                          const double *params, double *out)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (nlens < 0 || (nlens > 0 && (!ids || !counts))) return fail(c, LENS_EINVAL, "bad ids/counts");
+    int64_t tot = 0;
+    for (int i = 0; i < nlens; ++i) {
+        if (counts[i] < 0) return fail(c, LENS_EINVAL, "negative count");
+        tot += counts[i];
+    }
+    if (tot > 0 && (!params || !out)) return fail(c, LENS_EINVAL, "null params/out");
+    if (tot > INT_MAX) return fail(c, LENS_EINVAL, "too many proposals for one call");
+    std::vector<Lens *> Ls;
+    for (int i = 0; i < nlens; ++i) {
+        Lens *L = acquire(c, ids[i]);
+        if (!L) {
+            for (Lens *x : Ls) release(c, x);
+            return fail(c, LENS_ENOENT, "unknown lens id");
+        }
+        Ls.push_back(L);
+    }
+    DeviceGuard dg(c->device);
+    lens_status rs = LENS_OK;
+    if (tot > 0) {
+        std::lock_guard<std::mutex> lk(c->sync_mu);
+        rs = sync_buffers(c, tot);
+        if (rs == LENS_OK) {
+            ScratchLayout S = carve(c->d_sync, (int64_t)c->h_cap, true);
+            memcpy(c->h_params, params, (size_t)tot * lensk::kStride * sizeof(double));
+            hipError_t e = hipMemcpyAsync(S.params, c->h_params, (size_t)tot * lensk::kStride * sizeof(double),
+                                          hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = lensk::launch_prep(S.params, tot, S.pc, c->stream);
+            int64_t off = 0;
+            for (int i = 0; i < nlens && e == hipSuccess; ++i) {
+                if (counts[i] > 0) e = lensk::launch_loglike_fp32(Ls[i]->g, S.pc + off * lensk::kPC, counts[i], S.out + off, c->stream);
+                off += counts[i];
+            }
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->h_out, S.out, (size_t)tot * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) rs = hip_fail(c, e, "lens_loglike_multi");
+            else memcpy(out, c->h_out, (size_t)tot * sizeof(double));
+        }
+    }
+    for (Lens *x : Ls) release(c, x);
+    return rs;
+}
+
+extern "C" lens_status lens_model_image(lens_ctx *c, lens_id id, const double *params1, int32_t stage,
+                                        double *out_img)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (!params1 || !out_img || (stage != 0 && stage != 1)) return fail(c, LENS_EINVAL, "bad arguments");
+    Lens *L = acquire(c, id);
+    if (!L) return fail(c, LENS_ENOENT, "unknown lens id");
+    DeviceGuard dg(c->device);
+    const int64_t npix = (int64_t)L->g.ny * L->g.nx;
+    lens_status rs = LENS_OK;
+    {
+        std::lock_guard<std::mutex> lk(c->sync_mu);
+        // device: params(20 doubles) | pc | img | tmp
+        const size_t bytes = 4096 + 2 * align_up((size_t)npix * 4, kAlign);
+        void *dbuf = nullptr;
+        rs = stream_scratch(c, c->stream, bytes, &dbuf);
+        if (rs == LENS_OK) {
+            char *b = (char *)dbuf;
+            double *dp = (double *)b;
+            float *dpc = (float *)(b + 2048);
+            float *img = (float *)(b + 4096);
+            float *tmp = (float *)(b + 4096 + align_up((size_t)npix * 4, kAlign));
+            std::vector<float> pc(lensk::kPC), hi((size_t)npix);
+            hipError_t e = hipMemcpyAsync(dp, params1, lensk::kStride * sizeof(double), hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = lensk::launch_prep(dp, 1, dpc, c->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(pc.data(), dpc, lensk::kPC * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e == hipSuccess && pc[lensk::PC_VALID] == 0.0f) {
+                rs = fail(c, LENS_EINVAL, "proposal outside the parameter domain");
+            } else {
+                if (e == hipSuccess) e = lensk::launch_model_image(L->g, dpc, stage, img, tmp, c->stream);
+                if (e == hipSuccess) e = hipMemcpyAsync(hi.data(), img, (size_t)npix * 4, hipMemcpyDeviceToHost, c->stream);
+                if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+                if (e != hipSuccess) rs = hip_fail(c, e, "lens_model_image");
+                else
+                    for (int64_t i = 0; i < npix; ++i) out_img[i] = (double)hi[(size_t)i];
+            }
+        }
+    }
+    release(c, L);
+    return rs;
+}
+
+// ---------------------------------------------------------------------------
+// serving
+// ---------------------------------------------------------------------------
+namespace {
+
+void finish_request(lens_ctx *c, Request *r)
+{
+    // called with smu held, when the last tile of r has completed
+    if (r->cancel) {
+        r->state = RState::Canceled;
+        r->status = LENS_ECANCELED;
+        c->stats.requests_canceled++;
+    } else if (r->status == LENS_PENDING) {
+        memcpy(r->out, r->result.data(), (size_t)r->n * sizeof(double));
+        r->state = RState::Done;
+        r->status = LENS_OK;
+        c->stats.requests_done++;
+        c->stats.proposals_done += r->n;
+    } else {
+        r->state = RState::Error;
+        c->stats.requests_failed++;
+    }
+    r->lens->requests--;
+    r->result.clear();
+    r->result.shrink_to_fit();
+    r->params.clear();
+    r->params.shrink_to_fit();
+}
+
+void ensure_arena(lens_ctx *c)
+{
+    if (c->d_arena) return;
+    const size_t want = align_up((size_t)c->max_inflight * kTileMax * kBytesPerProposal + (size_t)c->max_inflight * 3 * kAlign,
+                                 1 << 20);
+    if (!charge(c, (int64_t)want)) return;
+    c->d_arena = dev_alloc(c, want);
+    if (!c->d_arena) {
+        uncharge(c, (int64_t)want);
+        return;
+    }
+    if (hipHostMalloc((void **)&c->h_arena, want, hipHostMallocDefault) != hipSuccess) {
+        dev_free(c, c->d_arena);
+        c->d_arena = nullptr;
+        uncharge(c, (int64_t)want);
+        return;
+    }
+    c->arena.reset(want);
+}
+
+size_t tile_bytes(int64_t n)
+{
+    return align_up((size_t)n * lensk::kStride * 8, kAlign) + align_up((size_t)n * lensk::kPC * 4, kAlign) +
+           align_up((size_t)n * 8, kAlign);
+}
+
+// Launch as many tiles as slots and arena space allow (smu held).
+void admit(lens_ctx *c)
+{
+    if (c->dev_error.load() || !c->d_arena) return;
+    int stream_rr = (int)c->stats.launches;
+    while ((int)c->running.size() < c->max_inflight && !c->queue.empty()) {
+        Request *r = c->queue.front();
+        if (r->cancel) {
+            c->queue.pop_front();
+            if (r->tiles_running == 0) {
+                finish_request(c, r);
+                c->dcv.notify_all();
+            }
+            continue;
+        }
+        const int64_t n = std::min<int64_t>(kTileMax, r->n - r->next_tile);
+        const size_t bytes = tile_bytes(n);
+        size_t off = 0;
+        if (!c->arena.alloc(bytes, &off)) break;  // wait for memory to free up
+        Tile t;
+        t.req = r;
+        t.off = r->next_tile;
+        t.n = n;
+        t.arena_off = off;
+        t.arena_bytes = bytes;
+        t.stream = stream_rr++ % kServeStreams;
+        hipStream_t hs = c->sstreams[t.stream];
+        char *db = (char *)c->d_arena + off;
+        char *hb = c->h_arena + off;
+        double *dparams = (double *)db;
+        float *dpc = (float *)(db + align_up((size_t)n * lensk::kStride * 8, kAlign));
+        double *dout = (double *)((char *)dpc + align_up((size_t)n * lensk::kPC * 4, kAlign));
+        double *hparams = (double *)hb;
+        double *hout = (double *)(hb + ((char *)dout - db));
+        memcpy(hparams, r->params.data() + t.off * lensk::kStride, (size_t)n * lensk::kStride * 8);
+        hipError_t e = hipMemcpyAsync(dparams, hparams, (size_t)n * lensk::kStride * 8, hipMemcpyHostToDevice, hs);
+        if (e == hipSuccess) e = launch_lens(r->lens, dparams, dpc, n, dout, hs);
+        if (e == hipSuccess) e = hipMemcpyAsync(hout, dout, (size_t)n * 8, hipMemcpyDeviceToHost, hs);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventRecord(t.ev, hs);
+        if (e != hipSuccess) {
+            c->dev_error.store(1);
+            c->arena.release(off, bytes);
+            return;
+        }
+        c->stats.launches++;
+        r->state = RState::Running;
+        r->tiles_running++;
+        r->next_tile += n;
+        if (r->next_tile >= r->n) c->queue.pop_front();
+        c->running.push_back(t);
+    }
+}
+
+// Retire finished tiles (smu held).  Returns true if anything finished.
+bool retire(lens_ctx *c)
+{
+    bool any = false;
+    for (size_t i = 0; i < c->running.size();) {
+        Tile &t = c->running[i];
+        hipError_t q = hipEventQuery(t.ev);
+        if (q == hipErrorNotReady) {
+            ++i;
+            continue;
+        }
+        Request *r = t.req;
+        if (q != hipSuccess) {
+            c->dev_error.store(1);
+            r->status = LENS_EDEVICE;
+        } else if (!r->cancel) {
+            const char *hb = c->h_arena + t.arena_off;
+            const size_t oo = align_up((size_t)t.n * lensk::kStride * 8, kAlign) + align_up((size_t)t.n * lensk::kPC * 4, kAlign);
+            memcpy(r->result.data() + t.off, hb + oo, (size_t)t.n * 8);
+        }
+        (void)hipEventDestroy(t.ev);
+        c->arena.release(t.arena_off, t.arena_bytes);
+        r->tiles_running--;
+        r->done += t.n;
+        if (r->tiles_running == 0 && (r->done >= r->n || r->cancel || r->status != LENS_PENDING)) {
+            if (r->status != LENS_PENDING || r->cancel) {
+                // drop tiles not yet launched
+                auto it = std::find(c->queue.begin(), c->queue.end(), r);
+                if (it != c->queue.end()) c->queue.erase(it);
+            }
+            finish_request(c, r);
+        }
+        c->running[i] = c->running.back();
+        c->running.pop_back();
+        any = true;
+    }
+    if (c->dev_error.load()) {
+        // sticky failure: every queued request fails
+        while (!c->queue.empty()) {
+            Request *r = c->queue.front();
+            c->queue.pop_front();
+            if (r->tiles_running == 0 && (r->state == RState::Queued || r->state == RState::Running)) {
+                r->status = LENS_EDEVICE;
+                finish_request(c, r);
+            }
+        }
+        any = true;
+    }
+    return any;
+}
+
+void scheduler_main(lens_ctx *c)
+{
+    (void)hipSetDevice(c->device);
+    std::unique_lock<std::mutex> lk(c->smu);
+    while (true) {
+        admit(c);
+        if (retire(c)) {
+            c->dcv.notify_all();
+            admit(c);
+        }
+        if (c->stop && c->running.empty()) break;
+        if (c->running.empty()) {
+            c->scv.wait(lk, [&] { return c->stop || (!c->queue.empty() && !c->dev_error.load()); });
+        } else {
+            // tiles in flight: poll their events without holding the lock for long
+            lk.unlock();
+            std::this_thread::sleep_for(std::chrono::microseconds(20));
+            lk.lock();
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" lens_status lens_submit(lens_ctx *c, lens_id id, const double *params, int64_t n, double *out,
+                                   lens_req *out_req)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (n < 0 || !out_req || (n > 0 && (!params || !out))) return fail(c, LENS_EINVAL, "bad params/out/n");
+    Lens *L = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto it = c->lenses.find(id);
+        if (it == c->lenses.end()) return fail(c, LENS_ENOENT, "unknown lens id");
+        L = it->second;
+        std::lock_guard<std::mutex> sl(c->smu);
+        ensure_arena(c);  // tile buffers are allocated here, never on the scheduler thread
+        if (!c->d_arena) return fail(c, LENS_ENOMEM, "HBM budget exhausted (serving arena)");
+        if (c->nonblocking && (int)c->running.size() >= c->max_inflight)
+            return fail(c, LENS_EAGAIN, "all serving slots busy");
+        Request *r = new Request();
+        r->id = c->next_req++;
+        r->lens = L;
+        r->n = n;
+        r->params.assign(params, params + n * lensk::kStride);
+        r->result.assign((size_t)n, 0.0);
+        r->out = out;
+        L->requests++;
+        c->reqs[r->id] = r;
+        c->stats.requests_submitted++;
+        *out_req = r->id;
+        if (n == 0) {
+            finish_request(c, r);
+        } else {
+            c->queue.push_back(r);
+        }
+    }
+    c->scv.notify_all();
+    return LENS_OK;
+}
+
+namespace {
+lens_status final_status(lens_ctx *c, Request *r)
+{
+    // smu held; returns the request's final answer and forgets it
+    lens_status s = r->status;
+    c->reqs.erase(r->id);
+    delete r;
+    return s;
+}
+bool is_final(const Request *r)
+{
+    return r->state == RState::Done || r->state == RState::Error || r->state == RState::Canceled;
+}
+}  // namespace
+
+extern "C" lens_status lens_poll(lens_ctx *c, lens_req req)
+{
+    if (!c) return LENS_EINVAL;
+    std::lock_guard<std::mutex> lk(c->smu);
+    auto it = c->reqs.find(req);
+    if (it == c->reqs.end()) return fail(c, LENS_ENOENT, "unknown request id");
+    if (!is_final(it->second)) return LENS_PENDING;
+    return final_status(c, it->second);
+}
+
+extern "C" lens_status lens_wait(lens_ctx *c, lens_req req, int64_t timeout_us)
+{
+    if (!c) return LENS_EINVAL;
+    std::unique_lock<std::mutex> lk(c->smu);
+    auto it = c->reqs.find(req);
+    if (it == c->reqs.end()) return fail(c, LENS_ENOENT, "unknown request id");
+    Request *r = it->second;
+    auto pred = [&] { return is_final(r); };
+    if (timeout_us < 0) c->dcv.wait(lk, pred);
+    else if (!c->dcv.wait_for(lk, std::chrono::microseconds(timeout_us), pred)) return LENS_ETIMEDOUT;
+    return final_status(c, r);
+}
+
+extern "C" lens_status lens_cancel(lens_ctx *c, lens_req req)
+{
+    if (!c) return LENS_EINVAL;
+    std::unique_lock<std::mutex> lk(c->smu);
+    auto it = c->reqs.find(req);
+    if (it == c->reqs.end()) return fail(c, LENS_ENOENT, "unknown request id");
+    Request *r = it->second;
+    if (!is_final(r)) {
+        r->cancel = true;
+        if (r->tiles_running == 0) {
+            auto q = std::find(c->queue.begin(), c->queue.end(), r);
+            if (q != c->queue.end()) c->queue.erase(q);
+            finish_request(c, r);
+        } else {
+            c->dcv.wait(lk, [&] { return is_final(r); });
+        }
+    }
+    c->reqs.erase(r->id);
+    delete r;
+    return LENS_OK;
+}
+
+extern "C" lens_status lens_get_stats(lens_ctx *c, lens_stats *out)
+{
+    if (!c || !out) return LENS_EINVAL;
+    std::lock_guard<std::mutex> lk(c->smu);
+    *out = c->stats;
+    out->queued = (int64_t)c->queue.size();
+    out->inflight = (int64_t)c->running.size();
+    out->hbm_budget_bytes = c->budget;
+    out->hbm_used_bytes = c->used.load();
+    return LENS_OK;
+}

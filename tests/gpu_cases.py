@@ -1,0 +1,51 @@
+"""Shared helpers of the GPU tests: seeded cases whose data come from the FP64 oracle."""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+import oracle
+from paper_2503_08586_amd import synth
+
+TOL_FP32 = 1e-6     # |dlnL| / (chi2/2 + |C|), FP32 and split modes
+TOL_BF16 = 1e-3     # plain BF16 mode
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def oracle_data(spec: synth.LensSpec):
+    orc = oracle.default()
+    return spec.make_data(lambda sp, t: orc.model_image(sp.ny, sp.nx, sp.dpix, sp.s, sp.psf, t, stage=1))
+
+
+def oracle_loglike(spec: synth.LensSpec, params):
+    orc = oracle.default()
+    lnl, chi2 = orc.loglike(spec.geom, spec.psf, spec.data, spec.sigma, spec.mask, params, return_chi2=True)
+    C = orc.loglike_norm(spec.sigma, spec.mask)
+    return lnl, chi2, C
+
+
+def rel_err(got, ref, chi2, C):
+    """The error metric of the parity gate: |dlnL| / (chi2/2 + |C|); exact -inf matches give 0."""
+    got = np.asarray(got)
+    ref = np.asarray(ref)
+    both_inf = np.isneginf(got) & np.isneginf(ref)
+    den = 0.5 * np.where(np.isfinite(chi2), chi2, 0.0) + abs(C)
+    den = np.where(den > 0, den, 1.0)
+    e = np.abs(got - ref) / den
+    return np.where(both_inf, 0.0, e)
+
+
+def custom_spec(seed, ny, nx, dpix, s, psf, mask, nprop, sigma_range=(0.005, 0.02)) -> synth.LensSpec:
+    rng = np.random.default_rng(seed)
+    truth = synth.draw_params(rng, 1)[0]
+    props = synth.draw_params(rng, nprop)
+    sigma = rng.uniform(sigma_range[0], sigma_range[1], (ny, nx))
+    noise = rng.normal(size=(ny, nx)) * sigma
+    spec = synth.LensSpec(ny, nx, dpix, s, psf, sigma, mask.astype(np.uint8), truth, props, noise)
+    oracle_data(spec)
+    return spec

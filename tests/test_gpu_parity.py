@@ -1,0 +1,230 @@
+"""GPU path (through the C ABI) against the FP64 oracle, element by element.
+
+Gate: |lnL_gpu - lnL_oracle| / (chi2/2 + |C|) <= 1e-6 for the FP32 path, with
+C = -1/2 sum_mask ln(2 pi sigma^2).  Out-of-domain proposals must be -inf on
+both sides.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from gpu_cases import TOL_FP32, custom_spec, oracle_data, oracle_loglike, rel_err, say
+from paper_2503_08586_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2503_08586_amd import binding
+    c = binding.LensContext(0)
+    yield c
+    c.close()
+
+
+def _check(spec, got, params, tol=TOL_FP32, label=""):
+    ref, chi2, C = oracle_loglike(spec, params)
+    assert np.array_equal(np.isneginf(got), np.isneginf(ref)), label
+    e = rel_err(got, ref, chi2, C)
+    say("%s: n=%d max err %.3e p99 %.3e" % (label, len(got), e.max(), np.quantile(e, 0.99)))
+    assert e.max() <= tol, (label, e.max(), int(np.argmax(e)))
+    return e
+
+
+def test_c1_all_proposals(ctx):
+    say("case: 64x64 s=1 k=11, 1000 proposals")
+    spec = synth.config1()[0]
+    oracle_data(spec)
+    lid = ctx.load(spec)
+    got = ctx.loglike(lid, spec.proposals)
+    _check(spec, got, spec.proposals, label="c1")
+    ctx.unload(lid)
+
+
+def test_c2_full_call_sampled(ctx):
+    say("case: 128x128 s=4 k=21, 65536 proposals in one call, 48 sampled")
+    spec = synth.config2()[0]
+    oracle_data(spec)
+    lid = ctx.load(spec)
+    got = ctx.loglike(lid, spec.proposals)
+    assert got.shape == (65536,) and np.all(np.isfinite(got))
+    idx = np.random.default_rng(0).choice(65536, 48, replace=False)
+    idx = np.concatenate([idx, [0, 65535]])
+    _check(spec, got[idx], spec.proposals[idx], label="c2 sampled")
+    # the truth itself: chi2 ~ M
+    t = ctx.loglike(lid, spec.truth[None, :])
+    _check(spec, t, spec.truth[None, :], label="c2 truth")
+    ctx.unload(lid)
+
+
+def test_model_image_stages(ctx):
+    say("case: model images, 128x128 s=4 k=21")
+    import oracle
+    orc = oracle.default()
+    spec = synth.config2(nprop=4)[0]
+    oracle_data(spec)
+    lid = ctx.load(spec)
+    for t in range(4):
+        p = spec.proposals[t]
+        for stage in (0, 1):
+            g = ctx.model_image(lid, p, stage)
+            r = orc.model_image(spec.ny, spec.nx, spec.dpix, spec.s, spec.psf, p, stage=stage)
+            scale = np.abs(r).max()
+            err = np.abs(g - r).max() / scale
+            say("stage %d proposal %d: max |diff|/max|img| = %.3e" % (stage, t, err))
+            assert err < 3e-6
+    ctx.unload(lid)
+
+
+GEOMS = [
+    # (name, ny, nx, dpix, s, k, mask)
+    ("psf_larger_than_image", 5, 7, 0.2, 1, 11, "full"),
+    ("odd_sizes_s3", 17, 23, 0.1, 3, 5, "circle"),
+    ("delta_psf", 33, 30, 0.08, 2, 1, "full"),
+    ("ring_mask_s4", 40, 37, 0.07, 4, 9, "ring"),
+    ("max_psf_63", 64, 64, 0.05, 1, 63, "circle"),
+    ("wide_sparse_mask", 9, 130, 0.05, 2, 7, "random"),
+    ("single_pixel", 1, 1, 0.1, 2, 3, "full"),
+    ("tall_s2_k13", 150, 41, 0.06, 2, 13, "circle"),
+    ("s5_k41", 48, 52, 0.05, 5, 41, "circle"),
+]
+
+
+def _mask(kind, ny, nx, dpix, rng):
+    if kind == "full":
+        return np.ones((ny, nx), np.uint8)
+    if kind == "circle":
+        return synth.circular_mask(ny, nx, dpix, 0.45 * min(ny, nx) * dpix)
+    if kind == "ring":
+        a = synth.circular_mask(ny, nx, dpix, 0.45 * min(ny, nx) * dpix)
+        b = synth.circular_mask(ny, nx, dpix, 0.2 * min(ny, nx) * dpix)
+        return (a - b).astype(np.uint8)
+    return (rng.random((ny, nx)) < 0.3).astype(np.uint8)
+
+
+@pytest.mark.parametrize("geom", GEOMS, ids=[g[0] for g in GEOMS])
+def test_geometries(ctx, geom):
+    name, ny, nx, dpix, s, k, mk = geom
+    say("case: geometry %s" % name)
+    rng = np.random.default_rng(sum(map(ord, name)))
+    psf = synth.gaussian_psf(k, 3.0 * dpix, dpix) if k > 1 else np.ones((1, 1))
+    psf = psf * (1.0 + 0.3 * rng.random(psf.shape))      # asymmetric, not normalised
+    spec = custom_spec(7, ny, nx, dpix, s, psf, _mask(mk, ny, nx, dpix, rng), 37)
+    lid = ctx.load(spec)
+    got = ctx.loglike(lid, spec.proposals)
+    _check(spec, got, spec.proposals, label=name)
+    ctx.unload(lid)
+
+
+def test_empty_mask_and_empty_batch(ctx):
+    say("case: empty mask, empty batch")
+    spec = custom_spec(3, 20, 20, 0.1, 2, synth.gaussian_psf(5, 0.2, 0.1), np.zeros((20, 20)), 5)
+    lid = ctx.load(spec)
+    got = ctx.loglike(lid, spec.proposals)
+    assert np.all(got == 0.0)
+    assert ctx.loglike(lid, np.zeros((0, 20))).shape == (0,)
+    ctx.unload(lid)
+
+
+def test_special_proposals(ctx):
+    say("case: special and out-of-domain proposals")
+    spec = synth.config1(nprop=1)[0]
+    oracle_data(spec)
+    lid = ctx.load(spec)
+    base = spec.truth.copy()
+    S = synth.SLOT
+
+    def mod(**kw):
+        p = base.copy()
+        for k_, v in kw.items():
+            p[S[k_]] = v
+        return p
+
+    good = [mod(q_m=1.0), mod(q_l=1.0, q_s=1.0), mod(theta_E=0.0), mod(g1=0.0, g2=0.0),
+            mod(I_l=0.0), mod(I_s=0.0), mod(n_l=0.1, n_s=20.0), mod(n_l=20.0, n_s=0.1),
+            mod(q_m=0.999999), mod(q_m=0.05), mod(x_m=0.0, y_m=0.0), mod(x_s=0.0, y_s=0.0, q_s=1.0),
+            mod(R_s=1e-3), mod(R_l=30.0), mod(theta_E=3.0, q_m=0.3), mod(g1=0.3, g2=-0.3)]
+    bad = [mod(theta_E=-1e-9), mod(q_m=0.0), mod(q_l=1.0000001), mod(q_s=-0.2), mod(R_l=0.0),
+           mod(R_s=-1.0), mod(n_l=0.0999), mod(n_s=20.01), mod(x_s=math.nan), mod(g2=math.inf),
+           mod(I_l=-math.inf)]
+    P = np.stack(good + bad)
+    got = ctx.loglike(lid, P)
+    assert np.all(np.isneginf(got[len(good):]))
+    _check(spec, got, P, label="special")
+    ctx.unload(lid)
+
+
+def test_batch_composition_bitwise(ctx):
+    say("case: batch composition and order")
+    spec = synth.config2(nprop=3000)[0]
+    oracle_data(spec)
+    lid = ctx.load(spec)
+    full = ctx.loglike(lid, spec.proposals)
+    perm = np.random.default_rng(1).permutation(3000)
+    shuf = ctx.loglike(lid, spec.proposals[perm])
+    assert np.array_equal(full[perm], shuf)
+    part = ctx.loglike(lid, spec.proposals[1234:1301])
+    assert np.array_equal(full[1234:1301], part)
+    ctx.unload(lid)
+
+
+def test_device_entry_point_matches_host(ctx):
+    say("case: device-buffer entry point")
+    import torch
+    spec = synth.config1(nprop=777)[0]
+    oracle_data(spec)
+    lid = ctx.load(spec)
+    host = ctx.loglike(lid, spec.proposals)
+    dp = torch.from_numpy(spec.proposals).cuda()
+    do = torch.empty(777, dtype=torch.float64, device="cuda")
+    ctx.loglike_device(lid, dp, do)
+    torch.cuda.synchronize()
+    assert np.array_equal(do.cpu().numpy(), host)
+    s2 = torch.cuda.Stream()
+    do2 = torch.empty(777, dtype=torch.float64, device="cuda")
+    with torch.cuda.stream(s2):
+        ctx.loglike_device(lid, dp, do2, stream=s2)
+    s2.synchronize()
+    assert np.array_equal(do2.cpu().numpy(), host)
+    ctx.unload(lid)
+
+
+def test_multi_matches_single(ctx):
+    say("case: multi-lens call")
+    specs = synth.config3(nlens=6, scale_props=0.05)
+    lids = []
+    for sp in specs:
+        oracle_data(sp)
+        lids.append(ctx.load(sp))
+    outs = ctx.loglike_multi(lids, [sp.proposals for sp in specs])
+    for sp, lid, o in zip(specs, lids, outs):
+        assert np.array_equal(o, ctx.loglike(lid, sp.proposals))
+    _check(specs[0], outs[0][:16], specs[0].proposals[:16], label="multi lens0")
+    for lid in lids:
+        ctx.unload(lid)
+
+
+def test_serving_mixed_equals_alone(ctx):
+    say("case: serving, mixed vs alone")
+    specs = synth.config5_lenses(5)
+    lids = []
+    for sp in specs:
+        oracle_data(sp)
+        lids.append(ctx.load(sp))
+    rng = np.random.default_rng(5)
+    reqs = []
+    for i in range(24):
+        j = int(rng.integers(0, len(lids)))
+        n = int(rng.integers(100, 10001)) if i % 6 else 9000
+        P = synth.draw_params(rng, n)
+        reqs.append((j, P, ctx.submit(lids[j], P)))
+    for j, P, rq in reqs:
+        assert ctx.wait(rq) == 0
+        alone = ctx.loglike(lids[j], P)
+        assert np.array_equal(rq.out, alone)
+    st = ctx.stats()
+    assert st["requests_done"] >= 24
+    _check(specs[reqs[0][0]], reqs[0][2].out[:8], reqs[0][1][:8], label="served")
+    for lid in lids:
+        ctx.unload(lid)
