@@ -149,7 +149,7 @@ lens_status lens_loglike_batch(lens_ctx *ctx, lens_id id, const double *params, 
                                double *out_loglike);
 
 /* Same on device buffers: d_params [n][20] and d_out [n] in device memory,
- * enqueued on the hipStream_t `stream` (NULL: the context's stream) and not
+ * enqueued on the hipStream_t `stream` (NULL: the default stream) and not
  * waited for.  The caller keeps both buffers alive until the stream passes
  * the call.  Calls on one stream run in order; the library keeps a separate
  * scratch buffer per stream. */

@@ -1,10 +1,19 @@
-// lens_device.h -- per-sub-pixel physics of the forward model, FP32, gfx950.
+// lens_device.h -- per-sub-pixel physics of the forward model, gfx950.
 //
 // Cao et al. (2025), Sec. 2.1 (Eqs. 1-2) and Sec. 2.4 (Eqs. 8-10, 12-14).
-// Every function here is evaluated E times per proposal (E = sub-pixels in
-// the mask's PSF-dilated footprint), so it is written for the vector ALU:
-// no divisions, hardware exp2/log2/rsq/rcp, per-proposal constants folded in
-// the prep kernel, branch-free except the two range splits of the SIE.
+// Every function here runs E times per proposal (E = sub-pixels in the
+// mask's PSF-dilated footprint).
+//
+// Precision.  beta = theta - alpha is a difference of arcsecond-sized
+// numbers, and a Sersic profile with n > 1 has an infinitely steep cusp at
+// its centre: an FP32 ray trace (absolute error ~4e-7 arcsec) gives 1e-5
+// brightness errors next to a cusp.  Likewise b_n (R/R_e)^(1/n) amplifies the
+// relative error of (R/R_e)^(1/n) by up to ~30.  So the ray trace and the
+// profiles run in FP64 -- FP64 FMAs issue at the FP32 rate on CDNA4 -- with
+// FP32 hardware only where its error is not amplified: the reciprocal and
+// reciprocal-square-root seeds (refined by a Newton step) and log2 of the
+// elliptical radius, whose error reaches the exponent scaled by
+// b_n/(2n ln 2) ~ 1.  The binned pixel is rounded to FP32 once.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -14,123 +23,125 @@
 
 namespace lensk {
 
-__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ float hw_rsq(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
 
-// 1/x refined by one Newton step (about half an ulp).
-__device__ __forceinline__ float rcp_nr(float x)
+// 1/sqrt(x) and 1/x for x in the normal FP32 range: FP32 hardware seed and
+// one FP64 Newton step (relative error ~1e-14).
+__device__ __forceinline__ double rsq_nr(double x)
 {
-    float r = hw_rcp(x);
-    return fmaf(r, fmaf(-x, r, 1.0f), r);
+    const double r = (double)__builtin_amdgcn_rsqf((float)x);
+    return fma(0.5 * r, fma(-(x * r), r, 1.0), r);
 }
 
-template <int N>
-__device__ __forceinline__ float horner(const float (&c)[N], float w)
+__device__ __forceinline__ double rcp_nr(double x)
 {
-    float p = c[N - 1];
+    const double r = (double)__builtin_amdgcn_rcpf((float)x);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+// 1/sqrt(x) for any x > 0: FP64 hardware seed and two Newton steps.
+__device__ __forceinline__ double rsq64(double x)
+{
+    double r = __builtin_amdgcn_rsq(x);
+    r = fma(0.5 * r, fma(-(x * r), r, 1.0), r);
+    return fma(0.5 * r, fma(-(x * r), r, 1.0), r);
+}
+
+template <typename T, int N>
+__device__ __forceinline__ T horner(const T (&c)[N], T w)
+{
+    T p = c[N - 1];
 #pragma unroll
-    for (int i = N - 2; i >= 0; --i) p = fmaf(p, w, c[i]);
+    for (int i = N - 2; i >= 0; --i) p = fma(p, w, c[i]);
     return p;
 }
 
-// atan(t)/t, even in t.  |t| <= 1: polynomial in t^2; |t| > 1: atan t = pi/2 - atan(1/t).
-__device__ __forceinline__ float atan_over_t(float t)
+// 2^y for y in [-1022, 1023]: 2^round(y) times a polynomial in the remainder.
+__device__ __forceinline__ double exp2_64(double y)
 {
-    const float z = fabsf(t);
-    const bool big = z > 1.0f;
-    const float zi = big ? rcp_nr(z) : z;
-    const float p = horner(kAtanOverT, zi * zi);
-    return big ? fmaf(-zi, p, 1.57079632679f) * zi : p;
+    const double k = rint(y);
+    return ldexp(horner(kExp2_64, y - k), (int)k);
 }
 
-// atanh(t)/t, even in t, |t| < 1.  |t| <= 1/2: polynomial in t^2; otherwise
-// (ln 2 / 2) log2((1+z)/(1-z)) / z with the rounding error of 1+z carried
-// exactly (1-z is exact for z in [1/2, 1]).
-__device__ __forceinline__ float atanh_over_t(float t)
+constexpr double kPi2 = 1.5707963267948966;
+constexpr double kAtanh075 = 0.97295507452765665255;   // atanh(3/4)
+
+// theta_E sqrt(q) atan(c u1)/c (the SIE deflection along the major axis).
+// |c u1| <= 1: polynomial in (c u1)^2; else atan t = pi/2 - atan(1/t).
+__device__ __forceinline__ double sie_a1(double u1, double ce, double bsie, double bsc)
 {
-    const float z = fabsf(t);
-    if (z <= 0.5f) return horner(kAtanhOverT, z * z);
-    const float num = 1.0f + z;
-    const float err = z - (num - 1.0f);
-    const float den = 1.0f - z;
-    const float rd = hw_rcp(den);
-    float q = num * rd;
-    q = fmaf(fmaf(-q, den, num) + err, rd, q);
-    return (0.346573590280f * hw_log2(q)) * rcp_nr(z);
+    const double t = ce * u1;
+    const double z = fabs(t);
+    const bool big = z > 1.0;
+    const double zi = big ? rcp_nr(z) : z;
+    const double p = horner(kAtanOverT64, zi * zi);
+    return big ? copysign(bsc * fma(-zi, p, kPi2), t) : bsie * u1 * p;
 }
 
-// Derived constants of one proposal, uniform across the workgroup.
-struct PropC {
-    float xm, ym, cm, sm, q2m, ce, bsie, g1, g2;
-    float Il, cl, sl, Al, Bl, el, BLh, BLl;
-    float Is, xs, ys, cs, ss, As, Bs, es, BSh, BSl;
-};
-
-__device__ __forceinline__ PropC load_prop(const float *__restrict__ c)
+// theta_E sqrt(q) atanh(c u2)/c (along the minor axis).  |t| <= 1/2:
+// polynomial in t^2; 1/2 < |t| <= 0.9: atanh z = atanh(3/4) + atanh((z - 3/4)/(1 - 3z/4)),
+// whose second argument lies in [-0.4, 0.47]; |t| > 0.9 (axis ratios below
+// 0.44 only): the logarithm.
+__device__ __forceinline__ double sie_a2(double u2, double ce, double bsie, double bsc)
 {
-    PropC P;
-    P.xm = c[PC_XM]; P.ym = c[PC_YM]; P.cm = c[PC_CM]; P.sm = c[PC_SM];
-    P.q2m = c[PC_Q2M]; P.ce = c[PC_CE]; P.bsie = c[PC_BSIE]; P.g1 = c[PC_G1]; P.g2 = c[PC_G2];
-    P.Il = c[PC_IL]; P.cl = c[PC_CL]; P.sl = c[PC_SL]; P.Al = c[PC_AL]; P.Bl = c[PC_BL];
-    P.el = c[PC_EL]; P.BLh = c[PC_BLH]; P.BLl = c[PC_BLL];
-    P.Is = c[PC_IS]; P.xs = c[PC_XS]; P.ys = c[PC_YS]; P.cs = c[PC_CS]; P.ss = c[PC_SS];
-    P.As = c[PC_AS]; P.Bs = c[PC_BS]; P.es = c[PC_ES]; P.BSh = c[PC_BSH]; P.BSl = c[PC_BSL];
-    return P;
+    const double t = ce * u2;
+    const double z = fabs(t);
+    if (z <= 0.9) {
+        const bool red = z > 0.5;
+        const double zr = red ? (z - 0.75) * rcp_nr(fma(-0.75, z, 1.0)) : z;
+        const double p = horner(kAtanhOverT64, zr * zr);
+        return red ? copysign(bsc * fma(zr, p, kAtanh075), t) : bsie * u2 * p;
+    }
+    return copysign(bsc * 0.5 * log((1.0 + z) / (1.0 - z)), t);
 }
 
 // Elliptical Sersic (Eqs. 8, 10) at offset (dx, dy) from its centre:
-//   I exp(-b (R/R_e)^(1/n) + b) = I 2^(B (1 - t)),  t = ((R/R_e)^2)^(1/(2n)),  B = b log2 e.
-// A = q/R_e^2 and Bq = 1/(q R_e^2) fold the axis ratio and radius; B is carried
-// as hi + lo so that its FP32 rounding does not bias the central brightness.
-__device__ __forceinline__ float sersic(float dx, float dy, float c, float s, float A, float Bq,
-                                        float e, float Bh, float Bl, float I)
+//   I_e exp(-b ((R/R_e)^(1/n) - 1)) = I_e 2^(B (1 - t)),  t = ((R/R_e)^2)^(1/(2n)),  B = b log2 e.
+__device__ __forceinline__ double sersic(double dx, double dy, const LightK &L)
 {
-    const float x1 = fmaf(c, dx, s * dy);
-    const float x2 = fmaf(c, dy, -(s * dx));
-    const float r2 = fmaf(A, x1 * x1, Bq * (x2 * x2));
-    const float t = hw_exp2(fminf(e * hw_log2(r2), 64.0f));
-    const float omt = 1.0f - t;
-    return I * hw_exp2(fmaf(Bh, omt, Bl * omt));
+    const double x1 = fma(L.c, dx, L.s * dy);
+    const double x2 = fma(L.c, dy, -(L.s * dx));
+    const double r2 = fma(L.A, x1 * x1, L.Bq * (x2 * x2));
+    const double lg = (double)hw_log2((float)r2);
+    const double t = exp2_64(fmin(fmax(L.e * lg, -1000.0), 64.0));
+    return L.I * exp2_64(fmax(L.B * (1.0 - t), -1000.0));
 }
 
 // Lens light at theta plus source light at beta = theta - alpha_SIE - alpha_shear (Eqs. 1-2).
-// SIE (kappa = theta_E / (2 R_p)) in the frame of the mass ellipse:
-//   alpha' = theta_E sqrt(q) (u1 F(c u1), u2 G(c u2)),  u = x'/psi,  psi = sqrt(q^2 x1'^2 + x2'^2),
-//   c = sqrt(1 - q^2), F = atan(t)/t, G = atanh(t)/t  (smooth through q = 1, alpha = 0 at the centre).
+// SIE (kappa = theta_E / (2 R_p)) in the frame of the mass ellipse, u = x'/psi,
+// psi = sqrt(q^2 x1'^2 + x2'^2), c = sqrt(1 - q^2):
+//   alpha' = theta_E sqrt(q) / c (atan(c u1), atanh(c u2)),  alpha = 0 at the centre.
 // Shear: alpha = -(g1 x + g2 y, g2 x - g1 y).
-__device__ __forceinline__ float scene(float x, float y, const PropC &P)
+__device__ __forceinline__ double scene(double x, double y, const PropBlock &P)
 {
-    const float dx = x - P.xm, dy = y - P.ym;
-    const float x1 = fmaf(P.cm, dx, P.sm * dy);
-    const float x2 = fmaf(P.cm, dy, -(P.sm * dx));
-    const float psi2 = fmaf(P.q2m, x1 * x1, x2 * x2);
-    const float ir = psi2 > 0.0f ? hw_rsq(psi2) : 0.0f;
-    const float u1 = x1 * ir, u2 = x2 * ir;
-    const float a1 = P.bsie * u1 * atan_over_t(P.ce * u1);
-    const float a2 = P.bsie * u2 * atanh_over_t(P.ce * u2);
-    const float bx = (x - fmaf(P.cm, a1, -(P.sm * a2))) + fmaf(P.g1, x, P.g2 * y);
-    const float by = (y - fmaf(P.sm, a1, P.cm * a2)) + fmaf(P.g2, x, -(P.g1 * y));
-    const float il = sersic(dx, dy, P.cl, P.sl, P.Al, P.Bl, P.el, P.BLh, P.BLl, P.Il);
-    const float is = sersic(bx - P.xs, by - P.ys, P.cs, P.ss, P.As, P.Bs, P.es, P.BSh, P.BSl, P.Is);
-    return il + is;
+    const double dx = x - P.xm, dy = y - P.ym;
+    const double x1 = fma(P.cm, dx, P.sm * dy);
+    const double x2 = fma(P.cm, dy, -(P.sm * dx));
+    const double psi2 = fma(P.q2m, x1 * x1, x2 * x2);
+    double ir;
+    if (psi2 >= 1e-30) ir = rsq_nr(psi2);
+    else ir = psi2 > 0.0 ? rsq64(psi2) : 0.0;
+    const double a1 = sie_a1(x1 * ir, P.ce, P.bsie, P.bsc);
+    const double a2 = sie_a2(x2 * ir, P.ce, P.bsie, P.bsc);
+    const double bx = ((x - fma(P.cm, a1, -(P.sm * a2))) + fma(P.g1, x, P.g2 * y)) - P.xs;
+    const double by = ((y - fma(P.sm, a1, P.cm * a2)) + fma(P.g2, x, -(P.g1 * y))) - P.ys;
+    return sersic(dx, dy, P.lens) + sersic(bx, by, P.src);
 }
 
 // Binned (mean) value of pixel (y, x): s x s sub-pixel centres (Sec. 2.1).
 // Fine-grid index fx = x s + u maps to position (fx - (nx s - 1)/2) * pixel_scale / s.
-__device__ __forceinline__ float binned_pixel(const LensGeom &g, const PropC &P, int y, int x)
+__device__ __forceinline__ float binned_pixel(const LensGeom &g, const PropBlock &P, int y, int x)
 {
     const int s = g.s;
-    float acc = 0.0f;
+    double acc = 0.0;
     for (int v = 0; v < s; ++v) {
-        const float yy = ((float)(y * s + v) - g.cfy) * g.sd;
+        const double yy = ((double)(y * s + v) - g.cfy) * g.sd;
         for (int u = 0; u < s; ++u) {
-            const float xx = ((float)(x * s + u) - g.cfx) * g.sd;
+            const double xx = ((double)(x * s + u) - g.cfx) * g.sd;
             acc += scene(xx, yy, P);
         }
     }
-    return acc * g.inv_s2;
+    return (float)(acc * g.inv_s2);
 }
 
 // Sersic b_n: root of P(2n, b) = 1/2 (Eq. 9), FP64 Newton safeguarded by

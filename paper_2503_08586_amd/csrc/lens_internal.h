@@ -9,23 +9,31 @@
 namespace lensk {
 
 constexpr int kStride = 20;   // doubles per proposal vector
-constexpr int kPC = 32;       // floats of derived per-proposal constants
 constexpr int kBlock = 256;   // threads per workgroup of the likelihood kernels
 constexpr int kMaxK = 63;     // largest PSF side
-constexpr float kNMin = 0.1f, kNMax = 20.0f;
+constexpr double kNMin = 0.1, kNMax = 20.0;
 
-// Layout of the derived per-proposal constants (written by the prep kernel).
-enum : int {
-    PC_VALID = 0,
-    // SIE + shear
-    PC_XM, PC_YM, PC_CM, PC_SM, PC_Q2M, PC_CE, PC_BSIE, PC_G1, PC_G2,
-    // lens light: amplitude, rotation, q/R^2, 1/(q R^2), 1/(2n), b_n log2(e) as hi + lo
-    PC_IL, PC_CL, PC_SL, PC_AL, PC_BL, PC_EL, PC_BLH, PC_BLL,
-    // source light: the same plus its centre
-    PC_IS, PC_XS, PC_YS, PC_CS, PC_SS, PC_AS, PC_BS, PC_ES, PC_BSH, PC_BSL,
-    PC_COUNT
+// Derived constants of one Sersic component (Sec. 2.4, Eqs. 8, 10).
+struct LightK {
+    double c, s;      // cos, sin of the position angle
+    double A, Bq;     // q / R_e^2, 1 / (q R_e^2): (R_p / R_e)^2 = A x1^2 + Bq x2^2
+    double e;         // 1 / (2n): t = ((R_p/R_e)^2)^e = (R_p/R_e)^(1/n)
+    double B;         // b_n log2(e): I = I_e 2^(B (1 - t))
+    double I;         // I_e
 };
-static_assert(PC_COUNT <= kPC, "per-proposal constant block too small");
+
+// Derived constants of one proposal, written by the prep kernel and read
+// (uniformly, through the scalar cache) by every workgroup of that proposal.
+struct alignas(16) PropBlock {
+    double valid;                              // 1 inside the domain, 0 outside
+    double xm, ym, cm, sm, q2m, ce;            // SIE: centre, cos/sin phi, q^2, c = sqrt(1 - q^2)
+    double bsie, bsc;                          // theta_E sqrt(q), theta_E sqrt(q) / c (0 if c = 0)
+    double g1, g2, xs, ys;                     // shear, source centre
+    LightK lens, src;
+    double pad[5];
+};
+static_assert(sizeof(PropBlock) == 256, "PropBlock layout");
+constexpr int kPCBytes = (int)sizeof(PropBlock);
 
 // Everything a likelihood launch needs to know about one resident lens.
 struct LensGeom {
@@ -35,8 +43,8 @@ struct LensGeom {
     int ring_rows;         // strip_h + 2r binned rows kept in LDS
     int ring_w;            // floats per LDS row
     int kc;                // float4 chunks of the conv window (4*kc >= k + 3)
-    float sd;              // pixel_scale / s: sub-pixel pitch
-    float cfx, cfy;        // (nx*s - 1)/2, (ny*s - 1)/2: fine-grid centre
+    double sd;             // pixel_scale / s: sub-pixel pitch
+    double cfx, cfy;       // (nx*s - 1)/2, (ny*s - 1)/2: fine-grid centre
     float inv_s2;          // 1/s^2
     double norm;           // C = -1/2 sum_mask ln(2 pi sigma^2)
     const float *psf;      // flipped kernel Kf[a][b] = K[k-1-a][k-1-b], [k][k]
@@ -52,12 +60,12 @@ struct LensGeom {
 size_t ring_bytes(const LensGeom &g);
 int choose_kc(int k);
 
-hipError_t launch_prep(const double *d_params, int64_t n, float *d_pc, hipStream_t st);
-hipError_t launch_loglike_fp32(const LensGeom &g, const float *d_pc, int64_t n, double *d_out,
+hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, hipStream_t st);
+hipError_t launch_loglike_fp32(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out,
                                hipStream_t st);
 // stage 0: binned image of one proposal into d_img [ny][nx]; stage 1: convolved,
 // using d_tmp [ny][nx] for the binned image.
-hipError_t launch_model_image(const LensGeom &g, const float *d_pc, int stage, float *d_img,
+hipError_t launch_model_image(const LensGeom &g, const PropBlock *d_pc, int stage, float *d_img,
                               float *d_tmp, hipStream_t st);
 
 }  // namespace lensk

@@ -18,13 +18,26 @@ namespace lensk {
 // ---------------------------------------------------------------------------
 // prep
 // ---------------------------------------------------------------------------
+__device__ LightK light_constants(double I, double R, double n, double q, double phi)
+{
+    LightK L;
+    L.c = cos(phi);
+    L.s = sin(phi);
+    L.A = q / (R * R);
+    L.Bq = 1.0 / (q * R * R);
+    L.e = 0.5 / n;
+    L.B = bn_device(n) * 1.4426950408889634;
+    L.I = I;
+    return L;
+}
+
 __global__ void __launch_bounds__(256) k_prep(const double *__restrict__ params, int64_t n,
-                                              float *__restrict__ pc)
+                                              PropBlock *__restrict__ pc)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double *p = params + i * kStride;
-    float *c = pc + i * kPC;
+    PropBlock b{};
     double v[19];
     bool ok = true;
 #pragma unroll
@@ -35,54 +48,26 @@ __global__ void __launch_bounds__(256) k_prep(const double *__restrict__ params,
     ok = ok && v[0] >= 0.0;
     ok = ok && v[1] > 0.0 && v[1] <= 1.0 && v[10] > 0.0 && v[10] <= 1.0 && v[15] > 0.0 && v[15] <= 1.0;
     ok = ok && v[8] > 0.0 && v[13] > 0.0;
-    ok = ok && v[9] >= (double)kNMin && v[9] <= (double)kNMax && v[14] >= (double)kNMin && v[14] <= (double)kNMax;
-    if (!ok) {
-        for (int j = 0; j < kPC; ++j) c[j] = 0.0f;
-        return;
+    ok = ok && v[9] >= kNMin && v[9] <= kNMax && v[14] >= kNMin && v[14] <= kNMax;
+    if (ok) {
+        const double q = v[1];
+        b.valid = 1.0;
+        b.xm = v[3];
+        b.ym = v[4];
+        b.cm = cos(v[2]);
+        b.sm = sin(v[2]);
+        b.q2m = q * q;
+        b.ce = sqrt((1.0 - q) * (1.0 + q));
+        b.bsie = v[0] * sqrt(q);
+        b.bsc = b.ce > 0.0 ? b.bsie / b.ce : 0.0;
+        b.g1 = v[5];
+        b.g2 = v[6];
+        b.xs = v[17];
+        b.ys = v[18];
+        b.lens = light_constants(v[7], v[8], v[9], v[10], v[11]);
+        b.src = light_constants(v[12], v[13], v[14], v[15], v[16]);
     }
-    const double log2e = 1.4426950408889634;
-    // mass
-    const double q = v[1];
-    c[PC_VALID] = 1.0f;
-    c[PC_XM] = (float)v[3];
-    c[PC_YM] = (float)v[4];
-    c[PC_CM] = (float)cos(v[2]);
-    c[PC_SM] = (float)sin(v[2]);
-    c[PC_Q2M] = (float)(q * q);
-    c[PC_CE] = (float)sqrt((1.0 - q) * (1.0 + q));
-    c[PC_BSIE] = (float)(v[0] * sqrt(q));
-    c[PC_G1] = (float)v[5];
-    c[PC_G2] = (float)v[6];
-    // lens light
-    {
-        const double R = v[8], nn = v[9], ql = v[10];
-        const double B = bn_device(nn) * log2e;
-        const float Bh = (float)B;
-        c[PC_IL] = (float)v[7];
-        c[PC_CL] = (float)cos(v[11]);
-        c[PC_SL] = (float)sin(v[11]);
-        c[PC_AL] = (float)(ql / (R * R));
-        c[PC_BL] = (float)(1.0 / (ql * R * R));
-        c[PC_EL] = (float)(0.5 / nn);
-        c[PC_BLH] = Bh;
-        c[PC_BLL] = (float)(B - (double)Bh);
-    }
-    // source light
-    {
-        const double R = v[13], nn = v[14], qs = v[15];
-        const double B = bn_device(nn) * log2e;
-        const float Bh = (float)B;
-        c[PC_IS] = (float)v[12];
-        c[PC_XS] = (float)v[17];
-        c[PC_YS] = (float)v[18];
-        c[PC_CS] = (float)cos(v[16]);
-        c[PC_SS] = (float)sin(v[16]);
-        c[PC_AS] = (float)(qs / (R * R));
-        c[PC_BS] = (float)(1.0 / (qs * R * R));
-        c[PC_ES] = (float)(0.5 / nn);
-        c[PC_BSH] = Bh;
-        c[PC_BSL] = (float)(B - (double)Bh);
-    }
+    pc[i] = b;
 }
 
 // ---------------------------------------------------------------------------
@@ -98,7 +83,7 @@ __device__ __forceinline__ double wave_sum(double v)
 // Binned rows [ya, yb) (all < ny) into their ring slots: every pixel in the
 // row's needed range is evaluated; the rest of the row is cleared when the
 // slot is being reused (clear = true).
-__device__ __forceinline__ void fill_rows(const LensGeom &g, const PropC &P, float *ring,
+__device__ __forceinline__ void fill_rows(const LensGeom &g, const PropBlock &P, float *ring,
                                           const uint32_t *__restrict__ evl, const int *__restrict__ evpre,
                                           const int2 *__restrict__ evr, int ya, int yb, bool clear)
 {
@@ -186,7 +171,7 @@ __device__ __forceinline__ double conv_rows(const LensGeom &g, const float *ring
 
 template <int K>
 __global__ void __launch_bounds__(kBlock)
-k_loglike_fp32(const LensGeom g, const float *__restrict__ pc, const float *__restrict__ psf,
+k_loglike_fp32(const LensGeom g, const PropBlock *__restrict__ pc, const float *__restrict__ psf,
                const uint32_t *__restrict__ evl, const int *__restrict__ evpre, const int2 *__restrict__ evr,
                const uint32_t *__restrict__ cvl, const int *__restrict__ cvpre,
                const float *__restrict__ data, const float *__restrict__ wgt, double *__restrict__ out)
@@ -195,12 +180,12 @@ k_loglike_fp32(const LensGeom g, const float *__restrict__ pc, const float *__re
     float *ring = reinterpret_cast<float *>(lds4);
     __shared__ double red[kBlock / 64];
     const int64_t p = blockIdx.x;
-    const float *c = pc + p * kPC;
-    if (c[PC_VALID] == 0.0f) {
+    const PropBlock *c = pc + p;
+    if (c->valid == 0.0) {
         if (threadIdx.x == 0) out[p] = -INFINITY;
         return;
     }
-    const PropC P = load_prop(c);
+    const PropBlock P = *c;
     const int ny = g.ny, r = g.r, H = g.strip_h;
     const int n4 = g.ring_rows * g.ring_w / 4;
     for (int i = threadIdx.x; i < n4; i += blockDim.x) lds4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -236,11 +221,11 @@ k_loglike_fp32(const LensGeom g, const float *__restrict__ pc, const float *__re
 // ---------------------------------------------------------------------------
 // debug model images
 // ---------------------------------------------------------------------------
-__global__ void k_model_binned(const LensGeom g, const float *__restrict__ pc, float *__restrict__ img)
+__global__ void k_model_binned(const LensGeom g, const PropBlock *__restrict__ pc, float *__restrict__ img)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.ny * g.nx) return;
-    const PropC P = load_prop(pc);
+    const PropBlock P = *pc;
     img[i] = binned_pixel(g, P, i / g.nx, i % g.nx);
 }
 
@@ -270,7 +255,7 @@ int choose_kc(int k) { return (k + 6) / 4; }
 
 size_t ring_bytes(const LensGeom &g) { return (size_t)g.ring_rows * g.ring_w * sizeof(float); }
 
-hipError_t launch_prep(const double *d_params, int64_t n, float *d_pc, hipStream_t st)
+hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     const int bs = 256;
@@ -280,14 +265,14 @@ hipError_t launch_prep(const double *d_params, int64_t n, float *d_pc, hipStream
 }
 
 template <int K>
-static hipError_t launch_k(const LensGeom &g, const float *d_pc, int64_t n, double *d_out, hipStream_t st)
+static hipError_t launch_k(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, hipStream_t st)
 {
     hipLaunchKernelGGL(k_loglike_fp32<K>, dim3((unsigned)n), dim3(kBlock), ring_bytes(g), st, g, d_pc,
                        g.psf, g.evl, g.evpre, g.evr, g.cvl, g.cvpre, g.data, g.wgt, d_out);
     return hipGetLastError();
 }
 
-hipError_t launch_loglike_fp32(const LensGeom &g, const float *d_pc, int64_t n, double *d_out, hipStream_t st)
+hipError_t launch_loglike_fp32(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     switch (g.k) {
@@ -302,7 +287,7 @@ hipError_t launch_loglike_fp32(const LensGeom &g, const float *d_pc, int64_t n, 
     }
 }
 
-hipError_t launch_model_image(const LensGeom &g, const float *d_pc, int stage, float *d_img, float *d_tmp,
+hipError_t launch_model_image(const LensGeom &g, const PropBlock *d_pc, int stage, float *d_img, float *d_tmp,
                               hipStream_t st)
 {
     const int npix = g.ny * g.nx;

@@ -34,7 +34,7 @@ namespace {
 constexpr size_t kAlign = 256;
 constexpr int kServeStreams = 4;
 constexpr int64_t kTileMax = 8192;           // proposals per serving launch
-constexpr size_t kBytesPerProposal = lensk::kStride * sizeof(double) + lensk::kPC * sizeof(float) + sizeof(double);
+constexpr size_t kBytesPerProposal = lensk::kStride * sizeof(double) + lensk::kPCBytes + sizeof(double);
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -280,13 +280,13 @@ lens_status stream_scratch(lens_ctx *c, hipStream_t st, size_t bytes, void **out
 
 struct ScratchLayout {
     double *params;
-    float *pc;
+    lensk::PropBlock *pc;
     double *out;
 };
 
 size_t scratch_bytes(int64_t n, bool with_params_out)
 {
-    size_t b = align_up((size_t)n * lensk::kPC * sizeof(float), kAlign);
+    size_t b = align_up((size_t)n * lensk::kPCBytes, kAlign);
     if (with_params_out)
         b += align_up((size_t)n * lensk::kStride * sizeof(double), kAlign) + align_up((size_t)n * sizeof(double), kAlign);
     return b;
@@ -296,8 +296,8 @@ ScratchLayout carve(void *base, int64_t n, bool with_params_out)
 {
     ScratchLayout L{};
     char *p = (char *)base;
-    L.pc = (float *)p;
-    p += align_up((size_t)n * lensk::kPC * sizeof(float), kAlign);
+    L.pc = (lensk::PropBlock *)p;
+    p += align_up((size_t)n * lensk::kPCBytes, kAlign);
     if (with_params_out) {
         L.params = (double *)p;
         p += align_up((size_t)n * lensk::kStride * sizeof(double), kAlign);
@@ -306,7 +306,7 @@ ScratchLayout carve(void *base, int64_t n, bool with_params_out)
     return L;
 }
 
-hipError_t launch_lens(const Lens *L, const double *d_params, float *d_pc, int64_t n, double *d_out,
+hipError_t launch_lens(const Lens *L, const double *d_params, lensk::PropBlock *d_pc, int64_t n, double *d_out,
                        hipStream_t st)
 {
     hipError_t e = lensk::launch_prep(d_params, n, d_pc, st);
@@ -497,9 +497,9 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
         return fail(c, LENS_EINVAL, "image too wide for the LDS line buffer at this PSF size");
     g.strip_h = H;
     g.ring_rows = H + 2 * r;
-    g.sd = (float)(d->pixel_scale / s);
-    g.cfx = (float)(0.5 * ((double)nx * s - 1.0));
-    g.cfy = (float)(0.5 * ((double)ny * s - 1.0));
+    g.sd = d->pixel_scale / s;
+    g.cfx = 0.5 * ((double)nx * s - 1.0);
+    g.cfy = 0.5 * ((double)ny * s - 1.0);
     g.inv_s2 = (float)(1.0 / ((double)s * s));
     g.norm = norm;
     // host images
@@ -712,7 +712,7 @@ extern "C" lens_status lens_loglike_batch_device(lens_ctx *c, lens_id id, const 
         return LENS_OK;
     }
     DeviceGuard dg(c->device);
-    hipStream_t hs = stream ? (hipStream_t)stream : c->stream;
+    hipStream_t hs = (hipStream_t)stream;  // NULL: the default stream
     void *scr = nullptr;
     lens_status rs = stream_scratch(c, hs, scratch_bytes(n, false), &scr);
     if (rs == LENS_OK) {
@@ -759,7 +759,7 @@ extern "C" lens_status lens_loglike_multi(lens_ctx *c, int32_t nlens, const lens
             if (e == hipSuccess) e = lensk::launch_prep(S.params, tot, S.pc, c->stream);
             int64_t off = 0;
             for (int i = 0; i < nlens && e == hipSuccess; ++i) {
-                if (counts[i] > 0) e = lensk::launch_loglike_fp32(Ls[i]->g, S.pc + off * lensk::kPC, counts[i], S.out + off, c->stream);
+                if (counts[i] > 0) e = lensk::launch_loglike_fp32(Ls[i]->g, S.pc + off, counts[i], S.out + off, c->stream);
                 off += counts[i];
             }
             if (e == hipSuccess)
@@ -793,15 +793,16 @@ extern "C" lens_status lens_model_image(lens_ctx *c, lens_id id, const double *p
         if (rs == LENS_OK) {
             char *b = (char *)dbuf;
             double *dp = (double *)b;
-            float *dpc = (float *)(b + 2048);
+            lensk::PropBlock *dpc = (lensk::PropBlock *)(b + 2048);
             float *img = (float *)(b + 4096);
             float *tmp = (float *)(b + 4096 + align_up((size_t)npix * 4, kAlign));
-            std::vector<float> pc(lensk::kPC), hi((size_t)npix);
+            lensk::PropBlock pc{};
+            std::vector<float> hi((size_t)npix);
             hipError_t e = hipMemcpyAsync(dp, params1, lensk::kStride * sizeof(double), hipMemcpyHostToDevice, c->stream);
             if (e == hipSuccess) e = lensk::launch_prep(dp, 1, dpc, c->stream);
-            if (e == hipSuccess) e = hipMemcpyAsync(pc.data(), dpc, lensk::kPC * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipMemcpyAsync(&pc, dpc, sizeof(pc), hipMemcpyDeviceToHost, c->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-            if (e == hipSuccess && pc[lensk::PC_VALID] == 0.0f) {
+            if (e == hipSuccess && pc.valid == 0.0) {
                 rs = fail(c, LENS_EINVAL, "proposal outside the parameter domain");
             } else {
                 if (e == hipSuccess) e = lensk::launch_model_image(L->g, dpc, stage, img, tmp, c->stream);
@@ -868,7 +869,7 @@ void ensure_arena(lens_ctx *c)
 
 size_t tile_bytes(int64_t n)
 {
-    return align_up((size_t)n * lensk::kStride * 8, kAlign) + align_up((size_t)n * lensk::kPC * 4, kAlign) +
+    return align_up((size_t)n * lensk::kStride * 8, kAlign) + align_up((size_t)n * lensk::kPCBytes, kAlign) +
            align_up((size_t)n * 8, kAlign);
 }
 
@@ -902,8 +903,8 @@ void admit(lens_ctx *c)
         char *db = (char *)c->d_arena + off;
         char *hb = c->h_arena + off;
         double *dparams = (double *)db;
-        float *dpc = (float *)(db + align_up((size_t)n * lensk::kStride * 8, kAlign));
-        double *dout = (double *)((char *)dpc + align_up((size_t)n * lensk::kPC * 4, kAlign));
+        lensk::PropBlock *dpc = (lensk::PropBlock *)(db + align_up((size_t)n * lensk::kStride * 8, kAlign));
+        double *dout = (double *)((char *)dpc + align_up((size_t)n * lensk::kPCBytes, kAlign));
         double *hparams = (double *)hb;
         double *hout = (double *)(hb + ((char *)dout - db));
         memcpy(hparams, r->params.data() + t.off * lensk::kStride, (size_t)n * lensk::kStride * 8);
@@ -943,7 +944,7 @@ bool retire(lens_ctx *c)
             r->status = LENS_EDEVICE;
         } else if (!r->cancel) {
             const char *hb = c->h_arena + t.arena_off;
-            const size_t oo = align_up((size_t)t.n * lensk::kStride * 8, kAlign) + align_up((size_t)t.n * lensk::kPC * 4, kAlign);
+            const size_t oo = align_up((size_t)t.n * lensk::kStride * 8, kAlign) + align_up((size_t)t.n * lensk::kPCBytes, kAlign);
             memcpy(r->result.data() + t.off, hb + oo, (size_t)t.n * 8);
         }
         (void)hipEventDestroy(t.ev);

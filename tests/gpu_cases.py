@@ -40,6 +40,30 @@ def rel_err(got, ref, chi2, C):
     return np.where(both_inf, 0.0, e)
 
 
+def fp32_floor(spec, params, chi2, C):
+    """First-order effect on lnL of rounding every model and data pixel to FP32.
+
+    The FP32 path stores the binned image (and the data) in FP32, i.e. with a
+    relative error up to u = 2^-24 per pixel.  Perturbing m_i and d_i by u|m_i|
+    and u|d_i| changes chi^2/2 by at most u sum_i |r_i| (|m_i| + |d_i|) w_i,
+    r_i = (d_i - m_i) w_i.  Returned in the units of rel_err, times 3 for the
+    few roundings that follow (PSF sum, residual)."""
+    import oracle
+    orc = oracle.default()
+    u = 2.0 ** -24
+    out = np.zeros(len(params))
+    sel = spec.mask == 1
+    w = 1.0 / spec.sigma[sel]
+    d = spec.data[sel]
+    for i, p in enumerate(params):
+        if not orc.params_valid(p):
+            continue
+        m = orc.model_image(spec.ny, spec.nx, spec.dpix, spec.s, spec.psf, p, stage=1)[sel]
+        r = (d - m) * w
+        out[i] = 3.0 * u * np.sum(np.abs(r) * (np.abs(m) + np.abs(d)) * w) / (0.5 * chi2[i] + abs(C))
+    return out
+
+
 def custom_spec(seed, ny, nx, dpix, s, psf, mask, nprop, sigma_range=(0.005, 0.02)) -> synth.LensSpec:
     rng = np.random.default_rng(seed)
     truth = synth.draw_params(rng, 1)[0]

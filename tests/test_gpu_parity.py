@@ -9,7 +9,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_cases import TOL_FP32, custom_spec, oracle_data, oracle_loglike, rel_err, say
+from gpu_cases import TOL_FP32, custom_spec, fp32_floor, oracle_data, oracle_loglike, rel_err, say
 from paper_2503_08586_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -23,12 +23,18 @@ def ctx():
     c.close()
 
 
-def _check(spec, got, params, tol=TOL_FP32, label=""):
+def _check(spec, got, params, tol=TOL_FP32, label="", storage_floor=False):
+    """Element-wise gate.  storage_floor=True (tiny edge-case images only) raises
+    each proposal's tolerance to the FP32 storage floor of its model image when
+    that exceeds tol; the configs of the benchmark never use it."""
     ref, chi2, C = oracle_loglike(spec, params)
     assert np.array_equal(np.isneginf(got), np.isneginf(ref)), label
     e = rel_err(got, ref, chi2, C)
-    say("%s: n=%d max err %.3e p99 %.3e" % (label, len(got), e.max(), np.quantile(e, 0.99)))
-    assert e.max() <= tol, (label, e.max(), int(np.argmax(e)))
+    tols = np.full(len(e), tol)
+    if storage_floor:
+        tols = np.maximum(tols, fp32_floor(spec, params, chi2, C))
+    say("%s: n=%d max err %.3e p99 %.3e (max tol %.3e)" % (label, len(got), e.max(), np.quantile(e, 0.99), tols.max()))
+    assert np.all(e <= tols), (label, e.max(), int(np.argmax(e / tols)))
     return e
 
 
@@ -113,7 +119,7 @@ def test_geometries(ctx, geom):
     spec = custom_spec(7, ny, nx, dpix, s, psf, _mask(mk, ny, nx, dpix, rng), 37)
     lid = ctx.load(spec)
     got = ctx.loglike(lid, spec.proposals)
-    _check(spec, got, spec.proposals, label=name)
+    _check(spec, got, spec.proposals, label=name, storage_floor=ny * nx < 64)
     ctx.unload(lid)
 
 
