@@ -57,10 +57,11 @@ __device__ __forceinline__ T horner(const T (&c)[N], T w)
 }
 
 // 2^y for y in [-1022, 1023]: 2^round(y) times a polynomial in the remainder.
-__device__ __forceinline__ double exp2_64(double y)
+template <int N>
+__device__ __forceinline__ double exp2_64(const double (&c)[N], double y)
 {
     const double k = rint(y);
-    return ldexp(horner(kExp2_64, y - k), (int)k);
+    return ldexp(horner(c, y - k), (int)k);
 }
 
 constexpr double kPi2 = 1.5707963267948966;
@@ -96,15 +97,14 @@ __device__ __forceinline__ double sie_a2(double u2, double ce, double bsie, doub
 }
 
 // Elliptical Sersic (Eqs. 8, 10) at offset (dx, dy) from its centre:
-//   I_e exp(-b ((R/R_e)^(1/n) - 1)) = I_e 2^(B (1 - t)),  t = ((R/R_e)^2)^(1/(2n)),  B = b log2 e.
+//   I_e exp(-b ((R/R_e)^(1/n) - 1)) = I_e 2^(B (1 - t)),  t = ((R/R_e)^2)^(1/(2n)),  B = b log2 e,
+// with (R/R_e)^2 = P dx^2 + Q dy^2 + S dx dy, the rotation of Eq. 10 folded into P, Q, S.
 __device__ __forceinline__ double sersic(double dx, double dy, const LightK &L)
 {
-    const double x1 = fma(L.c, dx, L.s * dy);
-    const double x2 = fma(L.c, dy, -(L.s * dx));
-    const double r2 = fma(L.A, x1 * x1, L.Bq * (x2 * x2));
+    const double r2 = fma(L.P, dx * dx, fma(L.Q, dy * dy, L.S * (dx * dy)));
     const double lg = (double)hw_log2((float)r2);
-    const double t = exp2_64(fmin(fmax(L.e * lg, -1000.0), 64.0));
-    return L.I * exp2_64(fmax(L.B * (1.0 - t), -1000.0));
+    const double t = exp2_64(kExp2T64, fmin(fmax(L.e * lg, -1000.0), 64.0));
+    return L.I * exp2_64(kExp2E64, fmax(L.B * (1.0 - t), -1000.0));
 }
 
 // Lens light at theta plus source light at beta = theta - alpha_SIE - alpha_shear (Eqs. 1-2).

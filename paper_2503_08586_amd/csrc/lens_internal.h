@@ -15,8 +15,7 @@ constexpr double kNMin = 0.1, kNMax = 20.0;
 
 // Derived constants of one Sersic component (Sec. 2.4, Eqs. 8, 10).
 struct LightK {
-    double c, s;      // cos, sin of the position angle
-    double A, Bq;     // q / R_e^2, 1 / (q R_e^2): (R_p / R_e)^2 = A x1^2 + Bq x2^2
+    double P, Q, S;   // (R_p/R_e)^2 = P dx^2 + Q dy^2 + S dx dy, the rotation of Eq. 10 folded in
     double e;         // 1 / (2n): t = ((R_p/R_e)^2)^e = (R_p/R_e)^(1/n)
     double B;         // b_n log2(e): I = I_e 2^(B (1 - t))
     double I;         // I_e
@@ -30,7 +29,7 @@ struct alignas(16) PropBlock {
     double bsie, bsc;                          // theta_E sqrt(q), theta_E sqrt(q) / c (0 if c = 0)
     double g1, g2, xs, ys;                     // shear, source centre
     LightK lens, src;
-    double pad[5];
+    double pad[7];
 };
 static_assert(sizeof(PropBlock) == 256, "PropBlock layout");
 constexpr int kPCBytes = (int)sizeof(PropBlock);

@@ -20,11 +20,12 @@ namespace lensk {
 // ---------------------------------------------------------------------------
 __device__ LightK light_constants(double I, double R, double n, double q, double phi)
 {
+    // x1 = c dx + s dy, x2 = -s dx + c dy, (R_p/R_e)^2 = (q x1^2 + x2^2/q) / R_e^2
+    const double c = cos(phi), s = sin(phi), A = q / (R * R), Bq = 1.0 / (q * R * R);
     LightK L;
-    L.c = cos(phi);
-    L.s = sin(phi);
-    L.A = q / (R * R);
-    L.Bq = 1.0 / (q * R * R);
+    L.P = A * c * c + Bq * s * s;
+    L.Q = A * s * s + Bq * c * c;
+    L.S = 2.0 * (A - Bq) * c * s;
     L.e = 0.5 / n;
     L.B = bn_device(n) * 1.4426950408889634;
     L.I = I;
