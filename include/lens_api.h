@@ -38,9 +38,11 @@
  * The domain is: every slot 0..18 finite, theta_E >= 0, each axis ratio in
  * (0, 1], R_l > 0, R_s > 0, n_l and n_s in [0.1, 20].
  *
- * Arithmetic: ray tracing and light in FP32, the PSF convolution in FP32
- * (LENS_PREC_FP32) or as a BF16 matrix-core contraction (the other
- * precisions), the chi-square reduction and the result in FP64.
+ * Arithmetic: the ray trace and the Sersic exponents in FP64 (FP32 hardware
+ * seeds refined by Newton steps, FP32 log2), the binned image rounded to FP32
+ * once, the PSF convolution in FP32 on the vector ALU (LENS_PREC_FP32) or as a
+ * BF16 matrix-core contraction with FP32 accumulation (the other precisions),
+ * the chi-square reduction and the result in FP64.
  *
  * Threading: every entry point is thread-safe.  Errors: every call returns a
  * lens_status; on a call error nothing is written to the outputs and
@@ -184,6 +186,11 @@ lens_status lens_get_stats(lens_ctx *ctx, lens_stats *out);
  * A proposal outside the domain gives LENS_EINVAL. */
 lens_status lens_model_image(lens_ctx *ctx, lens_id id, const double *params1, int32_t stage,
                              double *out_img);
+
+/* Self-test of the device (which = 0: the matrix-core operand layout the
+ * BF16 convolution relies on, a 16x32 by 32x16 product of small integers).
+ * *result = max |device - exact|, 0 when the layout holds. */
+lens_status lens_selftest(lens_ctx *ctx, int32_t which, double *result);
 
 const char *lens_strerror(lens_status st);
 /* Last error message of the calling thread on this context ("" if none). */

@@ -43,7 +43,7 @@ EXPORTED = [
     "lens_init", "lens_shutdown", "lens_load_data", "lens_unload", "lens_get_info",
     "lens_loglike_batch", "lens_loglike_batch_device", "lens_loglike_multi",
     "lens_submit", "lens_poll", "lens_wait", "lens_cancel", "lens_get_stats",
-    "lens_model_image", "lens_strerror", "lens_last_error",
+    "lens_model_image", "lens_selftest", "lens_strerror", "lens_last_error",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -128,6 +128,7 @@ def load():
         "lens_cancel": ([vp, i64], i32),
         "lens_get_stats": ([vp, ctypes.POINTER(lens_stats)], i32),
         "lens_model_image": ([vp, i64, dp, i32, dp], i32),
+        "lens_selftest": ([vp, i32, dp], i32),
         "lens_strerror": ([i32], ctypes.c_char_p),
         "lens_last_error": ([vp], ctypes.c_char_p),
     }
@@ -326,6 +327,12 @@ def lens_model_image(ctx, lens_id, params1, stage: int, ny: int, nx: int) -> np.
     return out
 
 
+def lens_selftest(ctx, which: int = 0) -> float:
+    r = ctypes.c_double()
+    _check(ctx, load().lens_selftest(ctx, which, ctypes.byref(r)))
+    return r.value
+
+
 def lens_strerror(st: int) -> str:
     return load().lens_strerror(st).decode()
 
@@ -402,3 +409,6 @@ class LensContext:
 
     def stats(self) -> dict:
         return lens_get_stats(self.ctx)
+
+    def selftest(self, which=0) -> float:
+        return lens_selftest(self.ctx, which)

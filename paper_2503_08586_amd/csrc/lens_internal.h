@@ -34,14 +34,26 @@ struct alignas(16) PropBlock {
 static_assert(sizeof(PropBlock) == 256, "PropBlock layout");
 constexpr int kPCBytes = (int)sizeof(PropBlock);
 
+// PSF-convolution modes (the public LENS_PREC_* values).
+enum : int { MODE_FP32 = 0, MODE_SPLIT = 1, MODE_BF16 = 2, MODE_SPLIT3 = 3 };
+__host__ __device__ constexpr int mode_planes(int mode)
+{
+    return mode == MODE_SPLIT ? 2 : mode == MODE_SPLIT3 ? 3 : 1;
+}
+
 // Everything a likelihood launch needs to know about one resident lens.
 struct LensGeom {
     int ny, nx, s, k, r;   // rows, columns, supersampling, PSF side, (k-1)/2
     int pitch;             // row pitch (floats) of data and weight, multiple of 4
+    int mode;              // MODE_*
+    int nt;                // threads per workgroup (256 or 512)
     int strip_h;           // output rows per strip
     int ring_rows;         // strip_h + 2r binned rows kept in LDS
-    int ring_w;            // floats per LDS row
-    int kc;                // float4 chunks of the conv window (4*kc >= k + 3)
+    int ring_w;            // elements per LDS row (FP32 ring: floats; MFMA ring: bf16 per plane)
+    int plane;             // MFMA ring: elements per bf16 plane (ring_rows * ring_w)
+    int L;                 // MFMA: window length per segment, 16 + k - 1 rounded up to 8
+    int nchunks;           // MFMA: K-chunks of 32, ceil(k L / 32)
+    int nstrips;           // ceil(ny / strip_h)
     double sd;             // pixel_scale / s: sub-pixel pitch
     double cfx, cfy;       // (nx*s - 1)/2, (ny*s - 1)/2: fine-grid centre
     float inv_s2;          // 1/s^2
@@ -52,16 +64,29 @@ struct LensGeom {
     const uint32_t *evl;   // pixels whose binned value is needed, (y << 16) | x, row-major
     const int *evpre;      // [ny + 1] prefix of evl by row
     const int2 *evr;       // [ny] needed column range [lo, hi) of each row
-    const uint32_t *cvl;   // groups of 4 output pixels covering the mask, (y << 16) | x0
-    const int *cvpre;      // [ny + 1] prefix of cvl by row
+    const uint32_t *cvl;   // FP32 mode: groups of 4 output pixels covering the mask, (y << 16) | x0
+    const int *cvpre;      // FP32 mode: [ny + 1] prefix of cvl by row
+    const uint4 *aop;      // MFMA: Toeplitz A operand, [nchunks][planes][64 lanes] x 8 bf16
+    const uint32_t *seg;   // MFMA: 16-wide output segments (y << 16) | x0, padded per strip to 16
+    const int *tpre;       // MFMA: [nstrips + 1] first tile of each strip
 };
+constexpr uint32_t kDummySeg = 0xffffffffu;
 
 size_t ring_bytes(const LensGeom &g);
 int choose_kc(int k);
+// LDS row width (elements) and bytes per ring row for a mode, PSF side and width
+int ring_width(int mode, int k, int nx);
+size_t ring_row_bytes(int mode, int k, int nx);
+// largest dynamic LDS one workgroup may use on this device
+size_t max_lds_bytes();
+hipError_t set_lds_limits(size_t bytes);
 
 hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, hipStream_t st);
-hipError_t launch_loglike_fp32(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out,
-                               hipStream_t st);
+// the fused likelihood of n proposals of one lens (FP32 or MFMA convolution per g.mode)
+hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out,
+                          hipStream_t st);
+// self-test of the matrix-core operand layout: D = A B for a 16x32 by 32x16 BF16 product
+hipError_t launch_mfma_probe(const uint16_t *d_a, const uint16_t *d_b, float *d_d, hipStream_t st);
 // stage 0: binned image of one proposal into d_img [ny][nx]; stage 1: convolved,
 // using d_tmp [ny][nx] for the binned image.
 hipError_t launch_model_image(const LensGeom &g, const PropBlock *d_pc, int stage, float *d_img,

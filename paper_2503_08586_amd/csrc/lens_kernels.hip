@@ -1,8 +1,11 @@
 // lens_kernels.hip -- HIP kernels of the batched lens log-likelihood (gfx950).
 //
-// k_prep          one thread per proposal: domain check, FP64 b_n, derived FP32 constants.
+// k_prep          one thread per proposal: domain check, FP64 b_n, derived constants.
 // k_loglike_fp32  one workgroup per proposal: the whole forward model and the
-//                 chi-square in one pass, the binned image never leaving LDS.
+//                 chi-square in one pass, the binned image never leaving LDS;
+//                 PSF convolution on the vector ALU in FP32.
+// k_loglike_mfma  the same with the PSF convolution as a BF16 matrix-core
+//                 contraction (plain, hi+lo split or hi+mid+lo split operands).
 // k_model_*       debug: full model images of one proposal.
 //
 // Forward model: Cao et al. (2025), Sec. 2.1 (Eqs. 1-3), Sec. 2.2 (Eq. 5), Sec. 2.4.
@@ -72,8 +75,11 @@ __global__ void __launch_bounds__(256) k_prep(const double *__restrict__ params,
 }
 
 // ---------------------------------------------------------------------------
-// fused FP32 likelihood
+// fused likelihood: shared pieces
 // ---------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 __device__ __forceinline__ double wave_sum(double v)
 {
 #pragma unroll
@@ -81,10 +87,53 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
+// round-to-nearest-even FP32 -> BF16 (finite inputs)
+__device__ __forceinline__ uint16_t bf16_rn(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// How a binned value is kept in the LDS ring: FP32, or NPL BF16 planes whose
+// sum is the value (hi, hi + lo, hi + mid + lo).
+template <int MODE>
+struct RingStore {
+    static constexpr int NPL = mode_planes(MODE);
+    __device__ static void put(void *ring, int plane, int idx, float v)
+    {
+        if (MODE == MODE_FP32) {
+            static_cast<float *>(ring)[idx] = v;
+        } else {
+            uint16_t *b = static_cast<uint16_t *>(ring);
+            const uint16_t h = bf16_rn(v);
+            b[idx] = h;
+            if (NPL >= 2) {
+                const float r1 = v - bf16_f(h);
+                const uint16_t m = bf16_rn(r1);
+                b[plane + idx] = m;
+                if (NPL >= 3) b[2 * plane + idx] = bf16_rn(r1 - bf16_f(m));
+            }
+        }
+    }
+    __device__ static void zero(void *ring, int plane, int idx)
+    {
+        if (MODE == MODE_FP32) {
+            static_cast<float *>(ring)[idx] = 0.0f;
+        } else {
+            uint16_t *b = static_cast<uint16_t *>(ring);
+#pragma unroll
+            for (int p = 0; p < NPL; ++p) b[p * plane + idx] = 0;
+        }
+    }
+};
+
 // Binned rows [ya, yb) (all < ny) into their ring slots: every pixel in the
 // row's needed range is evaluated; the rest of the row is cleared when the
-// slot is being reused (clear = true).
-__device__ __forceinline__ void fill_rows(const LensGeom &g, const PropBlock &P, float *ring,
+// slot is being reused (clear = true).  Ring column of image column x is x + r.
+template <int MODE, int NT>
+__device__ __forceinline__ void fill_rows(const LensGeom &g, const PropBlock &P, void *ring,
                                           const uint32_t *__restrict__ evl, const int *__restrict__ evpre,
                                           const int2 *__restrict__ evr, int ya, int yb, bool clear)
 {
@@ -95,25 +144,70 @@ __device__ __forceinline__ void fill_rows(const LensGeom &g, const PropBlock &P,
             int slot = slot_a + (y - ya);
             if (slot >= RB) slot -= RB;
             const int2 lr = evr[y];
-            for (int x = threadIdx.x; x < nx; x += blockDim.x)
-                if (x < lr.x || x >= lr.y) ring[slot * W + r + x] = 0.0f;
+            for (int x = threadIdx.x; x < nx; x += NT)
+                if (x < lr.x || x >= lr.y) RingStore<MODE>::zero(ring, g.plane, slot * W + r + x);
         }
     }
     const int fb = evpre[yb];
-    for (int f = evpre[ya] + threadIdx.x; f < fb; f += blockDim.x) {
+    for (int f = evpre[ya] + threadIdx.x; f < fb; f += NT) {
         const uint32_t e = evl[f];
         const int y = (int)(e >> 16), x = (int)(e & 0xffffu);
         int slot = slot_a + (y - ya);
         if (slot >= RB) slot -= RB;
-        ring[slot * W + r + x] = binned_pixel(g, P, y, x);
+        RingStore<MODE>::put(ring, g.plane, slot * W + r + x, binned_pixel(g, P, y, x));
     }
 }
 
+// The strip loop shared by both kernels: binned rows enter the ring strip by
+// strip, each binned row is computed once, and conv(y0, y1, strip) adds the
+// chi-square of output rows [y0, y1).
+template <int MODE, int NT, typename Conv>
+__device__ __forceinline__ void strip_loop(const LensGeom &g, const PropBlock &P, void *ring,
+                                           const uint32_t *__restrict__ evl, const int *__restrict__ evpre,
+                                           const int2 *__restrict__ evr, double *__restrict__ out,
+                                           int64_t p, Conv conv)
+{
+    __shared__ double red[NT / 64];
+    const int ny = g.ny, r = g.r, H = g.strip_h, RB = g.ring_rows;
+    const int nwords = (MODE == MODE_FP32 ? RB * g.ring_w : RB * g.ring_w * mode_planes(MODE) / 2) / 4;
+    float4 *r4 = static_cast<float4 *>(ring);
+    for (int i = threadIdx.x; i < nwords; i += NT) r4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    // binned rows [0, r) precede the first strip
+    fill_rows<MODE, NT>(g, P, ring, evl, evpre, evr, 0, min(r, ny), false);
+    double acc = 0.0;
+    int strip = 0;
+    for (int y0 = 0; y0 < ny; y0 += H, ++strip) {
+        __syncthreads();  // the previous strip is done reading the slots reused below
+        const int ya = y0 + r, yb = y0 + H + r;  // new binned rows
+        if (y0 > 0) {
+            for (int y = max(ya, ny); y < yb; ++y) {  // rows past the image: clear reused slots
+                const int slot = (y + r) % RB;
+                for (int x = threadIdx.x; x < g.nx; x += NT) RingStore<MODE>::zero(ring, g.plane, slot * g.ring_w + r + x);
+            }
+        }
+        if (ya < ny) fill_rows<MODE, NT>(g, P, ring, evl, evpre, evr, ya, min(yb, ny), y0 > 0);
+        __syncthreads();
+        acc += conv(y0, min(y0 + H, ny), strip);
+    }
+    acc = wave_sum(acc);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double s = 0.0;
+        for (int w = 0; w < NT / 64; ++w) s += red[w];
+        out[p] = g.norm - 0.5 * s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP32 PSF convolution on the vector ALU
+// ---------------------------------------------------------------------------
 // chi-square contribution of output rows [ya, yb): four horizontally adjacent
 // outputs per thread, the window of each PSF row held in registers, PSF
 // weights read through the scalar cache.  Row partial sums are accumulated
 // separately (blocked summation).
-template <int K>
+template <int K, int NT>
 __device__ __forceinline__ double conv_rows(const LensGeom &g, const float *ring, const float *__restrict__ psf,
                                             const uint32_t *__restrict__ cvl, const int *__restrict__ cvpre,
                                             const float *__restrict__ data, const float *__restrict__ wgt,
@@ -123,7 +217,7 @@ __device__ __forceinline__ double conv_rows(const LensGeom &g, const float *ring
     const int W = g.ring_w, RB = g.ring_rows;
     double acc = 0.0;
     const int gb = cvpre[yb];
-    for (int gi = cvpre[ya] + threadIdx.x; gi < gb; gi += blockDim.x) {
+    for (int gi = cvpre[ya] + threadIdx.x; gi < gb; gi += NT) {
         const uint32_t e = cvl[gi];
         const int y = (int)(e >> 16), x0 = (int)(e & 0xffffu);
         float o0 = 0.f, o1 = 0.f, o2 = 0.f, o3 = 0.f;
@@ -170,8 +264,8 @@ __device__ __forceinline__ double conv_rows(const LensGeom &g, const float *ring
     return acc;
 }
 
-template <int K>
-__global__ void __launch_bounds__(kBlock)
+template <int K, int NT>
+__global__ void __launch_bounds__(NT)
 k_loglike_fp32(const LensGeom g, const PropBlock *__restrict__ pc, const float *__restrict__ psf,
                const uint32_t *__restrict__ evl, const int *__restrict__ evpre, const int2 *__restrict__ evr,
                const uint32_t *__restrict__ cvl, const int *__restrict__ cvpre,
@@ -179,7 +273,6 @@ k_loglike_fp32(const LensGeom g, const PropBlock *__restrict__ pc, const float *
 {
     extern __shared__ float4 lds4[];
     float *ring = reinterpret_cast<float *>(lds4);
-    __shared__ double red[kBlock / 64];
     const int64_t p = blockIdx.x;
     const PropBlock *c = pc + p;
     if (c->valid == 0.0) {
@@ -187,36 +280,132 @@ k_loglike_fp32(const LensGeom g, const PropBlock *__restrict__ pc, const float *
         return;
     }
     const PropBlock P = *c;
-    const int ny = g.ny, r = g.r, H = g.strip_h;
-    const int n4 = g.ring_rows * g.ring_w / 4;
-    for (int i = threadIdx.x; i < n4; i += blockDim.x) lds4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    __syncthreads();
-    // binned rows [0, r) precede the first strip
-    fill_rows(g, P, ring, evl, evpre, evr, 0, min(r, ny), false);
+    strip_loop<MODE_FP32, NT>(g, P, ring, evl, evpre, evr, out, p, [&](int y0, int y1, int) {
+        return conv_rows<K, NT>(g, ring, psf, cvl, cvpre, data, wgt, y0, y1);
+    });
+}
+
+// ---------------------------------------------------------------------------
+// PSF convolution as a BF16 matrix-core contraction
+// ---------------------------------------------------------------------------
+// For a segment of 16 outputs x0..x0+15 of row y,
+//   out[x0 + j] = sum_{a, i} T_a[j, i] w_a[i],  T_a[j, i] = Kf[a][i - j] (0 <= i - j < k),
+//   w_a[i] = binned[y - r + a][x0 - r + i],  i < L = 16 + k - 1 (rounded up to 8),
+// i.e. C = A B with A the banded Toeplitz expansion of the flipped PSF
+// (16 x kL, built once per lens) and the B column of a segment its stacked
+// PSF-row windows.  One v_mfma_f32_16x16x32_bf16 takes 32 of the kL products
+// for 16 segments at once.  Operand layout (wave64): lane l holds A row l%16,
+// B column l%16, K elements 8(l/16)..8(l/16)+7 of the 32; D rows 4(l/16)..+3
+// of column l%16.  Split modes form (a_hi + a_lo)(b_hi + b_lo) without the
+// lo*lo term, or the six products of three planes that reach 2^-24.
+template <int MODE>
+__device__ __forceinline__ f32x4 mfma_products(const bf16x8 (&a)[3], const bf16x8 (&b)[3], f32x4 c)
+{
+    if (MODE == MODE_SPLIT3) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], c, 0, 0, 0);
+    }
+    if (MODE == MODE_SPLIT || MODE == MODE_SPLIT3) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], c, 0, 0, 0);
+    }
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], c, 0, 0, 0);
+}
+
+template <int MODE, int NT>
+__device__ __forceinline__ double conv_mfma(const LensGeom &g, const uint16_t *ring,
+                                            const uint4 *__restrict__ aop, const uint32_t *__restrict__ seg,
+                                            const int *__restrict__ tpre, const float *__restrict__ data,
+                                            const float *__restrict__ wgt, int strip)
+{
+    constexpr int NPL = mode_planes(MODE);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int n = lane & 15, kb = lane >> 4;
+    const int W = g.ring_w, RB = g.ring_rows, L = g.L, nch = g.nchunks, plane = g.plane;
     double acc = 0.0;
-    for (int y0 = 0; y0 < ny; y0 += H) {
-        __syncthreads();  // the previous strip is done reading the slots reused below
-        // new binned rows [y0 + r, y0 + H + r); rows past the image stay zero
-        const int ya = y0 + r, yb = y0 + H + r;
-        if (y0 > 0) {
-            // rows beyond the image: clear their reused slots
-            for (int y = max(ya, ny); y < yb; ++y) {
-                const int slot = (y + r) % g.ring_rows;
-                for (int x = threadIdx.x; x < g.nx; x += blockDim.x) ring[slot * g.ring_w + r + x] = 0.0f;
+    const int t1 = tpre[strip + 1];
+    for (int t = tpre[strip] + wave; t < t1; t += NT / 64) {
+        const uint32_t e = seg[t * 16 + n];
+        const bool dummy = e == kDummySeg;
+        const int y = dummy ? 0 : (int)(e >> 16), x0 = dummy ? 0 : (int)(e & 0xffffu);
+        int slot = y % RB;           // ring slot of binned row y - r + a, a = 0
+        int i = 8 * kb;              // window offset of this lane's K elements, K = 8 kb
+        while (i >= L) {             // (only for L < 32)
+            i -= L;
+            slot = slot + 1 == RB ? 0 : slot + 1;
+        }
+        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        const uint4 *ap = aop + lane;
+        for (int ch = 0; ch < nch; ++ch) {
+            bf16x8 av[3], bv[3];
+            const uint16_t *bp = ring + slot * W + x0 + i;
+#pragma unroll
+            for (int q = 0; q < NPL; ++q) {
+                av[q] = __builtin_bit_cast(bf16x8, ap[q * 64]);
+                bv[q] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(bp + q * plane));
+            }
+            c = mfma_products<MODE>(av, bv, c);
+            ap += NPL * 64;
+            i += 32;
+            while (i >= L) {
+                i -= L;
+                slot = slot + 1 == RB ? 0 : slot + 1;
             }
         }
-        if (ya < ny) fill_rows(g, P, ring, evl, evpre, evr, ya, min(yb, ny), y0 > 0);
-        __syncthreads();
-        acc += conv_rows<K>(g, ring, psf, cvl, cvpre, data, wgt, y0, min(y0 + H, ny));
+        if (!dummy) {
+            const int xo = x0 + 4 * kb;
+            const float4 d = *reinterpret_cast<const float4 *>(data + (size_t)y * g.pitch + xo);
+            const float4 w = *reinterpret_cast<const float4 *>(wgt + (size_t)y * g.pitch + xo);
+            const double r0 = (double)((d.x - c[0]) * w.x);
+            const double r1 = (double)((d.y - c[1]) * w.y);
+            const double r2 = (double)((d.z - c[2]) * w.z);
+            const double r3 = (double)((d.w - c[3]) * w.w);
+            acc = fma(r0, r0, acc);
+            acc = fma(r1, r1, acc);
+            acc = fma(r2, r2, acc);
+            acc = fma(r3, r3, acc);
+        }
     }
-    acc = wave_sum(acc);
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double s = 0.0;
-        for (int w = 0; w < kBlock / 64; ++w) s += red[w];
-        out[p] = g.norm - 0.5 * s;
+    return acc;
+}
+
+template <int MODE, int NT>
+__global__ void __launch_bounds__(NT)
+k_loglike_mfma(const LensGeom g, const PropBlock *__restrict__ pc, const uint32_t *__restrict__ evl,
+               const int *__restrict__ evpre, const int2 *__restrict__ evr, const uint4 *__restrict__ aop,
+               const uint32_t *__restrict__ seg, const int *__restrict__ tpre, const float *__restrict__ data,
+               const float *__restrict__ wgt, double *__restrict__ out)
+{
+    extern __shared__ float4 lds4[];
+    uint16_t *ring = reinterpret_cast<uint16_t *>(lds4);
+    const int64_t p = blockIdx.x;
+    const PropBlock *c = pc + p;
+    if (c->valid == 0.0) {
+        if (threadIdx.x == 0) out[p] = -INFINITY;
+        return;
     }
+    const PropBlock P = *c;
+    strip_loop<MODE, NT>(g, P, ring, evl, evpre, evr, out, p, [&](int, int, int strip) {
+        return conv_mfma<MODE, NT>(g, ring, aop, seg, tpre, data, wgt, strip);
+    });
+}
+
+__global__ void k_mfma_probe(const uint16_t *__restrict__ a, const uint16_t *__restrict__ b, float *__restrict__ d)
+{
+    // a: 16 x 32 row-major, b: 32 x 16 row-major, d: 16 x 16 row-major; one wave
+    const int l = threadIdx.x, n = l & 15, kb = l >> 4;
+    bf16x8 av, bv;
+    uint16_t ta[8], tb[8];
+    for (int e = 0; e < 8; ++e) {
+        ta[e] = a[n * 32 + 8 * kb + e];
+        tb[e] = b[(8 * kb + e) * 16 + n];
+    }
+    av = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(ta));
+    bv = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(tb));
+    f32x4 c = {0.f, 0.f, 0.f, 0.f};
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+    for (int v = 0; v < 4; ++v) d[(4 * kb + v) * 16 + n] = c[v];
 }
 
 // ---------------------------------------------------------------------------
@@ -254,7 +443,28 @@ __global__ void k_model_conv(const LensGeom g, const float *__restrict__ img, fl
 // ---------------------------------------------------------------------------
 int choose_kc(int k) { return (k + 6) / 4; }
 
-size_t ring_bytes(const LensGeom &g) { return (size_t)g.ring_rows * g.ring_w * sizeof(float); }
+int ring_width(int mode, int k, int nx)
+{
+    if (mode == MODE_FP32) return (nx + 3) / 4 * 4 + 4 * choose_kc(k);
+    const int L = (16 + k - 1 + 7) / 8 * 8;
+    return (nx + 15) / 16 * 16 + L;
+}
+
+size_t ring_row_bytes(int mode, int k, int nx)
+{
+    return (size_t)ring_width(mode, k, nx) * (mode == MODE_FP32 ? 4 : 2 * mode_planes(mode));
+}
+
+size_t ring_bytes(const LensGeom &g) { return (size_t)g.ring_rows * ring_row_bytes(g.mode, g.k, g.nx); }
+
+size_t max_lds_bytes()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 65536;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+        return 65536;
+    return (size_t)v;
+}
 
 hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, hipStream_t st)
 {
@@ -265,20 +475,20 @@ hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, hipSt
     return hipGetLastError();
 }
 
-template <int K>
+template <int K, int NT>
 static hipError_t launch_k(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_loglike_fp32<K>, dim3((unsigned)n), dim3(kBlock), ring_bytes(g), st, g, d_pc,
+    hipLaunchKernelGGL((k_loglike_fp32<K, NT>), dim3((unsigned)n), dim3(NT), ring_bytes(g), st, g, d_pc,
                        g.psf, g.evl, g.evpre, g.evr, g.cvl, g.cvpre, g.data, g.wgt, d_out);
     return hipGetLastError();
 }
 
-hipError_t launch_loglike_fp32(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, hipStream_t st)
+template <int NT>
+static hipError_t launch_fp32_nt(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, hipStream_t st)
 {
-    if (n <= 0) return hipSuccess;
     switch (g.k) {
 #define LENS_K(KK) \
-    case KK: return launch_k<KK>(g, d_pc, n, d_out, st);
+    case KK: return launch_k<KK, NT>(g, d_pc, n, d_out, st);
         LENS_K(1) LENS_K(3) LENS_K(5) LENS_K(7) LENS_K(9) LENS_K(11) LENS_K(13) LENS_K(15)
         LENS_K(17) LENS_K(19) LENS_K(21) LENS_K(23) LENS_K(25) LENS_K(27) LENS_K(29) LENS_K(31)
         LENS_K(33) LENS_K(35) LENS_K(37) LENS_K(39) LENS_K(41) LENS_K(43) LENS_K(45) LENS_K(47)
@@ -286,6 +496,72 @@ hipError_t launch_loglike_fp32(const LensGeom &g, const PropBlock *d_pc, int64_t
 #undef LENS_K
     default: return hipErrorInvalidValue;
     }
+}
+
+template <int MODE, int NT>
+static hipError_t launch_m(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, hipStream_t st)
+{
+    hipLaunchKernelGGL((k_loglike_mfma<MODE, NT>), dim3((unsigned)n), dim3(NT), ring_bytes(g), st, g, d_pc,
+                       g.evl, g.evpre, g.evr, g.aop, g.seg, g.tpre, g.data, g.wgt, d_out);
+    return hipGetLastError();
+}
+
+template <int NT>
+static hipError_t launch_nt(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, hipStream_t st)
+{
+    switch (g.mode) {
+    case MODE_FP32: return launch_fp32_nt<NT>(g, d_pc, n, d_out, st);
+    case MODE_BF16: return launch_m<MODE_BF16, NT>(g, d_pc, n, d_out, st);
+    case MODE_SPLIT: return launch_m<MODE_SPLIT, NT>(g, d_pc, n, d_out, st);
+    case MODE_SPLIT3: return launch_m<MODE_SPLIT3, NT>(g, d_pc, n, d_out, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    if (g.nt == 512) return launch_nt<512>(g, d_pc, n, d_out, st);
+    if (g.nt == 256) return launch_nt<256>(g, d_pc, n, d_out, st);
+    return hipErrorInvalidValue;
+}
+
+template <int NT>
+static hipError_t set_limits_nt(int bytes)
+{
+    hipError_t e = hipSuccess;
+#define LENS_K(KK)                                                                                   \
+    if (e == hipSuccess)                                                                             \
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_loglike_fp32<KK, NT>),             \
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    LENS_K(1) LENS_K(3) LENS_K(5) LENS_K(7) LENS_K(9) LENS_K(11) LENS_K(13) LENS_K(15)
+    LENS_K(17) LENS_K(19) LENS_K(21) LENS_K(23) LENS_K(25) LENS_K(27) LENS_K(29) LENS_K(31)
+    LENS_K(33) LENS_K(35) LENS_K(37) LENS_K(39) LENS_K(41) LENS_K(43) LENS_K(45) LENS_K(47)
+    LENS_K(49) LENS_K(51) LENS_K(53) LENS_K(55) LENS_K(57) LENS_K(59) LENS_K(61) LENS_K(63)
+#undef LENS_K
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_BF16, NT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT, NT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    if (e == hipSuccess)
+        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT3, NT>),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    return e;
+}
+
+hipError_t set_lds_limits(size_t bytes)
+{
+    hipError_t e = set_limits_nt<256>((int)bytes);
+    if (e == hipSuccess) e = set_limits_nt<512>((int)bytes);
+    return e;
+}
+
+hipError_t launch_mfma_probe(const uint16_t *d_a, const uint16_t *d_b, float *d_d, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, st, d_a, d_b, d_d);
+    return hipGetLastError();
 }
 
 hipError_t launch_model_image(const LensGeom &g, const PropBlock *d_pc, int stage, float *d_img, float *d_tmp,

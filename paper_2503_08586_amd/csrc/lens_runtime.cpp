@@ -123,6 +123,31 @@ struct Arena {
 
 thread_local std::unordered_map<const void *, std::string> t_err;
 
+// round-to-nearest-even FP32 -> BF16 and the plane split v = p0 + p1 (+ p2)
+uint16_t bf16_rn_host(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+float bf16_to_float(uint16_t h)
+{
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+void split_bf16(float v, int npl, uint16_t *out)
+{
+    for (int q = 0; q < npl; ++q) {
+        out[q] = bf16_rn_host(v);
+        v -= bf16_to_float(out[q]);
+    }
+}
+
 }  // namespace
 
 struct lens_ctx {
@@ -133,6 +158,7 @@ struct lens_ctx {
     lens_dev_free_fn dfree = nullptr;
     void *user = nullptr;
     int64_t budget = 0;
+    size_t lds_max = 65536;               // dynamic LDS one workgroup may use
     std::atomic<int64_t> used{0};
     std::atomic<int> dev_error{0};
 
@@ -311,7 +337,7 @@ hipError_t launch_lens(const Lens *L, const double *d_params, lensk::PropBlock *
 {
     hipError_t e = lensk::launch_prep(d_params, n, d_pc, st);
     if (e != hipSuccess) return e;
-    return lensk::launch_loglike_fp32(L->g, d_pc, n, d_out, st);
+    return lensk::launch_loglike(L->g, d_pc, n, d_out, st);
 }
 
 void scheduler_main(lens_ctx *c);
@@ -351,6 +377,11 @@ extern "C" lens_status lens_init(const lens_init_opts *opts, lens_ctx **out)
     for (int i = 0; i < kServeStreams; ++i)
         if (hipStreamCreateWithFlags(&c->sstreams[i], hipStreamNonBlocking) != hipSuccess) return LENS_EDEVICE;
     c->stats.hbm_budget_bytes = c->budget;
+    {
+        const size_t m = lensk::max_lds_bytes();
+        if (m > 65536 && lensk::set_lds_limits(m) == hipSuccess) c->lds_max = m;
+        else (void)hipGetLastError();
+    }
     lens_ctx *raw = c.release();
     raw->sched = std::thread(scheduler_main, raw);
     *out = raw;
@@ -439,7 +470,8 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     if (s < 1 || s > 8) return fail(c, LENS_EINVAL, "supersample must be in 1..8");
     if (k < 1 || k > lensk::kMaxK || (k & 1) == 0) return fail(c, LENS_EINVAL, "psf_size must be odd, 1..63");
     if (!d->psf || !d->data || !d->sigma || !d->mask) return fail(c, LENS_EINVAL, "null array in descriptor");
-    if (d->precision != LENS_PREC_FP32) return fail(c, LENS_EINVAL, "precision mode not available");
+    if (d->precision < LENS_PREC_FP32 || d->precision > LENS_PREC_BF16_SPLIT3)
+        return fail(c, LENS_EINVAL, "unknown precision mode");
     const int64_t npix = (int64_t)ny * nx;
     for (int i = 0; i < k * k; ++i)
         if (!std::isfinite(d->psf[i])) return fail(c, LENS_EINVAL, "non-finite PSF value");
@@ -455,7 +487,8 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     }
     const int r = (k - 1) / 2;
     const int kc = lensk::choose_kc(k);
-    const int pitch = (int)align_up((size_t)nx, 4);
+    const int mode = d->precision;  // LENS_PREC_* equal lensk::MODE_*
+    const int pitch = (int)align_up((size_t)nx, 16);
     // masked column range of each row
     std::vector<int> mlo(ny, INT_MAX), mhi(ny, INT_MIN);
     for (int y = 0; y < ny; ++y)
@@ -487,16 +520,56 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     }
     evpre[ny] = (int)evl.size();
     cvpre[ny] = (int)cvl.size();
-    // strip height: as tall as fits 64 KB of LDS, at most 16 rows
+    // Workgroup shape: strips of up to 16 rows; 256 threads while the ring fits
+    // 40 KB (4 workgroups, i.e. 4 waves per SIMD, share a CU's 160 KB), else
+    // 512 threads under 80 KB, else the device's per-workgroup maximum.
     LensGeom g{};
-    g.ny = ny; g.nx = nx; g.s = s; g.k = k; g.r = r; g.pitch = pitch; g.kc = kc;
-    g.ring_w = (int)align_up((size_t)nx, 4) + 4 * kc;
-    int H = 16;
-    while (H > 1 && (size_t)(H + 2 * r) * g.ring_w * 4 > 65536) --H;
-    if ((size_t)(H + 2 * r) * g.ring_w * 4 > 65536)
-        return fail(c, LENS_EINVAL, "image too wide for the LDS line buffer at this PSF size");
+    g.ny = ny; g.nx = nx; g.s = s; g.k = k; g.r = r; g.pitch = pitch; g.mode = mode;
+    g.ring_w = lensk::ring_width(mode, k, nx);
+    const size_t row_b = lensk::ring_row_bytes(mode, k, nx);
+    const size_t lds_max = c->lds_max;
+    auto rows_fit = [&](size_t budget) { return (int)std::min<size_t>(budget / row_b, 1 << 20) - 2 * r; };
+    int H = std::min(16, rows_fit(40960));
+    int nt = 256;
+    if (H < 8) {
+        nt = 512;
+        H = std::min(16, rows_fit(std::min<size_t>(81920, lds_max)));
+    }
+    if (H < 4) H = std::min(16, rows_fit(lds_max));
+    if (H < 1) return fail(c, LENS_EINVAL, "image too wide for the LDS line buffer at this PSF size");
+    g.nt = nt;
     g.strip_h = H;
     g.ring_rows = H + 2 * r;
+    g.plane = g.ring_rows * g.ring_w;
+    g.nstrips = (ny + H - 1) / H;
+    // MFMA operands: 16-wide output segments per strip (padded to tiles of 16)
+    // and the banded Toeplitz expansion of the flipped PSF, split into BF16 planes
+    std::vector<uint32_t> seg;
+    std::vector<int> tpre(g.nstrips + 1, 0);
+    std::vector<uint16_t> aop;
+    if (mode != LENS_PREC_FP32) {
+        g.L = (int)align_up((size_t)(16 + k - 1), 8);
+        g.nchunks = (int)((k * g.L + 31) / 32);
+        for (int st = 0; st < g.nstrips; ++st) {
+            tpre[st] = (int)(seg.size() / 16);
+            for (int y = st * H; y < std::min(ny, (st + 1) * H); ++y)
+                if (mhi[y] > mlo[y])
+                    for (int x0 = mlo[y] & ~15; x0 < mhi[y]; x0 += 16) seg.push_back(((uint32_t)y << 16) | (uint32_t)x0);
+            while (seg.size() % 16) seg.push_back(lensk::kDummySeg);
+        }
+        tpre[g.nstrips] = (int)(seg.size() / 16);
+        const int npl = lensk::mode_planes(mode);
+        aop.assign((size_t)g.nchunks * npl * 64 * 8, 0);
+        for (int ch = 0; ch < g.nchunks; ++ch)
+            for (int lane = 0; lane < 64; ++lane)
+                for (int e = 0; e < 8; ++e) {
+                    const int K = 32 * ch + 8 * (lane >> 4) + e, a = K / g.L, i = K % g.L, b = i - (lane & 15);
+                    const float v = (a < k && b >= 0 && b < k) ? (float)d->psf[(size_t)(k - 1 - a) * k + (k - 1 - b)] : 0.0f;
+                    uint16_t pl[3];
+                    split_bf16(v, npl, pl);
+                    for (int q = 0; q < npl; ++q) aop[(((size_t)ch * npl + q) * 64 + lane) * 8 + e] = pl[q];
+                }
+    }
     g.sd = d->pixel_scale / s;
     g.cfx = 0.5 * ((double)nx * s - 1.0);
     g.cfy = 0.5 * ((double)ny * s - 1.0);
@@ -523,6 +596,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     const size_t o_psf = place(hk.size() * 4), o_d = place(hd.size() * 4), o_w = place(hw.size() * 4);
     const size_t o_evl = place(evl.size() * 4), o_evpre = place(evpre.size() * 4), o_evr = place(evr.size() * 8);
     const size_t o_cvl = place(cvl.size() * 4), o_cvpre = place(cvpre.size() * 4);
+    const size_t o_aop = place(aop.size() * 2), o_seg = place(seg.size() * 4), o_tpre = place(tpre.size() * 4);
     const size_t total = off;
     DeviceGuard dg(c->device);
     if (!charge(c, (int64_t)total)) return fail(c, LENS_ENOMEM, "HBM budget exhausted");
@@ -539,7 +613,9 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     } cp[] = {{o_psf, hk.data(), hk.size() * 4},     {o_d, hd.data(), hd.size() * 4},
               {o_w, hw.data(), hw.size() * 4},       {o_evl, evl.data(), evl.size() * 4},
               {o_evpre, evpre.data(), evpre.size() * 4}, {o_evr, evr.data(), evr.size() * 8},
-              {o_cvl, cvl.data(), cvl.size() * 4},   {o_cvpre, cvpre.data(), cvpre.size() * 4}};
+              {o_cvl, cvl.data(), cvl.size() * 4},   {o_cvpre, cvpre.data(), cvpre.size() * 4},
+              {o_aop, aop.data(), aop.size() * 2},   {o_seg, seg.data(), seg.size() * 4},
+              {o_tpre, tpre.data(), tpre.size() * 4}};
     for (auto &e : cp) {
         if (!e.n) continue;
         hipError_t he = hipMemcpyAsync(b + e.o, e.src, e.n, hipMemcpyHostToDevice, c->stream);
@@ -563,6 +639,9 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     g.evr = (const int2 *)(b + o_evr);
     g.cvl = (const uint32_t *)(b + o_cvl);
     g.cvpre = (const int *)(b + o_cvpre);
+    g.aop = (const uint4 *)(b + o_aop);
+    g.seg = (const uint32_t *)(b + o_seg);
+    g.tpre = (const int *)(b + o_tpre);
     Lens *L = new Lens();
     L->g = g;
     L->precision = d->precision;
@@ -759,7 +838,7 @@ extern "C" lens_status lens_loglike_multi(lens_ctx *c, int32_t nlens, const lens
             if (e == hipSuccess) e = lensk::launch_prep(S.params, tot, S.pc, c->stream);
             int64_t off = 0;
             for (int i = 0; i < nlens && e == hipSuccess; ++i) {
-                if (counts[i] > 0) e = lensk::launch_loglike_fp32(Ls[i]->g, S.pc + off, counts[i], S.out + off, c->stream);
+                if (counts[i] > 0) e = lensk::launch_loglike(Ls[i]->g, S.pc + off, counts[i], S.out + off, c->stream);
                 off += counts[i];
             }
             if (e == hipSuccess)
@@ -1109,5 +1188,40 @@ extern "C" lens_status lens_get_stats(lens_ctx *c, lens_stats *out)
     out->inflight = (int64_t)c->running.size();
     out->hbm_budget_bytes = c->budget;
     out->hbm_used_bytes = c->used.load();
+    return LENS_OK;
+}
+
+extern "C" lens_status lens_selftest(lens_ctx *c, int32_t which, double *result)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (!result || which != 0) return fail(c, LENS_EINVAL, "unknown self-test");
+    DeviceGuard dg(c->device);
+    // D = A B, A 16x32 and B 32x16 with small integers (exact in BF16 and FP32)
+    std::vector<uint16_t> ha(16 * 32), hb(32 * 16);
+    std::vector<double> ref(16 * 16, 0.0);
+    for (int i = 0; i < 16; ++i)
+        for (int kk = 0; kk < 32; ++kk) ha[i * 32 + kk] = bf16_rn_host((float)((i * 7 + kk * 3) % 11 - 5));
+    for (int kk = 0; kk < 32; ++kk)
+        for (int j = 0; j < 16; ++j) hb[kk * 16 + j] = bf16_rn_host((float)((kk * 5 + j * 2) % 9 - 4));
+    for (int i = 0; i < 16; ++i)
+        for (int j = 0; j < 16; ++j)
+            for (int kk = 0; kk < 32; ++kk) ref[i * 16 + j] += (double)bf16_to_float(ha[i * 32 + kk]) * bf16_to_float(hb[kk * 16 + j]);
+    std::lock_guard<std::mutex> lk(c->sync_mu);
+    void *dbuf = nullptr;
+    lens_status rs = stream_scratch(c, c->stream, 4096, &dbuf);
+    if (rs != LENS_OK) return rs;
+    uint16_t *da = (uint16_t *)dbuf, *db = da + 16 * 32;
+    float *dd = (float *)((char *)dbuf + 2048);
+    std::vector<float> hd(256);
+    hipError_t e = hipMemcpyAsync(da, ha.data(), ha.size() * 2, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(db, hb.data(), hb.size() * 2, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = lensk::launch_mfma_probe(da, db, dd, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(hd.data(), dd, 256 * 4, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "lens_selftest");
+    double err = 0.0;
+    for (int i = 0; i < 256; ++i) err = std::max(err, std::fabs((double)hd[i] - ref[i]));
+    *result = err;
     return LENS_OK;
 }

@@ -9,7 +9,7 @@ import math
 import numpy as np
 import pytest
 
-from gpu_cases import TOL_FP32, custom_spec, fp32_floor, oracle_data, oracle_loglike, rel_err, say
+from gpu_cases import TOL_BF16, TOL_FP32, custom_spec, fp32_floor, oracle_data, oracle_loglike, rel_err, say
 from paper_2503_08586_amd import synth
 
 pytestmark = pytest.mark.gpu
@@ -23,16 +23,23 @@ def ctx():
     c.close()
 
 
-def _check(spec, got, params, tol=TOL_FP32, label="", storage_floor=False):
+# storage unit of each convolution mode: FP32, hi+lo BF16 (two planes of 8
+# significant bits: 2^-17 relative), plain BF16, hi+mid+lo BF16
+UNIT = {0: 2.0 ** -24, 1: 2.0 ** -17, 2: 2.0 ** -8, 3: 2.0 ** -24}
+MODE_TOL = {0: TOL_FP32, 1: TOL_FP32, 2: TOL_BF16, 3: TOL_FP32}
+MODES = [("fp32", 0), ("split", 1), ("bf16", 2), ("split3", 3)]
+
+
+def _check(spec, got, params, tol=TOL_FP32, label="", storage_floor=False, unit=2.0 ** -24):
     """Element-wise gate.  storage_floor=True (tiny edge-case images only) raises
-    each proposal's tolerance to the FP32 storage floor of its model image when
-    that exceeds tol; the configs of the benchmark never use it."""
+    each proposal's tolerance to the storage floor of its model image in the
+    mode's unit when that exceeds tol; the benchmark configs never use it."""
     ref, chi2, C = oracle_loglike(spec, params)
     assert np.array_equal(np.isneginf(got), np.isneginf(ref)), label
     e = rel_err(got, ref, chi2, C)
     tols = np.full(len(e), tol)
     if storage_floor:
-        tols = np.maximum(tols, fp32_floor(spec, params, chi2, C))
+        tols = np.maximum(tols, fp32_floor(spec, params, chi2, C) * unit / 2.0 ** -24)
     say("%s: n=%d max err %.3e p99 %.3e (max tol %.3e)" % (label, len(got), e.max(), np.quantile(e, 0.99), tols.max()))
     assert np.all(e <= tols), (label, e.max(), int(np.argmax(e / tols)))
     return e
@@ -109,17 +116,62 @@ def _mask(kind, ny, nx, dpix, rng):
     return (rng.random((ny, nx)) < 0.3).astype(np.uint8)
 
 
-@pytest.mark.parametrize("geom", GEOMS, ids=[g[0] for g in GEOMS])
-def test_geometries(ctx, geom):
+_geom_cache = {}
+
+
+def _geom_spec(geom):
     name, ny, nx, dpix, s, k, mk = geom
-    say("case: geometry %s" % name)
-    rng = np.random.default_rng(sum(map(ord, name)))
-    psf = synth.gaussian_psf(k, 3.0 * dpix, dpix) if k > 1 else np.ones((1, 1))
-    psf = psf * (1.0 + 0.3 * rng.random(psf.shape))      # asymmetric, not normalised
-    spec = custom_spec(7, ny, nx, dpix, s, psf, _mask(mk, ny, nx, dpix, rng), 37)
-    lid = ctx.load(spec)
+    if name not in _geom_cache:
+        rng = np.random.default_rng(sum(map(ord, name)))
+        psf = synth.gaussian_psf(k, 3.0 * dpix, dpix) if k > 1 else np.ones((1, 1))
+        psf = psf * (1.0 + 0.3 * rng.random(psf.shape))      # asymmetric, not normalised
+        _geom_cache[name] = custom_spec(7, ny, nx, dpix, s, psf, _mask(mk, ny, nx, dpix, rng), 37)
+    return _geom_cache[name]
+
+
+@pytest.mark.parametrize("mode", MODES, ids=[m[0] for m in MODES])
+@pytest.mark.parametrize("geom", GEOMS, ids=[g[0] for g in GEOMS])
+def test_geometries(ctx, geom, mode):
+    name, ny, nx = geom[0], geom[1], geom[2]
+    mname, m = mode
+    say("case: geometry %s, mode %s" % (name, mname))
+    spec = _geom_spec(geom)
+    lid = ctx.load(spec, precision=m)
     got = ctx.loglike(lid, spec.proposals)
-    _check(spec, got, spec.proposals, label=name, storage_floor=ny * nx < 64)
+    _check(spec, got, spec.proposals, tol=MODE_TOL[m], label="%s/%s" % (name, mname),
+           storage_floor=ny * nx < 64, unit=UNIT[m])
+    ctx.unload(lid)
+
+
+def test_mfma_operand_layout(ctx):
+    say("case: matrix-core operand layout self-test")
+    assert ctx.selftest(0) == 0.0
+
+
+@pytest.mark.parametrize("mode", MODES, ids=[m[0] for m in MODES])
+def test_precision_workload(ctx, mode):
+    """200x200 px, s = 4, 41x41 Moffat PSF: the precision workload's lens shape."""
+    mname, m = mode
+    say("case: 200x200 s=4 Moffat k=41, mode %s, 24 proposals" % mname)
+    spec = synth.config4(nlens=1, nprop=24)[0]
+    oracle_data(spec)
+    lid = ctx.load(spec, precision=m)
+    got = ctx.loglike(lid, spec.proposals)
+    _check(spec, got, spec.proposals, tol=MODE_TOL[m], label="precision/%s" % mname)
+    t = ctx.loglike(lid, spec.truth[None, :])
+    _check(spec, t, spec.truth[None, :], tol=MODE_TOL[m], label="precision truth/%s" % mname)
+    ctx.unload(lid)
+
+
+def test_mfma_batch_composition_bitwise(ctx):
+    say("case: batch composition, split mode")
+    spec = synth.config1(nprop=500)[0]
+    oracle_data(spec)
+    lid = ctx.load(spec, precision=1)
+    full = ctx.loglike(lid, spec.proposals)
+    perm = np.random.default_rng(2).permutation(500)
+    assert np.array_equal(full[perm], ctx.loglike(lid, spec.proposals[perm]))
+    assert np.array_equal(full[100:133], ctx.loglike(lid, spec.proposals[100:133]))
     ctx.unload(lid)
 
 
