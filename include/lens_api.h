@@ -98,6 +98,10 @@ typedef struct lens_init_opts {
     lens_dev_free_fn dev_free;
     void *alloc_user;
     void *stream;               /* hipStream_t for the blocking calls; NULL: a library-owned stream */
+    int32_t autotune;           /* 1: time candidate strip heights and workgroup sizes for every new
+                                   lens shape at load (cached per shape bucket, and in the file named
+                                   by the LENS_AUTOTUNE_CACHE environment variable if set); 0: a
+                                   fixed rule from the LDS footprint */
 } lens_init_opts;
 
 /* One observed lens image.  All arrays are host memory, row-major, copied by
@@ -160,7 +164,13 @@ lens_status lens_loglike_batch_device(lens_ctx *ctx, lens_id id, const double *d
 
 /* Many lenses in one persistent launch.  ids[i] with counts[i] proposals;
  * params holds the proposals of lens 0, then lens 1, ... ([sum counts][20]),
- * out the results in the same order.  Blocking, host buffers. */
+ * out the results in the same order.  Blocking, host buffers.  Workgroups
+ * pull (lens, proposal) items, longest first, from a device work counter; the
+ * call shape (ids and counts) is captured once as a hipGraph and replayed on
+ * later calls of the same shape (the 8 most recent shapes are kept).  Lenses
+ * of different precision or workgroup size go to separate persistent launches
+ * inside the same graph.  Every result equals the single-lens result bit for
+ * bit. */
 lens_status lens_loglike_multi(lens_ctx *ctx, int32_t nlens, const lens_id *ids,
                                const int64_t *counts, const double *params, double *out);
 

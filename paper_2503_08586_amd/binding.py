@@ -60,6 +60,7 @@ class lens_init_opts(ctypes.Structure):
         ("dev_free", FREE_FN),
         ("alloc_user", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
+        ("autotune", ctypes.c_int32),
     ]
 
 
@@ -196,7 +197,7 @@ _hooks_by_ctx = {}
 
 def lens_init(device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 0,
               nonblocking_submit: bool = False, use_torch_allocator: bool = True,
-              stream: Optional[int] = None):
+              stream: Optional[int] = None, autotune: bool = False):
     lib = load()
     o = lens_init_opts()
     o.device = device
@@ -209,6 +210,7 @@ def lens_init(device: int = 0, hbm_budget_bytes: int = 0, max_inflight: int = 0,
         o.dev_alloc = hooks.alloc
         o.dev_free = hooks.free
     o.stream = stream
+    o.autotune = 1 if autotune else 0
     ctx = ctypes.c_void_p()
     st = lib.lens_init(ctypes.byref(o), ctypes.byref(ctx))
     if st != LENS_OK:

@@ -67,10 +67,9 @@ struct LensGeom {
     const uint32_t *cvl;   // FP32 mode: groups of 4 output pixels covering the mask, (y << 16) | x0
     const int *cvpre;      // FP32 mode: [ny + 1] prefix of cvl by row
     const uint4 *aop;      // MFMA: Toeplitz A operand, [nchunks][planes][64 lanes] x 8 bf16
-    const uint32_t *seg;   // MFMA: 16-wide output segments (y << 16) | x0, padded per strip to 16
-    const int *tpre;       // MFMA: [nstrips + 1] first tile of each strip
+    const uint32_t *seg;   // MFMA: 16-wide output segments (y << 16) | x0 covering the mask, row-major
+    const int *segpre;     // MFMA: [ny + 1] prefix of seg by row
 };
-constexpr uint32_t kDummySeg = 0xffffffffu;
 
 size_t ring_bytes(const LensGeom &g);
 int choose_kc(int k);
@@ -85,6 +84,11 @@ hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, hipSt
 // the fused likelihood of n proposals of one lens (FP32 or MFMA convolution per g.mode)
 hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out,
                           hipStream_t st);
+// persistent multi-lens launch (counter reset + kernel) and its occupancy
+int batch_blocks_per_cu(int mode, int nt, size_t lds);
+hipError_t launch_batch(int mode, int nt, int grid, size_t lds, const LensGeom *d_geoms, const int *d_lstart,
+                        const int64_t *d_lout, int nl, int nitems, const PropBlock *d_pc, double *d_out,
+                        unsigned int *d_counter, hipStream_t st);
 // self-test of the matrix-core operand layout: D = A B for a 16x32 by 32x16 BF16 product
 hipError_t launch_mfma_probe(const uint16_t *d_a, const uint16_t *d_b, float *d_d, hipStream_t st);
 // stage 0: binned image of one proposal into d_img [ny][nx]; stage 1: convolved,

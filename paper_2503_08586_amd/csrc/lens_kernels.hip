@@ -316,19 +316,20 @@ __device__ __forceinline__ f32x4 mfma_products(const bf16x8 (&a)[3], const bf16x
 template <int MODE, int NT>
 __device__ __forceinline__ double conv_mfma(const LensGeom &g, const uint16_t *ring,
                                             const uint4 *__restrict__ aop, const uint32_t *__restrict__ seg,
-                                            const int *__restrict__ tpre, const float *__restrict__ data,
-                                            const float *__restrict__ wgt, int strip)
+                                            const int *__restrict__ segpre, const float *__restrict__ data,
+                                            const float *__restrict__ wgt, int ya, int yb)
 {
     constexpr int NPL = mode_planes(MODE);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int n = lane & 15, kb = lane >> 4;
     const int W = g.ring_w, RB = g.ring_rows, L = g.L, nch = g.nchunks, plane = g.plane;
     double acc = 0.0;
-    const int t1 = tpre[strip + 1];
-    for (int t = tpre[strip] + wave; t < t1; t += NT / 64) {
-        const uint32_t e = seg[t * 16 + n];
-        const bool dummy = e == kDummySeg;
-        const int y = dummy ? 0 : (int)(e >> 16), x0 = dummy ? 0 : (int)(e & 0xffffu);
+    const int s0 = segpre[ya], s1 = segpre[yb];
+    for (int t = s0 + 16 * wave; t < s1; t += 16 * (NT / 64)) {
+        // a tile of 16 segments; lanes past the strip's last segment compute a discarded column
+        const bool dummy = t + n >= s1;
+        const uint32_t e = dummy ? 0u : seg[t + n];
+        const int y = (int)(e >> 16), x0 = (int)(e & 0xffffu);
         int slot = y % RB;           // ring slot of binned row y - r + a, a = 0
         int i = 8 * kb;              // window offset of this lane's K elements, K = 8 kb
         while (i >= L) {             // (only for L < 32)
@@ -374,7 +375,7 @@ template <int MODE, int NT>
 __global__ void __launch_bounds__(NT)
 k_loglike_mfma(const LensGeom g, const PropBlock *__restrict__ pc, const uint32_t *__restrict__ evl,
                const int *__restrict__ evpre, const int2 *__restrict__ evr, const uint4 *__restrict__ aop,
-               const uint32_t *__restrict__ seg, const int *__restrict__ tpre, const float *__restrict__ data,
+               const uint32_t *__restrict__ seg, const int *__restrict__ segpre, const float *__restrict__ data,
                const float *__restrict__ wgt, double *__restrict__ out)
 {
     extern __shared__ float4 lds4[];
@@ -386,9 +387,121 @@ k_loglike_mfma(const LensGeom g, const PropBlock *__restrict__ pc, const uint32_
         return;
     }
     const PropBlock P = *c;
-    strip_loop<MODE, NT>(g, P, ring, evl, evpre, evr, out, p, [&](int, int, int strip) {
-        return conv_mfma<MODE, NT>(g, ring, aop, seg, tpre, data, wgt, strip);
+    strip_loop<MODE, NT>(g, P, ring, evl, evpre, evr, out, p, [&](int y0, int y1, int) {
+        return conv_mfma<MODE, NT>(g, ring, aop, seg, segpre, data, wgt, y0, y1);
     });
+}
+
+// ---------------------------------------------------------------------------
+// persistent multi-lens kernel
+// ---------------------------------------------------------------------------
+// FP32 convolution with the PSF side chosen at run time (each lens of a batch
+// has its own).  It issues, for every output, the same fmaf sequence as
+// conv_rows<K> (weights in ascending order within a PSF row, row partials added
+// in ascending row order), so batch and single-lens results agree bit for
+// bit; the window slides through four registers instead of a K-sized array,
+// which keeps the batch kernel's register count at the single-lens level.
+template <int NT>
+__device__ __forceinline__ double conv_rows_rt(const LensGeom &g, const float *ring, int ya, int yb)
+{
+    const int W = g.ring_w, RB = g.ring_rows, k = g.k;
+    const float *__restrict__ psf = g.psf;
+    double acc = 0.0;
+    const int gb = g.cvpre[yb];
+    for (int gi = g.cvpre[ya] + threadIdx.x; gi < gb; gi += NT) {
+        const uint32_t e = g.cvl[gi];
+        const int y = (int)(e >> 16), x0 = (int)(e & 0xffffu);
+        float o0 = 0.f, o1 = 0.f, o2 = 0.f, o3 = 0.f;
+        int slot = y % RB;
+        for (int a = 0; a < k; ++a) {
+            const float *row = ring + slot * W + x0;
+            const float *kr = psf + a * k;
+            float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
+            float v0 = row[0], v1 = row[1], v2 = row[2];
+            int b = 0;
+            for (; b + 4 <= k; b += 4) {
+                const float w0 = kr[b], w1 = kr[b + 1], w2 = kr[b + 2], w3 = kr[b + 3];
+                const float v3 = row[b + 3], v4 = row[b + 4], v5 = row[b + 5], v6 = row[b + 6];
+                p0 = fmaf(w0, v0, p0); p1 = fmaf(w0, v1, p1); p2 = fmaf(w0, v2, p2); p3 = fmaf(w0, v3, p3);
+                p0 = fmaf(w1, v1, p0); p1 = fmaf(w1, v2, p1); p2 = fmaf(w1, v3, p2); p3 = fmaf(w1, v4, p3);
+                p0 = fmaf(w2, v2, p0); p1 = fmaf(w2, v3, p1); p2 = fmaf(w2, v4, p2); p3 = fmaf(w2, v5, p3);
+                p0 = fmaf(w3, v3, p0); p1 = fmaf(w3, v4, p1); p2 = fmaf(w3, v5, p2); p3 = fmaf(w3, v6, p3);
+                v0 = v4; v1 = v5; v2 = v6;
+            }
+            for (; b < k; ++b) {
+                const float w = kr[b], v3 = row[b + 3];
+                p0 = fmaf(w, v0, p0); p1 = fmaf(w, v1, p1); p2 = fmaf(w, v2, p2); p3 = fmaf(w, v3, p3);
+                v0 = v1; v1 = v2; v2 = v3;
+            }
+            o0 += p0;
+            o1 += p1;
+            o2 += p2;
+            o3 += p3;
+            slot = (slot + 1 == RB) ? 0 : slot + 1;
+        }
+        const float4 d = *reinterpret_cast<const float4 *>(g.data + (size_t)y * g.pitch + x0);
+        const float4 w = *reinterpret_cast<const float4 *>(g.wgt + (size_t)y * g.pitch + x0);
+        const double r0 = (double)((d.x - o0) * w.x);
+        const double r1 = (double)((d.y - o1) * w.y);
+        const double r2 = (double)((d.z - o2) * w.z);
+        const double r3 = (double)((d.w - o3) * w.w);
+        acc = fma(r0, r0, acc);
+        acc = fma(r1, r1, acc);
+        acc = fma(r2, r2, acc);
+        acc = fma(r3, r3, acc);
+    }
+    return acc;
+}
+
+__global__ void k_reset_counter(unsigned int *counter) { *counter = 0u; }
+
+// Work items are (lens, proposal) pairs numbered lens-major in the batch's
+// order (longest per-proposal cost first); item i belongs to the lens j with
+// lstart[j] <= i < lstart[j + 1], and its result goes to out[lout[j] + i - lstart[j]].
+// Each workgroup takes the next item from a global counter until none is left:
+// every wave leaves the loop on the same item index, so the grid drains.
+template <int MODE, int NT>
+__global__ void __launch_bounds__(NT)
+k_loglike_batch(const LensGeom *__restrict__ geoms, const int *__restrict__ lstart,
+                const int64_t *__restrict__ lout, int nl, int nitems, const PropBlock *__restrict__ pc,
+                double *__restrict__ out, unsigned int *__restrict__ counter)
+{
+    extern __shared__ float4 lds4[];
+    __shared__ int s_item;
+    while (true) {
+        if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
+        __syncthreads();
+        // uniform across the workgroup: readfirstlane lets the compiler keep the
+        // lens descriptor and the proposal constants in scalar registers
+        const int item = __builtin_amdgcn_readfirstlane(s_item);
+        __syncthreads();
+        if (item >= nitems) break;
+        int lo = 0, hi = nl;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (lstart[mid] <= item) lo = mid; else hi = mid;
+        }
+        lo = __builtin_amdgcn_readfirstlane(lo);
+        const LensGeom g = geoms[lo];
+        const int64_t p = lout[lo] + (item - lstart[lo]);
+        const PropBlock *c = pc + p;
+        if (c->valid == 0.0) {
+            if (threadIdx.x == 0) out[p] = -INFINITY;
+            continue;
+        }
+        const PropBlock P = *c;
+        if (MODE == MODE_FP32) {
+            float *ring = reinterpret_cast<float *>(lds4);
+            strip_loop<MODE, NT>(g, P, ring, g.evl, g.evpre, g.evr, out, p, [&](int y0, int y1, int) {
+                return conv_rows_rt<NT>(g, ring, y0, y1);
+            });
+        } else {
+            uint16_t *ring = reinterpret_cast<uint16_t *>(lds4);
+            strip_loop<MODE, NT>(g, P, ring, g.evl, g.evpre, g.evr, out, p, [&](int y0, int y1, int) {
+                return conv_mfma<MODE, NT>(g, ring, g.aop, g.seg, g.segpre, g.data, g.wgt, y0, y1);
+            });
+        }
+    }
 }
 
 __global__ void k_mfma_probe(const uint16_t *__restrict__ a, const uint16_t *__restrict__ b, float *__restrict__ d)
@@ -502,7 +615,7 @@ template <int MODE, int NT>
 static hipError_t launch_m(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, hipStream_t st)
 {
     hipLaunchKernelGGL((k_loglike_mfma<MODE, NT>), dim3((unsigned)n), dim3(NT), ring_bytes(g), st, g, d_pc,
-                       g.evl, g.evpre, g.evr, g.aop, g.seg, g.tpre, g.data, g.wgt, d_out);
+                       g.evl, g.evpre, g.evr, g.aop, g.seg, g.segpre, g.data, g.wgt, d_out);
     return hipGetLastError();
 }
 
@@ -525,6 +638,8 @@ hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, d
     if (g.nt == 256) return launch_nt<256>(g, d_pc, n, d_out, st);
     return hipErrorInvalidValue;
 }
+
+static const void *batch_kernel(int mode, int nt);
 
 template <int NT>
 static hipError_t set_limits_nt(int bytes)
@@ -555,7 +670,59 @@ hipError_t set_lds_limits(size_t bytes)
 {
     hipError_t e = set_limits_nt<256>((int)bytes);
     if (e == hipSuccess) e = set_limits_nt<512>((int)bytes);
+    for (int nt : {256, 512})
+        for (int m : {MODE_FP32, MODE_SPLIT, MODE_BF16, MODE_SPLIT3})
+            if (e == hipSuccess)
+                e = hipFuncSetAttribute(batch_kernel(m, nt), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
     return e;
+}
+
+template <int MODE, int NT>
+static const void *batch_kernel_ptr()
+{
+    return reinterpret_cast<const void *>(&k_loglike_batch<MODE, NT>);
+}
+
+static const void *batch_kernel(int mode, int nt)
+{
+    if (nt == 256) {
+        switch (mode) {
+        case MODE_FP32: return batch_kernel_ptr<MODE_FP32, 256>();
+        case MODE_SPLIT: return batch_kernel_ptr<MODE_SPLIT, 256>();
+        case MODE_BF16: return batch_kernel_ptr<MODE_BF16, 256>();
+        case MODE_SPLIT3: return batch_kernel_ptr<MODE_SPLIT3, 256>();
+        }
+    } else if (nt == 512) {
+        switch (mode) {
+        case MODE_FP32: return batch_kernel_ptr<MODE_FP32, 512>();
+        case MODE_SPLIT: return batch_kernel_ptr<MODE_SPLIT, 512>();
+        case MODE_BF16: return batch_kernel_ptr<MODE_BF16, 512>();
+        case MODE_SPLIT3: return batch_kernel_ptr<MODE_SPLIT3, 512>();
+        }
+    }
+    return nullptr;
+}
+
+int batch_blocks_per_cu(int mode, int nt, size_t lds)
+{
+    const void *k = batch_kernel(mode, nt);
+    int nb = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, nt, lds) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_batch(int mode, int nt, int grid, size_t lds, const LensGeom *d_geoms, const int *d_lstart,
+                        const int64_t *d_lout, int nl, int nitems, const PropBlock *d_pc, double *d_out,
+                        unsigned int *d_counter, hipStream_t st)
+{
+    const void *k = batch_kernel(mode, nt);
+    if (!k || grid <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(1), 0, st, d_counter);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    void *args[] = {(void *)&d_geoms, (void *)&d_lstart, (void *)&d_lout, (void *)&nl, (void *)&nitems,
+                    (void *)&d_pc, (void *)&d_out, (void *)&d_counter};
+    return hipLaunchKernel(k, dim3(grid), dim3(nt), args, lds, st);
 }
 
 hipError_t launch_mfma_probe(const uint16_t *d_a, const uint16_t *d_b, float *d_d, hipStream_t st)

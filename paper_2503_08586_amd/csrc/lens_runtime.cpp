@@ -123,6 +123,21 @@ struct Arena {
 
 thread_local std::unordered_map<const void *, std::string> t_err;
 
+// One multi-lens call shape (lens ids and proposal counts) captured as a
+// hipGraph: H2D params -> prep -> one persistent launch per (mode, workgroup
+// size) group -> D2H results.  Replayed for every call with the same shape.
+struct Plan {
+    std::vector<lens_id> ids;
+    std::vector<int64_t> counts;
+    int64_t tot = 0;
+    void *dev = nullptr;
+    size_t bytes = 0;
+    double *h_params = nullptr, *h_out = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t used = 0;
+};
+
 // round-to-nearest-even FP32 -> BF16 and the plane split v = p0 + p1 (+ p2)
 uint16_t bf16_rn_host(float f)
 {
@@ -146,6 +161,39 @@ void split_bf16(float v, int npl, uint16_t *out)
         out[q] = bf16_rn_host(v);
         v -= bf16_to_float(out[q]);
     }
+}
+
+// Strip height H and workgroup size of one lens: the LDS ring holds H + k - 1
+// binned rows.  False if even H = 1 does not fit.
+bool set_tiles(LensGeom &g, int H, int nt, size_t lds_max)
+{
+    if (H < 1) return false;
+    H = std::min(H, g.ny);
+    const size_t bytes = (size_t)(H + 2 * g.r) * lensk::ring_row_bytes(g.mode, g.k, g.nx);
+    if (bytes > lds_max) return false;
+    g.nt = nt;
+    g.strip_h = H;
+    g.ring_rows = H + 2 * g.r;
+    g.plane = g.ring_rows * g.ring_w;
+    g.nstrips = (g.ny + H - 1) / H;
+    return true;
+}
+
+// Default shape: strips of up to 16 rows; 256 threads while the ring fits
+// 40 KB (4 workgroups, i.e. 4 waves per SIMD, share a CU's 160 KB), else 512
+// threads under 80 KB, else the device's per-workgroup maximum.
+int default_strip(const LensGeom &g, size_t lds_max, int *nt)
+{
+    const size_t row_b = lensk::ring_row_bytes(g.mode, g.k, g.nx);
+    auto rows_fit = [&](size_t budget) { return (int)std::min<size_t>(budget / row_b, 1 << 20) - 2 * g.r; };
+    int H = std::min(16, rows_fit(40960));
+    *nt = 256;
+    if (H < 8) {
+        *nt = 512;
+        H = std::min(16, rows_fit(std::min<size_t>(81920, lds_max)));
+    }
+    if (H < 4) H = std::min(16, rows_fit(lds_max));
+    return H;
 }
 
 }  // namespace
@@ -172,6 +220,17 @@ struct lens_ctx {
     size_t h_cap = 0;                     // proposals
     void *d_sync = nullptr;               // params | pc | out for the blocking calls
     size_t d_sync_bytes = 0;
+
+    // autotuner: (strip height, workgroup size) per shape bucket
+    bool autotune = false;
+    std::mutex tune_mu;
+    std::map<std::string, std::pair<int, int>> tune_cache;
+    std::string tune_file;
+    int num_cus = 256;
+
+    // multi-lens plans (graph-captured persistent launches), guarded by sync_mu
+    std::map<std::string, struct Plan *> plans;
+    uint64_t plan_clock = 0;
 
     // serving
     int max_inflight = 8;
@@ -341,6 +400,8 @@ hipError_t launch_lens(const Lens *L, const double *d_params, lensk::PropBlock *
 }
 
 void scheduler_main(lens_ctx *c);
+lens_status tune_lens(lens_ctx *c, Lens *L);
+void drop_plan(lens_ctx *c, Plan *pl);
 
 }  // namespace
 
@@ -377,6 +438,23 @@ extern "C" lens_status lens_init(const lens_init_opts *opts, lens_ctx **out)
     for (int i = 0; i < kServeStreams; ++i)
         if (hipStreamCreateWithFlags(&c->sstreams[i], hipStreamNonBlocking) != hipSuccess) return LENS_EDEVICE;
     c->stats.hbm_budget_bytes = c->budget;
+    c->autotune = o.autotune != 0;
+    {
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) == hipSuccess && cus > 0)
+            c->num_cus = cus;
+        const char *tf = getenv("LENS_AUTOTUNE_CACHE");
+        if (tf && *tf) {
+            c->tune_file = tf;
+            FILE *f = fopen(tf, "r");
+            if (f) {
+                char key[256];
+                int H = 0, nt = 0;
+                while (fscanf(f, "%255s %d %d", key, &H, &nt) == 3) c->tune_cache[key] = {H, nt};
+                fclose(f);
+            }
+        }
+    }
     {
         const size_t m = lensk::max_lds_bytes();
         if (m > 65536 && lensk::set_lds_limits(m) == hipSuccess) c->lds_max = m;
@@ -411,6 +489,16 @@ extern "C" void lens_shutdown(lens_ctx *c)
             (void)hipStreamSynchronize(c->sstreams[i]);
             (void)hipStreamDestroy(c->sstreams[i]);
         }
+    for (auto &kv : c->plans) {
+        Plan *pl = kv.second;
+        if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+        if (pl->graph) (void)hipGraphDestroy(pl->graph);
+        dev_free(c, pl->dev);
+        if (pl->h_params) (void)hipHostFree(pl->h_params);
+        if (pl->h_out) (void)hipHostFree(pl->h_out);
+        delete pl;
+    }
+    c->plans.clear();
     for (auto &kv : c->reqs) delete kv.second;
     c->reqs.clear();
     for (auto &kv : c->lenses) {
@@ -455,6 +543,104 @@ extern "C" const char *lens_last_error(lens_ctx *c)
     auto it = t_err.find(c);
     return it == t_err.end() ? "" : it->second.c_str();
 }
+
+
+// ---------------------------------------------------------------------------
+// autotuner
+// ---------------------------------------------------------------------------
+namespace {
+
+std::string shape_key(const LensGeom &g, int64_t needed)
+{
+    char buf[160];
+    // needed pixels in steps of 1/8 of the image: the mask's share of the work
+    snprintf(buf, sizeof(buf), "gfx950/m%d/k%d/s%d/y%d/x%d/f%d", g.mode, g.k, g.s, (g.ny + 15) / 16,
+             (g.nx + 15) / 16, (int)(8 * needed / std::max<int64_t>(1, (int64_t)g.ny * g.nx)));
+    return buf;
+}
+
+// Times each candidate (strip height, workgroup size) on synthetic proposals
+// of typical shape and keeps the fastest for the lens's shape bucket.
+lens_status tune_lens(lens_ctx *c, Lens *L)
+{
+    const std::string key = shape_key(L->g, L->needed);
+    {
+        std::lock_guard<std::mutex> lk(c->tune_mu);
+        auto it = c->tune_cache.find(key);
+        if (it != c->tune_cache.end()) {
+            LensGeom g2 = L->g;
+            if (set_tiles(g2, it->second.first, it->second.second, c->lds_max)) L->g = g2;
+            return LENS_OK;
+        }
+    }
+    const int64_t n = std::max<int64_t>(512, 8LL * c->num_cus);
+    std::vector<double> hp((size_t)n * lensk::kStride, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        const double j = (double)(i % 97) / 97.0;   // mild spread, all inside the domain
+        double *p = &hp[(size_t)i * lensk::kStride];
+        p[0] = 0.8 + 0.8 * j; p[1] = 0.6 + 0.3 * j; p[2] = 3.0 * j; p[3] = 0.05 - 0.1 * j; p[4] = 0.02;
+        p[5] = 0.03; p[6] = -0.02; p[7] = 0.2; p[8] = 0.4 + 0.4 * j; p[9] = 1.0 + 2.5 * j; p[10] = 0.8;
+        p[11] = 1.0; p[12] = 0.3; p[13] = 0.2 + 0.5 * j; p[14] = 0.7 + 2.0 * j; p[15] = 0.7; p[16] = 2.0;
+        p[17] = 0.3 - 0.6 * j; p[18] = -0.1;
+    }
+    std::lock_guard<std::mutex> lk(c->sync_mu);
+    void *buf = nullptr;
+    const size_t pb = align_up((size_t)n * lensk::kStride * 8, kAlign), cb = align_up((size_t)n * lensk::kPCBytes, kAlign);
+    lens_status rs = stream_scratch(c, c->stream, pb + cb + (size_t)n * 8, &buf);
+    if (rs != LENS_OK) return rs;
+    double *dp = (double *)buf;
+    lensk::PropBlock *dpc = (lensk::PropBlock *)((char *)buf + pb);
+    double *dout = (double *)((char *)buf + pb + cb);
+    HIPCHK(c, hipMemcpyAsync(dp, hp.data(), hp.size() * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, lensk::launch_prep(dp, n, dpc, c->stream));
+    hipEvent_t e0, e1;
+    HIPCHK(c, hipEventCreate(&e0));
+    HIPCHK(c, hipEventCreate(&e1));
+    float best = 1e30f;
+    int bestH = L->g.strip_h, bestNT = L->g.nt;
+    for (int nt : {256, 512})
+        for (int H : {4, 8, 16, 32}) {
+            LensGeom g2 = L->g;
+            if (!set_tiles(g2, H, nt, c->lds_max) || g2.strip_h != H) continue;
+            float t = 1e30f;
+            hipError_t e = lensk::launch_loglike(g2, dpc, n, dout, c->stream);  // warm-up
+            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+                e = hipEventRecord(e0, c->stream);
+                if (e == hipSuccess) e = lensk::launch_loglike(g2, dpc, n, dout, c->stream);
+                if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e == hipSuccess) t = std::min(t, ms);
+            }
+            if (e != hipSuccess) {
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                return hip_fail(c, e, "autotune launch");
+            }
+            if (t < best) {
+                best = t;
+                bestH = H;
+                bestNT = nt;
+            }
+        }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    LensGeom g2 = L->g;
+    if (set_tiles(g2, bestH, bestNT, c->lds_max)) L->g = g2;
+    std::lock_guard<std::mutex> tk(c->tune_mu);
+    c->tune_cache[key] = {L->g.strip_h, L->g.nt};
+    if (!c->tune_file.empty()) {
+        FILE *f = fopen(c->tune_file.c_str(), "a");
+        if (f) {
+            fprintf(f, "%s %d %d\n", key.c_str(), L->g.strip_h, L->g.nt);
+            fclose(f);
+        }
+    }
+    return LENS_OK;
+}
+
+}  // namespace
 
 // ---------------------------------------------------------------------------
 // lens registry
@@ -520,44 +706,26 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     }
     evpre[ny] = (int)evl.size();
     cvpre[ny] = (int)cvl.size();
-    // Workgroup shape: strips of up to 16 rows; 256 threads while the ring fits
-    // 40 KB (4 workgroups, i.e. 4 waves per SIMD, share a CU's 160 KB), else
-    // 512 threads under 80 KB, else the device's per-workgroup maximum.
     LensGeom g{};
     g.ny = ny; g.nx = nx; g.s = s; g.k = k; g.r = r; g.pitch = pitch; g.mode = mode;
     g.ring_w = lensk::ring_width(mode, k, nx);
-    const size_t row_b = lensk::ring_row_bytes(mode, k, nx);
-    const size_t lds_max = c->lds_max;
-    auto rows_fit = [&](size_t budget) { return (int)std::min<size_t>(budget / row_b, 1 << 20) - 2 * r; };
-    int H = std::min(16, rows_fit(40960));
-    int nt = 256;
-    if (H < 8) {
-        nt = 512;
-        H = std::min(16, rows_fit(std::min<size_t>(81920, lds_max)));
-    }
-    if (H < 4) H = std::min(16, rows_fit(lds_max));
-    if (H < 1) return fail(c, LENS_EINVAL, "image too wide for the LDS line buffer at this PSF size");
-    g.nt = nt;
-    g.strip_h = H;
-    g.ring_rows = H + 2 * r;
-    g.plane = g.ring_rows * g.ring_w;
-    g.nstrips = (ny + H - 1) / H;
-    // MFMA operands: 16-wide output segments per strip (padded to tiles of 16)
-    // and the banded Toeplitz expansion of the flipped PSF, split into BF16 planes
+    if (!set_tiles(g, default_strip(g, c->lds_max, &g.nt), g.nt, c->lds_max))
+        return fail(c, LENS_EINVAL, "image too wide for the LDS line buffer at this PSF size");
+    // MFMA operands: 16-wide output segments covering the mask (row-major, with
+    // row prefix) and the banded Toeplitz expansion of the flipped PSF, split
+    // into BF16 planes
     std::vector<uint32_t> seg;
-    std::vector<int> tpre(g.nstrips + 1, 0);
+    std::vector<int> segpre(ny + 1, 0);
     std::vector<uint16_t> aop;
     if (mode != LENS_PREC_FP32) {
         g.L = (int)align_up((size_t)(16 + k - 1), 8);
         g.nchunks = (int)((k * g.L + 31) / 32);
-        for (int st = 0; st < g.nstrips; ++st) {
-            tpre[st] = (int)(seg.size() / 16);
-            for (int y = st * H; y < std::min(ny, (st + 1) * H); ++y)
-                if (mhi[y] > mlo[y])
-                    for (int x0 = mlo[y] & ~15; x0 < mhi[y]; x0 += 16) seg.push_back(((uint32_t)y << 16) | (uint32_t)x0);
-            while (seg.size() % 16) seg.push_back(lensk::kDummySeg);
+        for (int y = 0; y < ny; ++y) {
+            segpre[y] = (int)seg.size();
+            if (mhi[y] > mlo[y])
+                for (int x0 = mlo[y] & ~15; x0 < mhi[y]; x0 += 16) seg.push_back(((uint32_t)y << 16) | (uint32_t)x0);
         }
-        tpre[g.nstrips] = (int)(seg.size() / 16);
+        segpre[ny] = (int)seg.size();
         const int npl = lensk::mode_planes(mode);
         aop.assign((size_t)g.nchunks * npl * 64 * 8, 0);
         for (int ch = 0; ch < g.nchunks; ++ch)
@@ -596,7 +764,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     const size_t o_psf = place(hk.size() * 4), o_d = place(hd.size() * 4), o_w = place(hw.size() * 4);
     const size_t o_evl = place(evl.size() * 4), o_evpre = place(evpre.size() * 4), o_evr = place(evr.size() * 8);
     const size_t o_cvl = place(cvl.size() * 4), o_cvpre = place(cvpre.size() * 4);
-    const size_t o_aop = place(aop.size() * 2), o_seg = place(seg.size() * 4), o_tpre = place(tpre.size() * 4);
+    const size_t o_aop = place(aop.size() * 2), o_seg = place(seg.size() * 4), o_segpre = place(segpre.size() * 4);
     const size_t total = off;
     DeviceGuard dg(c->device);
     if (!charge(c, (int64_t)total)) return fail(c, LENS_ENOMEM, "HBM budget exhausted");
@@ -615,7 +783,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
               {o_evpre, evpre.data(), evpre.size() * 4}, {o_evr, evr.data(), evr.size() * 8},
               {o_cvl, cvl.data(), cvl.size() * 4},   {o_cvpre, cvpre.data(), cvpre.size() * 4},
               {o_aop, aop.data(), aop.size() * 2},   {o_seg, seg.data(), seg.size() * 4},
-              {o_tpre, tpre.data(), tpre.size() * 4}};
+              {o_segpre, segpre.data(), segpre.size() * 4}};
     for (auto &e : cp) {
         if (!e.n) continue;
         hipError_t he = hipMemcpyAsync(b + e.o, e.src, e.n, hipMemcpyHostToDevice, c->stream);
@@ -641,7 +809,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     g.cvpre = (const int *)(b + o_cvpre);
     g.aop = (const uint4 *)(b + o_aop);
     g.seg = (const uint32_t *)(b + o_seg);
-    g.tpre = (const int *)(b + o_tpre);
+    g.segpre = (const int *)(b + o_segpre);
     Lens *L = new Lens();
     L->g = g;
     L->precision = d->precision;
@@ -649,6 +817,15 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     L->needed = (int64_t)evl.size();
     L->slab = slab;
     L->bytes = total;
+    if (c->autotune) {
+        lens_status ts = tune_lens(c, L);
+        if (ts != LENS_OK) {
+            dev_free(c, slab);
+            uncharge(c, (int64_t)total);
+            delete L;
+            return ts;
+        }
+    }
     {
         std::lock_guard<std::mutex> lk(c->mu);
         L->id = c->next_id++;
@@ -662,6 +839,7 @@ extern "C" lens_status lens_unload(lens_ctx *c, lens_id id)
 {
     if (!c) return LENS_EINVAL;
     Lens *L = nullptr;
+    std::lock_guard<std::mutex> plk(c->sync_mu);
     {
         std::lock_guard<std::mutex> lk(c->mu);
         auto it = c->lenses.find(id);
@@ -678,6 +856,14 @@ extern "C" lens_status lens_unload(lens_ctx *c, lens_id id)
     // every launch that read the lens has completed: blocking calls synchronise,
     // serving requests are finished; device-buffer calls are ordered on their streams
     (void)hipDeviceSynchronize();
+    for (auto it = c->plans.begin(); it != c->plans.end();) {
+        if (std::find(it->second->ids.begin(), it->second->ids.end(), id) != it->second->ids.end()) {
+            drop_plan(c, it->second);
+            it = c->plans.erase(it);
+        } else {
+            ++it;
+        }
+    }
     dev_free(c, L->slab);
     uncharge(c, (int64_t)L->bytes);
     delete L;
@@ -803,6 +989,142 @@ extern "C" lens_status lens_loglike_batch_device(lens_ctx *c, lens_id id, const 
     return rs;
 }
 
+namespace {
+
+void drop_plan(lens_ctx *c, Plan *pl)
+{
+    // sync_mu held; the plan's launches have completed (every call synchronises)
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    dev_free(c, pl->dev);
+    uncharge(c, (int64_t)pl->bytes);
+    if (pl->h_params) (void)hipHostFree(pl->h_params);
+    if (pl->h_out) (void)hipHostFree(pl->h_out);
+    delete pl;
+}
+
+std::string plan_key(int32_t nlens, const lens_id *ids, const int64_t *counts)
+{
+    std::string k;
+    k.reserve((size_t)nlens * 24);
+    char buf[48];
+    for (int i = 0; i < nlens; ++i) {
+        snprintf(buf, sizeof(buf), "%lld:%lld,", (long long)ids[i], (long long)counts[i]);
+        k += buf;
+    }
+    return k;
+}
+
+// Build and capture the graph of one call shape (sync_mu held).
+lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int64_t *counts,
+                       const std::vector<Lens *> &Ls, int64_t tot, Plan **out)
+{
+    auto pl = std::make_unique<Plan>();
+    pl->ids.assign(ids, ids + nlens);
+    pl->counts.assign(counts, counts + nlens);
+    pl->tot = tot;
+    // groups by (mode, workgroup size); inside a group lenses in descending
+    // per-proposal cost, so the longest items start first
+    std::vector<int64_t> off(nlens + 1, 0);
+    for (int i = 0; i < nlens; ++i) off[i + 1] = off[i] + counts[i];
+    std::map<std::pair<int, int>, std::vector<int>> groups;
+    for (int i = 0; i < nlens; ++i)
+        if (counts[i] > 0) groups[{Ls[i]->g.mode, Ls[i]->g.nt}].push_back(i);
+    struct G {
+        int mode, nt, nl, nitems, grid;
+        size_t lds, o_geom, o_ls, o_lo;
+    };
+    std::vector<G> gs;
+    std::vector<LensGeom> hgeom;
+    std::vector<int> hls;
+    std::vector<int64_t> hlo;
+    for (auto &kv : groups) {
+        std::vector<int> &v = kv.second;
+        auto cost = [&](int i) {
+            const LensGeom &g = Ls[i]->g;
+            return (double)Ls[i]->needed * g.s * g.s * 200.0 + (double)Ls[i]->masked * g.k * g.k;
+        };
+        std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return cost(a) > cost(b); });
+        G gg{};
+        gg.mode = kv.first.first;
+        gg.nt = kv.first.second;
+        gg.nl = (int)v.size();
+        gg.o_geom = hgeom.size();
+        gg.o_ls = hls.size();
+        gg.o_lo = hlo.size();
+        int items = 0;
+        for (int i : v) {
+            hgeom.push_back(Ls[i]->g);
+            hls.push_back(items);
+            hlo.push_back(off[i]);
+            items += (int)counts[i];
+            gg.lds = std::max(gg.lds, lensk::ring_bytes(Ls[i]->g));
+        }
+        hls.push_back(items);
+        gg.nitems = items;
+        gg.grid = c->num_cus * lensk::batch_blocks_per_cu(gg.mode, gg.nt, gg.lds);
+        gs.push_back(gg);
+    }
+    // device layout: params | pc | out | geoms | lstart | lout | counters
+    const size_t b_par = align_up((size_t)tot * lensk::kStride * 8, kAlign);
+    const size_t b_pc = align_up((size_t)tot * lensk::kPCBytes, kAlign);
+    const size_t b_out = align_up((size_t)tot * 8, kAlign);
+    const size_t b_geom = align_up(hgeom.size() * sizeof(LensGeom), kAlign);
+    const size_t b_ls = align_up(hls.size() * 4, kAlign), b_lo = align_up(hlo.size() * 8, kAlign);
+    const size_t b_cnt = align_up(gs.size() * 4 + 4, kAlign);
+    pl->bytes = b_par + b_pc + b_out + b_geom + b_ls + b_lo + b_cnt;
+    if (!charge(c, (int64_t)pl->bytes)) return fail(c, LENS_ENOMEM, "HBM budget exhausted (batch plan)");
+    pl->dev = dev_alloc(c, pl->bytes);
+    if (!pl->dev) {
+        uncharge(c, (int64_t)pl->bytes);
+        return fail(c, LENS_ENOMEM, "device allocation failed (batch plan)");
+    }
+    char *b = (char *)pl->dev;
+    double *d_par = (double *)b;
+    lensk::PropBlock *d_pc = (lensk::PropBlock *)(b + b_par);
+    double *d_out = (double *)(b + b_par + b_pc);
+    LensGeom *d_geom = (LensGeom *)(b + b_par + b_pc + b_out);
+    int *d_ls = (int *)((char *)d_geom + b_geom);
+    int64_t *d_lo = (int64_t *)((char *)d_ls + b_ls);
+    unsigned int *d_cnt = (unsigned int *)((char *)d_lo + b_lo);
+    Plan *raw = pl.get();
+    auto bail = [&](hipError_t e, const char *what) {
+        raw->used = 0;
+        drop_plan(c, pl.release());
+        return hip_fail(c, e, what);
+    };
+    hipError_t e = hipHostMalloc((void **)&pl->h_params, (size_t)tot * lensk::kStride * 8, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&pl->h_out, (size_t)tot * 8, hipHostMallocDefault);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_geom, hgeom.data(), hgeom.size() * sizeof(LensGeom), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_ls, hls.data(), hls.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_lo, hlo.data(), hlo.size() * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return bail(e, "batch plan set-up");
+    // capture: the graph holds only copies and kernels (the work counters are
+    // cleared by a kernel node, never by a memset node)
+    e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return bail(e, "hipStreamBeginCapture");
+    hipError_t ce = hipMemcpyAsync(d_par, pl->h_params, (size_t)tot * lensk::kStride * 8, hipMemcpyHostToDevice, c->stream);
+    if (ce == hipSuccess) ce = lensk::launch_prep(d_par, tot, d_pc, c->stream);
+    for (size_t gi = 0; gi < gs.size() && ce == hipSuccess; ++gi) {
+        const G &gg = gs[gi];
+        ce = lensk::launch_batch(gg.mode, gg.nt, gg.grid, gg.lds, d_geom + gg.o_geom, d_ls + gg.o_ls, d_lo + gg.o_lo,
+                                 gg.nl, gg.nitems, d_pc, d_out, d_cnt + gi, c->stream);
+    }
+    if (ce == hipSuccess) ce = hipMemcpyAsync(pl->h_out, d_out, (size_t)tot * 8, hipMemcpyDeviceToHost, c->stream);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(c->stream, &graph);
+    pl->graph = graph;
+    if (ce != hipSuccess) return bail(ce, "batch plan capture");
+    if (e != hipSuccess) return bail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return bail(e, "hipGraphInstantiate");
+    *out = pl.release();
+    return LENS_OK;
+}
+
+}  // namespace
+
 extern "C" lens_status lens_loglike_multi(lens_ctx *c, int32_t nlens, const lens_id *ids, const int64_t *counts,
                                           const double *params, double *out)
 {
@@ -816,6 +1138,9 @@ extern "C" lens_status lens_loglike_multi(lens_ctx *c, int32_t nlens, const lens
     }
     if (tot > 0 && (!params || !out)) return fail(c, LENS_EINVAL, "null params/out");
     if (tot > INT_MAX) return fail(c, LENS_EINVAL, "too many proposals for one call");
+    if (tot == 0) return LENS_OK;
+    DeviceGuard dg(c->device);
+    std::lock_guard<std::mutex> lk(c->sync_mu);
     std::vector<Lens *> Ls;
     for (int i = 0; i < nlens; ++i) {
         Lens *L = acquire(c, ids[i]);
@@ -825,28 +1150,30 @@ extern "C" lens_status lens_loglike_multi(lens_ctx *c, int32_t nlens, const lens
         }
         Ls.push_back(L);
     }
-    DeviceGuard dg(c->device);
+    const std::string key = plan_key(nlens, ids, counts);
+    Plan *pl = nullptr;
     lens_status rs = LENS_OK;
-    if (tot > 0) {
-        std::lock_guard<std::mutex> lk(c->sync_mu);
-        rs = sync_buffers(c, tot);
-        if (rs == LENS_OK) {
-            ScratchLayout S = carve(c->d_sync, (int64_t)c->h_cap, true);
-            memcpy(c->h_params, params, (size_t)tot * lensk::kStride * sizeof(double));
-            hipError_t e = hipMemcpyAsync(S.params, c->h_params, (size_t)tot * lensk::kStride * sizeof(double),
-                                          hipMemcpyHostToDevice, c->stream);
-            if (e == hipSuccess) e = lensk::launch_prep(S.params, tot, S.pc, c->stream);
-            int64_t off = 0;
-            for (int i = 0; i < nlens && e == hipSuccess; ++i) {
-                if (counts[i] > 0) e = lensk::launch_loglike(Ls[i]->g, S.pc + off, counts[i], S.out + off, c->stream);
-                off += counts[i];
-            }
-            if (e == hipSuccess)
-                e = hipMemcpyAsync(c->h_out, S.out, (size_t)tot * sizeof(double), hipMemcpyDeviceToHost, c->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-            if (e != hipSuccess) rs = hip_fail(c, e, "lens_loglike_multi");
-            else memcpy(out, c->h_out, (size_t)tot * sizeof(double));
+    auto it = c->plans.find(key);
+    if (it != c->plans.end()) {
+        pl = it->second;
+    } else {
+        if (c->plans.size() >= 8) {  // keep the 8 most recently used shapes
+            auto victim = c->plans.begin();
+            for (auto j = c->plans.begin(); j != c->plans.end(); ++j)
+                if (j->second->used < victim->second->used) victim = j;
+            drop_plan(c, victim->second);
+            c->plans.erase(victim);
         }
+        rs = build_plan(c, nlens, ids, counts, Ls, tot, &pl);
+        if (rs == LENS_OK) c->plans[key] = pl;
+    }
+    if (rs == LENS_OK) {
+        pl->used = ++c->plan_clock;
+        memcpy(pl->h_params, params, (size_t)tot * lensk::kStride * 8);
+        hipError_t e = hipGraphLaunch(pl->exec, c->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) rs = hip_fail(c, e, "lens_loglike_multi");
+        else memcpy(out, pl->h_out, (size_t)tot * 8);
     }
     for (Lens *x : Ls) release(c, x);
     return rs;

@@ -286,3 +286,42 @@ def test_serving_mixed_equals_alone(ctx):
     _check(specs[reqs[0][0]], reqs[0][2].out[:8], reqs[0][1][:8], label="served")
     for lid in lids:
         ctx.unload(lid)
+
+
+@pytest.mark.parametrize("mode", [("fp32", 0), ("split", 1)], ids=["fp32", "split"])
+def test_multi_graph_replays(ctx, mode):
+    """The multi-lens call is a captured graph: replay it several times with eager
+    single-lens calls in between; every replay equals the single-lens results."""
+    mname, m = mode
+    say("case: multi-lens graph replays, mode %s" % mname)
+    specs = synth.config3(nlens=10, scale_props=0.04)
+    lids = []
+    for sp in specs:
+        oracle_data(sp)
+        lids.append(ctx.load(sp, precision=m))
+    singles = [ctx.loglike(lid, sp.proposals) for sp, lid in zip(specs, lids)]
+    for rep in range(4):
+        outs = ctx.loglike_multi(lids, [sp.proposals for sp in specs])
+        for o, ref in zip(outs, singles):
+            assert np.array_equal(o, ref), rep
+        j = rep % len(specs)
+        assert np.array_equal(ctx.loglike(lids[j], specs[j].proposals), singles[j])
+    _check(specs[1], outs[1][:12], specs[1].proposals[:12], tol=MODE_TOL[m], label="multi/%s" % mname)
+    # a different call shape (subset, other counts) builds its own plan
+    outs2 = ctx.loglike_multi(lids[2:5], [sp.proposals[:7] for sp in specs[2:5]])
+    for o, ref in zip(outs2, singles[2:5]):
+        assert np.array_equal(o, ref[:7])
+    for lid in lids:
+        ctx.unload(lid)
+
+
+def test_autotuned_context():
+    say("case: autotuned context")
+    from paper_2503_08586_amd import binding
+    with binding.LensContext(0, autotune=True) as c2:
+        for sp in (synth.config2(nprop=64)[0], synth.config4(nlens=1, nprop=8)[0]):
+            oracle_data(sp)
+            lid = c2.load(sp)
+            got = c2.loglike(lid, sp.proposals)
+            _check(sp, got, sp.proposals, label="autotuned %dx%d" % (sp.ny, sp.nx))
+            c2.unload(lid)
