@@ -1,9 +1,9 @@
 #!/usr/bin/env python3
 """Throughput of the batched lens log-likelihood on one MI355X.
 
-One step = one call of the whole hot path (prep + fused likelihood kernel)
-over one batch of proposals already resident in HBM: the plain survey-scale
-workload, one lens of 128x128 pixels at 0.05"/px, 4x4 supersampling
+Default workload (plain, survey scale): one step = one call of the whole hot
+path (prep + fused likelihood kernel) over one batch of proposals already
+resident in HBM: one lens of 128x128 pixels at 0.05"/px, 4x4 supersampling
 (262,144 ray-traced points per proposal), a 21x21 Gaussian PSF (FWHM 0.1"),
 a 3" circular mask, noise sigma 0.01, and 65,536 proposals per call drawn
 uniformly from the prior box.  Prints one JSON line.
@@ -11,6 +11,11 @@ uniformly from the prior box.  Prints one JSON line.
 The CPU-baseline leg times the FP64 oracle on a bounded sample of the same
 proposals on the host's cores and checks the GPU results of that sample
 against it.
+
+--workload batch|precision|serving runs the other measurements (256 uneven
+lenses in one persistent graph-captured launch vs one lens at a time; 64
+lenses of 200x200 px with a 41x41 Moffat PSF per convolution precision; a
+Poisson request stream over 1,000 resident lenses with p50/p99 latency).
 """
 from __future__ import annotations
 
@@ -41,7 +46,46 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target wall time of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (for HBM counter calibration)")
+    ap.add_argument("--workload", default="plain", choices=["plain", "batch", "precision", "serving"])
+    ap.add_argument("--precision", default=None, choices=["fp32", "split", "bf16", "split3"])
+    ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--requests", type=int, default=300, help="serving: requests per offered load")
     return ap.parse_args()
+
+
+PREC = {"fp32": 0, "split": 1, "bf16": 2, "split3": 3}
+
+
+def gpu_data(ctx, spec):
+    """Noise-free image from the library's forward model at the truth, plus the seeded noise."""
+    tmp = ctx.load(spec, data=np.zeros((spec.ny, spec.nx)))
+    model = ctx.model_image(tmp, spec.truth, stage=1)
+    ctx.unload(tmp)
+    spec.data = model + spec.noise
+
+
+def credited_slots(spec, M):
+    """Credited VALU work of one proposal (60 FMA-class + 10 transcendentals per sub-pixel
+    evaluation, one FMA per PSF tap at each masked pixel, one FP64 FMA per masked pixel)."""
+    E = dilated_count(spec.mask, (spec.k - 1) // 2) * spec.s * spec.s
+    return E * SLOTS_PER_EVAL + M * spec.k * spec.k + M, E
+
+
+def oracle_sample(specs_props, nthreads=0):
+    """Times the oracle over (spec, proposals) pairs; returns (lnL list, chi2 list, C list, seconds)."""
+    import oracle
+    orc = oracle.default()
+    out = []
+    t0 = time.perf_counter()
+    for spec, P in specs_props:
+        ref, chi2 = orc.loglike(spec.geom, spec.psf, spec.data, spec.sigma, spec.mask, P, nthreads=nthreads,
+                                return_chi2=True)
+        out.append((ref, chi2, orc.loglike_norm(spec.sigma, spec.mask)))
+    return out, time.perf_counter() - t0, orc.num_threads()
+
+
+def rel_errors(gpu, ref, chi2, C):
+    return np.abs(gpu - ref) / (0.5 * chi2 + abs(C))
 
 
 def dilated_count(mask, r):
@@ -65,6 +109,12 @@ def main():
 
     from paper_2503_08586_amd import binding, synth
 
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "precision":
+        return run_precision(args)
+    if args.workload == "serving":
+        return run_serving(args)
     if args.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
         y = torch.empty_like(x)
@@ -78,13 +128,10 @@ def main():
 
     spec = synth.config2(nprop=args.nprop)[0]
     n = spec.proposals.shape[0]
-    ctx = binding.LensContext(0)
-    # noise-free data image from the library's own forward model at the truth, plus the seeded noise
-    tmp = ctx.load(spec, data=np.zeros((spec.ny, spec.nx)))
-    model = ctx.model_image(tmp, spec.truth, stage=1)
-    ctx.unload(tmp)
-    spec.data = model + spec.noise
-    lid = ctx.load(spec)
+    ctx = binding.LensContext(0, autotune=args.autotune)
+    gpu_data(ctx, spec)
+    prec = PREC[args.precision or "fp32"]
+    lid = ctx.load(spec, precision=prec)
     info = ctx.info(lid)
 
     dev = torch.device("cuda", 0)
@@ -164,7 +211,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "plain survey scale: 1 lens, 128x128 px at 0.05\"/px, 4x4 supersampling, "
                                "21x21 Gaussian PSF FWHM 0.1\", r=3\" mask, %d proposals per call, "
-                               "FP32 path, FP64 chi2" % n,
+                               "FP64 ray trace, %s PSF convolution, FP64 chi2" % (n, args.precision or "fp32"),
                    "path": "lens_loglike_batch_device", "proposals_per_call": n,
                    "subpixel_evals_per_s": value * E},
         "roofline": roofline,
@@ -172,6 +219,205 @@ def main():
         "max_rel_err_vs_oracle": max_err,
         "pcie_inclusive_evals_per_s": host_rate,
     }
+    print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
+def _stream_ctx(binding, torch, **kw):
+    """A context whose blocking calls run on a torch stream (so HIP events see them)."""
+    st = torch.cuda.Stream()
+    return binding.LensContext(0, stream=st.cuda_stream, **kw), st
+
+
+def run_batch(args):
+    import torch
+
+    from paper_2503_08586_amd import binding, synth
+    prec = PREC[args.precision or "fp32"]
+    specs = synth.config3()
+    ctx, st = _stream_ctx(binding, torch, autotune=args.autotune)
+    lids, slots, evs = [], 0.0, 0
+    for sp in specs:
+        gpu_data(ctx, sp)
+        lid = ctx.load(sp, precision=prec)
+        lids.append(lid)
+        sl, E = credited_slots(sp, ctx.info(lid)["masked_pixels"])
+        slots += sl * sp.proposals.shape[0]
+        evs += E * sp.proposals.shape[0]
+    plist = [sp.proposals for sp in specs]
+    n = int(sum(p.shape[0] for p in plist))
+    for _ in range(args.warmup):
+        outs = ctx.loglike_multi(lids, plist)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(st)
+        outs = ctx.loglike_multi(lids, plist)
+        ev[i][1].record(st)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / args.steps
+    gpu_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    # plain: the same proposals one lens at a time, no graph, no persistent kernel
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    singles = [ctx.loglike(lid, p) for lid, p in zip(lids, plist)]
+    plain_s = time.perf_counter() - t0
+    same = all(np.array_equal(a, b) for a, b in zip(outs, singles))
+    sample = [(specs[j], specs[j].proposals[:2]) for j in range(0, len(specs), 8)]
+    res, tc, threads = oracle_sample(sample)
+    errs = [rel_errors(outs[j][:2], r[0], r[1], r[2]).max() for (j, r) in zip(range(0, len(specs), 8), res)]
+    rec = {
+        "metric": METRIC, "value": n / step_s, "unit": "loglike evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "batching: 256 lenses, N~U{48..160}, 0.05-0.074\"/px, s in {2,4}, k in 11..31, "
+                               "%d proposals (U{128..4096} per lens), one persistent launch in a hipGraph, "
+                               "host buffers, %s PSF convolution" % (n, args.precision or "fp32"),
+                   "proposals_per_call": n, "autotune": bool(args.autotune)},
+        "plain_one_lens_at_a_time_evals_per_s": n / plain_s,
+        "batched_over_plain": plain_s / step_s,
+        "batched_equals_plain_bitwise": bool(same),
+        "roofline": {"bound": "alu", "achieved": slots / (gpu_ms * 1e-3) / 1e12, "peak": PEAK_SLOT_PER_S / 1e12,
+                     "unit": "Tslot/s", "frac": slots / (gpu_ms * 1e-3) / PEAK_SLOT_PER_S, "traffic": None,
+                     "kernel": "k_loglike_batch (graph: H2D, prep, persistent kernel, D2H)", "call_ms": gpu_ms},
+        "cpu_baseline": {"value": sum(len(P) for _, P in sample) / tc, "unit": "loglike evals/s", "cores": threads,
+                         "kind": "oracle", "sample": "2 proposals of each of 32 lenses (every 8th)"},
+        "max_rel_err_vs_oracle": float(max(errs)),
+        "subpixel_evals_per_s": evs / step_s,
+    }
+    print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
+def run_precision(args):
+    import torch
+
+    from paper_2503_08586_amd import binding, synth
+    specs = synth.config4()
+    ctx, st = _stream_ctx(binding, torch, autotune=args.autotune)
+    for sp in specs:
+        gpu_data(ctx, sp)
+    modes = [args.precision] if args.precision else ["fp32", "split", "split3", "bf16"]
+    sample_idx = list(range(0, len(specs), 4))
+    res, tc, threads = oracle_sample([(specs[j], specs[j].proposals[:2]) for j in sample_idx])
+    per = {}
+    for m in modes:
+        lids = [ctx.load(sp, precision=PREC[m]) for sp in specs]
+        plist = [sp.proposals for sp in specs]
+        n = int(sum(p.shape[0] for p in plist))
+        slots = sum(credited_slots(sp, ctx.info(l)["masked_pixels"])[0] * sp.proposals.shape[0]
+                    for sp, l in zip(specs, lids))
+        for _ in range(max(1, args.warmup)):
+            outs = ctx.loglike_multi(lids, plist)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        a.record(st)
+        for _ in range(args.steps):
+            outs = ctx.loglike_multi(lids, plist)
+        b.record(st)
+        torch.cuda.synchronize()
+        step_s = (time.perf_counter() - t0) / args.steps
+        gpu_ms = a.elapsed_time(b) / args.steps
+        errs = np.concatenate([rel_errors(outs[j][:2], r[0], r[1], r[2]) for j, r in zip(sample_idx, res)])
+        per[m] = {"evals_per_s": n / step_s, "ms_per_step": step_s * 1e3, "max_rel_err": float(errs.max()),
+                  "p99_rel_err": float(np.quantile(errs, 0.99)),
+                  "frac_credited_alu": slots / (gpu_ms * 1e-3) / PEAK_SLOT_PER_S}
+        for l in lids:
+            ctx.unload(l)
+    best = max(per, key=lambda m: per[m]["evals_per_s"] if (m == "bf16" or per[m]["max_rel_err"] <= 1e-6) else 0)
+    rec = {"metric": METRIC, "value": per[best]["evals_per_s"], "unit": "loglike evals/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": per[best]["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+           "config": {"workload": "precision: 64 lenses 200x200 px at 0.05\"/px, s=4, 41x41 Moffat beta=3 FWHM 0.15\", "
+                                  "16,384 proposals each, one multi-lens call per step", "value_mode": best},
+           "modes": per,
+           "cpu_baseline": {"value": 2 * len(sample_idx) / tc, "unit": "loglike evals/s", "cores": threads,
+                            "kind": "oracle", "sample": "2 proposals of each of 16 lenses"}}
+    print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
+def run_serving(args):
+    import threading
+
+    import torch
+
+    from paper_2503_08586_amd import binding, synth
+    prec = PREC[args.precision or "split"]
+    lenses = synth.config5_lenses()
+    ctx = binding.LensContext(0, max_inflight=8, autotune=args.autotune)
+    lids = []
+    for sp in lenses:
+        gpu_data(ctx, sp)
+        lids.append(ctx.load(sp, precision=prec))
+    rng = synth.rng_for_config(5)
+    mean_b = 5050.0
+
+    def make_requests(count):
+        out = []
+        for _ in range(count):
+            j = int(rng.integers(0, len(lids)))
+            b = int(rng.integers(100, 10001))
+            out.append((j, synth.draw_params(rng, b)))
+        return out
+
+    def run_stream(reqs, rate):
+        """Open-loop Poisson arrivals at `rate` requests/s (rate None: all at once)."""
+        arr = np.zeros(len(reqs)) if rate is None else synth.poisson_arrivals(rng, rate, len(reqs))
+        t_sub = [0.0] * len(reqs)
+        t_done = [None] * len(reqs)
+        handles = [None] * len(reqs)
+        lock = threading.Lock()
+        stop = [False]
+
+        def poller():
+            pending = set()
+            while True:
+                with lock:
+                    pending.update(i for i, h in enumerate(handles) if h is not None and t_done[i] is None)
+                done = []
+                for i in list(pending):
+                    if ctx.poll(handles[i]) == 0:
+                        t_done[i] = time.perf_counter()
+                        done.append(i)
+                pending.difference_update(done)
+                if stop[0] and not pending and all(t is not None for t in t_done):
+                    return
+                time.sleep(50e-6)
+
+        th = threading.Thread(target=poller)
+        th.start()
+        t0 = time.perf_counter()
+        for i, (j, P) in enumerate(reqs):
+            while time.perf_counter() - t0 < arr[i]:
+                time.sleep(20e-6)
+            t_sub[i] = time.perf_counter()
+            h = ctx.submit(lids[j], P)
+            with lock:
+                handles[i] = h
+        stop[0] = True
+        th.join()
+        t_end = max(t_done)
+        lat = np.array([d - s for d, s in zip(t_done, t_sub)])
+        props = sum(P.shape[0] for _, P in reqs)
+        return props / (t_end - t0), lat
+
+    # peak: a backlog of requests submitted at once
+    peak, _ = run_stream(make_requests(max(60, args.requests // 3)), None)
+    loads = {}
+    for rho in (0.5, 0.6, 0.7, 0.8, 0.9, 1.0):
+        thr, lat = run_stream(make_requests(args.requests), rho * peak / mean_b)
+        loads[str(rho)] = {"offered_evals_per_s": rho * peak, "evals_per_s": thr,
+                           "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+    rec = {"metric": METRIC, "value": peak, "unit": "loglike evals/s", "n_gpus": 1, "steps": args.requests,
+           "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f32+bf16" if prec else "f32", "data": "synthetic",
+           "config": {"workload": "serving: 1,000 resident lenses N~U{48..200}, k~U{11..41}, s=4, Gaussian/Moffat "
+                                  "PSFs; Poisson requests of U{100..10000} proposals on random lenses; %s convolution"
+                                  % (args.precision or "split"), "requests_per_load": args.requests},
+           "offered_loads": loads, "stats": ctx.stats()}
     print(json.dumps(rec), flush=True)
     ctx.close()
 

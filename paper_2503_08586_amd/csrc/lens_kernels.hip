@@ -468,7 +468,9 @@ k_loglike_batch(const LensGeom *__restrict__ geoms, const int *__restrict__ lsta
 {
     extern __shared__ float4 lds4[];
     __shared__ int s_item;
-    while (true) {
+    // a workgroup never takes more than nitems items: the cap bounds the loop
+    // even if the counter protocol were broken
+    for (int iter = 0; iter <= nitems; ++iter) {
         if (threadIdx.x == 0) s_item = (int)atomicAdd(counter, 1u);
         __syncthreads();
         // uniform across the workgroup: readfirstlane lets the compiler keep the
@@ -487,20 +489,26 @@ k_loglike_batch(const LensGeom *__restrict__ geoms, const int *__restrict__ lsta
         const PropBlock *c = pc + p;
         if (c->valid == 0.0) {
             if (threadIdx.x == 0) out[p] = -INFINITY;
-            continue;
-        }
-        const PropBlock P = *c;
-        if (MODE == MODE_FP32) {
-            float *ring = reinterpret_cast<float *>(lds4);
-            strip_loop<MODE, NT>(g, P, ring, g.evl, g.evpre, g.evr, out, p, [&](int y0, int y1, int) {
-                return conv_rows_rt<NT>(g, ring, y0, y1);
-            });
         } else {
-            uint16_t *ring = reinterpret_cast<uint16_t *>(lds4);
-            strip_loop<MODE, NT>(g, P, ring, g.evl, g.evpre, g.evr, out, p, [&](int y0, int y1, int) {
-                return conv_mfma<MODE, NT>(g, ring, g.aop, g.seg, g.segpre, g.data, g.wgt, y0, y1);
-            });
+            const PropBlock P = *c;
+            if (MODE == MODE_FP32) {
+                float *ring = reinterpret_cast<float *>(lds4);
+                strip_loop<MODE, NT>(g, P, ring, g.evl, g.evpre, g.evr, out, p, [&](int y0, int y1, int) {
+                    return conv_rows_rt<NT>(g, ring, y0, y1);
+                });
+            } else {
+                uint16_t *ring = reinterpret_cast<uint16_t *>(lds4);
+                strip_loop<MODE, NT>(g, P, ring, g.evl, g.evpre, g.evr, out, p, [&](int y0, int y1, int) {
+                    return conv_mfma<MODE, NT>(g, ring, g.aop, g.seg, g.segpre, g.data, g.wgt, y0, y1);
+                });
+            }
         }
+        // Reconverge before thread 0 takes the next item.  Without this barrier
+        // the thread-0 result store above and the thread-0 atomic at the top of
+        // the loop can be merged into one divergent region spanning the back
+        // edge, and the other lanes would pass the next barrier before the new
+        // item has been published.
+        __syncthreads();
     }
 }
 
