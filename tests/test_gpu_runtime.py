@@ -1,0 +1,178 @@
+"""Error conventions and request life cycle of the C ABI, on the device."""
+import numpy as np
+import pytest
+
+from gpu_cases import oracle_data, say
+from paper_2503_08586_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def b():
+    from paper_2503_08586_amd import binding
+    return binding
+
+
+@pytest.fixture(scope="module")
+def ctx(b):
+    c = b.LensContext(0, max_inflight=4)
+    yield c
+    c.close()
+
+
+def _spec(nprop=50):
+    sp = synth.config1(nprop=nprop)[0]
+    oracle_data(sp)
+    return sp
+
+
+def test_bad_descriptors(ctx, b):
+    say("case: bad descriptors")
+    sp = _spec(1)
+    good = dict(ny=sp.ny, nx=sp.nx, dpix=sp.dpix, s=sp.s, psf=sp.psf, data=sp.data, sigma=sp.sigma, mask=sp.mask)
+    bad = [
+        dict(s=0), dict(s=9), dict(dpix=0.0), dict(dpix=-1.0), dict(dpix=float("nan")),
+        dict(psf=np.ones((4, 4))), dict(sigma=np.where(sp.mask == 1, 0.0, 1.0)),
+        dict(sigma=np.where(sp.mask == 1, np.nan, 1.0)), dict(data=np.where(sp.mask == 1, np.inf, 0.0)),
+        dict(psf=np.full((3, 3), np.nan)),
+    ]
+    for kw in bad:
+        a = dict(good)
+        a.update(kw)
+        with pytest.raises(b.LensError) as ei:
+            ctx.load_raw(a["ny"], a["nx"], a["dpix"], a["s"], a["psf"], a["data"], a["sigma"], a["mask"])
+        assert ei.value.status == b.LENS_EINVAL, kw
+    with pytest.raises(b.LensError) as ei:
+        ctx.load_raw(sp.ny, sp.nx, sp.dpix, sp.s, sp.psf, sp.data, sp.sigma, sp.mask, precision=7)
+    assert ei.value.status == b.LENS_EINVAL
+    # sigma and data may be anything outside the mask
+    lid = ctx.load_raw(sp.ny, sp.nx, sp.dpix, sp.s, sp.psf, np.where(sp.mask == 1, sp.data, np.nan),
+                       np.where(sp.mask == 1, sp.sigma, 0.0), sp.mask)
+    assert np.array_equal(ctx.loglike(lid, sp.proposals), ctx.loglike(lid, sp.proposals))
+    ctx.unload(lid)
+
+
+def test_unknown_ids(ctx, b):
+    say("case: unknown lens and request ids")
+    for fn in (lambda: ctx.loglike(987654, np.zeros((1, 20))), lambda: ctx.unload(987654),
+               lambda: ctx.info(987654), lambda: ctx.submit(987654, np.zeros((1, 20)))):
+        with pytest.raises(b.LensError) as ei:
+            fn()
+        assert ei.value.status == b.LENS_ENOENT
+    fake = b.Request(ctx.ctx, 123456789, np.zeros(1))
+    with pytest.raises(b.LensError):
+        ctx.poll(fake)
+
+
+def test_info_and_norm(ctx):
+    say("case: lens info")
+    sp = _spec(1)
+    lid = ctx.load(sp)
+    info = ctx.info(lid)
+    assert info["masked_pixels"] == int(sp.mask.sum())
+    C = -0.5 * np.sum(np.log(2 * np.pi * sp.sigma[sp.mask == 1] ** 2))
+    assert abs(info["norm"] - C) < 1e-9 * abs(C)
+    assert info["needed_pixels"] >= info["masked_pixels"]
+    ctx.unload(lid)
+
+
+def _slow_spec():
+    """200x200 px, s = 4, 41x41 PSF: ~30 ms per 16,384 proposals, so requests stay in flight."""
+    sp = synth.config4(nlens=1, nprop=16384)[0]
+    oracle_data(sp)
+    return sp
+
+
+def test_request_life_cycle(ctx, b):
+    say("case: submit / poll / wait / cancel")
+    sp = _spec(3000)
+    lid = ctx.load(sp)
+    ref = ctx.loglike(lid, sp.proposals)
+    r = ctx.submit(lid, sp.proposals)
+    assert ctx.wait(r) == b.LENS_OK
+    assert np.array_equal(r.out, ref)
+    with pytest.raises(b.LensError) as ei:       # the id is forgotten after its final answer
+        ctx.poll(r)
+    assert ei.value.status == b.LENS_ENOENT
+    r2 = ctx.submit(lid, sp.proposals[:100])
+    while ctx.poll(r2) == b.LENS_PENDING:
+        pass
+    assert np.array_equal(r2.out, ref[:100])
+    r0 = ctx.submit(lid, np.zeros((0, 20)))      # zero-proposal request
+    assert ctx.wait(r0) == b.LENS_OK
+    ctx.unload(lid)
+    # a slow lens keeps requests in flight: unload is refused, the last queued
+    # request can be cancelled before it runs and its output is never written
+    slow = _slow_spec()
+    sl = ctx.load(slow)
+    reqs = [ctx.submit(sl, slow.proposals) for _ in range(6)]
+    with pytest.raises(b.LensError) as ei:
+        ctx.unload(sl)
+    assert ei.value.status == b.LENS_EBUSY
+    reqs[-1].out[:] = 12345.0
+    ctx.cancel(reqs[-1])
+    for rq in reqs[:-1]:
+        assert ctx.wait(rq) == b.LENS_OK
+    assert np.all(reqs[-1].out == 12345.0)
+    assert np.array_equal(reqs[0].out, reqs[1].out)
+    st = ctx.stats()
+    assert st["requests_canceled"] >= 1 and st["requests_done"] >= 7
+    ctx.unload(sl)
+
+
+def test_wait_timeout(ctx, b):
+    say("case: wait timeout")
+    sp = _spec(2000)
+    lid = ctx.load(sp)
+    big = np.tile(sp.proposals, (40, 1))
+    r = ctx.submit(lid, big)
+    st = ctx.wait(r, timeout_us=1)
+    assert st in (b.LENS_ETIMEDOUT, b.LENS_OK)
+    if st == b.LENS_ETIMEDOUT:
+        assert ctx.wait(r) == b.LENS_OK
+    ctx.unload(lid)
+
+
+def test_hbm_budget(b):
+    say("case: HBM budget")
+    sp = _spec(10)
+    with b.LensContext(0, hbm_budget_bytes=200_000) as c:
+        with pytest.raises(b.LensError) as ei:
+            for _ in range(10):
+                c.load(sp)
+        assert ei.value.status == b.LENS_ENOMEM
+        assert c.stats()["hbm_used_bytes"] <= 200_000
+
+
+def test_nonblocking_submit(b):
+    say("case: non-blocking submit")
+    slow = _slow_spec()
+    with b.LensContext(0, max_inflight=1, nonblocking_submit=True) as c:
+        lid = c.load(slow)
+        reqs, again = [], 0
+        for _ in range(12):
+            try:
+                reqs.append(c.submit(lid, slow.proposals[:8192]))
+            except b.LensError as e:
+                assert e.status == b.LENS_EAGAIN
+                again += 1
+            if reqs and again == 0:
+                import time
+                time.sleep(0.002)   # let the scheduler occupy the single slot
+        for r in reqs:
+            assert c.wait(r) == b.LENS_OK
+        assert again > 0 and len(reqs) > 0
+        c.unload(lid)
+
+
+def test_model_image_rejects_bad_proposal(ctx, b):
+    say("case: model image domain")
+    sp = _spec(1)
+    lid = ctx.load(sp)
+    p = sp.truth.copy()
+    p[synth.SLOT["q_m"]] = 1.5
+    with pytest.raises(b.LensError) as ei:
+        ctx.model_image(lid, p, 1)
+    assert ei.value.status == b.LENS_EINVAL
+    ctx.unload(lid)
