@@ -88,6 +88,22 @@ def rel_errors(gpu, ref, chi2, C):
     return np.abs(gpu - ref) / (0.5 * chi2 + abs(C))
 
 
+def measured_traffic(prec):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE record, or None
+    when there is none or the kernel sources have changed since it was taken."""
+    if prec != 0:
+        return None
+    from paper_2503_08586_amd import profiling
+    try:
+        with open(profiling.RECORD) as f:
+            rec = json.load(f)
+        if rec.get("kernel_src_sha256") != profiling.kernel_hash():
+            return None
+        return rec["traffic_bytes_per_launch"]
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def dilated_count(mask, r):
     """Pixels of the mask dilated by a (2r+1)^2 box (the sub-pixel work the path needs)."""
     ny, nx = mask.shape
@@ -170,7 +186,7 @@ def main():
     slots_per_prop = E * SLOTS_PER_EVAL + M * spec.k * spec.k + M
     achieved = slots_per_prop * n / (kern_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOT_PER_S / 1e12,
-                "unit": "Tslot/s", "frac": achieved / PEAK_SLOT_PER_S, "traffic": None,
+                "unit": "Tslot/s", "frac": achieved / PEAK_SLOT_PER_S, "traffic": measured_traffic(prec),
                 "kernel": "k_loglike_fp32<21> (+ k_prep)", "kernel_ms": kern_ms,
                 "slots_per_proposal": slots_per_prop, "subpixel_evals_per_proposal": E}
 
