@@ -47,12 +47,23 @@ __device__ __forceinline__ double rsq64(double x)
     return fma(0.5 * r, fma(-(x * r), r, 1.0), r);
 }
 
-template <typename T, int N>
-__device__ __forceinline__ T horner(const T (&c)[N], T w)
+// a b + c as one VOP3 v_fma_f64 with c taken from an SGPR pair; c must be
+// wave-uniform (here: a polynomial coefficient).  Written out because the
+// compiler otherwise keeps FP64 coefficients in VGPRs and emits v_fmac_f64,
+// whose tied addend costs a v_mov_b64 per step and ~40 VGPRs for the tables.
+__device__ __forceinline__ double fma_c(double a, double b, double c)
 {
-    T p = c[N - 1];
+    double d;
+    asm("v_fma_f64 %0, %1, %2, %3" : "=v"(d) : "v"(a), "v"(b), "s"(c));
+    return d;
+}
+
+template <int N>
+__device__ __forceinline__ double horner(const double (&c)[N], double w)
+{
+    double p = c[N - 1];
 #pragma unroll
-    for (int i = N - 2; i >= 0; --i) p = fma(p, w, c[i]);
+    for (int i = N - 2; i >= 0; --i) p = fma_c(p, w, c[i]);
     return p;
 }
 
@@ -91,9 +102,15 @@ __device__ __forceinline__ double sie_a2(double u2, double ce, double bsie, doub
         const bool red = z > 0.5;
         const double zr = red ? (z - 0.75) * rcp_nr(fma(-0.75, z, 1.0)) : z;
         const double p = horner(kAtanhOverT64, zr * zr);
-        return red ? copysign(bsc * fma(zr, p, kAtanh075), t) : bsie * u2 * p;
+        return red ? copysign(bsc * fma_c(zr, p, kAtanh075), t) : bsie * u2 * p;
     }
-    return copysign(bsc * 0.5 * log((1.0 + z) / (1.0 - z)), t);
+    // atanh z = (ln 2 / 2) log2 y with y = (1 + z)/(1 - z) > 19:
+    // FP32 log2 seed l0 (absolute error ~1e-6), then one Newton step on 2^l = y,
+    // l1 = l0 + (y 2^-l0 - 1) log2 e, whose error is quadratic in the seed's (~1e-13).
+    const double y = (1.0 + z) * rcp_nr(1.0 - z);
+    const double l0 = (double)hw_log2((float)y);
+    const double l1 = fma(fma(y, exp2_64(kExp2T64, -l0), -1.0), 1.4426950408889634, l0);
+    return copysign(bsc * 0.34657359027997264 * l1, t);
 }
 
 // Elliptical Sersic (Eqs. 8, 10) at offset (dx, dy) from its centre:

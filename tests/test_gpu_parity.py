@@ -222,6 +222,21 @@ def test_special_proposals(ctx):
     ctx.unload(lid)
 
 
+def test_low_axis_ratio_mass(ctx):
+    """Mass axis ratios below 0.44 send the minor-axis deflection through its
+    logarithm branch (|c u2| > 0.9) on part of the grid; sweep q down to 0.05
+    with the rest of each proposal from the prior."""
+    say("case: low mass axis ratios (atanh logarithm branch)")
+    spec = synth.config1(nprop=96)[0]
+    oracle_data(spec)
+    lid = ctx.load(spec)
+    P = spec.proposals.copy()
+    P[:, synth.SLOT["q_m"]] = np.linspace(0.05, 0.45, len(P))
+    got = ctx.loglike(lid, P)
+    _check(spec, got, P, label="low q_m")
+    ctx.unload(lid)
+
+
 def test_batch_composition_bitwise(ctx):
     say("case: batch composition and order")
     spec = synth.config2(nprop=3000)[0]
