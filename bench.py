@@ -64,6 +64,11 @@ def gpu_data(ctx, spec):
     spec.data = model + spec.noise
 
 
+def path_dtype(prec):
+    """Arithmetic types of the path: FP64 ray trace, light and chi2; FP32 or BF16-MFMA convolution."""
+    return "f64+f32" if prec in (None, "fp32") else "f64+bf16"
+
+
 def credited_slots(spec, M):
     """Credited VALU work of one proposal (60 FMA-class + 10 transcendentals per sub-pixel
     evaluation, one FMA per PSF tap at each masked pixel, one FP64 FMA per masked pixel)."""
@@ -223,7 +228,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": path_dtype(args.precision),
         "data": "synthetic",
         "config": {"workload": "plain survey scale: 1 lens, 128x128 px at 0.05\"/px, 4x4 supersampling, "
                                "21x21 Gaussian PSF FWHM 0.1\", r=3\" mask, %d proposals per call, "
@@ -286,7 +291,7 @@ def run_batch(args):
     rec = {
         "metric": METRIC, "value": n / step_s, "unit": "loglike evals/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": path_dtype(args.precision), "data": "synthetic",
         "config": {"workload": "batching: 256 lenses, N~U{48..160}, 0.05-0.074\"/px, s in {2,4}, k in 11..31, "
                                "%d proposals (U{128..4096} per lens), one persistent launch in a hipGraph, "
                                "host buffers, %s PSF convolution" % (n, args.precision or "fp32"),
@@ -342,10 +347,13 @@ def run_precision(args):
                   "frac_credited_alu": slots / (gpu_ms * 1e-3) / PEAK_SLOT_PER_S}
         for l in lids:
             ctx.unload(l)
-    best = max(per, key=lambda m: per[m]["evals_per_s"] if (m == "bf16" or per[m]["max_rel_err"] <= 1e-6) else 0)
+    # value: the fastest mode whose sampled lnL error is within 1e-6 (plain BF16, gated at 1e-3, is reported
+    # beside it in "modes" but never as value)
+    ok = [m for m in per if per[m]["max_rel_err"] <= 1e-6] or list(per)
+    best = max(ok, key=lambda m: per[m]["evals_per_s"])
     rec = {"metric": METRIC, "value": per[best]["evals_per_s"], "unit": "loglike evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": per[best]["ms_per_step"],
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16", "data": "synthetic",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": path_dtype(best), "data": "synthetic",
            "config": {"workload": "precision: 64 lenses 200x200 px at 0.05\"/px, s=4, 41x41 Moffat beta=3 FWHM 0.15\", "
                                   "16,384 proposals each, one multi-lens call per step", "value_mode": best},
            "modes": per,
@@ -429,7 +437,7 @@ def run_serving(args):
                            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
     rec = {"metric": METRIC, "value": peak, "unit": "loglike evals/s", "n_gpus": 1, "steps": args.requests,
            "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32+bf16" if prec else "f32", "data": "synthetic",
+           "dtype": path_dtype(args.precision or "split"), "data": "synthetic",
            "config": {"workload": "serving: 1,000 resident lenses N~U{48..200}, k~U{11..41}, s=4, Gaussian/Moffat "
                                   "PSFs; Poisson requests of U{100..10000} proposals on random lenses; %s convolution"
                                   % (args.precision or "split"), "requests_per_load": args.requests},

@@ -125,6 +125,11 @@ typedef struct lens_info {
     int64_t needed_pixels;      /* pixels inside the mask dilated by the PSF footprint */
     int64_t device_bytes;       /* device memory held for this lens */
     double norm;                /* C = -1/2 sum_mask ln(2 pi sigma^2) */
+    int32_t strip_rows;         /* tile shape of the likelihood kernel: output rows per strip */
+    int32_t threads;            /*   and workgroup size (fixed rule or autotuner) */
+    int64_t lds_bytes;          /* dynamic LDS of one workgroup (the binned-row ring) */
+    int32_t blocks_per_cu;      /* resident workgroups per compute unit at that shape */
+    int32_t reserved;           /* 0 */
 } lens_info;
 
 typedef struct lens_stats {
@@ -148,6 +153,9 @@ void lens_shutdown(lens_ctx *ctx);
 lens_status lens_load_data(lens_ctx *ctx, const lens_data_desc *desc, lens_id *out_id);
 /* Free a lens.  LENS_EBUSY while requests on it are queued or running. */
 lens_status lens_unload(lens_ctx *ctx, lens_id id);
+/* Describe a resident lens: its sizes, M, C and the tile shape its likelihood
+ * kernel runs at (strip rows, threads, LDS bytes, resident workgroups per CU).
+ * LENS_ENOENT for an unknown id. */
 lens_status lens_get_info(lens_ctx *ctx, lens_id id, lens_info *out);
 
 /* lnL of n proposals (host buffers, params [n][20], out [n]).  Blocks until

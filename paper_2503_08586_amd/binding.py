@@ -85,6 +85,8 @@ class lens_info(ctypes.Structure):
         ("psf_size", ctypes.c_int32), ("precision", ctypes.c_int32),
         ("masked_pixels", ctypes.c_int64), ("needed_pixels", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64), ("norm", ctypes.c_double),
+        ("strip_rows", ctypes.c_int32), ("threads", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
+        ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 

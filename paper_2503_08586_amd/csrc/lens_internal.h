@@ -78,7 +78,8 @@ int ring_width(int mode, int k, int nx);
 size_t ring_row_bytes(int mode, int k, int nx);
 // largest dynamic LDS one workgroup may use on this device
 size_t max_lds_bytes();
-hipError_t set_lds_limits(size_t bytes);
+size_t set_lds_limits(size_t bytes);   // dynamic LDS now accepted by every ring kernel; 0 on refusal
+size_t lds_per_cu();
 
 hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, hipStream_t st);
 // the fused likelihood of n proposals of one lens (FP32 or MFMA convolution per g.mode)
@@ -86,6 +87,7 @@ hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, d
                           hipStream_t st);
 // persistent multi-lens launch (counter reset + kernel) and its occupancy
 int batch_blocks_per_cu(int mode, int nt, size_t lds);
+int loglike_blocks_per_cu(const LensGeom &g);    // resident single-lens workgroups per CU; 0 if unknown
 hipError_t launch_batch(int mode, int nt, int grid, size_t lds, const LensGeom *d_geoms, const int *d_lstart,
                         const int64_t *d_lout, int nl, int nitems, const PropBlock *d_pc, double *d_out,
                         unsigned int *d_counter, hipStream_t st);

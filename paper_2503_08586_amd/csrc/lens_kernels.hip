@@ -11,7 +11,9 @@
 // Forward model: Cao et al. (2025), Sec. 2.1 (Eqs. 1-3), Sec. 2.2 (Eq. 5), Sec. 2.4.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
+#include <vector>
 
 #include "lens_device.h"
 #include "lens_internal.h"
@@ -578,13 +580,21 @@ size_t ring_row_bytes(int mode, int k, int nx)
 
 size_t ring_bytes(const LensGeom &g) { return (size_t)g.ring_rows * ring_row_bytes(g.mode, g.k, g.nx); }
 
+// Dynamic LDS one workgroup may use: the opt-in limit when the device reports
+// one above the default per-block limit (gfx950 addresses all 160 KB of a CU
+// from one workgroup), never more than a CU holds.
 size_t max_lds_bytes()
 {
-    int dev = 0, v = 0;
+    int dev = 0, v = 0, optin = 0, per_cu = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 65536;
-    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
-        return 65536;
-    return (size_t)v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) v = 65536;
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, dev) != hipSuccess) optin = 0;
+    if (hipDeviceGetAttribute(&per_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess)
+        per_cu = 0;
+    (void)hipGetLastError();
+    size_t m = (size_t)std::max(v, optin);
+    if (per_cu > 0) m = std::min(m, (size_t)per_cu);
+    return m;
 }
 
 hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, hipStream_t st)
@@ -650,39 +660,79 @@ hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, d
 static const void *batch_kernel(int mode, int nt);
 
 template <int NT>
-static hipError_t set_limits_nt(int bytes)
+static const void *loglike_kernel_nt(const LensGeom &g)
 {
-    hipError_t e = hipSuccess;
-#define LENS_K(KK)                                                                                   \
-    if (e == hipSuccess)                                                                             \
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_loglike_fp32<KK, NT>),             \
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    switch (g.mode) {
+    case MODE_BF16: return reinterpret_cast<const void *>(&k_loglike_mfma<MODE_BF16, NT>);
+    case MODE_SPLIT: return reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT, NT>);
+    case MODE_SPLIT3: return reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT3, NT>);
+    case MODE_FP32: break;
+    default: return nullptr;
+    }
+    switch (g.k) {
+#define LENS_K(KK) \
+    case KK: return reinterpret_cast<const void *>(&k_loglike_fp32<KK, NT>);
+        LENS_K(1) LENS_K(3) LENS_K(5) LENS_K(7) LENS_K(9) LENS_K(11) LENS_K(13) LENS_K(15)
+        LENS_K(17) LENS_K(19) LENS_K(21) LENS_K(23) LENS_K(25) LENS_K(27) LENS_K(29) LENS_K(31)
+        LENS_K(33) LENS_K(35) LENS_K(37) LENS_K(39) LENS_K(41) LENS_K(43) LENS_K(45) LENS_K(47)
+        LENS_K(49) LENS_K(51) LENS_K(53) LENS_K(55) LENS_K(57) LENS_K(59) LENS_K(61) LENS_K(63)
+#undef LENS_K
+    default: return nullptr;
+    }
+}
+
+int loglike_blocks_per_cu(const LensGeom &g)
+{
+    const void *k = g.nt == 512 ? loglike_kernel_nt<512>(g) : g.nt == 256 ? loglike_kernel_nt<256>(g) : nullptr;
+    int nb = 0;
+    if (!k || hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k, g.nt, ring_bytes(g)) != hipSuccess) return 0;
+    return nb;
+}
+
+template <int NT>
+static void likelihood_kernels_nt(std::vector<const void *> &v)
+{
+#define LENS_K(KK) v.push_back(reinterpret_cast<const void *>(&k_loglike_fp32<KK, NT>));
     LENS_K(1) LENS_K(3) LENS_K(5) LENS_K(7) LENS_K(9) LENS_K(11) LENS_K(13) LENS_K(15)
     LENS_K(17) LENS_K(19) LENS_K(21) LENS_K(23) LENS_K(25) LENS_K(27) LENS_K(29) LENS_K(31)
     LENS_K(33) LENS_K(35) LENS_K(37) LENS_K(39) LENS_K(41) LENS_K(43) LENS_K(45) LENS_K(47)
     LENS_K(49) LENS_K(51) LENS_K(53) LENS_K(55) LENS_K(57) LENS_K(59) LENS_K(61) LENS_K(63)
 #undef LENS_K
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_BF16, NT>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT, NT>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    if (e == hipSuccess)
-        e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT3, NT>),
-                                hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-    return e;
+    v.push_back(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_BF16, NT>));
+    v.push_back(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT, NT>));
+    v.push_back(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT3, NT>));
+    for (int m : {MODE_FP32, MODE_SPLIT, MODE_BF16, MODE_SPLIT3}) v.push_back(batch_kernel(m, NT));
 }
 
-hipError_t set_lds_limits(size_t bytes)
+// Raise every ring-using kernel's dynamic-LDS limit so that dynamic plus
+// static LDS reaches `bytes`.  Returns the dynamic bytes all of them accept
+// (0 if the runtime refused any, leaving the default limit in force).
+size_t set_lds_limits(size_t bytes)
 {
-    hipError_t e = set_limits_nt<256>((int)bytes);
-    if (e == hipSuccess) e = set_limits_nt<512>((int)bytes);
-    for (int nt : {256, 512})
-        for (int m : {MODE_FP32, MODE_SPLIT, MODE_BF16, MODE_SPLIT3})
-            if (e == hipSuccess)
-                e = hipFuncSetAttribute(batch_kernel(m, nt), hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    return e;
+    std::vector<const void *> ks;
+    likelihood_kernels_nt<256>(ks);
+    likelihood_kernels_nt<512>(ks);
+    size_t usable = bytes;
+    for (const void *k : ks) {
+        hipFuncAttributes a{};
+        if (!k || hipFuncGetAttributes(&a, k) != hipSuccess) return 0;
+        const size_t dyn = bytes > a.sharedSizeBytes ? bytes - a.sharedSizeBytes : 0;
+        if (dyn == 0 || hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn) != hipSuccess)
+            return 0;
+        usable = std::min(usable, dyn);
+    }
+    return usable;
+}
+
+size_t lds_per_cu()
+{
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess || v <= 0) {
+        (void)hipGetLastError();
+        return 65536;
+    }
+    return (size_t)v;
 }
 
 template <int MODE, int NT>

@@ -179,21 +179,28 @@ bool set_tiles(LensGeom &g, int H, int nt, size_t lds_max)
     return true;
 }
 
-// Default shape: strips of up to 16 rows; 256 threads while the ring fits
-// 40 KB (4 workgroups, i.e. 4 waves per SIMD, share a CU's 160 KB), else 512
-// threads under 80 KB, else the device's per-workgroup maximum.
-int default_strip(const LensGeom &g, size_t lds_max, int *nt)
+// Default shape, from full-batch timings on MI355X:
+// - FP32 convolution whose ring for 16-row strips fits a quarter of a CU's LDS:
+//   256 threads, 16 rows (the most resident workgroups);
+// - otherwise 512 threads and the tallest strip of min(32, ny), 16, 8 or 4 rows
+//   whose ring lets two workgroups share a CU (powers of two keep the MFMA
+//   convolution's 16-segment tiles spread evenly over the 8 waves);
+// - failing that, the tallest strip that fits one workgroup's LDS.
+int default_strip(const LensGeom &g, size_t lds_max, size_t lds_cu, int *nt)
 {
     const size_t row_b = lensk::ring_row_bytes(g.mode, g.k, g.nx);
-    auto rows_fit = [&](size_t budget) { return (int)std::min<size_t>(budget / row_b, 1 << 20) - 2 * g.r; };
-    int H = std::min(16, rows_fit(40960));
-    *nt = 256;
-    if (H < 8) {
-        *nt = 512;
-        H = std::min(16, rows_fit(std::min<size_t>(81920, lds_max)));
+    const auto ring = [&](int H) { return (size_t)(H + 2 * g.r) * row_b; };
+    if (g.mode == lensk::MODE_FP32 && ring(std::min(16, g.ny)) <= std::min(lds_max, lds_cu / 4)) {
+        *nt = 256;
+        return std::min(16, g.ny);
     }
-    if (H < 4) H = std::min(16, rows_fit(lds_max));
-    return H;
+    *nt = 512;
+    const size_t half = std::min(lds_max, lds_cu / 2);
+    for (int H : {std::min(32, g.ny), 16, 8, 4})
+        if (H <= g.ny && ring(H) <= half) return H;
+    for (int H = std::min(32, g.ny); H >= 1; --H)
+        if (ring(H) <= lds_max) return H;
+    return 0;
 }
 
 }  // namespace
@@ -207,6 +214,7 @@ struct lens_ctx {
     void *user = nullptr;
     int64_t budget = 0;
     size_t lds_max = 65536;               // dynamic LDS one workgroup may use
+    size_t lds_cu = 65536;                // LDS of one compute unit
     std::atomic<int64_t> used{0};
     std::atomic<int> dev_error{0};
 
@@ -457,8 +465,10 @@ extern "C" lens_status lens_init(const lens_init_opts *opts, lens_ctx **out)
     }
     {
         const size_t m = lensk::max_lds_bytes();
-        if (m > 65536 && lensk::set_lds_limits(m) == hipSuccess) c->lds_max = m;
-        else (void)hipGetLastError();
+        const size_t u = m > 65536 ? lensk::set_lds_limits(m) : 0;
+        if (u > 65536) c->lds_max = u;
+        (void)hipGetLastError();
+        c->lds_cu = lensk::lds_per_cu();
     }
     lens_ctx *raw = c.release();
     raw->sched = std::thread(scheduler_main, raw);
@@ -573,7 +583,8 @@ lens_status tune_lens(lens_ctx *c, Lens *L)
             return LENS_OK;
         }
     }
-    const int64_t n = std::max<int64_t>(512, 8LL * c->num_cus);
+    // a batch large enough that the last partial wave of workgroups does not decide the ranking
+    const int64_t n = std::max<int64_t>(2048, 32LL * c->num_cus);
     std::vector<double> hp((size_t)n * lensk::kStride, 0.0);
     for (int64_t i = 0; i < n; ++i) {
         const double j = (double)(i % 97) / 97.0;   // mild spread, all inside the domain
@@ -598,32 +609,36 @@ lens_status tune_lens(lens_ctx *c, Lens *L)
     HIPCHK(c, hipEventCreate(&e1));
     float best = 1e30f;
     int bestH = L->g.strip_h, bestNT = L->g.nt;
+    std::vector<std::pair<int, int>> cand = {{L->g.strip_h, L->g.nt}};   // the default shape, then the grid
     for (int nt : {256, 512})
-        for (int H : {4, 8, 16, 32}) {
-            LensGeom g2 = L->g;
-            if (!set_tiles(g2, H, nt, c->lds_max) || g2.strip_h != H) continue;
-            float t = 1e30f;
-            hipError_t e = lensk::launch_loglike(g2, dpc, n, dout, c->stream);  // warm-up
-            for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
-                e = hipEventRecord(e0, c->stream);
-                if (e == hipSuccess) e = lensk::launch_loglike(g2, dpc, n, dout, c->stream);
-                if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                float ms = 0.f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                if (e == hipSuccess) t = std::min(t, ms);
-            }
-            if (e != hipSuccess) {
-                (void)hipEventDestroy(e0);
-                (void)hipEventDestroy(e1);
-                return hip_fail(c, e, "autotune launch");
-            }
-            if (t < best) {
-                best = t;
-                bestH = H;
-                bestNT = nt;
-            }
+        for (int H : {4, 8, 16, 32})
+            if (!(H == L->g.strip_h && nt == L->g.nt)) cand.push_back({H, nt});
+    for (const auto &hc : cand) {
+        const int H = hc.first, nt = hc.second;
+        LensGeom g2 = L->g;
+        if (!set_tiles(g2, H, nt, c->lds_max) || g2.strip_h != H) continue;
+        float t = 1e30f;
+        hipError_t e = lensk::launch_loglike(g2, dpc, n, dout, c->stream);  // warm-up
+        for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
+            e = hipEventRecord(e0, c->stream);
+            if (e == hipSuccess) e = lensk::launch_loglike(g2, dpc, n, dout, c->stream);
+            if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e == hipSuccess) t = std::min(t, ms);
         }
+        if (e != hipSuccess) {
+            (void)hipEventDestroy(e0);
+            (void)hipEventDestroy(e1);
+            return hip_fail(c, e, "autotune launch");
+        }
+        if (t < best) {
+            best = t;
+            bestH = H;
+            bestNT = nt;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     LensGeom g2 = L->g;
@@ -650,6 +665,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     lens_status st = check_ctx(c);
     if (st != LENS_OK) return st;
     if (!d || !out_id) return fail(c, LENS_EINVAL, "null descriptor or output");
+    DeviceGuard dg(c->device);   // the tile choice queries the device's occupancy
     const int ny = d->ny, nx = d->nx, s = d->supersample, k = d->psf_size;
     if (ny < 1 || nx < 1 || ny > 4096 || nx > 4096) return fail(c, LENS_EINVAL, "ny, nx must be in 1..4096");
     if (!(d->pixel_scale > 0.0) || !std::isfinite(d->pixel_scale)) return fail(c, LENS_EINVAL, "pixel_scale must be > 0");
@@ -709,7 +725,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     LensGeom g{};
     g.ny = ny; g.nx = nx; g.s = s; g.k = k; g.r = r; g.pitch = pitch; g.mode = mode;
     g.ring_w = lensk::ring_width(mode, k, nx);
-    if (!set_tiles(g, default_strip(g, c->lds_max, &g.nt), g.nt, c->lds_max))
+    if (!set_tiles(g, default_strip(g, c->lds_max, c->lds_cu, &g.nt), g.nt, c->lds_max))
         return fail(c, LENS_EINVAL, "image too wide for the LDS line buffer at this PSF size");
     // MFMA operands: 16-wide output segments covering the mask (row-major, with
     // row prefix) and the banded Toeplitz expansion of the flipped PSF, split
@@ -766,7 +782,6 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     const size_t o_cvl = place(cvl.size() * 4), o_cvpre = place(cvpre.size() * 4);
     const size_t o_aop = place(aop.size() * 2), o_seg = place(seg.size() * 4), o_segpre = place(segpre.size() * 4);
     const size_t total = off;
-    DeviceGuard dg(c->device);
     if (!charge(c, (int64_t)total)) return fail(c, LENS_ENOMEM, "HBM budget exhausted");
     void *slab = dev_alloc(c, total);
     if (!slab) {
@@ -884,6 +899,14 @@ extern "C" lens_status lens_get_info(lens_ctx *c, lens_id id, lens_info *out)
     out->needed_pixels = L->needed;
     out->device_bytes = (int64_t)L->bytes;
     out->norm = L->g.norm;
+    out->strip_rows = L->g.strip_h;
+    out->threads = L->g.nt;
+    out->lds_bytes = (int64_t)lensk::ring_bytes(L->g);
+    out->reserved = 0;
+    {
+        DeviceGuard dg(c->device);
+        out->blocks_per_cu = lensk::loglike_blocks_per_cu(L->g);
+    }
     release(c, L);
     return LENS_OK;
 }

@@ -57,7 +57,18 @@ def main():
     rec = {"kernel": "k_loglike_fp32<21,256>", "workload": "plain 128x128 s=4 k=21, 65,536 proposals/launch",
            "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw, "dispatches": [nf, nw],
            "copy_fetch_kib": copy_f, "copy_write_kib": copy_w, "scale_fetch": sf, "scale_write": sw,
-           "traffic_bytes_per_launch": (kf * sf + kw * sw) * 1024.0, "kernel_src_sha256": kernel_hash()}
+           "traffic_bytes_per_launch": (kf * sf + kw * sw) * 1024.0, "kernel_src_sha256": kernel_hash(),
+           "commands": [
+               "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_copy_fetch -o p -- "
+               "python3 bench.py --copy-calibration",
+               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_copy_write -o p -- "
+               "python3 bench.py --copy-calibration",
+               "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_plain_fetch -o p -- "
+               "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline",
+               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_plain_write -o p -- "
+               "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline",
+               "python -m paper_2503_08586_amd.profiling gpurun_out/pmc_copy_fetch gpurun_out/pmc_copy_write "
+               "gpurun_out/pmc_plain_fetch gpurun_out/pmc_plain_write"]}
     with open(RECORD, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))

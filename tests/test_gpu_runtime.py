@@ -74,6 +74,10 @@ def test_info_and_norm(ctx):
     C = -0.5 * np.sum(np.log(2 * np.pi * sp.sigma[sp.mask == 1] ** 2))
     assert abs(info["norm"] - C) < 1e-9 * abs(C)
     assert info["needed_pixels"] >= info["masked_pixels"]
+    assert info["threads"] in (256, 512) and 1 <= info["strip_rows"] <= 32
+    assert 0 < info["lds_bytes"] <= 160 * 1024 and info["blocks_per_cu"] >= 1
+    say("tile: %d rows x %d threads, %d B LDS, %d workgroups/CU" % (
+        info["strip_rows"], info["threads"], info["lds_bytes"], info["blocks_per_cu"]))
     ctx.unload(lid)
 
 
