@@ -113,23 +113,32 @@ __device__ __forceinline__ double sie_a2(double u2, double ce, double bsie, doub
     return copysign(bsc * 0.34657359027997264 * l1, t);
 }
 
-// Elliptical Sersic (Eqs. 8, 10) at offset (dx, dy) from its centre:
-//   I_e exp(-b ((R/R_e)^(1/n) - 1)) = I_e 2^(B (1 - t)),  t = ((R/R_e)^2)^(1/(2n)),  B = b log2 e,
+// Elliptical Sersic (Eqs. 8, 10) at offset (dx, dy) from its centre, without
+// its amplitude:
+//   exp(-b ((R/R_e)^(1/n) - 1)) = 2^(B (1 - t)),  t = ((R/R_e)^2)^(1/(2n)),  B = b log2 e,
 // with (R/R_e)^2 = P dx^2 + Q dy^2 + S dx dy, the rotation of Eq. 10 folded into P, Q, S.
-__device__ __forceinline__ double sersic(double dx, double dy, const LightK &L)
+// log2 (R/R_e)^2 is clamped to [-2048, 128] in one FP32 med3: the centre
+// (R = 0) then gives t = 2^-(2048 e) ~ 0 and an overflowing radius a finite t,
+// so every exponent below stays finite; B (1 - t) >= -2000 keeps the last
+// exponent in int range (2^-2000 is 0 in FP64).
+__device__ __forceinline__ double sersic_shape(double dx, double dy, const LightK &L)
 {
     const double r2 = fma(L.P, dx * dx, fma(L.Q, dy * dy, L.S * (dx * dy)));
-    const double lg = (double)hw_log2((float)r2);
-    const double t = exp2_64(kExp2T64, fmin(fmax(L.e * lg, -1000.0), 64.0));
-    return L.I * exp2_64(kExp2E64, fmax(L.B * (1.0 - t), -1000.0));
+    const float lg = __builtin_amdgcn_fmed3f(hw_log2((float)r2), -2048.0f, 128.0f);
+    const double t = exp2_64(kExp2E64, L.e * (double)lg);
+    return exp2_64(kExp2E64, fmax(fma(-L.B, t, L.B), -2000.0));
 }
 
-// Lens light at theta plus source light at beta = theta - alpha_SIE - alpha_shear (Eqs. 1-2).
+struct Light2 {
+    double lens, src;   // lens light at theta, source light at beta, without amplitudes
+};
+
+// Lens light at theta and source light at beta = theta - alpha_SIE - alpha_shear (Eqs. 1-2).
 // SIE (kappa = theta_E / (2 R_p)) in the frame of the mass ellipse, u = x'/psi,
 // psi = sqrt(q^2 x1'^2 + x2'^2), c = sqrt(1 - q^2):
 //   alpha' = theta_E sqrt(q) / c (atan(c u1), atanh(c u2)),  alpha = 0 at the centre.
 // Shear: alpha = -(g1 x + g2 y, g2 x - g1 y).
-__device__ __forceinline__ double scene(double x, double y, const PropBlock &P)
+__device__ __forceinline__ Light2 scene(double x, double y, const PropBlock &P)
 {
     const double dx = x - P.xm, dy = y - P.ym;
     const double x1 = fma(P.cm, dx, P.sm * dy);
@@ -142,23 +151,34 @@ __device__ __forceinline__ double scene(double x, double y, const PropBlock &P)
     const double a2 = sie_a2(x2 * ir, P.ce, P.bsie, P.bsc);
     const double bx = ((x - fma(P.cm, a1, -(P.sm * a2))) + fma(P.g1, x, P.g2 * y)) - P.xs;
     const double by = ((y - fma(P.sm, a1, P.cm * a2)) + fma(P.g2, x, -(P.g1 * y))) - P.ys;
-    return sersic(dx, dy, P.lens) + sersic(bx, by, P.src);
+    return {sersic_shape(dx, dy, P.lens), sersic_shape(bx, by, P.src)};
 }
 
 // Binned (mean) value of pixel (y, x): s x s sub-pixel centres (Sec. 2.1).
-// Fine-grid index fx = x s + u maps to position (fx - (nx s - 1)/2) * pixel_scale / s.
+// Fine-grid index fx = x s + u maps to position (fx - (nx s - 1)/2) * pixel_scale / s;
+// along a sub-pixel row the position steps by pixel_scale / s (at most 7 FP64
+// additions, ~1e-15 arcsec apart from the direct product).  Lens and source
+// light are summed apart and take their amplitudes once.
 __device__ __forceinline__ float binned_pixel(const LensGeom &g, const PropBlock &P, int y, int x)
 {
     const int s = g.s;
-    double acc = 0.0;
+    const double x0 = ((double)(x * s) - g.cfx) * g.sd;
+    // the step lives in a VGPR: as an SGPR pair it is spilled and reloaded
+    // (v_readlane) on every sub-pixel
+    double step = g.sd;
+    asm("" : "+v"(step));
+    double al = 0.0, as = 0.0;
     for (int v = 0; v < s; ++v) {
         const double yy = ((double)(y * s + v) - g.cfy) * g.sd;
+        double xx = x0;
         for (int u = 0; u < s; ++u) {
-            const double xx = ((double)(x * s + u) - g.cfx) * g.sd;
-            acc += scene(xx, yy, P);
+            const Light2 l = scene(xx, yy, P);
+            al += l.lens;
+            as += l.src;
+            xx += step;
         }
     }
-    return (float)(acc * g.inv_s2);
+    return (float)(fma(P.lens.I, al, P.src.I * as) * g.inv_s2);
 }
 
 // Sersic b_n: root of P(2n, b) = 1/2 (Eq. 9), FP64 Newton safeguarded by
