@@ -106,76 +106,88 @@ __device__ __forceinline__ double sie_a2(double u2, double ce, double bsie, doub
     }
     // atanh z = (ln 2 / 2) log2 y with y = (1 + z)/(1 - z) > 19:
     // FP32 log2 seed l0 (absolute error ~1e-6), then one Newton step on 2^l = y,
-    // l1 = l0 + (y 2^-l0 - 1) log2 e, whose error is quadratic in the seed's (~1e-13).
+    // l1 = l0 + (y 2^-l0 - 1) log2 e: quadratic in the seed's error (~1e-13), plus the
+    // 2^x polynomial's 1.9e-9, i.e. < 1e-9 relative in atanh z (log2 y > 4.2).
     const double y = (1.0 + z) * rcp_nr(1.0 - z);
     const double l0 = (double)hw_log2((float)y);
-    const double l1 = fma(fma(y, exp2_64(kExp2T64, -l0), -1.0), 1.4426950408889634, l0);
+    const double l1 = fma(fma(y, exp2_64(kExp2_64, -l0), -1.0), 1.4426950408889634, l0);
     return copysign(bsc * 0.34657359027997264 * l1, t);
 }
 
-// Elliptical Sersic (Eqs. 8, 10) at offset (dx, dy) from its centre, without
-// its amplitude:
-//   exp(-b ((R/R_e)^(1/n) - 1)) = 2^(B (1 - t)),  t = ((R/R_e)^2)^(1/(2n)),  B = b log2 e,
-// with (R/R_e)^2 = P dx^2 + Q dy^2 + S dx dy, the rotation of Eq. 10 folded into P, Q, S.
-// log2 (R/R_e)^2 is clamped to [-2048, 128] in one FP32 med3: the centre
-// (R = 0) then gives t = 2^-(2048 e) ~ 0 and an overflowing radius a finite t,
-// so every exponent below stays finite; B (1 - t) >= -2000 keeps the last
-// exponent in int range (2^-2000 is 0 in FP64).
-__device__ __forceinline__ double sersic_shape(double dx, double dy, const LightK &L)
+// Elliptical Sersic (Eqs. 8, 10) without its amplitude, from r2 = (R/R_e)^2:
+//   exp(-b ((R/R_e)^(1/n) - 1)) = 2^(B (1 - t)),  t = r2^(1/(2n)),  B = b log2 e.
+// log2 r2 is clamped to [-2048, 128] in one FP32 med3: the centre (r2 = 0)
+// then gives t = 2^-(2048 e) ~ 0 and an overflowing radius a finite t, so every
+// exponent below stays finite; B (1 - t) >= -2000 keeps the last exponent in
+// int range (2^-2000 is 0 in FP64).
+__device__ __forceinline__ double sersic_r2(double r2, const LightK &L)
 {
-    const double r2 = fma(L.P, dx * dx, fma(L.Q, dy * dy, L.S * (dx * dy)));
     const float lg = __builtin_amdgcn_fmed3f(hw_log2((float)r2), -2048.0f, 128.0f);
-    const double t = exp2_64(kExp2E64, L.e * (double)lg);
-    return exp2_64(kExp2E64, fmax(fma(-L.B, t, L.B), -2000.0));
+    const double t = exp2_64(kExp2_64, L.e * (double)lg);
+    return exp2_64(kExp2_64, fmax(fma(-L.B, t, L.B), -2000.0));
 }
 
-struct Light2 {
-    double lens, src;   // lens light at theta, source light at beta, without amplitudes
-};
-
-// Lens light at theta and source light at beta = theta - alpha_SIE - alpha_shear (Eqs. 1-2).
-// SIE (kappa = theta_E / (2 R_p)) in the frame of the mass ellipse, u = x'/psi,
-// psi = sqrt(q^2 x1'^2 + x2'^2), c = sqrt(1 - q^2):
-//   alpha' = theta_E sqrt(q) / c (atan(c u1), atanh(c u2)),  alpha = 0 at the centre.
-// Shear: alpha = -(g1 x + g2 y, g2 x - g1 y).
-__device__ __forceinline__ Light2 scene(double x, double y, const PropBlock &P)
+// (R/R_e)^2 = P dx^2 + Q dy^2 + S dx dy at offset (dx, dy) from a light centre,
+// the rotation and axis ratio of Eq. 10 folded into P, Q, S.
+__device__ __forceinline__ double ellip_r2(double dx, double dy, const LightK &L)
 {
-    const double dx = x - P.xm, dy = y - P.ym;
-    const double x1 = fma(P.cm, dx, P.sm * dy);
-    const double x2 = fma(P.cm, dy, -(P.sm * dx));
+    return fma(L.P, dx * dx, fma(L.Q, dy * dy, L.S * (dx * dy)));
+}
+
+// Source-plane position beta = theta - alpha_SIE - alpha_shear (Eqs. 1-2), given
+// the sub-pixel's coordinates (x1, x2) in the frame of the mass ellipse and the
+// part of beta linear in theta, (lx, ly) = theta - alpha_shear - source centre.
+// SIE (kappa = theta_E / (2 R_p)): u = x'/psi, psi = sqrt(q^2 x1^2 + x2^2),
+// c = sqrt(1 - q^2), alpha' = theta_E sqrt(q) / c (atan(c u1), atanh(c u2)),
+// rotated back by the mass angle; alpha = 0 at the centre.
+// Shear: alpha = -(g1 x + g2 y, g2 x - g1 y).
+__device__ __forceinline__ void ray_trace(double x1, double x2, double lx, double ly, const PropBlock &P,
+                                          double &bx, double &by)
+{
     const double psi2 = fma(P.q2m, x1 * x1, x2 * x2);
     double ir;
     if (psi2 >= 1e-30) ir = rsq_nr(psi2);
     else ir = psi2 > 0.0 ? rsq64(psi2) : 0.0;
     const double a1 = sie_a1(x1 * ir, P.ce, P.bsie, P.bsc);
     const double a2 = sie_a2(x2 * ir, P.ce, P.bsie, P.bsc);
-    const double bx = ((x - fma(P.cm, a1, -(P.sm * a2))) + fma(P.g1, x, P.g2 * y)) - P.xs;
-    const double by = ((y - fma(P.sm, a1, P.cm * a2)) + fma(P.g2, x, -(P.g1 * y))) - P.ys;
-    return {sersic_shape(dx, dy, P.lens), sersic_shape(bx, by, P.src)};
+    bx = lx - fma(P.cm, a1, -(P.sm * a2));
+    by = ly - fma(P.sm, a1, P.cm * a2);
 }
 
 // Binned (mean) value of pixel (y, x): s x s sub-pixel centres (Sec. 2.1).
-// Fine-grid index fx = x s + u maps to position (fx - (nx s - 1)/2) * pixel_scale / s;
-// along a sub-pixel row the position steps by pixel_scale / s (at most 7 FP64
-// additions, ~1e-15 arcsec apart from the direct product).  Lens and source
-// light are summed apart and take their amplitudes once.
+// Fine-grid index fx = x s + u maps to position (fx - (nx s - 1)/2) * pixel_scale / s.
+// Along a sub-pixel row the x offset dx from the mass centre steps by
+// pixel_scale / s (at most 7 FP64 additions, ~1e-15 arcsec from the direct
+// product), and everything else linear in x is one FMA in dx with per-row
+// constants: the mass-frame coordinates, theta - alpha_shear - source centre,
+// and the lens light's (R/R_e)^2 (a quadratic in dx).  Lens and source light
+// are summed apart and take their amplitudes once.
 __device__ __forceinline__ float binned_pixel(const LensGeom &g, const PropBlock &P, int y, int x)
 {
     const int s = g.s;
     const double x0 = ((double)(x * s) - g.cfx) * g.sd;
+    const double dx0 = x0 - P.xm;
     // the step lives in a VGPR: as an SGPR pair it is spilled and reloaded
     // (v_readlane) on every sub-pixel
-    double step = g.sd;
-    asm("" : "+v"(step));
+    double h = g.sd;
+    asm("" : "+v"(h));
     double al = 0.0, as = 0.0;
     for (int v = 0; v < s; ++v) {
         const double yy = ((double)(y * s + v) - g.cfy) * g.sd;
-        double xx = x0;
+        const double dy = yy - P.ym;
+        // values at dx = 0 of: x1 = cm dx + sm dy, x2 = cm dy - sm dx,
+        // lx = x + g1 x + g2 y - xs, ly = y + g2 x - g1 y - ys (x = xm + dx)
+        const double c1 = P.sm * dy, c2 = P.cm * dy;
+        const double cx = (P.xm + fma(P.g1, P.xm, P.g2 * yy)) - P.xs;
+        const double cy = (yy + fma(P.g2, P.xm, -(P.g1 * yy))) - P.ys;
+        const double rs = P.lens.S * dy, rq = P.lens.Q * (dy * dy);
+        double dx = dx0;
         for (int u = 0; u < s; ++u) {
-            const Light2 l = scene(xx, yy, P);
-            al += l.lens;
-            as += l.src;
-            xx += step;
+            double bx, by;
+            ray_trace(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.g1p, dx, cx), fma(P.g2, dx, cy), P, bx, by);
+            al += sersic_r2(fma(fma(P.lens.P, dx, rs), dx, rq), P.lens);
+            as += sersic_r2(ellip_r2(bx, by, P.src), P.src);
+            dx += h;
         }
     }
     return (float)(fma(P.lens.I, al, P.src.I * as) * g.inv_s2);

@@ -29,7 +29,8 @@ struct alignas(16) PropBlock {
     double bsie, bsc;                          // theta_E sqrt(q), theta_E sqrt(q) / c (0 if c = 0)
     double g1, g2, xs, ys;                     // shear, source centre
     LightK lens, src;
-    double pad[7];
+    double g1p;                                // 1 + g1: d/dx of x + g1 x + g2 y
+    double pad[6];
 };
 static_assert(sizeof(PropBlock) == 256, "PropBlock layout");
 constexpr int kPCBytes = (int)sizeof(PropBlock);

@@ -67,6 +67,7 @@ __global__ void __launch_bounds__(256) k_prep(const double *__restrict__ params,
         b.bsie = v[0] * sqrt(q);
         b.bsc = b.ce > 0.0 ? b.bsie / b.ce : 0.0;
         b.g1 = v[5];
+        b.g1p = 1.0 + v[5];
         b.g2 = v[6];
         b.xs = v[17];
         b.ys = v[18];

@@ -237,6 +237,24 @@ def test_low_axis_ratio_mass(ctx):
     ctx.unload(lid)
 
 
+def test_sersic_index_sweep(ctx):
+    """Sersic indices over the whole domain [0.1, 20] (log-uniform, both
+    components): b_n (R/R_e)^(1/n) grows to ~60 at n = 20 and amplifies any
+    error in (R/R_e)^(1/n), so the prior box alone (n <= 4) would not show it."""
+    say("case: Sersic index sweep over [0.1, 20]")
+    spec = synth.config2(nprop=48)[0]
+    spec.s = 2                                   # survey geometry, fewer sub-pixels for the oracle
+    oracle_data(spec)
+    lid = ctx.load(spec)
+    P = spec.proposals.copy()
+    rng = np.random.default_rng(20)
+    P[:, synth.SLOT["n_l"]] = np.exp(rng.uniform(np.log(0.1), np.log(20.0), len(P)))
+    P[:, synth.SLOT["n_s"]] = np.exp(rng.uniform(np.log(0.1), np.log(20.0), len(P)))
+    got = ctx.loglike(lid, P)
+    _check(spec, got, P, label="n sweep")
+    ctx.unload(lid)
+
+
 def test_batch_composition_bitwise(ctx):
     say("case: batch composition and order")
     spec = synth.config2(nprop=3000)[0]
