@@ -58,21 +58,41 @@ __device__ __forceinline__ double fma_c(double a, double b, double c)
     return d;
 }
 
+// sum_i c[i] w^i; `lead` holds c[N - 1] (a caller may pass it in a VGPR
+// loaded once outside its loop, which saves a v_mov_b64 per evaluation).
 template <int N>
-__device__ __forceinline__ double horner(const double (&c)[N], double w)
+__device__ __forceinline__ double horner(const double (&c)[N], double w, double lead)
 {
-    double p = c[N - 1];
+    double p = lead;
 #pragma unroll
     for (int i = N - 2; i >= 0; --i) p = fma_c(p, w, c[i]);
     return p;
 }
 
+template <int N>
+__device__ __forceinline__ double horner(const double (&c)[N], double w)
+{
+    return horner(c, w, c[N - 1]);
+}
+
+template <int N>
+__device__ __forceinline__ constexpr double leading(const double (&c)[N])
+{
+    return c[N - 1];
+}
+
 // 2^y for y in [-1022, 1023]: 2^round(y) times a polynomial in the remainder.
+template <int N>
+__device__ __forceinline__ double exp2_64(const double (&c)[N], double y, double lead)
+{
+    const double k = rint(y);
+    return ldexp(horner(c, y - k, lead), (int)k);
+}
+
 template <int N>
 __device__ __forceinline__ double exp2_64(const double (&c)[N], double y)
 {
-    const double k = rint(y);
-    return ldexp(horner(c, y - k), (int)k);
+    return exp2_64(c, y, c[N - 1]);
 }
 
 constexpr double kPi2 = 1.5707963267948966;
@@ -120,11 +140,12 @@ __device__ __forceinline__ double sie_a2(double u2, double ce, double bsie, doub
 // then gives t = 2^-(2048 e) ~ 0 and an overflowing radius a finite t, so every
 // exponent below stays finite; B (1 - t) >= -2000 keeps the last exponent in
 // int range (2^-2000 is 0 in FP64).
-__device__ __forceinline__ double sersic_r2(double r2, const LightK &L)
+// lead: the leading coefficient of kExp2_64 (see horner).
+__device__ __forceinline__ double sersic_r2(double r2, const LightK &L, double lead)
 {
     const float lg = __builtin_amdgcn_fmed3f(hw_log2((float)r2), -2048.0f, 128.0f);
-    const double t = exp2_64(kExp2_64, L.e * (double)lg);
-    return exp2_64(kExp2_64, fmax(fma(-L.B, t, L.B), -2000.0));
+    const double t = exp2_64(kExp2_64, L.e * (double)lg, lead);
+    return exp2_64(kExp2_64, fmax(fma(-L.B, t, L.B), -2000.0), lead);
 }
 
 // (R/R_e)^2 = P dx^2 + Q dy^2 + S dx dy at offset (dx, dy) from a light centre,
@@ -167,10 +188,10 @@ __device__ __forceinline__ float binned_pixel(const LensGeom &g, const PropBlock
     const int s = g.s;
     const double x0 = ((double)(x * s) - g.cfx) * g.sd;
     const double dx0 = x0 - P.xm;
-    // the step lives in a VGPR: as an SGPR pair it is spilled and reloaded
-    // (v_readlane) on every sub-pixel
-    double h = g.sd;
-    asm("" : "+v"(h));
+    // the step and the 2^x table's leading coefficient live in VGPRs: as SGPR
+    // pairs they are spilled or rematerialised on every sub-pixel
+    double h = g.sd, lead = leading(kExp2_64);
+    asm("" : "+v"(h), "+v"(lead));
     double al = 0.0, as = 0.0;
     for (int v = 0; v < s; ++v) {
         const double yy = ((double)(y * s + v) - g.cfy) * g.sd;
@@ -185,8 +206,8 @@ __device__ __forceinline__ float binned_pixel(const LensGeom &g, const PropBlock
         for (int u = 0; u < s; ++u) {
             double bx, by;
             ray_trace(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.g1p, dx, cx), fma(P.g2, dx, cy), P, bx, by);
-            al += sersic_r2(fma(fma(P.lens.P, dx, rs), dx, rq), P.lens);
-            as += sersic_r2(ellip_r2(bx, by, P.src), P.src);
+            al += sersic_r2(fma(fma(P.lens.P, dx, rs), dx, rq), P.lens, lead);
+            as += sersic_r2(ellip_r2(bx, by, P.src), P.src, lead);
             dx += h;
         }
     }
