@@ -69,11 +69,14 @@ def path_dtype(prec):
     return "f64+f32" if prec in (None, "fp32") else "f64+bf16"
 
 
-def credited_slots(spec, M):
+def credited_slots(spec, info):
     """Credited VALU work of one proposal (60 FMA-class + 10 transcendentals per sub-pixel
-    evaluation, one FMA per PSF tap at each masked pixel, one FP64 FMA per masked pixel)."""
-    E = dilated_count(spec.mask, (spec.k - 1) // 2) * spec.s * spec.s
-    return E * SLOTS_PER_EVAL + M * spec.k * spec.k + M, E
+    evaluation, one FMA per PSF tap at each masked pixel, one FP64 FMA per masked pixel).
+    The PSF is the kernel the library convolves with after its tail crop (info["psf_used"]),
+    and the sub-pixels are those of the mask dilated by that kernel (info["needed_pixels"])."""
+    M, k = info["masked_pixels"], info["psf_used"]
+    E = info["needed_pixels"] * spec.s * spec.s
+    return E * SLOTS_PER_EVAL + M * k * k + M, E
 
 
 def oracle_sample(specs_props, nthreads=0):
@@ -107,17 +110,6 @@ def measured_traffic(prec):
         return rec["traffic_bytes_per_launch"]
     except (OSError, ValueError, KeyError):
         return None
-
-
-def dilated_count(mask, r):
-    """Pixels of the mask dilated by a (2r+1)^2 box (the sub-pixel work the path needs)."""
-    ny, nx = mask.shape
-    m = np.pad(mask.astype(bool), r)
-    out = np.zeros((ny, nx), bool)
-    for dy in range(2 * r + 1):
-        for dx in range(2 * r + 1):
-            out |= m[dy:dy + ny, dx:dx + nx]
-    return int(out.sum())
 
 
 def main():
@@ -186,14 +178,15 @@ def main():
     assert np.array_equal(host_out, gpu_out)
 
     # roofline: credited algorithmic VALU work of one launch
-    M = info["masked_pixels"]
-    E = dilated_count(spec.mask, (spec.k - 1) // 2) * spec.s * spec.s
-    slots_per_prop = E * SLOTS_PER_EVAL + M * spec.k * spec.k + M
+    slots_per_prop, E = credited_slots(spec, info)
     achieved = slots_per_prop * n / (kern_ms * 1e-3)
+    kname = ("k_loglike_fp32<%d,%d>" % (info["psf_used"], info["threads"]) if prec == 0 else
+             "k_loglike_mfma<%d,%d>" % (prec, info["threads"]))
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOT_PER_S / 1e12,
                 "unit": "Tslot/s", "frac": achieved / PEAK_SLOT_PER_S, "traffic": measured_traffic(prec),
-                "kernel": "k_loglike_fp32<21> (+ k_prep)", "kernel_ms": kern_ms,
-                "slots_per_proposal": slots_per_prop, "subpixel_evals_per_proposal": E}
+                "kernel": kname + " (+ k_prep)", "kernel_ms": kern_ms,
+                "slots_per_proposal": slots_per_prop, "subpixel_evals_per_proposal": E,
+                "psf_used": info["psf_used"], "psf_given": info["psf_size"]}
 
     cpu = None
     max_err = None
@@ -262,7 +255,7 @@ def run_batch(args):
         gpu_data(ctx, sp)
         lid = ctx.load(sp, precision=prec)
         lids.append(lid)
-        sl, E = credited_slots(sp, ctx.info(lid)["masked_pixels"])
+        sl, E = credited_slots(sp, ctx.info(lid))
         slots += sl * sp.proposals.shape[0]
         evs += E * sp.proposals.shape[0]
     plist = [sp.proposals for sp in specs]
@@ -327,7 +320,7 @@ def run_precision(args):
         lids = [ctx.load(sp, precision=PREC[m]) for sp in specs]
         plist = [sp.proposals for sp in specs]
         n = int(sum(p.shape[0] for p in plist))
-        slots = sum(credited_slots(sp, ctx.info(l)["masked_pixels"])[0] * sp.proposals.shape[0]
+        slots = sum(credited_slots(sp, ctx.info(l))[0] * sp.proposals.shape[0]
                     for sp, l in zip(specs, lids))
         for _ in range(max(1, args.warmup)):
             outs = ctx.loglike_multi(lids, plist)

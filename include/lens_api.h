@@ -117,6 +117,11 @@ typedef struct lens_data_desc {
     const double *sigma;        /* ny*nx noise; > 0 and finite where mask = 1 */
     const uint8_t *mask;        /* ny*nx; nonzero = pixel enters the likelihood */
     int32_t precision;          /* LENS_PREC_* */
+    double psf_tail;            /* PSF tail crop: the kernel is cut to the smallest centred odd square
+                                   whose discarded taps' total |weight| is <= psf_tail * sum|K|, which
+                                   moves any convolved pixel by at most psf_tail * sum|K| * max|binned|.
+                                   0: the default 2^-48 (2^-24 below the FP32 resolution of the
+                                   brightest pixel); < 0: keep the full k x k kernel */
 } lens_data_desc;
 
 typedef struct lens_info {
@@ -129,7 +134,7 @@ typedef struct lens_info {
     int32_t threads;            /*   and workgroup size (fixed rule or autotuner) */
     int64_t lds_bytes;          /* dynamic LDS of one workgroup (the binned-row ring) */
     int32_t blocks_per_cu;      /* resident workgroups per compute unit at that shape */
-    int32_t reserved;           /* 0 */
+    int32_t psf_used;           /* side of the PSF kernel after the tail crop (psf_tail) */
 } lens_info;
 
 typedef struct lens_stats {
@@ -153,6 +158,15 @@ void lens_shutdown(lens_ctx *ctx);
 lens_status lens_load_data(lens_ctx *ctx, const lens_data_desc *desc, lens_id *out_id);
 /* Free a lens.  LENS_EBUSY while requests on it are queued or running. */
 lens_status lens_unload(lens_ctx *ctx, lens_id id);
+/* The PSF tail crop lens_load_data applies (Sec. 2.1 convolves the binned image
+ * with the PSF; taps that carry a negligible share of its weight are dropped):
+ * *k_used = the side of the smallest centred odd square of the k x k row-major
+ * kernel `psf` (host memory) whose outside taps' total |weight| is
+ * <= psf_tail * sum|K|.  psf_tail = 0 means 2^-48, psf_tail < 0 keeps k.  Host
+ * only (no device, no context).  LENS_EINVAL for null pointers, an even or
+ * non-positive k or a non-finite psf_tail. */
+lens_status lens_psf_crop(const double *psf, int32_t k, double psf_tail, int32_t *k_used);
+
 /* Describe a resident lens: its sizes, M, C and the tile shape its likelihood
  * kernel runs at (strip rows, threads, LDS bytes, resident workgroups per CU).
  * LENS_ENOENT for an unknown id. */

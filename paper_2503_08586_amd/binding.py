@@ -43,7 +43,7 @@ EXPORTED = [
     "lens_init", "lens_shutdown", "lens_load_data", "lens_unload", "lens_get_info",
     "lens_loglike_batch", "lens_loglike_batch_device", "lens_loglike_multi",
     "lens_submit", "lens_poll", "lens_wait", "lens_cancel", "lens_get_stats",
-    "lens_model_image", "lens_selftest", "lens_strerror", "lens_last_error",
+    "lens_model_image", "lens_selftest", "lens_psf_crop", "lens_strerror", "lens_last_error",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -76,6 +76,7 @@ class lens_data_desc(ctypes.Structure):
         ("sigma", ctypes.POINTER(ctypes.c_double)),
         ("mask", ctypes.POINTER(ctypes.c_uint8)),
         ("precision", ctypes.c_int32),
+        ("psf_tail", ctypes.c_double),
     ]
 
 
@@ -86,7 +87,7 @@ class lens_info(ctypes.Structure):
         ("masked_pixels", ctypes.c_int64), ("needed_pixels", ctypes.c_int64),
         ("device_bytes", ctypes.c_int64), ("norm", ctypes.c_double),
         ("strip_rows", ctypes.c_int32), ("threads", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
-        ("blocks_per_cu", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("blocks_per_cu", ctypes.c_int32), ("psf_used", ctypes.c_int32),
     ]
 
 
@@ -132,6 +133,7 @@ def load():
         "lens_get_stats": ([vp, ctypes.POINTER(lens_stats)], i32),
         "lens_model_image": ([vp, i64, dp, i32, dp], i32),
         "lens_selftest": ([vp, i32, dp], i32),
+        "lens_psf_crop": ([dp, i32, ctypes.c_double, ctypes.POINTER(i32)], i32),
         "lens_strerror": ([i32], ctypes.c_char_p),
         "lens_last_error": ([vp], ctypes.c_char_p),
     }
@@ -227,7 +229,7 @@ def lens_shutdown(ctx):
 
 
 def lens_load_data(ctx, ny, nx, pixel_scale, supersample, psf, data, sigma, mask,
-                   precision=LENS_PREC_FP32) -> int:
+                   precision=LENS_PREC_FP32, psf_tail=0.0) -> int:
     psf = np.ascontiguousarray(psf, dtype=np.float64)
     data = np.ascontiguousarray(data, dtype=np.float64)
     sigma = np.ascontiguousarray(sigma, dtype=np.float64)
@@ -240,9 +242,21 @@ def lens_load_data(ctx, ny, nx, pixel_scale, supersample, psf, data, sigma, mask
     d.psf, d.data, d.sigma = _dptr(psf), _dptr(data), _dptr(sigma)
     d.mask = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     d.precision = precision
+    d.psf_tail = psf_tail
     lid = ctypes.c_int64()
     _check(ctx, load().lens_load_data(ctx, ctypes.byref(d), ctypes.byref(lid)))
     return lid.value
+
+
+def lens_psf_crop(psf, psf_tail=0.0) -> int:
+    """Side of the PSF kernel lens_load_data convolves with after its tail crop (host only)."""
+    psf = np.ascontiguousarray(psf, dtype=np.float64)
+    k = psf.shape[0]
+    out = ctypes.c_int32()
+    st = load().lens_psf_crop(_dptr(psf), k, psf_tail, ctypes.byref(out))
+    if st != 0:
+        raise LensError(st, "lens_psf_crop")
+    return out.value
 
 
 def lens_unload(ctx, lens_id):
@@ -366,16 +380,16 @@ class LensContext:
     def __exit__(self, *a):
         self.close()
 
-    def load(self, spec, precision=LENS_PREC_FP32, data=None) -> int:
+    def load(self, spec, precision=LENS_PREC_FP32, data=None, psf_tail=0.0) -> int:
         """Load a synth.LensSpec (its data, or ``data`` if given)."""
         d = spec.data if data is None else data
         lid = lens_load_data(self.ctx, spec.ny, spec.nx, spec.dpix, spec.s, spec.psf, d, spec.sigma,
-                             spec.mask, precision)
+                             spec.mask, precision, psf_tail)
         self.geom[lid] = (spec.ny, spec.nx)
         return lid
 
-    def load_raw(self, ny, nx, dpix, s, psf, data, sigma, mask, precision=LENS_PREC_FP32) -> int:
-        lid = lens_load_data(self.ctx, ny, nx, dpix, s, psf, data, sigma, mask, precision)
+    def load_raw(self, ny, nx, dpix, s, psf, data, sigma, mask, precision=LENS_PREC_FP32, psf_tail=0.0) -> int:
+        lid = lens_load_data(self.ctx, ny, nx, dpix, s, psf, data, sigma, mask, precision, psf_tail)
         self.geom[lid] = (ny, nx)
         return lid
 

@@ -43,6 +43,7 @@ struct Lens {
     LensGeom g{};
     int precision = 0;
     int64_t masked = 0, needed = 0;
+    int psf_given = 0;      // PSF side as loaded (g.k is the side after the tail crop)
     void *slab = nullptr;   // one device allocation holding every array
     size_t bytes = 0;
     int users = 0;          // blocking calls in progress
@@ -660,23 +661,59 @@ lens_status tune_lens(lens_ctx *c, Lens *L)
 // ---------------------------------------------------------------------------
 // lens registry
 // ---------------------------------------------------------------------------
+extern "C" lens_status lens_psf_crop(const double *psf, int32_t k, double psf_tail, int32_t *k_used)
+{
+    if (!psf || !k_used || k < 1 || (k & 1) == 0 || !std::isfinite(psf_tail)) return LENS_EINVAL;
+    *k_used = k;
+    if (psf_tail < 0.0) return LENS_OK;
+    const double tol = psf_tail > 0.0 ? psf_tail : std::ldexp(1.0, -48);
+    const int rg = (k - 1) / 2;
+    double tot = 0.0;
+    for (int i = 0; i < k * k; ++i) tot += std::fabs(psf[i]);
+    for (int R = 0; R < rg; ++R) {
+        double out = 0.0;   // taps outside the centred (2R+1)^2 square, summed directly
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b)
+                if (std::abs(a - rg) > R || std::abs(b - rg) > R) out += std::fabs(psf[(size_t)a * k + b]);
+        if (out <= tol * tot) {
+            *k_used = 2 * R + 1;
+            break;
+        }
+    }
+    return LENS_OK;
+}
+
 extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens_id *out_id)
 {
     lens_status st = check_ctx(c);
     if (st != LENS_OK) return st;
     if (!d || !out_id) return fail(c, LENS_EINVAL, "null descriptor or output");
     DeviceGuard dg(c->device);   // the tile choice queries the device's occupancy
-    const int ny = d->ny, nx = d->nx, s = d->supersample, k = d->psf_size;
+    const int ny = d->ny, nx = d->nx, s = d->supersample, k_given = d->psf_size;
     if (ny < 1 || nx < 1 || ny > 4096 || nx > 4096) return fail(c, LENS_EINVAL, "ny, nx must be in 1..4096");
     if (!(d->pixel_scale > 0.0) || !std::isfinite(d->pixel_scale)) return fail(c, LENS_EINVAL, "pixel_scale must be > 0");
     if (s < 1 || s > 8) return fail(c, LENS_EINVAL, "supersample must be in 1..8");
-    if (k < 1 || k > lensk::kMaxK || (k & 1) == 0) return fail(c, LENS_EINVAL, "psf_size must be odd, 1..63");
+    if (k_given < 1 || k_given > lensk::kMaxK || (k_given & 1) == 0)
+        return fail(c, LENS_EINVAL, "psf_size must be odd, 1..63");
+    if (!std::isfinite(d->psf_tail)) return fail(c, LENS_EINVAL, "psf_tail must be finite");
     if (!d->psf || !d->data || !d->sigma || !d->mask) return fail(c, LENS_EINVAL, "null array in descriptor");
     if (d->precision < LENS_PREC_FP32 || d->precision > LENS_PREC_BF16_SPLIT3)
         return fail(c, LENS_EINVAL, "unknown precision mode");
     const int64_t npix = (int64_t)ny * nx;
-    for (int i = 0; i < k * k; ++i)
+    for (int i = 0; i < k_given * k_given; ++i)
         if (!std::isfinite(d->psf[i])) return fail(c, LENS_EINVAL, "non-finite PSF value");
+    // PSF tail crop (lens_psf_crop)
+    int k = k_given;
+    (void)lens_psf_crop(d->psf, k_given, d->psf_tail, &k);
+    std::vector<double> psf_c;
+    const double *psf = d->psf;
+    if (k < k_given) {
+        const int off = (k_given - k) / 2;
+        psf_c.resize((size_t)k * k);
+        for (int a = 0; a < k; ++a)
+            for (int b = 0; b < k; ++b) psf_c[(size_t)a * k + b] = d->psf[(size_t)(a + off) * k_given + (b + off)];
+        psf = psf_c.data();
+    }
     int64_t masked = 0;
     double norm = 0.0;
     for (int64_t i = 0; i < npix; ++i) {
@@ -748,7 +785,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
             for (int lane = 0; lane < 64; ++lane)
                 for (int e = 0; e < 8; ++e) {
                     const int K = 32 * ch + 8 * (lane >> 4) + e, a = K / g.L, i = K % g.L, b = i - (lane & 15);
-                    const float v = (a < k && b >= 0 && b < k) ? (float)d->psf[(size_t)(k - 1 - a) * k + (k - 1 - b)] : 0.0f;
+                    const float v = (a < k && b >= 0 && b < k) ? (float)psf[(size_t)(k - 1 - a) * k + (k - 1 - b)] : 0.0f;
                     uint16_t pl[3];
                     split_bf16(v, npl, pl);
                     for (int q = 0; q < npl; ++q) aop[(((size_t)ch * npl + q) * 64 + lane) * 8 + e] = pl[q];
@@ -769,7 +806,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
             hw[(size_t)y * pitch + x] = (float)(1.0 / d->sigma[i]);
         }
     for (int a = 0; a < k; ++a)
-        for (int b = 0; b < k; ++b) hk[(size_t)a * k + b] = (float)d->psf[(size_t)(k - 1 - a) * k + (k - 1 - b)];
+        for (int b = 0; b < k; ++b) hk[(size_t)a * k + b] = (float)psf[(size_t)(k - 1 - a) * k + (k - 1 - b)];
     // one slab
     size_t off = 0;
     auto place = [&](size_t bytes) {
@@ -828,6 +865,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     Lens *L = new Lens();
     L->g = g;
     L->precision = d->precision;
+    L->psf_given = k_given;
     L->masked = masked;
     L->needed = (int64_t)evl.size();
     L->slab = slab;
@@ -893,7 +931,7 @@ extern "C" lens_status lens_get_info(lens_ctx *c, lens_id id, lens_info *out)
     out->ny = L->g.ny;
     out->nx = L->g.nx;
     out->supersample = L->g.s;
-    out->psf_size = L->g.k;
+    out->psf_size = L->psf_given;
     out->precision = L->precision;
     out->masked_pixels = L->masked;
     out->needed_pixels = L->needed;
@@ -902,7 +940,7 @@ extern "C" lens_status lens_get_info(lens_ctx *c, lens_id id, lens_info *out)
     out->strip_rows = L->g.strip_h;
     out->threads = L->g.nt;
     out->lds_bytes = (int64_t)lensk::ring_bytes(L->g);
-    out->reserved = 0;
+    out->psf_used = L->g.k;
     {
         DeviceGuard dg(c->device);
         out->blocks_per_cu = lensk::loglike_blocks_per_cu(L->g);

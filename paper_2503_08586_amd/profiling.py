@@ -21,8 +21,11 @@ import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 RECORD = os.path.join(ROOT, "profiles", "traffic_plain_128px_s4_k21.txt")
+# everything that decides what the launch does: the kernels, and the runtime
+# that picks the PSF crop and the tile shape
 KERNEL_SOURCES = ["paper_2503_08586_amd/csrc/lens_kernels.hip", "paper_2503_08586_amd/csrc/lens_device.h",
-                  "paper_2503_08586_amd/csrc/lens_approx.h", "paper_2503_08586_amd/csrc/lens_internal.h"]
+                  "paper_2503_08586_amd/csrc/lens_approx.h", "paper_2503_08586_amd/csrc/lens_internal.h",
+                  "paper_2503_08586_amd/csrc/lens_runtime.cpp"]
 
 
 def kernel_hash():
@@ -34,27 +37,30 @@ def kernel_hash():
 
 
 def read_counter(d, counter, name_part):
-    """Mean per-dispatch value of `counter` over dispatches whose kernel name contains name_part."""
+    """Mean per-dispatch value of `counter` over dispatches whose kernel name contains
+    name_part, and the (last) full kernel name matched."""
     files = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
-    vals = []
+    vals, name = [], ""
     for f in files:
         for row in csv.DictReader(open(f)):
             if row.get("Counter_Name") == counter and name_part in row.get("Kernel_Name", ""):
                 vals.append(float(row["Counter_Value"]))
+                name = row["Kernel_Name"]
     if not vals:
         raise SystemExit("no %s rows for %s in %s" % (counter, name_part, d))
-    return sum(vals) / len(vals), len(vals)
+    return sum(vals) / len(vals), len(vals), name
 
 
 def main():
     cf, cw, pf, pw = sys.argv[1:5]
-    copy_f, _ = read_counter(cf, "FETCH_SIZE", "")
-    copy_w, _ = read_counter(cw, "WRITE_SIZE", "")
+    copy_f, _, _ = read_counter(cf, "FETCH_SIZE", "")
+    copy_w, _, _ = read_counter(cw, "WRITE_SIZE", "")
     # a 1 GiB copy reads and writes 1 GiB (2^20 KiB)
     sf, sw = 2.0 ** 20 / copy_f, 2.0 ** 20 / copy_w
-    kf, nf = read_counter(pf, "FETCH_SIZE", "k_loglike_fp32")
-    kw, nw = read_counter(pw, "WRITE_SIZE", "k_loglike_fp32")
-    rec = {"kernel": "k_loglike_fp32<21,256>", "workload": "plain 128x128 s=4 k=21, 65,536 proposals/launch",
+    kf, nf, kname = read_counter(pf, "FETCH_SIZE", "k_loglike_fp32")
+    kw, nw, _ = read_counter(pw, "WRITE_SIZE", "k_loglike_fp32")
+    rec = {"kernel": kname.split("(")[0].replace("void lensk::", ""),
+           "workload": "plain 128x128 s=4, 21x21 PSF as given, 65,536 proposals/launch",
            "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw, "dispatches": [nf, nw],
            "copy_fetch_kib": copy_f, "copy_write_kib": copy_w, "scale_fetch": sf, "scale_write": sw,
            "traffic_bytes_per_launch": (kf * sf + kw * sw) * 1024.0, "kernel_src_sha256": kernel_hash(),

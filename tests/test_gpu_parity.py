@@ -255,6 +255,32 @@ def test_sersic_index_sweep(ctx):
     ctx.unload(lid)
 
 
+def test_psf_tail_crop(ctx):
+    """The survey PSF (21x21 Gaussian, FWHM 2 px) is convolved at its 2^-48 tail
+    crop (13x13); with psf_tail < 0 the full kernel is used.  Both match the
+    oracle, which always convolves with the full kernel, and each other to far
+    below the gate."""
+    say("case: PSF tail crop, default and full kernel")
+    spec = synth.config2(nprop=64)[0]
+    spec.s = 2
+    oracle_data(spec)
+    lc = ctx.load(spec)
+    lf = ctx.load(spec, psf_tail=-1.0)
+    ic, i_f = ctx.info(lc), ctx.info(lf)
+    assert (ic["psf_size"], ic["psf_used"]) == (21, 13)
+    assert (i_f["psf_size"], i_f["psf_used"]) == (21, 21)
+    assert ic["needed_pixels"] < i_f["needed_pixels"]
+    gc, gf = ctx.loglike(lc, spec.proposals), ctx.loglike(lf, spec.proposals)
+    _check(spec, gc, spec.proposals, label="psf cropped")
+    _check(spec, gf, spec.proposals, label="psf full")
+    ref, chi2, C = oracle_loglike(spec, spec.proposals)
+    d = rel_err(gc, gf, chi2, C)
+    say("cropped vs full kernel: max %.3e" % d.max())
+    assert d.max() <= 1e-7
+    ctx.unload(lc)
+    ctx.unload(lf)
+
+
 def test_batch_composition_bitwise(ctx):
     say("case: batch composition and order")
     spec = synth.config2(nprop=3000)[0]
