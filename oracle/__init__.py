@@ -75,6 +75,7 @@ class Oracle:
             "oracle_model_image": ([i, i, d, i, i, _dp, _dp, i, _dp], i),
             "oracle_loglike_norm": ([i64, _dp, _u8p], d),
             "oracle_loglike": ([i, i, d, i, i, _dp, _dp, _dp, _u8p, _dp, i64, _dp, _dp, i], i),
+            "oracle_loglike_nnls": ([i, i, d, i, i, _dp, _dp, _dp, _u8p, _dp, i64, _dp, _dp, _dp, i], i),
             "oracle_num_threads": ([], i),
         }
         for name, (args, res) in sig.items():
@@ -184,6 +185,35 @@ class Oracle:
         if rc != 0:
             raise ValueError("bad argument to oracle_loglike")
         return (out, chi2) if return_chi2 else out
+
+    def loglike_nnls(self, geom, psf, data, sigma, mask, params, nthreads=0, return_chi2=False,
+                     return_amps=False):
+        """lnL with the two light amplitudes solved by non-negative least squares
+        (Sec. 2.3); the amplitude slots of ``params`` are ignored.  Returns lnL,
+        plus chi2 and/or the amplitudes [n, 2] (s_l, s_s) when asked."""
+        ny, nx, dpix, s = geom
+        psf = _f64(psf)
+        k = psf.shape[0]
+        data = _f64(data)
+        sigma = _f64(sigma)
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        assert data.shape == (ny, nx) and sigma.shape == (ny, nx) and mask.shape == (ny, nx)
+        p = _f64(params).reshape(-1, NPARAM_STRIDE)
+        n = p.shape[0]
+        out = np.empty(n, dtype=np.float64)
+        chi2 = np.empty(n, dtype=np.float64)
+        amps = np.empty((n, 2), dtype=np.float64)
+        rc = self.lib.oracle_loglike_nnls(ny, nx, float(dpix), s, k, _ptr(psf), _ptr(data), _ptr(sigma),
+                                          _ptr(mask, _u8p), _ptr(p), n, _ptr(out), _ptr(chi2), _ptr(amps),
+                                          int(nthreads))
+        if rc != 0:
+            raise ValueError("bad argument to oracle_loglike_nnls")
+        res = (out,)
+        if return_chi2:
+            res += (chi2,)
+        if return_amps:
+            res += (amps,)
+        return res if len(res) > 1 else out
 
     def num_threads(self) -> int:
         return self.lib.oracle_num_threads()

@@ -17,6 +17,7 @@
  *   - elliptical Sersic light                                   (Sec. 2.4, Eqs. 8-10)
  *   - SIE mass = elliptical power law at slope 2                (Sec. 2.4, Eq. 12 and text)
  *   - external shear                                            (Sec. 2.4, Eqs. 13-14)
+ *   - light amplitudes by non-negative least squares            (Sec. 2.3)
  *
  * Everything is FP64, scalar loops, libm only, on the full supersampled grid
  * (no skipping outside the mask), with a full-image direct convolution.
@@ -344,6 +345,124 @@ int oracle_loglike(int ny, int nx, double dpix, int s, int k, const double *psf,
             if (out_chi2) out_chi2[t] = chi2;
         }
         free(m);
+    }
+    return bad ? -1 : 0;
+}
+
+/* lnL with the light amplitudes solved linearly (Sec. 2.3): the unit-amplitude
+ * lens-light and source images, each binned and PSF-convolved, are the columns
+ * a and b of M; the amplitudes (s_l, s_s) minimise chi^2 = sum_mask ((d - M s)/sigma)^2
+ * subject to s >= 0 (non-negative least squares).  With two columns the
+ * minimiser is found by plain enumeration: for every support S of {l, s}
+ * (both, l only, s only, none) take the unconstrained least-squares solution on
+ * S (normal equations on S, zero elsewhere); keep it if it is >= 0; the
+ * feasible candidate with the smallest chi^2 -- computed by a direct pass over
+ * the residuals -- is the NNLS solution (the optimum is the least-squares
+ * solution on its own support).  A support whose normal matrix is singular
+ * (a column that vanishes on the mask) is skipped; dropping that column gives
+ * the same chi^2.  The proposal's amplitude slots 7 and 12 are ignored.
+ * out_chi2 and out_amp ([n][2]: s_l, s_s) may be NULL; proposals outside the
+ * domain give lnL = -inf, chi2 = +inf, amplitudes NaN.  Returns 0 or -1 on a
+ * bad argument. */
+int oracle_loglike_nnls(int ny, int nx, double dpix, int s, int k, const double *psf,
+                        const double *data, const double *sigma, const uint8_t *mask,
+                        const double *params, int64_t n, double *out, double *out_chi2,
+                        double *out_amp, int nthreads)
+{
+    if (!orc_geom_ok(ny, nx, dpix, s, k) || !psf || !data || !sigma || !mask ||
+        (n > 0 && (!params || !out)) || n < 0)
+        return -1;
+    int64_t npix = (int64_t)ny * nx;
+    for (int64_t i = 0; i < npix; ++i)
+        if (mask[i] && !(sigma[i] > 0.0 && isfinite(sigma[i]) && isfinite(data[i]))) return -1;
+    double C = oracle_loglike_norm(npix, sigma, mask);
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads) reduction(| : bad)
+#endif
+    {
+        double *a = (double *)malloc(sizeof(double) * (size_t)npix);
+        double *b = (double *)malloc(sizeof(double) * (size_t)npix);
+        if (!a || !b) bad = 1;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int64_t t = 0; t < n; ++t) {
+            if (!a || !b) continue;
+            double p[ORC_NP];
+            memcpy(p, params + t * ORC_NP, sizeof(p));
+            p[7] = 1.0;
+            p[12] = 0.0;
+            int ok = oracle_params_valid(p);
+            if (ok) {
+                oracle_model_image(ny, nx, dpix, s, k, psf, p, 1, a);   /* lens light, unit amplitude */
+                p[7] = 0.0;
+                p[12] = 1.0;
+                oracle_model_image(ny, nx, dpix, s, k, psf, p, 1, b);   /* source, unit amplitude */
+            }
+            if (!ok) {
+                out[t] = -INFINITY;
+                if (out_chi2) out_chi2[t] = INFINITY;
+                if (out_amp) out_amp[2 * t] = out_amp[2 * t + 1] = NAN;
+                continue;
+            }
+            /* normal equations F s = g of the weighted problem */
+            double F11 = 0.0, F12 = 0.0, F22 = 0.0, g1 = 0.0, g2 = 0.0;
+            for (int64_t i = 0; i < npix; ++i)
+                if (mask[i]) {
+                    double w = 1.0 / (sigma[i] * sigma[i]);
+                    F11 += w * a[i] * a[i];
+                    F12 += w * a[i] * b[i];
+                    F22 += w * b[i] * b[i];
+                    g1 += w * a[i] * data[i];
+                    g2 += w * b[i] * data[i];
+                }
+            double cand[4][2];
+            int nc = 0;
+            double det = F11 * F22 - F12 * F12;
+            if (det > 0.0) {
+                cand[nc][0] = (g1 * F22 - g2 * F12) / det;
+                cand[nc][1] = (g2 * F11 - g1 * F12) / det;
+                ++nc;
+            }
+            if (F11 > 0.0) {
+                cand[nc][0] = g1 / F11;
+                cand[nc][1] = 0.0;
+                ++nc;
+            }
+            if (F22 > 0.0) {
+                cand[nc][0] = 0.0;
+                cand[nc][1] = g2 / F22;
+                ++nc;
+            }
+            cand[nc][0] = 0.0;
+            cand[nc][1] = 0.0;
+            ++nc;
+            double best = INFINITY, bl = 0.0, bs = 0.0;
+            for (int c = 0; c < nc; ++c) {
+                if (!(cand[c][0] >= 0.0 && cand[c][1] >= 0.0)) continue;
+                double chi2 = 0.0;
+                for (int64_t i = 0; i < npix; ++i)
+                    if (mask[i]) {
+                        double r = (data[i] - cand[c][0] * a[i] - cand[c][1] * b[i]) / sigma[i];
+                        chi2 += r * r;
+                    }
+                if (chi2 < best) {
+                    best = chi2;
+                    bl = cand[c][0];
+                    bs = cand[c][1];
+                }
+            }
+            out[t] = C - 0.5 * best;
+            if (out_chi2) out_chi2[t] = best;
+            if (out_amp) {
+                out_amp[2 * t] = bl;
+                out_amp[2 * t + 1] = bs;
+            }
+        }
+        free(a);
+        free(b);
     }
     return bad ? -1 : 0;
 }

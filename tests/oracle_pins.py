@@ -15,6 +15,7 @@ import math
 
 import numpy as np
 import scipy.integrate
+import scipy.optimize
 import scipy.signal
 import scipy.special
 import scipy.stats
@@ -460,6 +461,104 @@ def pin_loglike_batch_independence(orc):
     assert np.array_equal(a[perm], b)
     c = orc.loglike(g, psf, data, sigma, mask, props[4:5])
     assert c[0] == a[4]
+
+
+# ----------------------------------------------------------------------------
+# Linear amplitudes by non-negative least squares (Sec. 2.3)
+# ----------------------------------------------------------------------------
+def _columns(orc, g, psf, p):
+    """Unit-amplitude lens-light and source images (the columns of M), binned and convolved."""
+    a = orc.model_image(g[0], g[1], g[2], g[3], psf, _with(p, I_l=1.0, I_s=0.0), stage=1)
+    b = orc.model_image(g[0], g[1], g[2], g[3], psf, _with(p, I_l=0.0, I_s=1.0), stage=1)
+    return a, b
+
+
+def _with(p, **kw):
+    q = p.copy()
+    for name, val in kw.items():
+        q[synth.SLOT[name]] = val
+    return q
+
+
+def pin_nnls_recovers_amplitudes(orc):
+    # noise-free data made with positive amplitudes: the solve returns them and chi^2 vanishes
+    rng, psf, sigma, mask, truth, g = _small_case(seed=21)
+    data = orc.model_image(g[0], g[1], g[2], g[3], psf, _with(truth, I_l=0.37, I_s=0.21), stage=1)
+    lnl, chi2, amps = orc.loglike_nnls(g, psf, data, sigma, mask, _with(truth, I_l=9.0, I_s=-3.0)[None],
+                                      return_chi2=True, return_amps=True)
+    assert np.allclose(amps[0], [0.37, 0.21], rtol=1e-9, atol=0), amps
+    assert chi2[0] < 1e-12 * np.sum((data / sigma)[mask == 1] ** 2)
+
+
+def pin_nnls_scipy(orc):
+    # the weighted problem min ||(M s - d)/sigma||, s >= 0, solved by scipy's Lawson-Hanson NNLS
+    rng, psf, sigma, mask, truth, g = _small_case(seed=22)
+    sel = mask == 1
+    props = [truth, _p(theta_E=1.0, n_s=0.8), _p(q_m=0.5, x_s=0.4), _p(R_l=0.3, n_l=4.0)]
+    model = orc.model_image(g[0], g[1], g[2], g[3], psf, truth, stage=1)
+    # data with a negative source component: NNLS must clip it on some proposals
+    a0, b0 = _columns(orc, g, psf, truth)
+    for data in (model + rng.normal(size=model.shape) * sigma, 0.3 * a0 - 0.25 * b0 + rng.normal(size=a0.shape) * sigma):
+        lnl, chi2, amps = orc.loglike_nnls(g, psf, data, sigma, mask, np.stack(props), return_chi2=True,
+                                          return_amps=True)
+        for t, p in enumerate(props):
+            a, b = _columns(orc, g, psf, p)
+            A = np.stack([a[sel] / sigma[sel], b[sel] / sigma[sel]], axis=1)
+            x, rnorm = scipy.optimize.nnls(A, data[sel] / sigma[sel])
+            assert np.allclose(amps[t], x, rtol=1e-8, atol=1e-12 * max(1.0, np.abs(x).max())), (t, amps[t], x)
+            assert abs(chi2[t] - rnorm ** 2) <= 1e-9 * rnorm ** 2, (chi2[t], rnorm ** 2)
+    # the second data set has a negative source: the proposal equal to the truth drops it
+    assert amps[0][1] == 0.0 and amps[0][0] > 0
+    # a negative lens light sized so that the lens-only fit is feasible but the
+    # source-only fit is better: with d = -c a + 0.3 b and c = 0.15 F12 / F11,
+    # chi2(source only) / chi2(lens only) = rho^2 / 4, rho^2 = F12^2 / (F11 F22)
+    w = 1.0 / sigma[sel] ** 2
+    F11, F12 = np.sum(w * a0[sel] ** 2), np.sum(w * a0[sel] * b0[sel])
+    assert F12 > 0
+    data = -0.15 * F12 / F11 * a0 + 0.3 * b0
+    amps = orc.loglike_nnls(g, psf, data, sigma, mask, truth[None], return_amps=True)[1]
+    A = np.stack([a0[sel] / sigma[sel], b0[sel] / sigma[sel]], axis=1)
+    x, rnorm = scipy.optimize.nnls(A, data[sel] / sigma[sel])
+    assert amps[0][0] == 0.0 and amps[0][1] > 0 and np.allclose(amps[0], x, rtol=1e-9), (amps, x)
+
+
+def pin_nnls_kkt_and_maximum(orc):
+    # KKT: F s - g = 0 on the support and >= 0 off it; and no non-negative amplitude pair does better
+    rng, psf, sigma, mask, truth, g = _small_case(seed=23)
+    sel = mask == 1
+    data = orc.model_image(g[0], g[1], g[2], g[3], psf, truth, stage=1) + rng.normal(size=sigma.shape) * sigma
+    props = synth.draw_params(rng, 4)
+    lnl, amps = orc.loglike_nnls(g, psf, data, sigma, mask, props, return_amps=True)
+    for t, p in enumerate(props):
+        a, b = _columns(orc, g, psf, p)
+        w = 1.0 / sigma[sel] ** 2
+        F = np.array([[np.sum(w * a[sel] * a[sel]), np.sum(w * a[sel] * b[sel])],
+                      [np.sum(w * a[sel] * b[sel]), np.sum(w * b[sel] * b[sel])]])
+        gv = np.array([np.sum(w * a[sel] * data[sel]), np.sum(w * b[sel] * data[sel])])
+        grad = F @ amps[t] - gv
+        scale = np.abs(gv).max()
+        for j in range(2):
+            if amps[t][j] > 0:
+                assert abs(grad[j]) <= 1e-9 * scale, (t, j, grad)
+            else:
+                assert amps[t][j] == 0.0 and grad[j] >= -1e-9 * scale, (t, j, grad)
+        trial = np.abs(rng.normal(size=(16, 2))) * np.maximum(amps[t], 0.05)
+        for ta in trial:
+            lt = orc.loglike(g, psf, data, sigma, mask, _with(p, I_l=ta[0], I_s=ta[1])[None])[0]
+            assert lt <= lnl[t] + 1e-12 * abs(lnl[t])
+        # lnL at the solved amplitudes equals the explicit-amplitude likelihood there
+        le = orc.loglike(g, psf, data, sigma, mask, _with(p, I_l=amps[t][0], I_s=amps[t][1])[None])[0]
+        assert abs(le - lnl[t]) <= 1e-10 * abs(lnl[t])
+
+
+def pin_nnls_domain(orc):
+    rng, psf, sigma, mask, truth, g = _small_case(seed=24)
+    data = orc.model_image(g[0], g[1], g[2], g[3], psf, truth, stage=1)
+    # amplitude slots are ignored (even non-finite); the other slots keep their domain
+    ok = orc.loglike_nnls(g, psf, data, sigma, mask, np.stack([_p(I_l=float("nan"), I_s=-5.0)]))
+    assert np.isfinite(ok[0])
+    out, amps = orc.loglike_nnls(g, psf, data, sigma, mask, np.stack([_p(q_m=0.0), _p(n_s=30.0)]), return_amps=True)
+    assert np.all(out == -np.inf) and np.all(np.isnan(amps))
 
 
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

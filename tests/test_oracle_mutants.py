@@ -38,6 +38,12 @@ MUTANTS = {
     "lens_light_off_mass_centre": [("p[10], p[11], p[3], p[4], x, y)", "p[10], p[11], p[17], p[18], x, y)")],
     "scene_xy_transposed": [("p[10], p[11], p[3], p[4], x, y)", "p[10], p[11], p[3], p[4], y, x)"),
                             ("p[17], p[18], bx, by)", "p[17], p[18], by, bx)")],
+    "nnls_no_positivity": [("if (!(cand[c][0] >= 0.0 && cand[c][1] >= 0.0)) continue;", "if (0) continue;")],
+    "nnls_weight_one_sigma": [("double w = 1.0 / (sigma[i] * sigma[i]);", "double w = 1.0 / sigma[i];")],
+    "nnls_cramer_sign": [("cand[nc][0] = (g1 * F22 - g2 * F12) / det;", "cand[nc][0] = (g1 * F22 + g2 * F12) / det;")],
+    "nnls_first_feasible": [("if (chi2 < best) {", "if (best == INFINITY) {")],
+    "nnls_amps_swapped": [("out_amp[2 * t] = bl;", "out_amp[2 * t] = bs;"),
+                          ("out_amp[2 * t + 1] = bs;", "out_amp[2 * t + 1] = bl;")],
     "lens_light_not_supersampled": [("acc += orc_scene(p, bl, bs, x, y);",
                                      "acc += orc_scene(p, bl, bs, x, y) - oracle_sersic(p[7], p[8], p[9], bl, p[10], p[11], p[3], p[4], x, y) + oracle_sersic(p[7], p[8], p[9], bl, p[10], p[11], p[3], p[4], ((double)j - 0.5 * (nx - 1)) * dpix, ((double)i - 0.5 * (ny - 1)) * dpix);")],
 }
