@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--workload", default="plain", choices=["plain", "batch", "precision", "serving"])
     ap.add_argument("--precision", default=None, choices=["fp32", "split", "bf16", "split3"])
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--amplitudes", default="explicit", choices=["explicit", "nnls"],
+                    help="light amplitudes as parameters, or solved by NNLS (Sec. 2.3; FP32 convolution)")
     ap.add_argument("--requests", type=int, default=300, help="serving: requests per offered load")
     return ap.parse_args()
 
@@ -69,25 +71,29 @@ def path_dtype(prec):
     return "f64+f32" if prec in (None, "fp32") else "f64+bf16"
 
 
-def credited_slots(spec, info):
+def credited_slots(spec, info, nnls=False):
     """Credited VALU work of one proposal (60 FMA-class + 10 transcendentals per sub-pixel
     evaluation, one FMA per PSF tap at each masked pixel, one FP64 FMA per masked pixel).
     The PSF is the kernel the library convolves with after its tail crop (info["psf_used"]),
-    and the sub-pixels are those of the mask dilated by that kernel (info["needed_pixels"])."""
+    and the sub-pixels are those of the mask dilated by that kernel (info["needed_pixels"]).
+    Solved amplitudes (nnls) convolve two channels and take five FP64 moments per masked pixel."""
     M, k = info["masked_pixels"], info["psf_used"]
     E = info["needed_pixels"] * spec.s * spec.s
+    if nnls:
+        return E * SLOTS_PER_EVAL + 2 * M * k * k + 5 * M, E
     return E * SLOTS_PER_EVAL + M * k * k + M, E
 
 
-def oracle_sample(specs_props, nthreads=0):
+def oracle_sample(specs_props, nthreads=0, nnls=False):
     """Times the oracle over (spec, proposals) pairs; returns (lnL list, chi2 list, C list, seconds)."""
     import oracle
     orc = oracle.default()
+    fn = orc.loglike_nnls if nnls else orc.loglike
     out = []
     t0 = time.perf_counter()
     for spec, P in specs_props:
-        ref, chi2 = orc.loglike(spec.geom, spec.psf, spec.data, spec.sigma, spec.mask, P, nthreads=nthreads,
-                                return_chi2=True)
+        ref, chi2 = fn(spec.geom, spec.psf, spec.data, spec.sigma, spec.mask, P, nthreads=nthreads,
+                       return_chi2=True)
         out.append((ref, chi2, orc.loglike_norm(spec.sigma, spec.mask)))
     return out, time.perf_counter() - t0, orc.num_threads()
 
@@ -144,7 +150,8 @@ def main():
     ctx = binding.LensContext(0, autotune=args.autotune)
     gpu_data(ctx, spec)
     prec = PREC[args.precision or "fp32"]
-    lid = ctx.load(spec, precision=prec)
+    nnls = args.amplitudes == "nnls"
+    lid = ctx.load(spec, precision=prec, amplitudes=1 if nnls else 0)
     info = ctx.info(lid)
 
     dev = torch.device("cuda", 0)
@@ -178,9 +185,10 @@ def main():
     assert np.array_equal(host_out, gpu_out)
 
     # roofline: credited algorithmic VALU work of one launch
-    slots_per_prop, E = credited_slots(spec, info)
+    slots_per_prop, E = credited_slots(spec, info, nnls)
     achieved = slots_per_prop * n / (kern_ms * 1e-3)
-    kname = ("k_loglike_fp32<%d,%d>" % (info["psf_used"], info["threads"]) if prec == 0 else
+    kname = ("k_loglike_nnls<%d>" % info["threads"] if nnls else
+             "k_loglike_fp32<%d,%d>" % (info["psf_used"], info["threads"]) if prec == 0 else
              "k_loglike_mfma<%d,%d>" % (prec, info["threads"]))
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOT_PER_S / 1e12,
                 "unit": "Tslot/s", "frac": achieved / PEAK_SLOT_PER_S, "traffic": measured_traffic(prec),
@@ -196,13 +204,14 @@ def main():
         threads = orc.num_threads()
         # calibrate on a few proposals, then size the sample for ~cpu_seconds
         probe = spec.proposals[:threads]
+        ofn = orc.loglike_nnls if nnls else orc.loglike
         tc0 = time.perf_counter()
-        orc.loglike(spec.geom, spec.psf, spec.data, spec.sigma, spec.mask, probe)
+        ofn(spec.geom, spec.psf, spec.data, spec.sigma, spec.mask, probe)
         per = (time.perf_counter() - tc0) / len(probe)
         ns = int(max(threads, min(n, round(args.cpu_seconds / max(per, 1e-9)))))
         sample = spec.proposals[:ns]
         tc0 = time.perf_counter()
-        ref, chi2 = orc.loglike(spec.geom, spec.psf, spec.data, spec.sigma, spec.mask, sample, return_chi2=True)
+        ref, chi2 = ofn(spec.geom, spec.psf, spec.data, spec.sigma, spec.mask, sample, return_chi2=True)
         tc = time.perf_counter() - tc0
         C = orc.loglike_norm(spec.sigma, spec.mask)
         err = np.abs(gpu_out[:ns] - ref) / (0.5 * chi2 + abs(C))
@@ -225,7 +234,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "plain survey scale: 1 lens, 128x128 px at 0.05\"/px, 4x4 supersampling, "
                                "21x21 Gaussian PSF FWHM 0.1\", r=3\" mask, %d proposals per call, "
-                               "FP64 ray trace, %s PSF convolution, FP64 chi2" % (n, args.precision or "fp32"),
+                               "FP64 ray trace, %s PSF convolution, FP64 chi2, %s amplitudes"
+                               % (n, args.precision or "fp32", "NNLS-solved" if nnls else "explicit"),
                    "path": "lens_loglike_batch_device", "proposals_per_call": n,
                    "subpixel_evals_per_s": value * E},
         "roofline": roofline,
@@ -248,14 +258,15 @@ def run_batch(args):
 
     from paper_2503_08586_amd import binding, synth
     prec = PREC[args.precision or "fp32"]
+    nnls = args.amplitudes == "nnls"
     specs = synth.config3()
     ctx, st = _stream_ctx(binding, torch, autotune=args.autotune)
     lids, slots, evs = [], 0.0, 0
     for sp in specs:
         gpu_data(ctx, sp)
-        lid = ctx.load(sp, precision=prec)
+        lid = ctx.load(sp, precision=prec, amplitudes=1 if nnls else 0)
         lids.append(lid)
-        sl, E = credited_slots(sp, ctx.info(lid))
+        sl, E = credited_slots(sp, ctx.info(lid), nnls)
         slots += sl * sp.proposals.shape[0]
         evs += E * sp.proposals.shape[0]
     plist = [sp.proposals for sp in specs]
@@ -279,7 +290,7 @@ def run_batch(args):
     plain_s = time.perf_counter() - t0
     same = all(np.array_equal(a, b) for a, b in zip(outs, singles))
     sample = [(specs[j], specs[j].proposals[:2]) for j in range(0, len(specs), 8)]
-    res, tc, threads = oracle_sample(sample)
+    res, tc, threads = oracle_sample(sample, nnls=nnls)
     errs = [rel_errors(outs[j][:2], r[0], r[1], r[2]).max() for (j, r) in zip(range(0, len(specs), 8), res)]
     rec = {
         "metric": METRIC, "value": n / step_s, "unit": "loglike evals/s", "n_gpus": 1,
@@ -287,7 +298,8 @@ def run_batch(args):
         "scaling": "weak", "vs_baseline": None, "dtype": path_dtype(args.precision), "data": "synthetic",
         "config": {"workload": "batching: 256 lenses, N~U{48..160}, 0.05-0.074\"/px, s in {2,4}, k in 11..31, "
                                "%d proposals (U{128..4096} per lens), one persistent launch in a hipGraph, "
-                               "host buffers, %s PSF convolution" % (n, args.precision or "fp32"),
+                               "host buffers, %s PSF convolution, %s amplitudes"
+                               % (n, args.precision or "fp32", "NNLS-solved" if nnls else "explicit"),
                    "proposals_per_call": n, "autotune": bool(args.autotune)},
         "plain_one_lens_at_a_time_evals_per_s": n / plain_s,
         "batched_over_plain": plain_s / step_s,

@@ -81,6 +81,14 @@ typedef int32_t lens_status;
 #define LENS_PREC_BF16 2          /* BF16 MFMA, single product (lnL error < 1e-3) */
 #define LENS_PREC_BF16_SPLIT3 3   /* BF16 MFMA, hi+mid+lo split, 6 products (lnL error < 1e-6) */
 
+/* Light amplitudes, chosen per lens at load. */
+#define LENS_AMP_EXPLICIT 0       /* I_l, I_s are parameters (slots 7 and 12) */
+#define LENS_AMP_NNLS 1           /* solved linearly (Sec. 2.3): the amplitudes minimise
+                                     sum_mask ((d - s_l a - s_s b)/sigma)^2 over s >= 0, with a, b the
+                                     lens-light and source images at unit amplitude, binned and
+                                     PSF-convolved; lnL is taken there and slots 7, 12 are ignored.
+                                     Needs LENS_PREC_FP32. */
+
 typedef struct lens_ctx lens_ctx;
 typedef int64_t lens_id;
 typedef int64_t lens_req;
@@ -117,6 +125,7 @@ typedef struct lens_data_desc {
     const double *sigma;        /* ny*nx noise; > 0 and finite where mask = 1 */
     const uint8_t *mask;        /* ny*nx; nonzero = pixel enters the likelihood */
     int32_t precision;          /* LENS_PREC_* */
+    int32_t amplitudes;         /* LENS_AMP_* (0: explicit) */
     double psf_tail;            /* PSF tail crop: the kernel is cut to the smallest centred odd square
                                    whose discarded taps' total |weight| is <= psf_tail * sum|K|, which
                                    moves any convolved pixel by at most psf_tail * sum|K| * max|binned|.
@@ -176,6 +185,14 @@ lens_status lens_get_info(lens_ctx *ctx, lens_id id, lens_info *out);
  * the results are in out.  n = 0 is a no-op. */
 lens_status lens_loglike_batch(lens_ctx *ctx, lens_id id, const double *params, int64_t n,
                                double *out_loglike);
+
+/* lnL and the amplitudes it was taken at (host buffers, out_amp [n][2]:
+ * s_l, s_s).  For a LENS_AMP_NNLS lens these are the solved amplitudes; for an
+ * explicit-amplitude lens, the proposal's slots 7 and 12.  Proposals outside
+ * the domain give lnL = -inf and NaN amplitudes.  Blocks like
+ * lens_loglike_batch. */
+lens_status lens_loglike_amps(lens_ctx *ctx, lens_id id, const double *params, int64_t n,
+                              double *out_loglike, double *out_amp);
 
 /* Same on device buffers: d_params [n][20] and d_out [n] in device memory,
  * enqueued on the hipStream_t `stream` (NULL: the default stream) and not

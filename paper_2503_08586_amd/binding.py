@@ -39,9 +39,12 @@ LENS_PREC_BF16_SPLIT = 1
 LENS_PREC_BF16 = 2
 LENS_PREC_BF16_SPLIT3 = 3
 
+LENS_AMP_EXPLICIT = 0
+LENS_AMP_NNLS = 1
+
 EXPORTED = [
     "lens_init", "lens_shutdown", "lens_load_data", "lens_unload", "lens_get_info",
-    "lens_loglike_batch", "lens_loglike_batch_device", "lens_loglike_multi",
+    "lens_loglike_batch", "lens_loglike_amps", "lens_loglike_batch_device", "lens_loglike_multi",
     "lens_submit", "lens_poll", "lens_wait", "lens_cancel", "lens_get_stats",
     "lens_model_image", "lens_selftest", "lens_psf_crop", "lens_strerror", "lens_last_error",
 ]
@@ -76,6 +79,7 @@ class lens_data_desc(ctypes.Structure):
         ("sigma", ctypes.POINTER(ctypes.c_double)),
         ("mask", ctypes.POINTER(ctypes.c_uint8)),
         ("precision", ctypes.c_int32),
+        ("amplitudes", ctypes.c_int32),
         ("psf_tail", ctypes.c_double),
     ]
 
@@ -124,6 +128,7 @@ def load():
         "lens_unload": ([vp, i64], i32),
         "lens_get_info": ([vp, i64, ctypes.POINTER(lens_info)], i32),
         "lens_loglike_batch": ([vp, i64, dp, i64, dp], i32),
+        "lens_loglike_amps": ([vp, i64, dp, i64, dp, dp], i32),
         "lens_loglike_batch_device": ([vp, i64, vp, i64, vp, vp], i32),
         "lens_loglike_multi": ([vp, i32, i64p, i64p, dp, dp], i32),
         "lens_submit": ([vp, i64, dp, i64, dp, i64p], i32),
@@ -229,7 +234,7 @@ def lens_shutdown(ctx):
 
 
 def lens_load_data(ctx, ny, nx, pixel_scale, supersample, psf, data, sigma, mask,
-                   precision=LENS_PREC_FP32, psf_tail=0.0) -> int:
+                   precision=LENS_PREC_FP32, psf_tail=0.0, amplitudes=0) -> int:
     psf = np.ascontiguousarray(psf, dtype=np.float64)
     data = np.ascontiguousarray(data, dtype=np.float64)
     sigma = np.ascontiguousarray(sigma, dtype=np.float64)
@@ -243,6 +248,7 @@ def lens_load_data(ctx, ny, nx, pixel_scale, supersample, psf, data, sigma, mask
     d.mask = mask.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
     d.precision = precision
     d.psf_tail = psf_tail
+    d.amplitudes = amplitudes
     lid = ctypes.c_int64()
     _check(ctx, load().lens_load_data(ctx, ctypes.byref(d), ctypes.byref(lid)))
     return lid.value
@@ -257,6 +263,15 @@ def lens_psf_crop(psf, psf_tail=0.0) -> int:
     if st != 0:
         raise LensError(st, "lens_psf_crop")
     return out.value
+
+
+def lens_loglike_amps(ctx, lens_id, params):
+    """(lnL [n], amplitudes [n, 2]) of every proposal row (host buffers)."""
+    p = _params(params)
+    out = np.empty(p.shape[0], dtype=np.float64)
+    amp = np.empty((p.shape[0], 2), dtype=np.float64)
+    _check(ctx, load().lens_loglike_amps(ctx, lens_id, _dptr(p), p.shape[0], _dptr(out), _dptr(amp)))
+    return out, amp
 
 
 def lens_unload(ctx, lens_id):
@@ -380,11 +395,11 @@ class LensContext:
     def __exit__(self, *a):
         self.close()
 
-    def load(self, spec, precision=LENS_PREC_FP32, data=None, psf_tail=0.0) -> int:
+    def load(self, spec, precision=LENS_PREC_FP32, data=None, psf_tail=0.0, amplitudes=0) -> int:
         """Load a synth.LensSpec (its data, or ``data`` if given)."""
         d = spec.data if data is None else data
         lid = lens_load_data(self.ctx, spec.ny, spec.nx, spec.dpix, spec.s, spec.psf, d, spec.sigma,
-                             spec.mask, precision, psf_tail)
+                             spec.mask, precision, psf_tail, amplitudes)
         self.geom[lid] = (spec.ny, spec.nx)
         return lid
 
@@ -396,6 +411,10 @@ class LensContext:
     def unload(self, lid):
         lens_unload(self.ctx, lid)
         self.geom.pop(lid, None)
+
+    def loglike_amps(self, lid, params):
+        """(lnL, amplitudes [n, 2]) at the solved (LENS_AMP_NNLS) or given amplitudes."""
+        return lens_loglike_amps(self.ctx, lid, params)
 
     def loglike(self, lid, params) -> np.ndarray:
         return lens_loglike_batch(self.ctx, lid, params)

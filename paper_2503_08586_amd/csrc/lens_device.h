@@ -175,15 +175,16 @@ __device__ __forceinline__ void ray_trace(double x1, double x2, double lx, doubl
     by = ly - fma(P.sm, a1, P.cm * a2);
 }
 
-// Binned (mean) value of pixel (y, x): s x s sub-pixel centres (Sec. 2.1).
-// Fine-grid index fx = x s + u maps to position (fx - (nx s - 1)/2) * pixel_scale / s.
+// Sub-pixel sums of pixel (y, x), whose binned value is their mean over the
+// s x s sub-pixel centres (Sec. 2.1).  Fine-grid index fx = x s + u maps to position (fx - (nx s - 1)/2) * pixel_scale / s.
 // Along a sub-pixel row the x offset dx from the mass centre steps by
 // pixel_scale / s (at most 7 FP64 additions, ~1e-15 arcsec from the direct
 // product), and everything else linear in x is one FMA in dx with per-row
 // constants: the mass-frame coordinates, theta - alpha_shear - source centre,
 // and the lens light's (R/R_e)^2 (a quadratic in dx).  Lens and source light
-// are summed apart and take their amplitudes once.
-__device__ __forceinline__ float binned_pixel(const LensGeom &g, const PropBlock &P, int y, int x)
+// are summed apart (al, as: sums over the sub-pixels at unit amplitude).
+__device__ __forceinline__ void binned_sums(const LensGeom &g, const PropBlock &P, int y, int x, double &al_out,
+                                            double &as_out)
 {
     const int s = g.s;
     const double x0 = ((double)(x * s) - g.cfx) * g.sd;
@@ -211,7 +212,24 @@ __device__ __forceinline__ float binned_pixel(const LensGeom &g, const PropBlock
             dx += h;
         }
     }
+    al_out = al;
+    as_out = as;
+}
+
+__device__ __forceinline__ float binned_pixel(const LensGeom &g, const PropBlock &P, int y, int x)
+{
+    double al, as;
+    binned_sums(g, P, y, x, al, as);
     return (float)(fma(P.lens.I, al, P.src.I * as) * g.inv_s2);
+}
+
+// The two unit-amplitude channels (lens light, source) of pixel (y, x), for
+// amplitudes solved by non-negative least squares (Sec. 2.3).
+__device__ __forceinline__ float2 binned_pixel2(const LensGeom &g, const PropBlock &P, int y, int x)
+{
+    double al, as;
+    binned_sums(g, P, y, x, al, as);
+    return make_float2((float)(al * g.inv_s2), (float)(as * g.inv_s2));
 }
 
 // Sersic b_n: root of P(2n, b) = 1/2 (Eq. 9), FP64 Newton safeguarded by

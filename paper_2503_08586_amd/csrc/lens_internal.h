@@ -24,7 +24,8 @@ struct LightK {
 // Derived constants of one proposal, written by the prep kernel and read
 // (uniformly, through the scalar cache) by every workgroup of that proposal.
 struct alignas(16) PropBlock {
-    double valid;                              // 1 inside the domain, 0 outside
+    double valid;                              // 1 inside the domain; 2 inside except for non-finite
+                                               // amplitudes (usable when they are solved); 0 outside
     double xm, ym, cm, sm, q2m, ce;            // SIE: centre, cos/sin phi, q^2, c = sqrt(1 - q^2)
     double bsie, bsc;                          // theta_E sqrt(q), theta_E sqrt(q) / c (0 if c = 0)
     double g1, g2, xs, ys;                     // shear, source centre
@@ -35,8 +36,10 @@ struct alignas(16) PropBlock {
 static_assert(sizeof(PropBlock) == 256, "PropBlock layout");
 constexpr int kPCBytes = (int)sizeof(PropBlock);
 
-// PSF-convolution modes (the public LENS_PREC_* values).
-enum : int { MODE_FP32 = 0, MODE_SPLIT = 1, MODE_BF16 = 2, MODE_SPLIT3 = 3 };
+// PSF-convolution modes (the public LENS_PREC_* values), and the FP32
+// convolution of two unit-amplitude channels (lens light, source) whose
+// amplitudes are solved by non-negative least squares (Sec. 2.3).
+enum : int { MODE_FP32 = 0, MODE_SPLIT = 1, MODE_BF16 = 2, MODE_SPLIT3 = 3, MODE_FP32N = 4 };
 __host__ __device__ constexpr int mode_planes(int mode)
 {
     return mode == MODE_SPLIT ? 2 : mode == MODE_SPLIT3 ? 3 : 1;
@@ -59,6 +62,7 @@ struct LensGeom {
     double cfx, cfy;       // (nx*s - 1)/2, (ny*s - 1)/2: fine-grid centre
     float inv_s2;          // 1/s^2
     double norm;           // C = -1/2 sum_mask ln(2 pi sigma^2)
+    double dd;             // MODE_FP32N: sum_mask (w d)^2 in FP64 of the FP32 w and d
     const float *psf;      // flipped kernel Kf[a][b] = K[k-1-a][k-1-b], [k][k]
     const float *data;     // [ny][pitch], 0 outside the mask and the image
     const float *wgt;      // [ny][pitch], mask/sigma, 0 outside the mask and the image
@@ -84,7 +88,8 @@ size_t lds_per_cu();
 
 hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, hipStream_t st);
 // the fused likelihood of n proposals of one lens (FP32 or MFMA convolution per g.mode)
-hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out,
+// d_amp (MODE_FP32N, may be null): the solved amplitudes, [n][2] (lens, source)
+hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, double *d_amp,
                           hipStream_t st);
 // persistent multi-lens launch (counter reset + kernel) and its occupancy
 int batch_blocks_per_cu(int mode, int nt, size_t lds);

@@ -49,15 +49,16 @@ __global__ void __launch_bounds__(256) k_prep(const double *__restrict__ params,
 #pragma unroll
     for (int j = 0; j < 19; ++j) {
         v[j] = p[j];
-        ok = ok && isfinite(v[j]);
+        if (j != 7 && j != 12) ok = ok && isfinite(v[j]);   // amplitudes: below
     }
+    const bool amps_ok = isfinite(v[7]) && isfinite(v[12]);
     ok = ok && v[0] >= 0.0;
     ok = ok && v[1] > 0.0 && v[1] <= 1.0 && v[10] > 0.0 && v[10] <= 1.0 && v[15] > 0.0 && v[15] <= 1.0;
     ok = ok && v[8] > 0.0 && v[13] > 0.0;
     ok = ok && v[9] >= kNMin && v[9] <= kNMax && v[14] >= kNMin && v[14] <= kNMax;
     if (ok) {
         const double q = v[1];
-        b.valid = 1.0;
+        b.valid = amps_ok ? 1.0 : 2.0;
         b.xm = v[3];
         b.ym = v[4];
         b.cm = cos(v[2]);
@@ -132,6 +133,13 @@ struct RingStore {
     }
 };
 
+// Two unit-amplitude channels (lens light, source) per ring element.
+template <>
+struct RingStore<MODE_FP32N> {
+    __device__ static void put(void *ring, int, int idx, float2 v) { static_cast<float2 *>(ring)[idx] = v; }
+    __device__ static void zero(void *ring, int, int idx) { static_cast<float2 *>(ring)[idx] = make_float2(0.f, 0.f); }
+};
+
 // Binned rows [ya, yb) (all < ny) into their ring slots: every pixel in the
 // row's needed range is evaluated; the rest of the row is cleared when the
 // slot is being reused (clear = true).  Ring column of image column x is x + r.
@@ -157,28 +165,31 @@ __device__ __forceinline__ void fill_rows(const LensGeom &g, const PropBlock &P,
         const int y = (int)(e >> 16), x = (int)(e & 0xffffu);
         int slot = slot_a + (y - ya);
         if (slot >= RB) slot -= RB;
-        RingStore<MODE>::put(ring, g.plane, slot * W + r + x, binned_pixel(g, P, y, x));
+        if constexpr (MODE == MODE_FP32N)
+            RingStore<MODE>::put(ring, g.plane, slot * W + r + x, binned_pixel2(g, P, y, x));
+        else
+            RingStore<MODE>::put(ring, g.plane, slot * W + r + x, binned_pixel(g, P, y, x));
     }
 }
 
-// The strip loop shared by both kernels: binned rows enter the ring strip by
-// strip, each binned row is computed once, and conv(y0, y1, strip) adds the
-// chi-square of output rows [y0, y1).
-template <int MODE, int NT, typename Conv>
-__device__ __forceinline__ void strip_loop(const LensGeom &g, const PropBlock &P, void *ring,
+// The strip sweep shared by every kernel: binned rows enter the ring strip by
+// strip, each binned row is computed once, and conv(y0, y1, strip) returns this
+// thread's contribution (chi-square, or the NNLS moments) of output rows [y0, y1).
+template <int MODE, int NT, typename Acc, typename Conv>
+__device__ __forceinline__ Acc strip_sweep(const LensGeom &g, const PropBlock &P, void *ring,
                                            const uint32_t *__restrict__ evl, const int *__restrict__ evpre,
-                                           const int2 *__restrict__ evr, double *__restrict__ out,
-                                           int64_t p, Conv conv)
+                                           const int2 *__restrict__ evr, Conv conv)
 {
-    __shared__ double red[NT / 64];
     const int ny = g.ny, r = g.r, H = g.strip_h, RB = g.ring_rows;
-    const int nwords = (MODE == MODE_FP32 ? RB * g.ring_w : RB * g.ring_w * mode_planes(MODE) / 2) / 4;
+    const int nwords = (MODE == MODE_FP32    ? RB * g.ring_w
+                        : MODE == MODE_FP32N ? 2 * RB * g.ring_w
+                                             : RB * g.ring_w * mode_planes(MODE) / 2) / 4;
     float4 *r4 = static_cast<float4 *>(ring);
     for (int i = threadIdx.x; i < nwords; i += NT) r4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     // binned rows [0, r) precede the first strip
     fill_rows<MODE, NT>(g, P, ring, evl, evpre, evr, 0, min(r, ny), false);
-    double acc = 0.0;
+    Acc acc{};
     int strip = 0;
     for (int y0 = 0; y0 < ny; y0 += H, ++strip) {
         __syncthreads();  // the previous strip is done reading the slots reused below
@@ -193,6 +204,19 @@ __device__ __forceinline__ void strip_loop(const LensGeom &g, const PropBlock &P
         __syncthreads();
         acc += conv(y0, min(y0 + H, ny), strip);
     }
+    return acc;
+}
+
+// Explicit amplitudes: lnL = C - chi^2 / 2, the per-thread chi-square sums
+// reduced through a wave64 shuffle tree and a fixed-order sum over the waves.
+template <int MODE, int NT, typename Conv>
+__device__ __forceinline__ void strip_loop(const LensGeom &g, const PropBlock &P, void *ring,
+                                           const uint32_t *__restrict__ evl, const int *__restrict__ evpre,
+                                           const int2 *__restrict__ evr, double *__restrict__ out,
+                                           int64_t p, Conv conv)
+{
+    __shared__ double red[NT / 64];
+    double acc = strip_sweep<MODE, NT, double>(g, P, ring, evl, evpre, evr, conv);
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
     __syncthreads();
@@ -200,6 +224,100 @@ __device__ __forceinline__ void strip_loop(const LensGeom &g, const PropBlock &P
         double s = 0.0;
         for (int w = 0; w < NT / 64; ++w) s += red[w];
         out[p] = g.norm - 0.5 * s;
+    }
+}
+
+// Moments of the amplitude solve (Sec. 2.3) over the masked pixels, with the
+// columns a (lens light) and b (source) of M at unit amplitude, the data d and
+// the weights w = mask/sigma: F = [[sum (wa)^2, sum (wa)(wb)], [., sum (wb)^2]],
+// g = (sum (wa)(wd), sum (wb)(wd)).  FP64 sums of products of FP32 values.
+struct Mom5 {
+    double f11, f12, f22, g1, g2;
+    __device__ Mom5 &operator+=(const Mom5 &o)
+    {
+        f11 += o.f11;
+        f12 += o.f12;
+        f22 += o.f22;
+        g1 += o.g1;
+        g2 += o.g2;
+        return *this;
+    }
+};
+
+// Non-negative least squares in two variables (Sec. 2.3): the minimiser of
+// chi^2(s) = D - 2 s.g + s.F s over s >= 0 is the least-squares solution on
+// one of the four supports (both, lens only, source only, none) that is
+// feasible and has the smallest chi^2; on a support S the optimum has
+// F_S s_S = g_S, so chi^2 = D - s_S.g_S.  D = sum (wd)^2.  Returns chi^2
+// (>= 0) and the amplitudes.
+__device__ inline double nnls2(const Mom5 &m, double D, double &sl, double &ss)
+{
+    double best = D;
+    sl = 0.0;
+    ss = 0.0;
+    const double det = m.f11 * m.f22 - m.f12 * m.f12;
+    if (det > 0.0) {
+        const double a = (m.g1 * m.f22 - m.g2 * m.f12) / det, b = (m.g2 * m.f11 - m.g1 * m.f12) / det;
+        const double c = D - (a * m.g1 + b * m.g2);
+        if (a >= 0.0 && b >= 0.0 && c < best) {
+            best = c;
+            sl = a;
+            ss = b;
+        }
+    }
+    if (m.f11 > 0.0 && m.g1 > 0.0) {
+        const double c = D - m.g1 * m.g1 / m.f11;
+        if (c < best) {
+            best = c;
+            sl = m.g1 / m.f11;
+            ss = 0.0;
+        }
+    }
+    if (m.f22 > 0.0 && m.g2 > 0.0) {
+        const double c = D - m.g2 * m.g2 / m.f22;
+        if (c < best) {
+            best = c;
+            sl = 0.0;
+            ss = m.g2 / m.f22;
+        }
+    }
+    return fmax(best, 0.0);
+}
+
+// Solved amplitudes: the NNLS moments reduced like the chi-square (five sums),
+// then one thread solves and writes lnL = C - chi^2 / 2 (and the amplitudes).
+template <int NT, typename Conv>
+__device__ __forceinline__ void strip_loop_nnls(const LensGeom &g, const PropBlock &P, void *ring,
+                                                const uint32_t *__restrict__ evl, const int *__restrict__ evpre,
+                                                const int2 *__restrict__ evr, double *__restrict__ out,
+                                                double *__restrict__ amp, int64_t p, Conv conv)
+{
+    __shared__ double red[5][NT / 64];
+    Mom5 m = strip_sweep<MODE_FP32N, NT, Mom5>(g, P, ring, evl, evpre, evr, conv);
+    m.f11 = wave_sum(m.f11);
+    m.f12 = wave_sum(m.f12);
+    m.f22 = wave_sum(m.f22);
+    m.g1 = wave_sum(m.g1);
+    m.g2 = wave_sum(m.g2);
+    if ((threadIdx.x & 63) == 0) {
+        const int w = threadIdx.x >> 6;
+        red[0][w] = m.f11;
+        red[1][w] = m.f12;
+        red[2][w] = m.f22;
+        red[3][w] = m.g1;
+        red[4][w] = m.g2;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        Mom5 t{0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int w = 0; w < NT / 64; ++w) t += Mom5{red[0][w], red[1][w], red[2][w], red[3][w], red[4][w]};
+        double sl, ss;
+        const double chi2 = nnls2(t, g.dd, sl, ss);
+        out[p] = g.norm - 0.5 * chi2;
+        if (amp) {
+            amp[2 * p] = sl;
+            amp[2 * p + 1] = ss;
+        }
     }
 }
 
@@ -278,7 +396,7 @@ k_loglike_fp32(const LensGeom g, const PropBlock *__restrict__ pc, const float *
     float *ring = reinterpret_cast<float *>(lds4);
     const int64_t p = blockIdx.x;
     const PropBlock *c = pc + p;
-    if (c->valid == 0.0) {
+    if (c->valid != 1.0) {
         if (threadIdx.x == 0) out[p] = -INFINITY;
         return;
     }
@@ -385,7 +503,7 @@ k_loglike_mfma(const LensGeom g, const PropBlock *__restrict__ pc, const uint32_
     uint16_t *ring = reinterpret_cast<uint16_t *>(lds4);
     const int64_t p = blockIdx.x;
     const PropBlock *c = pc + p;
-    if (c->valid == 0.0) {
+    if (c->valid != 1.0) {
         if (threadIdx.x == 0) out[p] = -INFINITY;
         return;
     }
@@ -456,6 +574,86 @@ __device__ __forceinline__ double conv_rows_rt(const LensGeom &g, const float *r
     return acc;
 }
 
+// The NNLS variant: both unit-amplitude channels (float2 ring) convolved with
+// the runtime-k sliding window of conv_rows_rt, and the moments of the
+// amplitude solve accumulated in FP64 from the FP32 columns, data and weights.
+template <int NT>
+__device__ __forceinline__ Mom5 conv_rows2_rt(const LensGeom &g, const float2 *ring, int ya, int yb)
+{
+    const int W = g.ring_w, RB = g.ring_rows, k = g.k;
+    const float *__restrict__ psf = g.psf;
+    Mom5 m{0.0, 0.0, 0.0, 0.0, 0.0};
+    const int gb = g.cvpre[yb];
+    for (int gi = g.cvpre[ya] + threadIdx.x; gi < gb; gi += NT) {
+        const uint32_t e = g.cvl[gi];
+        const int y = (int)(e >> 16), x0 = (int)(e & 0xffffu);
+        float2 o0 = make_float2(0.f, 0.f), o1 = o0, o2 = o0, o3 = o0;
+        int slot = y % RB;
+        for (int a = 0; a < k; ++a) {
+            const float2 *row = ring + slot * W + x0;
+            const float *kr = psf + a * k;
+            float2 p0 = make_float2(0.f, 0.f), p1 = p0, p2 = p0, p3 = p0;
+            float2 v0 = row[0], v1 = row[1], v2 = row[2];
+            for (int b = 0; b < k; ++b) {
+                const float w = kr[b];
+                const float2 v3 = row[b + 3];
+                p0.x = fmaf(w, v0.x, p0.x); p0.y = fmaf(w, v0.y, p0.y);
+                p1.x = fmaf(w, v1.x, p1.x); p1.y = fmaf(w, v1.y, p1.y);
+                p2.x = fmaf(w, v2.x, p2.x); p2.y = fmaf(w, v2.y, p2.y);
+                p3.x = fmaf(w, v3.x, p3.x); p3.y = fmaf(w, v3.y, p3.y);
+                v0 = v1;
+                v1 = v2;
+                v2 = v3;
+            }
+            o0.x += p0.x; o0.y += p0.y;
+            o1.x += p1.x; o1.y += p1.y;
+            o2.x += p2.x; o2.y += p2.y;
+            o3.x += p3.x; o3.y += p3.y;
+            slot = (slot + 1 == RB) ? 0 : slot + 1;
+        }
+        const float4 d = *reinterpret_cast<const float4 *>(g.data + (size_t)y * g.pitch + x0);
+        const float4 w = *reinterpret_cast<const float4 *>(g.wgt + (size_t)y * g.pitch + x0);
+        const float2 oo[4] = {o0, o1, o2, o3};
+        const float dd[4] = {d.x, d.y, d.z, d.w}, ww[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const double wj = (double)ww[j];
+            const double wa = wj * (double)oo[j].x, wb = wj * (double)oo[j].y, wd = wj * (double)dd[j];
+            m.f11 = fma(wa, wa, m.f11);
+            m.f12 = fma(wa, wb, m.f12);
+            m.f22 = fma(wb, wb, m.f22);
+            m.g1 = fma(wa, wd, m.g1);
+            m.g2 = fma(wb, wd, m.g2);
+        }
+    }
+    return m;
+}
+
+// Light amplitudes solved by NNLS (Sec. 2.3): one workgroup per proposal, the
+// two channels through the LDS ring and the FP32 convolution, the moments
+// reduced and the 2 x 2 problem solved in the workgroup.  amp may be null.
+template <int NT>
+__global__ void __launch_bounds__(NT)
+k_loglike_nnls(const LensGeom g, const PropBlock *__restrict__ pc, double *__restrict__ out,
+               double *__restrict__ amp)
+{
+    extern __shared__ float4 lds4[];
+    float2 *ring = reinterpret_cast<float2 *>(lds4);
+    const int64_t p = blockIdx.x;
+    const PropBlock *c = pc + p;
+    if (c->valid == 0.0) {
+        if (threadIdx.x == 0) {
+            out[p] = -INFINITY;
+            if (amp) amp[2 * p] = amp[2 * p + 1] = NAN;
+        }
+        return;
+    }
+    const PropBlock P = *c;
+    strip_loop_nnls<NT>(g, P, ring, g.evl, g.evpre, g.evr, out, amp, p, [&](int y0, int y1, int) {
+        return conv_rows2_rt<NT>(g, ring, y0, y1);
+    });
+}
+
 __global__ void k_reset_counter(unsigned int *counter) { *counter = 0u; }
 
 // Work items are (lens, proposal) pairs numbered lens-major in the batch's
@@ -490,11 +688,16 @@ k_loglike_batch(const LensGeom *__restrict__ geoms, const int *__restrict__ lsta
         const LensGeom g = geoms[lo];
         const int64_t p = lout[lo] + (item - lstart[lo]);
         const PropBlock *c = pc + p;
-        if (c->valid == 0.0) {
+        if (MODE == MODE_FP32N ? c->valid == 0.0 : c->valid != 1.0) {
             if (threadIdx.x == 0) out[p] = -INFINITY;
         } else {
             const PropBlock P = *c;
-            if (MODE == MODE_FP32) {
+            if constexpr (MODE == MODE_FP32N) {
+                float2 *ring = reinterpret_cast<float2 *>(lds4);
+                strip_loop_nnls<NT>(g, P, ring, g.evl, g.evpre, g.evr, out, nullptr, p, [&](int y0, int y1, int) {
+                    return conv_rows2_rt<NT>(g, ring, y0, y1);
+                });
+            } else if (MODE == MODE_FP32) {
                 float *ring = reinterpret_cast<float *>(lds4);
                 strip_loop<MODE, NT>(g, P, ring, g.evl, g.evpre, g.evr, out, p, [&](int y0, int y1, int) {
                     return conv_rows_rt<NT>(g, ring, y0, y1);
@@ -569,14 +772,15 @@ int choose_kc(int k) { return (k + 6) / 4; }
 
 int ring_width(int mode, int k, int nx)
 {
-    if (mode == MODE_FP32) return (nx + 3) / 4 * 4 + 4 * choose_kc(k);
+    if (mode == MODE_FP32 || mode == MODE_FP32N) return (nx + 3) / 4 * 4 + 4 * choose_kc(k);
     const int L = (16 + k - 1 + 7) / 8 * 8;
     return (nx + 15) / 16 * 16 + L;
 }
 
 size_t ring_row_bytes(int mode, int k, int nx)
 {
-    return (size_t)ring_width(mode, k, nx) * (mode == MODE_FP32 ? 4 : 2 * mode_planes(mode));
+    const size_t elem = mode == MODE_FP32 ? 4 : mode == MODE_FP32N ? 8 : 2 * mode_planes(mode);
+    return (size_t)ring_width(mode, k, nx) * elem;
 }
 
 size_t ring_bytes(const LensGeom &g) { return (size_t)g.ring_rows * ring_row_bytes(g.mode, g.k, g.nx); }
@@ -650,9 +854,23 @@ static hipError_t launch_nt(const LensGeom &g, const PropBlock *d_pc, int64_t n,
     }
 }
 
-hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, hipStream_t st)
+template <int NT>
+static hipError_t launch_nnls(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, double *d_amp,
+                              hipStream_t st)
+{
+    hipLaunchKernelGGL((k_loglike_nnls<NT>), dim3((unsigned)n), dim3(NT), ring_bytes(g), st, g, d_pc, d_out, d_amp);
+    return hipGetLastError();
+}
+
+hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, double *d_amp,
+                          hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
+    if (g.mode == MODE_FP32N) {
+        if (g.nt == 512) return launch_nnls<512>(g, d_pc, n, d_out, d_amp, st);
+        if (g.nt == 256) return launch_nnls<256>(g, d_pc, n, d_out, d_amp, st);
+        return hipErrorInvalidValue;
+    }
     if (g.nt == 512) return launch_nt<512>(g, d_pc, n, d_out, st);
     if (g.nt == 256) return launch_nt<256>(g, d_pc, n, d_out, st);
     return hipErrorInvalidValue;
@@ -667,6 +885,7 @@ static const void *loglike_kernel_nt(const LensGeom &g)
     case MODE_BF16: return reinterpret_cast<const void *>(&k_loglike_mfma<MODE_BF16, NT>);
     case MODE_SPLIT: return reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT, NT>);
     case MODE_SPLIT3: return reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT3, NT>);
+    case MODE_FP32N: return reinterpret_cast<const void *>(&k_loglike_nnls<NT>);
     case MODE_FP32: break;
     default: return nullptr;
     }
@@ -702,7 +921,8 @@ static void likelihood_kernels_nt(std::vector<const void *> &v)
     v.push_back(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_BF16, NT>));
     v.push_back(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT, NT>));
     v.push_back(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT3, NT>));
-    for (int m : {MODE_FP32, MODE_SPLIT, MODE_BF16, MODE_SPLIT3}) v.push_back(batch_kernel(m, NT));
+    v.push_back(reinterpret_cast<const void *>(&k_loglike_nnls<NT>));
+    for (int m : {MODE_FP32, MODE_SPLIT, MODE_BF16, MODE_SPLIT3, MODE_FP32N}) v.push_back(batch_kernel(m, NT));
 }
 
 // Raise every ring-using kernel's dynamic-LDS limit so that dynamic plus
@@ -750,6 +970,7 @@ static const void *batch_kernel(int mode, int nt)
         case MODE_SPLIT: return batch_kernel_ptr<MODE_SPLIT, 256>();
         case MODE_BF16: return batch_kernel_ptr<MODE_BF16, 256>();
         case MODE_SPLIT3: return batch_kernel_ptr<MODE_SPLIT3, 256>();
+        case MODE_FP32N: return batch_kernel_ptr<MODE_FP32N, 256>();
         }
     } else if (nt == 512) {
         switch (mode) {
@@ -757,6 +978,7 @@ static const void *batch_kernel(int mode, int nt)
         case MODE_SPLIT: return batch_kernel_ptr<MODE_SPLIT, 512>();
         case MODE_BF16: return batch_kernel_ptr<MODE_BF16, 512>();
         case MODE_SPLIT3: return batch_kernel_ptr<MODE_SPLIT3, 512>();
+        case MODE_FP32N: return batch_kernel_ptr<MODE_FP32N, 512>();
         }
     }
     return nullptr;

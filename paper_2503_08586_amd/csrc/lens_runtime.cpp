@@ -42,6 +42,7 @@ struct Lens {
     lens_id id = 0;
     LensGeom g{};
     int precision = 0;
+    int amplitudes = 0;     // LENS_AMP_*
     int64_t masked = 0, needed = 0;
     int psf_given = 0;      // PSF side as loaded (g.k is the side after the tail crop)
     void *slab = nullptr;   // one device allocation holding every array
@@ -376,13 +377,14 @@ struct ScratchLayout {
     double *params;
     lensk::PropBlock *pc;
     double *out;
+    double *amp;   // [n][2] solved amplitudes, right after out
 };
 
 size_t scratch_bytes(int64_t n, bool with_params_out)
 {
     size_t b = align_up((size_t)n * lensk::kPCBytes, kAlign);
     if (with_params_out)
-        b += align_up((size_t)n * lensk::kStride * sizeof(double), kAlign) + align_up((size_t)n * sizeof(double), kAlign);
+        b += align_up((size_t)n * lensk::kStride * sizeof(double), kAlign) + align_up((size_t)n * 3 * sizeof(double), kAlign);
     return b;
 }
 
@@ -396,16 +398,17 @@ ScratchLayout carve(void *base, int64_t n, bool with_params_out)
         L.params = (double *)p;
         p += align_up((size_t)n * lensk::kStride * sizeof(double), kAlign);
         L.out = (double *)p;
+        L.amp = L.out + n;
     }
     return L;
 }
 
 hipError_t launch_lens(const Lens *L, const double *d_params, lensk::PropBlock *d_pc, int64_t n, double *d_out,
-                       hipStream_t st)
+                       hipStream_t st, double *d_amp = nullptr)
 {
     hipError_t e = lensk::launch_prep(d_params, n, d_pc, st);
     if (e != hipSuccess) return e;
-    return lensk::launch_loglike(L->g, d_pc, n, d_out, st);
+    return lensk::launch_loglike(L->g, d_pc, n, d_out, d_amp, st);
 }
 
 void scheduler_main(lens_ctx *c);
@@ -619,10 +622,10 @@ lens_status tune_lens(lens_ctx *c, Lens *L)
         LensGeom g2 = L->g;
         if (!set_tiles(g2, H, nt, c->lds_max) || g2.strip_h != H) continue;
         float t = 1e30f;
-        hipError_t e = lensk::launch_loglike(g2, dpc, n, dout, c->stream);  // warm-up
+        hipError_t e = lensk::launch_loglike(g2, dpc, n, dout, nullptr, c->stream);  // warm-up
         for (int rep = 0; rep < 2 && e == hipSuccess; ++rep) {
             e = hipEventRecord(e0, c->stream);
-            if (e == hipSuccess) e = lensk::launch_loglike(g2, dpc, n, dout, c->stream);
+            if (e == hipSuccess) e = lensk::launch_loglike(g2, dpc, n, dout, nullptr, c->stream);
             if (e == hipSuccess) e = hipEventRecord(e1, c->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
@@ -699,6 +702,10 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     if (!d->psf || !d->data || !d->sigma || !d->mask) return fail(c, LENS_EINVAL, "null array in descriptor");
     if (d->precision < LENS_PREC_FP32 || d->precision > LENS_PREC_BF16_SPLIT3)
         return fail(c, LENS_EINVAL, "unknown precision mode");
+    if (d->amplitudes != LENS_AMP_EXPLICIT && d->amplitudes != LENS_AMP_NNLS)
+        return fail(c, LENS_EINVAL, "unknown amplitudes mode");
+    if (d->amplitudes == LENS_AMP_NNLS && d->precision != LENS_PREC_FP32)
+        return fail(c, LENS_EINVAL, "amplitudes solved by NNLS need the FP32 convolution (LENS_PREC_FP32)");
     const int64_t npix = (int64_t)ny * nx;
     for (int i = 0; i < k_given * k_given; ++i)
         if (!std::isfinite(d->psf[i])) return fail(c, LENS_EINVAL, "non-finite PSF value");
@@ -726,7 +733,8 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     }
     const int r = (k - 1) / 2;
     const int kc = lensk::choose_kc(k);
-    const int mode = d->precision;  // LENS_PREC_* equal lensk::MODE_*
+    // LENS_PREC_* equal lensk::MODE_*; solved amplitudes convolve two channels
+    const int mode = d->amplitudes == LENS_AMP_NNLS ? (int)lensk::MODE_FP32N : d->precision;
     const int pitch = (int)align_up((size_t)nx, 16);
     // masked column range of each row
     std::vector<int> mlo(ny, INT_MAX), mhi(ny, INT_MIN);
@@ -770,7 +778,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     std::vector<uint32_t> seg;
     std::vector<int> segpre(ny + 1, 0);
     std::vector<uint16_t> aop;
-    if (mode != LENS_PREC_FP32) {
+    if (mode == lensk::MODE_SPLIT || mode == lensk::MODE_BF16 || mode == lensk::MODE_SPLIT3) {
         g.L = (int)align_up((size_t)(16 + k - 1), 8);
         g.nchunks = (int)((k * g.L + 31) / 32);
         for (int y = 0; y < ny; ++y) {
@@ -807,6 +815,12 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
         }
     for (int a = 0; a < k; ++a)
         for (int b = 0; b < k; ++b) hk[(size_t)a * k + b] = (float)psf[(size_t)(k - 1 - a) * k + (k - 1 - b)];
+    // D = sum_mask (w d)^2 from the same FP32 values the kernels read (amplitude solve)
+    g.dd = 0.0;
+    for (size_t i = 0; i < hd.size(); ++i) {
+        const double wd = (double)hw[i] * (double)hd[i];
+        g.dd += wd * wd;
+    }
     // one slab
     size_t off = 0;
     auto place = [&](size_t bytes) {
@@ -865,6 +879,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     Lens *L = new Lens();
     L->g = g;
     L->precision = d->precision;
+    L->amplitudes = d->amplitudes;
     L->psf_given = k_given;
     L->masked = masked;
     L->needed = (int64_t)evl.size();
@@ -964,7 +979,7 @@ lens_status sync_buffers(lens_ctx *c, int64_t n)
         c->h_params = c->h_out = nullptr;
         c->h_cap = 0;
         HIPCHK(c, hipHostMalloc((void **)&c->h_params, cap * lensk::kStride * sizeof(double), hipHostMallocDefault));
-        HIPCHK(c, hipHostMalloc((void **)&c->h_out, cap * sizeof(double), hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->h_out, cap * 3 * sizeof(double), hipHostMallocDefault));
         c->h_cap = cap;
     }
     const size_t need = scratch_bytes((int64_t)c->h_cap, true);
@@ -1018,6 +1033,59 @@ extern "C" lens_status lens_loglike_batch(lens_ctx *c, lens_id id, const double 
             if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
             if (e != hipSuccess) rs = hip_fail(c, e, "lens_loglike_batch");
             else memcpy(out, c->h_out, (size_t)n * sizeof(double));
+        }
+    }
+    release(c, L);
+    return rs;
+}
+
+extern "C" lens_status lens_loglike_amps(lens_ctx *c, lens_id id, const double *params, int64_t n, double *out,
+                                         double *out_amp)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (n < 0 || (n > 0 && (!params || !out || !out_amp))) return fail(c, LENS_EINVAL, "bad params/out/out_amp/n");
+    if (n > INT_MAX) return fail(c, LENS_EINVAL, "n too large for one call");
+    Lens *L = acquire(c, id);
+    if (!L) return fail(c, LENS_ENOENT, "unknown lens id");
+    if (n == 0) {
+        release(c, L);
+        return LENS_OK;
+    }
+    const bool solved = L->g.mode == lensk::MODE_FP32N;
+    DeviceGuard dg(c->device);
+    lens_status rs = LENS_OK;
+    {
+        std::lock_guard<std::mutex> lk(c->sync_mu);
+        rs = sync_buffers(c, n);
+        if (rs == LENS_OK) {
+            ScratchLayout S = carve(c->d_sync, (int64_t)c->h_cap, true);
+            memcpy(c->h_params, params, (size_t)n * lensk::kStride * sizeof(double));
+            hipError_t e = hipMemcpyAsync(S.params, c->h_params, (size_t)n * lensk::kStride * sizeof(double),
+                                          hipMemcpyHostToDevice, c->stream);
+            if (e == hipSuccess) e = launch_lens(L, S.params, S.pc, n, S.out, c->stream, solved ? S.amp : nullptr);
+            // staging: out at [0, n), amplitudes at [h_cap, h_cap + 2n) (S.amp = S.out + h_cap)
+            double *h_amp = c->h_out + c->h_cap;
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(c->h_out, S.out, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess && solved)
+                e = hipMemcpyAsync(h_amp, S.amp, (size_t)n * 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) {
+                rs = hip_fail(c, e, "lens_loglike_amps");
+            } else {
+                memcpy(out, c->h_out, (size_t)n * sizeof(double));
+                for (int64_t i = 0; i < n; ++i) {
+                    const bool ok = out[i] != -INFINITY;
+                    if (solved) {
+                        out_amp[2 * i] = ok ? h_amp[2 * i] : NAN;
+                        out_amp[2 * i + 1] = ok ? h_amp[2 * i + 1] : NAN;
+                    } else {
+                        out_amp[2 * i] = ok ? params[i * lensk::kStride + 7] : NAN;
+                        out_amp[2 * i + 1] = ok ? params[i * lensk::kStride + 12] : NAN;
+                    }
+                }
+            }
         }
     }
     release(c, L);
@@ -1269,8 +1337,8 @@ extern "C" lens_status lens_model_image(lens_ctx *c, lens_id id, const double *p
             if (e == hipSuccess) e = lensk::launch_prep(dp, 1, dpc, c->stream);
             if (e == hipSuccess) e = hipMemcpyAsync(&pc, dpc, sizeof(pc), hipMemcpyDeviceToHost, c->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
-            if (e == hipSuccess && pc.valid == 0.0) {
-                rs = fail(c, LENS_EINVAL, "proposal outside the parameter domain");
+            if (e == hipSuccess && pc.valid != 1.0) {
+                rs = fail(c, LENS_EINVAL, "proposal outside the parameter domain (a model image needs finite amplitudes)");
             } else {
                 if (e == hipSuccess) e = lensk::launch_model_image(L->g, dpc, stage, img, tmp, c->stream);
                 if (e == hipSuccess) e = hipMemcpyAsync(hi.data(), img, (size_t)npix * 4, hipMemcpyDeviceToHost, c->stream);
