@@ -76,6 +76,7 @@ class Oracle:
             "oracle_loglike_norm": ([i64, _dp, _u8p], d),
             "oracle_loglike": ([i, i, d, i, i, _dp, _dp, _dp, _u8p, _dp, i64, _dp, _dp, i], i),
             "oracle_loglike_nnls": ([i, i, d, i, i, _dp, _dp, _dp, _u8p, _dp, i64, _dp, _dp, _dp, i], i),
+            "oracle_loglike_light": ([i, i, d, i, i, _dp, _dp, _dp, _u8p, _dp, i64, i, _dp, _dp, _dp, _dp, i], i),
             "oracle_num_threads": ([], i),
         }
         for name, (args, res) in sig.items():
@@ -208,6 +209,38 @@ class Oracle:
                                           int(nthreads))
         if rc != 0:
             raise ValueError("bad argument to oracle_loglike_nnls")
+        res = (out,)
+        if return_chi2:
+            res += (chi2,)
+        if return_amps:
+            res += (amps,)
+        return res if len(res) > 1 else out
+
+    LIGHT_COMPONENTS = {0: 2, 1: 1, 2: 1, 3: 4}
+
+    def loglike_light(self, geom, psf, data, sigma, mask, params, model, nfix=None, nthreads=0,
+                      return_chi2=False, return_amps=False):
+        """lnL of light model ``model`` (0 lens + source, 1 lens only, 2 lensed source only,
+        3 two components per galaxy with fixed indices ``nfix``) with all amplitudes
+        solved by non-negative least squares (Sec. 2.3).  Amplitudes [n, N] in component order."""
+        ny, nx, dpix, s = geom
+        psf = _f64(psf)
+        k = psf.shape[0]
+        data = _f64(data)
+        sigma = _f64(sigma)
+        mask = np.ascontiguousarray(mask, dtype=np.uint8)
+        p = _f64(params).reshape(-1, NPARAM_STRIDE)
+        n = p.shape[0]
+        N = self.LIGHT_COMPONENTS[model]
+        nf = _f64(nfix if nfix is not None else [1.0, 1.0, 1.0, 1.0]).reshape(4)
+        out = np.empty(n, dtype=np.float64)
+        chi2 = np.empty(n, dtype=np.float64)
+        amps = np.empty((n, N), dtype=np.float64)
+        rc = self.lib.oracle_loglike_light(ny, nx, float(dpix), s, k, _ptr(psf), _ptr(data), _ptr(sigma),
+                                           _ptr(mask, _u8p), _ptr(p), n, int(model), _ptr(nf), _ptr(out),
+                                           _ptr(chi2), _ptr(amps), int(nthreads))
+        if rc != 0:
+            raise ValueError("bad argument to oracle_loglike_light")
         res = (out,)
         if return_chi2:
             res += (chi2,)

@@ -18,6 +18,8 @@
  *   - SIE mass = elliptical power law at slope 2                (Sec. 2.4, Eq. 12 and text)
  *   - external shear                                            (Sec. 2.4, Eqs. 13-14)
  *   - light amplitudes by non-negative least squares            (Sec. 2.3)
+ *   - light models with one or two components per galaxy, and lens-only /
+ *     source-only fits                           (Sec. 3.1.2, Sec. 3.2 set-ups)
  *
  * Everything is FP64, scalar loops, libm only, on the full supersampled grid
  * (no skipping outside the mask), with a full-image direct convolution.
@@ -463,6 +465,219 @@ int oracle_loglike_nnls(int ny, int nx, double dpix, int s, int k, const double 
         }
         free(a);
         free(b);
+    }
+    return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Light models with several components, amplitudes solved (Sec. 2.3, and   */
+/* the fitting set-ups of Sec. 3.1.2 and Sec. 3.2)                           */
+/* ------------------------------------------------------------------------ */
+/* Components of the light models (amplitudes are never parameters here):
+ *   model 0 (lens and source): lens Sersic  (R = p[8],  n = p[9],  q = p[10], phi = p[11], centre p[3], p[4])
+ *                              source Sersic (R = p[13], n = p[14], q = p[15], phi = p[16], centre p[17], p[18])
+ *   model 1 (lens light only, no lensing): the lens Sersic above
+ *   model 2 (lensed source only, no lens light): the source Sersic above
+ *   model 3 (two components per galaxy, shared centre and ellipticity, indices
+ *            fixed): lens a (R = p[8], n = nfix[0]), lens b (R = p[9], n = nfix[1]),
+ *            both with q = p[10], phi = p[11], centre p[3], p[4];
+ *            source a (R = p[13], n = nfix[2]), source b (R = p[14], n = nfix[3]),
+ *            both with q = p[15], phi = p[16], centre p[17], p[18].
+ * The mass (slots 0-6) lenses the source components; model 1 ignores it. */
+static int orc_light_count(int model)
+{
+    return model == 0 ? 2 : model == 1 || model == 2 ? 1 : model == 3 ? 4 : 0;
+}
+
+/* domain of the slots a light model reads */
+static int orc_light_valid(const double *p, int model, const double *nfix)
+{
+    int mass = model != 1, lens = model != 2, src = model != 1;
+    if (mass) {
+        for (int i = 0; i < 7; ++i)
+            if (!isfinite(p[i])) return 0;
+        if (p[0] < 0.0 || !(p[1] > 0.0 && p[1] <= 1.0)) return 0;
+    }
+    if (lens) {
+        for (int i = 8; i < 12; ++i)
+            if (!isfinite(p[i])) return 0;
+        if (!isfinite(p[3]) || !isfinite(p[4]) || !(p[10] > 0.0 && p[10] <= 1.0) || !(p[8] > 0.0)) return 0;
+        if (model == 3 ? !(p[9] > 0.0) : !(p[9] >= ORC_N_MIN && p[9] <= ORC_N_MAX)) return 0;
+    }
+    if (src) {
+        for (int i = 13; i < 19; ++i)
+            if (!isfinite(p[i])) return 0;
+        if (!(p[15] > 0.0 && p[15] <= 1.0) || !(p[13] > 0.0)) return 0;
+        if (model == 3 ? !(p[14] > 0.0) : !(p[14] >= ORC_N_MIN && p[14] <= ORC_N_MAX)) return 0;
+    }
+    if (model == 3)
+        for (int j = 0; j < 4; ++j)
+            if (!(nfix[j] >= ORC_N_MIN && nfix[j] <= ORC_N_MAX)) return 0;
+    return 1;
+}
+
+/* unit-amplitude surface brightness of component c of a light model at (x, y) */
+static double orc_component(const double *p, int model, const double *nfix, const double *bn, int c,
+                            double x, double y)
+{
+    int lens_side = model == 1 || (model == 0 && c == 0) || (model == 3 && c < 2);
+    if (lens_side) {
+        double R = (model == 3 && c == 1) ? p[9] : p[8];
+        double n = model == 3 ? nfix[c] : p[9];
+        return oracle_sersic(1.0, R, n, bn[c], p[10], p[11], p[3], p[4], x, y);
+    }
+    double ax, ay;
+    oracle_deflection(p, x, y, &ax, &ay);
+    double bx = x - ax, by = y - ay;                                       /* Eq. 1 */
+    double R = (model == 3 && c == 3) ? p[14] : p[13];
+    double n = model == 3 ? nfix[c] : p[14];
+    return oracle_sersic(1.0, R, n, bn[c], p[15], p[16], p[17], p[18], bx, by);
+}
+
+/* Solve the m x m symmetric system A x = b (row-major, m <= 4) by Gaussian
+ * elimination with partial pivoting; returns 0 if A is singular (a pivot
+ * below 1e-13 of the largest diagonal entry). */
+static int orc_solve(int m, double *A, double *b, double *x)
+{
+    double dmax = 0.0;
+    for (int i = 0; i < m; ++i) dmax = fmax(dmax, fabs(A[i * m + i]));
+    if (!(dmax > 0.0)) return 0;
+    for (int col = 0; col < m; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < m; ++r)
+            if (fabs(A[r * m + col]) > fabs(A[piv * m + col])) piv = r;
+        if (!(fabs(A[piv * m + col]) > 1e-13 * dmax)) return 0;
+        if (piv != col) {
+            for (int c = 0; c < m; ++c) {
+                double t = A[col * m + c]; A[col * m + c] = A[piv * m + c]; A[piv * m + c] = t;
+            }
+            double t = b[col]; b[col] = b[piv]; b[piv] = t;
+        }
+        for (int r = col + 1; r < m; ++r) {
+            double f = A[r * m + col] / A[col * m + col];
+            for (int c = col; c < m; ++c) A[r * m + c] -= f * A[col * m + c];
+            b[r] -= f * b[col];
+        }
+    }
+    for (int r = m - 1; r >= 0; --r) {
+        double acc = b[r];
+        for (int c = r + 1; c < m; ++c) acc -= A[r * m + c] * x[c];
+        x[r] = acc / A[r * m + r];
+    }
+    return 1;
+}
+
+/* lnL of a light model with its amplitudes solved by non-negative least
+ * squares (Sec. 2.3), for any of the models above: the columns of M are the
+ * components at unit amplitude, binned and PSF-convolved; the NNLS minimiser
+ * is the least-squares solution, on one of the 2^N supports, that is >= 0
+ * and has the smallest chi^2 (computed by a direct pass over the residuals).
+ * nfix: the four fixed Sersic indices of model 3 (ignored otherwise).
+ * out_amp: [n][N] amplitudes in component order (may be NULL).  Proposals
+ * outside the model's domain give lnL = -inf and NaN amplitudes. */
+int oracle_loglike_light(int ny, int nx, double dpix, int s, int k, const double *psf,
+                         const double *data, const double *sigma, const uint8_t *mask,
+                         const double *params, int64_t n, int model, const double *nfix,
+                         double *out, double *out_chi2, double *out_amp, int nthreads)
+{
+    int N = orc_light_count(model);
+    if (!orc_geom_ok(ny, nx, dpix, s, k) || !psf || !data || !sigma || !mask || N == 0 ||
+        (model == 3 && !nfix) || (n > 0 && (!params || !out)) || n < 0)
+        return -1;
+    int64_t npix = (int64_t)ny * nx;
+    for (int64_t i = 0; i < npix; ++i)
+        if (mask[i] && !(sigma[i] > 0.0 && isfinite(sigma[i]) && isfinite(data[i]))) return -1;
+    double C = oracle_loglike_norm(npix, sigma, mask);
+    int bad = 0;
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#pragma omp parallel num_threads(nthreads) reduction(| : bad)
+#endif
+    {
+        double *col = (double *)malloc(sizeof(double) * (size_t)npix * 4);
+        double *img = (double *)malloc(sizeof(double) * (size_t)npix);
+        if (!col || !img) bad = 1;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int64_t t = 0; t < n; ++t) {
+            if (!col || !img) continue;
+            const double *p = params + t * ORC_NP;
+            if (!orc_light_valid(p, model, nfix)) {
+                out[t] = -INFINITY;
+                if (out_chi2) out_chi2[t] = INFINITY;
+                if (out_amp)
+                    for (int c = 0; c < N; ++c) out_amp[t * N + c] = NAN;
+                continue;
+            }
+            double bn[4];
+            for (int c = 0; c < N; ++c) {
+                int lens_side = model == 1 || (model == 0 && c == 0) || (model == 3 && c < 2);
+                bn[c] = oracle_bn(model == 3 ? nfix[c] : (lens_side ? p[9] : p[14]));
+            }
+            /* columns: each component binned (s x s mean) and convolved */
+            for (int c = 0; c < N; ++c) {
+                for (int i = 0; i < ny; ++i)
+                    for (int j = 0; j < nx; ++j) {
+                        double acc = 0.0;
+                        for (int v = 0; v < s; ++v)
+                            for (int u = 0; u < s; ++u) {
+                                double x, y;
+                                oracle_subpixel_xy(ny, nx, dpix, s, i, j, v, u, &x, &y);
+                                acc += orc_component(p, model, nfix, bn, c, x, y);
+                            }
+                        img[i * nx + j] = acc / ((double)s * s);
+                    }
+                oracle_convolve_same(img, ny, nx, psf, k, col + (size_t)c * npix);
+            }
+            /* normal equations of the weighted problem */
+            double F[16] = {0}, g[4] = {0};
+            for (int64_t i = 0; i < npix; ++i)
+                if (mask[i]) {
+                    double w = 1.0 / (sigma[i] * sigma[i]);
+                    for (int a = 0; a < N; ++a) {
+                        g[a] += w * col[(size_t)a * npix + i] * data[i];
+                        for (int b = 0; b < N; ++b) F[a * N + b] += w * col[(size_t)a * npix + i] * col[(size_t)b * npix + i];
+                    }
+                }
+            double best = INFINITY, bs[4] = {0, 0, 0, 0};
+            for (int S = 0; S < (1 << N); ++S) {
+                int idx[4], m = 0;
+                for (int c = 0; c < N; ++c)
+                    if (S & (1 << c)) idx[m++] = c;
+                double x[4] = {0, 0, 0, 0}, cand[4] = {0, 0, 0, 0};
+                if (m > 0) {
+                    double A[16], b[4];
+                    for (int a = 0; a < m; ++a) {
+                        b[a] = g[idx[a]];
+                        for (int c = 0; c < m; ++c) A[a * m + c] = F[idx[a] * N + idx[c]];
+                    }
+                    if (!orc_solve(m, A, b, x)) continue;
+                    int feasible = 1;
+                    for (int a = 0; a < m; ++a) feasible = feasible && x[a] >= 0.0;
+                    if (!feasible) continue;
+                    for (int a = 0; a < m; ++a) cand[idx[a]] = x[a];
+                }
+                double chi2 = 0.0;
+                for (int64_t i = 0; i < npix; ++i)
+                    if (mask[i]) {
+                        double mval = 0.0;
+                        for (int c = 0; c < N; ++c) mval += cand[c] * col[(size_t)c * npix + i];
+                        double r = (data[i] - mval) / sigma[i];
+                        chi2 += r * r;
+                    }
+                if (chi2 < best) {
+                    best = chi2;
+                    for (int c = 0; c < N; ++c) bs[c] = cand[c];
+                }
+            }
+            out[t] = C - 0.5 * best;
+            if (out_chi2) out_chi2[t] = best;
+            if (out_amp)
+                for (int c = 0; c < N; ++c) out_amp[t * N + c] = bs[c];
+        }
+        free(col);
+        free(img);
     }
     return bad ? -1 : 0;
 }

@@ -561,4 +561,102 @@ def pin_nnls_domain(orc):
     assert np.all(out == -np.inf) and np.all(np.isnan(amps))
 
 
+# ----------------------------------------------------------------------------
+# Light models: two components per galaxy (Sec. 3.2 set-up), lens-only and
+# source-only fits (Sec. 3.1.2), all amplitudes solved by NNLS (Sec. 2.3)
+# ----------------------------------------------------------------------------
+NFIX = (1.0, 4.0, 1.0, 4.0)
+
+
+def _light_columns(orc, g, psf, p, model):
+    """Unit-amplitude columns of a light model, each rendered by the one-component oracle path."""
+    def img(**kw):
+        return orc.model_image(g[0], g[1], g[2], g[3], psf, _with(p, **kw), stage=1)
+    lens0 = dict(I_s=0.0, I_l=1.0)
+    src0 = dict(I_l=0.0, I_s=1.0)
+    if model == 0:
+        return [img(**lens0), img(**src0)]
+    if model == 1:
+        return [img(theta_E=0.0, g1=0.0, g2=0.0, **lens0)]
+    if model == 2:
+        return [img(**src0)]
+    S = synth.SLOT
+    # the n slots hold radii in model 3; each rendering puts valid indices in both
+    return [img(R_l=p[S["R_l"]], n_l=NFIX[0], n_s=1.0, **lens0), img(R_l=p[S["n_l"]], n_l=NFIX[1], n_s=1.0, **lens0),
+            img(R_s=p[S["R_s"]], n_s=NFIX[2], n_l=1.0, **src0), img(R_s=p[S["n_s"]], n_s=NFIX[3], n_l=1.0, **src0)]
+
+
+def _double(**kw):
+    """A model-3 proposal: slot n_l holds R of the lens's second component, n_s the source's."""
+    base = dict(R_l=0.4, n_l=1.1, R_s=0.15, n_s=0.5)
+    base.update(kw)
+    return _p(**base)
+
+
+def pin_light_model0_is_the_two_column_nnls(orc):
+    rng, psf, sigma, mask, truth, g = _small_case(seed=31)
+    data = orc.model_image(g[0], g[1], g[2], g[3], psf, truth, stage=1) + rng.normal(size=sigma.shape) * sigma
+    props = synth.draw_params(rng, 5)
+    l0, a0 = orc.loglike_light(g, psf, data, sigma, mask, props, 0, return_amps=True)
+    l1, a1 = orc.loglike_nnls(g, psf, data, sigma, mask, props, return_amps=True)
+    assert np.allclose(l0, l1, rtol=1e-12, atol=0) and np.allclose(a0, a1, rtol=1e-9, atol=1e-15)
+
+
+def pin_light_models_scipy(orc):
+    # each model against scipy's Lawson-Hanson NNLS on columns rendered one component at a time
+    rng, psf, sigma, mask, truth, g = _small_case(seed=32)
+    sel = mask == 1
+    for model, props in ((1, [truth, _p(R_l=0.3, n_l=3.0)]), (2, [truth, _p(R_s=0.4, x_s=0.3)]),
+                         (3, [_double(), _double(R_l=0.9, n_l=0.2, R_s=0.3, n_s=0.08)])):
+        cols = _light_columns(orc, g, psf, props[0], model)
+        truth_amp = rng.uniform(0.1, 0.5, len(cols))
+        truth_amp[-1] = -0.05 if model == 3 else truth_amp[-1]      # one negative: NNLS clips it
+        data = sum(a * c for a, c in zip(truth_amp, cols)) + rng.normal(size=sigma.shape) * sigma
+        lnl, chi2, amps = orc.loglike_light(g, psf, data, sigma, mask, np.stack(props), model, nfix=NFIX,
+                                            return_chi2=True, return_amps=True)
+        for t, p in enumerate(props):
+            cols = _light_columns(orc, g, psf, p, model)
+            A = np.stack([c[sel] / sigma[sel] for c in cols], axis=1)
+            x, rnorm = scipy.optimize.nnls(A, data[sel] / sigma[sel])
+            assert np.allclose(amps[t], x, rtol=1e-7, atol=1e-10), (model, t, amps[t], x)
+            assert abs(chi2[t] - rnorm ** 2) <= 1e-9 * rnorm ** 2, (model, t, chi2[t], rnorm ** 2)
+
+
+def pin_light_models_ignore_unused_slots(orc):
+    rng, psf, sigma, mask, truth, g = _small_case(seed=33)
+    data = orc.model_image(g[0], g[1], g[2], g[3], psf, truth, stage=1)
+    base = orc.loglike_light(g, psf, data, sigma, mask, truth[None], 1)[0]
+    # lens-only: the mass, the shear and the source do not matter (even out of their domain)
+    other = _with(truth, theta_E=-3.0, q_m=0.0, g1=float("nan"), R_s=-1.0, x_s=7.0, I_l=float("inf"))
+    assert orc.loglike_light(g, psf, data, sigma, mask, other[None], 1)[0] == base
+    # source-only: the lens light does not matter
+    b2 = orc.loglike_light(g, psf, data, sigma, mask, truth[None], 2)[0]
+    other = _with(truth, R_l=-1.0, n_l=99.0, q_l=7.0, phi_l=float("nan"))
+    assert orc.loglike_light(g, psf, data, sigma, mask, other[None], 2)[0] == b2
+    # but a source-only fit does depend on the mass
+    assert orc.loglike_light(g, psf, data, sigma, mask, _with(truth, theta_E=0.5)[None], 2)[0] != b2
+
+
+def pin_light_model3_recovers_amplitudes(orc):
+    rng, psf, sigma, mask, truth, g = _small_case(seed=34)
+    p = _double()
+    cols = _light_columns(orc, g, psf, p, 3)
+    amp = np.array([0.2, 0.35, 0.15, 0.4])
+    data = sum(a * c for a, c in zip(amp, cols))
+    lnl, chi2, got = orc.loglike_light(g, psf, data, sigma, mask, p[None], 3, nfix=NFIX, return_chi2=True,
+                                       return_amps=True)
+    assert np.allclose(got[0], amp, rtol=1e-8), got
+    assert chi2[0] < 1e-12 * np.sum((data / sigma)[mask == 1] ** 2)
+
+
+def pin_light_model_domain(orc):
+    rng, psf, sigma, mask, truth, g = _small_case(seed=35)
+    data = orc.model_image(g[0], g[1], g[2], g[3], psf, truth, stage=1)
+    out, amps = orc.loglike_light(g, psf, data, sigma, mask, np.stack([_double(n_l=0.0), _double(q_s=0.0)]), 3,
+                                  nfix=NFIX, return_amps=True)
+    assert np.all(out == -np.inf) and np.all(np.isnan(amps))
+    out = orc.loglike_light(g, psf, data, sigma, mask, _double()[None], 3, nfix=(1.0, 4.0, 1.0, 25.0))
+    assert out[0] == -np.inf
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

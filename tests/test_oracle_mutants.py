@@ -44,6 +44,16 @@ MUTANTS = {
     "nnls_first_feasible": [("if (chi2 < best) {", "if (best == INFINITY) {")],
     "nnls_amps_swapped": [("out_amp[2 * t] = bl;", "out_amp[2 * t] = bs;"),
                           ("out_amp[2 * t + 1] = bs;", "out_amp[2 * t + 1] = bl;")],
+    "light_lens_b_radius": [("double R = (model == 3 && c == 1) ? p[9] : p[8];", "double R = p[8];")],
+    "light_source_b_index": [("double n = model == 3 ? nfix[c] : p[14];", "double n = model == 3 ? nfix[2] : p[14];")],
+    "light_source_unlensed": [("    double bx = x - ax, by = y - ay;                                       /* Eq. 1 */\n    double R = (model == 3",
+                               "    double bx = x, by = y;\n    double R = (model == 3")],
+    "light_solve_back_substitution": [("for (int c = r + 1; c < m; ++c) acc -= A[r * m + c] * x[c];",
+                                       "for (int c = r + 1; c < m; ++c) acc += A[r * m + c] * x[c];")],
+    "light_chi2_drops_component": [("for (int c = 0; c < N; ++c) mval += cand[c] * col[(size_t)c * npix + i];",
+                                    "for (int c = 1; c < N; ++c) mval += cand[c] * col[(size_t)c * npix + i];")],
+    "light_mass_in_lens_only": [("int mass = model != 1, lens = model != 2, src = model != 1;",
+                                 "int mass = 1, lens = model != 2, src = model != 1;")],
     "lens_light_not_supersampled": [("acc += orc_scene(p, bl, bs, x, y);",
                                      "acc += orc_scene(p, bl, bs, x, y) - oracle_sersic(p[7], p[8], p[9], bl, p[10], p[11], p[3], p[4], x, y) + oracle_sersic(p[7], p[8], p[9], bl, p[10], p[11], p[3], p[4], ((double)j - 0.5 * (nx - 1)) * dpix, ((double)i - 0.5 * (ny - 1)) * dpix);")],
 }
