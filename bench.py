@@ -34,6 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "loglike evals/s at ≤1e-6 rel err, batched vs plain; p50/p99 req latency"
 PEAK_SLOT_PER_S = 256 * 4 * 16 * 2.4e9        # FP32 VALU lane-slots/s (non-packed)
 SLOTS_PER_EVAL = 60 + 4 * 10                    # 60 FMA-class ops + 10 quarter-rate transcendentals
+DOUBLE_N = (1.0, 4.0, 1.0, 4.0)                 # fixed indices of the two-component model: disc and bulge
 
 
 def parse():
@@ -51,11 +52,22 @@ def parse():
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--amplitudes", default="explicit", choices=["explicit", "nnls"],
                     help="light amplitudes as parameters, or solved by NNLS (Sec. 2.3; FP32 convolution)")
+    ap.add_argument("--light-model", default="both", choices=list(LIGHT),
+                    help="light model (solved amplitudes): lens and source, lens light only, lensed source "
+                         "only, or two components per galaxy with indices 1 and 4 (implies --amplitudes nnls)")
     ap.add_argument("--requests", type=int, default=300, help="serving: requests per offered load")
     return ap.parse_args()
 
 
 PREC = {"fp32": 0, "split": 1, "bf16": 2, "split3": 3}
+LIGHT = {"both": 0, "lens": 1, "source": 2, "double": 3}
+# credited lane-slots per sub-pixel evaluation of each light model: the ray trace
+# (grid, SIE, shear, lens equation: ~34 FMA-class ops + 4 transcendentals = 50),
+# a Sersic component (~12 FMA + 3 transcendentals = 25 with its elliptical
+# radius), and a second component sharing that radius (~5 FMA + 2
+# transcendentals = 13)
+SLOTS_BY_MODEL = {0: 50 + 2 * 25, 1: 25, 2: 50 + 25, 3: 50 + 2 * (25 + 13)}
+CHANNELS = {0: 2, 1: 1, 2: 1, 3: 4}
 
 
 def gpu_data(ctx, spec):
@@ -71,24 +83,43 @@ def path_dtype(prec):
     return "f64+f32" if prec in (None, "fp32") else "f64+bf16"
 
 
-def credited_slots(spec, info, nnls=False):
+def credited_slots(spec, info, nnls=False, model=0):
     """Credited VALU work of one proposal (60 FMA-class + 10 transcendentals per sub-pixel
     evaluation, one FMA per PSF tap at each masked pixel, one FP64 FMA per masked pixel).
     The PSF is the kernel the library convolves with after its tail crop (info["psf_used"]),
     and the sub-pixels are those of the mask dilated by that kernel (info["needed_pixels"]).
-    Solved amplitudes (nnls) convolve two channels and take five FP64 moments per masked pixel."""
+    Solved amplitudes (nnls) convolve one channel per light component (N) and take
+    N(N+1)/2 + N FP64 moments per masked pixel; the per-evaluation credit follows the
+    light model (SLOTS_BY_MODEL)."""
     M, k = info["masked_pixels"], info["psf_used"]
     E = info["needed_pixels"] * spec.s * spec.s
     if nnls:
-        return E * SLOTS_PER_EVAL + 2 * M * k * k + 5 * M, E
+        N = CHANNELS[model]
+        return E * SLOTS_BY_MODEL[model] + N * M * k * k + (N * (N + 1) // 2 + N) * M, E
     return E * SLOTS_PER_EVAL + M * k * k + M, E
 
 
-def oracle_sample(specs_props, nthreads=0, nnls=False):
+def oracle_fn(nnls=False, model=0):
+    """The oracle's lnL of the chosen amplitude mode and light model, as
+    f(geom, psf, data, sigma, mask, P, nthreads=0, return_chi2=False)."""
+    import oracle
+    orc = oracle.default()
+    if not nnls:
+        return orc.loglike
+    if model == 0:
+        return orc.loglike_nnls
+
+    def f(geom, psf, data, sigma, mask, P, nthreads=0, return_chi2=False):
+        return orc.loglike_light(geom, psf, data, sigma, mask, P, model, nfix=DOUBLE_N, nthreads=nthreads,
+                                 return_chi2=return_chi2)
+    return f
+
+
+def oracle_sample(specs_props, nthreads=0, nnls=False, model=0):
     """Times the oracle over (spec, proposals) pairs; returns (lnL list, chi2 list, C list, seconds)."""
     import oracle
     orc = oracle.default()
-    fn = orc.loglike_nnls if nnls else orc.loglike
+    fn = oracle_fn(nnls, model)
     out = []
     t0 = time.perf_counter()
     for spec, P in specs_props:
@@ -150,8 +181,11 @@ def main():
     ctx = binding.LensContext(0, autotune=args.autotune)
     gpu_data(ctx, spec)
     prec = PREC[args.precision or "fp32"]
-    nnls = args.amplitudes == "nnls"
-    lid = ctx.load(spec, precision=prec, amplitudes=1 if nnls else 0)
+    model = LIGHT[args.light_model]
+    nnls = args.amplitudes == "nnls" or model != 0
+    if model == 3:
+        spec.proposals = synth.double_component_params(synth.rng_for_config(2), spec.proposals)
+    lid = ctx.load(spec, precision=prec, amplitudes=1 if nnls else 0, light_model=model, sersic_n=DOUBLE_N)
     info = ctx.info(lid)
 
     dev = torch.device("cuda", 0)
@@ -185,9 +219,9 @@ def main():
     assert np.array_equal(host_out, gpu_out)
 
     # roofline: credited algorithmic VALU work of one launch
-    slots_per_prop, E = credited_slots(spec, info, nnls)
+    slots_per_prop, E = credited_slots(spec, info, nnls, model)
     achieved = slots_per_prop * n / (kern_ms * 1e-3)
-    kname = ("k_loglike_nnls<%d>" % info["threads"] if nnls else
+    kname = ("k_loglike_nnls<%d,%d>" % (4 + model, info["threads"]) if nnls else
              "k_loglike_fp32<%d,%d>" % (info["psf_used"], info["threads"]) if prec == 0 else
              "k_loglike_mfma<%d,%d>" % (prec, info["threads"]))
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOT_PER_S / 1e12,
@@ -204,7 +238,7 @@ def main():
         threads = orc.num_threads()
         # calibrate on a few proposals, then size the sample for ~cpu_seconds
         probe = spec.proposals[:threads]
-        ofn = orc.loglike_nnls if nnls else orc.loglike
+        ofn = oracle_fn(nnls, model)
         tc0 = time.perf_counter()
         ofn(spec.geom, spec.psf, spec.data, spec.sigma, spec.mask, probe)
         per = (time.perf_counter() - tc0) / len(probe)
@@ -234,8 +268,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "plain survey scale: 1 lens, 128x128 px at 0.05\"/px, 4x4 supersampling, "
                                "21x21 Gaussian PSF FWHM 0.1\", r=3\" mask, %d proposals per call, "
-                               "FP64 ray trace, %s PSF convolution, FP64 chi2, %s amplitudes"
-                               % (n, args.precision or "fp32", "NNLS-solved" if nnls else "explicit"),
+                               "FP64 ray trace, %s PSF convolution, FP64 chi2, %s amplitudes%s"
+                               % (n, args.precision or "fp32", "NNLS-solved" if nnls else "explicit",
+                                  "" if model == 0 else ", light model: " + args.light_model),
                    "path": "lens_loglike_batch_device", "proposals_per_call": n,
                    "subpixel_evals_per_s": value * E},
         "roofline": roofline,
@@ -258,15 +293,19 @@ def run_batch(args):
 
     from paper_2503_08586_amd import binding, synth
     prec = PREC[args.precision or "fp32"]
-    nnls = args.amplitudes == "nnls"
+    model = LIGHT[args.light_model]
+    nnls = args.amplitudes == "nnls" or model != 0
     specs = synth.config3()
     ctx, st = _stream_ctx(binding, torch, autotune=args.autotune)
     lids, slots, evs = [], 0.0, 0
+    drng = synth.rng_for_config(3)
     for sp in specs:
         gpu_data(ctx, sp)
-        lid = ctx.load(sp, precision=prec, amplitudes=1 if nnls else 0)
+        if model == 3:
+            sp.proposals = synth.double_component_params(drng, sp.proposals)
+        lid = ctx.load(sp, precision=prec, amplitudes=1 if nnls else 0, light_model=model, sersic_n=DOUBLE_N)
         lids.append(lid)
-        sl, E = credited_slots(sp, ctx.info(lid), nnls)
+        sl, E = credited_slots(sp, ctx.info(lid), nnls, model)
         slots += sl * sp.proposals.shape[0]
         evs += E * sp.proposals.shape[0]
     plist = [sp.proposals for sp in specs]
@@ -290,7 +329,7 @@ def run_batch(args):
     plain_s = time.perf_counter() - t0
     same = all(np.array_equal(a, b) for a, b in zip(outs, singles))
     sample = [(specs[j], specs[j].proposals[:2]) for j in range(0, len(specs), 8)]
-    res, tc, threads = oracle_sample(sample, nnls=nnls)
+    res, tc, threads = oracle_sample(sample, nnls=nnls, model=model)
     errs = [rel_errors(outs[j][:2], r[0], r[1], r[2]).max() for (j, r) in zip(range(0, len(specs), 8), res)]
     rec = {
         "metric": METRIC, "value": n / step_s, "unit": "loglike evals/s", "n_gpus": 1,
@@ -298,8 +337,9 @@ def run_batch(args):
         "scaling": "weak", "vs_baseline": None, "dtype": path_dtype(args.precision), "data": "synthetic",
         "config": {"workload": "batching: 256 lenses, N~U{48..160}, 0.05-0.074\"/px, s in {2,4}, k in 11..31, "
                                "%d proposals (U{128..4096} per lens), one persistent launch in a hipGraph, "
-                               "host buffers, %s PSF convolution, %s amplitudes"
-                               % (n, args.precision or "fp32", "NNLS-solved" if nnls else "explicit"),
+                               "host buffers, %s PSF convolution, %s amplitudes%s"
+                               % (n, args.precision or "fp32", "NNLS-solved" if nnls else "explicit",
+                                  "" if model == 0 else ", light model: " + args.light_model),
                    "proposals_per_call": n, "autotune": bool(args.autotune)},
         "plain_one_lens_at_a_time_evals_per_s": n / plain_s,
         "batched_over_plain": plain_s / step_s,

@@ -12,8 +12,9 @@
  *   - lnL = sum over the fitting region of ln N(d_i; I_i, sigma_i)  (Sec. 2.2, Eq. 5)
  *   - SIE mass (the elliptical power law at slope 2) + external shear (Sec. 2.4, Eqs. 12-14)
  *   - elliptical Sersic light for lens and source                 (Sec. 2.4, Eqs. 8-10)
- * The light amplitudes are explicit parameters here; the paper's linear
- * (NNLS) amplitude solve of Sec. 2.3 is not part of this call.
+ * The light amplitudes are explicit parameters by default, or solved by
+ * non-negative least squares per proposal (Sec. 2.3, LENS_AMP_NNLS), which
+ * also admits the light models of Sec. 3.1.2 and 3.2 (LENS_LIGHT_*).
  *
  * Conventions (each is a reading of a passage the paper leaves open):
  *   - SIE convergence kappa = theta_E / (2 R_p), R_p = sqrt(q x1^2 + x2^2/q)
@@ -89,6 +90,18 @@ typedef int32_t lens_status;
                                      PSF-convolved; lnL is taken there and slots 7, 12 are ignored.
                                      Needs LENS_PREC_FP32. */
 
+/* Light models, chosen per lens at load; all but LENS_LIGHT_BOTH need
+ * LENS_AMP_NNLS.  Each model reads, and validates, only the slots it uses. */
+#define LENS_LIGHT_BOTH 0         /* one lens-light and one lensed source Sersic (default) */
+#define LENS_LIGHT_LENS 1         /* lens light only, no lensing (the galaxy fits of Sec. 3.1.2):
+                                     slots 3, 4 (centre) and 8-11 */
+#define LENS_LIGHT_SOURCE 2       /* lensed source only, no lens light: slots 0-6 and 13-18 */
+#define LENS_LIGHT_DOUBLE 3       /* two Sersic components per galaxy (Sec. 3.2), each pair sharing
+                                     centre, q and phi, with indices fixed per lens (sersic_n):
+                                     slot 8 is R_e of the lens's first component and slot 9 that of
+                                     its second; slots 13 and 14 likewise for the source.  Four
+                                     amplitudes in the order lens a, lens b, source a, source b */
+
 typedef struct lens_ctx lens_ctx;
 typedef int64_t lens_id;
 typedef int64_t lens_req;
@@ -131,6 +144,9 @@ typedef struct lens_data_desc {
                                    moves any convolved pixel by at most psf_tail * sum|K| * max|binned|.
                                    0: the default 2^-48 (2^-24 below the FP32 resolution of the
                                    brightest pixel); < 0: keep the full k x k kernel */
+    int32_t light_model;        /* LENS_LIGHT_* (0: lens and source) */
+    double sersic_n[4];         /* LENS_LIGHT_DOUBLE: fixed Sersic indices of lens a, lens b, source a,
+                                   source b, each in [0.1, 20] (Sec. 3.2 uses 1, 4, 1, 4); else ignored */
 } lens_data_desc;
 
 typedef struct lens_info {
@@ -144,6 +160,9 @@ typedef struct lens_info {
     int64_t lds_bytes;          /* dynamic LDS of one workgroup (the binned-row ring) */
     int32_t blocks_per_cu;      /* resident workgroups per compute unit at that shape */
     int32_t psf_used;           /* side of the PSF kernel after the tail crop (psf_tail) */
+    int32_t amplitudes;         /* LENS_AMP_* */
+    int32_t light_model;        /* LENS_LIGHT_* */
+    int32_t n_amplitudes;       /* amplitudes per proposal of lens_loglike_amps: 2, 1, 1 or 4 */
 } lens_info;
 
 typedef struct lens_stats {
@@ -186,8 +205,10 @@ lens_status lens_get_info(lens_ctx *ctx, lens_id id, lens_info *out);
 lens_status lens_loglike_batch(lens_ctx *ctx, lens_id id, const double *params, int64_t n,
                                double *out_loglike);
 
-/* lnL and the amplitudes it was taken at (host buffers, out_amp [n][2]:
- * s_l, s_s).  For a LENS_AMP_NNLS lens these are the solved amplitudes; for an
+/* lnL and the amplitudes it was taken at (host buffers, out_amp [n][N] with
+ * N = lens_info.n_amplitudes, in component order: lens light, source; lens
+ * only; source only; lens a, lens b, source a, source b).  For a
+ * LENS_AMP_NNLS lens these are the solved amplitudes; for an
  * explicit-amplitude lens, the proposal's slots 7 and 12.  Proposals outside
  * the domain give lnL = -inf and NaN amplitudes.  Blocks like
  * lens_loglike_batch. */
@@ -233,7 +254,9 @@ lens_status lens_get_stats(lens_ctx *ctx, lens_stats *out);
 
 /* Debug/test: the model image of one proposal (params1: 20 doubles) into
  * out_img [ny][nx]: stage 0 binned and unconvolved, stage 1 PSF-convolved.
- * A proposal outside the domain gives LENS_EINVAL. */
+ * The image is always that of the lens and source model with the explicit
+ * amplitudes of slots 7 and 12, whatever the lens's light model and
+ * amplitude mode.  A proposal outside that model's domain gives LENS_EINVAL. */
 lens_status lens_model_image(lens_ctx *ctx, lens_id id, const double *params1, int32_t stage,
                              double *out_img);
 

@@ -42,6 +42,11 @@ LENS_PREC_BF16_SPLIT3 = 3
 LENS_AMP_EXPLICIT = 0
 LENS_AMP_NNLS = 1
 
+LENS_LIGHT_BOTH = 0
+LENS_LIGHT_LENS = 1
+LENS_LIGHT_SOURCE = 2
+LENS_LIGHT_DOUBLE = 3
+
 EXPORTED = [
     "lens_init", "lens_shutdown", "lens_load_data", "lens_unload", "lens_get_info",
     "lens_loglike_batch", "lens_loglike_amps", "lens_loglike_batch_device", "lens_loglike_multi",
@@ -81,6 +86,8 @@ class lens_data_desc(ctypes.Structure):
         ("precision", ctypes.c_int32),
         ("amplitudes", ctypes.c_int32),
         ("psf_tail", ctypes.c_double),
+        ("light_model", ctypes.c_int32),
+        ("sersic_n", ctypes.c_double * 4),
     ]
 
 
@@ -92,6 +99,7 @@ class lens_info(ctypes.Structure):
         ("device_bytes", ctypes.c_int64), ("norm", ctypes.c_double),
         ("strip_rows", ctypes.c_int32), ("threads", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
         ("blocks_per_cu", ctypes.c_int32), ("psf_used", ctypes.c_int32),
+        ("amplitudes", ctypes.c_int32), ("light_model", ctypes.c_int32), ("n_amplitudes", ctypes.c_int32),
     ]
 
 
@@ -234,7 +242,8 @@ def lens_shutdown(ctx):
 
 
 def lens_load_data(ctx, ny, nx, pixel_scale, supersample, psf, data, sigma, mask,
-                   precision=LENS_PREC_FP32, psf_tail=0.0, amplitudes=0) -> int:
+                   precision=LENS_PREC_FP32, psf_tail=0.0, amplitudes=0, light_model=0,
+                   sersic_n=(1.0, 1.0, 1.0, 1.0)) -> int:
     psf = np.ascontiguousarray(psf, dtype=np.float64)
     data = np.ascontiguousarray(data, dtype=np.float64)
     sigma = np.ascontiguousarray(sigma, dtype=np.float64)
@@ -249,6 +258,11 @@ def lens_load_data(ctx, ny, nx, pixel_scale, supersample, psf, data, sigma, mask
     d.precision = precision
     d.psf_tail = psf_tail
     d.amplitudes = amplitudes
+    d.light_model = light_model
+    sn = [float(v) for v in sersic_n]
+    if len(sn) != 4:
+        raise ValueError("sersic_n holds four indices")
+    d.sersic_n[:] = sn
     lid = ctypes.c_int64()
     _check(ctx, load().lens_load_data(ctx, ctypes.byref(d), ctypes.byref(lid)))
     return lid.value
@@ -266,10 +280,13 @@ def lens_psf_crop(psf, psf_tail=0.0) -> int:
 
 
 def lens_loglike_amps(ctx, lens_id, params):
-    """(lnL [n], amplitudes [n, 2]) of every proposal row (host buffers)."""
+    """(lnL [n], amplitudes [n, N]) of every proposal row (host buffers); N is the
+    lens's ``n_amplitudes``."""
     p = _params(params)
+    info = lens_info()
+    _check(ctx, load().lens_get_info(ctx, lens_id, ctypes.byref(info)))
     out = np.empty(p.shape[0], dtype=np.float64)
-    amp = np.empty((p.shape[0], 2), dtype=np.float64)
+    amp = np.empty((p.shape[0], info.n_amplitudes), dtype=np.float64)
     _check(ctx, load().lens_loglike_amps(ctx, lens_id, _dptr(p), p.shape[0], _dptr(out), _dptr(amp)))
     return out, amp
 
@@ -395,11 +412,12 @@ class LensContext:
     def __exit__(self, *a):
         self.close()
 
-    def load(self, spec, precision=LENS_PREC_FP32, data=None, psf_tail=0.0, amplitudes=0) -> int:
+    def load(self, spec, precision=LENS_PREC_FP32, data=None, psf_tail=0.0, amplitudes=0, light_model=0,
+             sersic_n=(1.0, 1.0, 1.0, 1.0)) -> int:
         """Load a synth.LensSpec (its data, or ``data`` if given)."""
         d = spec.data if data is None else data
         lid = lens_load_data(self.ctx, spec.ny, spec.nx, spec.dpix, spec.s, spec.psf, d, spec.sigma,
-                             spec.mask, precision, psf_tail, amplitudes)
+                             spec.mask, precision, psf_tail, amplitudes, light_model, sersic_n)
         self.geom[lid] = (spec.ny, spec.nx)
         return lid
 
@@ -413,7 +431,7 @@ class LensContext:
         self.geom.pop(lid, None)
 
     def loglike_amps(self, lid, params):
-        """(lnL, amplitudes [n, 2]) at the solved (LENS_AMP_NNLS) or given amplitudes."""
+        """(lnL, amplitudes [n, N]) at the solved (LENS_AMP_NNLS) or given amplitudes."""
         return lens_loglike_amps(self.ctx, lid, params)
 
     def loglike(self, lid, params) -> np.ndarray:

@@ -141,11 +141,21 @@ __device__ __forceinline__ double sie_a2(double u2, double ce, double bsie, doub
 // exponent below stays finite; B (1 - t) >= -2000 keeps the last exponent in
 // int range (2^-2000 is 0 in FP64).
 // lead: the leading coefficient of kExp2_64 (see horner).
+__device__ __forceinline__ float log2_r2(double r2)
+{
+    return __builtin_amdgcn_fmed3f(hw_log2((float)r2), -2048.0f, 128.0f);
+}
+
+// 2^(B (1 - t)) with t = 2^(e lgd), lgd = log2 of (R/R_e)^2 (clamped as above)
+__device__ __forceinline__ double sersic_lg(double lgd, double e, double B, double lead)
+{
+    const double t = exp2_64(kExp2_64, e * lgd, lead);
+    return exp2_64(kExp2_64, fmax(fma(-B, t, B), -2000.0), lead);
+}
+
 __device__ __forceinline__ double sersic_r2(double r2, const LightK &L, double lead)
 {
-    const float lg = __builtin_amdgcn_fmed3f(hw_log2((float)r2), -2048.0f, 128.0f);
-    const double t = exp2_64(kExp2_64, L.e * (double)lg, lead);
-    return exp2_64(kExp2_64, fmax(fma(-L.B, t, L.B), -2000.0), lead);
+    return sersic_lg((double)log2_r2(r2), L.e, L.B, lead);
 }
 
 // (R/R_e)^2 = P dx^2 + Q dy^2 + S dx dy at offset (dx, dy) from a light centre,
@@ -183,9 +193,22 @@ __device__ __forceinline__ void ray_trace(double x1, double x2, double lx, doubl
 // constants: the mass-frame coordinates, theta - alpha_shear - source centre,
 // and the lens light's (R/R_e)^2 (a quadratic in dx).  Lens and source light
 // are summed apart (al, as: sums over the sub-pixels at unit amplitude).
-__device__ __forceinline__ void binned_sums(const LensGeom &g, const PropBlock &P, int y, int x, double &al_out,
-                                            double &as_out)
+template <int LM>
+struct LightChannels {
+    static constexpr int N = LM == LIGHT_BOTH ? 2 : LM == LIGHT_DOUBLE ? 4 : 1;
+};
+
+// Sub-pixel sums of pixel (y, x) of every light component at unit amplitude,
+// in the order: lens (a, b), source (a, b).  Lens light only skips the ray
+// trace; two components per galaxy share the elliptical radius of their side,
+// whose second component differs only in R_e: log2 (R/R_b)^2 = log2 (R/R_a)^2
+// + 2 log2(R_a/R_b).
+template <int LM>
+__device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlock &P, int y, int x,
+                                                double (&acc)[LightChannels<LM>::N])
 {
+    constexpr bool LENS = LM != LIGHT_SRC, SRC = LM != LIGHT_LENS, DBL = LM == LIGHT_DOUBLE;
+    constexpr int IS = DBL ? 2 : LENS ? 1 : 0;   // index of the (first) source channel
     const int s = g.s;
     const double x0 = ((double)(x * s) - g.cfx) * g.sd;
     const double dx0 = x0 - P.xm;
@@ -193,7 +216,10 @@ __device__ __forceinline__ void binned_sums(const LensGeom &g, const PropBlock &
     // pairs they are spilled or rematerialised on every sub-pixel
     double h = g.sd, lead = leading(kExp2_64);
     asm("" : "+v"(h), "+v"(lead));
-    double al = 0.0, as = 0.0;
+#pragma unroll
+    for (int c = 0; c < LightChannels<LM>::N; ++c) acc[c] = 0.0;
+    const double el = DBL ? g.fix_e[0] : P.lens.e, Bl = DBL ? g.fix_B[0] : P.lens.B;
+    const double es = DBL ? g.fix_e[2] : P.src.e, Bs = DBL ? g.fix_B[2] : P.src.B;
     for (int v = 0; v < s; ++v) {
         const double yy = ((double)(y * s + v) - g.cfy) * g.sd;
         const double dy = yy - P.ym;
@@ -205,15 +231,35 @@ __device__ __forceinline__ void binned_sums(const LensGeom &g, const PropBlock &
         const double rs = P.lens.S * dy, rq = P.lens.Q * (dy * dy);
         double dx = dx0;
         for (int u = 0; u < s; ++u) {
-            double bx, by;
-            ray_trace(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.g1p, dx, cx), fma(P.g2, dx, cy), P, bx, by);
-            al += sersic_r2(fma(fma(P.lens.P, dx, rs), dx, rq), P.lens, lead);
-            as += sersic_r2(ellip_r2(bx, by, P.src), P.src, lead);
+            if constexpr (SRC) {
+                double bx, by;
+                ray_trace(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.g1p, dx, cx), fma(P.g2, dx, cy), P, bx, by);
+                if constexpr (LENS && !DBL) {
+                    acc[0] += sersic_r2(fma(fma(P.lens.P, dx, rs), dx, rq), P.lens, lead);
+                    acc[1] += sersic_r2(ellip_r2(bx, by, P.src), P.src, lead);
+                } else {
+                    const double lgs = (double)log2_r2(ellip_r2(bx, by, P.src));
+                    acc[IS] += sersic_lg(lgs, es, Bs, lead);
+                    if constexpr (DBL) acc[IS + 1] += sersic_lg(lgs + P.dlg_s, g.fix_e[3], g.fix_B[3], lead);
+                }
+            }
+            if constexpr (LENS && (DBL || !SRC)) {
+                const double lgl = (double)log2_r2(fma(fma(P.lens.P, dx, rs), dx, rq));
+                acc[0] += sersic_lg(lgl, el, Bl, lead);
+                if constexpr (DBL) acc[1] += sersic_lg(lgl + P.dlg_l, g.fix_e[1], g.fix_B[1], lead);
+            }
             dx += h;
         }
     }
-    al_out = al;
-    as_out = as;
+}
+
+__device__ __forceinline__ void binned_sums(const LensGeom &g, const PropBlock &P, int y, int x, double &al_out,
+                                            double &as_out)
+{
+    double acc[2];
+    binned_channels<LIGHT_BOTH>(g, P, y, x, acc);
+    al_out = acc[0];
+    as_out = acc[1];
 }
 
 __device__ __forceinline__ float binned_pixel(const LensGeom &g, const PropBlock &P, int y, int x)
@@ -223,19 +269,22 @@ __device__ __forceinline__ float binned_pixel(const LensGeom &g, const PropBlock
     return (float)(fma(P.lens.I, al, P.src.I * as) * g.inv_s2);
 }
 
-// The two unit-amplitude channels (lens light, source) of pixel (y, x), for
+// The unit-amplitude channels of pixel (y, x) (binned values, FP32), for
 // amplitudes solved by non-negative least squares (Sec. 2.3).
-__device__ __forceinline__ float2 binned_pixel2(const LensGeom &g, const PropBlock &P, int y, int x)
+template <int LM>
+__device__ __forceinline__ void binned_pixel_channels(const LensGeom &g, const PropBlock &P, int y, int x,
+                                                      float (&ch)[LightChannels<LM>::N])
 {
-    double al, as;
-    binned_sums(g, P, y, x, al, as);
-    return make_float2((float)(al * g.inv_s2), (float)(as * g.inv_s2));
+    double acc[LightChannels<LM>::N];
+    binned_channels<LM>(g, P, y, x, acc);
+#pragma unroll
+    for (int c = 0; c < LightChannels<LM>::N; ++c) ch[c] = (float)(acc[c] * g.inv_s2);
 }
 
 // Sersic b_n: root of P(2n, b) = 1/2 (Eq. 9), FP64 Newton safeguarded by
 // bisection on [0, 2n + 1].  P by its power series, which converges for every
 // b in the bracket; the median of Gamma(2n) lies below 2n.
-__device__ inline double bn_device(double n)
+__host__ __device__ inline double sersic_bn(double n)
 {
     const double a = 2.0 * n;
     const double lga1 = lgamma(a + 1.0);

@@ -31,18 +31,46 @@ struct alignas(16) PropBlock {
     double g1, g2, xs, ys;                     // shear, source centre
     LightK lens, src;
     double g1p;                                // 1 + g1: d/dx of x + g1 x + g2 y
-    double pad[6];
+    double dlg_l, dlg_s;                       // two-component light: 2 log2(R_a / R_b) of the lens, of the source
+    double pad[4];
 };
 static_assert(sizeof(PropBlock) == 256, "PropBlock layout");
 constexpr int kPCBytes = (int)sizeof(PropBlock);
 
-// PSF-convolution modes (the public LENS_PREC_* values), and the FP32
-// convolution of two unit-amplitude channels (lens light, source) whose
-// amplitudes are solved by non-negative least squares (Sec. 2.3).
-enum : int { MODE_FP32 = 0, MODE_SPLIT = 1, MODE_BF16 = 2, MODE_SPLIT3 = 3, MODE_FP32N = 4 };
+// PSF-convolution modes: the public LENS_PREC_* values (0-3), then the FP32
+// convolution of unit-amplitude channels whose amplitudes are solved by
+// non-negative least squares (Sec. 2.3), one mode per light model: lens light
+// and source (4), lens light only, no lensing (5), lensed source only (6), and
+// two components per galaxy sharing centre and ellipticity with fixed Sersic
+// indices (7).
+enum : int {
+    MODE_FP32 = 0,
+    MODE_SPLIT = 1,
+    MODE_BF16 = 2,
+    MODE_SPLIT3 = 3,
+    MODE_FP32N = 4,
+    MODE_FP32N_LENS = 5,
+    MODE_FP32N_SRC = 6,
+    MODE_FP32N_DBL = 7
+};
 __host__ __device__ constexpr int mode_planes(int mode)
 {
     return mode == MODE_SPLIT ? 2 : mode == MODE_SPLIT3 ? 3 : 1;
+}
+__host__ __device__ constexpr bool mode_solved(int mode) { return mode >= MODE_FP32N; }
+// binned channels (components at unit amplitude) of a solved-amplitude mode
+__host__ __device__ constexpr int mode_channels(int mode)
+{
+    return mode == MODE_FP32N ? 2 : mode == MODE_FP32N_LENS || mode == MODE_FP32N_SRC ? 1 : mode == MODE_FP32N_DBL ? 4 : 0;
+}
+
+// Light models (the public LENS_LIGHT_* values); they fix what the prep kernel
+// reads from the parameter slots.
+enum : int { LIGHT_BOTH = 0, LIGHT_LENS = 1, LIGHT_SRC = 2, LIGHT_DOUBLE = 3 };
+__host__ __device__ constexpr int mode_light(int mode)
+{
+    return mode == MODE_FP32N_LENS ? LIGHT_LENS : mode == MODE_FP32N_SRC ? LIGHT_SRC
+                                                : mode == MODE_FP32N_DBL ? LIGHT_DOUBLE : LIGHT_BOTH;
 }
 
 // Everything a likelihood launch needs to know about one resident lens.
@@ -62,7 +90,9 @@ struct LensGeom {
     double cfx, cfy;       // (nx*s - 1)/2, (ny*s - 1)/2: fine-grid centre
     float inv_s2;          // 1/s^2
     double norm;           // C = -1/2 sum_mask ln(2 pi sigma^2)
-    double dd;             // MODE_FP32N: sum_mask (w d)^2 in FP64 of the FP32 w and d
+    double dd;             // solved amplitudes: sum_mask (w d)^2 in FP64 of the FP32 w and d
+    double fix_e[4];       // MODE_FP32N_DBL: 1/(2n) of the fixed indices (lens a, lens b, source a, source b)
+    double fix_B[4];       //   and b_n log2 e
     const float *psf;      // flipped kernel Kf[a][b] = K[k-1-a][k-1-b], [k][k]
     const float *data;     // [ny][pitch], 0 outside the mask and the image
     const float *wgt;      // [ny][pitch], mask/sigma, 0 outside the mask and the image
@@ -77,6 +107,7 @@ struct LensGeom {
 };
 
 size_t ring_bytes(const LensGeom &g);
+double host_sersic_bn(double n);   // b_n of Eq. 9, the prep kernel's FP64 root, on the host
 int choose_kc(int k);
 // LDS row width (elements) and bytes per ring row for a mode, PSF side and width
 int ring_width(int mode, int k, int nx);
@@ -86,9 +117,13 @@ size_t max_lds_bytes();
 size_t set_lds_limits(size_t bytes);   // dynamic LDS now accepted by every ring kernel; 0 on refusal
 size_t lds_per_cu();
 
-hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, hipStream_t st);
+// Derived constants of n proposals.  Each proposal is read under a light model:
+// `model` for all of them, or, with d_pstart (nl + 1 proposal offsets) and
+// d_pmodel (nl models) in device memory, that of the lens owning it.
+hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, int model, const int64_t *d_pstart,
+                       const int *d_pmodel, int nl, hipStream_t st);
 // the fused likelihood of n proposals of one lens (FP32 or MFMA convolution per g.mode)
-// d_amp (MODE_FP32N, may be null): the solved amplitudes, [n][2] (lens, source)
+// d_amp (solved-amplitude modes, may be null): the solved amplitudes, [n][mode_channels(g.mode)]
 hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, double *d_amp,
                           hipStream_t st);
 // persistent multi-lens launch (counter reset + kernel) and its occupancy

@@ -32,48 +32,82 @@ __device__ LightK light_constants(double I, double R, double n, double q, double
     L.Q = A * s * s + Bq * c * c;
     L.S = 2.0 * (A - Bq) * c * s;
     L.e = 0.5 / n;
-    L.B = bn_device(n) * 1.4426950408889634;
+    L.B = sersic_bn(n) * 1.4426950408889634;
     L.I = I;
     return L;
 }
 
-__global__ void __launch_bounds__(256) k_prep(const double *__restrict__ params, int64_t n,
-                                              PropBlock *__restrict__ pc)
+// One thread per proposal.  The light model decides which slots are read and
+// validated: lens light only ignores the mass, shear and source slots; source
+// only ignores the lens light; two components per galaxy read slots n_l and
+// n_s as the second components' R_e (their indices are fixed per lens and
+// taken from the lens descriptor by the likelihood kernel).
+__global__ void __launch_bounds__(256) k_prep(const double *__restrict__ params, int64_t n, PropBlock *__restrict__ pc,
+                                              int model, const int64_t *__restrict__ pstart,
+                                              const int *__restrict__ pmodel, int nl)
 {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    int lm = model;
+    if (pstart) {
+        int lo = 0, hi = nl;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (pstart[mid] <= i) lo = mid; else hi = mid;
+        }
+        lm = pmodel[lo];
+    }
     const double *p = params + i * kStride;
     PropBlock b{};
     double v[19];
-    bool ok = true;
 #pragma unroll
-    for (int j = 0; j < 19; ++j) {
-        v[j] = p[j];
-        if (j != 7 && j != 12) ok = ok && isfinite(v[j]);   // amplitudes: below
+    for (int j = 0; j < 19; ++j) v[j] = p[j];
+    const bool mass = lm != LIGHT_LENS, lens = lm != LIGHT_SRC, src = lm != LIGHT_LENS, dbl = lm == LIGHT_DOUBLE;
+    bool ok = isfinite(v[3]) && isfinite(v[4]);
+    if (mass) {
+#pragma unroll
+        for (int j = 0; j < 7; ++j) ok = ok && isfinite(v[j]);
+        ok = ok && v[0] >= 0.0 && v[1] > 0.0 && v[1] <= 1.0;
+    }
+    if (lens) {
+        ok = ok && isfinite(v[8]) && isfinite(v[9]) && isfinite(v[10]) && isfinite(v[11]);
+        ok = ok && v[10] > 0.0 && v[10] <= 1.0 && v[8] > 0.0;
+        ok = ok && (dbl ? v[9] > 0.0 : v[9] >= kNMin && v[9] <= kNMax);
+    }
+    if (src) {
+#pragma unroll
+        for (int j = 13; j < 19; ++j) ok = ok && isfinite(v[j]);
+        ok = ok && v[15] > 0.0 && v[15] <= 1.0 && v[13] > 0.0;
+        ok = ok && (dbl ? v[14] > 0.0 : v[14] >= kNMin && v[14] <= kNMax);
     }
     const bool amps_ok = isfinite(v[7]) && isfinite(v[12]);
-    ok = ok && v[0] >= 0.0;
-    ok = ok && v[1] > 0.0 && v[1] <= 1.0 && v[10] > 0.0 && v[10] <= 1.0 && v[15] > 0.0 && v[15] <= 1.0;
-    ok = ok && v[8] > 0.0 && v[13] > 0.0;
-    ok = ok && v[9] >= kNMin && v[9] <= kNMax && v[14] >= kNMin && v[14] <= kNMax;
     if (ok) {
-        const double q = v[1];
-        b.valid = amps_ok ? 1.0 : 2.0;
+        b.valid = (lm == LIGHT_BOTH && amps_ok) ? 1.0 : 2.0;
         b.xm = v[3];
         b.ym = v[4];
-        b.cm = cos(v[2]);
-        b.sm = sin(v[2]);
-        b.q2m = q * q;
-        b.ce = sqrt((1.0 - q) * (1.0 + q));
-        b.bsie = v[0] * sqrt(q);
-        b.bsc = b.ce > 0.0 ? b.bsie / b.ce : 0.0;
-        b.g1 = v[5];
-        b.g1p = 1.0 + v[5];
-        b.g2 = v[6];
-        b.xs = v[17];
-        b.ys = v[18];
-        b.lens = light_constants(v[7], v[8], v[9], v[10], v[11]);
-        b.src = light_constants(v[12], v[13], v[14], v[15], v[16]);
+        if (mass) {
+            const double q = v[1];
+            b.cm = cos(v[2]);
+            b.sm = sin(v[2]);
+            b.q2m = q * q;
+            b.ce = sqrt((1.0 - q) * (1.0 + q));
+            b.bsie = v[0] * sqrt(q);
+            b.bsc = b.ce > 0.0 ? b.bsie / b.ce : 0.0;
+            b.g1 = v[5];
+            b.g2 = v[6];
+            b.g1p = 1.0 + v[5];
+        }
+        // two-component light: e and B of the fixed indices come from the lens descriptor
+        if (lens) b.lens = light_constants(v[7], v[8], dbl ? 1.0 : v[9], v[10], v[11]);
+        if (src) {
+            b.xs = v[17];
+            b.ys = v[18];
+            b.src = light_constants(v[12], v[13], dbl ? 1.0 : v[14], v[15], v[16]);
+        }
+        if (dbl) {
+            b.dlg_l = 2.0 * log2(v[8] / v[9]);
+            b.dlg_s = 2.0 * log2(v[13] / v[14]);
+        }
     }
     pc[i] = b;
 }
@@ -133,12 +167,39 @@ struct RingStore {
     }
 };
 
-// Two unit-amplitude channels (lens light, source) per ring element.
-template <>
-struct RingStore<MODE_FP32N> {
-    __device__ static void put(void *ring, int, int idx, float2 v) { static_cast<float2 *>(ring)[idx] = v; }
-    __device__ static void zero(void *ring, int, int idx) { static_cast<float2 *>(ring)[idx] = make_float2(0.f, 0.f); }
+// Solved amplitudes: the NCH unit-amplitude channels of a pixel form one ring
+// element (float, float2 or float4).
+template <int NCH> struct FVec;
+template <> struct FVec<1> {
+    typedef float T;
+    __device__ static T make(const float (&c)[1]) { return c[0]; }
+    __device__ static float at(const T &v, int) { return v; }
 };
+template <> struct FVec<2> {
+    typedef float2 T;
+    __device__ static T make(const float (&c)[2]) { return make_float2(c[0], c[1]); }
+    __device__ static float at(const T &v, int i) { return i == 0 ? v.x : v.y; }
+};
+template <> struct FVec<4> {
+    typedef float4 T;
+    __device__ static T make(const float (&c)[4]) { return make_float4(c[0], c[1], c[2], c[3]); }
+    __device__ static float at(const T &v, int i) { return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w; }
+};
+
+template <int NCH>
+struct RingStoreN {
+    typedef typename FVec<NCH>::T T;
+    __device__ static void put(void *ring, int, int idx, T v) { static_cast<T *>(ring)[idx] = v; }
+    __device__ static void zero(void *ring, int, int idx)
+    {
+        const float z[NCH] = {};
+        static_cast<T *>(ring)[idx] = FVec<NCH>::make(z);
+    }
+};
+template <> struct RingStore<MODE_FP32N> : RingStoreN<2> {};
+template <> struct RingStore<MODE_FP32N_LENS> : RingStoreN<1> {};
+template <> struct RingStore<MODE_FP32N_SRC> : RingStoreN<1> {};
+template <> struct RingStore<MODE_FP32N_DBL> : RingStoreN<4> {};
 
 // Binned rows [ya, yb) (all < ny) into their ring slots: every pixel in the
 // row's needed range is evaluated; the rest of the row is cleared when the
@@ -165,9 +226,12 @@ __device__ __forceinline__ void fill_rows(const LensGeom &g, const PropBlock &P,
         const int y = (int)(e >> 16), x = (int)(e & 0xffffu);
         int slot = slot_a + (y - ya);
         if (slot >= RB) slot -= RB;
-        if constexpr (MODE == MODE_FP32N)
-            RingStore<MODE>::put(ring, g.plane, slot * W + r + x, binned_pixel2(g, P, y, x));
-        else
+        if constexpr (mode_solved(MODE)) {
+            constexpr int NCH = mode_channels(MODE);
+            float ch[NCH];
+            binned_pixel_channels<mode_light(MODE)>(g, P, y, x, ch);
+            RingStore<MODE>::put(ring, g.plane, slot * W + r + x, FVec<NCH>::make(ch));
+        } else
             RingStore<MODE>::put(ring, g.plane, slot * W + r + x, binned_pixel(g, P, y, x));
     }
 }
@@ -181,9 +245,9 @@ __device__ __forceinline__ Acc strip_sweep(const LensGeom &g, const PropBlock &P
                                            const int2 *__restrict__ evr, Conv conv)
 {
     const int ny = g.ny, r = g.r, H = g.strip_h, RB = g.ring_rows;
-    const int nwords = (MODE == MODE_FP32    ? RB * g.ring_w
-                        : MODE == MODE_FP32N ? 2 * RB * g.ring_w
-                                             : RB * g.ring_w * mode_planes(MODE) / 2) / 4;
+    const int nwords = (MODE == MODE_FP32      ? RB * g.ring_w
+                        : mode_solved(MODE) ? mode_channels(MODE) * RB * g.ring_w
+                                            : RB * g.ring_w * mode_planes(MODE) / 2) / 4;
     float4 *r4 = static_cast<float4 *>(ring);
     for (int i = threadIdx.x; i < nwords; i += NT) r4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
@@ -228,96 +292,154 @@ __device__ __forceinline__ void strip_loop(const LensGeom &g, const PropBlock &P
 }
 
 // Moments of the amplitude solve (Sec. 2.3) over the masked pixels, with the
-// columns a (lens light) and b (source) of M at unit amplitude, the data d and
-// the weights w = mask/sigma: F = [[sum (wa)^2, sum (wa)(wb)], [., sum (wb)^2]],
-// g = (sum (wa)(wd), sum (wb)(wd)).  FP64 sums of products of FP32 values.
-struct Mom5 {
-    double f11, f12, f22, g1, g2;
-    __device__ Mom5 &operator+=(const Mom5 &o)
+// columns c_a of M (each light component at unit amplitude), the data d and
+// the weights w = mask/sigma: F_ab = sum (w c_a)(w c_b) (upper triangle, row by
+// row) and g_a = sum (w c_a)(w d).  FP64 sums of products of FP32 values.
+template <int NCH>
+struct MomN {
+    static constexpr int NF = NCH * (NCH + 1) / 2, NM = NF + NCH;
+    double m[NM];
+    __device__ MomN &operator+=(const MomN &o)
     {
-        f11 += o.f11;
-        f12 += o.f12;
-        f22 += o.f22;
-        g1 += o.g1;
-        g2 += o.g2;
+#pragma unroll
+        for (int i = 0; i < NM; ++i) m[i] += o.m[i];
         return *this;
+    }
+    __device__ void add(const float (&c)[NCH], float d, float w)
+    {
+        double wc[NCH];
+        const double wd = (double)w * (double)d;
+#pragma unroll
+        for (int a = 0; a < NCH; ++a) wc[a] = (double)w * (double)c[a];
+        int i = 0;
+#pragma unroll
+        for (int a = 0; a < NCH; ++a)
+#pragma unroll
+            for (int b = a; b < NCH; ++b, ++i) m[i] = fma(wc[a], wc[b], m[i]);
+#pragma unroll
+        for (int a = 0; a < NCH; ++a) m[NF + a] = fma(wc[a], wd, m[NF + a]);
     }
 };
 
-// Non-negative least squares in two variables (Sec. 2.3): the minimiser of
-// chi^2(s) = D - 2 s.g + s.F s over s >= 0 is the least-squares solution on
-// one of the four supports (both, lens only, source only, none) that is
-// feasible and has the smallest chi^2; on a support S the optimum has
-// F_S s_S = g_S, so chi^2 = D - s_S.g_S.  D = sum (wd)^2.  Returns chi^2
-// (>= 0) and the amplitudes.
-__device__ inline double nnls2(const Mom5 &m, double D, double &sl, double &ss)
+// Non-negative least squares in NCH <= 4 variables (Sec. 2.3): the minimiser of
+// chi^2(s) = D - 2 s.g + s.F s over s >= 0 is the least-squares solution on one
+// of the 2^NCH supports that is feasible and has the smallest chi^2; on a
+// support S the optimum has F_S s_S = g_S, so chi^2 = D - s_S.g_S.  Each
+// support's system is solved by Gaussian elimination with partial pivoting
+// and skipped when singular (a pivot below 1e-13 of the largest diagonal
+// entry).  D = sum (wd)^2.  Returns chi^2 (>= 0) and the amplitudes.
+template <int NCH>
+__device__ inline double nnls_small(const MomN<NCH> &mo, double D, double (&best_s)[NCH])
 {
+    constexpr int NF = MomN<NCH>::NF;
+    double F[NCH][NCH];
+    int i = 0;
+    for (int a = 0; a < NCH; ++a)
+        for (int b = a; b < NCH; ++b) F[a][b] = F[b][a] = mo.m[i++];
+    double dmax = 0.0;
+    for (int a = 0; a < NCH; ++a) dmax = fmax(dmax, fabs(F[a][a]));
     double best = D;
-    sl = 0.0;
-    ss = 0.0;
-    const double det = m.f11 * m.f22 - m.f12 * m.f12;
-    if (det > 0.0) {
-        const double a = (m.g1 * m.f22 - m.g2 * m.f12) / det, b = (m.g2 * m.f11 - m.g1 * m.f12) / det;
-        const double c = D - (a * m.g1 + b * m.g2);
-        if (a >= 0.0 && b >= 0.0 && c < best) {
-            best = c;
-            sl = a;
-            ss = b;
+    for (int a = 0; a < NCH; ++a) best_s[a] = 0.0;
+    for (int S = 1; S < (1 << NCH); ++S) {
+        int idx[NCH], m = 0;
+        for (int a = 0; a < NCH; ++a)
+            if (S & (1 << a)) idx[m++] = a;
+        double A[NCH][NCH], b[NCH], x[NCH];
+        for (int r = 0; r < m; ++r) {
+            b[r] = mo.m[NF + idx[r]];
+            for (int c = 0; c < m; ++c) A[r][c] = F[idx[r]][idx[c]];
         }
-    }
-    if (m.f11 > 0.0 && m.g1 > 0.0) {
-        const double c = D - m.g1 * m.g1 / m.f11;
-        if (c < best) {
-            best = c;
-            sl = m.g1 / m.f11;
-            ss = 0.0;
+        bool ok = dmax > 0.0;
+        for (int col = 0; col < m && ok; ++col) {
+            int piv = col;
+            for (int r = col + 1; r < m; ++r)
+                if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+            if (!(fabs(A[piv][col]) > 1e-13 * dmax)) {
+                ok = false;
+                break;
+            }
+            if (piv != col) {
+                for (int c = 0; c < m; ++c) {
+                    const double t = A[col][c];
+                    A[col][c] = A[piv][c];
+                    A[piv][c] = t;
+                }
+                const double t = b[col];
+                b[col] = b[piv];
+                b[piv] = t;
+            }
+            for (int r = col + 1; r < m; ++r) {
+                const double f = A[r][col] / A[col][col];
+                for (int c = col; c < m; ++c) A[r][c] -= f * A[col][c];
+                b[r] -= f * b[col];
+            }
         }
-    }
-    if (m.f22 > 0.0 && m.g2 > 0.0) {
-        const double c = D - m.g2 * m.g2 / m.f22;
-        if (c < best) {
-            best = c;
-            sl = 0.0;
-            ss = m.g2 / m.f22;
+        if (!ok) continue;
+        for (int r = m - 1; r >= 0; --r) {
+            double acc = b[r];
+            for (int c = r + 1; c < m; ++c) acc -= A[r][c] * x[c];
+            x[r] = acc / A[r][r];
+        }
+        bool feasible = true;
+        double sg = 0.0;
+        for (int r = 0; r < m; ++r) {
+            feasible = feasible && x[r] >= 0.0;
+            sg += x[r] * mo.m[NF + idx[r]];
+        }
+        const double c2 = D - sg;
+        if (feasible && c2 < best) {
+            best = c2;
+            for (int a = 0; a < NCH; ++a) best_s[a] = 0.0;
+            for (int r = 0; r < m; ++r) best_s[idx[r]] = x[r];
         }
     }
     return fmax(best, 0.0);
 }
 
-// Solved amplitudes: the NNLS moments reduced like the chi-square (five sums),
-// then one thread solves and writes lnL = C - chi^2 / 2 (and the amplitudes).
-template <int NT, typename Conv>
-__device__ __forceinline__ void strip_loop_nnls(const LensGeom &g, const PropBlock &P, void *ring,
-                                                const uint32_t *__restrict__ evl, const int *__restrict__ evpre,
-                                                const int2 *__restrict__ evr, double *__restrict__ out,
-                                                double *__restrict__ amp, int64_t p, Conv conv)
+// Solved amplitudes: the moments reduced like the chi-square, then one thread
+// solves and writes lnL = C - chi^2 / 2 (and, if amp is not null, the NCH
+// amplitudes of proposal p at amp[NCH p ...]).
+template <int MODE, int NT, typename Conv>
+__device__ __forceinline__ void strip_loop_solved(const LensGeom &g, const PropBlock &P, void *ring,
+                                                  const uint32_t *__restrict__ evl, const int *__restrict__ evpre,
+                                                  const int2 *__restrict__ evr, double *__restrict__ out,
+                                                  double *__restrict__ amp, int64_t p, Conv conv)
 {
-    __shared__ double red[5][NT / 64];
-    Mom5 m = strip_sweep<MODE_FP32N, NT, Mom5>(g, P, ring, evl, evpre, evr, conv);
-    m.f11 = wave_sum(m.f11);
-    m.f12 = wave_sum(m.f12);
-    m.f22 = wave_sum(m.f22);
-    m.g1 = wave_sum(m.g1);
-    m.g2 = wave_sum(m.g2);
-    if ((threadIdx.x & 63) == 0) {
-        const int w = threadIdx.x >> 6;
-        red[0][w] = m.f11;
-        red[1][w] = m.f12;
-        red[2][w] = m.f22;
-        red[3][w] = m.g1;
-        red[4][w] = m.g2;
+    constexpr int NCH = mode_channels(MODE), NM = MomN<NCH>::NM;
+    __shared__ double red[NM][NT / 64];
+    if constexpr (NCH == 2) {
+        // each strip's moments are reduced over the wave and added to the
+        // wave's LDS slots at once, so that no FP64 accumulators stay live
+        // through the next strip's ray trace (74 VGPRs instead of 82: one
+        // more resident workgroup per CU)
+        for (int i = threadIdx.x; i < NM * (NT / 64); i += NT) (&red[0][0])[i] = 0.0;
+        (void)strip_sweep<MODE, NT, MomN<NCH>>(g, P, ring, evl, evpre, evr, [&](int y0, int y1, int st) {
+            MomN<NCH> mo = conv(y0, y1, st);
+#pragma unroll
+            for (int i = 0; i < NM; ++i) mo.m[i] = wave_sum(mo.m[i]);
+            if ((threadIdx.x & 63) == 0)
+                for (int i = 0; i < NM; ++i) red[i][threadIdx.x >> 6] += mo.m[i];
+            return MomN<NCH>{};
+        });
+    } else {
+        // one reduction at the end (for four channels the strip-wise one does
+        // not raise occupancy and costs more than it saves)
+        MomN<NCH> mo = strip_sweep<MODE, NT, MomN<NCH>>(g, P, ring, evl, evpre, evr, conv);
+#pragma unroll
+        for (int i = 0; i < NM; ++i) mo.m[i] = wave_sum(mo.m[i]);
+        if ((threadIdx.x & 63) == 0)
+            for (int i = 0; i < NM; ++i) red[i][threadIdx.x >> 6] = mo.m[i];
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        Mom5 t{0.0, 0.0, 0.0, 0.0, 0.0};
-        for (int w = 0; w < NT / 64; ++w) t += Mom5{red[0][w], red[1][w], red[2][w], red[3][w], red[4][w]};
-        double sl, ss;
-        const double chi2 = nnls2(t, g.dd, sl, ss);
+        MomN<NCH> t{};
+        for (int w = 0; w < NT / 64; ++w)
+            for (int i = 0; i < NM; ++i) t.m[i] += red[i][w];
+        double s[NCH];
+        const double chi2 = nnls_small<NCH>(t, g.dd, s);
         out[p] = g.norm - 0.5 * chi2;
-        if (amp) {
-            amp[2 * p] = sl;
-            amp[2 * p + 1] = ss;
-        }
+        if (amp)
+            for (int a = 0; a < NCH; ++a) amp[NCH * p + a] = s[a];
     }
 }
 
@@ -574,83 +696,125 @@ __device__ __forceinline__ double conv_rows_rt(const LensGeom &g, const float *r
     return acc;
 }
 
-// The NNLS variant: both unit-amplitude channels (float2 ring) convolved with
-// the runtime-k sliding window of conv_rows_rt, and the moments of the
-// amplitude solve accumulated in FP64 from the FP32 columns, data and weights.
-template <int NT>
-__device__ __forceinline__ Mom5 conv_rows2_rt(const LensGeom &g, const float2 *ring, int ya, int yb)
+// Solved amplitudes: the NCH unit-amplitude channels convolved with the
+// runtime-k sliding window of conv_rows_rt (the same fmaf order per channel),
+// and the moments of the amplitude solve accumulated in FP64 from the FP32
+// columns, data and weights.
+template <int MODE, int NT>
+__device__ __forceinline__ MomN<mode_channels(MODE)> conv_rows_solved(const LensGeom &g,
+                                                                      const typename FVec<mode_channels(MODE)>::T *ring,
+                                                                      int ya, int yb)
 {
+    constexpr int NCH = mode_channels(MODE);
+    // channels convolved in passes of at most two, so that four channels keep
+    // the register footprint of two
+    constexpr int CP = NCH < 2 ? NCH : 2, NPASS = NCH / CP;
+    typedef FVec<CP> V;
+    const typename V::T *ringp = reinterpret_cast<const typename V::T *>(ring);
     const int W = g.ring_w, RB = g.ring_rows, k = g.k;
     const float *__restrict__ psf = g.psf;
-    Mom5 m{0.0, 0.0, 0.0, 0.0, 0.0};
+    MomN<NCH> mo{};
     const int gb = g.cvpre[yb];
     for (int gi = g.cvpre[ya] + threadIdx.x; gi < gb; gi += NT) {
         const uint32_t e = g.cvl[gi];
         const int y = (int)(e >> 16), x0 = (int)(e & 0xffffu);
-        float2 o0 = make_float2(0.f, 0.f), o1 = o0, o2 = o0, o3 = o0;
-        int slot = y % RB;
-        for (int a = 0; a < k; ++a) {
-            const float2 *row = ring + slot * W + x0;
-            const float *kr = psf + a * k;
-            float2 p0 = make_float2(0.f, 0.f), p1 = p0, p2 = p0, p3 = p0;
-            float2 v0 = row[0], v1 = row[1], v2 = row[2];
-            for (int b = 0; b < k; ++b) {
-                const float w = kr[b];
-                const float2 v3 = row[b + 3];
-                p0.x = fmaf(w, v0.x, p0.x); p0.y = fmaf(w, v0.y, p0.y);
-                p1.x = fmaf(w, v1.x, p1.x); p1.y = fmaf(w, v1.y, p1.y);
-                p2.x = fmaf(w, v2.x, p2.x); p2.y = fmaf(w, v2.y, p2.y);
-                p3.x = fmaf(w, v3.x, p3.x); p3.y = fmaf(w, v3.y, p3.y);
-                v0 = v1;
-                v1 = v2;
-                v2 = v3;
+        float o[4][NCH] = {};
+#pragma unroll
+        for (int pass = 0; pass < NPASS; ++pass) {
+            int slot = y % RB;
+            for (int a = 0; a < k; ++a) {
+                const typename V::T *row = ringp + (size_t)(slot * W + x0) * NPASS + pass;
+                const float *kr = psf + a * k;
+                float pp[4][CP] = {};
+                typename V::T v0 = row[0], v1 = row[NPASS], v2 = row[2 * NPASS];
+                // up to two channels: four taps per step (their weights fetched
+                // together), then the tail; four channels: one tap per step (fewer
+                // live registers).  Per output and channel the fmaf order is
+                // ascending in b either way.
+                int b = 0;
+                for (; NCH <= 2 && b + 4 <= k; b += 4) {
+                    const float w0 = kr[b], w1 = kr[b + 1], w2 = kr[b + 2], w3 = kr[b + 3];
+                    const typename V::T v3 = row[(b + 3) * NPASS], v4 = row[(b + 4) * NPASS];
+                    const typename V::T v5 = row[(b + 5) * NPASS], v6 = row[(b + 6) * NPASS];
+#pragma unroll
+                    for (int c = 0; c < CP; ++c) {
+                        pp[0][c] = fmaf(w0, V::at(v0, c), pp[0][c]);
+                        pp[1][c] = fmaf(w0, V::at(v1, c), pp[1][c]);
+                        pp[2][c] = fmaf(w0, V::at(v2, c), pp[2][c]);
+                        pp[3][c] = fmaf(w0, V::at(v3, c), pp[3][c]);
+                        pp[0][c] = fmaf(w1, V::at(v1, c), pp[0][c]);
+                        pp[1][c] = fmaf(w1, V::at(v2, c), pp[1][c]);
+                        pp[2][c] = fmaf(w1, V::at(v3, c), pp[2][c]);
+                        pp[3][c] = fmaf(w1, V::at(v4, c), pp[3][c]);
+                        pp[0][c] = fmaf(w2, V::at(v2, c), pp[0][c]);
+                        pp[1][c] = fmaf(w2, V::at(v3, c), pp[1][c]);
+                        pp[2][c] = fmaf(w2, V::at(v4, c), pp[2][c]);
+                        pp[3][c] = fmaf(w2, V::at(v5, c), pp[3][c]);
+                        pp[0][c] = fmaf(w3, V::at(v3, c), pp[0][c]);
+                        pp[1][c] = fmaf(w3, V::at(v4, c), pp[1][c]);
+                        pp[2][c] = fmaf(w3, V::at(v5, c), pp[2][c]);
+                        pp[3][c] = fmaf(w3, V::at(v6, c), pp[3][c]);
+                    }
+                    v0 = v4;
+                    v1 = v5;
+                    v2 = v6;
+                }
+                for (; b < k; ++b) {
+                    const float w = kr[b];
+                    const typename V::T v3 = row[(b + 3) * NPASS];
+#pragma unroll
+                    for (int c = 0; c < CP; ++c) {
+                        pp[0][c] = fmaf(w, V::at(v0, c), pp[0][c]);
+                        pp[1][c] = fmaf(w, V::at(v1, c), pp[1][c]);
+                        pp[2][c] = fmaf(w, V::at(v2, c), pp[2][c]);
+                        pp[3][c] = fmaf(w, V::at(v3, c), pp[3][c]);
+                    }
+                    v0 = v1;
+                    v1 = v2;
+                    v2 = v3;
+                }
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+#pragma unroll
+                    for (int c = 0; c < CP; ++c) o[j][CP * pass + c] += pp[j][c];
+                slot = (slot + 1 == RB) ? 0 : slot + 1;
             }
-            o0.x += p0.x; o0.y += p0.y;
-            o1.x += p1.x; o1.y += p1.y;
-            o2.x += p2.x; o2.y += p2.y;
-            o3.x += p3.x; o3.y += p3.y;
-            slot = (slot + 1 == RB) ? 0 : slot + 1;
         }
         const float4 d = *reinterpret_cast<const float4 *>(g.data + (size_t)y * g.pitch + x0);
         const float4 w = *reinterpret_cast<const float4 *>(g.wgt + (size_t)y * g.pitch + x0);
-        const float2 oo[4] = {o0, o1, o2, o3};
-        const float dd[4] = {d.x, d.y, d.z, d.w}, ww[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const double wj = (double)ww[j];
-            const double wa = wj * (double)oo[j].x, wb = wj * (double)oo[j].y, wd = wj * (double)dd[j];
-            m.f11 = fma(wa, wa, m.f11);
-            m.f12 = fma(wa, wb, m.f12);
-            m.f22 = fma(wb, wb, m.f22);
-            m.g1 = fma(wa, wd, m.g1);
-            m.g2 = fma(wb, wd, m.g2);
-        }
+        mo.add(o[0], d.x, w.x);
+        mo.add(o[1], d.y, w.y);
+        mo.add(o[2], d.z, w.z);
+        mo.add(o[3], d.w, w.w);
     }
-    return m;
+    return mo;
 }
 
-// Light amplitudes solved by NNLS (Sec. 2.3): one workgroup per proposal, the
-// two channels through the LDS ring and the FP32 convolution, the moments
-// reduced and the 2 x 2 problem solved in the workgroup.  amp may be null.
-template <int NT>
+// Light amplitudes solved by NNLS (Sec. 2.3), for the light model of MODE: one
+// workgroup per proposal, the NCH channels through the LDS ring and the FP32
+// convolution, the moments reduced and the problem solved in the workgroup.
+// amp (may be null): [n][NCH].
+template <int MODE, int NT>
 __global__ void __launch_bounds__(NT)
 k_loglike_nnls(const LensGeom g, const PropBlock *__restrict__ pc, double *__restrict__ out,
                double *__restrict__ amp)
 {
+    constexpr int NCH = mode_channels(MODE);
     extern __shared__ float4 lds4[];
-    float2 *ring = reinterpret_cast<float2 *>(lds4);
+    auto *ring = reinterpret_cast<typename FVec<NCH>::T *>(lds4);
     const int64_t p = blockIdx.x;
     const PropBlock *c = pc + p;
     if (c->valid == 0.0) {
         if (threadIdx.x == 0) {
             out[p] = -INFINITY;
-            if (amp) amp[2 * p] = amp[2 * p + 1] = NAN;
+            if (amp)
+                for (int a = 0; a < NCH; ++a) amp[NCH * p + a] = NAN;
         }
         return;
     }
     const PropBlock P = *c;
-    strip_loop_nnls<NT>(g, P, ring, g.evl, g.evpre, g.evr, out, amp, p, [&](int y0, int y1, int) {
-        return conv_rows2_rt<NT>(g, ring, y0, y1);
+    strip_loop_solved<MODE, NT>(g, P, ring, g.evl, g.evpre, g.evr, out, amp, p, [&](int y0, int y1, int) {
+        return conv_rows_solved<MODE, NT>(g, ring, y0, y1);
     });
 }
 
@@ -688,15 +852,14 @@ k_loglike_batch(const LensGeom *__restrict__ geoms, const int *__restrict__ lsta
         const LensGeom g = geoms[lo];
         const int64_t p = lout[lo] + (item - lstart[lo]);
         const PropBlock *c = pc + p;
-        if (MODE == MODE_FP32N ? c->valid == 0.0 : c->valid != 1.0) {
+        if (mode_solved(MODE) ? c->valid == 0.0 : c->valid != 1.0) {
             if (threadIdx.x == 0) out[p] = -INFINITY;
         } else {
             const PropBlock P = *c;
-            if constexpr (MODE == MODE_FP32N) {
-                float2 *ring = reinterpret_cast<float2 *>(lds4);
-                strip_loop_nnls<NT>(g, P, ring, g.evl, g.evpre, g.evr, out, nullptr, p, [&](int y0, int y1, int) {
-                    return conv_rows2_rt<NT>(g, ring, y0, y1);
-                });
+            if constexpr (mode_solved(MODE)) {
+                auto *ring = reinterpret_cast<typename FVec<mode_channels(MODE)>::T *>(lds4);
+                strip_loop_solved<MODE, NT>(g, P, ring, g.evl, g.evpre, g.evr, out, nullptr, p,
+                                            [&](int y0, int y1, int) { return conv_rows_solved<MODE, NT>(g, ring, y0, y1); });
             } else if (MODE == MODE_FP32) {
                 float *ring = reinterpret_cast<float *>(lds4);
                 strip_loop<MODE, NT>(g, P, ring, g.evl, g.evpre, g.evr, out, p, [&](int y0, int y1, int) {
@@ -770,16 +933,18 @@ __global__ void k_model_conv(const LensGeom g, const float *__restrict__ img, fl
 // ---------------------------------------------------------------------------
 int choose_kc(int k) { return (k + 6) / 4; }
 
+double host_sersic_bn(double n) { return sersic_bn(n); }
+
 int ring_width(int mode, int k, int nx)
 {
-    if (mode == MODE_FP32 || mode == MODE_FP32N) return (nx + 3) / 4 * 4 + 4 * choose_kc(k);
+    if (mode == MODE_FP32 || mode_solved(mode)) return (nx + 3) / 4 * 4 + 4 * choose_kc(k);
     const int L = (16 + k - 1 + 7) / 8 * 8;
     return (nx + 15) / 16 * 16 + L;
 }
 
 size_t ring_row_bytes(int mode, int k, int nx)
 {
-    const size_t elem = mode == MODE_FP32 ? 4 : mode == MODE_FP32N ? 8 : 2 * mode_planes(mode);
+    const size_t elem = mode == MODE_FP32 ? 4 : mode_solved(mode) ? 4 * mode_channels(mode) : 2 * mode_planes(mode);
     return (size_t)ring_width(mode, k, nx) * elem;
 }
 
@@ -802,12 +967,13 @@ size_t max_lds_bytes()
     return m;
 }
 
-hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, hipStream_t st)
+hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, int model, const int64_t *d_pstart,
+                       const int *d_pmodel, int nl, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     const int bs = 256;
     const int64_t nb = (n + bs - 1) / bs;
-    hipLaunchKernelGGL(k_prep, dim3((unsigned)nb), dim3(bs), 0, st, d_params, n, d_pc);
+    hipLaunchKernelGGL(k_prep, dim3((unsigned)nb), dim3(bs), 0, st, d_params, n, d_pc, model, d_pstart, d_pmodel, nl);
     return hipGetLastError();
 }
 
@@ -854,19 +1020,33 @@ static hipError_t launch_nt(const LensGeom &g, const PropBlock *d_pc, int64_t n,
     }
 }
 
+template <int MODE, int NT>
+static hipError_t launch_nnls_m(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, double *d_amp,
+                                hipStream_t st)
+{
+    hipLaunchKernelGGL((k_loglike_nnls<MODE, NT>), dim3((unsigned)n), dim3(NT), ring_bytes(g), st, g, d_pc, d_out,
+                       d_amp);
+    return hipGetLastError();
+}
+
 template <int NT>
 static hipError_t launch_nnls(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, double *d_amp,
                               hipStream_t st)
 {
-    hipLaunchKernelGGL((k_loglike_nnls<NT>), dim3((unsigned)n), dim3(NT), ring_bytes(g), st, g, d_pc, d_out, d_amp);
-    return hipGetLastError();
+    switch (g.mode) {
+    case MODE_FP32N: return launch_nnls_m<MODE_FP32N, NT>(g, d_pc, n, d_out, d_amp, st);
+    case MODE_FP32N_LENS: return launch_nnls_m<MODE_FP32N_LENS, NT>(g, d_pc, n, d_out, d_amp, st);
+    case MODE_FP32N_SRC: return launch_nnls_m<MODE_FP32N_SRC, NT>(g, d_pc, n, d_out, d_amp, st);
+    case MODE_FP32N_DBL: return launch_nnls_m<MODE_FP32N_DBL, NT>(g, d_pc, n, d_out, d_amp, st);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, double *d_amp,
                           hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    if (g.mode == MODE_FP32N) {
+    if (mode_solved(g.mode)) {
         if (g.nt == 512) return launch_nnls<512>(g, d_pc, n, d_out, d_amp, st);
         if (g.nt == 256) return launch_nnls<256>(g, d_pc, n, d_out, d_amp, st);
         return hipErrorInvalidValue;
@@ -885,7 +1065,10 @@ static const void *loglike_kernel_nt(const LensGeom &g)
     case MODE_BF16: return reinterpret_cast<const void *>(&k_loglike_mfma<MODE_BF16, NT>);
     case MODE_SPLIT: return reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT, NT>);
     case MODE_SPLIT3: return reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT3, NT>);
-    case MODE_FP32N: return reinterpret_cast<const void *>(&k_loglike_nnls<NT>);
+    case MODE_FP32N: return reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N, NT>);
+    case MODE_FP32N_LENS: return reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N_LENS, NT>);
+    case MODE_FP32N_SRC: return reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N_SRC, NT>);
+    case MODE_FP32N_DBL: return reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N_DBL, NT>);
     case MODE_FP32: break;
     default: return nullptr;
     }
@@ -921,8 +1104,13 @@ static void likelihood_kernels_nt(std::vector<const void *> &v)
     v.push_back(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_BF16, NT>));
     v.push_back(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT, NT>));
     v.push_back(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT3, NT>));
-    v.push_back(reinterpret_cast<const void *>(&k_loglike_nnls<NT>));
-    for (int m : {MODE_FP32, MODE_SPLIT, MODE_BF16, MODE_SPLIT3, MODE_FP32N}) v.push_back(batch_kernel(m, NT));
+    v.push_back(reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N, NT>));
+    v.push_back(reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N_LENS, NT>));
+    v.push_back(reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N_SRC, NT>));
+    v.push_back(reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N_DBL, NT>));
+    for (int m : {MODE_FP32, MODE_SPLIT, MODE_BF16, MODE_SPLIT3, MODE_FP32N, MODE_FP32N_LENS, MODE_FP32N_SRC,
+                  MODE_FP32N_DBL})
+        v.push_back(batch_kernel(m, NT));
 }
 
 // Raise every ring-using kernel's dynamic-LDS limit so that dynamic plus
@@ -971,6 +1159,9 @@ static const void *batch_kernel(int mode, int nt)
         case MODE_BF16: return batch_kernel_ptr<MODE_BF16, 256>();
         case MODE_SPLIT3: return batch_kernel_ptr<MODE_SPLIT3, 256>();
         case MODE_FP32N: return batch_kernel_ptr<MODE_FP32N, 256>();
+        case MODE_FP32N_LENS: return batch_kernel_ptr<MODE_FP32N_LENS, 256>();
+        case MODE_FP32N_SRC: return batch_kernel_ptr<MODE_FP32N_SRC, 256>();
+        case MODE_FP32N_DBL: return batch_kernel_ptr<MODE_FP32N_DBL, 256>();
         }
     } else if (nt == 512) {
         switch (mode) {
@@ -979,6 +1170,9 @@ static const void *batch_kernel(int mode, int nt)
         case MODE_BF16: return batch_kernel_ptr<MODE_BF16, 512>();
         case MODE_SPLIT3: return batch_kernel_ptr<MODE_SPLIT3, 512>();
         case MODE_FP32N: return batch_kernel_ptr<MODE_FP32N, 512>();
+        case MODE_FP32N_LENS: return batch_kernel_ptr<MODE_FP32N_LENS, 512>();
+        case MODE_FP32N_SRC: return batch_kernel_ptr<MODE_FP32N_SRC, 512>();
+        case MODE_FP32N_DBL: return batch_kernel_ptr<MODE_FP32N_DBL, 512>();
         }
     }
     return nullptr;

@@ -43,6 +43,7 @@ struct Lens {
     LensGeom g{};
     int precision = 0;
     int amplitudes = 0;     // LENS_AMP_*
+    int light_model = 0;    // LENS_LIGHT_*
     int64_t masked = 0, needed = 0;
     int psf_given = 0;      // PSF side as loaded (g.k is the side after the tail crop)
     void *slab = nullptr;   // one device allocation holding every array
@@ -377,14 +378,14 @@ struct ScratchLayout {
     double *params;
     lensk::PropBlock *pc;
     double *out;
-    double *amp;   // [n][2] solved amplitudes, right after out
+    double *amp;   // [n][N] solved amplitudes (N <= 4), right after out
 };
 
 size_t scratch_bytes(int64_t n, bool with_params_out)
 {
     size_t b = align_up((size_t)n * lensk::kPCBytes, kAlign);
     if (with_params_out)
-        b += align_up((size_t)n * lensk::kStride * sizeof(double), kAlign) + align_up((size_t)n * 3 * sizeof(double), kAlign);
+        b += align_up((size_t)n * lensk::kStride * sizeof(double), kAlign) + align_up((size_t)n * 5 * sizeof(double), kAlign);
     return b;
 }
 
@@ -406,7 +407,7 @@ ScratchLayout carve(void *base, int64_t n, bool with_params_out)
 hipError_t launch_lens(const Lens *L, const double *d_params, lensk::PropBlock *d_pc, int64_t n, double *d_out,
                        hipStream_t st, double *d_amp = nullptr)
 {
-    hipError_t e = lensk::launch_prep(d_params, n, d_pc, st);
+    hipError_t e = lensk::launch_prep(d_params, n, d_pc, L->light_model, nullptr, nullptr, 0, st);
     if (e != hipSuccess) return e;
     return lensk::launch_loglike(L->g, d_pc, n, d_out, d_amp, st);
 }
@@ -607,7 +608,7 @@ lens_status tune_lens(lens_ctx *c, Lens *L)
     lensk::PropBlock *dpc = (lensk::PropBlock *)((char *)buf + pb);
     double *dout = (double *)((char *)buf + pb + cb);
     HIPCHK(c, hipMemcpyAsync(dp, hp.data(), hp.size() * 8, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, lensk::launch_prep(dp, n, dpc, c->stream));
+    HIPCHK(c, lensk::launch_prep(dp, n, dpc, L->light_model, nullptr, nullptr, 0, c->stream));
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -706,6 +707,14 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
         return fail(c, LENS_EINVAL, "unknown amplitudes mode");
     if (d->amplitudes == LENS_AMP_NNLS && d->precision != LENS_PREC_FP32)
         return fail(c, LENS_EINVAL, "amplitudes solved by NNLS need the FP32 convolution (LENS_PREC_FP32)");
+    if (d->light_model < LENS_LIGHT_BOTH || d->light_model > LENS_LIGHT_DOUBLE)
+        return fail(c, LENS_EINVAL, "unknown light model");
+    if (d->light_model != LENS_LIGHT_BOTH && d->amplitudes != LENS_AMP_NNLS)
+        return fail(c, LENS_EINVAL, "light models other than LENS_LIGHT_BOTH need LENS_AMP_NNLS");
+    if (d->light_model == LENS_LIGHT_DOUBLE)
+        for (int j = 0; j < 4; ++j)
+            if (!(d->sersic_n[j] >= lensk::kNMin && d->sersic_n[j] <= lensk::kNMax))
+                return fail(c, LENS_EINVAL, "sersic_n must be in [0.1, 20]");
     const int64_t npix = (int64_t)ny * nx;
     for (int i = 0; i < k_given * k_given; ++i)
         if (!std::isfinite(d->psf[i])) return fail(c, LENS_EINVAL, "non-finite PSF value");
@@ -733,8 +742,11 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     }
     const int r = (k - 1) / 2;
     const int kc = lensk::choose_kc(k);
-    // LENS_PREC_* equal lensk::MODE_*; solved amplitudes convolve two channels
-    const int mode = d->amplitudes == LENS_AMP_NNLS ? (int)lensk::MODE_FP32N : d->precision;
+    // LENS_PREC_* equal lensk::MODE_*; solved amplitudes convolve one channel per
+    // light component, in the mode of the light model
+    static const int solved_mode[4] = {lensk::MODE_FP32N, lensk::MODE_FP32N_LENS, lensk::MODE_FP32N_SRC,
+                                       lensk::MODE_FP32N_DBL};
+    const int mode = d->amplitudes == LENS_AMP_NNLS ? solved_mode[d->light_model] : d->precision;
     const int pitch = (int)align_up((size_t)nx, 16);
     // masked column range of each row
     std::vector<int> mlo(ny, INT_MAX), mhi(ny, INT_MIN);
@@ -804,6 +816,12 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     g.cfy = 0.5 * ((double)ny * s - 1.0);
     g.inv_s2 = (float)(1.0 / ((double)s * s));
     g.norm = norm;
+    // two components per galaxy: the fixed indices' 1/(2n) and b_n log2 e (Eqs. 8-9)
+    for (int j = 0; j < 4; ++j) {
+        const double nj = d->light_model == LENS_LIGHT_DOUBLE ? d->sersic_n[j] : 1.0;
+        g.fix_e[j] = 0.5 / nj;
+        g.fix_B[j] = lensk::host_sersic_bn(nj) * 1.4426950408889634;
+    }
     // host images
     std::vector<float> hd((size_t)ny * pitch, 0.0f), hw((size_t)ny * pitch, 0.0f), hk((size_t)k * k);
     for (int y = 0; y < ny; ++y)
@@ -880,6 +898,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     L->g = g;
     L->precision = d->precision;
     L->amplitudes = d->amplitudes;
+    L->light_model = d->light_model;
     L->psf_given = k_given;
     L->masked = masked;
     L->needed = (int64_t)evl.size();
@@ -956,6 +975,9 @@ extern "C" lens_status lens_get_info(lens_ctx *c, lens_id id, lens_info *out)
     out->threads = L->g.nt;
     out->lds_bytes = (int64_t)lensk::ring_bytes(L->g);
     out->psf_used = L->g.k;
+    out->amplitudes = L->amplitudes;
+    out->light_model = L->light_model;
+    out->n_amplitudes = lensk::mode_solved(L->g.mode) ? lensk::mode_channels(L->g.mode) : 2;
     {
         DeviceGuard dg(c->device);
         out->blocks_per_cu = lensk::loglike_blocks_per_cu(L->g);
@@ -979,7 +1001,7 @@ lens_status sync_buffers(lens_ctx *c, int64_t n)
         c->h_params = c->h_out = nullptr;
         c->h_cap = 0;
         HIPCHK(c, hipHostMalloc((void **)&c->h_params, cap * lensk::kStride * sizeof(double), hipHostMallocDefault));
-        HIPCHK(c, hipHostMalloc((void **)&c->h_out, cap * 3 * sizeof(double), hipHostMallocDefault));
+        HIPCHK(c, hipHostMalloc((void **)&c->h_out, cap * 5 * sizeof(double), hipHostMallocDefault));
         c->h_cap = cap;
     }
     const size_t need = scratch_bytes((int64_t)c->h_cap, true);
@@ -1052,7 +1074,8 @@ extern "C" lens_status lens_loglike_amps(lens_ctx *c, lens_id id, const double *
         release(c, L);
         return LENS_OK;
     }
-    const bool solved = L->g.mode == lensk::MODE_FP32N;
+    const bool solved = lensk::mode_solved(L->g.mode);
+    const int na = solved ? lensk::mode_channels(L->g.mode) : 2;
     DeviceGuard dg(c->device);
     lens_status rs = LENS_OK;
     {
@@ -1064,12 +1087,12 @@ extern "C" lens_status lens_loglike_amps(lens_ctx *c, lens_id id, const double *
             hipError_t e = hipMemcpyAsync(S.params, c->h_params, (size_t)n * lensk::kStride * sizeof(double),
                                           hipMemcpyHostToDevice, c->stream);
             if (e == hipSuccess) e = launch_lens(L, S.params, S.pc, n, S.out, c->stream, solved ? S.amp : nullptr);
-            // staging: out at [0, n), amplitudes at [h_cap, h_cap + 2n) (S.amp = S.out + h_cap)
+            // staging: out at [0, n), amplitudes at [h_cap, h_cap + na n) (S.amp = S.out + h_cap)
             double *h_amp = c->h_out + c->h_cap;
             if (e == hipSuccess)
                 e = hipMemcpyAsync(c->h_out, S.out, (size_t)n * sizeof(double), hipMemcpyDeviceToHost, c->stream);
             if (e == hipSuccess && solved)
-                e = hipMemcpyAsync(h_amp, S.amp, (size_t)n * 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+                e = hipMemcpyAsync(h_amp, S.amp, (size_t)n * na * sizeof(double), hipMemcpyDeviceToHost, c->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
             if (e != hipSuccess) {
                 rs = hip_fail(c, e, "lens_loglike_amps");
@@ -1078,8 +1101,7 @@ extern "C" lens_status lens_loglike_amps(lens_ctx *c, lens_id id, const double *
                 for (int64_t i = 0; i < n; ++i) {
                     const bool ok = out[i] != -INFINITY;
                     if (solved) {
-                        out_amp[2 * i] = ok ? h_amp[2 * i] : NAN;
-                        out_amp[2 * i + 1] = ok ? h_amp[2 * i + 1] : NAN;
+                        for (int a = 0; a < na; ++a) out_amp[na * i + a] = ok ? h_amp[na * i + a] : NAN;
                     } else {
                         out_amp[2 * i] = ok ? params[i * lensk::kStride + 7] : NAN;
                         out_amp[2 * i + 1] = ok ? params[i * lensk::kStride + 12] : NAN;
@@ -1194,14 +1216,20 @@ lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int
         gg.grid = c->num_cus * lensk::batch_blocks_per_cu(gg.mode, gg.nt, gg.lds);
         gs.push_back(gg);
     }
-    // device layout: params | pc | out | geoms | lstart | lout | counters
+    // light model of every proposal: one for all, or per lens by proposal offset
+    bool one_model = true;
+    for (int i = 1; i < nlens; ++i) one_model = one_model && Ls[i]->light_model == Ls[0]->light_model;
+    std::vector<int> hmodel(nlens);
+    for (int i = 0; i < nlens; ++i) hmodel[i] = Ls[i]->light_model;
+    // device layout: params | pc | out | geoms | lstart | lout | counters | pstart | pmodel
     const size_t b_par = align_up((size_t)tot * lensk::kStride * 8, kAlign);
     const size_t b_pc = align_up((size_t)tot * lensk::kPCBytes, kAlign);
     const size_t b_out = align_up((size_t)tot * 8, kAlign);
     const size_t b_geom = align_up(hgeom.size() * sizeof(LensGeom), kAlign);
     const size_t b_ls = align_up(hls.size() * 4, kAlign), b_lo = align_up(hlo.size() * 8, kAlign);
     const size_t b_cnt = align_up(gs.size() * 4 + 4, kAlign);
-    pl->bytes = b_par + b_pc + b_out + b_geom + b_ls + b_lo + b_cnt;
+    const size_t b_ps = align_up((size_t)(nlens + 1) * 8, kAlign), b_pm = align_up((size_t)nlens * 4, kAlign);
+    pl->bytes = b_par + b_pc + b_out + b_geom + b_ls + b_lo + b_cnt + b_ps + b_pm;
     if (!charge(c, (int64_t)pl->bytes)) return fail(c, LENS_ENOMEM, "HBM budget exhausted (batch plan)");
     pl->dev = dev_alloc(c, pl->bytes);
     if (!pl->dev) {
@@ -1216,6 +1244,8 @@ lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int
     int *d_ls = (int *)((char *)d_geom + b_geom);
     int64_t *d_lo = (int64_t *)((char *)d_ls + b_ls);
     unsigned int *d_cnt = (unsigned int *)((char *)d_lo + b_lo);
+    int64_t *d_ps = (int64_t *)((char *)d_cnt + b_cnt);
+    int *d_pm = (int *)((char *)d_ps + b_ps);
     Plan *raw = pl.get();
     auto bail = [&](hipError_t e, const char *what) {
         raw->used = 0;
@@ -1227,6 +1257,10 @@ lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int
     if (e == hipSuccess) e = hipMemcpyAsync(d_geom, hgeom.data(), hgeom.size() * sizeof(LensGeom), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d_ls, hls.data(), hls.size() * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d_lo, hlo.data(), hlo.size() * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && !one_model)
+        e = hipMemcpyAsync(d_ps, off.data(), (size_t)(nlens + 1) * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess && !one_model)
+        e = hipMemcpyAsync(d_pm, hmodel.data(), (size_t)nlens * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return bail(e, "batch plan set-up");
     // capture: the graph holds only copies and kernels (the work counters are
@@ -1234,7 +1268,9 @@ lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int
     e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bail(e, "hipStreamBeginCapture");
     hipError_t ce = hipMemcpyAsync(d_par, pl->h_params, (size_t)tot * lensk::kStride * 8, hipMemcpyHostToDevice, c->stream);
-    if (ce == hipSuccess) ce = lensk::launch_prep(d_par, tot, d_pc, c->stream);
+    if (ce == hipSuccess)
+        ce = one_model ? lensk::launch_prep(d_par, tot, d_pc, hmodel[0], nullptr, nullptr, 0, c->stream)
+                       : lensk::launch_prep(d_par, tot, d_pc, 0, d_ps, d_pm, nlens, c->stream);
     for (size_t gi = 0; gi < gs.size() && ce == hipSuccess; ++gi) {
         const G &gg = gs[gi];
         ce = lensk::launch_batch(gg.mode, gg.nt, gg.grid, gg.lds, d_geom + gg.o_geom, d_ls + gg.o_ls, d_lo + gg.o_lo,
@@ -1334,7 +1370,7 @@ extern "C" lens_status lens_model_image(lens_ctx *c, lens_id id, const double *p
             lensk::PropBlock pc{};
             std::vector<float> hi((size_t)npix);
             hipError_t e = hipMemcpyAsync(dp, params1, lensk::kStride * sizeof(double), hipMemcpyHostToDevice, c->stream);
-            if (e == hipSuccess) e = lensk::launch_prep(dp, 1, dpc, c->stream);
+            if (e == hipSuccess) e = lensk::launch_prep(dp, 1, dpc, LENS_LIGHT_BOTH, nullptr, nullptr, 0, c->stream);
             if (e == hipSuccess) e = hipMemcpyAsync(&pc, dpc, sizeof(pc), hipMemcpyDeviceToHost, c->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
             if (e == hipSuccess && pc.valid != 1.0) {

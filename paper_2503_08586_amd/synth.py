@@ -66,6 +66,21 @@ def draw_params(rng: np.random.Generator, n: int) -> np.ndarray:
     return out
 
 
+# the fixed Sersic indices of the two-component light model (Sec. 3.2): an
+# exponential disc and a de Vaucouleurs bulge per galaxy
+DOUBLE_SERSIC_N = (1.0, 4.0, 1.0, 4.0)
+
+
+def double_component_params(rng: np.random.Generator, params: np.ndarray) -> np.ndarray:
+    """Proposals of the two-component light model: a copy of ``params`` whose
+    n_l and n_s slots hold the second components' R_e, R_a x U[0.3, 3]."""
+    out = np.array(params, dtype=np.float64, copy=True)
+    n = out.shape[0]
+    out[:, SLOT["n_l"]] = out[:, SLOT["R_l"]] * rng.uniform(0.3, 3.0, n)
+    out[:, SLOT["n_s"]] = out[:, SLOT["R_s"]] * rng.uniform(0.3, 3.0, n)
+    return out
+
+
 def gaussian_psf(k: int, fwhm: float, dpix: float) -> np.ndarray:
     """k x k Gaussian, point-sampled at pixel centres, normalised to unit sum."""
     assert k % 2 == 1

@@ -57,9 +57,36 @@ def test_struct_layouts_match_header():
     # the ctypes mirrors of the ABI structs must have the C sizes (x86-64 SysV)
     from paper_2503_08586_amd import binding
     assert ctypes.sizeof(binding.lens_init_opts) == 4 + 4 + 8 + 4 + 4 + 8 * 4 + 8
-    assert ctypes.sizeof(binding.lens_data_desc) == 4 + 4 + 8 + 4 + 4 + 8 * 4 + 8 + 8
-    assert ctypes.sizeof(binding.lens_info) == 5 * 4 + 4 + 8 * 4 + 2 * 4 + 8 + 2 * 4
+    assert ctypes.sizeof(binding.lens_data_desc) == 4 + 4 + 8 + 4 + 4 + 8 * 4 + 4 + 4 + 8 + 4 + 4 + 8 * 4
+    assert ctypes.sizeof(binding.lens_info) == 5 * 4 + 4 + 8 * 4 + 2 * 4 + 8 + 5 * 4 + 4
     assert ctypes.sizeof(binding.lens_stats) == 10 * 8
+
+
+def test_struct_offsets_match_compiled_header(tmp_path):
+    # every field of the ctypes mirrors sits at the offset a C compiler gives it
+    import shutil
+    import subprocess
+    from paper_2503_08586_amd import binding
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [binding.lens_init_opts, binding.lens_data_desc, binding.lens_info, binding.lens_stats]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lens_api.h"', "int main(void) {"]
+    expect = []
+    for st in structs:
+        name = st.__name__
+        lines.append('printf("%%zu\\n", sizeof(%s));' % name)
+        expect.append(ctypes.sizeof(st))
+        for f, _ in st._fields_:
+            lines.append('printf("%%zu\\n", offsetof(%s, %s));' % (name, f))
+            expect.append(getattr(st, f).offset)
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(v) for v in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == expect
 
 
 def test_no_cpu_fallback_in_product_path():
