@@ -27,6 +27,9 @@ NPARAM_STRIDE = 20
 
 _dp = ctypes.POINTER(ctypes.c_double)
 _u8p = ctypes.POINTER(ctypes.c_uint8)
+_u32p = ctypes.POINTER(ctypes.c_uint32)
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
 
 
 def compile_oracle(src: str, out: str) -> str:
@@ -78,6 +81,10 @@ class Oracle:
             "oracle_loglike_nnls": ([i, i, d, i, i, _dp, _dp, _dp, _u8p, _dp, i64, _dp, _dp, _dp, i], i),
             "oracle_loglike_light": ([i, i, d, i, i, _dp, _dp, _dp, _u8p, _dp, i64, i, _dp, _dp, _dp, _dp, i], i),
             "oracle_num_threads": ([], i),
+            "oracle_philox4x32_10": ([_u32p, _u32p, _u32p], None),
+            "oracle_stretch_propose": ([i, i, i64, ctypes.c_uint64, d, _dp, _dp, _dp, _dp, _i32p], None),
+            "oracle_stretch_accept": ([i, i, i, _dp, _dp, _dp, _dp, _dp, _dp, _i64p], None),
+            "oracle_box_logprior": ([_dp, _dp, _dp], d),
         }
         for name, (args, res) in sig.items():
             fn = getattr(lib, name)
@@ -250,6 +257,62 @@ class Oracle:
 
     def num_threads(self) -> int:
         return self.lib.oracle_num_threads()
+
+    # -- sampler loop: the stretch move (Goodman & Weare 2010) driven by
+    #    Philox4x32-10 (Salmon et al. 2011), posterior of Sec. 2.2 -----------
+    def philox(self, ctr, key):
+        """The four Philox4x32-10 words of counter ``ctr`` (4 words) under ``key`` (2 words)."""
+        c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(4)
+        k = np.ascontiguousarray(key, dtype=np.uint32).reshape(2)
+        out = np.empty(4, dtype=np.uint32)
+        self.lib.oracle_philox4x32_10(_ptr(c, _u32p), _ptr(k, _u32p), _ptr(out, _u32p))
+        return out
+
+    def stretch_propose(self, walkers, half, t, seed, a):
+        """Proposals of half ``half`` in iteration ``t``: (Y [W/2, 20], z, ln u, partner index)."""
+        w = _f64(walkers).reshape(-1, NPARAM_STRIDE)
+        W = w.shape[0]
+        assert W % 2 == 0 and half in (0, 1)
+        h = W // 2
+        Y = np.empty((h, NPARAM_STRIDE))
+        z = np.empty(h)
+        logu = np.empty(h)
+        j = np.empty(h, dtype=np.int32)
+        self.lib.oracle_stretch_propose(W, int(half), int(t), int(seed), float(a), _ptr(w), _ptr(Y), _ptr(z),
+                                        _ptr(logu), _ptr(j, _i32p))
+        return Y, z, logu, j
+
+    def stretch_accept(self, walkers, lnp, half, d, Y, lnpY, z, logu, accepted=None):
+        """Acceptance of half ``half`` in place on ``walkers`` [W, 20] and ``lnp`` [W]."""
+        assert walkers.dtype == np.float64 and walkers.flags.c_contiguous
+        assert lnp.dtype == np.float64 and lnp.flags.c_contiguous
+        W = walkers.shape[0]
+        Y, lnpY, z, logu = _f64(Y), _f64(lnpY), _f64(z), _f64(logu)
+        acc = None
+        if accepted is not None:
+            assert accepted.dtype == np.int64 and accepted.flags.c_contiguous
+            acc = _ptr(accepted, _i64p)
+        self.lib.oracle_stretch_accept(W, int(half), int(d), _ptr(walkers), _ptr(lnp), _ptr(Y), _ptr(lnpY),
+                                       _ptr(z), _ptr(logu), acc)
+
+    def box_logprior(self, p, lo, hi) -> float:
+        """0 inside the uniform box [lo, hi] (every slot), -inf outside."""
+        return self.lib.oracle_box_logprior(_ptr(_f64(p)), _ptr(_f64(lo)), _ptr(_f64(hi)))
+
+    def ensemble_iteration(self, walkers, lnp, t, seed, a, lo, hi, loglike, accepted=None, trace=None):
+        """One iteration of the ensemble (half 0, then half 1) in place.  ``loglike(P)``
+        gives lnL of proposals [m, 20]; those outside the box get lnP = -inf and are
+        not evaluated.  ``trace`` (a list) receives (Y, z, ln u, partner, lnP(Y)) per half."""
+        d = int(np.count_nonzero(np.asarray(hi) > np.asarray(lo)))
+        for half in (0, 1):
+            Y, z, logu, j = self.stretch_propose(walkers, half, t, seed, a)
+            inside = np.array([self.box_logprior(y, lo, hi) == 0.0 for y in Y])
+            lnpY = np.full(len(Y), -np.inf)
+            if inside.any():
+                lnpY[inside] = loglike(Y[inside])
+            self.stretch_accept(walkers, lnp, half, d, Y, lnpY, z, logu, accepted)
+            if trace is not None:
+                trace.append((Y, z, logu, j, lnpY))
 
 
 _default = None

@@ -20,6 +20,11 @@
  *   - light amplitudes by non-negative least squares            (Sec. 2.3)
  *   - light models with one or two components per galaxy, and lens-only /
  *     source-only fits                           (Sec. 3.1.2, Sec. 3.2 set-ups)
+ *   - a sampler loop whose proposals never leave the device (the direction of
+ *     Sec. 4.2, against the transfer overhead of Sec. 3.1.4): the ensemble
+ *     stretch move of Goodman & Weare (2010, CAMCoS 5, 65), driven by the
+ *     Philox4x32-10 counter-based generator of Salmon et al. (2011, SC'11),
+ *     with the posterior of Sec. 2.2 under a uniform box prior
  *
  * Everything is FP64, scalar loops, libm only, on the full supersampled grid
  * (no skipping outside the mask), with a full-image direct convolution.
@@ -680,6 +685,100 @@ int oracle_loglike_light(int ny, int nx, double dpix, int s, int k, const double
         free(img);
     }
     return bad ? -1 : 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Counter-based random numbers: Philox4x32-10 (Salmon, Moraes, Dror & Shaw, */
+/* "Parallel random numbers: as easy as 1, 2, 3", SC'11, Sec. 3)             */
+/* ------------------------------------------------------------------------ */
+/* Ten rounds on a 4 x 32-bit counter under a 2 x 32-bit key.  One round
+ * multiplies the counter's words 0 and 2 by the two Philox constants, takes
+ * the 64-bit products apart, and recombines them with words 1 and 3 and the
+ * round key; the key advances by the two Weyl increments between rounds. */
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;    /* multipliers */
+    const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;    /* key increments */
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t p0 = (uint64_t)M0 * c0, p1 = (uint64_t)M1 * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0, n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ensemble sampler: the stretch move (Goodman & Weare 2010, Sec. 3; its      */
+/* parallel form splits the walkers in two halves that update in turn)       */
+/* ------------------------------------------------------------------------ */
+/* W walkers (W even), each a 20-slot parameter vector; half h holds walkers
+ * [h W/2, (h+1) W/2).  In iteration t, half h moves; walker k of that half
+ * draws the Philox words of counter (k, t mod 2^32, t div 2^32, 0) under key
+ * (seed mod 2^32, seed div 2^32):
+ *   word 0 -> partner j = (other half's first walker) + floor(word0 * (W/2) / 2^32)
+ *   word 1 -> u1 = (word1 + 1/2) / 2^32,  z = ((a - 1) u1 + 1)^2 / a,
+ *             distributed with density proportional to 1/sqrt(z) on [1/a, a]
+ *   word 2 -> u2 = (word2 + 1/2) / 2^32
+ * The proposal is Y = X_j + z (X_k - X_j); it replaces X_k when
+ *   ln u2 < (d - 1) ln z + lnP(Y) - lnP(X_k),
+ * d being the number of free slots.  Proposal of one half: */
+void oracle_stretch_propose(int W, int half, int64_t t, uint64_t seed, double a, const double *walkers,
+                            double *Y, double *z_out, double *logu_out, int32_t *partner_out)
+{
+    const int h = W / 2;
+    const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    for (int i = 0; i < h; ++i) {
+        const int k = half * h + i;
+        const uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(uint64_t)t, (uint32_t)((uint64_t)t >> 32), 0u};
+        uint32_t r[4];
+        oracle_philox4x32_10(ctr, key, r);
+        const int j = (1 - half) * h + (int)(((uint64_t)r[0] * (uint64_t)h) >> 32);
+        const double u1 = ((double)r[1] + 0.5) / 4294967296.0;
+        const double u2 = ((double)r[2] + 0.5) / 4294967296.0;
+        const double w = (a - 1.0) * u1 + 1.0;
+        const double z = w * w / a;
+        for (int s = 0; s < ORC_NP; ++s)
+            Y[(size_t)i * ORC_NP + s] = walkers[(size_t)j * ORC_NP + s] +
+                z * (walkers[(size_t)k * ORC_NP + s] - walkers[(size_t)j * ORC_NP + s]);
+        z_out[i] = z;
+        logu_out[i] = log(u2);
+        if (partner_out) partner_out[i] = j;
+    }
+}
+
+/* Acceptance of one half: lnpY[i] is lnP of proposal i (-inf outside the
+ * prior); accepted walkers take Y and lnpY, and their counters advance. */
+void oracle_stretch_accept(int W, int half, int d, double *walkers, double *lnp, const double *Y,
+                           const double *lnpY, const double *z, const double *logu, int64_t *accepted)
+{
+    const int h = W / 2;
+    for (int i = 0; i < h; ++i) {
+        const int k = half * h + i;
+        const double lhs = logu[i], rhs = (d - 1) * log(z[i]) + lnpY[i] - lnp[k];
+        if (lnpY[i] > -INFINITY && lhs < rhs) {
+            memcpy(walkers + (size_t)k * ORC_NP, Y + (size_t)i * ORC_NP,
+                   ORC_NP * sizeof(double));
+            lnp[k] = lnpY[i];
+            if (accepted) accepted[k] += 1;
+        }
+    }
+}
+
+/* ln of the uniform box prior up to its constant: 0 when lo[s] <= p[s] <=
+ * hi[s] for every slot, else -inf (Sec. 2.2: posterior = likelihood x prior) */
+double oracle_box_logprior(const double *p, const double *lo, const double *hi)
+{
+    for (int s = 0; s < ORC_NP; ++s)
+        if (!(p[s] >= lo[s] && p[s] <= hi[s])) return -INFINITY;
+    return 0.0;
 }
 
 int oracle_num_threads(void)

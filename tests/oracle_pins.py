@@ -659,4 +659,184 @@ def pin_light_model_domain(orc):
     assert out[0] == -np.inf
 
 
+# ----------------------------------------------------------------------------
+# sampler loop: Philox4x32-10 (Salmon et al. 2011) and the stretch move
+# (Goodman & Weare 2010) on the posterior of Sec. 2.2 under a box prior
+# ----------------------------------------------------------------------------
+GOLDEN = __import__("os").path.join(__import__("os").path.dirname(__import__("os").path.abspath(__file__)), "golden")
+
+
+def philox_kat():
+    """(counter, key, expected words) rows of the published Philox4x32-10 known answers."""
+    rows = []
+    with open(GOLDEN + "/philox4x32_10_kat.txt") as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            w = [int(v, 16) for v in line.split()]
+            rows.append((w[0:4], w[4:6], w[6:10]))
+    return rows
+
+
+def pin_philox_known_answers(orc):
+    rows = philox_kat()
+    assert len(rows) == 3
+    for ctr, key, want in rows:
+        got = [int(v) for v in orc.philox(ctr, key)]
+        assert got == want, (ctr, key, ["%08x" % v for v in got])
+
+
+def _gauss_case(d=5):
+    mu = np.zeros(20)
+    sig = np.ones(20)
+    mu[:d] = np.arange(d) * 0.5 - 1.0
+    sig[:d] = 0.3 + 0.2 * np.arange(d)
+    lo = np.zeros(20)
+    hi = np.zeros(20)
+    lo[:d] = mu[:d] - 50 * sig[:d]
+    hi[:d] = mu[:d] + 50 * sig[:d]
+    return mu, sig, lo, hi
+
+
+def pin_stretch_z_distribution(orc):
+    # z = ((a-1)u+1)^2/a is the inverse CDF of g(z) ~ 1/sqrt(z) on [1/a, a]:
+    # F(z) = (sqrt(a z) - 1)/(a - 1); the words -> u map is (word + 1/2) 2^-32
+    a, W = 2.7, 64
+    w = np.zeros((W, 20))
+    for t in range(3):
+        Y, z, logu, j = orc.stretch_propose(w, t % 2, t, 99, a)
+        for i in range(W // 2):
+            k = (t % 2) * (W // 2) + i
+            r = orc.philox([k, t, 0, 0], [99, 0])
+            u1 = (float(r[1]) + 0.5) / 2.0 ** 32
+            u2 = (float(r[2]) + 0.5) / 2.0 ** 32
+            assert 1.0 / a <= z[i] <= a
+            assert abs((math.sqrt(a * z[i]) - 1.0) / (a - 1.0) - u1) < 1e-12, (z[i], u1)
+            assert abs(logu[i] - math.log(u2)) < 1e-15
+    # the empirical distribution of z over many draws follows F
+    zs = np.concatenate([orc.stretch_propose(np.zeros((512, 20)), 0, t, 5, a)[1] for t in range(8)])
+    ks = scipy.stats.kstest(zs, lambda x: (np.sqrt(a * np.clip(x, 1 / a, a)) - 1.0) / (a - 1.0))
+    assert ks.pvalue > 1e-3, ks
+
+
+def pin_stretch_partner_in_other_half(orc):
+    W = 16
+    h = W // 2
+    counts = np.zeros(W, dtype=np.int64)
+    for t in range(400):
+        for half in (0, 1):
+            _, _, _, j = orc.stretch_propose(np.zeros((W, 20)), half, t, 3, 2.0)
+            assert np.all((j >= (1 - half) * h) & (j < (2 - half) * h)), (half, j)
+            np.add.at(counts, j, 1)
+            # the partner's offset is the high word of word0 * (W/2)
+            for i in range(h):
+                r = orc.philox([half * h + i, t, 0, 0], [3, 0])
+                assert j[i] == (1 - half) * h + (int(r[0]) * h >> 32)
+    assert scipy.stats.chisquare(counts).pvalue > 1e-3, counts
+
+
+def pin_stretch_proposal_line_and_fixed_slots(orc):
+    rng = np.random.default_rng(8)
+    W = 10
+    w = rng.normal(size=(W, 20))
+    w[:, 5] = 0.75            # a slot every walker shares stays exactly put
+    w[:, 19] = 0.0
+    Y, z, _, j = orc.stretch_propose(w, 1, 7, 21, 2.0)
+    for i in range(W // 2):
+        k = W // 2 + i
+        assert Y[i, 5] == 0.75 and Y[i, 19] == 0.0
+        # Y - X_j is z times X_k - X_j: parallel, with ratio z
+        dv, uv = Y[i] - w[j[i]], w[k] - w[j[i]]
+        assert abs(np.dot(dv, uv) / np.dot(uv, uv) - z[i]) < 1e-12
+        assert np.linalg.norm(dv - z[i] * uv) < 1e-12 * np.linalg.norm(uv)
+
+
+def pin_stretch_flat_target_acceptance(orc):
+    # with lnP constant inside the box, a move is taken with probability
+    # min(1, z^(d-1)); averaged over g(z) = 1/(c sqrt(z)) on [1/a, a], with
+    # c = 2 (sqrt(a) - 1/sqrt(a)), that is
+    # (1 - a^-(d-1/2)) / ((d - 1/2) c) + 2 (sqrt(a) - 1) / c
+    a, W, d = 2.0, 256, 3
+    c = 2.0 * (math.sqrt(a) - 1.0 / math.sqrt(a))
+    p_acc = ((1.0 - a ** -(d - 0.5)) / (d - 0.5) + 2.0 * (math.sqrt(a) - 1.0)) / c
+    lo = np.zeros(20)
+    hi = np.zeros(20)
+    hi[:d] = 1e9
+    lo[:d] = -1e9
+    w = np.zeros((W, 20))
+    w[:, :d] = np.random.default_rng(2).normal(size=(W, d))
+    lnp = np.zeros(W)
+    acc = np.zeros(W, dtype=np.int64)
+    T = 40
+    for t in range(T):
+        orc.ensemble_iteration(w, lnp, t, 17, a, lo, hi, lambda P: np.zeros(len(P)), accepted=acc)
+    n = W * T
+    rate = acc.sum() / n
+    assert abs(rate - p_acc) < 4.0 * math.sqrt(p_acc * (1 - p_acc) / n), (rate, p_acc)
+    # d = 1: every proposal inside the box is taken
+    lo1, hi1 = np.zeros(20), np.zeros(20)
+    lo1[0], hi1[0] = -1e9, 1e9
+    w1 = np.zeros((8, 20))
+    w1[:, 0] = np.arange(8.0)
+    acc1 = np.zeros(8, dtype=np.int64)
+    orc.ensemble_iteration(w1, np.zeros(8), 0, 4, a, lo1, hi1, lambda P: np.zeros(len(P)), accepted=acc1)
+    assert np.all(acc1 == 1)
+
+
+def pin_stretch_box_prior(orc):
+    # proposals outside the box are never taken, and are never evaluated
+    lo = np.zeros(20)
+    hi = np.zeros(20)
+    lo[:2], hi[:2] = 0.0, 1.0
+    rng = np.random.default_rng(4)
+    w = np.zeros((16, 20))
+    w[:, :2] = rng.uniform(0.0, 1.0, size=(16, 2))
+    lnp = np.zeros(16)
+    seen = []
+
+    def ll(P):
+        assert np.all((P[:, :2] >= 0.0) & (P[:, :2] <= 1.0))
+        seen.append(len(P))
+        return np.zeros(len(P))
+    for t in range(30):
+        orc.ensemble_iteration(w, lnp, t, 9, 3.0, lo, hi, ll)
+        assert np.all((w[:, :2] >= 0.0) & (w[:, :2] <= 1.0)) and np.all(w[:, 2:] == 0.0)
+    assert 0 < sum(seen) < 30 * 16
+    assert orc.box_logprior(w[0], lo, hi) == 0.0
+    q = w[0].copy()
+    q[1] = 1.0 + 1e-12
+    assert orc.box_logprior(q, lo, hi) == -np.inf
+    q[1] = np.nan
+    assert orc.box_logprior(q, lo, hi) == -np.inf
+
+
+def pin_stretch_samples_gaussian(orc):
+    # the ensemble's stationary distribution is the target: 5-d Gaussian,
+    # 32 walkers, 1,200 kept iterations; means within 0.2 sigma, variances
+    # within 15% (Monte Carlo error ~4%)
+    d, W, T, burn = 5, 32, 1500, 300
+    mu, sig, lo, hi = _gauss_case(d)
+    rng = np.random.default_rng(5)
+    w = np.zeros((W, 20))
+    w[:, :d] = mu[:d] + 0.1 * sig[:d] * rng.normal(size=(W, d))
+
+    def ll(P):
+        return -0.5 * np.sum(((P[:, :d] - mu[:d]) / sig[:d]) ** 2, axis=1)
+    lnp = ll(w)
+    keep = []
+    for t in range(T):
+        for half in (0, 1):
+            Y, z, logu, _ = orc.stretch_propose(w, half, t, 11, 2.0)
+            orc.stretch_accept(w, lnp, half, d, Y, ll(Y), z, logu)
+        if t >= burn:
+            keep.append(w[:, :d].copy())
+    S = np.concatenate(keep)
+    m = (S.mean(0) - mu[:d]) / sig[:d]
+    v = S.var(0) / sig[:d] ** 2
+    assert np.all(np.abs(m) < 0.2), m
+    assert np.all(np.abs(v - 1.0) < 0.15), v
+    # lnp tracks the walkers
+    assert np.allclose(lnp, ll(w), rtol=0, atol=1e-12)
+
+
 ALL_PINS = [v for k, v in sorted(globals().items()) if k.startswith("pin_")]

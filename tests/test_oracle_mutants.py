@@ -54,6 +54,14 @@ MUTANTS = {
                                     "for (int c = 1; c < N; ++c) mval += cand[c] * col[(size_t)c * npix + i];")],
     "light_mass_in_lens_only": [("int mass = model != 1, lens = model != 2, src = model != 1;",
                                  "int mass = 1, lens = model != 2, src = model != 1;")],
+    "philox_no_key_bump": [("            k0 += W0;\n            k1 += W1;\n", "")],
+    "philox_words_swapped": [("n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;", "n1 = lo0, n2 = hi0 ^ c3 ^ k1, n3 = lo1;")],
+    "stretch_drop_dimension_factor": [("rhs = (d - 1) * log(z[i])", "rhs = 0.0 * log(z[i])")],
+    "stretch_partner_same_half": [("const int j = (1 - half) * h +", "const int j = half * h +")],
+    "stretch_z_not_squared": [("const double z = w * w / a;", "const double z = w / a;")],
+    "stretch_accept_inverted": [("if (lnpY[i] > -INFINITY && lhs < rhs) {", "if (lnpY[i] > -INFINITY && lhs > rhs) {")],
+    "stretch_counter_ignores_iteration": [("const uint32_t ctr[4] = {(uint32_t)k, (uint32_t)(uint64_t)t,",
+                                           "const uint32_t ctr[4] = {(uint32_t)k, 0u,")],
     "lens_light_not_supersampled": [("acc += orc_scene(p, bl, bs, x, y);",
                                      "acc += orc_scene(p, bl, bs, x, y) - oracle_sersic(p[7], p[8], p[9], bl, p[10], p[11], p[3], p[4], x, y) + oracle_sersic(p[7], p[8], p[9], bl, p[10], p[11], p[3], p[4], ((double)j - 0.5 * (nx - 1)) * dpix, ((double)i - 0.5 * (ny - 1)) * dpix);")],
 }
