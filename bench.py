@@ -12,10 +12,12 @@ The CPU-baseline leg times the FP64 oracle on a bounded sample of the same
 proposals on the host's cores and checks the GPU results of that sample
 against it.
 
---workload batch|precision|serving runs the other measurements (256 uneven
-lenses in one persistent graph-captured launch vs one lens at a time; 64
-lenses of 200x200 px with a 41x41 Moffat PSF per convolution precision; a
-Poisson request stream over 1,000 resident lenses with p50/p99 latency).
+--workload batch|precision|serving|sampler runs the other measurements (256
+uneven lenses in one persistent graph-captured launch vs one lens at a time;
+64 lenses of 200x200 px with a 41x41 Moffat PSF per convolution precision; a
+Poisson request stream over 1,000 resident lenses with p50/p99 latency; a
+stretch-move ensemble that proposes, evaluates and accepts on the device vs
+the same moves driven from the host).
 """
 from __future__ import annotations
 
@@ -47,7 +49,8 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target wall time of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (for HBM counter calibration)")
-    ap.add_argument("--workload", default="plain", choices=["plain", "batch", "precision", "serving"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "batch", "precision", "serving", "sampler"])
+    ap.add_argument("--walkers", type=int, default=16384, help="sampler: ensemble size")
     ap.add_argument("--precision", default=None, choices=["fp32", "split", "bf16", "split3"])
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--amplitudes", default="explicit", choices=["explicit", "nnls"],
@@ -165,6 +168,8 @@ def main():
         return run_precision(args)
     if args.workload == "serving":
         return run_serving(args)
+    if args.workload == "sampler":
+        return run_sampler(args)
     if args.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
         y = torch.empty_like(x)
@@ -353,6 +358,105 @@ def run_batch(args):
         "subpixel_evals_per_s": evs / step_s,
     }
     print(json.dumps(rec), flush=True)
+    ctx.close()
+
+
+def _host_stretch(binding, ctx, lid, w, lnp, lo, hi, a, iters, rng):
+    """The stretch move driven from the host (numpy draws, host-buffer lnL calls):
+    the transfer pattern of a host-side sampler, for comparison with the device loop."""
+    W = w.shape[0]
+    h = W // 2
+    d = int(np.count_nonzero(hi > lo))
+    for _ in range(iters):
+        for half in (0, 1):
+            k = np.arange(half * h, (half + 1) * h)
+            j = (1 - half) * h + rng.integers(0, h, h)
+            z = ((a - 1.0) * rng.random(h) + 1.0) ** 2 / a
+            Y = w[j] + z[:, None] * (w[k] - w[j])
+            inside = np.all((Y >= lo) & (Y <= hi), axis=1)
+            lnY = np.full(h, -np.inf)
+            lnY[inside] = ctx.loglike(lid, Y[inside])
+            take = np.log(rng.random(h)) < (d - 1) * np.log(z) + lnY - lnp[k]
+            w[k[take]] = Y[take]
+            lnp[k[take]] = lnY[take]
+
+
+def run_sampler(args):
+    """Device-resident sampler loop on the plain survey-scale lens: an ensemble of
+    --walkers walkers moved by the stretch move, each half-step's proposals made,
+    evaluated and accepted on the device; one step = one iteration (W proposals)."""
+    import torch
+
+    from paper_2503_08586_amd import binding, synth
+    spec = synth.config2(nprop=1)[0]
+    ctx, st = _stream_ctx(binding, torch)
+    gpu_data(ctx, spec)
+    lid = ctx.load(spec)
+    info = ctx.info(lid)
+    lo = np.array([b[1] for b in synth.PRIOR_BOX] + [0.0])
+    hi = np.array([b[2] for b in synth.PRIOR_BOX] + [0.0])
+    W = args.walkers
+    rng = np.random.default_rng(synth.SEED_BASE + 6)
+    init = np.clip(spec.truth[None, :] + 0.02 * (hi - lo)[None, :] * rng.normal(size=(W, 20)), lo, hi)
+    ens = ctx.ensemble(lid, init, lo, hi, stretch=2.0, seed=synth.SEED_BASE)
+    ctx.ensemble_run(ens, args.warmup)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(st)
+    ctx.ensemble_run(ens, args.steps)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    loop_s = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    n = W * args.steps
+    w, lnp, acc, it = ctx.ensemble_get(ens)
+    # the same moves from the host: numpy draws, proposals and results over PCIe
+    hw, hl = init.copy(), ctx.loglike(lid, init)
+    hsteps = max(1, args.steps // 4)
+    t2 = time.perf_counter()
+    _host_stretch(binding, ctx, lid, hw, hl, lo, hi, 2.0, hsteps, rng)
+    host_s = time.perf_counter() - t2
+    host_rate = W * hsteps / host_s
+    slots_per_prop, E = credited_slots(spec, info)
+    cpu = None
+    max_err = None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.default()
+        threads = orc.num_threads()
+        tc0 = time.perf_counter()
+        orc.loglike(spec.geom, spec.psf, spec.data, spec.sigma, spec.mask, w[:threads])
+        per = (time.perf_counter() - tc0) / threads
+        ns = int(max(threads, min(W, round(args.cpu_seconds / max(per, 1e-9)))))
+        tc0 = time.perf_counter()
+        ref, chi2 = orc.loglike(spec.geom, spec.psf, spec.data, spec.sigma, spec.mask, w[:ns], return_chi2=True)
+        tc = time.perf_counter() - tc0
+        C = orc.loglike_norm(spec.sigma, spec.mask)
+        max_err = float((np.abs(lnp[:ns] - ref) / (0.5 * chi2 + abs(C))).max())
+        cpu = {"value": ns / tc, "unit": "loglike evals/s", "cores": threads, "kind": "oracle",
+               "sample": "lnL of the first %d final walkers, %.1f s" % (ns, tc)}
+    rec = {
+        "metric": METRIC, "value": n / loop_s, "unit": "loglike evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": loop_s / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": path_dtype(None),
+        "data": "synthetic",
+        "config": {"workload": "sampler loop on the device: %d-walker stretch-move ensemble on the plain "
+                               "survey-scale lens (128x128 px, s=4, 21x21 PSF), one step = one iteration "
+                               "(%d proposals made, evaluated and accepted on the device)" % (W, W),
+                   "walkers": W, "acceptance": float(acc.sum()) / max(1, W * it)},
+        "host_driven_loop_evals_per_s": host_rate,
+        "device_over_host_loop": (n / loop_s) / host_rate,
+        "roofline": {"bound": "alu", "achieved": slots_per_prop * n / (gpu_ms * 1e-3) / 1e12,
+                     "peak": PEAK_SLOT_PER_S / 1e12, "unit": "Tslot/s",
+                     "frac": slots_per_prop * n / (gpu_ms * 1e-3) / PEAK_SLOT_PER_S, "traffic": None,
+                     "kernel": "k_stretch_propose + k_loglike_fp32 + k_stretch_accept per half-step",
+                     "loop_ms": gpu_ms},
+        "cpu_baseline": cpu,
+        "max_rel_err_vs_oracle": max_err,
+    }
+    print(json.dumps(rec), flush=True)
+    ctx.ensemble_destroy(ens)
     ctx.close()
 
 

@@ -105,6 +105,7 @@ typedef int32_t lens_status;
 typedef struct lens_ctx lens_ctx;
 typedef int64_t lens_id;
 typedef int64_t lens_req;
+typedef int64_t lens_ens;
 
 /* Device-memory hooks.  alloc returns a device pointer or NULL; both are
  * called with the context's device current. */
@@ -251,6 +252,68 @@ lens_status lens_wait(lens_ctx *ctx, lens_req req, int64_t timeout_us);
  * and discards it; out is then not written.  The id is forgotten. */
 lens_status lens_cancel(lens_ctx *ctx, lens_req req);
 lens_status lens_get_stats(lens_ctx *ctx, lens_stats *out);
+
+/* ------------------------------------------------------------------------
+ * Sampler loop on the device.  The paper's sampler runs on the host and
+ * moves every proposal batch across PCIe (Sec. 3.1.4); Sec. 4.2 points to
+ * sampling on the GPU.  Here an ensemble of walkers lives in device memory
+ * and moves by the stretch move of Goodman & Weare (2010, CAMCoS 5, 65,
+ * Sec. 3), in its parallel form: the two halves of the ensemble update in
+ * turn.  Proposals are made, evaluated and accepted on the device, and only
+ * the final state and the requested chain rows return to the host.
+ *
+ * Target: lnP = lnL under a uniform box prior (Sec. 2.2): lo[s] <= p[s] <=
+ * hi[s] for every slot s.  A slot with lo = hi is fixed; d = the number of
+ * free slots enters the acceptance rule.  Fix the slots the lens ignores
+ * (slot 19; slots 7 and 12 with LENS_AMP_NNLS; the unused slots of a light
+ * model): free slots that do not change lnL only add random-walk directions.
+ *
+ * Iteration t, walker k of the moving half (half 0: walkers 0..W/2-1, then
+ * half 1): the Philox4x32-10 words (Salmon et al., SC'11) of counter
+ * (k, t mod 2^32, t div 2^32, 0) under key (seed mod 2^32, seed div 2^32),
+ * with u = (word + 1/2) 2^-32, give
+ *   partner j = (first walker of the other half) + floor(word0 (W/2) / 2^32),
+ *   z = ((a - 1) u1 + 1)^2 / a   (density ~ 1/sqrt(z) on [1/a, a]),
+ *   u2 from word 2;
+ * the proposal Y = X_j + z (X_k - X_j) replaces X_k when
+ *   ln u2 < (d - 1) ln z + lnP(Y) - lnP(X_k).
+ * Proposals outside the box get lnP = -inf without being evaluated.  The
+ * stream depends only on (seed, k, t): a run split over several calls equals
+ * one long run. */
+typedef struct lens_ensemble_desc {
+    int32_t walkers;            /* W, even, 4..2^24 (each half-step evaluates W/2 proposals) */
+    double stretch;             /* a > 1 (Goodman & Weare use 2) */
+    uint64_t seed;              /* Philox key */
+    const double *lo, *hi;      /* [20] box prior, finite, lo <= hi, at least one free slot */
+    const double *init;         /* [W][20] initial walkers, inside the box, each with finite lnL */
+} lens_ensemble_desc;
+
+/* Copies the walkers to the device and evaluates their lnP.  The ensemble
+ * holds its lens (lens_unload answers LENS_EBUSY) until destroyed.
+ * LENS_EINVAL for a bad descriptor, a walker outside the box or one whose
+ * lnL is -inf; LENS_ENOMEM past the HBM budget. */
+lens_status lens_ensemble_create(lens_ctx *ctx, lens_id id, const lens_ensemble_desc *desc, lens_ens *out);
+/* Advances the ensemble by `iterations` iterations (each moves both halves),
+ * entirely on the device, blocking until done.  chain (may be NULL): host
+ * [iterations/thin][W][20], the walkers after every thin-th iteration of this
+ * call; chain_lnp (may be NULL): host [iterations/thin][W], their lnP.  The
+ * chain rows are staged in device memory (charged to the HBM budget) and
+ * copied back at the end: split long runs into several calls. */
+lens_status lens_ensemble_run(lens_ctx *ctx, lens_ens ens, int64_t iterations, int32_t thin,
+                              double *chain, double *chain_lnp);
+/* The current walkers [W][20], their lnP [W], accepted moves per walker [W]
+ * and the iterations done so far; any output may be NULL. */
+lens_status lens_ensemble_get(lens_ctx *ctx, lens_ens ens, double *walkers, double *lnp,
+                              int64_t *accepted, int64_t *iteration);
+/* Frees the ensemble and releases its lens.  LENS_EBUSY during a call on it. */
+lens_status lens_ensemble_destroy(lens_ctx *ctx, lens_ens ens);
+/* The Philox4x32-10 words (Salmon et al., SC'11: ten rounds, multipliers
+ * 0xD2511F53 and 0xCD9E8D57, key increments 0x9E3779B9 and 0xBB67AE85) of
+ * the n counters (ctr[0] + i mod 2^32, ctr[1], ctr[2], ctr[3]), i < n <= 2^32,
+ * under key[2], computed on the device into out [n][4] (host).  The stream
+ * the sampler draws from, exposed for reproduction and tests. */
+lens_status lens_philox4x32_10(lens_ctx *ctx, const uint32_t *ctr, const uint32_t *key, int64_t n,
+                               uint32_t *out);
 
 /* Debug/test: the model image of one proposal (params1: 20 doubles) into
  * out_img [ny][nx]: stage 0 binned and unconvolved, stage 1 PSF-convolved.

@@ -52,6 +52,8 @@ EXPORTED = [
     "lens_loglike_batch", "lens_loglike_amps", "lens_loglike_batch_device", "lens_loglike_multi",
     "lens_submit", "lens_poll", "lens_wait", "lens_cancel", "lens_get_stats",
     "lens_model_image", "lens_selftest", "lens_psf_crop", "lens_strerror", "lens_last_error",
+    "lens_ensemble_create", "lens_ensemble_run", "lens_ensemble_get", "lens_ensemble_destroy",
+    "lens_philox4x32_10",
 ]
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
@@ -103,6 +105,17 @@ class lens_info(ctypes.Structure):
     ]
 
 
+class lens_ensemble_desc(ctypes.Structure):
+    _fields_ = [
+        ("walkers", ctypes.c_int32),
+        ("stretch", ctypes.c_double),
+        ("seed", ctypes.c_uint64),
+        ("lo", ctypes.POINTER(ctypes.c_double)),
+        ("hi", ctypes.POINTER(ctypes.c_double)),
+        ("init", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
 class lens_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "requests_submitted", "requests_done", "requests_failed", "requests_canceled",
@@ -129,6 +142,7 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
     i64p = ctypes.POINTER(ctypes.c_int64)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
     sig = {
         "lens_init": ([ctypes.POINTER(lens_init_opts), ctypes.POINTER(vp)], i32),
         "lens_shutdown": ([vp], None),
@@ -147,6 +161,11 @@ def load():
         "lens_model_image": ([vp, i64, dp, i32, dp], i32),
         "lens_selftest": ([vp, i32, dp], i32),
         "lens_psf_crop": ([dp, i32, ctypes.c_double, ctypes.POINTER(i32)], i32),
+        "lens_ensemble_create": ([vp, i64, ctypes.POINTER(lens_ensemble_desc), i64p], i32),
+        "lens_ensemble_run": ([vp, i64, i64, i32, dp, dp], i32),
+        "lens_ensemble_get": ([vp, i64, dp, dp, i64p, i64p], i32),
+        "lens_ensemble_destroy": ([vp, i64], i32),
+        "lens_philox4x32_10": ([vp, u32p, u32p, i64, u32p], i32),
         "lens_strerror": ([i32], ctypes.c_char_p),
         "lens_last_error": ([vp], ctypes.c_char_p),
     }
@@ -289,6 +308,75 @@ def lens_loglike_amps(ctx, lens_id, params):
     amp = np.empty((p.shape[0], info.n_amplitudes), dtype=np.float64)
     _check(ctx, load().lens_loglike_amps(ctx, lens_id, _dptr(p), p.shape[0], _dptr(out), _dptr(amp)))
     return out, amp
+
+
+def lens_ensemble_create(ctx, lens_id, init, lo, hi, stretch=2.0, seed=0) -> int:
+    """A stretch-move ensemble on the device from walkers ``init`` [W, 20] in the box [lo, hi]."""
+    w = _params(init)
+    lo = np.ascontiguousarray(lo, dtype=np.float64).reshape(STRIDE)
+    hi = np.ascontiguousarray(hi, dtype=np.float64).reshape(STRIDE)
+    d = lens_ensemble_desc()
+    d.walkers = w.shape[0]
+    d.stretch = float(stretch)
+    d.seed = int(seed) & 0xFFFFFFFFFFFFFFFF
+    d.lo, d.hi, d.init = _dptr(lo), _dptr(hi), _dptr(w)
+    eid = ctypes.c_int64()
+    _check(ctx, load().lens_ensemble_create(ctx, lens_id, ctypes.byref(d), ctypes.byref(eid)))
+    _ens_sizes[(ctx, eid.value)] = w.shape[0]
+    return eid.value
+
+
+def lens_ensemble_get(ctx, ens):
+    """(walkers [W, 20], lnP [W], accepted [W], iterations done)."""
+    it = ctypes.c_int64()
+    W = _ens_walkers(ctx, ens)
+    w = np.empty((W, STRIDE))
+    lnp = np.empty(W)
+    acc = np.empty(W, dtype=np.int64)
+    _check(ctx, load().lens_ensemble_get(ctx, ens, _dptr(w), _dptr(lnp),
+                                         acc.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ctypes.byref(it)))
+    return w, lnp, acc, it.value
+
+
+_ens_sizes = {}   # (context, ensemble) -> walkers
+
+
+def _ens_walkers(ctx, ens):
+    try:
+        return _ens_sizes[(ctx, ens)]
+    except KeyError:
+        raise LensError(LENS_ENOENT, "unknown ensemble id") from None
+
+
+def lens_ensemble_run(ctx, ens, iterations, thin=0, chain=False):
+    """Advance ``iterations`` iterations on the device; with ``chain`` returns
+    (chain [iterations/thin, W, 20], chain_lnp [iterations/thin, W])."""
+    if not chain:
+        _check(ctx, load().lens_ensemble_run(ctx, ens, int(iterations), int(thin), None, None))
+        return None
+    thin = max(1, int(thin))
+    W = _ens_walkers(ctx, ens)
+    ns = int(iterations) // thin
+    cw = np.empty((ns, W, STRIDE))
+    cl = np.empty((ns, W))
+    _check(ctx, load().lens_ensemble_run(ctx, ens, int(iterations), thin, _dptr(cw), _dptr(cl)))
+    return cw, cl
+
+
+def lens_ensemble_destroy(ctx, ens):
+    _check(ctx, load().lens_ensemble_destroy(ctx, ens))
+    _ens_sizes.pop((ctx, ens), None)
+
+
+def lens_philox4x32_10(ctx, ctr, key, n) -> np.ndarray:
+    """Philox4x32-10 words [n, 4] of counters (ctr[0] + i, ctr[1], ctr[2], ctr[3]), computed on the device."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32).reshape(4)
+    k = np.ascontiguousarray(key, dtype=np.uint32).reshape(2)
+    out = np.empty((int(n), 4), dtype=np.uint32)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    _check(ctx, load().lens_philox4x32_10(ctx, c.ctypes.data_as(u32p), k.ctypes.data_as(u32p), int(n),
+                                          out.ctypes.data_as(u32p)))
+    return out
 
 
 def lens_unload(ctx, lens_id):
@@ -449,6 +537,22 @@ class LensContext:
 
     def info(self, lid) -> dict:
         return lens_get_info(self.ctx, lid)
+
+    def ensemble(self, lid, init, lo, hi, stretch=2.0, seed=0) -> int:
+        """A device-resident stretch-move ensemble on lens ``lid`` (walkers ``init`` [W, 20])."""
+        return lens_ensemble_create(self.ctx, lid, init, lo, hi, stretch, seed)
+
+    def ensemble_run(self, ens, iterations, thin=0, chain=False):
+        return lens_ensemble_run(self.ctx, ens, iterations, thin, chain)
+
+    def ensemble_get(self, ens):
+        return lens_ensemble_get(self.ctx, ens)
+
+    def ensemble_destroy(self, ens):
+        lens_ensemble_destroy(self.ctx, ens)
+
+    def philox(self, ctr, key, n) -> np.ndarray:
+        return lens_philox4x32_10(self.ctx, ctr, key, n)
 
     def submit(self, lid, params) -> Request:
         return lens_submit(self.ctx, lid, params)

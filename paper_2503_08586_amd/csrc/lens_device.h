@@ -136,17 +136,22 @@ __device__ __forceinline__ double sie_a2(double u2, double ce, double bsie, doub
 
 // Elliptical Sersic (Eqs. 8, 10) without its amplitude, from r2 = (R/R_e)^2:
 //   exp(-b ((R/R_e)^(1/n) - 1)) = 2^(B (1 - t)),  t = r2^(1/(2n)),  B = b log2 e.
-// log2 r2 is clamped to [-2048, 128] in one FP32 med3: the centre (r2 = 0)
-// then gives t = 2^-(2048 e) ~ 0 and an overflowing radius a finite t, so every
-// exponent below stays finite; B (1 - t) >= -2000 keeps the last exponent in
-// int range (2^-2000 is 0 in FP64).
+// log2 r2 = (binary exponent of r2) + log2(mantissa in [1/2, 1)), the FP32
+// hardware log2 seeing only the mantissa and the sum taken in FP64: an absolute
+// error of ~1e-7 at any magnitude.  (An FP32 log2 of r2 itself is good to one
+// ulp of its result, ~1e-6 absolute once |log2 r2| nears 20, i.e. next to a
+// steep Sersic centre, and the exponent carries that error into the
+// brightness.)  The mantissa's log2 is clamped below at -2048, so the centre
+// (r2 = 0) gives t = 2^-(2048 e) ~ 0 rather than NaN; a radius whose t
+// overflows gives B (1 - t) = -inf, clamped to -2000 (2^-2000 is 0 in FP64).
 // lead: the leading coefficient of kExp2_64 (see horner).
-__device__ __forceinline__ float log2_r2(double r2)
+__device__ __forceinline__ double log2_r2(double r2)
 {
-    return __builtin_amdgcn_fmed3f(hw_log2((float)r2), -2048.0f, 128.0f);
+    const float lm = __builtin_amdgcn_fmed3f(hw_log2((float)__builtin_amdgcn_frexp_mant(r2)), -2048.0f, 0.0f);
+    return (double)__builtin_amdgcn_frexp_exp(r2) + (double)lm;
 }
 
-// 2^(B (1 - t)) with t = 2^(e lgd), lgd = log2 of (R/R_e)^2 (clamped as above)
+// 2^(B (1 - t)) with t = 2^(e lgd), lgd = log2 of (R/R_e)^2 (as above)
 __device__ __forceinline__ double sersic_lg(double lgd, double e, double B, double lead)
 {
     const double t = exp2_64(kExp2_64, e * lgd, lead);
@@ -155,7 +160,7 @@ __device__ __forceinline__ double sersic_lg(double lgd, double e, double B, doub
 
 __device__ __forceinline__ double sersic_r2(double r2, const LightK &L, double lead)
 {
-    return sersic_lg((double)log2_r2(r2), L.e, L.B, lead);
+    return sersic_lg(log2_r2(r2), L.e, L.B, lead);
 }
 
 // (R/R_e)^2 = P dx^2 + Q dy^2 + S dx dy at offset (dx, dy) from a light centre,
@@ -238,13 +243,13 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
                     acc[0] += sersic_r2(fma(fma(P.lens.P, dx, rs), dx, rq), P.lens, lead);
                     acc[1] += sersic_r2(ellip_r2(bx, by, P.src), P.src, lead);
                 } else {
-                    const double lgs = (double)log2_r2(ellip_r2(bx, by, P.src));
+                    const double lgs = log2_r2(ellip_r2(bx, by, P.src));
                     acc[IS] += sersic_lg(lgs, es, Bs, lead);
                     if constexpr (DBL) acc[IS + 1] += sersic_lg(lgs + P.dlg_s, g.fix_e[3], g.fix_B[3], lead);
                 }
             }
             if constexpr (LENS && (DBL || !SRC)) {
-                const double lgl = (double)log2_r2(fma(fma(P.lens.P, dx, rs), dx, rq));
+                const double lgl = log2_r2(fma(fma(P.lens.P, dx, rs), dx, rq));
                 acc[0] += sersic_lg(lgl, el, Bl, lead);
                 if constexpr (DBL) acc[1] += sersic_lg(lgl + P.dlg_l, g.fix_e[1], g.fix_B[1], lead);
             }

@@ -132,6 +132,17 @@ int loglike_blocks_per_cu(const LensGeom &g);    // resident single-lens workgro
 hipError_t launch_batch(int mode, int nt, int grid, size_t lds, const LensGeom *d_geoms, const int *d_lstart,
                         const int64_t *d_lout, int nl, int nitems, const PropBlock *d_pc, double *d_out,
                         unsigned int *d_counter, hipStream_t st);
+// sampler loop (lens_sampler.hip): Philox4x32-10 words of counters
+// (ctr[0] + i, ctr[1], ctr[2], ctr[3]), i < n, into d_out [n][4]; the two
+// halves of a stretch-move step (d_aux: [W/2][4] doubles)
+hipError_t launch_philox_words(const uint32_t ctr[4], const uint32_t key[2], int64_t n, uint32_t *d_out,
+                               hipStream_t st);
+hipError_t launch_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int light_model,
+                                  const double *d_walkers, const double *d_lo, const double *d_hi, double *d_Y,
+                                  double *d_aux, PropBlock *d_pc, hipStream_t st);
+hipError_t launch_stretch_accept(int W, int half, int d, double *d_walkers, double *d_lnp, const double *d_Y,
+                                 const double *d_aux, const double *d_lnl, int64_t *d_accepted, double *d_chain_w,
+                                 double *d_chain_lnp, hipStream_t st);
 // self-test of the matrix-core operand layout: D = A B for a 16x32 by 32x16 BF16 product
 hipError_t launch_mfma_probe(const uint16_t *d_a, const uint16_t *d_b, float *d_d, hipStream_t st);
 // stage 0: binned image of one proposal into d_img [ny][nx]; stage 1: convolved,

@@ -17,31 +17,15 @@
 
 #include "lens_device.h"
 #include "lens_internal.h"
+#include "lens_prep.h"
 
 namespace lensk {
 
 // ---------------------------------------------------------------------------
 // prep
 // ---------------------------------------------------------------------------
-__device__ LightK light_constants(double I, double R, double n, double q, double phi)
-{
-    // x1 = c dx + s dy, x2 = -s dx + c dy, (R_p/R_e)^2 = (q x1^2 + x2^2/q) / R_e^2
-    const double c = cos(phi), s = sin(phi), A = q / (R * R), Bq = 1.0 / (q * R * R);
-    LightK L;
-    L.P = A * c * c + Bq * s * s;
-    L.Q = A * s * s + Bq * c * c;
-    L.S = 2.0 * (A - Bq) * c * s;
-    L.e = 0.5 / n;
-    L.B = sersic_bn(n) * 1.4426950408889634;
-    L.I = I;
-    return L;
-}
-
-// One thread per proposal.  The light model decides which slots are read and
-// validated: lens light only ignores the mass, shear and source slots; source
-// only ignores the lens light; two components per galaxy read slots n_l and
-// n_s as the second components' R_e (their indices are fixed per lens and
-// taken from the lens descriptor by the likelihood kernel).
+// One thread per proposal; the light model of proposal i is `model`, or, with
+// a per-lens table, that of the lens owning i.
 __global__ void __launch_bounds__(256) k_prep(const double *__restrict__ params, int64_t n, PropBlock *__restrict__ pc,
                                               int model, const int64_t *__restrict__ pstart,
                                               const int *__restrict__ pmodel, int nl)
@@ -58,58 +42,10 @@ __global__ void __launch_bounds__(256) k_prep(const double *__restrict__ params,
         lm = pmodel[lo];
     }
     const double *p = params + i * kStride;
-    PropBlock b{};
     double v[19];
 #pragma unroll
     for (int j = 0; j < 19; ++j) v[j] = p[j];
-    const bool mass = lm != LIGHT_LENS, lens = lm != LIGHT_SRC, src = lm != LIGHT_LENS, dbl = lm == LIGHT_DOUBLE;
-    bool ok = isfinite(v[3]) && isfinite(v[4]);
-    if (mass) {
-#pragma unroll
-        for (int j = 0; j < 7; ++j) ok = ok && isfinite(v[j]);
-        ok = ok && v[0] >= 0.0 && v[1] > 0.0 && v[1] <= 1.0;
-    }
-    if (lens) {
-        ok = ok && isfinite(v[8]) && isfinite(v[9]) && isfinite(v[10]) && isfinite(v[11]);
-        ok = ok && v[10] > 0.0 && v[10] <= 1.0 && v[8] > 0.0;
-        ok = ok && (dbl ? v[9] > 0.0 : v[9] >= kNMin && v[9] <= kNMax);
-    }
-    if (src) {
-#pragma unroll
-        for (int j = 13; j < 19; ++j) ok = ok && isfinite(v[j]);
-        ok = ok && v[15] > 0.0 && v[15] <= 1.0 && v[13] > 0.0;
-        ok = ok && (dbl ? v[14] > 0.0 : v[14] >= kNMin && v[14] <= kNMax);
-    }
-    const bool amps_ok = isfinite(v[7]) && isfinite(v[12]);
-    if (ok) {
-        b.valid = (lm == LIGHT_BOTH && amps_ok) ? 1.0 : 2.0;
-        b.xm = v[3];
-        b.ym = v[4];
-        if (mass) {
-            const double q = v[1];
-            b.cm = cos(v[2]);
-            b.sm = sin(v[2]);
-            b.q2m = q * q;
-            b.ce = sqrt((1.0 - q) * (1.0 + q));
-            b.bsie = v[0] * sqrt(q);
-            b.bsc = b.ce > 0.0 ? b.bsie / b.ce : 0.0;
-            b.g1 = v[5];
-            b.g2 = v[6];
-            b.g1p = 1.0 + v[5];
-        }
-        // two-component light: e and B of the fixed indices come from the lens descriptor
-        if (lens) b.lens = light_constants(v[7], v[8], dbl ? 1.0 : v[9], v[10], v[11]);
-        if (src) {
-            b.xs = v[17];
-            b.ys = v[18];
-            b.src = light_constants(v[12], v[13], dbl ? 1.0 : v[14], v[15], v[16]);
-        }
-        if (dbl) {
-            b.dlg_l = 2.0 * log2(v[8] / v[9]);
-            b.dlg_s = 2.0 * log2(v[13] / v[14]);
-        }
-    }
-    pc[i] = b;
+    pc[i] = prep_proposal(v, lm);
 }
 
 // ---------------------------------------------------------------------------
@@ -305,12 +241,12 @@ struct MomN {
         for (int i = 0; i < NM; ++i) m[i] += o.m[i];
         return *this;
     }
-    __device__ void add(const float (&c)[NCH], float d, float w)
+    __device__ void add(const double (&c)[NCH], float d, float w)
     {
         double wc[NCH];
         const double wd = (double)w * (double)d;
 #pragma unroll
-        for (int a = 0; a < NCH; ++a) wc[a] = (double)w * (double)c[a];
+        for (int a = 0; a < NCH; ++a) wc[a] = (double)w * c[a];
         int i = 0;
 #pragma unroll
         for (int a = 0; a < NCH; ++a)
@@ -407,11 +343,10 @@ __device__ __forceinline__ void strip_loop_solved(const LensGeom &g, const PropB
 {
     constexpr int NCH = mode_channels(MODE), NM = MomN<NCH>::NM;
     __shared__ double red[NM][NT / 64];
-    if constexpr (NCH == 2) {
+    if constexpr (NCH >= 2) {
         // each strip's moments are reduced over the wave and added to the
         // wave's LDS slots at once, so that no FP64 accumulators stay live
-        // through the next strip's ray trace (74 VGPRs instead of 82: one
-        // more resident workgroup per CU)
+        // through the next strip's ray trace
         for (int i = threadIdx.x; i < NM * (NT / 64); i += NT) (&red[0][0])[i] = 0.0;
         (void)strip_sweep<MODE, NT, MomN<NCH>>(g, P, ring, evl, evpre, evr, [&](int y0, int y1, int st) {
             MomN<NCH> mo = conv(y0, y1, st);
@@ -422,8 +357,7 @@ __device__ __forceinline__ void strip_loop_solved(const LensGeom &g, const PropB
             return MomN<NCH>{};
         });
     } else {
-        // one reduction at the end (for four channels the strip-wise one does
-        // not raise occupancy and costs more than it saves)
+        // one channel: few moments, a single reduction at the end
         MomN<NCH> mo = strip_sweep<MODE, NT, MomN<NCH>>(g, P, ring, evl, evpre, evr, conv);
 #pragma unroll
         for (int i = 0; i < NM; ++i) mo.m[i] = wave_sum(mo.m[i]);
@@ -463,7 +397,7 @@ __device__ __forceinline__ double conv_rows(const LensGeom &g, const float *ring
     for (int gi = cvpre[ya] + threadIdx.x; gi < gb; gi += NT) {
         const uint32_t e = cvl[gi];
         const int y = (int)(e >> 16), x0 = (int)(e & 0xffffu);
-        float o0 = 0.f, o1 = 0.f, o2 = 0.f, o3 = 0.f;
+        double o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;   // sum over PSF rows in FP64
         int slot = y % RB;  // ring slot of binned row y - r
 #pragma unroll 1
         for (int a = 0; a < K; ++a) {
@@ -487,18 +421,18 @@ __device__ __forceinline__ double conv_rows(const LensGeom &g, const float *ring
                 p2 = fmaf(w, win[b + 2], p2);
                 p3 = fmaf(w, win[b + 3], p3);
             }
-            o0 += p0;
-            o1 += p1;
-            o2 += p2;
-            o3 += p3;
+            o0 += (double)p0;
+            o1 += (double)p1;
+            o2 += (double)p2;
+            o3 += (double)p3;
             slot = (slot + 1 == RB) ? 0 : slot + 1;
         }
         const float4 d = *reinterpret_cast<const float4 *>(data + (size_t)y * g.pitch + x0);
         const float4 w = *reinterpret_cast<const float4 *>(wgt + (size_t)y * g.pitch + x0);
-        const double r0 = (double)((d.x - o0) * w.x);
-        const double r1 = (double)((d.y - o1) * w.y);
-        const double r2 = (double)((d.z - o2) * w.z);
-        const double r3 = (double)((d.w - o3) * w.w);
+        const double r0 = ((double)d.x - o0) * (double)w.x;
+        const double r1 = ((double)d.y - o1) * (double)w.y;
+        const double r2 = ((double)d.z - o2) * (double)w.z;
+        const double r3 = ((double)d.w - o3) * (double)w.w;
         acc = fma(r0, r0, acc);
         acc = fma(r1, r1, acc);
         acc = fma(r2, r2, acc);
@@ -654,7 +588,7 @@ __device__ __forceinline__ double conv_rows_rt(const LensGeom &g, const float *r
     for (int gi = g.cvpre[ya] + threadIdx.x; gi < gb; gi += NT) {
         const uint32_t e = g.cvl[gi];
         const int y = (int)(e >> 16), x0 = (int)(e & 0xffffu);
-        float o0 = 0.f, o1 = 0.f, o2 = 0.f, o3 = 0.f;
+        double o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;   // sum over PSF rows in FP64
         int slot = y % RB;
         for (int a = 0; a < k; ++a) {
             const float *row = ring + slot * W + x0;
@@ -676,18 +610,18 @@ __device__ __forceinline__ double conv_rows_rt(const LensGeom &g, const float *r
                 p0 = fmaf(w, v0, p0); p1 = fmaf(w, v1, p1); p2 = fmaf(w, v2, p2); p3 = fmaf(w, v3, p3);
                 v0 = v1; v1 = v2; v2 = v3;
             }
-            o0 += p0;
-            o1 += p1;
-            o2 += p2;
-            o3 += p3;
+            o0 += (double)p0;
+            o1 += (double)p1;
+            o2 += (double)p2;
+            o3 += (double)p3;
             slot = (slot + 1 == RB) ? 0 : slot + 1;
         }
         const float4 d = *reinterpret_cast<const float4 *>(g.data + (size_t)y * g.pitch + x0);
         const float4 w = *reinterpret_cast<const float4 *>(g.wgt + (size_t)y * g.pitch + x0);
-        const double r0 = (double)((d.x - o0) * w.x);
-        const double r1 = (double)((d.y - o1) * w.y);
-        const double r2 = (double)((d.z - o2) * w.z);
-        const double r3 = (double)((d.w - o3) * w.w);
+        const double r0 = ((double)d.x - o0) * (double)w.x;
+        const double r1 = ((double)d.y - o1) * (double)w.y;
+        const double r2 = ((double)d.z - o2) * (double)w.z;
+        const double r3 = ((double)d.w - o3) * (double)w.w;
         acc = fma(r0, r0, acc);
         acc = fma(r1, r1, acc);
         acc = fma(r2, r2, acc);
@@ -718,7 +652,7 @@ __device__ __forceinline__ MomN<mode_channels(MODE)> conv_rows_solved(const Lens
     for (int gi = g.cvpre[ya] + threadIdx.x; gi < gb; gi += NT) {
         const uint32_t e = g.cvl[gi];
         const int y = (int)(e >> 16), x0 = (int)(e & 0xffffu);
-        float o[4][NCH] = {};
+        double o[4][NCH] = {};   // sums over PSF rows in FP64
 #pragma unroll
         for (int pass = 0; pass < NPASS; ++pass) {
             int slot = y % RB;
@@ -727,12 +661,13 @@ __device__ __forceinline__ MomN<mode_channels(MODE)> conv_rows_solved(const Lens
                 const float *kr = psf + a * k;
                 float pp[4][CP] = {};
                 typename V::T v0 = row[0], v1 = row[NPASS], v2 = row[2 * NPASS];
-                // up to two channels: four taps per step (their weights fetched
-                // together), then the tail; four channels: one tap per step (fewer
-                // live registers).  Per output and channel the fmaf order is
-                // ascending in b either way.
+                // one channel: four taps per step (their weights fetched
+                // together), then the tail; more channels: one tap per step
+                // (fewer live registers: one more resident workgroup per CU for
+                // two channels, 8.8e5 against 7.8e5 evals/s).  Per output and
+                // channel the fmaf order is ascending in b either way.
                 int b = 0;
-                for (; NCH <= 2 && b + 4 <= k; b += 4) {
+                for (; NCH == 1 && b + 4 <= k; b += 4) {
                     const float w0 = kr[b], w1 = kr[b + 1], w2 = kr[b + 2], w3 = kr[b + 3];
                     const typename V::T v3 = row[(b + 3) * NPASS], v4 = row[(b + 4) * NPASS];
                     const typename V::T v5 = row[(b + 5) * NPASS], v6 = row[(b + 6) * NPASS];
@@ -776,7 +711,7 @@ __device__ __forceinline__ MomN<mode_channels(MODE)> conv_rows_solved(const Lens
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
 #pragma unroll
-                    for (int c = 0; c < CP; ++c) o[j][CP * pass + c] += pp[j][c];
+                    for (int c = 0; c < CP; ++c) o[j][CP * pass + c] += (double)pp[j][c];
                 slot = (slot + 1 == RB) ? 0 : slot + 1;
             }
         }
@@ -914,7 +849,7 @@ __global__ void k_model_conv(const LensGeom g, const float *__restrict__ img, fl
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= g.ny * g.nx) return;
     const int y = i / g.nx, x = i % g.nx, k = g.k, r = g.r;
-    float o = 0.0f;
+    double o = 0.0;
     for (int a = 0; a < k; ++a) {
         const int yy = y - r + a;
         float pr = 0.0f;
@@ -923,9 +858,9 @@ __global__ void k_model_conv(const LensGeom g, const float *__restrict__ img, fl
             const float v = (yy >= 0 && yy < g.ny && xx >= 0 && xx < g.nx) ? img[yy * g.nx + xx] : 0.0f;
             pr = fmaf(g.psf[a * k + b], v, pr);
         }
-        o += pr;
+        o += (double)pr;
     }
-    out[i] = o;
+    out[i] = (float)o;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,88 @@
+// lens_prep.h -- derived constants of one proposal (the prep step of the
+// likelihood), shared by the prep kernel and the sampler's fused propose step.
+//
+// Cao et al. (2025), Sec. 2.4: SIE and shear constants (Eqs. 12-14), Sersic
+// constants with b_n from Eq. 9 and the rotation of Eq. 10 folded in.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "lens_device.h"
+#include "lens_internal.h"
+
+namespace lensk {
+
+__device__ inline LightK light_constants(double I, double R, double n, double q, double phi)
+{
+    // x1 = c dx + s dy, x2 = -s dx + c dy, (R_p/R_e)^2 = (q x1^2 + x2^2/q) / R_e^2
+    const double c = cos(phi), s = sin(phi), A = q / (R * R), Bq = 1.0 / (q * R * R);
+    LightK L;
+    L.P = A * c * c + Bq * s * s;
+    L.Q = A * s * s + Bq * c * c;
+    L.S = 2.0 * (A - Bq) * c * s;
+    L.e = 0.5 / n;
+    L.B = sersic_bn(n) * 1.4426950408889634;
+    L.I = I;
+    return L;
+}
+
+// Derived constants of the proposal with slots v[0..18] under light model
+// lm.  The light model decides which slots are read and validated: lens
+// light only ignores the mass, shear and source slots; source only ignores
+// the lens light; two components per galaxy read slots n_l and n_s as the
+// second components' R_e (their indices are fixed per lens and taken from the
+// lens descriptor by the likelihood kernel).
+__device__ inline PropBlock prep_proposal(const double *v, int lm)
+{
+    PropBlock b{};
+    const bool mass = lm != LIGHT_LENS, lens = lm != LIGHT_SRC, src = lm != LIGHT_LENS, dbl = lm == LIGHT_DOUBLE;
+    bool ok = isfinite(v[3]) && isfinite(v[4]);
+    if (mass) {
+#pragma unroll
+        for (int j = 0; j < 7; ++j) ok = ok && isfinite(v[j]);
+        ok = ok && v[0] >= 0.0 && v[1] > 0.0 && v[1] <= 1.0;
+    }
+    if (lens) {
+        ok = ok && isfinite(v[8]) && isfinite(v[9]) && isfinite(v[10]) && isfinite(v[11]);
+        ok = ok && v[10] > 0.0 && v[10] <= 1.0 && v[8] > 0.0;
+        ok = ok && (dbl ? v[9] > 0.0 : v[9] >= kNMin && v[9] <= kNMax);
+    }
+    if (src) {
+#pragma unroll
+        for (int j = 13; j < 19; ++j) ok = ok && isfinite(v[j]);
+        ok = ok && v[15] > 0.0 && v[15] <= 1.0 && v[13] > 0.0;
+        ok = ok && (dbl ? v[14] > 0.0 : v[14] >= kNMin && v[14] <= kNMax);
+    }
+    const bool amps_ok = isfinite(v[7]) && isfinite(v[12]);
+    if (ok) {
+        b.valid = (lm == LIGHT_BOTH && amps_ok) ? 1.0 : 2.0;
+        b.xm = v[3];
+        b.ym = v[4];
+        if (mass) {
+            const double q = v[1];
+            b.cm = cos(v[2]);
+            b.sm = sin(v[2]);
+            b.q2m = q * q;
+            b.ce = sqrt((1.0 - q) * (1.0 + q));
+            b.bsie = v[0] * sqrt(q);
+            b.bsc = b.ce > 0.0 ? b.bsie / b.ce : 0.0;
+            b.g1 = v[5];
+            b.g2 = v[6];
+            b.g1p = 1.0 + v[5];
+        }
+        // two-component light: e and B of the fixed indices come from the lens descriptor
+        if (lens) b.lens = light_constants(v[7], v[8], dbl ? 1.0 : v[9], v[10], v[11]);
+        if (src) {
+            b.xs = v[17];
+            b.ys = v[18];
+            b.src = light_constants(v[12], v[13], dbl ? 1.0 : v[14], v[15], v[16]);
+        }
+        if (dbl) {
+            b.dlg_l = 2.0 * log2(v[8] / v[9]);
+            b.dlg_s = 2.0 * log2(v[13] / v[14]);
+        }
+    }
+    return b;
+}
+
+}  // namespace lensk

@@ -129,6 +129,8 @@ thread_local std::unordered_map<const void *, std::string> t_err;
 // One multi-lens call shape (lens ids and proposal counts) captured as a
 // hipGraph: H2D params -> prep -> one persistent launch per (mode, workgroup
 // size) group -> D2H results.  Replayed for every call with the same shape.
+struct Ensemble;   // a sampler ensemble (defined with its entry points)
+
 struct Plan {
     std::vector<lens_id> ids;
     std::vector<int64_t> counts;
@@ -238,6 +240,10 @@ struct lens_ctx {
     std::map<std::string, std::pair<int, int>> tune_cache;
     std::string tune_file;
     int num_cus = 256;
+
+    // sampler ensembles (registry guarded by mu; each ensemble by its own mutex)
+    std::map<int64_t, Ensemble *> ensembles;
+    int64_t next_ens = 1;
 
     // multi-lens plans (graph-captured persistent launches), guarded by sync_mu
     std::map<std::string, struct Plan *> plans;
@@ -412,6 +418,25 @@ hipError_t launch_lens(const Lens *L, const double *d_params, lensk::PropBlock *
     return lensk::launch_loglike(L->g, d_pc, n, d_out, d_amp, st);
 }
 
+// A walker ensemble resident on the device (lens_ensemble_*).  It holds a
+// user reference on its lens until destroyed.
+struct Ensemble {
+    int64_t id = 0;
+    Lens *L = nullptr;
+    int W = 0, d = 0;             // walkers, free slots
+    double a = 2.0;               // stretch scale
+    uint64_t seed = 0;
+    int64_t t = 0;                // iterations done
+    void *slab = nullptr;         // lo | hi | walkers | lnp | accepted | Y | aux | pc | out
+    size_t bytes = 0;
+    double *lo = nullptr, *hi = nullptr, *walkers = nullptr, *lnp = nullptr, *Y = nullptr, *aux = nullptr,
+           *out = nullptr;
+    int64_t *accepted = nullptr;
+    lensk::PropBlock *pc = nullptr;
+    std::mutex mu;                // one call on an ensemble at a time
+    int users = 0;                // calls in progress (guarded by the context's mu)
+};
+
 void scheduler_main(lens_ctx *c);
 lens_status tune_lens(lens_ctx *c, Lens *L);
 void drop_plan(lens_ctx *c, Plan *pl);
@@ -516,6 +541,11 @@ extern "C" void lens_shutdown(lens_ctx *c)
     c->plans.clear();
     for (auto &kv : c->reqs) delete kv.second;
     c->reqs.clear();
+    for (auto &kv : c->ensembles) {
+        dev_free(c, kv.second->slab);
+        delete kv.second;
+    }
+    c->ensembles.clear();
     for (auto &kv : c->lenses) {
         dev_free(c, kv.second->slab);
         delete kv.second;
@@ -932,7 +962,7 @@ extern "C" lens_status lens_unload(lens_ctx *c, lens_id id)
         auto it = c->lenses.find(id);
         if (it == c->lenses.end()) return fail(c, LENS_ENOENT, "unknown lens id");
         L = it->second;
-        if (L->users > 0) return fail(c, LENS_EBUSY, "lens is in use by a running call");
+        if (L->users > 0) return fail(c, LENS_EBUSY, "lens is in use by a running call or a sampler ensemble");
         {
             std::lock_guard<std::mutex> sl(c->smu);
             if (L->requests > 0) return fail(c, LENS_EBUSY, "lens has serving requests in flight");
@@ -1715,5 +1745,265 @@ extern "C" lens_status lens_selftest(lens_ctx *c, int32_t which, double *result)
     double err = 0.0;
     for (int i = 0; i < 256; ++i) err = std::max(err, std::fabs((double)hd[i] - ref[i]));
     *result = err;
+    return LENS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sampler loop on the device: Philox4x32-10 words and stretch-move ensembles
+// ---------------------------------------------------------------------------
+extern "C" lens_status lens_philox4x32_10(lens_ctx *c, const uint32_t *ctr, const uint32_t *key, int64_t n,
+                                          uint32_t *out)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (!ctr || !key || n < 0 || (n > 0 && !out)) return fail(c, LENS_EINVAL, "bad ctr/key/out/n");
+    if (n > ((int64_t)1 << 32)) return fail(c, LENS_EINVAL, "n above 2^32 (the counter word would repeat)");
+    if (n == 0) return LENS_OK;
+    DeviceGuard dg(c->device);
+    std::lock_guard<std::mutex> lk(c->sync_mu);
+    void *dbuf = nullptr;
+    lens_status rs = stream_scratch(c, c->stream, (size_t)n * 16, &dbuf);
+    if (rs != LENS_OK) return rs;
+    hipError_t e = lensk::launch_philox_words(ctr, key, n, (uint32_t *)dbuf, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, dbuf, (size_t)n * 16, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return hip_fail(c, e, "lens_philox4x32_10");
+    return LENS_OK;
+}
+
+namespace {
+
+// the ensemble with a call reference taken (drop it with ensemble_done)
+Ensemble *ensemble_use(lens_ctx *c, lens_ens id)
+{
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->ensembles.find(id);
+    if (it == c->ensembles.end()) return nullptr;
+    it->second->users++;
+    return it->second;
+}
+
+void ensemble_done(lens_ctx *c, Ensemble *E)
+{
+    std::lock_guard<std::mutex> lk(c->mu);
+    E->users--;
+}
+
+void free_ensemble(lens_ctx *c, Ensemble *E)
+{
+    if (E->slab) {
+        (void)hipStreamSynchronize(c->stream);
+        dev_free(c, E->slab);
+        uncharge(c, (int64_t)E->bytes);
+    }
+    if (E->L) release(c, E->L);
+    delete E;
+}
+
+}  // namespace
+
+extern "C" lens_status lens_ensemble_create(lens_ctx *c, lens_id id, const lens_ensemble_desc *d, lens_ens *out)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (!d || !out || !d->lo || !d->hi || !d->init) return fail(c, LENS_EINVAL, "null descriptor, array or output");
+    const int W = d->walkers;
+    if (W < 4 || W > (1 << 24) || (W & 1)) return fail(c, LENS_EINVAL, "walkers must be even, 4..2^24");
+    if (!(d->stretch > 1.0) || !std::isfinite(d->stretch)) return fail(c, LENS_EINVAL, "stretch must be finite and > 1");
+    int dfree = 0;
+    for (int s = 0; s < lensk::kStride; ++s) {
+        if (!std::isfinite(d->lo[s]) || !std::isfinite(d->hi[s]) || d->lo[s] > d->hi[s])
+            return fail(c, LENS_EINVAL, "box bounds must be finite with lo <= hi");
+        dfree += d->hi[s] > d->lo[s];
+    }
+    if (dfree == 0) return fail(c, LENS_EINVAL, "the box fixes every slot");
+    for (int64_t k = 0; k < W; ++k)
+        for (int s = 0; s < lensk::kStride; ++s) {
+            const double v = d->init[k * lensk::kStride + s];
+            if (!(v >= d->lo[s] && v <= d->hi[s])) {
+                char msg[96];
+                snprintf(msg, sizeof(msg), "initial walker %lld is outside the box (slot %d)", (long long)k, s);
+                return fail(c, LENS_EINVAL, msg);
+            }
+        }
+    Lens *L = acquire(c, id);
+    if (!L) return fail(c, LENS_ENOENT, "unknown lens id");
+    DeviceGuard dg(c->device);
+    auto *E = new Ensemble();
+    E->L = L;
+    E->W = W;
+    E->d = dfree;
+    E->a = d->stretch;
+    E->seed = d->seed;
+    const size_t h = (size_t)W / 2, S = lensk::kStride;
+    const size_t o_lo = 0, o_hi = align_up(S * 8, kAlign), o_w = o_hi + align_up(S * 8, kAlign);
+    const size_t o_lnp = o_w + align_up((size_t)W * S * 8, kAlign), o_acc = o_lnp + align_up((size_t)W * 8, kAlign);
+    const size_t o_Y = o_acc + align_up((size_t)W * 8, kAlign), o_aux = o_Y + align_up(h * S * 8, kAlign);
+    const size_t o_pc = o_aux + align_up(h * 32, kAlign), o_out = o_pc + align_up((size_t)W * lensk::kPCBytes, kAlign);
+    E->bytes = o_out + align_up((size_t)W * 8, kAlign);
+    if (!charge(c, (int64_t)E->bytes)) {
+        E->bytes = 0;
+        free_ensemble(c, E);
+        return fail(c, LENS_ENOMEM, "HBM budget exhausted (ensemble)");
+    }
+    E->slab = dev_alloc(c, E->bytes);
+    if (!E->slab) {
+        uncharge(c, (int64_t)E->bytes);
+        E->bytes = 0;
+        free_ensemble(c, E);
+        return fail(c, LENS_ENOMEM, "device allocation failed (ensemble)");
+    }
+    char *b = (char *)E->slab;
+    E->lo = (double *)(b + o_lo);
+    E->hi = (double *)(b + o_hi);
+    E->walkers = (double *)(b + o_w);
+    E->lnp = (double *)(b + o_lnp);
+    E->accepted = (int64_t *)(b + o_acc);
+    E->Y = (double *)(b + o_Y);
+    E->aux = (double *)(b + o_aux);
+    E->pc = (lensk::PropBlock *)(b + o_pc);
+    E->out = (double *)(b + o_out);
+    std::vector<double> lnp0((size_t)W);
+    hipError_t e = hipMemcpyAsync(E->lo, d->lo, S * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(E->hi, d->hi, S * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(E->walkers, d->init, (size_t)W * S * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(E->accepted, 0, (size_t)W * 8, c->stream);
+    // lnP of the initial walkers (all inside the box): their lnL
+    if (e == hipSuccess) e = launch_lens(L, E->walkers, E->pc, W, E->lnp, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(lnp0.data(), E->lnp, (size_t)W * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        free_ensemble(c, E);
+        return hip_fail(c, e, "lens_ensemble_create");
+    }
+    for (int k = 0; k < W; ++k)
+        if (!(lnp0[(size_t)k] > -INFINITY)) {
+            char msg[96];
+            snprintf(msg, sizeof(msg), "initial walker %d has lnL = -inf (outside the model's domain)", k);
+            free_ensemble(c, E);
+            return fail(c, LENS_EINVAL, msg);
+        }
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        E->id = c->next_ens++;
+        c->ensembles[E->id] = E;
+    }
+    *out = E->id;
+    return LENS_OK;
+}
+
+namespace {
+lens_status ensemble_run(lens_ctx *c, Ensemble *E, int64_t iterations, int32_t thin, double *chain,
+                         double *chain_lnp, bool store);
+}
+
+extern "C" lens_status lens_ensemble_run(lens_ctx *c, lens_ens id, int64_t iterations, int32_t thin,
+                                         double *chain, double *chain_lnp)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (iterations < 0) return fail(c, LENS_EINVAL, "iterations must be >= 0");
+    const bool store = chain || chain_lnp;
+    if (store && thin < 1) return fail(c, LENS_EINVAL, "thin must be >= 1 when a chain is requested");
+    Ensemble *E = ensemble_use(c, id);
+    if (!E) return fail(c, LENS_ENOENT, "unknown ensemble id");
+    lens_status rs = ensemble_run(c, E, iterations, thin, chain, chain_lnp, store);
+    ensemble_done(c, E);
+    return rs;
+}
+
+namespace {
+
+lens_status ensemble_run(lens_ctx *c, Ensemble *E, int64_t iterations, int32_t thin, double *chain,
+                         double *chain_lnp, bool store)
+{
+    std::lock_guard<std::mutex> elk(E->mu);
+    DeviceGuard dg(c->device);
+    const int W = E->W, h = W / 2;
+    const size_t S = lensk::kStride;
+    const int64_t nstore = store ? iterations / thin : 0;
+    // device chain: [nstore][W][20] then [nstore][W]
+    void *dchain = nullptr;
+    size_t cbytes = 0;
+    if (nstore > 0) {
+        cbytes = (size_t)nstore * W * (S + 1) * 8;
+        if (!charge(c, (int64_t)cbytes)) return fail(c, LENS_ENOMEM, "HBM budget exhausted (chain)");
+        dchain = dev_alloc(c, cbytes);
+        if (!dchain) {
+            uncharge(c, (int64_t)cbytes);
+            return fail(c, LENS_ENOMEM, "device allocation failed (chain)");
+        }
+    }
+    double *cw = (double *)dchain, *cl = cw ? cw + (size_t)nstore * W * S : nullptr;
+    hipError_t e = hipSuccess;
+    for (int64_t it = 0; it < iterations && e == hipSuccess; ++it) {
+        const uint64_t t = (uint64_t)E->t + (uint64_t)it;
+        const bool keep = nstore > 0 && (it + 1) % thin == 0 && (it + 1) / thin <= nstore;
+        const int64_t slot = keep ? (it + 1) / thin - 1 : 0;
+        for (int half = 0; half < 2 && e == hipSuccess; ++half) {
+            e = lensk::launch_stretch_propose(W, half, t, E->seed, E->a, E->L->light_model, E->walkers, E->lo, E->hi,
+                                              E->Y, E->aux, E->pc, c->stream);
+            if (e == hipSuccess) e = lensk::launch_loglike(E->L->g, E->pc, h, E->out, nullptr, c->stream);
+            if (e == hipSuccess)
+                e = lensk::launch_stretch_accept(W, half, E->d, E->walkers, E->lnp, E->Y, E->aux, E->out, E->accepted,
+                                                 keep ? cw + (size_t)slot * W * S : nullptr,
+                                                 keep ? cl + (size_t)slot * W : nullptr, c->stream);
+        }
+    }
+    if (e == hipSuccess && chain && nstore > 0)
+        e = hipMemcpyAsync(chain, cw, (size_t)nstore * W * S * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && chain_lnp && nstore > 0)
+        e = hipMemcpyAsync(chain_lnp, cl, (size_t)nstore * W * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (dchain) {
+        (void)hipStreamSynchronize(c->stream);
+        dev_free(c, dchain);
+        uncharge(c, (int64_t)cbytes);
+    }
+    if (e != hipSuccess) return hip_fail(c, e, "lens_ensemble_run");
+    E->t += iterations;
+    return LENS_OK;
+}
+
+}  // namespace
+
+extern "C" lens_status lens_ensemble_get(lens_ctx *c, lens_ens id, double *walkers, double *lnp, int64_t *accepted,
+                                         int64_t *iteration)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    Ensemble *E = ensemble_use(c, id);
+    if (!E) return fail(c, LENS_ENOENT, "unknown ensemble id");
+    std::unique_lock<std::mutex> elk(E->mu);
+    DeviceGuard dg(c->device);
+    const int W = E->W;
+    hipError_t e = hipSuccess;
+    if (walkers)
+        e = hipMemcpyAsync(walkers, E->walkers, (size_t)W * lensk::kStride * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && lnp) e = hipMemcpyAsync(lnp, E->lnp, (size_t)W * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && accepted)
+        e = hipMemcpyAsync(accepted, E->accepted, (size_t)W * 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (iteration) *iteration = E->t;
+    elk.unlock();
+    ensemble_done(c, E);
+    if (e != hipSuccess) return hip_fail(c, e, "lens_ensemble_get");
+    return LENS_OK;
+}
+
+extern "C" lens_status lens_ensemble_destroy(lens_ctx *c, lens_ens id)
+{
+    if (!c) return LENS_EINVAL;
+    Ensemble *E = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        auto it = c->ensembles.find(id);
+        if (it == c->ensembles.end()) return fail(c, LENS_ENOENT, "unknown ensemble id");
+        E = it->second;
+        if (E->users > 0) return fail(c, LENS_EBUSY, "ensemble is in use by a running call");
+        c->ensembles.erase(it);
+    }
+    DeviceGuard dg(c->device);
+    free_ensemble(c, E);
     return LENS_OK;
 }

@@ -25,7 +25,7 @@ RECORD = os.path.join(ROOT, "profiles", "traffic_plain_128px_s4_k21.txt")
 # that picks the PSF crop and the tile shape
 KERNEL_SOURCES = ["paper_2503_08586_amd/csrc/lens_kernels.hip", "paper_2503_08586_amd/csrc/lens_device.h",
                   "paper_2503_08586_amd/csrc/lens_approx.h", "paper_2503_08586_amd/csrc/lens_internal.h",
-                  "paper_2503_08586_amd/csrc/lens_runtime.cpp"]
+                  "paper_2503_08586_amd/csrc/lens_prep.h", "paper_2503_08586_amd/csrc/lens_runtime.cpp"]
 
 
 def kernel_hash():

@@ -70,7 +70,8 @@ def test_struct_offsets_match_compiled_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    structs = [binding.lens_init_opts, binding.lens_data_desc, binding.lens_info, binding.lens_stats]
+    structs = [binding.lens_init_opts, binding.lens_data_desc, binding.lens_info, binding.lens_stats,
+               binding.lens_ensemble_desc]
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lens_api.h"', "int main(void) {"]
     expect = []
     for st in structs:

@@ -393,3 +393,31 @@ def test_autotuned_context():
             got = c2.loglike(lid, sp.proposals)
             _check(sp, got, sp.proposals, label="autotuned %dx%d" % (sp.ny, sp.nx))
             c2.unload(lid)
+
+
+def test_sampler_path_proposals(ctx):
+    """Proposals an ensemble sampler makes near a steep (n ~ 3.5) source centre
+    with large residuals at the brightest pixels: a regime a uniform draw from
+    the prior box rarely reaches, where the Sersic exponent amplifies any
+    absolute error in log2 (R/R_e)^2."""
+    import oracle
+    say("case: 64x64 s=1 k=11, 240 proposals from 5 seeded stretch-move iterations")
+    orc = oracle.default()
+    spec = synth.config1(nprop=1)[0]
+    oracle_data(spec)
+    lo = np.array([b[1] for b in synth.PRIOR_BOX] + [0.0])
+    hi = np.array([b[2] for b in synth.PRIOR_BOX] + [0.0])
+    rng = np.random.default_rng(2)
+    w = np.clip(np.clip(spec.truth, lo, hi)[None, :] + 0.02 * (hi - lo)[None, :] * rng.normal(size=(48, 20)), lo, hi)
+    lnp = orc.loglike(spec.geom, spec.psf, spec.data, spec.sigma, spec.mask, w)
+    props = []
+    for t in range(5):
+        trace = []
+        orc.ensemble_iteration(w, lnp, t, 1234567, 2.0, lo, hi,
+                               lambda P: orc.loglike(spec.geom, spec.psf, spec.data, spec.sigma, spec.mask, P),
+                               trace=trace)
+        props += [Y for Y, _, _, _, _ in trace]
+    P = np.concatenate(props)
+    lid = ctx.load(spec)
+    _check(spec, ctx.loglike(lid, P), P, label="sampler path")
+    ctx.unload(lid)
