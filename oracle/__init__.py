@@ -71,6 +71,7 @@ class Oracle:
             "oracle_sersic": ([d] * 10, d),
             "oracle_sie_deflection": ([d] * 7 + [_dp, _dp], None),
             "oracle_shear_deflection": ([d, d, d, d, _dp, _dp], None),
+            "oracle_epl_deflection": ([d] * 8 + [_dp, _dp], None),
             "oracle_deflection": ([_dp, d, d, _dp, _dp], None),
             "oracle_params_valid": ([_dp], i),
             "oracle_subpixel_xy": ([i, i, d, i, i, i, i, i, _dp, _dp], None),
@@ -110,6 +111,14 @@ class Oracle:
         """SIE deflection (Sec. 2.4: elliptical power law at slope 2) at one point."""
         ax, ay = ctypes.c_double(), ctypes.c_double()
         self.lib.oracle_sie_deflection(float(theta_E), float(q), float(phi), float(xm), float(ym),
+                                       float(x), float(y), ctypes.byref(ax), ctypes.byref(ay))
+        return ax.value, ay.value
+
+    def epl_deflection(self, theta_E, gamma, q, phi, xm, ym, x, y):
+        """Elliptical power-law deflection (Sec. 2.4; gamma = 2 is the SIE) at one point,
+        by quadrature of the elliptical-mass integrals."""
+        ax, ay = ctypes.c_double(), ctypes.c_double()
+        self.lib.oracle_epl_deflection(float(theta_E), float(gamma), float(q), float(phi), float(xm), float(ym),
                                        float(x), float(y), ctypes.byref(ax), ctypes.byref(ay))
         return ax.value, ay.value
 

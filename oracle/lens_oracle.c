@@ -49,11 +49,15 @@
  *       (k-1)/2, zero outside the image, output of the image's size.
  *   R12 supersample -> bin -> convolve.
  *   R13 lnL = -1/2 chi^2 - 1/2 sum_mask ln(2 pi sigma^2), sums over the mask.
+ *   R14 the power-law convergence of Sec. 2.4 is made elliptical on the same
+ *       elliptical radius R_p as the SIE, so gamma = 2 is exactly reading R1.
  *
- * Parameter vector of one proposal: 20 doubles (slot 19 unused, must be 0):
+ * Parameter vector of one proposal: 20 doubles:
  *   0 theta_E  1 q_m  2 phi_m  3 x_m  4 y_m  5 g1  6 g2
  *   7 I_l  8 R_l  9 n_l  10 q_l  11 phi_l
  *   12 I_s 13 R_s 14 n_s 15 q_s 16 phi_s 17 x_s 18 y_s
+ *   19 mass slope: 0 for the SIE (its closed form), gamma in [1.05, 2.95]
+ *      for the elliptical power law
  * Angles in radians, positions and radii in arcsec.
  */
 #include <math.h>
@@ -167,6 +171,49 @@ void oracle_sie_deflection(double theta_E, double q, double phi, double xm,
     *ay = s * a1 + c * a2;
 }
 
+/* Elliptical power law (EPL; Sec. 2.4, the power-law convergence made
+ * elliptical, reading R14): in the frame of the mass ellipse,
+ *   kappa = (3 - gamma)/2 (theta_E / R_p)^(gamma - 1),  R_p = sqrt(q x1^2 + x2^2/q),
+ * which is the SIE's kappa = theta_E / (2 R_p) at gamma = 2.  With
+ * xi^2 = x1^2 + x2^2/q^2 (so R_p = sqrt(q) xi) the deflection of any convergence
+ * constant on the ellipses xi = const is the classical pair of integrals
+ *   a1 = q x1 J0,  a2 = q x2 J1,
+ *   Jn = int_0^1 kappa(xi(u)) / d(u)^(n + 1/2) du,  d(u) = 1 - (1 - q^2) u,
+ *   xi(u)^2 = u A(u),  A(u) = x1^2 + x2^2 / d(u)
+ * (Schramm 1990; Keeton 2001, "A catalog of mass models", Sec. 2).  kappa(xi(u))
+ * carries the factor u^(-(gamma-1)/2), singular at u = 0; with u = v^m,
+ * m = 2 / (3 - gamma), that factor times du/dv is the constant m, and
+ *   Jn = int_0^1 (theta_E^2 / (q A(v^m)))^((gamma-1)/2) / d(v^m)^(n + 1/2) dv,
+ * a smooth integrand, taken by tanh-sinh quadrature (Takahasi & Mori 1974):
+ * v = 1/(1 + e^(-pi sinh tau)), tau = k h, h = 1/64, |tau| <= 4. */
+void oracle_epl_deflection(double theta_E, double gamma, double q, double phi, double xm, double ym,
+                           double x, double y, double *ax, double *ay)
+{
+    double dx = x - xm, dy = y - ym;
+    double c = cos(phi), s = sin(phi);
+    double x1 = c * dx + s * dy;          /* frame of the mass ellipse (Eq. 10) */
+    double x2 = -s * dx + c * dy;
+    if ((x1 == 0.0 && x2 == 0.0) || theta_E == 0.0) { *ax = 0.0; *ay = 0.0; return; }
+    const double h = 1.0 / 64.0, e2 = 1.0 - q * q, m = 2.0 / (3.0 - gamma);
+    const double b2 = theta_E * theta_E / q, p = 0.5 * (gamma - 1.0);
+    double J0 = 0.0, J1 = 0.0;
+    for (int k = -256; k <= 256; ++k) {
+        const double tau = k * h, sh = sinh(tau), ch = cosh(tau);
+        const double ex = exp(-M_PI * sh);
+        const double v = 1.0 / (1.0 + ex);                              /* (1 + tanh(pi/2 sinh tau))/2 */
+        const double w = h * M_PI * ch * ex / ((1.0 + ex) * (1.0 + ex));   /* dv/dtau */
+        if (!(w > 0.0) || !isfinite(w)) continue;
+        const double u = pow(v, m), d = 1.0 - e2 * u;
+        const double A = x1 * x1 + x2 * x2 / d;
+        const double f = w * pow(b2 / A, p) / sqrt(d);
+        J0 += f;
+        J1 += f / d;
+    }
+    const double a1 = q * x1 * J0, a2 = q * x2 * J1;
+    *ax = c * a1 - s * a2;                /* rotate back to the image frame */
+    *ay = s * a1 + c * a2;
+}
+
 void oracle_shear_deflection(double g1, double g2, double x, double y,
                              double *ax, double *ay)
 {
@@ -175,11 +222,15 @@ void oracle_shear_deflection(double g1, double g2, double x, double y,
     *ay = -(g2 * x - g1 * y);
 }
 
-/* Total deflection of one proposal at (x, y). */
+/* Total deflection of one proposal at (x, y).  Slot 19 selects the mass:
+ * 0 the SIE by its closed form, gamma in (1, 3) the EPL (reading R14). */
 void oracle_deflection(const double *p, double x, double y, double *ax, double *ay)
 {
     double sx, sy, hx, hy;
-    oracle_sie_deflection(p[0], p[1], p[2], p[3], p[4], x, y, &sx, &sy);
+    if (p[19] == 0.0)
+        oracle_sie_deflection(p[0], p[1], p[2], p[3], p[4], x, y, &sx, &sy);
+    else
+        oracle_epl_deflection(p[0], p[19], p[1], p[2], p[3], p[4], x, y, &sx, &sy);
     oracle_shear_deflection(p[5], p[6], x, y, &hx, &hy);
     *ax = sx + hx;
     *ay = sy + hy;
@@ -191,10 +242,14 @@ void oracle_deflection(const double *p, double x, double y, double *ax, double *
 #define ORC_N_MIN 0.1
 #define ORC_N_MAX 20.0
 
+#define ORC_GAMMA_MIN 1.05
+#define ORC_GAMMA_MAX 2.95
+
 int oracle_params_valid(const double *p)
 {
     for (int i = 0; i < 19; ++i)
         if (!isfinite(p[i])) return 0;
+    if (p[19] != 0.0 && !(p[19] >= ORC_GAMMA_MIN && p[19] <= ORC_GAMMA_MAX)) return 0;
     if (p[0] < 0.0) return 0;
     const int qs[3] = {1, 10, 15};
     for (int i = 0; i < 3; ++i)
@@ -502,6 +557,7 @@ static int orc_light_valid(const double *p, int model, const double *nfix)
         for (int i = 0; i < 7; ++i)
             if (!isfinite(p[i])) return 0;
         if (p[0] < 0.0 || !(p[1] > 0.0 && p[1] <= 1.0)) return 0;
+        if (p[19] != 0.0 && !(p[19] >= ORC_GAMMA_MIN && p[19] <= ORC_GAMMA_MAX)) return 0;
     }
     if (lens) {
         for (int i = 8; i < 12; ++i)

@@ -660,6 +660,102 @@ def pin_light_model_domain(orc):
 
 
 # ----------------------------------------------------------------------------
+# elliptical power-law mass (Sec. 2.4; gamma = 2 is the SIE)
+# ----------------------------------------------------------------------------
+def _epl_closed_form(theta_E, gamma, q, x1, x2):
+    """Tessore & Metcalf (2015, A&A 580, A79) closed form in the ellipse frame:
+    alpha = 2b/(1+q) (b/R)^(t-1) e^(i phi) 2F1(1, t/2; 2 - t/2; -(1-q)/(1+q) e^(2 i phi)),
+    t = gamma - 1, R e^(i phi) = q x1 + i x2, b = theta_E sqrt(q) for this
+    normalisation, evaluated with scipy's complex hypergeometric function."""
+    t = gamma - 1.0
+    b = theta_E * math.sqrt(q)
+    R = math.hypot(q * x1, x2)
+    e = complex(q * x1, x2) / R
+    f = (1.0 - q) / (1.0 + q)
+    F = scipy.special.hyp2f1(1.0, t / 2.0, 2.0 - t / 2.0, -f * e * e)
+    a = 2.0 * b / (1.0 + q) * (b / R) ** (t - 1.0) * e * F
+    return a.real, a.imag
+
+
+def pin_epl_reduces_to_sie(orc):
+    rng = np.random.default_rng(41)
+    for _ in range(40):
+        q = rng.uniform(0.1, 1.0)
+        phi = rng.uniform(0, math.pi)
+        x, y = rng.uniform(-2, 2, 2)
+        if rng.random() < 0.25:
+            x, y = x * 1e-3, y * 1e-3
+        a = orc.epl_deflection(1.3, 2.0, q, phi, 0.05, -0.03, x, y)
+        b = orc.sie_deflection(1.3, q, phi, 0.05, -0.03, x, y)
+        assert np.allclose(a, b, rtol=1e-12, atol=1e-14), (q, x, y, a, b)
+
+
+def pin_epl_circular_closed_form(orc):
+    # q = 1: alpha(r) = (2/r) int_0^r kappa r' dr' = theta_E^(gamma-1) r^(2-gamma) along x/r
+    for gamma in (1.05, 1.4, 1.9, 2.3, 2.7, 2.95):
+        for (x, y) in ((0.6, -0.8), (0.01, 0.02), (2.0, 1.5)):
+            r = math.hypot(x, y)
+            want = 1.2 ** (gamma - 1.0) * r ** (2.0 - gamma)
+            a = orc.epl_deflection(1.2, gamma, 1.0, 0.7, 0.0, 0.0, x, y)
+            assert np.allclose(a, (want * x / r, want * y / r), rtol=1e-12, atol=0), (gamma, x, y, a)
+
+
+def pin_epl_hypergeometric(orc):
+    rng = np.random.default_rng(42)
+    for _ in range(40):
+        gamma = rng.uniform(1.05, 2.95)
+        q = rng.uniform(0.2, 1.0)
+        x1, x2 = rng.uniform(-2, 2, 2)
+        want = _epl_closed_form(1.1, gamma, q, x1, x2)
+        got = orc.epl_deflection(1.1, gamma, q, 0.0, 0.0, 0.0, x1, x2)
+        assert np.allclose(got, want, rtol=1e-10, atol=1e-13), (gamma, q, x1, x2, got, want)
+    # a rotated, offset ellipse is the same deflection rotated back
+    got = orc.epl_deflection(1.1, 1.7, 0.6, 0.9, 0.2, -0.1, 0.8, 0.5)
+    c, s_ = math.cos(0.9), math.sin(0.9)
+    dx, dy = 0.6, 0.6
+    a1, a2 = _epl_closed_form(1.1, 1.7, 0.6, c * dx + s_ * dy, -s_ * dx + c * dy)
+    assert np.allclose(got, (c * a1 - s_ * a2, s_ * a1 + c * a2), rtol=1e-10)
+
+
+def pin_epl_divergence_and_curl(orc):
+    # div alpha = 2 kappa, curl alpha = 0, kappa = (3-gamma)/2 (theta_E/R_p)^(gamma-1)
+    h = 1e-5
+    for gamma, q, phi, (x, y) in ((1.4, 0.6, 0.3, (0.7, -0.4)), (2.6, 0.8, 2.0, (-0.5, 0.9)),
+                                  (1.9, 0.45, 1.2, (1.3, 0.2))):
+        def a(xx, yy):
+            return np.array(orc.epl_deflection(1.2, gamma, q, phi, 0.0, 0.0, xx, yy))
+        ax_x = (a(x + h, y)[0] - a(x - h, y)[0]) / (2 * h)
+        ay_y = (a(x, y + h)[1] - a(x, y - h)[1]) / (2 * h)
+        ax_y = (a(x, y + h)[0] - a(x, y - h)[0]) / (2 * h)
+        ay_x = (a(x + h, y)[1] - a(x - h, y)[1]) / (2 * h)
+        x1 = math.cos(phi) * x + math.sin(phi) * y
+        x2 = -math.sin(phi) * x + math.cos(phi) * y
+        Rp = math.sqrt(q * x1 * x1 + x2 * x2 / q)
+        kappa = 0.5 * (3.0 - gamma) * (1.2 / Rp) ** (gamma - 1.0)
+        assert abs(ax_x + ay_y - 2 * kappa) < 1e-7 * kappa, (gamma, ax_x + ay_y, 2 * kappa)
+        assert abs(ax_y - ay_x) < 1e-7 * kappa
+
+
+def pin_epl_in_the_likelihood(orc):
+    # slot 19 = 0 is the SIE by its closed form, slot 19 = 2 the EPL at gamma = 2
+    rng, psf, sigma, mask, truth, g = _small_case(seed=43)
+    data = orc.model_image(g[0], g[1], g[2], g[3], psf, truth, stage=1)
+    t2 = truth.copy()
+    t2[19] = 2.0
+    a = orc.loglike(g, psf, data, sigma, mask, np.stack([truth, t2]))
+    assert abs(a[0] - a[1]) < 1e-9 * abs(a[0]), a
+    # a steeper profile is a different model; the domain of gamma is [1.05, 2.95]
+    t3 = truth.copy()
+    t3[19] = 2.3
+    bad = [truth.copy() for _ in range(3)]
+    bad[0][19], bad[1][19], bad[2][19] = 0.5, 1.0, 3.0
+    r = orc.loglike(g, psf, data, sigma, mask, np.stack([t3] + bad))
+    assert np.isfinite(r[0]) and r[0] < a[0] - 1.0 and np.all(np.isneginf(r[1:])), r
+    m = orc.model_image(g[0], g[1], g[2], g[3], psf, t3, stage=0)
+    assert np.all(np.isfinite(m)) and m.max() > 0
+
+
+# ----------------------------------------------------------------------------
 # sampler loop: Philox4x32-10 (Salmon et al. 2011) and the stretch move
 # (Goodman & Weare 2010) on the posterior of Sec. 2.2 under a box prior
 # ----------------------------------------------------------------------------

@@ -54,6 +54,12 @@ MUTANTS = {
                                     "for (int c = 1; c < N; ++c) mval += cand[c] * col[(size_t)c * npix + i];")],
     "light_mass_in_lens_only": [("int mass = model != 1, lens = model != 2, src = model != 1;",
                                  "int mass = 1, lens = model != 2, src = model != 1;")],
+    "epl_substitution_power": [("m = 2.0 / (3.0 - gamma);", "m = 1.0 / (3.0 - gamma);")],
+    "epl_minor_axis_integral": [("        J1 += f / d;", "        J1 += f;")],
+    "epl_slope_exponent": [("p = 0.5 * (gamma - 1.0);", "p = 0.5 * gamma;")],
+    "epl_integrals_swapped": [("const double a1 = q * x1 * J0, a2 = q * x2 * J1;",
+                               "const double a1 = q * x1 * J1, a2 = q * x2 * J0;")],
+    "epl_slope_ignored": [("oracle_epl_deflection(p[0], p[19],", "oracle_epl_deflection(p[0], 2.0,")],
     "philox_no_key_bump": [("            k0 += W0;\n            k1 += W1;\n", "")],
     "philox_words_swapped": [("n1 = lo1, n2 = hi0 ^ c3 ^ k1, n3 = lo0;", "n1 = lo0, n2 = hi0 ^ c3 ^ k1, n3 = lo1;")],
     "stretch_drop_dimension_factor": [("rhs = (d - 1) * log(z[i])", "rhs = 0.0 * log(z[i])")],
