@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--light-model", default="both", choices=list(LIGHT),
                     help="light model (solved amplitudes): lens and source, lens light only, lensed source "
                          "only, or two components per galaxy with indices 1 and 4 (implies --amplitudes nnls)")
+    ap.add_argument("--mass", default="sie", choices=["sie", "epl"],
+                    help="mass model: the SIE, or the elliptical power law with slope gamma ~ U[1.5, 2.5] "
+                         "in slot 19")
     ap.add_argument("--requests", type=int, default=300, help="serving: requests per offered load")
     return ap.parse_args()
 
@@ -100,6 +103,16 @@ def credited_slots(spec, info, nnls=False, model=0):
         N = CHANNELS[model]
         return E * SLOTS_BY_MODEL[model] + N * M * k * k + (N * (N + 1) // 2 + N) * M, E
     return E * SLOTS_PER_EVAL + M * k * k + M, E
+
+
+def epl_terms(P):
+    """Mean length of the power-law deflection series over proposals P: the terms that
+    bring the tail f^N/(1 - f) below 1e-16, f = (1 - q_m)/(1 + q_m), at most 128."""
+    q = P[:, 1]
+    f = (1.0 - q) / (1.0 + q)
+    with np.errstate(divide="ignore"):
+        n = np.where(f > 0, np.ceil(np.log(1e-16 * (1.0 - f)) / np.log(np.where(f > 0, f, 0.5))), 1.0)
+    return float(np.clip(n, 1, 128).mean())
 
 
 def oracle_fn(nnls=False, model=0):
@@ -190,7 +203,13 @@ def main():
     nnls = args.amplitudes == "nnls" or model != 0
     if model == 3:
         spec.proposals = synth.double_component_params(synth.rng_for_config(2), spec.proposals)
-    lid = ctx.load(spec, precision=prec, amplitudes=1 if nnls else 0, light_model=model, sersic_n=DOUBLE_N)
+    epl = args.mass == "epl"
+    if epl:
+        spec.proposals[:, 19] = synth.rng_for_config(2).uniform(1.5, 2.5, n)
+        spec.truth = spec.truth.copy()
+        spec.truth[19] = 2.0
+    lid = ctx.load(spec, precision=prec, amplitudes=1 if nnls else 0, light_model=model, sersic_n=DOUBLE_N,
+                   mass_model=1 if epl else 0)
     info = ctx.info(lid)
 
     dev = torch.device("cuda", 0)
@@ -225,8 +244,11 @@ def main():
 
     # roofline: credited algorithmic VALU work of one launch
     slots_per_prop, E = credited_slots(spec, info, nnls, model)
+    if epl:   # the series' extra complex Horner steps, 4 FMAs each, per sub-pixel
+        slots_per_prop += E * 4 * (epl_terms(spec.proposals) - 1.0)
     achieved = slots_per_prop * n / (kern_ms * 1e-3)
-    kname = ("k_loglike_nnls<%d,%d>" % (4 + model, info["threads"]) if nnls else
+    kname = ("k_loglike_rt<8,%d>" % info["threads"] if epl and not nnls and prec == 0 else
+             "k_loglike_nnls<%d,%d>" % (4 + model + (8 if epl else 0), info["threads"]) if nnls else
              "k_loglike_fp32<%d,%d>" % (info["psf_used"], info["threads"]) if prec == 0 else
              "k_loglike_mfma<%d,%d>" % (prec, info["threads"]))
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOT_PER_S / 1e12,
@@ -273,9 +295,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "plain survey scale: 1 lens, 128x128 px at 0.05\"/px, 4x4 supersampling, "
                                "21x21 Gaussian PSF FWHM 0.1\", r=3\" mask, %d proposals per call, "
-                               "FP64 ray trace, %s PSF convolution, FP64 chi2, %s amplitudes%s"
+                               "FP64 ray trace, %s PSF convolution, FP64 chi2, %s amplitudes%s%s"
                                % (n, args.precision or "fp32", "NNLS-solved" if nnls else "explicit",
-                                  "" if model == 0 else ", light model: " + args.light_model),
+                                  "" if model == 0 else ", light model: " + args.light_model,
+                                  ", elliptical power-law mass, gamma ~ U[1.5, 2.5]" if epl else ""),
                    "path": "lens_loglike_batch_device", "proposals_per_call": n,
                    "subpixel_evals_per_s": value * E},
         "roofline": roofline,

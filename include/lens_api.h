@@ -10,7 +10,8 @@
  *   - s x s supersampling, binned by the pixel mean               (Sec. 2.1, after Eq. 2)
  *   - PSF convolution of the binned image                         (Sec. 2.1, Eq. 3)
  *   - lnL = sum over the fitting region of ln N(d_i; I_i, sigma_i)  (Sec. 2.2, Eq. 5)
- *   - SIE mass (the elliptical power law at slope 2) + external shear (Sec. 2.4, Eqs. 12-14)
+ *   - SIE mass (the elliptical power law at slope 2) + external shear (Sec. 2.4, Eqs. 12-14),
+ *     or the elliptical power law at any slope gamma (LENS_MASS_EPL)
  *   - elliptical Sersic light for lens and source                 (Sec. 2.4, Eqs. 8-10)
  * The light amplitudes are explicit parameters by default, or solved by
  * non-negative least squares per proposal (Sec. 2.3, LENS_AMP_NNLS), which
@@ -31,13 +32,15 @@
  *   - lnL = -1/2 chi^2 - 1/2 sum_mask ln(2 pi sigma^2), sums over mask pixels.
  *
  * Parameter vector: LENS_PARAM_STRIDE doubles per proposal, row-major
- * [n][20], arcsec and radians; slot 19 is ignored:
+ * [n][20], arcsec and radians:
  *   0 theta_E  1 q_m  2 phi_m  3 x_m  4 y_m  5 g1  6 g2
  *   7 I_l  8 R_l  9 n_l  10 q_l  11 phi_l
  *   12 I_s 13 R_s 14 n_s 15 q_s 16 phi_s 17 x_s 18 y_s
+ *   19 gamma, the power-law slope of a LENS_MASS_EPL lens (ignored by the SIE)
  * A proposal outside the domain is not a call error: its lnL is -INFINITY.
  * The domain is: every slot 0..18 finite, theta_E >= 0, each axis ratio in
- * (0, 1], R_l > 0, R_s > 0, n_l and n_s in [0.1, 20].
+ * (0, 1], R_l > 0, R_s > 0, n_l and n_s in [0.1, 20]; for LENS_MASS_EPL also
+ * gamma in [1.05, 2.95].
  *
  * Arithmetic: the ray trace and the Sersic exponents in FP64 (FP32 hardware
  * seeds refined by Newton steps, FP32 log2), the binned image rounded to FP32
@@ -89,6 +92,14 @@ typedef int32_t lens_status;
                                      lens-light and source images at unit amplitude, binned and
                                      PSF-convolved; lnL is taken there and slots 7, 12 are ignored.
                                      Needs LENS_PREC_FP32. */
+
+/* Mass models, chosen per lens at load. */
+#define LENS_MASS_SIE 0           /* singular isothermal ellipsoid, kappa = theta_E / (2 R_p) (default) */
+#define LENS_MASS_EPL 1           /* elliptical power law (Sec. 2.4), kappa = (3 - gamma)/2 (theta_E / R_p)^(gamma - 1)
+                                     on the same elliptical radius R_p, gamma from slot 19; gamma = 2 is
+                                     the SIE.  Deflection by the hypergeometric series of Tessore &
+                                     Metcalf (2015), summed to a 1e-16 tail for axis ratios >= 0.15
+                                     (at most 128 terms below that) */
 
 /* Light models, chosen per lens at load; all but LENS_LIGHT_BOTH need
  * LENS_AMP_NNLS.  Each model reads, and validates, only the slots it uses. */
@@ -148,6 +159,7 @@ typedef struct lens_data_desc {
     int32_t light_model;        /* LENS_LIGHT_* (0: lens and source) */
     double sersic_n[4];         /* LENS_LIGHT_DOUBLE: fixed Sersic indices of lens a, lens b, source a,
                                    source b, each in [0.1, 20] (Sec. 3.2 uses 1, 4, 1, 4); else ignored */
+    int32_t mass_model;         /* LENS_MASS_* (0: SIE) */
 } lens_data_desc;
 
 typedef struct lens_info {
@@ -164,6 +176,7 @@ typedef struct lens_info {
     int32_t amplitudes;         /* LENS_AMP_* */
     int32_t light_model;        /* LENS_LIGHT_* */
     int32_t n_amplitudes;       /* amplitudes per proposal of lens_loglike_amps: 2, 1, 1 or 4 */
+    int32_t mass_model;         /* LENS_MASS_* */
 } lens_info;
 
 typedef struct lens_stats {

@@ -42,6 +42,9 @@ LENS_PREC_BF16_SPLIT3 = 3
 LENS_AMP_EXPLICIT = 0
 LENS_AMP_NNLS = 1
 
+LENS_MASS_SIE = 0
+LENS_MASS_EPL = 1
+
 LENS_LIGHT_BOTH = 0
 LENS_LIGHT_LENS = 1
 LENS_LIGHT_SOURCE = 2
@@ -90,6 +93,7 @@ class lens_data_desc(ctypes.Structure):
         ("psf_tail", ctypes.c_double),
         ("light_model", ctypes.c_int32),
         ("sersic_n", ctypes.c_double * 4),
+        ("mass_model", ctypes.c_int32),
     ]
 
 
@@ -102,6 +106,7 @@ class lens_info(ctypes.Structure):
         ("strip_rows", ctypes.c_int32), ("threads", ctypes.c_int32), ("lds_bytes", ctypes.c_int64),
         ("blocks_per_cu", ctypes.c_int32), ("psf_used", ctypes.c_int32),
         ("amplitudes", ctypes.c_int32), ("light_model", ctypes.c_int32), ("n_amplitudes", ctypes.c_int32),
+        ("mass_model", ctypes.c_int32),
     ]
 
 
@@ -262,7 +267,7 @@ def lens_shutdown(ctx):
 
 def lens_load_data(ctx, ny, nx, pixel_scale, supersample, psf, data, sigma, mask,
                    precision=LENS_PREC_FP32, psf_tail=0.0, amplitudes=0, light_model=0,
-                   sersic_n=(1.0, 1.0, 1.0, 1.0)) -> int:
+                   sersic_n=(1.0, 1.0, 1.0, 1.0), mass_model=0) -> int:
     psf = np.ascontiguousarray(psf, dtype=np.float64)
     data = np.ascontiguousarray(data, dtype=np.float64)
     sigma = np.ascontiguousarray(sigma, dtype=np.float64)
@@ -282,6 +287,7 @@ def lens_load_data(ctx, ny, nx, pixel_scale, supersample, psf, data, sigma, mask
     if len(sn) != 4:
         raise ValueError("sersic_n holds four indices")
     d.sersic_n[:] = sn
+    d.mass_model = mass_model
     lid = ctypes.c_int64()
     _check(ctx, load().lens_load_data(ctx, ctypes.byref(d), ctypes.byref(lid)))
     return lid.value
@@ -501,11 +507,11 @@ class LensContext:
         self.close()
 
     def load(self, spec, precision=LENS_PREC_FP32, data=None, psf_tail=0.0, amplitudes=0, light_model=0,
-             sersic_n=(1.0, 1.0, 1.0, 1.0)) -> int:
+             sersic_n=(1.0, 1.0, 1.0, 1.0), mass_model=0) -> int:
         """Load a synth.LensSpec (its data, or ``data`` if given)."""
         d = spec.data if data is None else data
         lid = lens_load_data(self.ctx, spec.ny, spec.nx, spec.dpix, spec.s, spec.psf, d, spec.sigma,
-                             spec.mask, precision, psf_tail, amplitudes, light_model, sersic_n)
+                             spec.mask, precision, psf_tail, amplitudes, light_model, sersic_n, mass_model)
         self.geom[lid] = (spec.ny, spec.nx)
         return lid
 

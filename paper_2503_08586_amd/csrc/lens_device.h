@@ -190,6 +190,77 @@ __device__ __forceinline__ void ray_trace(double x1, double x2, double lx, doubl
     by = ly - fma(P.sm, a1, P.cm * a2);
 }
 
+// Elliptical power law (Sec. 2.4: kappa = (3 - gamma)/2 (theta_E / R_p)^(gamma - 1)
+// on the SIE's elliptical radius R_p, so gamma = 2 is the SIE).  In the frame
+// of the mass ellipse, with R e^(i phi) = q x1 + i x2, t = gamma - 1,
+// b = theta_E sqrt(q) and f = (1 - q)/(1 + q), the deflection is (Tessore &
+// Metcalf 2015, the hypergeometric function written as its series)
+//   alpha1 + i alpha2 = 2 b^t / (1 + q) R^(1 - t) e^(i phi) sum_n a_n e^(2 i n phi),
+//   a_0 = 1,  a_n = -f (2n - 2 + t) / (2n + 2 - t) a_(n-1),  |a_n| <= f^n.
+// The sum is taken by Horner in w = e^(2 i phi) with the proposal's
+// coefficients from LDS (epl_setup); R^(1 - t) = 2^((1 - t)/2 log2 R^2), with
+// log2 R^2 refined by one Newton step on 2^l = R^2 and both powers of two at
+// degree 11 (4e-16): the deflection is good to ~1e-14 relative.  alpha = 0 for
+// R^2 < 1e-30 (a sub-pixel within 1e-15 arcsec of the mass centre).
+__device__ __forceinline__ double *epl_coefs()
+{
+    __shared__ double c[kEplMaxTerms];
+    return c;
+}
+__device__ __forceinline__ int *epl_nterms()
+{
+    __shared__ int n;
+    return &n;
+}
+
+// The series coefficients of proposal P into LDS, by thread 0, with the number
+// of terms that brings the tail f^N / (1 - f) below 1e-16 (at most
+// kEplMaxTerms: axis ratios below 0.15 then keep a tail above 1e-16).  The
+// caller's next barrier publishes them.
+__device__ inline void epl_setup(const PropBlock &P)
+{
+    if (threadIdx.x != 0) return;
+    const double f = -P.epl_mf, t = 1.0 - 2.0 * P.epl_h;
+    int N = 1;
+    if (f > 0.0) N = (int)ceil(log(1e-16 * (1.0 - f)) / log(f));
+    N = N < 1 ? 1 : N > kEplMaxTerms ? kEplMaxTerms : N;
+    double *c = epl_coefs();
+    double a = 1.0;
+    c[0] = 1.0;
+    for (int n = 1; n < N; ++n) {
+        a *= P.epl_mf * (2.0 * n - 2.0 + t) / (2.0 * n + 2.0 - t);
+        c[n] = a;
+    }
+    *epl_nterms() = N;
+}
+
+__device__ __forceinline__ void ray_trace_epl(double x1, double x2, double lx, double ly, const PropBlock &P,
+                                              double &bx, double &by)
+{
+    const double psi2 = fma(P.q2m, x1 * x1, x2 * x2);   // R^2
+    double a1 = 0.0, a2 = 0.0;
+    if (psi2 >= 1e-30) {
+        const double ir = rsq_nr(psi2);
+        const double c1 = P.epl_q * x1 * ir, s1 = x2 * ir;                 // e^(i phi)
+        const double wr = fma(c1, c1, -(s1 * s1)), wi = 2.0 * c1 * s1;     // e^(2 i phi)
+        const double *c = epl_coefs();
+        const int N = __builtin_amdgcn_readfirstlane(*epl_nterms());
+        double sr = c[N - 1], si = 0.0;
+        for (int n = N - 2; n >= 0; --n) {
+            const double tr = fma(sr, wr, fma(-si, wi, c[n]));
+            si = fma(sr, wi, si * wr);
+            sr = tr;
+        }
+        const double l0 = log2_r2(psi2);
+        const double l1 = fma(fma(psi2, exp2_64(kExp2Hi64, -l0), -1.0), 1.4426950408889634, l0);
+        const double mag = P.epl_pref * exp2_64(kExp2Hi64, P.epl_h * l1);
+        a1 = mag * fma(c1, sr, -(s1 * si));
+        a2 = mag * fma(c1, si, s1 * sr);
+    }
+    bx = lx - fma(P.cm, a1, -(P.sm * a2));
+    by = ly - fma(P.sm, a1, P.cm * a2);
+}
+
 // Sub-pixel sums of pixel (y, x), whose binned value is their mean over the
 // s x s sub-pixel centres (Sec. 2.1).  Fine-grid index fx = x s + u maps to position (fx - (nx s - 1)/2) * pixel_scale / s.
 // Along a sub-pixel row the x offset dx from the mass centre steps by
@@ -208,7 +279,7 @@ struct LightChannels {
 // trace; two components per galaxy share the elliptical radius of their side,
 // whose second component differs only in R_e: log2 (R/R_b)^2 = log2 (R/R_a)^2
 // + 2 log2(R_a/R_b).
-template <int LM>
+template <int LM, bool EPL = false>
 __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlock &P, int y, int x,
                                                 double (&acc)[LightChannels<LM>::N])
 {
@@ -238,7 +309,11 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
         for (int u = 0; u < s; ++u) {
             if constexpr (SRC) {
                 double bx, by;
-                ray_trace(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.g1p, dx, cx), fma(P.g2, dx, cy), P, bx, by);
+                if constexpr (EPL)
+                    ray_trace_epl(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.g1p, dx, cx), fma(P.g2, dx, cy), P, bx,
+                                  by);
+                else
+                    ray_trace(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.g1p, dx, cx), fma(P.g2, dx, cy), P, bx, by);
                 if constexpr (LENS && !DBL) {
                     acc[0] += sersic_r2(fma(fma(P.lens.P, dx, rs), dx, rq), P.lens, lead);
                     acc[1] += sersic_r2(ellip_r2(bx, by, P.src), P.src, lead);
@@ -258,30 +333,32 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
     }
 }
 
+template <bool EPL = false>
 __device__ __forceinline__ void binned_sums(const LensGeom &g, const PropBlock &P, int y, int x, double &al_out,
                                             double &as_out)
 {
     double acc[2];
-    binned_channels<LIGHT_BOTH>(g, P, y, x, acc);
+    binned_channels<LIGHT_BOTH, EPL>(g, P, y, x, acc);
     al_out = acc[0];
     as_out = acc[1];
 }
 
+template <bool EPL = false>
 __device__ __forceinline__ float binned_pixel(const LensGeom &g, const PropBlock &P, int y, int x)
 {
     double al, as;
-    binned_sums(g, P, y, x, al, as);
+    binned_sums<EPL>(g, P, y, x, al, as);
     return (float)(fma(P.lens.I, al, P.src.I * as) * g.inv_s2);
 }
 
 // The unit-amplitude channels of pixel (y, x) (binned values, FP32), for
 // amplitudes solved by non-negative least squares (Sec. 2.3).
-template <int LM>
+template <int LM, bool EPL = false>
 __device__ __forceinline__ void binned_pixel_channels(const LensGeom &g, const PropBlock &P, int y, int x,
                                                       float (&ch)[LightChannels<LM>::N])
 {
     double acc[LightChannels<LM>::N];
-    binned_channels<LM>(g, P, y, x, acc);
+    binned_channels<LM, EPL>(g, P, y, x, acc);
 #pragma unroll
     for (int c = 0; c < LightChannels<LM>::N; ++c) ch[c] = (float)(acc[c] * g.inv_s2);
 }

@@ -32,7 +32,9 @@ struct alignas(16) PropBlock {
     LightK lens, src;
     double g1p;                                // 1 + g1: d/dx of x + g1 x + g2 y
     double dlg_l, dlg_s;                       // two-component light: 2 log2(R_a / R_b) of the lens, of the source
-    double pad[4];
+    // elliptical power law (slope gamma = t + 1): q, 2 b^t / (1 + q) with b = theta_E sqrt(q),
+    // (1 - t) / 2, and -f = -(1 - q) / (1 + q) (the series ratio's sign and scale)
+    double epl_q, epl_pref, epl_h, epl_mf;
 };
 static_assert(sizeof(PropBlock) == 256, "PropBlock layout");
 constexpr int kPCBytes = (int)sizeof(PropBlock);
@@ -43,6 +45,8 @@ constexpr int kPCBytes = (int)sizeof(PropBlock);
 // and source (4), lens light only, no lensing (5), lensed source only (6), and
 // two components per galaxy sharing centre and ellipticity with fixed Sersic
 // indices (7).
+// The flag MODE_EPL (added to any of them) selects the elliptical power-law
+// mass in place of the SIE.
 enum : int {
     MODE_FP32 = 0,
     MODE_SPLIT = 1,
@@ -51,17 +55,23 @@ enum : int {
     MODE_FP32N = 4,
     MODE_FP32N_LENS = 5,
     MODE_FP32N_SRC = 6,
-    MODE_FP32N_DBL = 7
+    MODE_FP32N_DBL = 7,
+    MODE_EPL = 8
 };
+__host__ __device__ constexpr int mode_base(int mode) { return mode & 7; }
+__host__ __device__ constexpr bool mode_epl(int mode) { return (mode & MODE_EPL) != 0; }
 __host__ __device__ constexpr int mode_planes(int mode)
 {
-    return mode == MODE_SPLIT ? 2 : mode == MODE_SPLIT3 ? 3 : 1;
+    return mode_base(mode) == MODE_SPLIT ? 2 : mode_base(mode) == MODE_SPLIT3 ? 3 : 1;
 }
-__host__ __device__ constexpr bool mode_solved(int mode) { return mode >= MODE_FP32N; }
+__host__ __device__ constexpr bool mode_solved(int mode) { return mode_base(mode) >= MODE_FP32N; }
 // binned channels (components at unit amplitude) of a solved-amplitude mode
 __host__ __device__ constexpr int mode_channels(int mode)
 {
-    return mode == MODE_FP32N ? 2 : mode == MODE_FP32N_LENS || mode == MODE_FP32N_SRC ? 1 : mode == MODE_FP32N_DBL ? 4 : 0;
+    return mode_base(mode) == MODE_FP32N                                             ? 2
+           : mode_base(mode) == MODE_FP32N_LENS || mode_base(mode) == MODE_FP32N_SRC ? 1
+           : mode_base(mode) == MODE_FP32N_DBL                                      ? 4
+                                                                                    : 0;
 }
 
 // Light models (the public LENS_LIGHT_* values); they fix what the prep kernel
@@ -69,9 +79,15 @@ __host__ __device__ constexpr int mode_channels(int mode)
 enum : int { LIGHT_BOTH = 0, LIGHT_LENS = 1, LIGHT_SRC = 2, LIGHT_DOUBLE = 3 };
 __host__ __device__ constexpr int mode_light(int mode)
 {
-    return mode == MODE_FP32N_LENS ? LIGHT_LENS : mode == MODE_FP32N_SRC ? LIGHT_SRC
-                                                : mode == MODE_FP32N_DBL ? LIGHT_DOUBLE : LIGHT_BOTH;
+    return mode_base(mode) == MODE_FP32N_LENS  ? LIGHT_LENS
+           : mode_base(mode) == MODE_FP32N_SRC ? LIGHT_SRC
+           : mode_base(mode) == MODE_FP32N_DBL ? LIGHT_DOUBLE
+                                               : LIGHT_BOTH;
 }
+// The prep step's model code: light model | (mass model << 8), mass 1 = EPL.
+constexpr int kMassShift = 8;
+constexpr int kEplMaxTerms = 128;   // terms of the power-law deflection series
+constexpr double kGammaMin = 1.05, kGammaMax = 2.95;
 
 // Everything a likelihood launch needs to know about one resident lens.
 struct LensGeom {
@@ -117,9 +133,10 @@ size_t max_lds_bytes();
 size_t set_lds_limits(size_t bytes);   // dynamic LDS now accepted by every ring kernel; 0 on refusal
 size_t lds_per_cu();
 
-// Derived constants of n proposals.  Each proposal is read under a light model:
-// `model` for all of them, or, with d_pstart (nl + 1 proposal offsets) and
-// d_pmodel (nl models) in device memory, that of the lens owning it.
+// Derived constants of n proposals.  Each proposal is read under a model code
+// (light model | mass << kMassShift): `model` for all of them, or, with
+// d_pstart (nl + 1 proposal offsets) and d_pmodel (nl codes) in device memory,
+// that of the lens owning it.
 hipError_t launch_prep(const double *d_params, int64_t n, PropBlock *d_pc, int model, const int64_t *d_pstart,
                        const int *d_pmodel, int nl, hipStream_t st);
 // the fused likelihood of n proposals of one lens (FP32 or MFMA convolution per g.mode)
@@ -137,7 +154,7 @@ hipError_t launch_batch(int mode, int nt, int grid, size_t lds, const LensGeom *
 // halves of a stretch-move step (d_aux: [W/2][4] doubles)
 hipError_t launch_philox_words(const uint32_t ctr[4], const uint32_t key[2], int64_t n, uint32_t *d_out,
                                hipStream_t st);
-hipError_t launch_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int light_model,
+hipError_t launch_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int model_code,
                                   const double *d_walkers, const double *d_lo, const double *d_hi, double *d_Y,
                                   double *d_aux, PropBlock *d_pc, hipStream_t st);
 hipError_t launch_stretch_accept(int W, int half, int d, double *d_walkers, double *d_lnp, const double *d_Y,

@@ -42,9 +42,9 @@ __global__ void __launch_bounds__(256) k_prep(const double *__restrict__ params,
         lm = pmodel[lo];
     }
     const double *p = params + i * kStride;
-    double v[19];
+    double v[kStride];
 #pragma unroll
-    for (int j = 0; j < 19; ++j) v[j] = p[j];
+    for (int j = 0; j < kStride; ++j) v[j] = p[j];
     pc[i] = prep_proposal(v, lm);
 }
 
@@ -136,6 +136,8 @@ template <> struct RingStore<MODE_FP32N> : RingStoreN<2> {};
 template <> struct RingStore<MODE_FP32N_LENS> : RingStoreN<1> {};
 template <> struct RingStore<MODE_FP32N_SRC> : RingStoreN<1> {};
 template <> struct RingStore<MODE_FP32N_DBL> : RingStoreN<4> {};
+// the mass model does not change the ring
+template <int MODE> struct RingStoreM : RingStore<mode_base(MODE)> {};
 
 // Binned rows [ya, yb) (all < ny) into their ring slots: every pixel in the
 // row's needed range is evaluated; the rest of the row is cleared when the
@@ -153,7 +155,7 @@ __device__ __forceinline__ void fill_rows(const LensGeom &g, const PropBlock &P,
             if (slot >= RB) slot -= RB;
             const int2 lr = evr[y];
             for (int x = threadIdx.x; x < nx; x += NT)
-                if (x < lr.x || x >= lr.y) RingStore<MODE>::zero(ring, g.plane, slot * W + r + x);
+                if (x < lr.x || x >= lr.y) RingStoreM<MODE>::zero(ring, g.plane, slot * W + r + x);
         }
     }
     const int fb = evpre[yb];
@@ -165,10 +167,10 @@ __device__ __forceinline__ void fill_rows(const LensGeom &g, const PropBlock &P,
         if constexpr (mode_solved(MODE)) {
             constexpr int NCH = mode_channels(MODE);
             float ch[NCH];
-            binned_pixel_channels<mode_light(MODE)>(g, P, y, x, ch);
-            RingStore<MODE>::put(ring, g.plane, slot * W + r + x, FVec<NCH>::make(ch));
+            binned_pixel_channels<mode_light(MODE), mode_epl(MODE)>(g, P, y, x, ch);
+            RingStoreM<MODE>::put(ring, g.plane, slot * W + r + x, FVec<NCH>::make(ch));
         } else
-            RingStore<MODE>::put(ring, g.plane, slot * W + r + x, binned_pixel(g, P, y, x));
+            RingStoreM<MODE>::put(ring, g.plane, slot * W + r + x, binned_pixel<mode_epl(MODE)>(g, P, y, x));
     }
 }
 
@@ -181,9 +183,9 @@ __device__ __forceinline__ Acc strip_sweep(const LensGeom &g, const PropBlock &P
                                            const int2 *__restrict__ evr, Conv conv)
 {
     const int ny = g.ny, r = g.r, H = g.strip_h, RB = g.ring_rows;
-    const int nwords = (MODE == MODE_FP32      ? RB * g.ring_w
-                        : mode_solved(MODE) ? mode_channels(MODE) * RB * g.ring_w
-                                            : RB * g.ring_w * mode_planes(MODE) / 2) / 4;
+    const int nwords = (mode_base(MODE) == MODE_FP32 ? RB * g.ring_w
+                        : mode_solved(MODE)            ? mode_channels(MODE) * RB * g.ring_w
+                                                       : RB * g.ring_w * mode_planes(MODE) / 2) / 4;
     float4 *r4 = static_cast<float4 *>(ring);
     for (int i = threadIdx.x; i < nwords; i += NT) r4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
@@ -197,7 +199,7 @@ __device__ __forceinline__ Acc strip_sweep(const LensGeom &g, const PropBlock &P
         if (y0 > 0) {
             for (int y = max(ya, ny); y < yb; ++y) {  // rows past the image: clear reused slots
                 const int slot = (y + r) % RB;
-                for (int x = threadIdx.x; x < g.nx; x += NT) RingStore<MODE>::zero(ring, g.plane, slot * g.ring_w + r + x);
+                for (int x = threadIdx.x; x < g.nx; x += NT) RingStoreM<MODE>::zero(ring, g.plane, slot * g.ring_w + r + x);
             }
         }
         if (ya < ny) fill_rows<MODE, NT>(g, P, ring, evl, evpre, evr, ya, min(yb, ny), y0 > 0);
@@ -216,6 +218,7 @@ __device__ __forceinline__ void strip_loop(const LensGeom &g, const PropBlock &P
                                            int64_t p, Conv conv)
 {
     __shared__ double red[NT / 64];
+    if constexpr (mode_epl(MODE)) epl_setup(P);   // published by strip_sweep's first barrier
     double acc = strip_sweep<MODE, NT, double>(g, P, ring, evl, evpre, evr, conv);
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -343,6 +346,7 @@ __device__ __forceinline__ void strip_loop_solved(const LensGeom &g, const PropB
 {
     constexpr int NCH = mode_channels(MODE), NM = MomN<NCH>::NM;
     __shared__ double red[NM][NT / 64];
+    if constexpr (mode_epl(MODE)) epl_setup(P);   // published by strip_sweep's first barrier
     if constexpr (NCH >= 2) {
         // each strip's moments are reduced over the wave and added to the
         // wave's LDS slots at once, so that no FP64 accumulators stay live
@@ -478,12 +482,12 @@ k_loglike_fp32(const LensGeom g, const PropBlock *__restrict__ pc, const float *
 template <int MODE>
 __device__ __forceinline__ f32x4 mfma_products(const bf16x8 (&a)[3], const bf16x8 (&b)[3], f32x4 c)
 {
-    if (MODE == MODE_SPLIT3) {
+    if (mode_base(MODE) == MODE_SPLIT3) {
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], c, 0, 0, 0);
     }
-    if (MODE == MODE_SPLIT || MODE == MODE_SPLIT3) {
+    if (mode_base(MODE) == MODE_SPLIT || mode_base(MODE) == MODE_SPLIT3) {
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], c, 0, 0, 0);
     }
@@ -753,6 +757,26 @@ k_loglike_nnls(const LensGeom g, const PropBlock *__restrict__ pc, double *__res
     });
 }
 
+// Explicit amplitudes with the PSF side chosen at run time (conv_rows_rt): the
+// elliptical power-law lenses, whose ray trace is too long for the PSF-size
+// templates of k_loglike_fp32 to pay.
+template <int MODE, int NT>
+__global__ void __launch_bounds__(NT) k_loglike_rt(const LensGeom g, const PropBlock *__restrict__ pc,
+                                                   double *__restrict__ out)
+{
+    extern __shared__ float4 lds4[];
+    float *ring = reinterpret_cast<float *>(lds4);
+    const int64_t p = blockIdx.x;
+    const PropBlock *c = pc + p;
+    if (c->valid != 1.0) {
+        if (threadIdx.x == 0) out[p] = -INFINITY;
+        return;
+    }
+    const PropBlock P = *c;
+    strip_loop<MODE, NT>(g, P, ring, g.evl, g.evpre, g.evr, out, p,
+                         [&](int y0, int y1, int) { return conv_rows_rt<NT>(g, ring, y0, y1); });
+}
+
 __global__ void k_reset_counter(unsigned int *counter) { *counter = 0u; }
 
 // Work items are (lens, proposal) pairs numbered lens-major in the batch's
@@ -795,7 +819,7 @@ k_loglike_batch(const LensGeom *__restrict__ geoms, const int *__restrict__ lsta
                 auto *ring = reinterpret_cast<typename FVec<mode_channels(MODE)>::T *>(lds4);
                 strip_loop_solved<MODE, NT>(g, P, ring, g.evl, g.evpre, g.evr, out, nullptr, p,
                                             [&](int y0, int y1, int) { return conv_rows_solved<MODE, NT>(g, ring, y0, y1); });
-            } else if (MODE == MODE_FP32) {
+            } else if (mode_base(MODE) == MODE_FP32) {
                 float *ring = reinterpret_cast<float *>(lds4);
                 strip_loop<MODE, NT>(g, P, ring, g.evl, g.evpre, g.evr, out, p, [&](int y0, int y1, int) {
                     return conv_rows_rt<NT>(g, ring, y0, y1);
@@ -836,12 +860,17 @@ __global__ void k_mfma_probe(const uint16_t *__restrict__ a, const uint16_t *__r
 // ---------------------------------------------------------------------------
 // debug model images
 // ---------------------------------------------------------------------------
+template <bool EPL>
 __global__ void k_model_binned(const LensGeom g, const PropBlock *__restrict__ pc, float *__restrict__ img)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= g.ny * g.nx) return;
     const PropBlock P = *pc;
-    img[i] = binned_pixel(g, P, i / g.nx, i % g.nx);
+    if constexpr (EPL) {
+        epl_setup(P);
+        __syncthreads();
+    }
+    if (i >= g.ny * g.nx) return;
+    img[i] = binned_pixel<EPL>(g, P, i / g.nx, i % g.nx);
 }
 
 __global__ void k_model_conv(const LensGeom g, const float *__restrict__ img, float *__restrict__ out)
@@ -872,14 +901,16 @@ double host_sersic_bn(double n) { return sersic_bn(n); }
 
 int ring_width(int mode, int k, int nx)
 {
-    if (mode == MODE_FP32 || mode_solved(mode)) return (nx + 3) / 4 * 4 + 4 * choose_kc(k);
+    if (mode_base(mode) == MODE_FP32 || mode_solved(mode)) return (nx + 3) / 4 * 4 + 4 * choose_kc(k);
     const int L = (16 + k - 1 + 7) / 8 * 8;
     return (nx + 15) / 16 * 16 + L;
 }
 
 size_t ring_row_bytes(int mode, int k, int nx)
 {
-    const size_t elem = mode == MODE_FP32 ? 4 : mode_solved(mode) ? 4 * mode_channels(mode) : 2 * mode_planes(mode);
+    const size_t elem = mode_base(mode) == MODE_FP32 ? 4
+                        : mode_solved(mode)          ? 4 * mode_channels(mode)
+                                                     : 2 * mode_planes(mode);
     return (size_t)ring_width(mode, k, nx) * elem;
 }
 
@@ -935,44 +966,45 @@ static hipError_t launch_fp32_nt(const LensGeom &g, const PropBlock *d_pc, int64
     }
 }
 
-template <int MODE, int NT>
-static hipError_t launch_m(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, hipStream_t st)
-{
-    hipLaunchKernelGGL((k_loglike_mfma<MODE, NT>), dim3((unsigned)n), dim3(NT), ring_bytes(g), st, g, d_pc,
-                       g.evl, g.evpre, g.evr, g.aop, g.seg, g.segpre, g.data, g.wgt, d_out);
-    return hipGetLastError();
-}
+// Every mode, with the SIE and with the elliptical power law (MODE_EPL).
+#define LENS_FOR_MODES(X) \
+    X(0) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15)
 
-template <int NT>
-static hipError_t launch_nt(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, hipStream_t st)
+// The single-lens likelihood kernel of a mode other than the SIE's FP32 one
+// (which has one kernel per PSF side): runtime-k FP32, MFMA, or solved amplitudes.
+template <int MODE, int NT>
+static const void *mode_kernel_ptr()
 {
-    switch (g.mode) {
-    case MODE_FP32: return launch_fp32_nt<NT>(g, d_pc, n, d_out, st);
-    case MODE_BF16: return launch_m<MODE_BF16, NT>(g, d_pc, n, d_out, st);
-    case MODE_SPLIT: return launch_m<MODE_SPLIT, NT>(g, d_pc, n, d_out, st);
-    case MODE_SPLIT3: return launch_m<MODE_SPLIT3, NT>(g, d_pc, n, d_out, st);
-    default: return hipErrorInvalidValue;
-    }
+    if constexpr (mode_solved(MODE)) return reinterpret_cast<const void *>(&k_loglike_nnls<MODE, NT>);
+    else if constexpr (mode_base(MODE) == MODE_FP32) return reinterpret_cast<const void *>(&k_loglike_rt<MODE, NT>);
+    else return reinterpret_cast<const void *>(&k_loglike_mfma<MODE, NT>);
 }
 
 template <int MODE, int NT>
-static hipError_t launch_nnls_m(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, double *d_amp,
-                                hipStream_t st)
-{
-    hipLaunchKernelGGL((k_loglike_nnls<MODE, NT>), dim3((unsigned)n), dim3(NT), ring_bytes(g), st, g, d_pc, d_out,
-                       d_amp);
-    return hipGetLastError();
-}
-
-template <int NT>
-static hipError_t launch_nnls(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, double *d_amp,
+static hipError_t launch_mode(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, double *d_amp,
                               hipStream_t st)
 {
+    if constexpr (mode_solved(MODE))
+        hipLaunchKernelGGL((k_loglike_nnls<MODE, NT>), dim3((unsigned)n), dim3(NT), ring_bytes(g), st, g, d_pc, d_out,
+                           d_amp);
+    else if constexpr (mode_base(MODE) == MODE_FP32)
+        hipLaunchKernelGGL((k_loglike_rt<MODE, NT>), dim3((unsigned)n), dim3(NT), ring_bytes(g), st, g, d_pc, d_out);
+    else
+        hipLaunchKernelGGL((k_loglike_mfma<MODE, NT>), dim3((unsigned)n), dim3(NT), ring_bytes(g), st, g, d_pc,
+                           g.evl, g.evpre, g.evr, g.aop, g.seg, g.segpre, g.data, g.wgt, d_out);
+    return hipGetLastError();
+}
+
+template <int NT>
+static hipError_t launch_nt(const LensGeom &g, const PropBlock *d_pc, int64_t n, double *d_out, double *d_amp,
+                            hipStream_t st)
+{
+    if (g.mode == MODE_FP32) return launch_fp32_nt<NT>(g, d_pc, n, d_out, st);
     switch (g.mode) {
-    case MODE_FP32N: return launch_nnls_m<MODE_FP32N, NT>(g, d_pc, n, d_out, d_amp, st);
-    case MODE_FP32N_LENS: return launch_nnls_m<MODE_FP32N_LENS, NT>(g, d_pc, n, d_out, d_amp, st);
-    case MODE_FP32N_SRC: return launch_nnls_m<MODE_FP32N_SRC, NT>(g, d_pc, n, d_out, d_amp, st);
-    case MODE_FP32N_DBL: return launch_nnls_m<MODE_FP32N_DBL, NT>(g, d_pc, n, d_out, d_amp, st);
+#define LENS_M(M) \
+    case M: return launch_mode<M, NT>(g, d_pc, n, d_out, d_amp, st);
+        LENS_FOR_MODES(LENS_M)
+#undef LENS_M
     default: return hipErrorInvalidValue;
     }
 }
@@ -981,13 +1013,8 @@ hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, d
                           hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    if (mode_solved(g.mode)) {
-        if (g.nt == 512) return launch_nnls<512>(g, d_pc, n, d_out, d_amp, st);
-        if (g.nt == 256) return launch_nnls<256>(g, d_pc, n, d_out, d_amp, st);
-        return hipErrorInvalidValue;
-    }
-    if (g.nt == 512) return launch_nt<512>(g, d_pc, n, d_out, st);
-    if (g.nt == 256) return launch_nt<256>(g, d_pc, n, d_out, st);
+    if (g.nt == 512) return launch_nt<512>(g, d_pc, n, d_out, d_amp, st);
+    if (g.nt == 256) return launch_nt<256>(g, d_pc, n, d_out, d_amp, st);
     return hipErrorInvalidValue;
 }
 
@@ -996,16 +1023,14 @@ static const void *batch_kernel(int mode, int nt);
 template <int NT>
 static const void *loglike_kernel_nt(const LensGeom &g)
 {
-    switch (g.mode) {
-    case MODE_BF16: return reinterpret_cast<const void *>(&k_loglike_mfma<MODE_BF16, NT>);
-    case MODE_SPLIT: return reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT, NT>);
-    case MODE_SPLIT3: return reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT3, NT>);
-    case MODE_FP32N: return reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N, NT>);
-    case MODE_FP32N_LENS: return reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N_LENS, NT>);
-    case MODE_FP32N_SRC: return reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N_SRC, NT>);
-    case MODE_FP32N_DBL: return reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N_DBL, NT>);
-    case MODE_FP32: break;
-    default: return nullptr;
+    if (g.mode != MODE_FP32) {
+        switch (g.mode) {
+#define LENS_M(M) \
+    case M: return mode_kernel_ptr<M, NT>();
+            LENS_FOR_MODES(LENS_M)
+#undef LENS_M
+        default: return nullptr;
+        }
     }
     switch (g.k) {
 #define LENS_K(KK) \
@@ -1036,16 +1061,11 @@ static void likelihood_kernels_nt(std::vector<const void *> &v)
     LENS_K(33) LENS_K(35) LENS_K(37) LENS_K(39) LENS_K(41) LENS_K(43) LENS_K(45) LENS_K(47)
     LENS_K(49) LENS_K(51) LENS_K(53) LENS_K(55) LENS_K(57) LENS_K(59) LENS_K(61) LENS_K(63)
 #undef LENS_K
-    v.push_back(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_BF16, NT>));
-    v.push_back(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT, NT>));
-    v.push_back(reinterpret_cast<const void *>(&k_loglike_mfma<MODE_SPLIT3, NT>));
-    v.push_back(reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N, NT>));
-    v.push_back(reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N_LENS, NT>));
-    v.push_back(reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N_SRC, NT>));
-    v.push_back(reinterpret_cast<const void *>(&k_loglike_nnls<MODE_FP32N_DBL, NT>));
-    for (int m : {MODE_FP32, MODE_SPLIT, MODE_BF16, MODE_SPLIT3, MODE_FP32N, MODE_FP32N_LENS, MODE_FP32N_SRC,
-                  MODE_FP32N_DBL})
-        v.push_back(batch_kernel(m, NT));
+#define LENS_M(M)                                 \
+    if (M != MODE_FP32) v.push_back(mode_kernel_ptr<M, NT>()); \
+    v.push_back(batch_kernel(M, NT));
+    LENS_FOR_MODES(LENS_M)
+#undef LENS_M
 }
 
 // Raise every ring-using kernel's dynamic-LDS limit so that dynamic plus
@@ -1079,38 +1099,17 @@ size_t lds_per_cu()
     return (size_t)v;
 }
 
-template <int MODE, int NT>
-static const void *batch_kernel_ptr()
-{
-    return reinterpret_cast<const void *>(&k_loglike_batch<MODE, NT>);
-}
-
 static const void *batch_kernel(int mode, int nt)
 {
-    if (nt == 256) {
-        switch (mode) {
-        case MODE_FP32: return batch_kernel_ptr<MODE_FP32, 256>();
-        case MODE_SPLIT: return batch_kernel_ptr<MODE_SPLIT, 256>();
-        case MODE_BF16: return batch_kernel_ptr<MODE_BF16, 256>();
-        case MODE_SPLIT3: return batch_kernel_ptr<MODE_SPLIT3, 256>();
-        case MODE_FP32N: return batch_kernel_ptr<MODE_FP32N, 256>();
-        case MODE_FP32N_LENS: return batch_kernel_ptr<MODE_FP32N_LENS, 256>();
-        case MODE_FP32N_SRC: return batch_kernel_ptr<MODE_FP32N_SRC, 256>();
-        case MODE_FP32N_DBL: return batch_kernel_ptr<MODE_FP32N_DBL, 256>();
-        }
-    } else if (nt == 512) {
-        switch (mode) {
-        case MODE_FP32: return batch_kernel_ptr<MODE_FP32, 512>();
-        case MODE_SPLIT: return batch_kernel_ptr<MODE_SPLIT, 512>();
-        case MODE_BF16: return batch_kernel_ptr<MODE_BF16, 512>();
-        case MODE_SPLIT3: return batch_kernel_ptr<MODE_SPLIT3, 512>();
-        case MODE_FP32N: return batch_kernel_ptr<MODE_FP32N, 512>();
-        case MODE_FP32N_LENS: return batch_kernel_ptr<MODE_FP32N_LENS, 512>();
-        case MODE_FP32N_SRC: return batch_kernel_ptr<MODE_FP32N_SRC, 512>();
-        case MODE_FP32N_DBL: return batch_kernel_ptr<MODE_FP32N_DBL, 512>();
-        }
+    switch (mode) {
+#define LENS_M(M)                                                                                    \
+    case M:                                                                                          \
+        return nt == 256 ? reinterpret_cast<const void *>(&k_loglike_batch<M, 256>)                  \
+               : nt == 512 ? reinterpret_cast<const void *>(&k_loglike_batch<M, 512>) : nullptr;
+        LENS_FOR_MODES(LENS_M)
+#undef LENS_M
+    default: return nullptr;
     }
-    return nullptr;
 }
 
 int batch_blocks_per_cu(int mode, int nt, size_t lds)
@@ -1146,13 +1145,11 @@ hipError_t launch_model_image(const LensGeom &g, const PropBlock *d_pc, int stag
 {
     const int npix = g.ny * g.nx;
     const int bs = 256, nb = (npix + bs - 1) / bs;
-    if (stage == 0) {
-        hipLaunchKernelGGL(k_model_binned, dim3(nb), dim3(bs), 0, st, g, d_pc, d_img);
-        return hipGetLastError();
-    }
-    hipLaunchKernelGGL(k_model_binned, dim3(nb), dim3(bs), 0, st, g, d_pc, d_tmp);
+    float *dst = stage == 0 ? d_img : d_tmp;
+    if (mode_epl(g.mode)) hipLaunchKernelGGL((k_model_binned<true>), dim3(nb), dim3(bs), 0, st, g, d_pc, dst);
+    else hipLaunchKernelGGL((k_model_binned<false>), dim3(nb), dim3(bs), 0, st, g, d_pc, dst);
     hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || stage == 0) return e;
     hipLaunchKernelGGL(k_model_conv, dim3(nb), dim3(bs), 0, st, g, d_tmp, d_img);
     return hipGetLastError();
 }

@@ -26,21 +26,25 @@ __device__ inline LightK light_constants(double I, double R, double n, double q,
     return L;
 }
 
-// Derived constants of the proposal with slots v[0..18] under light model
-// lm.  The light model decides which slots are read and validated: lens
-// light only ignores the mass, shear and source slots; source only ignores
-// the lens light; two components per galaxy read slots n_l and n_s as the
-// second components' R_e (their indices are fixed per lens and taken from the
-// lens descriptor by the likelihood kernel).
-__device__ inline PropBlock prep_proposal(const double *v, int lm)
+// Derived constants of the proposal with slots v[0..19] under model code
+// (light model | mass << kMassShift).  The light model decides which slots are
+// read and validated: lens light only ignores the mass, shear and source
+// slots; source only ignores the lens light; two components per galaxy read
+// slots n_l and n_s as the second components' R_e (their indices are fixed per
+// lens and taken from the lens descriptor by the likelihood kernel).  The
+// elliptical power law reads its slope gamma from slot 19 (the SIE ignores it).
+__device__ inline PropBlock prep_proposal(const double *v, int code)
 {
     PropBlock b{};
+    const int lm = code & ((1 << kMassShift) - 1);
+    const bool epl = (code >> kMassShift) & 1;
     const bool mass = lm != LIGHT_LENS, lens = lm != LIGHT_SRC, src = lm != LIGHT_LENS, dbl = lm == LIGHT_DOUBLE;
     bool ok = isfinite(v[3]) && isfinite(v[4]);
     if (mass) {
 #pragma unroll
         for (int j = 0; j < 7; ++j) ok = ok && isfinite(v[j]);
         ok = ok && v[0] >= 0.0 && v[1] > 0.0 && v[1] <= 1.0;
+        if (epl) ok = ok && v[19] >= kGammaMin && v[19] <= kGammaMax;
     }
     if (lens) {
         ok = ok && isfinite(v[8]) && isfinite(v[9]) && isfinite(v[10]) && isfinite(v[11]);
@@ -69,6 +73,13 @@ __device__ inline PropBlock prep_proposal(const double *v, int lm)
             b.g1 = v[5];
             b.g2 = v[6];
             b.g1p = 1.0 + v[5];
+            if (epl) {
+                const double t = v[19] - 1.0;
+                b.epl_q = q;
+                b.epl_pref = 2.0 * pow(v[0] * sqrt(q), t) / (1.0 + q);
+                b.epl_h = 0.5 * (1.0 - t);
+                b.epl_mf = -(1.0 - q) / (1.0 + q);
+            }
         }
         // two-component light: e and B of the fixed indices come from the lens descriptor
         if (lens) b.lens = light_constants(v[7], v[8], dbl ? 1.0 : v[9], v[10], v[11]);

@@ -44,6 +44,8 @@ struct Lens {
     int precision = 0;
     int amplitudes = 0;     // LENS_AMP_*
     int light_model = 0;    // LENS_LIGHT_*
+    int mass_model = 0;     // LENS_MASS_*
+    int prep_code = 0;      // the prep step's model code: light model | mass << kMassShift
     int64_t masked = 0, needed = 0;
     int psf_given = 0;      // PSF side as loaded (g.k is the side after the tail crop)
     void *slab = nullptr;   // one device allocation holding every array
@@ -195,7 +197,7 @@ int default_strip(const LensGeom &g, size_t lds_max, size_t lds_cu, int *nt)
 {
     const size_t row_b = lensk::ring_row_bytes(g.mode, g.k, g.nx);
     const auto ring = [&](int H) { return (size_t)(H + 2 * g.r) * row_b; };
-    if (g.mode == lensk::MODE_FP32 && ring(std::min(16, g.ny)) <= std::min(lds_max, lds_cu / 4)) {
+    if (lensk::mode_base(g.mode) == lensk::MODE_FP32 && ring(std::min(16, g.ny)) <= std::min(lds_max, lds_cu / 4)) {
         *nt = 256;
         return std::min(16, g.ny);
     }
@@ -413,7 +415,7 @@ ScratchLayout carve(void *base, int64_t n, bool with_params_out)
 hipError_t launch_lens(const Lens *L, const double *d_params, lensk::PropBlock *d_pc, int64_t n, double *d_out,
                        hipStream_t st, double *d_amp = nullptr)
 {
-    hipError_t e = lensk::launch_prep(d_params, n, d_pc, L->light_model, nullptr, nullptr, 0, st);
+    hipError_t e = lensk::launch_prep(d_params, n, d_pc, L->prep_code, nullptr, nullptr, 0, st);
     if (e != hipSuccess) return e;
     return lensk::launch_loglike(L->g, d_pc, n, d_out, d_amp, st);
 }
@@ -638,7 +640,7 @@ lens_status tune_lens(lens_ctx *c, Lens *L)
     lensk::PropBlock *dpc = (lensk::PropBlock *)((char *)buf + pb);
     double *dout = (double *)((char *)buf + pb + cb);
     HIPCHK(c, hipMemcpyAsync(dp, hp.data(), hp.size() * 8, hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, lensk::launch_prep(dp, n, dpc, L->light_model, nullptr, nullptr, 0, c->stream));
+    HIPCHK(c, lensk::launch_prep(dp, n, dpc, L->prep_code, nullptr, nullptr, 0, c->stream));
     hipEvent_t e0, e1;
     HIPCHK(c, hipEventCreate(&e0));
     HIPCHK(c, hipEventCreate(&e1));
@@ -741,6 +743,8 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
         return fail(c, LENS_EINVAL, "unknown light model");
     if (d->light_model != LENS_LIGHT_BOTH && d->amplitudes != LENS_AMP_NNLS)
         return fail(c, LENS_EINVAL, "light models other than LENS_LIGHT_BOTH need LENS_AMP_NNLS");
+    if (d->mass_model != LENS_MASS_SIE && d->mass_model != LENS_MASS_EPL)
+        return fail(c, LENS_EINVAL, "unknown mass model");
     if (d->light_model == LENS_LIGHT_DOUBLE)
         for (int j = 0; j < 4; ++j)
             if (!(d->sersic_n[j] >= lensk::kNMin && d->sersic_n[j] <= lensk::kNMax))
@@ -776,7 +780,8 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     // light component, in the mode of the light model
     static const int solved_mode[4] = {lensk::MODE_FP32N, lensk::MODE_FP32N_LENS, lensk::MODE_FP32N_SRC,
                                        lensk::MODE_FP32N_DBL};
-    const int mode = d->amplitudes == LENS_AMP_NNLS ? solved_mode[d->light_model] : d->precision;
+    const int mode = (d->amplitudes == LENS_AMP_NNLS ? solved_mode[d->light_model] : d->precision) |
+                     (d->mass_model == LENS_MASS_EPL ? (int)lensk::MODE_EPL : 0);
     const int pitch = (int)align_up((size_t)nx, 16);
     // masked column range of each row
     std::vector<int> mlo(ny, INT_MAX), mhi(ny, INT_MIN);
@@ -820,7 +825,8 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     std::vector<uint32_t> seg;
     std::vector<int> segpre(ny + 1, 0);
     std::vector<uint16_t> aop;
-    if (mode == lensk::MODE_SPLIT || mode == lensk::MODE_BF16 || mode == lensk::MODE_SPLIT3) {
+    if (lensk::mode_base(mode) == lensk::MODE_SPLIT || lensk::mode_base(mode) == lensk::MODE_BF16 ||
+        lensk::mode_base(mode) == lensk::MODE_SPLIT3) {
         g.L = (int)align_up((size_t)(16 + k - 1), 8);
         g.nchunks = (int)((k * g.L + 31) / 32);
         for (int y = 0; y < ny; ++y) {
@@ -929,6 +935,8 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     L->precision = d->precision;
     L->amplitudes = d->amplitudes;
     L->light_model = d->light_model;
+    L->mass_model = d->mass_model;
+    L->prep_code = d->light_model | (d->mass_model << lensk::kMassShift);
     L->psf_given = k_given;
     L->masked = masked;
     L->needed = (int64_t)evl.size();
@@ -1007,6 +1015,7 @@ extern "C" lens_status lens_get_info(lens_ctx *c, lens_id id, lens_info *out)
     out->psf_used = L->g.k;
     out->amplitudes = L->amplitudes;
     out->light_model = L->light_model;
+    out->mass_model = L->mass_model;
     out->n_amplitudes = lensk::mode_solved(L->g.mode) ? lensk::mode_channels(L->g.mode) : 2;
     {
         DeviceGuard dg(c->device);
@@ -1248,9 +1257,9 @@ lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int
     }
     // light model of every proposal: one for all, or per lens by proposal offset
     bool one_model = true;
-    for (int i = 1; i < nlens; ++i) one_model = one_model && Ls[i]->light_model == Ls[0]->light_model;
+    for (int i = 1; i < nlens; ++i) one_model = one_model && Ls[i]->prep_code == Ls[0]->prep_code;
     std::vector<int> hmodel(nlens);
-    for (int i = 0; i < nlens; ++i) hmodel[i] = Ls[i]->light_model;
+    for (int i = 0; i < nlens; ++i) hmodel[i] = Ls[i]->prep_code;
     // device layout: params | pc | out | geoms | lstart | lout | counters | pstart | pmodel
     const size_t b_par = align_up((size_t)tot * lensk::kStride * 8, kAlign);
     const size_t b_pc = align_up((size_t)tot * lensk::kPCBytes, kAlign);
@@ -1400,7 +1409,8 @@ extern "C" lens_status lens_model_image(lens_ctx *c, lens_id id, const double *p
             lensk::PropBlock pc{};
             std::vector<float> hi((size_t)npix);
             hipError_t e = hipMemcpyAsync(dp, params1, lensk::kStride * sizeof(double), hipMemcpyHostToDevice, c->stream);
-            if (e == hipSuccess) e = lensk::launch_prep(dp, 1, dpc, LENS_LIGHT_BOTH, nullptr, nullptr, 0, c->stream);
+            const int code = LENS_LIGHT_BOTH | (L->mass_model << lensk::kMassShift);
+            if (e == hipSuccess) e = lensk::launch_prep(dp, 1, dpc, code, nullptr, nullptr, 0, c->stream);
             if (e == hipSuccess) e = hipMemcpyAsync(&pc, dpc, sizeof(pc), hipMemcpyDeviceToHost, c->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
             if (e == hipSuccess && pc.valid != 1.0) {
@@ -1941,7 +1951,7 @@ lens_status ensemble_run(lens_ctx *c, Ensemble *E, int64_t iterations, int32_t t
         const bool keep = nstore > 0 && (it + 1) % thin == 0 && (it + 1) / thin <= nstore;
         const int64_t slot = keep ? (it + 1) / thin - 1 : 0;
         for (int half = 0; half < 2 && e == hipSuccess; ++half) {
-            e = lensk::launch_stretch_propose(W, half, t, E->seed, E->a, E->L->light_model, E->walkers, E->lo, E->hi,
+            e = lensk::launch_stretch_propose(W, half, t, E->seed, E->a, E->L->prep_code, E->walkers, E->lo, E->hi,
                                               E->Y, E->aux, E->pc, c->stream);
             if (e == hipSuccess) e = lensk::launch_loglike(E->L->g, E->pc, h, E->out, nullptr, c->stream);
             if (e == hipSuccess)

@@ -64,7 +64,7 @@ __global__ void __launch_bounds__(256) k_philox_words(uint4 base, uint2 key, int
 // A proposal outside the box is not evaluated: its prepared constants are
 // marked outside the domain, so the likelihood kernel returns -inf at once.
 __global__ void __launch_bounds__(256)
-k_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int light_model,
+k_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int model_code,
                   const double *__restrict__ walkers, const double *__restrict__ lo,
                   const double *__restrict__ hi, double *__restrict__ Y, double4 *__restrict__ aux,
                   PropBlock *__restrict__ pc)
@@ -89,7 +89,7 @@ k_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int ligh
         Y[(size_t)i * kStride + s] = v[s];
     }
     aux[i] = make_double4(z, log(u2), inside ? 1.0 : 0.0, 0.0);
-    pc[i] = inside ? prep_proposal(v, light_model) : PropBlock{};
+    pc[i] = inside ? prep_proposal(v, model_code) : PropBlock{};
 }
 
 // Walker k takes its proposal when ln u2 < (d - 1) ln z + lnP(Y) - lnP(X_k),
@@ -132,13 +132,13 @@ hipError_t launch_philox_words(const uint32_t ctr[4], const uint32_t key[2], int
     return hipGetLastError();
 }
 
-hipError_t launch_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int light_model,
+hipError_t launch_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int model_code,
                                   const double *d_walkers, const double *d_lo, const double *d_hi, double *d_Y,
                                   double *d_aux, PropBlock *d_pc, hipStream_t st)
 {
     const int h = W / 2, bs = 256;
     hipLaunchKernelGGL(k_stretch_propose, dim3((unsigned)((h + bs - 1) / bs)), dim3(bs), 0, st, W, half, t, seed,
-                       a, light_model, d_walkers, d_lo, d_hi, d_Y, reinterpret_cast<double4 *>(d_aux), d_pc);
+                       a, model_code, d_walkers, d_lo, d_hi, d_Y, reinterpret_cast<double4 *>(d_aux), d_pc);
     return hipGetLastError();
 }
 

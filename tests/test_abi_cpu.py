@@ -57,8 +57,8 @@ def test_struct_layouts_match_header():
     # the ctypes mirrors of the ABI structs must have the C sizes (x86-64 SysV)
     from paper_2503_08586_amd import binding
     assert ctypes.sizeof(binding.lens_init_opts) == 4 + 4 + 8 + 4 + 4 + 8 * 4 + 8
-    assert ctypes.sizeof(binding.lens_data_desc) == 4 + 4 + 8 + 4 + 4 + 8 * 4 + 4 + 4 + 8 + 4 + 4 + 8 * 4
-    assert ctypes.sizeof(binding.lens_info) == 5 * 4 + 4 + 8 * 4 + 2 * 4 + 8 + 5 * 4 + 4
+    assert ctypes.sizeof(binding.lens_data_desc) == 4 + 4 + 8 + 4 + 4 + 8 * 4 + 4 + 4 + 8 + 4 + 4 + 8 * 4 + 4 + 4
+    assert ctypes.sizeof(binding.lens_info) == 5 * 4 + 4 + 8 * 4 + 2 * 4 + 8 + 6 * 4
     assert ctypes.sizeof(binding.lens_stats) == 10 * 8
 
 
