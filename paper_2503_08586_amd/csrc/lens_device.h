@@ -389,7 +389,10 @@ __host__ __device__ inline double sersic_bn(double n)
         if (!(xn > lo && xn < hi)) xn = 0.5 * (lo + hi);
         const double dx = fabs(xn - x);
         x = xn;
-        if (dx <= 4e-16 * x || hi - lo <= 4e-16 * x) break;
+        // Newton converges quadratically: after a step below 1e-9 relative the new
+        // iterate is exact to rounding (~1e-15 from the series and exp); waiting for
+        // a step below 4e-16 instead runs up to 11 iterations bouncing at the last ulp
+        if (dx <= 1e-9 * x || hi - lo <= 4e-16 * x) break;
     }
     return x;
 }

@@ -63,7 +63,7 @@ __global__ void __launch_bounds__(256) k_philox_words(uint4 base, uint2 key, int
 // Y = X_j + z (X_k - X_j).  aux[i] = (z, ln u2, inside the box ? 1 : 0, -).
 // A proposal outside the box is not evaluated: its prepared constants are
 // marked outside the domain, so the likelihood kernel returns -inf at once.
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
 k_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int model_code,
                   const double *__restrict__ walkers, const double *__restrict__ lo,
                   const double *__restrict__ hi, double *__restrict__ Y, double4 *__restrict__ aux,
@@ -136,7 +136,9 @@ hipError_t launch_stretch_propose(int W, int half, uint64_t t, uint64_t seed, do
                                   const double *d_walkers, const double *d_lo, const double *d_hi, double *d_Y,
                                   double *d_aux, PropBlock *d_pc, hipStream_t st)
 {
-    const int h = W / 2, bs = 256;
+    // one wave per workgroup: the prep step is latency-bound (two b_n roots per
+    // walker), so the half's walkers are spread over as many CUs as possible
+    const int h = W / 2, bs = 64;
     hipLaunchKernelGGL(k_stretch_propose, dim3((unsigned)((h + bs - 1) / bs)), dim3(bs), 0, st, W, half, t, seed,
                        a, model_code, d_walkers, d_lo, d_hi, d_Y, reinterpret_cast<double4 *>(d_aux), d_pc);
     return hipGetLastError();

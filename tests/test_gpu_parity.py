@@ -105,6 +105,8 @@ GEOMS = [
     ("single_pixel", 1, 1, 0.1, 2, 3, "full"),
     ("tall_s2_k13", 150, 41, 0.06, 2, 13, "circle"),
     ("s5_k41", 48, 52, 0.05, 5, 41, "circle"),
+    ("max_width_4096", 6, 4096, 0.05, 1, 3, "random"),
+    ("max_height_4096", 4096, 5, 0.05, 1, 5, "random"),
 ]
 
 

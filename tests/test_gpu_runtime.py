@@ -46,6 +46,18 @@ def test_bad_descriptors(ctx, b):
     with pytest.raises(b.LensError) as ei:
         ctx.load_raw(sp.ny, sp.nx, sp.dpix, sp.s, sp.psf, sp.data, sp.sigma, sp.mask, precision=7)
     assert ei.value.status == b.LENS_EINVAL
+    # dimensions past 4096, and an image too wide for the LDS line buffer at its PSF size
+    z = np.zeros((2, 4097))
+    with pytest.raises(b.LensError) as ei:
+        ctx.load_raw(2, 4097, 0.05, 1, np.ones((1, 1)), z, z + 1.0, np.ones((2, 4097), np.uint8))
+    assert ei.value.status == b.LENS_EINVAL
+    wide = np.zeros((70, 4096))
+    psf63 = np.zeros((63, 63))
+    psf63[31, 31] = 1.0
+    psf63[0, 0] = psf63[62, 62] = 0.25       # keeps the 63x63 footprint through the tail crop
+    with pytest.raises(b.LensError) as ei:
+        ctx.load_raw(70, 4096, 0.05, 1, psf63, wide, wide + 1.0, np.ones((70, 4096), np.uint8))
+    assert ei.value.status == b.LENS_EINVAL
     # sigma and data may be anything outside the mask
     lid = ctx.load_raw(sp.ny, sp.nx, sp.dpix, sp.s, sp.psf, np.where(sp.mask == 1, sp.data, np.nan),
                        np.where(sp.mask == 1, sp.sigma, 0.0), sp.mask)
