@@ -17,6 +17,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <tuple>
 #include <memory>
 #include <mutex>
 #include <string>
@@ -1213,13 +1214,20 @@ lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int
     pl->ids.assign(ids, ids + nlens);
     pl->counts.assign(counts, counts + nlens);
     pl->tot = tot;
-    // groups by (mode, workgroup size); inside a group lenses in descending
-    // per-proposal cost, so the longest items start first
+    // groups by (mode, workgroup size, resident workgroups per CU at the lens's
+    // own LDS ring): a persistent launch sizes its grid by its largest ring, so
+    // lenses whose rings allow more workgroups per CU are not held to the
+    // occupancy of the widest; inside a group lenses in descending per-proposal
+    // cost, so the longest items start first
     std::vector<int64_t> off(nlens + 1, 0);
     for (int i = 0; i < nlens; ++i) off[i + 1] = off[i] + counts[i];
-    std::map<std::pair<int, int>, std::vector<int>> groups;
+    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
     for (int i = 0; i < nlens; ++i)
-        if (counts[i] > 0) groups[{Ls[i]->g.mode, Ls[i]->g.nt}].push_back(i);
+        if (counts[i] > 0) {
+            const LensGeom &g = Ls[i]->g;
+            const int occ = lensk::batch_blocks_per_cu(g.mode, g.nt, lensk::ring_bytes(g));
+            groups[std::make_tuple(g.mode, g.nt, -occ)].push_back(i);
+        }
     struct G {
         int mode, nt, nl, nitems, grid;
         size_t lds, o_geom, o_ls, o_lo;
@@ -1236,8 +1244,8 @@ lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int
         };
         std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return cost(a) > cost(b); });
         G gg{};
-        gg.mode = kv.first.first;
-        gg.nt = kv.first.second;
+        gg.mode = std::get<0>(kv.first);
+        gg.nt = std::get<1>(kv.first);
         gg.nl = (int)v.size();
         gg.o_geom = hgeom.size();
         gg.o_ls = hls.size();
