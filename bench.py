@@ -49,8 +49,11 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target wall time of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (for HBM counter calibration)")
-    ap.add_argument("--workload", default="plain", choices=["plain", "batch", "precision", "serving", "sampler"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "batch", "precision", "serving", "sampler",
+                                                             "sampler_many"])
     ap.add_argument("--walkers", type=int, default=16384, help="sampler: ensemble size")
+    ap.add_argument("--lenses", type=int, default=256, help="sampler_many: lenses, one ensemble each")
+    ap.add_argument("--walkers-per-lens", type=int, default=64, help="sampler_many: walkers per ensemble")
     ap.add_argument("--precision", default=None, choices=["fp32", "split", "bf16", "split3"])
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--amplitudes", default="explicit", choices=["explicit", "nnls"],
@@ -183,6 +186,8 @@ def main():
         return run_serving(args)
     if args.workload == "sampler":
         return run_sampler(args)
+    if args.workload == "sampler_many":
+        return run_sampler_many(args)
     if args.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
         y = torch.empty_like(x)
@@ -480,6 +485,92 @@ def run_sampler(args):
     }
     print(json.dumps(rec), flush=True)
     ctx.ensemble_destroy(ens)
+    ctx.close()
+
+
+def run_sampler_many(args):
+    """Survey fitting: --lenses heterogeneous lenses of the batching mix, each
+    with its own --walkers-per-lens ensemble, advanced together (pooled
+    proposals per half-step); one step = one iteration of every ensemble.
+    Beside it, the same ensembles advanced one after another."""
+    import torch
+
+    from paper_2503_08586_amd import binding, synth
+    specs = synth.config3(nlens=args.lenses, scale_props=0.0)
+    ctx, st = _stream_ctx(binding, torch)
+    lo = np.array([b[1] for b in synth.PRIOR_BOX] + [0.0])
+    hi = np.array([b[2] for b in synth.PRIOR_BOX] + [0.0])
+    W = args.walkers_per_lens
+    rng = np.random.default_rng(synth.SEED_BASE + 7)
+    lids, pooled, single, slots = [], [], [], 0.0
+    for i, sp in enumerate(specs):
+        gpu_data(ctx, sp)
+        lid = ctx.load(sp)
+        lids.append(lid)
+        sl, _ = credited_slots(sp, ctx.info(lid))
+        slots += sl * W
+        init = np.clip(sp.truth[None, :] + 0.02 * (hi - lo)[None, :] * rng.normal(size=(W, 20)), lo, hi)
+        pooled.append(ctx.ensemble(lid, init, lo, hi, stretch=2.0, seed=synth.SEED_BASE + i))
+        single.append(ctx.ensemble(lid, init, lo, hi, stretch=2.0, seed=synth.SEED_BASE + i))
+    ctx.ensemble_run_many(pooled, args.warmup)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(st)
+    ctx.ensemble_run_many(pooled, args.steps)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    loop_s = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    n = W * len(specs) * args.steps
+    # the same ensembles one after another (after the same warm-up)
+    for e in single:
+        ctx.ensemble_run(e, args.warmup)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for e in single:
+        ctx.ensemble_run(e, args.steps)
+    torch.cuda.synchronize()
+    seq_s = time.perf_counter() - t1
+    same = all(all(np.array_equal(x, y) for x, y in zip(ctx.ensemble_get(p)[:3], ctx.ensemble_get(q)[:3]))
+               for p, q in zip(pooled, single))
+    acc = sum(float(ctx.ensemble_get(p)[2].sum()) for p in pooled)
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the final walkers of the first lenses, lens by lens, until about --cpu-seconds
+        tc, ns, nl = 0.0, 0, 0
+        for j in range(len(specs)):
+            w, _, _, _ = ctx.ensemble_get(pooled[j])
+            _, dt, threads = oracle_sample([(specs[j], w)])
+            tc, ns, nl = tc + dt, ns + len(w), nl + 1
+            if tc >= args.cpu_seconds:
+                break
+        cpu = {"value": ns / tc, "unit": "loglike evals/s", "cores": min(threads, W), "kind": "oracle",
+               "sample": "lnL of the %d final walkers of each of the first %d lenses, %.1f s" % (W, nl, tc)}
+    rec = {
+        "metric": METRIC, "value": n / loop_s, "unit": "loglike evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": loop_s / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": path_dtype(None),
+        "data": "synthetic",
+        "config": {"workload": "survey sampling on the device: %d lenses of the batching mix (N 48-160 px, "
+                               "s 2|4, k 11-31), one %d-walker stretch-move ensemble each, advanced together; "
+                               "one step = one iteration of every ensemble (%d proposals)"
+                               % (len(specs), W, W * len(specs)),
+                   "lenses": len(specs), "walkers_per_lens": W,
+                   "acceptance": acc / max(1, W * len(specs) * (args.steps + args.warmup))},
+        "separate_runs_evals_per_s": n / seq_s,
+        "pooled_over_separate": seq_s / loop_s,
+        "pooled_equals_separate_bitwise": same,
+        "roofline": {"bound": "alu", "achieved": slots * args.steps / (gpu_ms * 1e-3) / 1e12,
+                     "peak": PEAK_SLOT_PER_S / 1e12, "unit": "Tslot/s",
+                     "frac": slots * args.steps / (gpu_ms * 1e-3) / PEAK_SLOT_PER_S, "traffic": None,
+                     "kernel": "k_stretch_propose_many + k_loglike_batch + k_stretch_accept_many per half-step",
+                     "loop_ms": gpu_ms},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    for e in pooled + single:
+        ctx.ensemble_destroy(e)
     ctx.close()
 
 

@@ -314,6 +314,19 @@ lens_status lens_ensemble_create(lens_ctx *ctx, lens_id id, const lens_ensemble_
  * copied back at the end: split long runs into several calls. */
 lens_status lens_ensemble_run(lens_ctx *ctx, lens_ens ens, int64_t iterations, int32_t thin,
                               double *chain, double *chain_lnp);
+/* Advances the n distinct ensembles ens[0..n-1] by `iterations` iterations
+ * each, together: every half-step makes the proposals of all of them in one
+ * launch, evaluates the pooled proposals with the multi-lens likelihood
+ * (lens_loglike_multi's grouping and kernels) and accepts them in one launch,
+ * so that many small ensembles, one per lens of a survey, fill the device
+ * where each alone would not.  Each ensemble moves exactly as under
+ * lens_ensemble_run from its own iteration count (same stream, same result,
+ * bit for bit); no chain is returned (read the state with lens_ensemble_get).
+ * Blocks until done.  LENS_EINVAL for a repeated id or more than INT_MAX
+ * pooled proposals (sum of W/2); LENS_ENOENT for an unknown id (nothing
+ * moves); LENS_ENOMEM past the HBM budget for the pooled scratch,
+ * sum W/2 x 456 bytes plus the per-ensemble descriptors. */
+lens_status lens_ensemble_run_many(lens_ctx *ctx, int32_t n, const lens_ens *ens, int64_t iterations);
 /* The current walkers [W][20], their lnP [W], accepted moves per walker [W]
  * and the iterations done so far; any output may be NULL. */
 lens_status lens_ensemble_get(lens_ctx *ctx, lens_ens ens, double *walkers, double *lnp,

@@ -55,7 +55,8 @@ EXPORTED = [
     "lens_loglike_batch", "lens_loglike_amps", "lens_loglike_batch_device", "lens_loglike_multi",
     "lens_submit", "lens_poll", "lens_wait", "lens_cancel", "lens_get_stats",
     "lens_model_image", "lens_selftest", "lens_psf_crop", "lens_strerror", "lens_last_error",
-    "lens_ensemble_create", "lens_ensemble_run", "lens_ensemble_get", "lens_ensemble_destroy",
+    "lens_ensemble_create", "lens_ensemble_run", "lens_ensemble_run_many", "lens_ensemble_get",
+    "lens_ensemble_destroy",
     "lens_philox4x32_10",
 ]
 
@@ -168,6 +169,7 @@ def load():
         "lens_psf_crop": ([dp, i32, ctypes.c_double, ctypes.POINTER(i32)], i32),
         "lens_ensemble_create": ([vp, i64, ctypes.POINTER(lens_ensemble_desc), i64p], i32),
         "lens_ensemble_run": ([vp, i64, i64, i32, dp, dp], i32),
+        "lens_ensemble_run_many": ([vp, i32, i64p, i64], i32),
         "lens_ensemble_get": ([vp, i64, dp, dp, i64p, i64p], i32),
         "lens_ensemble_destroy": ([vp, i64], i32),
         "lens_philox4x32_10": ([vp, u32p, u32p, i64, u32p], i32),
@@ -369,6 +371,14 @@ def lens_ensemble_run(ctx, ens, iterations, thin=0, chain=False):
     return cw, cl
 
 
+def lens_ensemble_run_many(ctx, ens_ids, iterations):
+    """Advance every ensemble of ``ens_ids`` (distinct) by ``iterations``
+    iterations together, pooling their proposals into shared launches."""
+    ids = np.ascontiguousarray(np.asarray(ens_ids, dtype=np.int64).reshape(-1))
+    ptr = ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if ids.size else None
+    _check(ctx, load().lens_ensemble_run_many(ctx, int(ids.size), ptr, int(iterations)))
+
+
 def lens_ensemble_destroy(ctx, ens):
     _check(ctx, load().lens_ensemble_destroy(ctx, ens))
     _ens_sizes.pop((ctx, ens), None)
@@ -550,6 +560,9 @@ class LensContext:
 
     def ensemble_run(self, ens, iterations, thin=0, chain=False):
         return lens_ensemble_run(self.ctx, ens, iterations, thin, chain)
+
+    def ensemble_run_many(self, ens_ids, iterations):
+        lens_ensemble_run_many(self.ctx, ens_ids, iterations)
 
     def ensemble_get(self, ens):
         return lens_ensemble_get(self.ctx, ens)

@@ -154,6 +154,24 @@ hipError_t launch_batch(int mode, int nt, int grid, size_t lds, const LensGeom *
 // halves of a stretch-move step (d_aux: [W/2][4] doubles)
 hipError_t launch_philox_words(const uint32_t ctr[4], const uint32_t key[2], int64_t n, uint32_t *d_out,
                                hipStream_t st);
+// One ensemble of a multi-ensemble step, in device memory.  Its walkers of the
+// moving half occupy pooled slots [off, off + W/2).
+struct EnsembleDev {
+    int W, d, code, pad;        // walkers, free slots, prep model code
+    uint64_t seed;
+    int64_t t0;                 // the ensemble's iteration at the start of the call
+    double a;                   // stretch scale
+    double *walkers, *lnp;
+    int64_t *accepted;
+    const double *lo, *hi;
+    int64_t off;
+};
+// stage 0: proposals of half `half` of every ensemble at iteration t0 + it into
+// the pooled d_Y [total][20], d_aux [total][4], d_pc [total]; stage 1: their
+// acceptance from the pooled lnL d_lnl [total].  d_hoff: [n + 1] prefix of W/2.
+hipError_t launch_stretch_many(int half, int64_t it, const EnsembleDev *d_ens, const int64_t *d_hoff, int n,
+                               int64_t total, double *d_Y, double *d_aux, PropBlock *d_pc, int stage, const double *d_lnl,
+                               hipStream_t st);
 hipError_t launch_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int model_code,
                                   const double *d_walkers, const double *d_lo, const double *d_hi, double *d_Y,
                                   double *d_aux, PropBlock *d_pc, hipStream_t st);

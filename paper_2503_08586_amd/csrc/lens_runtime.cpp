@@ -1206,6 +1206,64 @@ std::string plan_key(int32_t nlens, const lens_id *ids, const int64_t *counts)
     return k;
 }
 
+// Persistent-launch groups of a multi-lens evaluation.  Entry i of Ls owns
+// counts[i] proposals at pooled offset off[i].  Groups by (mode, workgroup
+// size, resident workgroups per CU at the lens's own LDS ring): a persistent
+// launch sizes its grid by its largest ring, so lenses whose rings allow more
+// workgroups per CU are not held to the occupancy of the widest; inside a
+// group lenses in descending per-proposal cost, so the longest items start
+// first.
+struct BatchGroup {
+    int mode, nt, nl, nitems, grid;
+    size_t lds, o_geom, o_ls, o_lo;
+};
+struct BatchGroups {
+    std::vector<BatchGroup> gs;
+    std::vector<LensGeom> geom;   // per entry, group by group
+    std::vector<int> lstart;      // per group: entry item starts, then the group's item count
+    std::vector<int64_t> lout;    // per entry: pooled offset of its first proposal
+};
+
+void group_batch(lens_ctx *c, const std::vector<Lens *> &Ls, const int64_t *counts, const int64_t *off,
+                 BatchGroups *out)
+{
+    const int nl = (int)Ls.size();
+    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+    for (int i = 0; i < nl; ++i)
+        if (counts[i] > 0) {
+            const LensGeom &g = Ls[i]->g;
+            const int occ = lensk::batch_blocks_per_cu(g.mode, g.nt, lensk::ring_bytes(g));
+            groups[std::make_tuple(g.mode, g.nt, -occ)].push_back(i);
+        }
+    for (auto &kv : groups) {
+        std::vector<int> &v = kv.second;
+        auto cost = [&](int i) {
+            const LensGeom &g = Ls[i]->g;
+            return (double)Ls[i]->needed * g.s * g.s * 200.0 + (double)Ls[i]->masked * g.k * g.k;
+        };
+        std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return cost(a) > cost(b); });
+        BatchGroup gg{};
+        gg.mode = std::get<0>(kv.first);
+        gg.nt = std::get<1>(kv.first);
+        gg.nl = (int)v.size();
+        gg.o_geom = out->geom.size();
+        gg.o_ls = out->lstart.size();
+        gg.o_lo = out->lout.size();
+        int items = 0;
+        for (int i : v) {
+            out->geom.push_back(Ls[i]->g);
+            out->lstart.push_back(items);
+            out->lout.push_back(off[i]);
+            items += (int)counts[i];
+            gg.lds = std::max(gg.lds, lensk::ring_bytes(Ls[i]->g));
+        }
+        out->lstart.push_back(items);
+        gg.nitems = items;
+        gg.grid = c->num_cus * lensk::batch_blocks_per_cu(gg.mode, gg.nt, gg.lds);
+        out->gs.push_back(gg);
+    }
+}
+
 // Build and capture the graph of one call shape (sync_mu held).
 lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int64_t *counts,
                        const std::vector<Lens *> &Ls, int64_t tot, Plan **out)
@@ -1214,55 +1272,14 @@ lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int
     pl->ids.assign(ids, ids + nlens);
     pl->counts.assign(counts, counts + nlens);
     pl->tot = tot;
-    // groups by (mode, workgroup size, resident workgroups per CU at the lens's
-    // own LDS ring): a persistent launch sizes its grid by its largest ring, so
-    // lenses whose rings allow more workgroups per CU are not held to the
-    // occupancy of the widest; inside a group lenses in descending per-proposal
-    // cost, so the longest items start first
     std::vector<int64_t> off(nlens + 1, 0);
     for (int i = 0; i < nlens; ++i) off[i + 1] = off[i] + counts[i];
-    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
-    for (int i = 0; i < nlens; ++i)
-        if (counts[i] > 0) {
-            const LensGeom &g = Ls[i]->g;
-            const int occ = lensk::batch_blocks_per_cu(g.mode, g.nt, lensk::ring_bytes(g));
-            groups[std::make_tuple(g.mode, g.nt, -occ)].push_back(i);
-        }
-    struct G {
-        int mode, nt, nl, nitems, grid;
-        size_t lds, o_geom, o_ls, o_lo;
-    };
-    std::vector<G> gs;
-    std::vector<LensGeom> hgeom;
-    std::vector<int> hls;
-    std::vector<int64_t> hlo;
-    for (auto &kv : groups) {
-        std::vector<int> &v = kv.second;
-        auto cost = [&](int i) {
-            const LensGeom &g = Ls[i]->g;
-            return (double)Ls[i]->needed * g.s * g.s * 200.0 + (double)Ls[i]->masked * g.k * g.k;
-        };
-        std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return cost(a) > cost(b); });
-        G gg{};
-        gg.mode = std::get<0>(kv.first);
-        gg.nt = std::get<1>(kv.first);
-        gg.nl = (int)v.size();
-        gg.o_geom = hgeom.size();
-        gg.o_ls = hls.size();
-        gg.o_lo = hlo.size();
-        int items = 0;
-        for (int i : v) {
-            hgeom.push_back(Ls[i]->g);
-            hls.push_back(items);
-            hlo.push_back(off[i]);
-            items += (int)counts[i];
-            gg.lds = std::max(gg.lds, lensk::ring_bytes(Ls[i]->g));
-        }
-        hls.push_back(items);
-        gg.nitems = items;
-        gg.grid = c->num_cus * lensk::batch_blocks_per_cu(gg.mode, gg.nt, gg.lds);
-        gs.push_back(gg);
-    }
+    BatchGroups bg;
+    group_batch(c, Ls, counts, off.data(), &bg);
+    std::vector<BatchGroup> &gs = bg.gs;
+    std::vector<LensGeom> &hgeom = bg.geom;
+    std::vector<int> &hls = bg.lstart;
+    std::vector<int64_t> &hlo = bg.lout;
     // light model of every proposal: one for all, or per lens by proposal offset
     bool one_model = true;
     for (int i = 1; i < nlens; ++i) one_model = one_model && Ls[i]->prep_code == Ls[0]->prep_code;
@@ -1319,7 +1336,7 @@ lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int
         ce = one_model ? lensk::launch_prep(d_par, tot, d_pc, hmodel[0], nullptr, nullptr, 0, c->stream)
                        : lensk::launch_prep(d_par, tot, d_pc, 0, d_ps, d_pm, nlens, c->stream);
     for (size_t gi = 0; gi < gs.size() && ce == hipSuccess; ++gi) {
-        const G &gg = gs[gi];
+        const BatchGroup &gg = gs[gi];
         ce = lensk::launch_batch(gg.mode, gg.nt, gg.grid, gg.lds, d_geom + gg.o_geom, d_ls + gg.o_ls, d_lo + gg.o_lo,
                                  gg.nl, gg.nitems, d_pc, d_out, d_cnt + gi, c->stream);
     }
@@ -1984,6 +2001,136 @@ lens_status ensemble_run(lens_ctx *c, Ensemble *E, int64_t iterations, int32_t t
 }
 
 }  // namespace
+
+namespace {
+
+// Advances every ensemble of Es (their mutexes held) by `iterations`: per
+// half-step one proposal launch over all their moving halves, the persistent
+// multi-lens likelihood launches over the pooled proposals, one acceptance
+// launch.
+lens_status ensemble_run_many(lens_ctx *c, const std::vector<Ensemble *> &Es, int64_t iterations)
+{
+    const int n = (int)Es.size();
+    std::vector<int64_t> hoff(n + 1, 0), cnt(n);
+    std::vector<Lens *> Ls(n);
+    for (int e = 0; e < n; ++e) {
+        cnt[e] = Es[e]->W / 2;
+        hoff[e + 1] = hoff[e] + cnt[e];
+        Ls[e] = Es[e]->L;
+    }
+    const int64_t tot = hoff[n];
+    if (tot > INT_MAX) return fail(c, LENS_EINVAL, "too many walkers for one call");
+    BatchGroups bg;
+    group_batch(c, Ls, cnt.data(), hoff.data(), &bg);
+    std::vector<lensk::EnsembleDev> hens(n);
+    for (int e = 0; e < n; ++e) {
+        const Ensemble *E = Es[e];
+        lensk::EnsembleDev &D = hens[e];
+        D.W = E->W;
+        D.d = E->d;
+        D.code = E->L->prep_code;
+        D.pad = 0;
+        D.seed = E->seed;
+        D.t0 = E->t;
+        D.a = E->a;
+        D.walkers = E->walkers;
+        D.lnp = E->lnp;
+        D.accepted = E->accepted;
+        D.lo = E->lo;
+        D.hi = E->hi;
+        D.off = hoff[e];
+    }
+    // device: ensembles | hoff | Y | aux | pc | lnL | geoms | lstart | lout | counters
+    const size_t S = lensk::kStride;
+    const size_t b_ens = align_up((size_t)n * sizeof(lensk::EnsembleDev), kAlign);
+    const size_t b_hoff = align_up((size_t)(n + 1) * 8, kAlign);
+    const size_t b_Y = align_up((size_t)tot * S * 8, kAlign), b_aux = align_up((size_t)tot * 32, kAlign);
+    const size_t b_pc = align_up((size_t)tot * lensk::kPCBytes, kAlign), b_out = align_up((size_t)tot * 8, kAlign);
+    const size_t b_geom = align_up(bg.geom.size() * sizeof(LensGeom), kAlign);
+    const size_t b_ls = align_up(bg.lstart.size() * 4, kAlign), b_lo = align_up(bg.lout.size() * 8, kAlign);
+    const size_t b_cnt = align_up(bg.gs.size() * 4 + 4, kAlign);
+    const size_t bytes = b_ens + b_hoff + b_Y + b_aux + b_pc + b_out + b_geom + b_ls + b_lo + b_cnt;
+    if (!charge(c, (int64_t)bytes)) return fail(c, LENS_ENOMEM, "HBM budget exhausted (multi-ensemble step)");
+    void *dev = dev_alloc(c, bytes);
+    if (!dev) {
+        uncharge(c, (int64_t)bytes);
+        return fail(c, LENS_ENOMEM, "device allocation failed (multi-ensemble step)");
+    }
+    char *b = (char *)dev;
+    auto *d_ens = (lensk::EnsembleDev *)b;
+    auto *d_hoff = (int64_t *)(b += b_ens);
+    auto *d_Y = (double *)(b += b_hoff);
+    auto *d_aux = (double *)(b += b_Y);
+    auto *d_pc = (lensk::PropBlock *)(b += b_aux);
+    auto *d_out = (double *)(b += b_pc);
+    auto *d_geom = (LensGeom *)(b += b_out);
+    auto *d_ls = (int *)(b += b_geom);
+    auto *d_lo = (int64_t *)(b += b_ls);
+    auto *d_cnt = (unsigned int *)(b += b_lo);
+    hipError_t e = hipMemcpyAsync(d_ens, hens.data(), (size_t)n * sizeof(lensk::EnsembleDev), hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_hoff, hoff.data(), (size_t)(n + 1) * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_geom, bg.geom.data(), bg.geom.size() * sizeof(LensGeom), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_ls, bg.lstart.data(), bg.lstart.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_lo, bg.lout.data(), bg.lout.size() * 8, hipMemcpyHostToDevice, c->stream);
+    for (int64_t it = 0; it < iterations && e == hipSuccess; ++it)
+        for (int half = 0; half < 2 && e == hipSuccess; ++half) {
+            e = lensk::launch_stretch_many(half, it, d_ens, d_hoff, n, tot, d_Y, d_aux, d_pc, 0, nullptr, c->stream);
+            for (size_t gi = 0; gi < bg.gs.size() && e == hipSuccess; ++gi) {
+                const BatchGroup &gg = bg.gs[gi];
+                e = lensk::launch_batch(gg.mode, gg.nt, gg.grid, gg.lds, d_geom + gg.o_geom, d_ls + gg.o_ls,
+                                        d_lo + gg.o_lo, gg.nl, gg.nitems, d_pc, d_out, d_cnt + gi, c->stream);
+            }
+            if (e == hipSuccess)
+                e = lensk::launch_stretch_many(half, it, d_ens, d_hoff, n, tot, d_Y, d_aux, d_pc, 1, d_out, c->stream);
+        }
+    hipError_t es = hipStreamSynchronize(c->stream);
+    if (e == hipSuccess) e = es;
+    dev_free(c, dev);
+    uncharge(c, (int64_t)bytes);
+    if (e != hipSuccess) return hip_fail(c, e, "lens_ensemble_run_many");
+    for (Ensemble *E : Es) E->t += iterations;
+    return LENS_OK;
+}
+
+}  // namespace
+
+extern "C" lens_status lens_ensemble_run_many(lens_ctx *c, int32_t n, const lens_ens *ids, int64_t iterations)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (n < 0 || (n > 0 && !ids)) return fail(c, LENS_EINVAL, "bad ensemble list");
+    if (iterations < 0) return fail(c, LENS_EINVAL, "iterations must be >= 0");
+    std::vector<lens_ens> sorted(ids, ids + n);
+    std::sort(sorted.begin(), sorted.end());
+    if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+        return fail(c, LENS_EINVAL, "an ensemble is listed twice");
+    std::vector<Ensemble *> Es;
+    for (int i = 0; i < n; ++i) {
+        Ensemble *E = ensemble_use(c, ids[i]);
+        if (!E) {
+            for (Ensemble *x : Es) ensemble_done(c, x);
+            return fail(c, LENS_ENOENT, "unknown ensemble id");
+        }
+        Es.push_back(E);
+    }
+    lens_status rs = LENS_OK;
+    {
+        // one call on an ensemble at a time; locks taken in id order
+        std::vector<Ensemble *> byid(Es);
+        std::sort(byid.begin(), byid.end(), [](const Ensemble *x, const Ensemble *y) { return x->id < y->id; });
+        std::vector<std::unique_lock<std::mutex>> locks;
+        locks.reserve(byid.size());
+        for (Ensemble *E : byid) locks.emplace_back(E->mu);
+        if (n > 0 && iterations > 0) {
+            DeviceGuard dg(c->device);
+            rs = ensemble_run_many(c, Es, iterations);
+        }
+    }
+    for (Ensemble *E : Es) ensemble_done(c, E);
+    return rs;
+}
 
 extern "C" lens_status lens_ensemble_get(lens_ctx *c, lens_ens id, double *walkers, double *lnp, int64_t *accepted,
                                          int64_t *iteration)

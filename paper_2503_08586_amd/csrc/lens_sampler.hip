@@ -60,18 +60,16 @@ __global__ void __launch_bounds__(256) k_philox_words(uint4 base, uint2 key, int
 // 2^32): word 0 picks the partner j in the other half, word 1 the stretch
 // factor z = ((a - 1) u1 + 1)^2 / a (density ~ 1/sqrt(z) on [1/a, a]), word 2
 // the acceptance draw u2; u = (word + 1/2) 2^-32.  The proposal is
-// Y = X_j + z (X_k - X_j).  aux[i] = (z, ln u2, inside the box ? 1 : 0, -).
+// Y = X_j + z (X_k - X_j).  aux = (z, ln u2, inside the box ? 1 : 0, -).
 // A proposal outside the box is not evaluated: its prepared constants are
 // marked outside the domain, so the likelihood kernel returns -inf at once.
-__global__ void __launch_bounds__(64)
-k_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int model_code,
-                  const double *__restrict__ walkers, const double *__restrict__ lo,
-                  const double *__restrict__ hi, double *__restrict__ Y, double4 *__restrict__ aux,
-                  PropBlock *__restrict__ pc)
+__device__ __forceinline__ void stretch_propose_one(int W, int half, int i, uint64_t t, uint64_t seed, double a,
+                                                    int model_code, const double *__restrict__ walkers,
+                                                    const double *__restrict__ lo, const double *__restrict__ hi,
+                                                    double *__restrict__ Y, double4 *__restrict__ aux,
+                                                    PropBlock *__restrict__ pc)
 {
     const int h = W / 2;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= h) return;
     const int k = half * h + i;
     const uint4 r = philox4x32_10(make_uint4((uint32_t)k, (uint32_t)t, (uint32_t)(t >> 32), 0u),
                                   make_uint2((uint32_t)seed, (uint32_t)(seed >> 32)));
@@ -86,32 +84,28 @@ k_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int mode
     for (int s = 0; s < kStride; ++s) {
         v[s] = xj[s] + z * (xk[s] - xj[s]);
         inside = inside && v[s] >= lo[s] && v[s] <= hi[s];
-        Y[(size_t)i * kStride + s] = v[s];
+        Y[s] = v[s];
     }
-    aux[i] = make_double4(z, log(u2), inside ? 1.0 : 0.0, 0.0);
-    pc[i] = inside ? prep_proposal(v, model_code) : PropBlock{};
+    *aux = make_double4(z, log(u2), inside ? 1.0 : 0.0, 0.0);
+    *pc = inside ? prep_proposal(v, model_code) : PropBlock{};
 }
 
 // Walker k takes its proposal when ln u2 < (d - 1) ln z + lnP(Y) - lnP(X_k),
 // lnP(Y) = lnL(Y) inside the box and -inf outside; d = free slots.  With
 // chain_w non-null the walker's state after the move (taken or not) is
 // written to chain_w[k], its lnP to chain_lnp[k].
-__global__ void __launch_bounds__(256)
-k_stretch_accept(int W, int half, int d, double *__restrict__ walkers, double *__restrict__ lnp,
-                 const double *__restrict__ Y, const double4 *__restrict__ aux, const double *__restrict__ lnl,
-                 int64_t *__restrict__ accepted, double *__restrict__ chain_w, double *__restrict__ chain_lnp)
+__device__ __forceinline__ void stretch_accept_one(int W, int half, int i, int d, double *__restrict__ walkers,
+                                                   double *__restrict__ lnp, const double *__restrict__ Y,
+                                                   double4 x, double lnl, int64_t *__restrict__ accepted,
+                                                   double *__restrict__ chain_w, double *__restrict__ chain_lnp)
 {
-    const int h = W / 2;
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= h) return;
-    const int k = half * h + i;
-    const double4 x = aux[i];
-    const double lnpY = x.z != 0.0 ? lnl[i] : -INFINITY;
+    const int k = half * (W / 2) + i;
+    const double lnpY = x.z != 0.0 ? lnl : -INFINITY;
     const double rhs = (double)(d - 1) * log(x.x) + lnpY - lnp[k];
     double *wk = walkers + (size_t)k * kStride;
     if (lnpY > -INFINITY && x.y < rhs) {
 #pragma unroll
-        for (int s = 0; s < kStride; ++s) wk[s] = Y[(size_t)i * kStride + s];
+        for (int s = 0; s < kStride; ++s) wk[s] = Y[s];
         lnp[k] = lnpY;
         accepted[k] += 1;
     }
@@ -120,6 +114,66 @@ k_stretch_accept(int W, int half, int d, double *__restrict__ walkers, double *_
         for (int s = 0; s < kStride; ++s) chain_w[(size_t)k * kStride + s] = wk[s];
         chain_lnp[k] = lnp[k];
     }
+}
+
+__global__ void __launch_bounds__(64)
+k_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int model_code,
+                  const double *__restrict__ walkers, const double *__restrict__ lo,
+                  const double *__restrict__ hi, double *__restrict__ Y, double4 *__restrict__ aux,
+                  PropBlock *__restrict__ pc)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= W / 2) return;
+    stretch_propose_one(W, half, i, t, seed, a, model_code, walkers, lo, hi, Y + (size_t)i * kStride, aux + i, pc + i);
+}
+
+__global__ void __launch_bounds__(256)
+k_stretch_accept(int W, int half, int d, double *__restrict__ walkers, double *__restrict__ lnp,
+                 const double *__restrict__ Y, const double4 *__restrict__ aux, const double *__restrict__ lnl,
+                 int64_t *__restrict__ accepted, double *__restrict__ chain_w, double *__restrict__ chain_lnp)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= W / 2) return;
+    stretch_accept_one(W, half, i, d, walkers, lnp, Y + (size_t)i * kStride, aux[i], lnl[i], accepted, chain_w,
+                       chain_lnp);
+}
+
+// Many ensembles in one launch: the moving halves of all of them, walker i of
+// the pooled half belonging to ensemble e with hoff[e] <= i < hoff[e + 1]
+// (hoff: prefix of W/2 over the ensembles).  Each walker runs exactly the
+// single-ensemble arithmetic, at its ensemble's own iteration t0 + it.
+__device__ __forceinline__ int ensemble_of(const int64_t *__restrict__ hoff, int n, int64_t i)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (hoff[mid] <= i) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(64)
+k_stretch_propose_many(const EnsembleDev *__restrict__ ens, const int64_t *__restrict__ hoff, int n, int half,
+                       int64_t it, double *__restrict__ Y, double4 *__restrict__ aux, PropBlock *__restrict__ pc)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= hoff[n]) return;
+    const EnsembleDev &E = ens[ensemble_of(hoff, n, g)];
+    const int i = (int)(g - E.off);
+    stretch_propose_one(E.W, half, i, (uint64_t)(E.t0 + it), E.seed, E.a, E.code, E.walkers, E.lo, E.hi,
+                        Y + (size_t)g * kStride, aux + g, pc + g);
+}
+
+__global__ void __launch_bounds__(256)
+k_stretch_accept_many(const EnsembleDev *__restrict__ ens, const int64_t *__restrict__ hoff, int n, int half,
+                      const double *__restrict__ Y, const double4 *__restrict__ aux, const double *__restrict__ lnl)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= hoff[n]) return;
+    const EnsembleDev &E = ens[ensemble_of(hoff, n, g)];
+    const int i = (int)(g - E.off);
+    stretch_accept_one(E.W, half, i, E.d, E.walkers, E.lnp, Y + (size_t)g * kStride, aux[g], lnl[g], E.accepted,
+                       nullptr, nullptr);
 }
 
 hipError_t launch_philox_words(const uint32_t ctr[4], const uint32_t key[2], int64_t n, uint32_t *d_out,
@@ -141,6 +195,23 @@ hipError_t launch_stretch_propose(int W, int half, uint64_t t, uint64_t seed, do
     const int h = W / 2, bs = 64;
     hipLaunchKernelGGL(k_stretch_propose, dim3((unsigned)((h + bs - 1) / bs)), dim3(bs), 0, st, W, half, t, seed,
                        a, model_code, d_walkers, d_lo, d_hi, d_Y, reinterpret_cast<double4 *>(d_aux), d_pc);
+    return hipGetLastError();
+}
+
+hipError_t launch_stretch_many(int half, int64_t it, const EnsembleDev *d_ens, const int64_t *d_hoff, int n,
+                               int64_t total, double *d_Y, double *d_aux, PropBlock *d_pc, int stage, const double *d_lnl,
+                               hipStream_t st)
+{
+    if (total <= 0) return hipSuccess;
+    if (stage == 0) {
+        const int bs = 64;
+        hipLaunchKernelGGL(k_stretch_propose_many, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, d_ens,
+                           d_hoff, n, half, it, d_Y, reinterpret_cast<double4 *>(d_aux), d_pc);
+    } else {
+        const int bs = 256;
+        hipLaunchKernelGGL(k_stretch_accept_many, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, d_ens,
+                           d_hoff, n, half, d_Y, reinterpret_cast<const double4 *>(d_aux), d_lnl);
+    }
     return hipGetLastError();
 }
 

@@ -219,3 +219,94 @@ def test_ensemble_errors(ctx):
         ctx.ensemble_destroy(ens)
     assert ei.value.status == binding.LENS_ENOENT
     ctx.unload(lid)
+
+
+def _many_cases():
+    """Lenses of several kinds and sizes, each with an ensemble size and a
+    box: (label, spec, load kwargs, W, lo, hi)."""
+    out = []
+    lo, hi = _box()
+    s1 = synth.config1(nprop=1)[0]
+    oracle_data(s1)
+    out.append(("c1 sie", s1, {}, 32, lo, hi))
+    out.append(("c1 sie W=4", s1, {}, 4, lo, hi))
+    lo_n, hi_n = _box([("I_l", 0.0), ("I_s", 0.0)])
+    out.append(("c1 nnls", s1, {"amplitudes": 1}, 48, lo_n, hi_n))
+    se = synth.config1(nprop=1)[0]
+    se.truth = se.truth.copy()
+    se.truth[19] = 2.2
+    oracle_data(se)
+    lo_e, hi_e = lo.copy(), hi.copy()
+    lo_e[19], hi_e[19] = 1.5, 2.5
+    out.append(("c1 epl", se, {"mass_model": 1}, 20, lo_e, hi_e))
+    for i, spec in enumerate(synth.config3(nlens=3, scale_props=0.0)):
+        oracle_data(spec)
+        out.append(("c3 lens %d (%dpx s=%d k=%d)" % (i, spec.ny, spec.s, spec.psf.shape[0]), spec,
+                    {"precision": 3} if i == 1 else {}, 64 + 32 * i, lo, hi))
+    return out
+
+
+def test_ensemble_run_many_equals_separate_runs(ctx):
+    """Pooled half-steps over many ensembles move each exactly as its own run,
+    bit for bit, from its own iteration count; one pooled iteration of a
+    member is checked against the oracle directly."""
+    cases = _many_cases()
+    say("case: %d ensembles on %d lenses, pooled vs separate runs" % (len(cases), len(cases)))
+    rng = np.random.default_rng(11)
+    lids, pooled, single = [], [], []
+    for n, (label, spec, kw, W, lo, hi) in enumerate(cases):
+        lid = ctx.load(spec, **kw)
+        lids.append(lid)
+        around = np.clip(spec.truth, lo, hi)
+        init = _init(rng, W, lo, hi, around=around, scale=0.02)
+        pooled.append(ctx.ensemble(lid, init, lo, hi, seed=500 + n))
+        single.append(ctx.ensemble(lid, init, lo, hi, seed=500 + n))
+    # members start from different iteration counts
+    ctx.ensemble_run(pooled[2], 2)
+    ctx.ensemble_run(single[2], 2)
+    for calls in (1, 3, 2):
+        ctx.ensemble_run_many(pooled, calls)
+        for e in single:
+            ctx.ensemble_run(e, calls)
+        for (label, *_), p, s in zip(cases, pooled, single):
+            a, b = ctx.ensemble_get(p), ctx.ensemble_get(s)
+            assert all(np.array_equal(x, y) for x, y in zip(a[:3], b[:3])) and a[3] == b[3], label
+    assert sum(int(ctx.ensemble_get(p)[2].sum()) for p in pooled) > 50
+    # one pooled iteration of the first member against the oracle
+    label, spec, kw, W, lo, hi = cases[0]
+    before, lb, _, t = ctx.ensemble_get(pooled[0])
+    ctx.ensemble_run_many(pooled, 1)
+    after, la, _, _ = ctx.ensemble_get(pooled[0])
+    stats = {"acc": 0, "rej": 0}
+    _check_iteration(spec, before, lb, after, la, t, 500, 2.0, lo, hi, False, stats)
+    for e in pooled + single:
+        ctx.ensemble_destroy(e)
+    for lid in lids:
+        ctx.unload(lid)
+
+
+def test_ensemble_run_many_errors(ctx):
+    from paper_2503_08586_amd import binding
+    spec = synth.config1(nprop=1)[0]
+    oracle_data(spec)
+    lid = ctx.load(spec)
+    lo, hi = _box()
+    init = _init(np.random.default_rng(8), 8, lo, hi, around=np.clip(spec.truth, lo, hi), scale=0.02)
+    e1 = ctx.ensemble(lid, init, lo, hi, seed=1)
+    e2 = ctx.ensemble(lid, init, lo, hi, seed=2)
+    ctx.ensemble_run_many([], 5)
+    ctx.ensemble_run_many([e1, e2], 0)
+    for ids, status in (([e1, e1], binding.LENS_EINVAL), ([e1, e2 + 1000], binding.LENS_ENOENT)):
+        with pytest.raises(binding.LensError) as ei:
+            ctx.ensemble_run_many(ids, 1)
+        assert ei.value.status == status, ids
+    with pytest.raises(binding.LensError) as ei:
+        ctx.ensemble_run_many([e1], -1)
+    assert ei.value.status == binding.LENS_EINVAL
+    # nothing moved
+    assert ctx.ensemble_get(e1)[3] == 0 and np.array_equal(ctx.ensemble_get(e1)[0], init)
+    ctx.ensemble_run_many([e2, e1], 2)
+    assert ctx.ensemble_get(e1)[3] == 2 and ctx.ensemble_get(e2)[3] == 2
+    for e in (e1, e2):
+        ctx.ensemble_destroy(e)
+    ctx.unload(lid)
