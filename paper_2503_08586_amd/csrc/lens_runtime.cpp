@@ -266,6 +266,9 @@ struct lens_ctx {
     void *d_arena = nullptr;
     char *h_arena = nullptr;
     hipStream_t sstreams[kServeStreams] = {};
+    // batch-plan capture, under sync_mu only: no other thread enqueues on a
+    // stream while it is being captured
+    hipStream_t cap_stream = nullptr;
     std::thread sched;
     bool stop = false;
     lens_stats stats{};
@@ -478,6 +481,7 @@ extern "C" lens_status lens_init(const lens_init_opts *opts, lens_ctx **out)
     }
     for (int i = 0; i < kServeStreams; ++i)
         if (hipStreamCreateWithFlags(&c->sstreams[i], hipStreamNonBlocking) != hipSuccess) return LENS_EDEVICE;
+    if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) return LENS_EDEVICE;
     c->stats.hbm_budget_bytes = c->budget;
     c->autotune = o.autotune != 0;
     {
@@ -532,6 +536,10 @@ extern "C" void lens_shutdown(lens_ctx *c)
             (void)hipStreamSynchronize(c->sstreams[i]);
             (void)hipStreamDestroy(c->sstreams[i]);
         }
+    if (c->cap_stream) {
+        (void)hipStreamSynchronize(c->cap_stream);
+        (void)hipStreamDestroy(c->cap_stream);
+    }
     for (auto &kv : c->plans) {
         Plan *pl = kv.second;
         if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
@@ -1207,10 +1215,12 @@ std::string plan_key(int32_t nlens, const lens_id *ids, const int64_t *counts)
 }
 
 // Persistent-launch groups of a multi-lens evaluation.  Entry i of Ls owns
-// counts[i] proposals at pooled offset off[i].  Groups by (mode, workgroup
-// size, resident workgroups per CU at the lens's own LDS ring): a persistent
-// launch sizes its grid by its largest ring, so lenses whose rings allow more
-// workgroups per CU are not held to the occupancy of the widest; inside a
+// counts[i] proposals at pooled offset off[i].  Lenses share a launch when
+// they share a mode and a workgroup size, and the resident workgroups per CU
+// that their own LDS rings allow (the occupancy) are within 25% of the
+// group's highest: a persistent launch sizes its grid by its largest ring, so
+// a wide lens would hold narrow ones to its occupancy, while every extra
+// launch ends in a tail where a few long items keep most CUs idle.  Inside a
 // group lenses in descending per-proposal cost, so the longest items start
 // first.
 struct BatchGroup {
@@ -1228,13 +1238,27 @@ void group_batch(lens_ctx *c, const std::vector<Lens *> &Ls, const int64_t *coun
                  BatchGroups *out)
 {
     const int nl = (int)Ls.size();
-    std::map<std::tuple<int, int, int>, std::vector<int>> groups;
+    std::map<std::tuple<int, int, int>, std::vector<int>> classes;   // (mode, nt, -occupancy)
     for (int i = 0; i < nl; ++i)
         if (counts[i] > 0) {
             const LensGeom &g = Ls[i]->g;
             const int occ = lensk::batch_blocks_per_cu(g.mode, g.nt, lensk::ring_bytes(g));
-            groups[std::make_tuple(g.mode, g.nt, -occ)].push_back(i);
+            classes[std::make_tuple(g.mode, g.nt, -occ)].push_back(i);
         }
+    // classes in descending occupancy within a (mode, nt); a class joins the
+    // open group while 4 occ >= 3 occ_top
+    std::vector<std::pair<std::pair<int, int>, std::vector<int>>> groups;
+    int top = 0;
+    for (auto &kv : classes) {
+        const int mode = std::get<0>(kv.first), nt = std::get<1>(kv.first), occ = -std::get<2>(kv.first);
+        const bool join = !groups.empty() && groups.back().first == std::make_pair(mode, nt) && 4 * occ >= 3 * top;
+        if (!join) {
+            groups.push_back({{mode, nt}, {}});
+            top = occ;
+        }
+        auto &v = groups.back().second;
+        v.insert(v.end(), kv.second.begin(), kv.second.end());
+    }
     for (auto &kv : groups) {
         std::vector<int> &v = kv.second;
         auto cost = [&](int i) {
@@ -1243,8 +1267,8 @@ void group_batch(lens_ctx *c, const std::vector<Lens *> &Ls, const int64_t *coun
         };
         std::stable_sort(v.begin(), v.end(), [&](int a, int b) { return cost(a) > cost(b); });
         BatchGroup gg{};
-        gg.mode = std::get<0>(kv.first);
-        gg.nt = std::get<1>(kv.first);
+        gg.mode = kv.first.first;
+        gg.nt = kv.first.second;
         gg.nl = (int)v.size();
         gg.o_geom = out->geom.size();
         gg.o_ls = out->lstart.size();
@@ -1262,6 +1286,19 @@ void group_batch(lens_ctx *c, const std::vector<Lens *> &Ls, const int64_t *coun
         gg.grid = c->num_cus * lensk::batch_blocks_per_cu(gg.mode, gg.nt, gg.lds);
         out->gs.push_back(gg);
     }
+}
+
+// Launches the groups of bg in order on stream st.
+hipError_t launch_groups(const BatchGroups &bg, hipStream_t st, const LensGeom *d_geom, const int *d_ls,
+                         const int64_t *d_lo, const lensk::PropBlock *d_pc, double *d_out, unsigned int *d_cnt)
+{
+    hipError_t e = hipSuccess;
+    for (size_t gi = 0; gi < bg.gs.size() && e == hipSuccess; ++gi) {
+        const BatchGroup &gg = bg.gs[gi];
+        e = lensk::launch_batch(gg.mode, gg.nt, gg.grid, gg.lds, d_geom + gg.o_geom, d_ls + gg.o_ls, d_lo + gg.o_lo,
+                                gg.nl, gg.nitems, d_pc, d_out, d_cnt + gi, st);
+    }
+    return e;
 }
 
 // Build and capture the graph of one call shape (sync_mu held).
@@ -1329,20 +1366,18 @@ lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int
     if (e != hipSuccess) return bail(e, "batch plan set-up");
     // capture: the graph holds only copies and kernels (the work counters are
     // cleared by a kernel node, never by a memset node)
-    e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+    // captured on a stream of its own (only this thread, under sync_mu, uses it)
+    hipStream_t cs = c->cap_stream;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bail(e, "hipStreamBeginCapture");
-    hipError_t ce = hipMemcpyAsync(d_par, pl->h_params, (size_t)tot * lensk::kStride * 8, hipMemcpyHostToDevice, c->stream);
+    hipError_t ce = hipMemcpyAsync(d_par, pl->h_params, (size_t)tot * lensk::kStride * 8, hipMemcpyHostToDevice, cs);
     if (ce == hipSuccess)
-        ce = one_model ? lensk::launch_prep(d_par, tot, d_pc, hmodel[0], nullptr, nullptr, 0, c->stream)
-                       : lensk::launch_prep(d_par, tot, d_pc, 0, d_ps, d_pm, nlens, c->stream);
-    for (size_t gi = 0; gi < gs.size() && ce == hipSuccess; ++gi) {
-        const BatchGroup &gg = gs[gi];
-        ce = lensk::launch_batch(gg.mode, gg.nt, gg.grid, gg.lds, d_geom + gg.o_geom, d_ls + gg.o_ls, d_lo + gg.o_lo,
-                                 gg.nl, gg.nitems, d_pc, d_out, d_cnt + gi, c->stream);
-    }
-    if (ce == hipSuccess) ce = hipMemcpyAsync(pl->h_out, d_out, (size_t)tot * 8, hipMemcpyDeviceToHost, c->stream);
+        ce = one_model ? lensk::launch_prep(d_par, tot, d_pc, hmodel[0], nullptr, nullptr, 0, cs)
+                       : lensk::launch_prep(d_par, tot, d_pc, 0, d_ps, d_pm, nlens, cs);
+    if (ce == hipSuccess) ce = launch_groups(bg, cs, d_geom, d_ls, d_lo, d_pc, d_out, d_cnt);
+    if (ce == hipSuccess) ce = hipMemcpyAsync(pl->h_out, d_out, (size_t)tot * 8, hipMemcpyDeviceToHost, cs);
     hipGraph_t graph = nullptr;
-    e = hipStreamEndCapture(c->stream, &graph);
+    e = hipStreamEndCapture(cs, &graph);
     pl->graph = graph;
     if (ce != hipSuccess) return bail(ce, "batch plan capture");
     if (e != hipSuccess) return bail(e, "hipStreamEndCapture");
@@ -2077,11 +2112,7 @@ lens_status ensemble_run_many(lens_ctx *c, const std::vector<Ensemble *> &Es, in
     for (int64_t it = 0; it < iterations && e == hipSuccess; ++it)
         for (int half = 0; half < 2 && e == hipSuccess; ++half) {
             e = lensk::launch_stretch_many(half, it, d_ens, d_hoff, n, tot, d_Y, d_aux, d_pc, 0, nullptr, c->stream);
-            for (size_t gi = 0; gi < bg.gs.size() && e == hipSuccess; ++gi) {
-                const BatchGroup &gg = bg.gs[gi];
-                e = lensk::launch_batch(gg.mode, gg.nt, gg.grid, gg.lds, d_geom + gg.o_geom, d_ls + gg.o_ls,
-                                        d_lo + gg.o_lo, gg.nl, gg.nitems, d_pc, d_out, d_cnt + gi, c->stream);
-            }
+            if (e == hipSuccess) e = launch_groups(bg, c->stream, d_geom, d_ls, d_lo, d_pc, d_out, d_cnt);
             if (e == hipSuccess)
                 e = lensk::launch_stretch_many(half, it, d_ens, d_hoff, n, tot, d_Y, d_aux, d_pc, 1, d_out, c->stream);
         }

@@ -310,3 +310,51 @@ def test_ensemble_run_many_errors(ctx):
     for e in (e1, e2):
         ctx.ensemble_destroy(e)
     ctx.unload(lid)
+
+
+def test_ensemble_concurrent_with_multi_plan_builds(ctx):
+    """A multi-lens call shape is captured into a graph the first time it is
+    seen; the capture uses a stream of its own, so an ensemble advancing on
+    another thread meanwhile is neither captured nor disturbed."""
+    import threading
+    say("case: ensemble run on one thread while multi-lens plans are captured on another")
+    specs = synth.config3(nlens=4, scale_props=0.01)
+    lids = []
+    for sp in specs:
+        oracle_data(sp)
+        lids.append(ctx.load(sp))
+    singles = [ctx.loglike(lid, sp.proposals) for sp, lid in zip(specs, lids)]
+    s1 = synth.config1(nprop=1)[0]
+    oracle_data(s1)
+    lo, hi = _box()
+    init = _init(np.random.default_rng(21), 32, lo, hi, around=np.clip(s1.truth, lo, hi), scale=0.02)
+    lid1 = ctx.load(s1)
+    e_conc = ctx.ensemble(lid1, init, lo, hi, seed=77)
+    e_ref = ctx.ensemble(lid1, init, lo, hi, seed=77)
+    errors = []
+
+    def sampler():
+        try:
+            for _ in range(30):
+                ctx.ensemble_run(e_conc, 1)
+        except Exception as ex:   # reported by the main thread
+            errors.append(ex)
+
+    th = threading.Thread(target=sampler)
+    th.start()
+    try:
+        # new call shapes (other counts each time) build and capture new plans
+        for m in range(1, 9):
+            outs = ctx.loglike_multi(lids, [sp.proposals[:m + j] for j, sp in enumerate(specs)])
+            for j, (o, ref) in enumerate(zip(outs, singles)):
+                assert np.array_equal(o, ref[:m + j]), (m, j)
+    finally:
+        th.join()
+    assert not errors, errors
+    ctx.ensemble_run(e_ref, 30)
+    a, b = ctx.ensemble_get(e_conc), ctx.ensemble_get(e_ref)
+    assert all(np.array_equal(x, y) for x, y in zip(a[:3], b[:3])) and a[3] == b[3] == 30
+    for e in (e_conc, e_ref):
+        ctx.ensemble_destroy(e)
+    for lid in lids + [lid1]:
+        ctx.unload(lid)
