@@ -1,12 +1,15 @@
 """Writes lens_approx.h: polynomial coefficients for the device math.
 
-Three functions of the FP64 part of the forward model:
+Functions of the FP64 part of the forward model:
   F(t) = atan(t) / t   on |t| <= 1  (|t| > 1 is reduced by atan t = pi/2 - atan(1/t))
   G(t) = atanh(t) / t  on |t| <= 1/2 (|t| > 1/2 is reduced by the addition formula)
   2^f                  on |f| <= 1/2 (2^y = 2^round(y) 2^(y - round(y))), at two degrees
-F and G are fitted as polynomials in w = t^2, 2^f in f, by least squares in *relative*
-error on Chebyshev-distributed nodes (a near-minimax fit), with the function
-values taken at 40 significant digits (mpmath).  Run from this directory:
+  b_n                  the Sersic constant of Eq. 9, the root b of P(2n, b) = 1/2
+                       (P: regularized lower incomplete gamma), piecewise on n
+F and G are fitted as polynomials in w = t^2, 2^f in f, b_n in the interval's
+own variable u, by least squares in *relative* error on Chebyshev-distributed
+nodes (a near-minimax fit), with the function values taken at 40 significant
+digits (mpmath).  Run from this directory:
     python gen_approx.py > lens_approx.h
 """
 import sys
@@ -35,6 +38,61 @@ def f_atanh(w):
 
 def f_exp2(x):
     return mp.power(2, mp.mpf(x))
+
+
+def sersic_bn(n):
+    """b_n: the root b of P(2n, b) = 1/2.  Start: the large-n expansion
+    2n - 1/3 + 4/(405 n); for small n, the leading term of the series of P,
+    b^(2n) / Gamma(2n + 1) = 1/2."""
+    n = mp.mpf(n)
+    a = 2 * n
+    x0 = a - mp.mpf(1) / 3 + mp.mpf(4) / (405 * n) if n > 0.35 else (mp.gamma(a + 1) / 2) ** (1 / a)
+    return mp.findroot(lambda b: mp.gammainc(a, 0, b, regularized=True) - mp.mpf(1) / 2, x0)
+
+
+# b_n table: quarter-octave intervals in n from BN_LO, fitted on the interval
+# widened by 2.5% of its half-width either side (the device picks the interval
+# from an FP32 log2, which may round across an edge)
+BN_LO, BN_PER_OCT, BN_INTERVALS, BN_DEG, BN_WIDEN = 0.1, 4, 31, 10, 1.025
+
+
+def fit_bn():
+    mids, invh, coefs, worst = [], [], [], 0.0
+    npts = 60
+    k = np.arange(npts)
+    u = BN_WIDEN * np.cos(np.pi * (k + 0.5) / npts)
+    uv = np.linspace(-BN_WIDEN, BN_WIDEN, 201)
+    for j in range(BN_INTERVALS):
+        lo = mp.mpf(BN_LO) * mp.power(2, mp.mpf(j) / BN_PER_OCT)
+        hi = mp.mpf(BN_LO) * mp.power(2, mp.mpf(j + 1) / BN_PER_OCT)
+        m, h = (lo + hi) / 2, (hi - lo) / 2
+        y = np.array([float(sersic_bn(m + h * mp.mpf(float(v)))) for v in u])
+        V = np.vander(u, BN_DEG + 1, increasing=True) / y[:, None]
+        c, *_ = np.linalg.lstsq(V, np.ones_like(y), rcond=None)
+        yv = np.array([float(sersic_bn(m + h * mp.mpf(float(v)))) for v in uv])
+        worst = max(worst, float(np.abs(np.polyval(c[::-1], uv) / yv - 1).max()))
+        mids.append(float(m))
+        invh.append(float(1 / h))
+        coefs.append(c)
+    return mids, invh, coefs, worst
+
+
+def emit_bn(mids, invh, coefs, err):
+    out = ["// b_n of Eq. 9 (Sersic): %d intervals of a quarter octave in n from %.1f (to %.4g);"
+           % (BN_INTERVALS, BN_LO, BN_LO * 2 ** (BN_INTERVALS / BN_PER_OCT)),
+           "// on interval j, b_n = sum_i kBnCoef[j][i] u^i, u = (n - kBnMid[j]) kBnInvHalf[j];",
+           "// max relative fit error %.2e for |u| <= %.3f" % (err, BN_WIDEN),
+           "constexpr int kBnIntervals = %d, kBnPerOctave = %d, kBnDeg = %d;" % (BN_INTERVALS, BN_PER_OCT, BN_DEG),
+           "constexpr double kBnLo = %.17e;" % BN_LO,
+           "__device__ static constexpr double kBnMid[%d] = {" % BN_INTERVALS]
+    out += ["    %.17e," % v for v in mids]
+    out += ["};", "__device__ static constexpr double kBnInvHalf[%d] = {" % BN_INTERVALS]
+    out += ["    %.17e," % v for v in invh]
+    out += ["};", "__device__ static constexpr double kBnCoef[%d][%d] = {" % (BN_INTERVALS, BN_DEG + 1)]
+    for c in coefs:
+        out += ["    {" + ", ".join("%.17e" % v for v in c) + "},"]
+    out += ["};"]
+    return "\n".join(out)
 
 
 def fit(f, a, b, deg, npts=4000):
@@ -86,6 +144,9 @@ def main():
     print(emit("kAtanhOverT64", ch64, eh64, "[0, 1/4]", "double"))
     print(emit("kExp2_64", ce64, ee64, "[-1/2, 1/2] (2^f, f = w)", "double"))
     print(emit("kExp2Hi64", cx64, ex64, "[-1/2, 1/2] (2^f, f = w)", "double"))
+    # b_n: degree 10 on quarter octaves reaches the FP64 least-squares floor
+    # (~2e-15; degree 8 leaves 3e-13 on the first intervals)
+    print(emit_bn(*fit_bn()))
 
 
 if __name__ == "__main__":

@@ -365,8 +365,9 @@ __device__ __forceinline__ void binned_pixel_channels(const LensGeom &g, const P
 
 // Sersic b_n: root of P(2n, b) = 1/2 (Eq. 9), FP64 Newton safeguarded by
 // bisection on [0, 2n + 1].  P by its power series, which converges for every
-// b in the bracket; the median of Gamma(2n) lies below 2n.
-__host__ __device__ inline double sersic_bn(double n)
+// b in the bracket; the median of Gamma(2n) lies below 2n.  Host only (the
+// fixed indices of two-component light); the device uses sersic_bn_fit.
+__host__ inline double sersic_bn(double n)
 {
     const double a = 2.0 * n;
     const double lga1 = lgamma(a + 1.0);
@@ -395,6 +396,23 @@ __host__ __device__ inline double sersic_bn(double n)
         if (dx <= 1e-9 * x || hi - lo <= 4e-16 * x) break;
     }
     return x;
+}
+
+// b_n of Eq. 9 from the piecewise fit (lens_approx.h): the quarter-octave
+// interval of n from an FP32 log2 (each interval's fit covers a rounding across
+// its edges), then one degree-10 Horner pass in FP64; within 5e-15 relative of
+// the root for n in [kNMin, kNMax], where the iteration above needs an
+// incomplete-gamma series with a division per term at every Newton step.
+__device__ __forceinline__ double sersic_bn_fit(double n)
+{
+    int j = (int)__builtin_floorf((float)kBnPerOctave * hw_log2((float)(n * (1.0 / kBnLo))));
+    j = j < 0 ? 0 : j > kBnIntervals - 1 ? kBnIntervals - 1 : j;
+    const double u = (n - kBnMid[j]) * kBnInvHalf[j];
+    const double *c = kBnCoef[j];
+    double r = c[kBnDeg];
+#pragma unroll
+    for (int i = kBnDeg - 1; i >= 0; --i) r = fma(r, u, c[i]);
+    return r;
 }
 
 }  // namespace lensk

@@ -123,7 +123,7 @@ struct LensGeom {
 };
 
 size_t ring_bytes(const LensGeom &g);
-double host_sersic_bn(double n);   // b_n of Eq. 9, the prep kernel's FP64 root, on the host
+double host_sersic_bn(double n);   // b_n of Eq. 9 by FP64 Newton iteration, on the host
 int choose_kc(int k);
 // LDS row width (elements) and bytes per ring row for a mode, PSF side and width
 int ring_width(int mode, int k, int nx);

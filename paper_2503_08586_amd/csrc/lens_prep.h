@@ -15,13 +15,15 @@ namespace lensk {
 __device__ inline LightK light_constants(double I, double R, double n, double q, double phi)
 {
     // x1 = c dx + s dy, x2 = -s dx + c dy, (R_p/R_e)^2 = (q x1^2 + x2^2/q) / R_e^2
-    const double c = cos(phi), s = sin(phi), A = q / (R * R), Bq = 1.0 / (q * R * R);
+    double s, c;
+    sincos(phi, &s, &c);
+    const double A = q / (R * R), Bq = 1.0 / (q * R * R);
     LightK L;
     L.P = A * c * c + Bq * s * s;
     L.Q = A * s * s + Bq * c * c;
     L.S = 2.0 * (A - Bq) * c * s;
     L.e = 0.5 / n;
-    L.B = sersic_bn(n) * 1.4426950408889634;
+    L.B = sersic_bn_fit(n) * 1.4426950408889634;
     L.I = I;
     return L;
 }
@@ -64,8 +66,7 @@ __device__ inline PropBlock prep_proposal(const double *v, int code)
         b.ym = v[4];
         if (mass) {
             const double q = v[1];
-            b.cm = cos(v[2]);
-            b.sm = sin(v[2]);
+            sincos(v[2], &b.sm, &b.cm);
             b.q2m = q * q;
             b.ce = sqrt((1.0 - q) * (1.0 + q));
             b.bsie = v[0] * sqrt(q);

@@ -36,7 +36,8 @@ def rel_err(got, ref, chi2, C):
     both_inf = np.isneginf(got) & np.isneginf(ref)
     den = 0.5 * np.where(np.isfinite(chi2), chi2, 0.0) + abs(C)
     den = np.where(den > 0, den, 1.0)
-    e = np.abs(got - ref) / den
+    with np.errstate(invalid="ignore"):   # -inf - -inf, masked below
+        e = np.abs(got - ref) / den
     return np.where(both_inf, 0.0, e)
 
 
