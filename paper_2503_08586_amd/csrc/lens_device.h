@@ -100,14 +100,21 @@ constexpr double kAtanh075 = 0.97295507452765665255;   // atanh(3/4)
 
 // theta_E sqrt(q) atan(c u1)/c (the SIE deflection along the major axis).
 // |c u1| <= 1: polynomial in (c u1)^2; else atan t = pi/2 - atan(1/t).
+// |c u1| > 1 needs q < 1/sqrt(2) and a cone around the major axis, so most
+// waves have no such lane: they skip the reduction on a wave-uniform branch
+// (a divergent one would still issue it, with the lanes masked off).  Each
+// lane's arithmetic is the same on either path.
 __device__ __forceinline__ double sie_a1(double u1, double ce, double bsie, double bsc)
 {
     const double t = ce * u1;
     const double z = fabs(t);
     const bool big = z > 1.0;
-    const double zi = big ? rcp_nr(z) : z;
-    const double p = horner(kAtanOverT64, zi * zi);
-    return big ? copysign(bsc * fma(-zi, p, kPi2), t) : bsie * u1 * p;
+    if (__builtin_amdgcn_ballot_w64(big)) {
+        const double zi = big ? rcp_nr(z) : z;
+        const double p = horner(kAtanOverT64, zi * zi);
+        return big ? copysign(bsc * fma(-zi, p, kPi2), t) : bsie * u1 * p;
+    }
+    return bsie * u1 * horner(kAtanOverT64, z * z);
 }
 
 // theta_E sqrt(q) atanh(c u2)/c (along the minor axis).  |t| <= 1/2:
