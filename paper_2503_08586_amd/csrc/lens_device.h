@@ -127,9 +127,13 @@ __device__ __forceinline__ double sie_a2(double u2, double ce, double bsie, doub
     const double z = fabs(t);
     if (z <= 0.9) {
         const bool red = z > 0.5;
-        const double zr = red ? (z - 0.75) * rcp_nr(fma(-0.75, z, 1.0)) : z;
-        const double p = horner(kAtanhOverT64, zr * zr);
-        return red ? copysign(bsc * fma_c(zr, p, kAtanh075), t) : bsie * u2 * p;
+        // the reduction on a wave-uniform branch, as in sie_a1
+        if (__builtin_amdgcn_ballot_w64(red)) {
+            const double zr = red ? (z - 0.75) * rcp_nr(fma(-0.75, z, 1.0)) : z;
+            const double p = horner(kAtanhOverT64, zr * zr);
+            return red ? copysign(bsc * fma_c(zr, p, kAtanh075), t) : bsie * u2 * p;
+        }
+        return bsie * u2 * horner(kAtanhOverT64, z * z);
     }
     // atanh z = (ln 2 / 2) log2 y with y = (1 + z)/(1 - z) > 19:
     // FP32 log2 seed l0 (absolute error ~1e-6), then one Newton step on 2^l = y,
