@@ -49,5 +49,36 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+ASAN_DRIVER = os.path.join(HERE, "_build", "runtime_asan_driver")
+# host code only: the device code is the library's own (sanitizers on the GPU
+# side are neither wanted nor available)
+ASAN_HOST = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-g"]
+
+
+def build_asan_driver(verbose: bool = False) -> str:
+    """The C-ABI driver tests/runtime_sanitize_driver.cpp, linked with the
+    runtime compiled with host-side AddressSanitizer and UBSan and with the
+    library's own kernel objects (build() first)."""
+    objdir = os.path.join(HERE, "_build")
+    kobjs = [os.path.join(objdir, os.path.splitext(s)[0] + ".o") for s in SOURCES if s.endswith(".hip")]
+    rt = os.path.join(objdir, "lens_runtime_asan.o")
+    drv = os.path.join(objdir, "runtime_sanitize_driver.o")
+    steps = [
+        [HIPCC, "-x", "hip"] + FLAGS + ASAN_HOST + ["-c", os.path.join(CSRC, "lens_runtime.cpp"), "-o", rt],
+        [HIPCC, "-x", "hip"] + FLAGS + ASAN_HOST + ["-c", os.path.join(ROOT, "tests", "runtime_sanitize_driver.cpp"),
+                                                     "-o", drv],
+        [HIPCC, "--offload-arch=gfx950"] + ASAN_HOST + [drv, rt] + kobjs + ["-lpthread", "-o", ASAN_DRIVER],
+    ]
+    for cmd in steps:
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("sanitizer driver build failed")
+    return ASAN_DRIVER
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

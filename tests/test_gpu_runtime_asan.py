@@ -1,0 +1,39 @@
+"""The runtime's host code under AddressSanitizer and UBSan on the GPU: the
+driver tests/runtime_sanitize_driver.cpp, linked with a host-instrumented
+build of the runtime (paper_2503_08586_amd.build.build_asan_driver), drives
+every entry point of the C-ABI (loading, blocking and multi-lens calls,
+serving with cancellations, the sampler ensembles, error paths, shutdown with
+work in flight) and must finish without a sanitizer report."""
+import os
+import subprocess
+
+import pytest
+
+from gpu_cases import say
+from paper_2503_08586_amd import build
+
+pytestmark = pytest.mark.gpu
+
+# allocations the HIP and HSA runtimes keep until the process ends
+LSAN_SUPPRESSIONS = """leak:libamdhip64
+leak:libhsa-runtime64
+leak:libhsakmt
+leak:libdrm
+"""
+
+
+def test_runtime_under_host_asan_ubsan(tmp_path):
+    exe = build.ASAN_DRIVER
+    if not os.path.exists(exe):
+        pytest.skip("sanitizer driver not built (paper_2503_08586_amd.build.build_asan_driver)")
+    supp = tmp_path / "lsan.supp"
+    supp.write_text(LSAN_SUPPRESSIONS)
+    env = dict(os.environ,
+               ASAN_OPTIONS="detect_leaks=1:halt_on_error=1:verify_asan_link_order=0",
+               LSAN_OPTIONS="suppressions=%s" % supp,
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+    say("case: C-ABI driver under host ASan/UBSan")
+    r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=240)
+    out = r.stdout + r.stderr
+    say(out[-3000:])
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), out[-6000:]
