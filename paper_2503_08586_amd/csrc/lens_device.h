@@ -183,13 +183,15 @@ __device__ __forceinline__ double ellip_r2(double dx, double dy, const LightK &L
 
 // Source-plane position beta = theta - alpha_SIE - alpha_shear (Eqs. 1-2), given
 // the sub-pixel's coordinates (x1, x2) in the frame of the mass ellipse and the
-// part of beta linear in theta, (lx, ly) = theta - alpha_shear - source centre.
-// SIE (kappa = theta_E / (2 R_p)): u = x'/psi, psi = sqrt(q^2 x1^2 + x2^2),
-// c = sqrt(1 - q^2), alpha' = theta_E sqrt(q) / c (atan(c u1), atanh(c u2)),
-// rotated back by the mass angle; alpha = 0 at the centre.
-// Shear: alpha = -(g1 x + g2 y, g2 x - g1 y).
-__device__ __forceinline__ void ray_trace(double x1, double x2, double lx, double ly, const PropBlock &P,
-                                          double &bx, double &by)
+// part of beta linear in theta taken in that frame, (u1, u2) = R(-phi_m)
+// (theta - alpha_shear - source centre).  Returns w = R(-phi_m) (beta - source
+// centre) = u - alpha', the deflection alpha' staying in the mass frame (the
+// source's quadratic form is rotated once per proposal instead).
+// SIE (kappa = theta_E / (2 R_p)): psi = sqrt(q^2 x1^2 + x2^2), c = sqrt(1 - q^2),
+// alpha' = theta_E sqrt(q) / c (atan(c x1/psi), atanh(c x2/psi)) in the mass
+// frame; alpha' = 0 at the centre.  Shear (inside u): alpha = -(g1 x + g2 y, g2 x - g1 y).
+__device__ __forceinline__ void ray_trace(double x1, double x2, double u1, double u2, const PropBlock &P,
+                                          double &w1, double &w2)
 {
     const double psi2 = fma(P.q2m, x1 * x1, x2 * x2);
     double ir;
@@ -197,8 +199,8 @@ __device__ __forceinline__ void ray_trace(double x1, double x2, double lx, doubl
     else ir = psi2 > 0.0 ? rsq64(psi2) : 0.0;
     const double a1 = sie_a1(x1 * ir, P.ce, P.bsie, P.bsc);
     const double a2 = sie_a2(x2 * ir, P.ce, P.bsie, P.bsc);
-    bx = lx - fma(P.cm, a1, -(P.sm * a2));
-    by = ly - fma(P.sm, a1, P.cm * a2);
+    w1 = u1 - a1;
+    w2 = u2 - a2;
 }
 
 // Elliptical power law (Sec. 2.4: kappa = (3 - gamma)/2 (theta_E / R_p)^(gamma - 1)
@@ -245,8 +247,8 @@ __device__ inline void epl_setup(const PropBlock &P)
     *epl_nterms() = N;
 }
 
-__device__ __forceinline__ void ray_trace_epl(double x1, double x2, double lx, double ly, const PropBlock &P,
-                                              double &bx, double &by)
+__device__ __forceinline__ void ray_trace_epl(double x1, double x2, double u1, double u2, const PropBlock &P,
+                                              double &w1, double &w2)
 {
     const double psi2 = fma(P.q2m, x1 * x1, x2 * x2);   // R^2
     double a1 = 0.0, a2 = 0.0;
@@ -268,8 +270,8 @@ __device__ __forceinline__ void ray_trace_epl(double x1, double x2, double lx, d
         a1 = mag * fma(c1, sr, -(s1 * si));
         a2 = mag * fma(c1, si, s1 * sr);
     }
-    bx = lx - fma(P.cm, a1, -(P.sm * a2));
-    by = ly - fma(P.sm, a1, P.cm * a2);
+    w1 = u1 - a1;
+    w2 = u2 - a2;
 }
 
 // Sub-pixel sums of pixel (y, x), whose binned value is their mean over the
@@ -277,8 +279,9 @@ __device__ __forceinline__ void ray_trace_epl(double x1, double x2, double lx, d
 // Along a sub-pixel row the x offset dx from the mass centre steps by
 // pixel_scale / s (at most 7 FP64 additions, ~1e-15 arcsec from the direct
 // product), and everything else linear in x is one FMA in dx with per-row
-// constants: the mass-frame coordinates, theta - alpha_shear - source centre,
-// and the lens light's (R/R_e)^2 (a quadratic in dx).  Lens and source light
+// constants: the mass-frame coordinates, theta - alpha_shear - source centre
+// (rotated into the mass frame), and the lens light's (R/R_e)^2 (a quadratic
+// in dx).  Lens and source light
 // are summed apart (al, as: sums over the sub-pixels at unit amplitude).
 template <int LM>
 struct LightChannels {
@@ -311,25 +314,28 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
         const double yy = ((double)(y * s + v) - g.cfy) * g.sd;
         const double dy = yy - P.ym;
         // values at dx = 0 of: x1 = cm dx + sm dy, x2 = cm dy - sm dx,
-        // lx = x + g1 x + g2 y - xs, ly = y + g2 x - g1 y - ys (x = xm + dx)
+        // lx = x + g1 x + g2 y - xs, ly = y + g2 x - g1 y - ys (x = xm + dx),
+        // and of their mass-frame rotation u1 = cm lx + sm ly, u2 = cm ly - sm lx
         const double c1 = P.sm * dy, c2 = P.cm * dy;
         const double cx = (P.xm + fma(P.g1, P.xm, P.g2 * yy)) - P.xs;
         const double cy = (yy + fma(P.g2, P.xm, -(P.g1 * yy))) - P.ys;
+        const double cu1 = fma(P.cm, cx, P.sm * cy), cu2 = fma(P.cm, cy, -(P.sm * cx));
         const double rs = P.lens.S * dy, rq = P.lens.Q * (dy * dy);
         double dx = dx0;
         for (int u = 0; u < s; ++u) {
             if constexpr (SRC) {
-                double bx, by;
+                double w1, w2;
                 if constexpr (EPL)
-                    ray_trace_epl(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.g1p, dx, cx), fma(P.g2, dx, cy), P, bx,
-                                  by);
+                    ray_trace_epl(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.ku1, dx, cu1), fma(P.ku2, dx, cu2), P,
+                                  w1, w2);
                 else
-                    ray_trace(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.g1p, dx, cx), fma(P.g2, dx, cy), P, bx, by);
+                    ray_trace(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.ku1, dx, cu1), fma(P.ku2, dx, cu2), P, w1,
+                              w2);
                 if constexpr (LENS && !DBL) {
                     acc[0] += sersic_r2(fma(fma(P.lens.P, dx, rs), dx, rq), P.lens, lead);
-                    acc[1] += sersic_r2(ellip_r2(bx, by, P.src), P.src, lead);
+                    acc[1] += sersic_r2(ellip_r2(w1, w2, P.src), P.src, lead);
                 } else {
-                    const double lgs = log2_r2(ellip_r2(bx, by, P.src));
+                    const double lgs = log2_r2(ellip_r2(w1, w2, P.src));
                     acc[IS] += sersic_lg(lgs, es, Bs, lead);
                     if constexpr (DBL) acc[IS + 1] += sersic_lg(lgs + P.dlg_s, g.fix_e[3], g.fix_B[3], lead);
                 }

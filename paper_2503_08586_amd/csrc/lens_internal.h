@@ -29,14 +29,18 @@ struct alignas(16) PropBlock {
     double xm, ym, cm, sm, q2m, ce;            // SIE: centre, cos/sin phi, q^2, c = sqrt(1 - q^2)
     double bsie, bsc;                          // theta_E sqrt(q), theta_E sqrt(q) / c (0 if c = 0)
     double g1, g2, xs, ys;                     // shear, source centre
+    // lens light: (R_p/R_e)^2 in image-plane offsets from the centre; source:
+    // in source-plane offsets from its centre taken in the frame of the mass
+    // ellipse, w = R(-phi_m) (beta - source centre), so that the ray trace
+    // never rotates its deflection back
     LightK lens, src;
-    double g1p;                                // 1 + g1: d/dx of x + g1 x + g2 y
+    double ku1, ku2;                           // d/dx of u = R(-phi_m) (theta - alpha_shear - source centre)
     double dlg_l, dlg_s;                       // two-component light: 2 log2(R_a / R_b) of the lens, of the source
     // elliptical power law (slope gamma = t + 1): q, 2 b^t / (1 + q) with b = theta_E sqrt(q),
     // (1 - t) / 2, and -f = -(1 - q) / (1 + q) (the series ratio's sign and scale)
     double epl_q, epl_pref, epl_h, epl_mf;
 };
-static_assert(sizeof(PropBlock) == 256, "PropBlock layout");
+static_assert(sizeof(PropBlock) == 272, "PropBlock layout");
 constexpr int kPCBytes = (int)sizeof(PropBlock);
 
 // PSF-convolution modes: the public LENS_PREC_* values (0-3), then the FP32

@@ -73,7 +73,9 @@ __device__ inline PropBlock prep_proposal(const double *v, int code)
             b.bsc = b.ce > 0.0 ? b.bsie / b.ce : 0.0;
             b.g1 = v[5];
             b.g2 = v[6];
-            b.g1p = 1.0 + v[5];
+            // u1 = cm lx + sm ly, u2 = cm ly - sm lx with lx = (1 + g1) dx + ..., ly = g2 dx + ...
+            b.ku1 = fma(b.cm, 1.0 + v[5], b.sm * v[6]);
+            b.ku2 = fma(b.cm, v[6], -(b.sm * (1.0 + v[5])));
             if (epl) {
                 const double t = v[19] - 1.0;
                 b.epl_q = q;
@@ -88,6 +90,12 @@ __device__ inline PropBlock prep_proposal(const double *v, int code)
             b.xs = v[17];
             b.ys = v[18];
             b.src = light_constants(v[12], v[13], dbl ? 1.0 : v[14], v[15], v[16]);
+            // the source's quadratic form in the mass frame: beta - centre = R(phi_m) w, so
+            // P' w1^2 + Q' w2^2 + S' w1 w2 with [P' S'/2; S'/2 Q'] = R^T [P S/2; S/2 Q] R
+            const double c = b.cm, s = b.sm, P = b.src.P, Q = b.src.Q, S = b.src.S;
+            b.src.P = fma(P, c * c, fma(Q, s * s, S * (c * s)));
+            b.src.Q = fma(P, s * s, fma(Q, c * c, -(S * (c * s))));
+            b.src.S = fma(2.0 * (Q - P), c * s, S * ((c - s) * (c + s)));
         }
         if (dbl) {
             b.dlg_l = 2.0 * log2(v[8] / v[9]);
