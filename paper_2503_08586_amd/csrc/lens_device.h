@@ -313,13 +313,10 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
     for (int v = 0; v < s; ++v) {
         const double yy = ((double)(y * s + v) - g.cfy) * g.sd;
         const double dy = yy - P.ym;
-        // values at dx = 0 of: x1 = cm dx + sm dy, x2 = cm dy - sm dx,
-        // lx = x + g1 x + g2 y - xs, ly = y + g2 x - g1 y - ys (x = xm + dx),
-        // and of their mass-frame rotation u1 = cm lx + sm ly, u2 = cm ly - sm lx
+        // values at dx = 0 of: x1 = cm dx + sm dy, x2 = cm dy - sm dx and of
+        // u = R(-phi_m) (theta - alpha_shear - source centre)
         const double c1 = P.sm * dy, c2 = P.cm * dy;
-        const double cx = (P.xm + fma(P.g1, P.xm, P.g2 * yy)) - P.xs;
-        const double cy = (yy + fma(P.g2, P.xm, -(P.g1 * yy))) - P.ys;
-        const double cu1 = fma(P.cm, cx, P.sm * cy), cu2 = fma(P.cm, cy, -(P.sm * cx));
+        const double cu1 = fma(P.bu1, yy, P.au1), cu2 = fma(P.bu2, yy, P.au2);
         const double rs = P.lens.S * dy, rq = P.lens.Q * (dy * dy);
         double dx = dx0;
         for (int u = 0; u < s; ++u) {

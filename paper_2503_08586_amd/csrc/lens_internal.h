@@ -28,7 +28,9 @@ struct alignas(16) PropBlock {
                                                // amplitudes (usable when they are solved); 0 outside
     double xm, ym, cm, sm, q2m, ce;            // SIE: centre, cos/sin phi, q^2, c = sqrt(1 - q^2)
     double bsie, bsc;                          // theta_E sqrt(q), theta_E sqrt(q) / c (0 if c = 0)
-    double g1, g2, xs, ys;                     // shear, source centre
+    // u = R(-phi_m) (theta - alpha_shear - source centre) at the mass centre's
+    // abscissa (dx = 0), affine in the ordinate y: u1 = au1 + bu1 y, u2 = au2 + bu2 y
+    double au1, bu1, au2, bu2;
     // lens light: (R_p/R_e)^2 in image-plane offsets from the centre; source:
     // in source-plane offsets from its centre taken in the frame of the mass
     // ellipse, w = R(-phi_m) (beta - source centre), so that the ray trace

@@ -71,11 +71,17 @@ __device__ inline PropBlock prep_proposal(const double *v, int code)
             b.ce = sqrt((1.0 - q) * (1.0 + q));
             b.bsie = v[0] * sqrt(q);
             b.bsc = b.ce > 0.0 ? b.bsie / b.ce : 0.0;
-            b.g1 = v[5];
-            b.g2 = v[6];
-            // u1 = cm lx + sm ly, u2 = cm ly - sm lx with lx = (1 + g1) dx + ..., ly = g2 dx + ...
-            b.ku1 = fma(b.cm, 1.0 + v[5], b.sm * v[6]);
-            b.ku2 = fma(b.cm, v[6], -(b.sm * (1.0 + v[5])));
+            // theta - alpha_shear - source centre = (lx, ly) with (x = xm + dx)
+            //   lx = (1 + g1) x + g2 y - xs,  ly = g2 x + (1 - g1) y - ys,
+            // rotated into the mass frame: u1 = cm lx + sm ly, u2 = cm ly - sm lx
+            const double g1 = v[5], g2 = v[6], xs = v[17], ys = v[18];
+            const double X0 = fma(1.0 + g1, v[3], -xs), Y0 = fma(g2, v[3], -ys);   // lx, ly at x = xm, y = 0
+            b.ku1 = fma(b.cm, 1.0 + g1, b.sm * g2);
+            b.ku2 = fma(b.cm, g2, -(b.sm * (1.0 + g1)));
+            b.au1 = fma(b.cm, X0, b.sm * Y0);
+            b.bu1 = fma(b.cm, g2, b.sm * (1.0 - g1));
+            b.au2 = fma(b.cm, Y0, -(b.sm * X0));
+            b.bu2 = fma(b.cm, 1.0 - g1, -(b.sm * g2));
             if (epl) {
                 const double t = v[19] - 1.0;
                 b.epl_q = q;
@@ -87,8 +93,6 @@ __device__ inline PropBlock prep_proposal(const double *v, int code)
         // two-component light: e and B of the fixed indices come from the lens descriptor
         if (lens) b.lens = light_constants(v[7], v[8], dbl ? 1.0 : v[9], v[10], v[11]);
         if (src) {
-            b.xs = v[17];
-            b.ys = v[18];
             b.src = light_constants(v[12], v[13], dbl ? 1.0 : v[14], v[15], v[16]);
             // the source's quadratic form in the mass frame: beta - centre = R(phi_m) w, so
             // P' w1^2 + Q' w2^2 + S' w1 w2 with [P' S'/2; S'/2 Q'] = R^T [P S/2; S/2 Q] R
