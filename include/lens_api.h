@@ -325,7 +325,7 @@ lens_status lens_ensemble_run(lens_ctx *ctx, lens_ens ens, int64_t iterations, i
  * Blocks until done.  LENS_EINVAL for a repeated id or more than INT_MAX
  * pooled proposals (sum of W/2); LENS_ENOENT for an unknown id (nothing
  * moves); LENS_ENOMEM past the HBM budget for the pooled scratch,
- * sum W/2 x 456 bytes plus the per-ensemble descriptors. */
+ * sum W/2 x 472 bytes plus the per-ensemble descriptors. */
 lens_status lens_ensemble_run_many(lens_ctx *ctx, int32_t n, const lens_ens *ens, int64_t iterations);
 /* The current walkers [W][20], their lnP [W], accepted moves per walker [W]
  * and the iterations done so far; any output may be NULL. */
