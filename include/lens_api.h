@@ -185,10 +185,18 @@ typedef struct lens_stats {
     int64_t queued, inflight;
     int64_t hbm_budget_bytes, hbm_used_bytes;
     int64_t launches;
+    /* request latency, lens_submit to the result written (lens_poll / lens_wait
+     * answer LENS_OK from then on): exact quantiles over the most recent
+     * (at most 4,096) completed requests, the maximum over all of them */
+    int64_t latency_count;      /* completed requests in the quantile window */
+    double latency_p50_us, latency_p99_us, latency_max_us;
 } lens_stats;
 
 /* Context.  lens_init creates the context on opts->device (NULL opts: all
- * defaults).  lens_shutdown waits for in-flight work, cancels queued
+ * defaults).  With the environment variable LENS_LOG set to 1 at lens_init,
+ * the context writes one line to stderr per event: set-up, lens load and
+ * unload, batch-plan capture, ensemble create and destroy, and every call
+ * error with its message.  lens_shutdown waits for in-flight work, cancels queued
  * requests and frees everything; the pointer is invalid afterwards. */
 lens_status lens_init(const lens_init_opts *opts, lens_ctx **out);
 void lens_shutdown(lens_ctx *ctx);

@@ -125,7 +125,8 @@ class lens_ensemble_desc(ctypes.Structure):
 class lens_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "requests_submitted", "requests_done", "requests_failed", "requests_canceled",
-        "proposals_done", "queued", "inflight", "hbm_budget_bytes", "hbm_used_bytes", "launches")]
+        "proposals_done", "queued", "inflight", "hbm_budget_bytes", "hbm_used_bytes", "launches",
+        "latency_count")] + [(n, ctypes.c_double) for n in ("latency_p50_us", "latency_p99_us", "latency_max_us")]
 
 
 class LensError(RuntimeError):

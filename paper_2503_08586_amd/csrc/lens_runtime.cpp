@@ -12,6 +12,7 @@
 #include <climits>
 #include <cmath>
 #include <condition_variable>
+#include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -34,6 +35,7 @@ namespace {
 
 constexpr size_t kAlign = 256;
 constexpr int kServeStreams = 4;
+constexpr size_t kLatencyWindow = 4096;   // completed requests kept for the latency quantiles
 constexpr int64_t kTileMax = 8192;           // proposals per serving launch
 constexpr size_t kBytesPerProposal = lensk::kStride * sizeof(double) + lensk::kPCBytes + sizeof(double);
 
@@ -75,6 +77,7 @@ struct Request {
     int tiles_running = 0;
     bool cancel = false;
     std::vector<double> result;   // assembled here, copied to out when complete
+    std::chrono::steady_clock::time_point t_submit;
 };
 
 struct Tile {
@@ -272,6 +275,10 @@ struct lens_ctx {
     std::thread sched;
     bool stop = false;
     lens_stats stats{};
+    // latencies (us) of the most recent completed requests, a ring (guarded by smu)
+    std::vector<double> lat_ring;
+    size_t lat_pos = 0;
+    int log = 0;                          // LENS_LOG at init: 1 = one stderr line per event
 };
 
 namespace {
@@ -289,9 +296,23 @@ struct DeviceGuard {
     }
 };
 
+// One line to stderr when the context was created with LENS_LOG=1.
+void log_line(const lens_ctx *c, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void log_line(const lens_ctx *c, const char *fmt, ...)
+{
+    if (!c || !c->log) return;
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    fprintf(stderr, "[lens %p] %s\n", (const void *)c, buf);
+}
+
 lens_status fail(lens_ctx *c, lens_status st, const std::string &msg)
 {
     t_err[c] = msg;
+    log_line(c, "error %d (%s): %s", (int)st, lens_strerror(st), msg.c_str());
     return st;
 }
 
@@ -464,6 +485,10 @@ extern "C" lens_status lens_init(const lens_init_opts *opts, lens_ctx **out)
     if ((o.dev_alloc == nullptr) != (o.dev_free == nullptr)) return LENS_EINVAL;
     auto c = std::make_unique<lens_ctx>();
     c->device = o.device;
+    {
+        const char *lg = getenv("LENS_LOG");
+        c->log = lg && atoi(lg) > 0;
+    }
     DeviceGuard dg(c->device);
     c->alloc = o.dev_alloc;
     c->dfree = o.dev_free;
@@ -508,6 +533,8 @@ extern "C" lens_status lens_init(const lens_init_opts *opts, lens_ctx **out)
         c->lds_cu = lensk::lds_per_cu();
     }
     lens_ctx *raw = c.release();
+    log_line(raw, "init: device %d, %d CUs, %zu B of LDS per workgroup, HBM budget %lld B, %s stream", raw->device,
+             raw->num_cus, raw->lds_max, (long long)raw->budget, raw->own_stream ? "own" : "caller's");
     raw->sched = std::thread(scheduler_main, raw);
     *out = raw;
     return LENS_OK;
@@ -516,6 +543,7 @@ extern "C" lens_status lens_init(const lens_init_opts *opts, lens_ctx **out)
 extern "C" void lens_shutdown(lens_ctx *c)
 {
     if (!c) return;
+    log_line(c, "shutdown");
     {
         std::unique_lock<std::mutex> lk(c->smu);
         for (Request *r : c->queue) {
@@ -965,6 +993,9 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
         L->id = c->next_id++;
         c->lenses[L->id] = L;
     }
+    log_line(c, "load lens %lld: %dx%d px, s=%d, PSF %d (convolved %d), mode %d, %d-row strips x %d threads, %zu B",
+             (long long)L->id, L->g.ny, L->g.nx, L->g.s, d->psf_size, L->g.k, L->g.mode, L->g.strip_h, L->g.nt,
+             L->bytes);
     *out_id = L->id;
     return LENS_OK;
 }
@@ -998,6 +1029,7 @@ extern "C" lens_status lens_unload(lens_ctx *c, lens_id id)
             ++it;
         }
     }
+    log_line(c, "unload lens %lld", (long long)id);
     dev_free(c, L->slab);
     uncharge(c, (int64_t)L->bytes);
     delete L;
@@ -1383,6 +1415,8 @@ lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int
     if (e != hipSuccess) return bail(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return bail(e, "hipGraphInstantiate");
+    log_line(c, "batch plan captured: %d lenses, %lld proposals, %zu persistent launches, %zu B", (int)nlens,
+             (long long)tot, gs.size(), pl->bytes);
     *out = pl.release();
     return LENS_OK;
 }
@@ -1507,6 +1541,12 @@ void finish_request(lens_ctx *c, Request *r)
         r->status = LENS_OK;
         c->stats.requests_done++;
         c->stats.proposals_done += r->n;
+        const double us =
+            std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now() - r->t_submit).count();
+        if (c->lat_ring.size() < kLatencyWindow) c->lat_ring.push_back(us);
+        else c->lat_ring[c->lat_pos] = us;
+        c->lat_pos = (c->lat_pos + 1) % kLatencyWindow;
+        c->stats.latency_max_us = std::max(c->stats.latency_max_us, us);
     } else {
         r->state = RState::Error;
         c->stats.requests_failed++;
@@ -1697,6 +1737,7 @@ extern "C" lens_status lens_submit(lens_ctx *c, lens_id id, const double *params
         r->params.assign(params, params + n * lensk::kStride);
         r->result.assign((size_t)n, 0.0);
         r->out = out;
+        r->t_submit = std::chrono::steady_clock::now();
         L->requests++;
         c->reqs[r->id] = r;
         c->stats.requests_submitted++;
@@ -1780,6 +1821,16 @@ extern "C" lens_status lens_get_stats(lens_ctx *c, lens_stats *out)
     out->inflight = (int64_t)c->running.size();
     out->hbm_budget_bytes = c->budget;
     out->hbm_used_bytes = c->used.load();
+    // nearest-rank quantiles of the latency window
+    std::vector<double> w(c->lat_ring);
+    out->latency_count = (int64_t)w.size();
+    auto rank = [&](double q) {
+        const size_t k = (size_t)std::ceil(q * (double)w.size()) - 1;
+        std::nth_element(w.begin(), w.begin() + k, w.end());
+        return w[k];
+    };
+    out->latency_p50_us = w.empty() ? 0.0 : rank(0.50);
+    out->latency_p99_us = w.empty() ? 0.0 : rank(0.99);
     return LENS_OK;
 }
 
@@ -1958,6 +2009,8 @@ extern "C" lens_status lens_ensemble_create(lens_ctx *c, lens_id id, const lens_
         E->id = c->next_ens++;
         c->ensembles[E->id] = E;
     }
+    log_line(c, "ensemble %lld on lens %lld: %d walkers, %d free slots, %zu B", (long long)E->id, (long long)id, W,
+             dfree, E->bytes);
     *out = E->id;
     return LENS_OK;
 }
@@ -2201,5 +2254,6 @@ extern "C" lens_status lens_ensemble_destroy(lens_ctx *c, lens_ens id)
     }
     DeviceGuard dg(c->device);
     free_ensemble(c, E);
+    log_line(c, "ensemble %lld destroyed", (long long)id);
     return LENS_OK;
 }

@@ -192,3 +192,67 @@ def test_model_image_rejects_bad_proposal(ctx, b):
         ctx.model_image(lid, p, 1)
     assert ei.value.status == b.LENS_EINVAL
     ctx.unload(lid)
+
+
+def test_latency_statistics(b):
+    """The context's request-latency window against the client's own clock:
+    each request's latency (submit to result written) lies inside the client's
+    submit-to-wait bracket, so every order statistic is bounded by the
+    client's."""
+    import time
+    say("case: serving latency statistics")
+    with b.LensContext(0, max_inflight=2) as c:
+        sp = _spec(2000)
+        lid = c.load(sp)
+        st0 = c.stats()
+        assert st0["latency_count"] == 0 and st0["latency_p50_us"] == 0.0 and st0["latency_max_us"] == 0.0
+        walls = []
+        for i in range(12):
+            t0 = time.perf_counter()
+            r = c.submit(lid, sp.proposals[:100 + 150 * i])
+            assert c.wait(r) == b.LENS_OK
+            walls.append((time.perf_counter() - t0) * 1e6)
+        st = c.stats()
+        walls.sort()
+        assert st["latency_count"] == 12
+        assert 0.0 < st["latency_p50_us"] <= st["latency_p99_us"] <= st["latency_max_us"]
+        assert st["latency_p99_us"] == st["latency_max_us"]          # nearest rank of 12: the largest
+        assert st["latency_p50_us"] <= walls[5] and st["latency_max_us"] <= walls[-1]
+        c.unload(lid)
+
+
+def test_env_gated_log(tmp_path):
+    """LENS_LOG=1 at lens_init: one stderr line per event, errors with their
+    message; without it the library writes nothing."""
+    import os
+    import subprocess
+    import sys
+    say("case: LENS_LOG in a child process")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = "\n".join([
+        "import numpy as np",
+        "from paper_2503_08586_amd import binding, synth",
+        "sp = synth.config1(nprop=8)[0]",
+        "sp.make_data(lambda s, t: np.zeros((s.ny, s.nx)))",
+        "with binding.LensContext(0) as c:",
+        "    lid = c.load(sp)",
+        "    c.loglike(lid, sp.proposals)",
+        "    try:",
+        "        c.unload(lid + 1000)",
+        "    except binding.LensError:",
+        "        pass",
+        "    c.unload(lid)",
+        "print('child done')",
+    ])
+    for log in ("1", "0"):
+        env = dict(os.environ, LENS_LOG=log, PYTHONPATH=root)
+        r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, env=env, timeout=180,
+                           cwd=root)
+        assert r.returncode == 0 and "child done" in r.stdout, r.stderr[-2000:]
+        lines = [x for x in r.stderr.splitlines() if x.startswith("[lens ")]
+        if log == "1":
+            text = "\n".join(lines)
+            for want in ("init: device 0", "load lens", "error -3 (", "unknown lens id", "unload lens", "shutdown"):
+                assert want in text, (want, text)
+        else:
+            assert lines == [], lines

@@ -31,7 +31,8 @@ def test_runtime_under_host_asan_ubsan(tmp_path):
     env = dict(os.environ,
                ASAN_OPTIONS="detect_leaks=1:halt_on_error=1:verify_asan_link_order=0",
                LSAN_OPTIONS="suppressions=%s" % supp,
-               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+               UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1",
+               LENS_LOG="1")   # the event log's formatting runs under the sanitizers too
     say("case: C-ABI driver under host ASan/UBSan")
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=240)
     out = r.stdout + r.stderr
