@@ -171,7 +171,7 @@ def measured_traffic(prec):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py measures one GPU; this build runs on a single MI355X (got --gpus %d)" % args.gpus,
+        print("bench.py measures one GPU: the library runs on a single MI355X (got --gpus %d)" % args.gpus,
               file=sys.stderr)
         sys.exit(2)
     import torch

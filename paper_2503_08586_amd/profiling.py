@@ -51,6 +51,11 @@ def read_counter(d, counter, name_part):
     return sum(vals) / len(vals), len(vals), name
 
 
+def rel(d):
+    """A counter directory as given on the command line, relative to the repository root."""
+    return os.path.relpath(os.path.abspath(d), ROOT)
+
+
 def main():
     cf, cw, pf, pw = sys.argv[1:5]
     copy_f, _, _ = read_counter(cf, "FETCH_SIZE", "")
@@ -64,17 +69,17 @@ def main():
            "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw, "dispatches": [nf, nw],
            "copy_fetch_kib": copy_f, "copy_write_kib": copy_w, "scale_fetch": sf, "scale_write": sw,
            "traffic_bytes_per_launch": (kf * sf + kw * sw) * 1024.0, "kernel_src_sha256": kernel_hash(),
+           # the commands that wrote the four counter directories given here
            "commands": [
-               "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_copy_fetch -o p -- "
-               "python3 bench.py --copy-calibration",
-               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_copy_write -o p -- "
-               "python3 bench.py --copy-calibration",
-               "rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/pmc_plain_fetch -o p -- "
-               "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline",
-               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/pmc_plain_write -o p -- "
-               "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline",
-               "python -m paper_2503_08586_amd.profiling gpurun_out/pmc_copy_fetch gpurun_out/pmc_copy_write "
-               "gpurun_out/pmc_plain_fetch gpurun_out/pmc_plain_write"]}
+               "rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s -o p -- python3 bench.py --copy-calibration"
+               % rel(cf),
+               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s -o p -- python3 bench.py --copy-calibration"
+               % rel(cw),
+               "rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s -o p -- "
+               "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline" % rel(pf),
+               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s -o p -- "
+               "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline" % rel(pw),
+               "python -m paper_2503_08586_amd.profiling %s %s %s %s" % tuple(rel(x) for x in (cf, cw, pf, pw))]}
     with open(RECORD, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
