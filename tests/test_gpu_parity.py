@@ -146,11 +146,12 @@ def test_geometries(ctx, geom, mode):
     got = ctx.loglike(lid, spec.proposals)
     # The benchmark workloads keep the plain gates.  These edge images (delta
     # PSF, tiny images, s = 1..5) average little, so a mode's per-pixel storage
-    # unit shows through: tiny images in every mode, and every edge image in
-    # the two reduced-precision modes, are gated at the mode's storage floor
+    # unit shows through: masks of fewer than 64 pixels in every mode (chi2
+    # averages the rounding over the masked pixels only), and every edge image
+    # in the two reduced-precision modes, are gated at the mode's storage floor
     # (a worst-case bound) when that exceeds the plain gate.
     _check(spec, got, spec.proposals, tol=MODE_TOL[m], label="%s/%s" % (name, mname),
-           storage_floor=ny * nx < 64 or m in (1, 2), unit=UNIT[m])
+           storage_floor=int(spec.mask.sum()) < 64 or m in (1, 2), unit=UNIT[m])
     ctx.unload(lid)
 
 
@@ -423,3 +424,58 @@ def test_sampler_path_proposals(ctx):
     lid = ctx.load(spec)
     _check(spec, ctx.loglike(lid, P), P, label="sampler path")
     ctx.unload(lid)
+
+
+def _random_geoms(n=10, seed=2503):
+    """Seeded random geometries: sizes 1-71 px, supersampling 1-8 (6-8 not in
+    GEOMS), odd PSF sides 1-63, all four mask kinds."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, s in enumerate((6, 7, 8, 1, 2, 3, 4, 5, 6, 8)[:n]):
+        ny, nx = int(rng.integers(1, 72)), int(rng.integers(1, 72))
+        k = int(rng.choice(np.arange(1, 64, 2)))
+        dpix = float(rng.uniform(0.03, 0.12))
+        out.append(("rand%d_%dx%d_s%d_k%d" % (i, ny, nx, s, k), ny, nx, dpix, s, k, ("full", "circle", "ring",
+                                                                                    "random")[i % 4]))
+    return out
+
+
+RAND_GEOMS = _random_geoms()
+
+
+def _random_spec(geom, epl):
+    name, ny, nx, dpix, s, k, mk = geom
+    rng = np.random.default_rng(sum(map(ord, name)) + (7 if epl else 0))
+    psf = synth.gaussian_psf(k, 3.0 * dpix, dpix) if k > 1 else np.ones((1, 1))
+    psf = psf * (1.0 + 0.3 * rng.random(psf.shape))
+    mask = _mask(mk, ny, nx, dpix, rng)
+    if mask.sum() == 0:
+        mask[ny // 2, nx // 2] = 1
+    spec = custom_spec(11 + epl, ny, nx, dpix, s, psf, mask, 24)
+    if epl:
+        spec.truth = spec.truth.copy()
+        spec.truth[19] = 2.1
+        spec.proposals = np.array(spec.proposals, copy=True)
+        spec.proposals[:, 19] = rng.uniform(1.2, 2.8, len(spec.proposals))
+        oracle_data(spec)
+    return spec
+
+
+@pytest.mark.parametrize("geom", RAND_GEOMS, ids=[g[0] for g in RAND_GEOMS])
+def test_random_geometries(ctx, geom):
+    """fp32 and split3 on every random geometry, and the elliptical power law
+    (fp32) on three of them, against the oracle."""
+    name = geom[0]
+    say("case: random geometry %s" % name)
+    spec = _random_spec(geom, False)
+    for mname, m in (("fp32", 0), ("split3", 3)):
+        lid = ctx.load(spec, precision=m)
+        _check(spec, ctx.loglike(lid, spec.proposals), spec.proposals, tol=MODE_TOL[m],
+               label="%s/%s" % (name, mname), storage_floor=int(spec.mask.sum()) < 64, unit=UNIT[m])
+        ctx.unload(lid)
+    if RAND_GEOMS.index(geom) % 3 == 0:
+        spec = _random_spec(geom, True)
+        lid = ctx.load(spec, mass_model=1)
+        _check(spec, ctx.loglike(lid, spec.proposals), spec.proposals, label="%s/epl" % name,
+               storage_floor=int(spec.mask.sum()) < 64)
+        ctx.unload(lid)
