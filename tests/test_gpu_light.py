@@ -205,3 +205,41 @@ def test_mixed_light_models_in_multi_call(ctx):
         assert np.all(e <= TOL_FP32)
     for lid in lids:
         ctx.unload(lid)
+
+
+def _random_light_cases(seed=3582):
+    """Seeded geometries for the solved-amplitude kernels: supersampling 1-8,
+    odd PSF sides up to 63, sizes 12-60 px, masks of at least 64 pixels;
+    each with one light model, one of them with the power-law mass."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i, (s, model) in enumerate(((7, 0), (3, 1), (8, 2), (5, 3), (2, 0), (6, 3))):
+        ny, nx = int(rng.integers(12, 61)), int(rng.integers(12, 61))
+        k = int(rng.choice(np.arange(1, 64, 2)))
+        dpix = float(rng.uniform(0.04, 0.1))
+        out.append(("rl%d_%dx%d_s%d_k%d_m%d" % (i, ny, nx, s, k, model), ny, nx, dpix, s, k, model, i == 4))
+    return out
+
+
+RAND_LIGHT = _random_light_cases()
+
+
+@pytest.mark.parametrize("case", RAND_LIGHT, ids=[c[0] for c in RAND_LIGHT])
+def test_light_models_random_geometries(ctx, case):
+    from gpu_cases import custom_spec
+    name, ny, nx, dpix, s, k, model, epl = case
+    say("case: %s%s" % (name, " (power-law mass)" if epl else ""))
+    rng = np.random.default_rng(sum(map(ord, name)))
+    psf = synth.gaussian_psf(k, 3.0 * dpix, dpix) if k > 1 else np.ones((1, 1))
+    psf = psf * (1.0 + 0.3 * rng.random(psf.shape))
+    mask = synth.circular_mask(ny, nx, dpix, 0.45 * min(ny, nx) * dpix)
+    if mask.sum() < 64:
+        mask = np.ones((ny, nx), np.uint8)
+    spec = custom_spec(29 + model, ny, nx, dpix, s, psf, mask, 16)
+    P = _props(spec, model)
+    if epl:
+        P = np.array(P, copy=True)
+        P[:, 19] = rng.uniform(1.3, 2.7, len(P))
+    lid = ctx.load(spec, amplitudes=NNLS, light_model=model, sersic_n=NFIX, mass_model=1 if epl else 0)
+    _check(spec, lid, ctx, P, model, name, n_amp=4)
+    ctx.unload(lid)
