@@ -256,3 +256,32 @@ def test_env_gated_log(tmp_path):
                 assert want in text, (want, text)
         else:
             assert lines == [], lines
+
+
+def test_serving_every_lens_kind(ctx, b):
+    """Serving with lenses of every kind at once (FP32 and split3 convolution,
+    amplitudes solved for two light models, the power-law mass with explicit
+    and solved amplitudes): each request's results equal the same proposals
+    evaluated alone, bit for bit."""
+    say("case: serving across lens kinds")
+    specs = synth.config3(nlens=6, scale_props=0.0)
+    kinds = [dict(), dict(precision=3), dict(amplitudes=1), dict(amplitudes=1, light_model=3, sersic_n=(1, 4, 1, 4)),
+             dict(mass_model=1), dict(mass_model=1, amplitudes=1)]
+    rng = np.random.default_rng(41)
+    lids = []
+    for sp, kw in zip(specs, kinds):
+        oracle_data(sp)
+        lids.append(ctx.load(sp, **kw))
+    reqs = []
+    for i in range(18):
+        j = i % len(lids)
+        P = synth.draw_params(rng, int(rng.integers(50, 3000)))
+        if kinds[j].get("mass_model") == 1:
+            P[:, 19] = rng.uniform(1.4, 2.6, len(P))
+        reqs.append((j, P, ctx.submit(lids[j], P)))
+    for j, P, r in reqs:
+        assert ctx.wait(r) == b.LENS_OK
+        assert np.array_equal(r.out, ctx.loglike(lids[j], P)), (j, kinds[j])
+        assert np.isfinite(r.out).sum() > 0
+    for lid in lids:
+        ctx.unload(lid)
