@@ -285,3 +285,69 @@ def test_serving_every_lens_kind(ctx, b):
         assert np.isfinite(r.out).sum() > 0
     for lid in lids:
         ctx.unload(lid)
+
+
+def test_concurrent_calls_from_threads(b):
+    """Four threads on one context, each repeating a different kind of call
+    (blocking batch, multi-lens graph, serving, sampler ensemble): every
+    result equals the one computed alone beforehand."""
+    import threading
+    say("case: concurrent calls from four threads")
+    with b.LensContext(0, max_inflight=4) as c:
+        specs = synth.config3(nlens=3, scale_props=0.02)
+        lids = []
+        for sp in specs:
+            oracle_data(sp)
+            lids.append(c.load(sp))
+        P = [sp.proposals for sp in specs]
+        ref_single = [c.loglike(lid, p) for lid, p in zip(lids, P)]
+        ref_multi = c.loglike_multi(lids, P)
+        lo = np.array([x[1] for x in synth.PRIOR_BOX] + [0.0])
+        hi = np.array([x[2] for x in synth.PRIOR_BOX] + [0.0])
+        init = np.clip(specs[0].truth + 0.02 * (hi - lo) * np.random.default_rng(3).normal(size=(16, 20)), lo, hi)
+        e_ref = c.ensemble(lids[0], init, lo, hi, seed=5)
+        e_run = c.ensemble(lids[0], init, lo, hi, seed=5)
+        errors = []
+        reps = 12
+
+        def guard(fn):
+            def run():
+                try:
+                    fn()
+                except Exception as ex:   # reported by the main thread
+                    errors.append(ex)
+            return run
+
+        def blocking():
+            for r in range(reps):
+                j = r % 3
+                assert np.array_equal(c.loglike(lids[j], P[j]), ref_single[j])
+
+        def multi():
+            for _ in range(reps):
+                out = c.loglike_multi(lids, P)
+                assert all(np.array_equal(o, x) for o, x in zip(out, ref_multi))
+
+        def serving():
+            for r in range(reps):
+                j = r % 3
+                q = c.submit(lids[j], P[j])
+                assert c.wait(q) == b.LENS_OK and np.array_equal(q.out, ref_single[j])
+
+        def sampler():
+            for _ in range(reps):
+                c.ensemble_run(e_run, 1)
+
+        th = [threading.Thread(target=guard(f)) for f in (blocking, multi, serving, sampler)]
+        for t in th:
+            t.start()
+        for t in th:
+            t.join()
+        assert not errors, errors
+        c.ensemble_run(e_ref, reps)
+        a, r = c.ensemble_get(e_run), c.ensemble_get(e_ref)
+        assert all(np.array_equal(x, y) for x, y in zip(a[:3], r[:3])) and a[3] == r[3] == reps
+        for e in (e_ref, e_run):
+            c.ensemble_destroy(e)
+        for lid in lids:
+            c.unload(lid)
