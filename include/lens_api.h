@@ -329,12 +329,16 @@ lens_status lens_ensemble_run(lens_ctx *ctx, lens_ens ens, int64_t iterations, i
  * so that many small ensembles, one per lens of a survey, fill the device
  * where each alone would not.  Each ensemble moves exactly as under
  * lens_ensemble_run from its own iteration count (same stream, same result,
- * bit for bit); no chain is returned (read the state with lens_ensemble_get).
- * Blocks until done.  LENS_EINVAL for a repeated id or more than INT_MAX
- * pooled proposals (sum of W/2); LENS_ENOENT for an unknown id (nothing
- * moves); LENS_ENOMEM past the HBM budget for the pooled scratch,
- * sum W/2 x 472 bytes plus the per-ensemble descriptors. */
-lens_status lens_ensemble_run_many(lens_ctx *ctx, int32_t n, const lens_ens *ens, int64_t iterations);
+ * bit for bit).  chains (may be NULL): n host pointers, chains[e] receiving
+ * [iterations/thin][W_e][20], the walkers of ensemble e after every thin-th
+ * iteration of this call; chain_lnps likewise [iterations/thin][W_e]; a NULL
+ * entry skips that ensemble.  Blocks until done.  LENS_EINVAL for a repeated
+ * id, thin < 1 with a chain requested, or more than INT_MAX pooled proposals
+ * (sum of W/2); LENS_ENOENT for an unknown id (nothing moves); LENS_ENOMEM past
+ * the HBM budget for the pooled scratch, sum W/2 x 472 bytes plus the
+ * per-ensemble descriptors and the staged chain rows. */
+lens_status lens_ensemble_run_many(lens_ctx *ctx, int32_t n, const lens_ens *ens, int64_t iterations, int32_t thin,
+                                   double *const *chains, double *const *chain_lnps);
 /* The current walkers [W][20], their lnP [W], accepted moves per walker [W]
  * and the iterations done so far; any output may be NULL. */
 lens_status lens_ensemble_get(lens_ctx *ctx, lens_ens ens, double *walkers, double *lnp,

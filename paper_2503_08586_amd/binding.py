@@ -170,7 +170,7 @@ def load():
         "lens_psf_crop": ([dp, i32, ctypes.c_double, ctypes.POINTER(i32)], i32),
         "lens_ensemble_create": ([vp, i64, ctypes.POINTER(lens_ensemble_desc), i64p], i32),
         "lens_ensemble_run": ([vp, i64, i64, i32, dp, dp], i32),
-        "lens_ensemble_run_many": ([vp, i32, i64p, i64], i32),
+        "lens_ensemble_run_many": ([vp, i32, i64p, i64, i32, ctypes.POINTER(dp), ctypes.POINTER(dp)], i32),
         "lens_ensemble_get": ([vp, i64, dp, dp, i64p, i64p], i32),
         "lens_ensemble_destroy": ([vp, i64], i32),
         "lens_philox4x32_10": ([vp, u32p, u32p, i64, u32p], i32),
@@ -372,12 +372,27 @@ def lens_ensemble_run(ctx, ens, iterations, thin=0, chain=False):
     return cw, cl
 
 
-def lens_ensemble_run_many(ctx, ens_ids, iterations):
+def lens_ensemble_run_many(ctx, ens_ids, iterations, thin=0, chain=False):
     """Advance every ensemble of ``ens_ids`` (distinct) by ``iterations``
-    iterations together, pooling their proposals into shared launches."""
+    iterations together, pooling their proposals into shared launches; with
+    ``chain`` returns one (chain [iterations/thin, W, 20], chain_lnp
+    [iterations/thin, W]) pair per ensemble."""
     ids = np.ascontiguousarray(np.asarray(ens_ids, dtype=np.int64).reshape(-1))
     ptr = ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if ids.size else None
-    _check(ctx, load().lens_ensemble_run_many(ctx, int(ids.size), ptr, int(iterations)))
+    if not chain:
+        _check(ctx, load().lens_ensemble_run_many(ctx, int(ids.size), ptr, int(iterations), int(thin), None, None))
+        return None
+    thin = max(1, int(thin))
+    ns = int(iterations) // thin
+    outs = []
+    for e in ids:
+        W = _ens_walkers(ctx, int(e))
+        outs.append((np.empty((ns, W, STRIDE)), np.empty((ns, W))))
+    dp = ctypes.POINTER(ctypes.c_double)
+    cw = (dp * max(1, len(outs)))(*[_dptr(a) for a, _ in outs])
+    cl = (dp * max(1, len(outs)))(*[_dptr(b) for _, b in outs])
+    _check(ctx, load().lens_ensemble_run_many(ctx, int(ids.size), ptr, int(iterations), thin, cw, cl))
+    return outs
 
 
 def lens_ensemble_destroy(ctx, ens):
@@ -562,8 +577,8 @@ class LensContext:
     def ensemble_run(self, ens, iterations, thin=0, chain=False):
         return lens_ensemble_run(self.ctx, ens, iterations, thin, chain)
 
-    def ensemble_run_many(self, ens_ids, iterations):
-        lens_ensemble_run_many(self.ctx, ens_ids, iterations)
+    def ensemble_run_many(self, ens_ids, iterations, thin=0, chain=False):
+        return lens_ensemble_run_many(self.ctx, ens_ids, iterations, thin, chain)
 
     def ensemble_get(self, ens):
         return lens_ensemble_get(self.ctx, ens)

@@ -171,13 +171,16 @@ struct EnsembleDev {
     int64_t *accepted;
     const double *lo, *hi;
     int64_t off;
+    double *chain_w, *chain_lnp;   // device chain staging of this call, [rows][W][20] and [rows][W]; may be null
 };
 // stage 0: proposals of half `half` of every ensemble at iteration t0 + it into
 // the pooled d_Y [total][20], d_aux [total][4], d_pc [total]; stage 1: their
-// acceptance from the pooled lnL d_lnl [total].  d_hoff: [n + 1] prefix of W/2.
+// acceptance from the pooled lnL d_lnl [total], and with slot >= 0 the walkers
+// after the move written to chain row `slot` of every ensemble that has a
+// chain.  d_hoff: [n + 1] prefix of W/2.
 hipError_t launch_stretch_many(int half, int64_t it, const EnsembleDev *d_ens, const int64_t *d_hoff, int n,
                                int64_t total, double *d_Y, double *d_aux, PropBlock *d_pc, int stage, const double *d_lnl,
-                               hipStream_t st);
+                               int64_t slot, hipStream_t st);
 hipError_t launch_stretch_propose(int W, int half, uint64_t t, uint64_t seed, double a, int model_code,
                                   const double *d_walkers, const double *d_lo, const double *d_hi, double *d_Y,
                                   double *d_aux, PropBlock *d_pc, hipStream_t st);

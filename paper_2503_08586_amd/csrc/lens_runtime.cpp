@@ -2096,7 +2096,8 @@ namespace {
 // half-step one proposal launch over all their moving halves, the persistent
 // multi-lens likelihood launches over the pooled proposals, one acceptance
 // launch.
-lens_status ensemble_run_many(lens_ctx *c, const std::vector<Ensemble *> &Es, int64_t iterations)
+lens_status ensemble_run_many(lens_ctx *c, const std::vector<Ensemble *> &Es, int64_t iterations, int32_t thin,
+                              double *const *chains, double *const *chain_lnps)
 {
     const int n = (int)Es.size();
     std::vector<int64_t> hoff(n + 1, 0), cnt(n);
@@ -2128,7 +2129,13 @@ lens_status ensemble_run_many(lens_ctx *c, const std::vector<Ensemble *> &Es, in
         D.hi = E->hi;
         D.off = hoff[e];
     }
-    // device: ensembles | hoff | Y | aux | pc | lnL | geoms | lstart | lout | counters
+    // chain rows kept per ensemble, staged on the device: [nstore][W][20] then [nstore][W]
+    const bool store = chains || chain_lnps;
+    const int64_t nstore = store ? iterations / thin : 0;
+    std::vector<size_t> coff(n + 1, 0);
+    for (int e = 0; e < n; ++e)
+        coff[e + 1] = coff[e] + (size_t)nstore * Es[e]->W * (lensk::kStride + 1);
+    // device: ensembles | hoff | Y | aux | pc | lnL | geoms | lstart | lout | counters | chains
     const size_t S = lensk::kStride;
     const size_t b_ens = align_up((size_t)n * sizeof(lensk::EnsembleDev), kAlign);
     const size_t b_hoff = align_up((size_t)(n + 1) * 8, kAlign);
@@ -2137,7 +2144,8 @@ lens_status ensemble_run_many(lens_ctx *c, const std::vector<Ensemble *> &Es, in
     const size_t b_geom = align_up(bg.geom.size() * sizeof(LensGeom), kAlign);
     const size_t b_ls = align_up(bg.lstart.size() * 4, kAlign), b_lo = align_up(bg.lout.size() * 8, kAlign);
     const size_t b_cnt = align_up(bg.gs.size() * 4 + 4, kAlign);
-    const size_t bytes = b_ens + b_hoff + b_Y + b_aux + b_pc + b_out + b_geom + b_ls + b_lo + b_cnt;
+    const size_t b_chain = align_up(coff[n] * 8, kAlign);
+    const size_t bytes = b_ens + b_hoff + b_Y + b_aux + b_pc + b_out + b_geom + b_ls + b_lo + b_cnt + b_chain;
     if (!charge(c, (int64_t)bytes)) return fail(c, LENS_ENOMEM, "HBM budget exhausted (multi-ensemble step)");
     void *dev = dev_alloc(c, bytes);
     if (!dev) {
@@ -2155,6 +2163,11 @@ lens_status ensemble_run_many(lens_ctx *c, const std::vector<Ensemble *> &Es, in
     auto *d_ls = (int *)(b += b_geom);
     auto *d_lo = (int64_t *)(b += b_ls);
     auto *d_cnt = (unsigned int *)(b += b_lo);
+    auto *d_chain = (double *)(b += b_cnt);
+    for (int e = 0; e < n; ++e) {
+        hens[e].chain_w = nstore > 0 ? d_chain + coff[e] : nullptr;
+        hens[e].chain_lnp = nstore > 0 ? d_chain + coff[e] + (size_t)nstore * Es[e]->W * S : nullptr;
+    }
     hipError_t e = hipMemcpyAsync(d_ens, hens.data(), (size_t)n * sizeof(lensk::EnsembleDev), hipMemcpyHostToDevice,
                                   c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d_hoff, hoff.data(), (size_t)(n + 1) * 8, hipMemcpyHostToDevice, c->stream);
@@ -2162,13 +2175,25 @@ lens_status ensemble_run_many(lens_ctx *c, const std::vector<Ensemble *> &Es, in
         e = hipMemcpyAsync(d_geom, bg.geom.data(), bg.geom.size() * sizeof(LensGeom), hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d_ls, bg.lstart.data(), bg.lstart.size() * 4, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(d_lo, bg.lout.data(), bg.lout.size() * 8, hipMemcpyHostToDevice, c->stream);
-    for (int64_t it = 0; it < iterations && e == hipSuccess; ++it)
+    for (int64_t it = 0; it < iterations && e == hipSuccess; ++it) {
+        const bool keep = nstore > 0 && (it + 1) % thin == 0 && (it + 1) / thin <= nstore;
+        const int64_t slot = keep ? (it + 1) / thin - 1 : -1;
         for (int half = 0; half < 2 && e == hipSuccess; ++half) {
-            e = lensk::launch_stretch_many(half, it, d_ens, d_hoff, n, tot, d_Y, d_aux, d_pc, 0, nullptr, c->stream);
+            e = lensk::launch_stretch_many(half, it, d_ens, d_hoff, n, tot, d_Y, d_aux, d_pc, 0, nullptr, -1,
+                                           c->stream);
             if (e == hipSuccess) e = launch_groups(bg, c->stream, d_geom, d_ls, d_lo, d_pc, d_out, d_cnt);
             if (e == hipSuccess)
-                e = lensk::launch_stretch_many(half, it, d_ens, d_hoff, n, tot, d_Y, d_aux, d_pc, 1, d_out, c->stream);
+                e = lensk::launch_stretch_many(half, it, d_ens, d_hoff, n, tot, d_Y, d_aux, d_pc, 1, d_out, slot,
+                                               c->stream);
         }
+    }
+    for (int k = 0; k < n && e == hipSuccess && nstore > 0; ++k) {
+        const size_t rows = (size_t)nstore * Es[k]->W;
+        if (chains && chains[k])
+            e = hipMemcpyAsync(chains[k], d_chain + coff[k], rows * S * 8, hipMemcpyDeviceToHost, c->stream);
+        if (e == hipSuccess && chain_lnps && chain_lnps[k])
+            e = hipMemcpyAsync(chain_lnps[k], d_chain + coff[k] + rows * S, rows * 8, hipMemcpyDeviceToHost, c->stream);
+    }
     hipError_t es = hipStreamSynchronize(c->stream);
     if (e == hipSuccess) e = es;
     dev_free(c, dev);
@@ -2180,12 +2205,14 @@ lens_status ensemble_run_many(lens_ctx *c, const std::vector<Ensemble *> &Es, in
 
 }  // namespace
 
-extern "C" lens_status lens_ensemble_run_many(lens_ctx *c, int32_t n, const lens_ens *ids, int64_t iterations)
+extern "C" lens_status lens_ensemble_run_many(lens_ctx *c, int32_t n, const lens_ens *ids, int64_t iterations,
+                                              int32_t thin, double *const *chains, double *const *chain_lnps)
 {
     lens_status st = check_ctx(c);
     if (st != LENS_OK) return st;
     if (n < 0 || (n > 0 && !ids)) return fail(c, LENS_EINVAL, "bad ensemble list");
     if (iterations < 0) return fail(c, LENS_EINVAL, "iterations must be >= 0");
+    if ((chains || chain_lnps) && thin < 1) return fail(c, LENS_EINVAL, "thin must be >= 1 when chains are requested");
     std::vector<lens_ens> sorted(ids, ids + n);
     std::sort(sorted.begin(), sorted.end());
     if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
@@ -2209,7 +2236,7 @@ extern "C" lens_status lens_ensemble_run_many(lens_ctx *c, int32_t n, const lens
         for (Ensemble *E : byid) locks.emplace_back(E->mu);
         if (n > 0 && iterations > 0) {
             DeviceGuard dg(c->device);
-            rs = ensemble_run_many(c, Es, iterations);
+            rs = ensemble_run_many(c, Es, iterations, thin, chains, chain_lnps);
         }
     }
     for (Ensemble *E : Es) ensemble_done(c, E);

@@ -166,14 +166,17 @@ k_stretch_propose_many(const EnsembleDev *__restrict__ ens, const int64_t *__res
 
 __global__ void __launch_bounds__(256)
 k_stretch_accept_many(const EnsembleDev *__restrict__ ens, const int64_t *__restrict__ hoff, int n, int half,
-                      const double *__restrict__ Y, const double4 *__restrict__ aux, const double *__restrict__ lnl)
+                      const double *__restrict__ Y, const double4 *__restrict__ aux, const double *__restrict__ lnl,
+                      int64_t slot)
 {
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= hoff[n]) return;
     const EnsembleDev &E = ens[ensemble_of(hoff, n, g)];
     const int i = (int)(g - E.off);
+    const bool keep = slot >= 0 && E.chain_w;
     stretch_accept_one(E.W, half, i, E.d, E.walkers, E.lnp, Y + (size_t)g * kStride, aux[g], lnl[g], E.accepted,
-                       nullptr, nullptr);
+                       keep ? E.chain_w + (size_t)slot * E.W * kStride : nullptr,
+                       keep ? E.chain_lnp + (size_t)slot * E.W : nullptr);
 }
 
 hipError_t launch_philox_words(const uint32_t ctr[4], const uint32_t key[2], int64_t n, uint32_t *d_out,
@@ -200,7 +203,7 @@ hipError_t launch_stretch_propose(int W, int half, uint64_t t, uint64_t seed, do
 
 hipError_t launch_stretch_many(int half, int64_t it, const EnsembleDev *d_ens, const int64_t *d_hoff, int n,
                                int64_t total, double *d_Y, double *d_aux, PropBlock *d_pc, int stage, const double *d_lnl,
-                               hipStream_t st)
+                               int64_t slot, hipStream_t st)
 {
     if (total <= 0) return hipSuccess;
     if (stage == 0) {
@@ -210,7 +213,7 @@ hipError_t launch_stretch_many(int half, int64_t it, const EnsembleDev *d_ens, c
     } else {
         const int bs = 256;
         hipLaunchKernelGGL(k_stretch_accept_many, dim3((unsigned)((total + bs - 1) / bs)), dim3(bs), 0, st, d_ens,
-                           d_hoff, n, half, d_Y, reinterpret_cast<const double4 *>(d_aux), d_lnl);
+                           d_hoff, n, half, d_Y, reinterpret_cast<const double4 *>(d_aux), d_lnl, slot);
     }
     return hipGetLastError();
 }

@@ -250,7 +250,10 @@ int main()
         std::vector<double> chain((size_t)3 * W * 20), chain_lnp((size_t)3 * W);
         CK(lens_ensemble_run(c, e1, 6, 2, chain.data(), chain_lnp.data()));
         const lens_ens both[2] = {e2, e3};
-        CK(lens_ensemble_run_many(c, 2, both, 3));
+        std::vector<double> pc2((size_t)W * 20), pc3((size_t)W * 20), pl2(W), pl3(W);
+        double *const cws[2] = {pc2.data(), pc3.data()};
+        double *const cls[2] = {pl2.data(), nullptr};   // a null entry skips that ensemble
+        CK(lens_ensemble_run_many(c, 2, both, 3, 3, cws, cls));
         std::vector<double> w((size_t)W * 20), lnp(W);
         std::vector<int64_t> acc(W);
         int64_t it = 0;
@@ -258,7 +261,8 @@ int main()
         TRUE(it == 3);
         EXPECT(lens_unload(c, A), LENS_EBUSY);
         const lens_ens dup[2] = {e1, e1};
-        EXPECT(lens_ensemble_run_many(c, 2, dup, 1), LENS_EINVAL);
+        EXPECT(lens_ensemble_run_many(c, 2, dup, 1, 0, nullptr, nullptr), LENS_EINVAL);
+        EXPECT(lens_ensemble_run_many(c, 2, both, 1, 0, cws, nullptr), LENS_EINVAL);   // thin < 1 with a chain
         for (lens_ens e : {e1, e2, e3}) CK(lens_ensemble_destroy(c, e));
         EXPECT(lens_ensemble_destroy(c, e1), LENS_ENOENT);
         uint32_t ctr[4] = {0, 0, 0, 0}, key[2] = {1, 2}, words[40];

@@ -272,6 +272,11 @@ def test_ensemble_run_many_equals_separate_runs(ctx):
             a, b = ctx.ensemble_get(p), ctx.ensemble_get(s)
             assert all(np.array_equal(x, y) for x, y in zip(a[:3], b[:3])) and a[3] == b[3], label
     assert sum(int(ctx.ensemble_get(p)[2].sum()) for p in pooled) > 50
+    # chains: every second iteration of a 4-iteration call, per ensemble
+    pc = ctx.ensemble_run_many(pooled, 4, thin=2, chain=True)
+    for (label, *_), (cw, cl), s_ in zip(cases, pc, single):
+        sw, sl = ctx.ensemble_run(s_, 4, thin=2, chain=True)
+        assert cw.shape == sw.shape and np.array_equal(cw, sw) and np.array_equal(cl, sl), label
     # one pooled iteration of the first member against the oracle
     label, spec, kw, W, lo, hi = cases[0]
     before, lb, _, t = ctx.ensemble_get(pooled[0])
@@ -303,6 +308,15 @@ def test_ensemble_run_many_errors(ctx):
     with pytest.raises(binding.LensError) as ei:
         ctx.ensemble_run_many([e1], -1)
     assert ei.value.status == binding.LENS_EINVAL
+    # a chain with thin < 1
+    import ctypes
+    dp = ctypes.POINTER(ctypes.c_double)
+    buf = np.empty((2, 8, 20))
+    arr = (dp * 1)(buf.ctypes.data_as(dp))
+    ids = np.array([e1], dtype=np.int64)
+    st = binding.load().lens_ensemble_run_many(ctx.ctx, 1, ids.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), 2, 0,
+                                                arr, None)
+    assert st == binding.LENS_EINVAL
     # nothing moved
     assert ctx.ensemble_get(e1)[3] == 0 and np.array_equal(ctx.ensemble_get(e1)[0], init)
     ctx.ensemble_run_many([e2, e1], 2)
