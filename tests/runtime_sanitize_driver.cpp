@@ -9,10 +9,12 @@
 // domain); their accuracy is the parity tests' business.
 #include <hip/hip_runtime_api.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <thread>
 #include <vector>
 
 #include "lens_api.h"
@@ -295,6 +297,76 @@ int main()
         EXPECT(lens_load_data(c, &bad, &x), LENS_EINVAL);
         EXPECT(lens_wait(c, 987654, 0), LENS_ENOENT);
         TRUE(lens_last_error(c) != nullptr);
+    }
+
+    // three threads on the context at once: blocking and multi-lens calls,
+    // serving with cancellations, ensembles created, run and destroyed
+    {
+        std::vector<double> Pa = proposals(700, false, 9), Pd = proposals(500, true, 9);
+        std::vector<double> refA(700), refD(500);
+        CK(lens_loglike_batch(c, A, Pa.data(), 700, refA.data()));
+        CK(lens_loglike_batch(c, D, Pd.data(), 500, refD.data()));
+        std::atomic<int> bad{0};
+        auto blocking = [&]() {
+            std::vector<double> o(700), m(1200);
+            const lens_id ids[2] = {A, D};
+            const int64_t cnt[2] = {700, 500};
+            std::vector<double> pm(Pa);
+            pm.insert(pm.end(), Pd.begin(), Pd.end());
+            for (int r = 0; r < 8; ++r) {
+                if (lens_loglike_batch(c, A, Pa.data(), 700, o.data()) != LENS_OK || !same_bits(refA, o.data(), 700))
+                    bad++;
+                if (lens_loglike_multi(c, 2, ids, cnt, pm.data(), m.data()) != LENS_OK ||
+                    !same_bits(refA, m.data(), 700) || !same_bits(refD, m.data() + 700, 500))
+                    bad++;
+            }
+        };
+        auto serving = [&]() {
+            for (int r = 0; r < 8; ++r) {
+                std::vector<double> o1(700), o2(500);
+                lens_req q1 = 0, q2 = 0;
+                if (lens_submit(c, A, Pa.data(), 700, o1.data(), &q1) != LENS_OK) bad++;
+                if (lens_submit(c, D, Pd.data(), 500, o2.data(), &q2) != LENS_OK) bad++;
+                if (r % 3 == 0) {
+                    if (lens_cancel(c, q2) != LENS_OK) bad++;
+                } else if (lens_wait(c, q2, -1) != LENS_OK || !same_bits(refD, o2.data(), 500)) {
+                    bad++;
+                }
+                if (lens_wait(c, q1, -1) != LENS_OK || !same_bits(refA, o1.data(), 700)) bad++;
+            }
+        };
+        auto sampling = [&]() {
+            double lo[20], hi[20];
+            for (int s = 0; s < 19; ++s) {
+                lo[s] = kLo[s];
+                hi[s] = kHi[s];
+            }
+            lo[19] = hi[19] = 0.0;
+            std::vector<double> init = proposals(8, false, 0);
+            lens_ensemble_desc ed;
+            memset(&ed, 0, sizeof(ed));
+            ed.walkers = 8;
+            ed.stretch = 2.0;
+            ed.seed = 3;
+            ed.lo = lo;
+            ed.hi = hi;
+            ed.init = init.data();
+            for (int r = 0; r < 4; ++r) {
+                lens_ens e = 0;
+                if (lens_ensemble_create(c, B, &ed, &e) != LENS_OK) {
+                    bad++;
+                    continue;
+                }
+                if (lens_ensemble_run(c, e, 3, 0, nullptr, nullptr) != LENS_OK) bad++;
+                if (lens_ensemble_run_many(c, 1, &e, 2, 0, nullptr, nullptr) != LENS_OK) bad++;
+                if (lens_ensemble_destroy(c, e) != LENS_OK) bad++;
+            }
+        };
+        std::thread t1(blocking), t2(serving), t3(sampling);
+        t1.join();
+        t2.join();
+        t3.join();
+        TRUE(bad.load() == 0);
     }
 
     for (lens_id id : {A, B, Cn, D, E}) CK(lens_unload(c, id));
