@@ -608,7 +608,9 @@ def run_precision(args):
         step_s = (time.perf_counter() - t0) / args.steps
         gpu_ms = a.elapsed_time(b) / args.steps
         errs = np.concatenate([rel_errors(outs[j][:2], r[0], r[1], r[2]) for j, r in zip(sample_idx, res)])
-        per[m] = {"evals_per_s": n / step_s, "ms_per_step": step_s * 1e3, "max_rel_err": float(errs.max()),
+        inf = ctx.info(lids[0])
+        per[m] = {"tile": [inf["strip_rows"], inf["threads"], inf["blocks_per_cu"], inf["lds_bytes"]],
+                  "evals_per_s": n / step_s, "ms_per_step": step_s * 1e3, "max_rel_err": float(errs.max()),
                   "p99_rel_err": float(np.quantile(errs, 0.99)),
                   "frac_credited_alu": slots / (gpu_ms * 1e-3) / PEAK_SLOT_PER_S}
         for l in lids:

@@ -108,6 +108,9 @@ struct LensGeom {
     int L;                 // MFMA: window length per segment, 16 + k - 1 rounded up to 8
     int nchunks;           // MFMA: K-chunks of 32, ceil(k L / 32)
     int nstrips;           // ceil(ny / strip_h)
+    int xoff;              // ring column of image column x is x + r - xoff (a multiple of 16 at or left of
+                           // every masked column: the ring spans only the columns the convolution reads)
+    int span;              // columns from xoff to the right edge of the mask (ring width less the PSF window)
     double sd;             // pixel_scale / s: sub-pixel pitch
     double cfx, cfy;       // (nx*s - 1)/2, (ny*s - 1)/2: fine-grid centre
     float inv_s2;          // 1/s^2
@@ -131,9 +134,10 @@ struct LensGeom {
 size_t ring_bytes(const LensGeom &g);
 double host_sersic_bn(double n);   // b_n of Eq. 9 by FP64 Newton iteration, on the host
 int choose_kc(int k);
-// LDS row width (elements) and bytes per ring row for a mode, PSF side and width
-int ring_width(int mode, int k, int nx);
-size_t ring_row_bytes(int mode, int k, int nx);
+// LDS row width (elements) and bytes per ring row for a mode, PSF side and
+// span (LensGeom::span: the masked columns from xoff on)
+int ring_width(int mode, int k, int span);
+size_t ring_row_bytes(int mode, int k, int span);
 // largest dynamic LDS one workgroup may use on this device
 size_t max_lds_bytes();
 size_t set_lds_limits(size_t bytes);   // dynamic LDS now accepted by every ring kernel; 0 on refusal

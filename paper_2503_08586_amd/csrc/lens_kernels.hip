@@ -141,21 +141,23 @@ template <int MODE> struct RingStoreM : RingStore<mode_base(MODE)> {};
 
 // Binned rows [ya, yb) (all < ny) into their ring slots: every pixel in the
 // row's needed range is evaluated; the rest of the row is cleared when the
-// slot is being reused (clear = true).  Ring column of image column x is x + r.
+// slot is being reused (clear = true).  Ring column of image column x is
+// x + r - xoff; columns outside the image are never written and stay zero.
 template <int MODE, int NT>
 __device__ __forceinline__ void fill_rows(const LensGeom &g, const PropBlock &P, void *ring,
                                           const uint32_t *__restrict__ evl, const int *__restrict__ evpre,
                                           const int2 *__restrict__ evr, int ya, int yb, bool clear)
 {
-    const int W = g.ring_w, RB = g.ring_rows, r = g.r, nx = g.nx;
+    const int W = g.ring_w, RB = g.ring_rows, r = g.r, c0 = r - g.xoff;
     const int slot_a = (ya + r) % RB;  // rows [ya, yb) occupy consecutive slots modulo RB
     if (clear) {
+        const int xa = max(0, -c0), xb = min(g.nx, W - c0);   // image columns that have ring columns
         for (int y = ya; y < yb; ++y) {
             int slot = slot_a + (y - ya);
             if (slot >= RB) slot -= RB;
             const int2 lr = evr[y];
-            for (int x = threadIdx.x; x < nx; x += NT)
-                if (x < lr.x || x >= lr.y) RingStoreM<MODE>::zero(ring, g.plane, slot * W + r + x);
+            for (int x = xa + threadIdx.x; x < xb; x += NT)
+                if (x < lr.x || x >= lr.y) RingStoreM<MODE>::zero(ring, g.plane, slot * W + c0 + x);
         }
     }
     const int fb = evpre[yb];
@@ -168,9 +170,9 @@ __device__ __forceinline__ void fill_rows(const LensGeom &g, const PropBlock &P,
             constexpr int NCH = mode_channels(MODE);
             float ch[NCH];
             binned_pixel_channels<mode_light(MODE), mode_epl(MODE)>(g, P, y, x, ch);
-            RingStoreM<MODE>::put(ring, g.plane, slot * W + r + x, FVec<NCH>::make(ch));
+            RingStoreM<MODE>::put(ring, g.plane, slot * W + c0 + x, FVec<NCH>::make(ch));
         } else
-            RingStoreM<MODE>::put(ring, g.plane, slot * W + r + x, binned_pixel<mode_epl(MODE)>(g, P, y, x));
+            RingStoreM<MODE>::put(ring, g.plane, slot * W + c0 + x, binned_pixel<mode_epl(MODE)>(g, P, y, x));
     }
 }
 
@@ -197,9 +199,11 @@ __device__ __forceinline__ Acc strip_sweep(const LensGeom &g, const PropBlock &P
         __syncthreads();  // the previous strip is done reading the slots reused below
         const int ya = y0 + r, yb = y0 + H + r;  // new binned rows
         if (y0 > 0) {
+            const int c0 = r - g.xoff, xa = max(0, -c0), xb = min(g.nx, g.ring_w - c0);
             for (int y = max(ya, ny); y < yb; ++y) {  // rows past the image: clear reused slots
                 const int slot = (y + r) % RB;
-                for (int x = threadIdx.x; x < g.nx; x += NT) RingStoreM<MODE>::zero(ring, g.plane, slot * g.ring_w + r + x);
+                for (int x = xa + threadIdx.x; x < xb; x += NT)
+                    RingStoreM<MODE>::zero(ring, g.plane, slot * g.ring_w + c0 + x);
             }
         }
         if (ya < ny) fill_rows<MODE, NT>(g, P, ring, evl, evpre, evr, ya, min(yb, ny), y0 > 0);
@@ -405,7 +409,7 @@ __device__ __forceinline__ double conv_rows(const LensGeom &g, const float *ring
         int slot = y % RB;  // ring slot of binned row y - r
 #pragma unroll 1
         for (int a = 0; a < K; ++a) {
-            const float4 *rowp = reinterpret_cast<const float4 *>(ring + slot * W + x0);
+            const float4 *rowp = reinterpret_cast<const float4 *>(ring + slot * W + x0 - g.xoff);
             float win[4 * KC];
 #pragma unroll
             for (int i = 0; i < KC; ++i) {
@@ -494,6 +498,13 @@ __device__ __forceinline__ f32x4 mfma_products(const bf16x8 (&a)[3], const bf16x
     return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[0], c, 0, 0, 0);
 }
 
+// The FP32 accumulator of the contraction is added into FP64 sums every
+// kFlushChunks K-chunks: summed over all k L products in FP32, an output
+// collects a rounding error at every accumulate step relative to its whole
+// running sum, which reached ~5e-7 of the lnL error metric on the 200x200 /
+// 41x41 workload; flushed, each FP32 partial is a short sum.
+constexpr int kFlushChunks = 2;
+
 template <int MODE, int NT>
 __device__ __forceinline__ double conv_mfma(const LensGeom &g, const uint16_t *ring,
                                             const uint4 *__restrict__ aop, const uint32_t *__restrict__ seg,
@@ -509,7 +520,7 @@ __device__ __forceinline__ double conv_mfma(const LensGeom &g, const uint16_t *r
     for (int t = s0 + 16 * wave; t < s1; t += 16 * (NT / 64)) {
         // a tile of 16 segments; lanes past the strip's last segment compute a discarded column
         const bool dummy = t + n >= s1;
-        const uint32_t e = dummy ? 0u : seg[t + n];
+        const uint32_t e = dummy ? seg[s0] : seg[t + n];
         const int y = (int)(e >> 16), x0 = (int)(e & 0xffffu);
         int slot = y % RB;           // ring slot of binned row y - r + a, a = 0
         int i = 8 * kb;              // window offset of this lane's K elements, K = 8 kb
@@ -517,32 +528,41 @@ __device__ __forceinline__ double conv_mfma(const LensGeom &g, const uint16_t *r
             i -= L;
             slot = slot + 1 == RB ? 0 : slot + 1;
         }
-        f32x4 c = {0.f, 0.f, 0.f, 0.f};
+        const uint16_t *rb = ring + (x0 - g.xoff);
+        double o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;   // outputs 4 kb .. 4 kb + 3 of column n, FP64
         const uint4 *ap = aop + lane;
-        for (int ch = 0; ch < nch; ++ch) {
-            bf16x8 av[3], bv[3];
-            const uint16_t *bp = ring + slot * W + x0 + i;
+        for (int ch0 = 0; ch0 < nch; ch0 += kFlushChunks) {
+            f32x4 c = {0.f, 0.f, 0.f, 0.f};
+            const int ch1 = min(ch0 + kFlushChunks, nch);
+            for (int ch = ch0; ch < ch1; ++ch) {
+                bf16x8 av[3], bv[3];
+                const uint16_t *bp = rb + slot * W + i;
 #pragma unroll
-            for (int q = 0; q < NPL; ++q) {
-                av[q] = __builtin_bit_cast(bf16x8, ap[q * 64]);
-                bv[q] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(bp + q * plane));
+                for (int q = 0; q < NPL; ++q) {
+                    av[q] = __builtin_bit_cast(bf16x8, ap[q * 64]);
+                    bv[q] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(bp + q * plane));
+                }
+                c = mfma_products<MODE>(av, bv, c);
+                ap += NPL * 64;
+                i += 32;
+                while (i >= L) {
+                    i -= L;
+                    slot = slot + 1 == RB ? 0 : slot + 1;
+                }
             }
-            c = mfma_products<MODE>(av, bv, c);
-            ap += NPL * 64;
-            i += 32;
-            while (i >= L) {
-                i -= L;
-                slot = slot + 1 == RB ? 0 : slot + 1;
-            }
+            o0 += (double)c[0];
+            o1 += (double)c[1];
+            o2 += (double)c[2];
+            o3 += (double)c[3];
         }
         if (!dummy) {
             const int xo = x0 + 4 * kb;
             const float4 d = *reinterpret_cast<const float4 *>(data + (size_t)y * g.pitch + xo);
             const float4 w = *reinterpret_cast<const float4 *>(wgt + (size_t)y * g.pitch + xo);
-            const double r0 = (double)((d.x - c[0]) * w.x);
-            const double r1 = (double)((d.y - c[1]) * w.y);
-            const double r2 = (double)((d.z - c[2]) * w.z);
-            const double r3 = (double)((d.w - c[3]) * w.w);
+            const double r0 = ((double)d.x - o0) * (double)w.x;
+            const double r1 = ((double)d.y - o1) * (double)w.y;
+            const double r2 = ((double)d.z - o2) * (double)w.z;
+            const double r3 = ((double)d.w - o3) * (double)w.w;
             acc = fma(r0, r0, acc);
             acc = fma(r1, r1, acc);
             acc = fma(r2, r2, acc);
@@ -595,7 +615,7 @@ __device__ __forceinline__ double conv_rows_rt(const LensGeom &g, const float *r
         double o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;   // sum over PSF rows in FP64
         int slot = y % RB;
         for (int a = 0; a < k; ++a) {
-            const float *row = ring + slot * W + x0;
+            const float *row = ring + slot * W + x0 - g.xoff;
             const float *kr = psf + a * k;
             float p0 = 0.f, p1 = 0.f, p2 = 0.f, p3 = 0.f;
             float v0 = row[0], v1 = row[1], v2 = row[2];
@@ -661,7 +681,7 @@ __device__ __forceinline__ MomN<mode_channels(MODE)> conv_rows_solved(const Lens
         for (int pass = 0; pass < NPASS; ++pass) {
             int slot = y % RB;
             for (int a = 0; a < k; ++a) {
-                const typename V::T *row = ringp + (size_t)(slot * W + x0) * NPASS + pass;
+                const typename V::T *row = ringp + (size_t)(slot * W + x0 - g.xoff) * NPASS + pass;
                 const float *kr = psf + a * k;
                 float pp[4][CP] = {};
                 typename V::T v0 = row[0], v1 = row[NPASS], v2 = row[2 * NPASS];
@@ -899,22 +919,25 @@ int choose_kc(int k) { return (k + 6) / 4; }
 
 double host_sersic_bn(double n) { return sersic_bn(n); }
 
-int ring_width(int mode, int k, int nx)
+// Output groups (4 wide, FP32) and segments (16 wide, matrix cores) start at
+// multiples of 4 and 16 at or right of xoff, below xoff + span, and each reads
+// a window of 4 KC or L ring columns from its start.
+int ring_width(int mode, int k, int span)
 {
-    if (mode_base(mode) == MODE_FP32 || mode_solved(mode)) return (nx + 3) / 4 * 4 + 4 * choose_kc(k);
+    if (mode_base(mode) == MODE_FP32 || mode_solved(mode)) return (span + 3) / 4 * 4 + 4 * choose_kc(k);
     const int L = (16 + k - 1 + 7) / 8 * 8;
-    return (nx + 15) / 16 * 16 + L;
+    return (span + 15) / 16 * 16 + L;
 }
 
-size_t ring_row_bytes(int mode, int k, int nx)
+size_t ring_row_bytes(int mode, int k, int span)
 {
     const size_t elem = mode_base(mode) == MODE_FP32 ? 4
                         : mode_solved(mode)          ? 4 * mode_channels(mode)
                                                      : 2 * mode_planes(mode);
-    return (size_t)ring_width(mode, k, nx) * elem;
+    return (size_t)ring_width(mode, k, span) * elem;
 }
 
-size_t ring_bytes(const LensGeom &g) { return (size_t)g.ring_rows * ring_row_bytes(g.mode, g.k, g.nx); }
+size_t ring_bytes(const LensGeom &g) { return (size_t)g.ring_rows * ring_row_bytes(g.mode, g.k, g.span); }
 
 // Dynamic LDS one workgroup may use: the opt-in limit when the device reports
 // one above the default per-block limit (gfx950 addresses all 160 KB of a CU

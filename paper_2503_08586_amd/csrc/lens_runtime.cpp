@@ -149,7 +149,7 @@ struct Plan {
     uint64_t used = 0;
 };
 
-// round-to-nearest-even FP32 -> BF16 and the plane split v = p0 + p1 (+ p2)
+// round-to-nearest-even FP32 -> BF16 and back
 uint16_t bf16_rn_host(float f)
 {
     uint32_t u;
@@ -166,12 +166,66 @@ float bf16_to_float(uint16_t h)
     return f;
 }
 
-void split_bf16(float v, int npl, uint16_t *out)
+// The flipped PSF Kf[a][b] = K[k-1-a][k-1-b] as npl BF16 planes per tap
+// ([k*k][npl]), each plane the nearest BF16 to what the earlier ones leave of
+// the FP32 tap, except that the last plane of some taps is rounded to its
+// other neighbour so that the planes sum, over the whole kernel, to the FP64
+// sum of K.  The kernel's rounding would otherwise scale every model pixel by
+// a common factor 1 + sum(K - planes)/sum(K), off by up to ~2^-17 for two
+// planes, an error that the chi-square does not average away.  Taps are
+// flipped in the order of the least added error, each only when that brings
+// the residual sum closer to zero; no tap's error exceeds one unit of its last
+// plane.
+std::vector<uint16_t> split_psf_planes(const double *psf, int k, int npl)
 {
-    for (int q = 0; q < npl; ++q) {
-        out[q] = bf16_rn_host(v);
-        v -= bf16_to_float(out[q]);
+    const int n = k * k;
+    std::vector<uint16_t> out((size_t)n * npl);
+    std::vector<double> e(n), ealt(n);
+    std::vector<uint16_t> alt(n);
+    double E = 0.0;
+    for (int t = 0; t < n; ++t) {
+        const int a = t / k, b = t % k;
+        const double K = psf[(size_t)(k - 1 - a) * k + (k - 1 - b)];
+        float v = (float)K;
+        double sum = 0.0;
+        for (int q = 0; q < npl; ++q) {
+            const uint16_t h = bf16_rn_host(v);
+            out[(size_t)t * npl + q] = h;
+            if (q + 1 < npl) v -= bf16_to_float(h);   // exact: v and its nearest BF16 share the leading bits
+            sum += (double)bf16_to_float(h);
+        }
+        e[t] = K - sum;
+        E += e[t];
+        // the other BF16 neighbour of the last plane's target v
+        const uint16_t h = out[(size_t)t * npl + npl - 1];
+        const float fh = bf16_to_float(h);
+        alt[t] = h;
+        ealt[t] = e[t];
+        if (v != 0.0f && fh != 0.0f && std::isfinite(fh) && fh != v) {
+            // one BF16 unit towards v: +1 in the magnitude bits moves away from 0
+            const bool up_mag = std::fabs(v) > std::fabs(fh);
+            const uint16_t o = up_mag ? (uint16_t)(h + 1) : (uint16_t)(h - 1);
+            const float fo = bf16_to_float(o);
+            if (std::isfinite(fo) && (fo > 0.0f) == (fh > 0.0f)) {
+                alt[t] = o;
+                ealt[t] = e[t] + (double)fh - (double)fo;
+            }
+        }
     }
+    std::vector<int> order(n);
+    for (int t = 0; t < n; ++t) order[t] = t;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return std::fabs(ealt[x]) - std::fabs(e[x]) < std::fabs(ealt[y]) - std::fabs(e[y]);
+    });
+    for (int t : order) {
+        if (alt[t] == out[(size_t)t * npl + npl - 1]) continue;
+        const double E2 = E - e[t] + ealt[t];
+        if (std::fabs(E2) < std::fabs(E)) {
+            out[(size_t)t * npl + npl - 1] = alt[t];
+            E = E2;
+        }
+    }
+    return out;
 }
 
 // Strip height H and workgroup size of one lens: the LDS ring holds H + k - 1
@@ -180,7 +234,7 @@ bool set_tiles(LensGeom &g, int H, int nt, size_t lds_max)
 {
     if (H < 1) return false;
     H = std::min(H, g.ny);
-    const size_t bytes = (size_t)(H + 2 * g.r) * lensk::ring_row_bytes(g.mode, g.k, g.nx);
+    const size_t bytes = (size_t)(H + 2 * g.r) * lensk::ring_row_bytes(g.mode, g.k, g.span);
     if (bytes > lds_max) return false;
     g.nt = nt;
     g.strip_h = H;
@@ -199,7 +253,7 @@ bool set_tiles(LensGeom &g, int H, int nt, size_t lds_max)
 // - failing that, the tallest strip that fits one workgroup's LDS.
 int default_strip(const LensGeom &g, size_t lds_max, size_t lds_cu, int *nt)
 {
-    const size_t row_b = lensk::ring_row_bytes(g.mode, g.k, g.nx);
+    const size_t row_b = lensk::ring_row_bytes(g.mode, g.k, g.span);
     const auto ring = [&](int H) { return (size_t)(H + 2 * g.r) * row_b; };
     if (lensk::mode_base(g.mode) == lensk::MODE_FP32 && ring(std::min(16, g.ny)) <= std::min(lds_max, lds_cu / 4)) {
         *nt = 256;
@@ -853,7 +907,18 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     cvpre[ny] = (int)cvl.size();
     LensGeom g{};
     g.ny = ny; g.nx = nx; g.s = s; g.k = k; g.r = r; g.pitch = pitch; g.mode = mode;
-    g.ring_w = lensk::ring_width(mode, k, nx);
+    // the ring spans the masked columns [xoff, xoff + span) plus the PSF
+    // window: xoff is the leftmost masked column rounded down to 16, where
+    // every output group and segment starts at or after it
+    int mlo_all = INT_MAX, mhi_all = 0;
+    for (int y = 0; y < ny; ++y)
+        if (mhi[y] > mlo[y]) {
+            mlo_all = std::min(mlo_all, mlo[y]);
+            mhi_all = std::max(mhi_all, mhi[y]);
+        }
+    g.xoff = mlo_all == INT_MAX ? 0 : (mlo_all & ~15);
+    g.span = mlo_all == INT_MAX ? 1 : mhi_all - g.xoff;
+    g.ring_w = lensk::ring_width(mode, k, g.span);
     if (!set_tiles(g, default_strip(g, c->lds_max, c->lds_cu, &g.nt), g.nt, c->lds_max))
         return fail(c, LENS_EINVAL, "image too wide for the LDS line buffer at this PSF size");
     // MFMA operands: 16-wide output segments covering the mask (row-major, with
@@ -873,15 +938,15 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
         }
         segpre[ny] = (int)seg.size();
         const int npl = lensk::mode_planes(mode);
+        const std::vector<uint16_t> kpl = split_psf_planes(psf, k, npl);   // [tap of the flipped PSF][plane]
         aop.assign((size_t)g.nchunks * npl * 64 * 8, 0);
         for (int ch = 0; ch < g.nchunks; ++ch)
             for (int lane = 0; lane < 64; ++lane)
                 for (int e = 0; e < 8; ++e) {
                     const int K = 32 * ch + 8 * (lane >> 4) + e, a = K / g.L, i = K % g.L, b = i - (lane & 15);
-                    const float v = (a < k && b >= 0 && b < k) ? (float)psf[(size_t)(k - 1 - a) * k + (k - 1 - b)] : 0.0f;
-                    uint16_t pl[3];
-                    split_bf16(v, npl, pl);
-                    for (int q = 0; q < npl; ++q) aop[(((size_t)ch * npl + q) * 64 + lane) * 8 + e] = pl[q];
+                    if (!(a < k && b >= 0 && b < k)) continue;
+                    for (int q = 0; q < npl; ++q)
+                        aop[(((size_t)ch * npl + q) * 64 + lane) * 8 + e] = kpl[((size_t)a * k + b) * npl + q];
                 }
     }
     g.sd = d->pixel_scale / s;
