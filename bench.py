@@ -1,23 +1,30 @@
 #!/usr/bin/env python3
 """Throughput of the batched lens log-likelihood on one MI355X.
 
-Default workload (plain, survey scale): one step = one call of the whole hot
-path (prep + fused likelihood kernel) over one batch of proposals already
-resident in HBM: one lens of 128x128 pixels at 0.05"/px, 4x4 supersampling
-(262,144 ray-traced points per proposal), a 21x21 Gaussian PSF (FWHM 0.1"),
-a 3" circular mask, noise sigma 0.01, and 65,536 proposals per call drawn
-uniformly from the prior box.  Prints one JSON line.
+Default workload (batched, the largest single-GPU configuration): one step =
+one multi-lens call of the whole hot path over 64 lenses of 200x200 px at
+0.05"/px with 4x4 supersampling and a 41x41 Moffat PSF (beta 3, FWHM 0.15"),
+16,384 proposals per lens (1,048,576 per step) already resident in HBM: the
+prep step, then one persistent launch in which workgroups pull (lens,
+proposal) items, with the PSF convolution on the BF16 matrix cores in the
+three-plane split that meets the 1e-6 lnL gate and an FP64 chi-square.
+Beside it, in the same JSON line:
+- the plain path: the FP32 one-lens-per-call kernels over the same lenses
+  and proposals, device buffers;
+- the lnL error of both against the FP64 oracle on a seeded sample (max and
+  p99), and the oracle's own rate on that sample (all host cores and one);
+- a short serving leg: Poisson requests over 1,000 resident lenses of mixed
+  shape in the same precision, with p50/p99 latency at 80% of peak and a
+  sampled error;
+- the roofline of the persistent kernel with its vector-ALU and matrix-core
+  terms.
 
-The CPU-baseline leg times the FP64 oracle on a bounded sample of the same
-proposals on the host's cores and checks the GPU results of that sample
-against it.
-
---workload batch|precision|serving|sampler runs the other measurements (256
-uneven lenses in one persistent graph-captured launch vs one lens at a time;
-64 lenses of 200x200 px with a 41x41 Moffat PSF per convolution precision; a
-Poisson request stream over 1,000 resident lenses with p50/p99 latency; a
-stretch-move ensemble that proposes, evaluates and accepts on the device vs
-the same moves driven from the host).
+--workload plain|batch|precision|serving|sampler|sampler_many runs the
+other measurements (one survey-scale lens with 65,536 proposals per call;
+256 uneven lenses in one persistent graph-captured launch vs one lens at a
+time; the 64 precision lenses in every convolution mode; the serving sweep
+over offered loads; a stretch-move ensemble on the device vs driven from the
+host; many pooled ensembles).
 """
 from __future__ import annotations
 
@@ -35,7 +42,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "loglike evals/s at ≤1e-6 rel err, batched vs plain; p50/p99 req latency"
 PEAK_SLOT_PER_S = 256 * 4 * 16 * 2.4e9        # FP32 VALU lane-slots/s (non-packed)
+PEAK_BF16_FLOP_S = 2.5e15                       # dense BF16 matrix-core peak
 SLOTS_PER_EVAL = 60 + 4 * 10                    # 60 FMA-class ops + 10 quarter-rate transcendentals
+PRODUCTS = {1: 3, 2: 1, 3: 6}                   # BF16 products per PSF tap: split, bf16, split3
 DOUBLE_N = (1.0, 4.0, 1.0, 4.0)                 # fixed indices of the two-component model: disc and bulge
 
 
@@ -46,11 +55,18 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nprop", type=int, default=65536)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="batched: skip the serving leg")
+    ap.add_argument("--no-plain", action="store_true", help="batched: skip the plain one-lens-per-call leg")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target wall time of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (for HBM counter calibration)")
-    ap.add_argument("--workload", default="plain", choices=["plain", "batch", "precision", "serving", "sampler",
-                                                             "sampler_many"])
+    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "batch", "precision", "serving",
+                                                               "sampler", "sampler_many"])
+    ap.add_argument("--sample-per-lens", type=int, default=16,
+                    help="batched: proposals per sampled lens checked against the oracle (and timing its CPU rate)")
+    ap.add_argument("--sample-lenses", type=int, default=16,
+                    help="batched: lenses sampled (evenly spaced) for the oracle check")
+    ap.add_argument("--serve-requests", type=int, default=240, help="batched: requests of the serving leg")
     ap.add_argument("--walkers", type=int, default=16384, help="sampler: ensemble size")
     ap.add_argument("--lenses", type=int, default=256, help="sampler_many: lenses, one ensemble each")
     ap.add_argument("--walkers-per-lens", type=int, default=64, help="sampler_many: walkers per ensemble")
@@ -92,20 +108,40 @@ def path_dtype(prec):
     return "f64+f32" if prec in (None, "fp32") else "f64+bf16"
 
 
-def credited_slots(spec, info, nnls=False, model=0):
+def credited_slots(spec, info, nnls=False, model=0, prec=0):
     """Credited VALU work of one proposal (60 FMA-class + 10 transcendentals per sub-pixel
     evaluation, one FMA per PSF tap at each masked pixel, one FP64 FMA per masked pixel).
     The PSF is the kernel the library convolves with after its tail crop (info["psf_used"]),
     and the sub-pixels are those of the mask dilated by that kernel (info["needed_pixels"]).
     Solved amplitudes (nnls) convolve one channel per light component (N) and take
     N(N+1)/2 + N FP64 moments per masked pixel; the per-evaluation credit follows the
-    light model (SLOTS_BY_MODEL)."""
+    light model (SLOTS_BY_MODEL).  In the matrix-core precisions (prec 1-3) the PSF taps
+    run on the BF16 MFMA and are credited there (conv_flops), not to the vector ALU."""
     M, k = info["masked_pixels"], info["psf_used"]
     E = info["needed_pixels"] * spec.s * spec.s
     if nnls:
         N = CHANNELS[model]
         return E * SLOTS_BY_MODEL[model] + N * M * k * k + (N * (N + 1) // 2 + N) * M, E
+    if prec in PRODUCTS:
+        return E * SLOTS_PER_EVAL + M, E
     return E * SLOTS_PER_EVAL + M * k * k + M, E
+
+
+def conv_flops(info):
+    """Algorithmic PSF-convolution flops of one proposal: 2 M k^2 (the band padding of
+    the Toeplitz operand is not credited)."""
+    return 2.0 * info["masked_pixels"] * info["psf_used"] ** 2
+
+
+def roofline_terms(slots, flops, prec, seconds):
+    """T_valu = credited slots / VALU peak; T_mfma = credited convolution flops times the
+    products per tap / dense BF16 peak (matrix-core precisions only); the fraction is
+    max(T_valu, T_mfma) / measured time."""
+    t_valu = slots / PEAK_SLOT_PER_S
+    t_mfma = flops * PRODUCTS[prec] / PEAK_BF16_FLOP_S if prec in PRODUCTS else 0.0
+    return {"t_valu_s": t_valu, "t_mfma_s": t_mfma, "t_measured_s": seconds,
+            "frac": max(t_valu, t_mfma) / seconds,
+            "bound": "alu" if t_valu >= t_mfma else "mfma"}
 
 
 def epl_terms(P):
@@ -152,14 +188,15 @@ def rel_errors(gpu, ref, chi2, C):
     return np.abs(gpu - ref) / (0.5 * chi2 + abs(C))
 
 
-def measured_traffic(prec):
-    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE/WRITE_SIZE record, or None
-    when there is none or the kernel sources have changed since it was taken."""
-    if prec != 0:
-        return None
+def measured_traffic(workload):
+    """HBM bytes per launch of the workload's dominant kernel from its committed rocprofv3
+    FETCH_SIZE/WRITE_SIZE record, or None when there is none or the kernel sources have
+    changed since it was taken."""
     from paper_2503_08586_amd import profiling
+    if workload not in profiling.RECORDS:
+        return None
     try:
-        with open(profiling.RECORD) as f:
+        with open(profiling.record_path(workload)) as f:
             rec = json.load(f)
         if rec.get("kernel_src_sha256") != profiling.kernel_hash():
             return None
@@ -178,16 +215,6 @@ def main():
 
     from paper_2503_08586_amd import binding, synth
 
-    if args.workload == "batch":
-        return run_batch(args)
-    if args.workload == "precision":
-        return run_precision(args)
-    if args.workload == "serving":
-        return run_serving(args)
-    if args.workload == "sampler":
-        return run_sampler(args)
-    if args.workload == "sampler_many":
-        return run_sampler_many(args)
     if args.copy_calibration:
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
         y = torch.empty_like(x)
@@ -198,6 +225,18 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "copies": 3}))
         return
+    if args.workload == "batched":
+        return run_batched(args)
+    if args.workload == "batch":
+        return run_batch(args)
+    if args.workload == "precision":
+        return run_precision(args)
+    if args.workload == "serving":
+        return run_serving(args)
+    if args.workload == "sampler":
+        return run_sampler(args)
+    if args.workload == "sampler_many":
+        return run_sampler_many(args)
 
     spec = synth.config2(nprop=args.nprop)[0]
     n = spec.proposals.shape[0]
@@ -251,16 +290,17 @@ def main():
     assert np.array_equal(host_out, gpu_out)
 
     # roofline: credited algorithmic VALU work of one launch
-    slots_per_prop, E = credited_slots(spec, info, nnls, model)
+    slots_per_prop, E = credited_slots(spec, info, nnls, model, prec)
     if epl:   # the series' extra complex Horner steps, 4 FMAs each, per sub-pixel
         slots_per_prop += E * 4 * (epl_terms(spec.proposals) - 1.0)
     achieved = slots_per_prop * n / (kern_ms * 1e-3)
+    terms = roofline_terms(slots_per_prop * n, conv_flops(info) * n, prec, kern_ms * 1e-3)
     kname = ("k_loglike_rt<8,%d>" % info["threads"] if epl and not nnls and prec == 0 else
              "k_loglike_nnls<%d,%d>" % (4 + model + (8 if epl else 0), info["threads"]) if nnls else
              "k_loglike_fp32<%d,%d>" % (info["psf_used"], info["threads"]) if prec == 0 else
              "k_loglike_mfma<%d,%d>" % (prec, info["threads"]))
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_SLOT_PER_S / 1e12,
-                "unit": "Tslot/s", "frac": achieved / PEAK_SLOT_PER_S, "traffic": measured_traffic(prec),
+                "unit": "Tslot/s", "frac": terms["frac"], "terms": terms, "traffic": measured_traffic("plain") if prec == 0 and not nnls and not epl else None,
                 "kernel": kname + " (+ k_prep)", "kernel_ms": kern_ms,
                 "slots_per_proposal": slots_per_prop, "subpixel_evals_per_proposal": E,
                 "psf_used": info["psf_used"], "psf_given": info["psf_size"]}
@@ -324,6 +364,257 @@ def _stream_ctx(binding, torch, **kw):
     return binding.LensContext(0, stream=st.cuda_stream, **kw), st
 
 
+def cpu_model():
+    """The host CPU's model name and logical core count (from /proc/cpuinfo)."""
+    name = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    name = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return name, os.cpu_count()
+
+
+def _timed_steps(fn, stream, steps, warmup):
+    """warmup untimed calls, then steps timed calls bracketed by synchronisations; returns
+    (wall seconds per step, mean HIP-event milliseconds per step on `stream`)."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for a, b in ev:
+        a.record(stream)
+        fn()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    return wall, float(np.mean([a.elapsed_time(b) for a, b in ev]))
+
+
+def run_batched(args):
+    """The default line: 64 precision-workload lenses in one device-buffer multi-lens call
+    per step, batched mixed precision vs the plain FP32 one-lens-per-call path."""
+    import torch
+
+    from paper_2503_08586_amd import binding, synth
+    mode = args.precision or "split3"
+    prec = PREC[mode]
+    specs = synth.config4()
+    dev = torch.device("cuda", 0)
+    st = torch.cuda.Stream()
+    ctx = binding.LensContext(0, stream=st.cuda_stream, autotune=args.autotune)
+    for sp in specs:
+        gpu_data(ctx, sp)
+    lids = [ctx.load(sp, precision=prec) for sp in specs]
+    counts = [sp.proposals.shape[0] for sp in specs]
+    n = int(sum(counts))
+    P = np.ascontiguousarray(np.concatenate([sp.proposals for sp in specs]))
+    pd = torch.from_numpy(P).to(dev)
+    od = torch.empty(n, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    step_s, kern_ms = _timed_steps(lambda: ctx.loglike_multi_device(lids, counts, pd, od, st), st, args.steps,
+                                   args.warmup)
+    got = od.cpu().numpy()
+    offs = np.concatenate([[0], np.cumsum(counts)])
+    infos = [ctx.info(l) for l in lids]
+    slots = sum(credited_slots(sp, inf, prec=prec)[0] * c for sp, inf, c in zip(specs, infos, counts))
+    flops = sum(conv_flops(inf) * c for inf, c in zip(infos, counts))
+    evals = sum(credited_slots(sp, inf, prec=prec)[1] * c for sp, inf, c in zip(specs, infos, counts))
+    terms = roofline_terms(slots, flops, prec, kern_ms * 1e-3)
+    roofline = {"bound": terms["bound"], "achieved": slots / (kern_ms * 1e-3) / 1e12,
+                "peak": PEAK_SLOT_PER_S / 1e12, "unit": "Tslot/s", "frac": terms["frac"],
+                "traffic": measured_traffic("batched") if mode == "split3" else None,
+                "mfma": {"achieved": flops * PRODUCTS.get(prec, 0) / (kern_ms * 1e-3) / 1e12,
+                         "peak": PEAK_BF16_FLOP_S / 1e12, "unit": "TFLOP/s",
+                         "frac": terms["t_mfma_s"] / (kern_ms * 1e-3),
+                         "note": "2 M k^2 flops per proposal times %d BF16 products per tap"
+                                 % PRODUCTS.get(prec, 0)},
+                "terms": terms,
+                "kernel": "k_loglike_batch<%d,%d> (+ k_prep, counter reset)" % (prec, infos[0]["threads"]),
+                "kernel_ms": kern_ms, "slots_per_step": slots, "conv_flops_per_step": flops,
+                "tile": [infos[0]["strip_rows"], infos[0]["threads"], infos[0]["blocks_per_cu"],
+                         infos[0]["lds_bytes"]]}
+
+    # the plain path: FP32, one lens per call, same proposals, device buffers
+    plain = None
+    got32 = None
+    if not args.no_plain:
+        lids32 = [ctx.load(sp, precision=0) for sp in specs]
+        o32 = torch.empty(n, dtype=torch.float64, device=dev)
+
+        def plain_pass():
+            for j, l in enumerate(lids32):
+                ctx.loglike_device(l, pd[offs[j]:offs[j + 1]], o32[offs[j]:offs[j + 1]], st)
+        pstep, pms = _timed_steps(plain_pass, st, 1, 1)
+        got32 = o32.cpu().numpy()
+        plain = {"evals_per_s": n / pstep, "ms_per_pass": pstep * 1e3, "event_ms": pms,
+                 "path": "lens_loglike_batch_device per lens, FP32 PSF convolution (k_loglike_fp32<41,256>)"}
+        for l in lids32:
+            ctx.unload(l)
+
+    # error of both paths on a seeded sample, and the oracle's own rate on it
+    errs = {}
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        orc = oracle.default()
+        rng = np.random.default_rng(synth.SEED_BASE + 40)
+        k = args.sample_per_lens
+        sel = np.unique(np.linspace(0, len(specs) - 1, args.sample_lenses).round().astype(int))
+        picks = {int(j): np.sort(rng.choice(counts[j], k, replace=False)) for j in sel}
+        sample = [(specs[j], specs[j].proposals[picks[j]]) for j in picks]
+        res, tc, threads = oracle_sample(sample)
+        e_b = np.concatenate([rel_errors(got[offs[j] + picks[j]], r[0], r[1], r[2]) for j, r in zip(picks, res)])
+        errs["batched"] = {"max": float(e_b.max()), "p99": float(np.quantile(e_b, 0.99)), "n": int(e_b.size)}
+        if got32 is not None:
+            e_p = np.concatenate([rel_errors(got32[offs[j] + picks[j]], r[0], r[1], r[2])
+                                  for j, r in zip(picks, res)])
+            errs["plain"] = {"max": float(e_p.max()), "p99": float(np.quantile(e_p, 0.99)), "n": int(e_p.size)}
+        # one thread, four proposals of the first sampled lens
+        j0 = int(sel[0])
+        t1 = time.perf_counter()
+        orc.loglike(specs[j0].geom, specs[j0].psf, specs[j0].data, specs[j0].sigma, specs[j0].mask,
+                    specs[j0].proposals[picks[j0][:4]], nthreads=1)
+        t1 = time.perf_counter() - t1
+        model, ncpu = cpu_model()
+        cpu = {"value": k * len(picks) / tc, "unit": "loglike evals/s", "cores": min(threads, k), "kind": "oracle",
+               "sample": "%d seeded proposals of each of %d evenly spaced lenses (%d; one oracle call per lens), "
+                         "%.1f s" % (k, len(picks), k * len(picks), tc),
+               "single_thread": {"value": 4 / t1, "sample": "4 proposals of lens %d, %.1f s" % (j0, t1)},
+               "cpu_model": model, "logical_cpus": ncpu}
+    for l in lids:
+        ctx.unload(l)
+    ctx.close()
+
+    serving = None if args.no_serving else serving_leg(args, mode)
+    rec = {
+        "metric": METRIC, "value": n / step_s, "unit": "loglike evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": step_s * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": path_dtype(mode), "data": "synthetic",
+        "config": {"workload": "batched precision workload: 64 lenses 200x200 px at 0.05\"/px, 4x4 supersampling, "
+                               "41x41 Moffat PSF beta 3 FWHM 0.15\", r=3\" mask, 16,384 proposals per lens per step, "
+                               "one device-buffer multi-lens call (persistent launch), FP64 ray trace, %s BF16 "
+                               "matrix-core PSF convolution, FP64 chi2" % mode,
+                   "path": "lens_loglike_multi_device", "proposals_per_step": n, "precision": mode,
+                   "subpixel_evals_per_s": evals / step_s},
+        "plain": plain,
+        "batched_over_plain": (n / step_s) / plain["evals_per_s"] if plain else None,
+        "rel_err_vs_oracle": errs,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "serving": serving,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+def serve_stream(ctx, lids, reqs, rate, rng):
+    """Open-loop Poisson arrivals of reqs [(lens index, proposals)] at `rate` requests/s
+    (None: all at once); returns (served evals/s, per-request latency seconds, handles)."""
+    import threading
+    arr = np.zeros(len(reqs)) if rate is None else synth_mod().poisson_arrivals(rng, rate, len(reqs))
+    t_sub = [0.0] * len(reqs)
+    t_done = [None] * len(reqs)
+    handles = [None] * len(reqs)
+    lock = threading.Lock()
+    stop = [False]
+
+    def poller():
+        pending = set()
+        while True:
+            with lock:
+                pending.update(i for i, h in enumerate(handles) if h is not None and t_done[i] is None)
+            done = []
+            for i in list(pending):
+                if ctx.poll(handles[i]) == 0:
+                    t_done[i] = time.perf_counter()
+                    done.append(i)
+            pending.difference_update(done)
+            if stop[0] and not pending and all(t is not None for t in t_done):
+                return
+            time.sleep(50e-6)
+
+    th = threading.Thread(target=poller)
+    th.start()
+    t0 = time.perf_counter()
+    for i, (j, P) in enumerate(reqs):
+        while time.perf_counter() - t0 < arr[i]:
+            time.sleep(20e-6)
+        t_sub[i] = time.perf_counter()
+        h = ctx.submit(lids[j], P)
+        with lock:
+            handles[i] = h
+    stop[0] = True
+    th.join()
+    lat = np.array([d - s_ for d, s_ in zip(t_done, t_sub)])
+    props = sum(P.shape[0] for _, P in reqs)
+    return props / (max(t_done) - t0), lat, handles
+
+
+def synth_mod():
+    from paper_2503_08586_amd import synth
+    return synth
+
+
+def serving_leg(args, mode, loads=(0.8,), nreq=None, sample_err=True):
+    """C5 serving: 1,000 resident lenses of mixed shape in precision `mode`, Poisson requests
+    of U{100..10000} proposals on random lenses; the saturated peak from a backlog, then
+    each offered load as a fraction of that peak with p50/p99 latency; a few requests'
+    results against the oracle."""
+    from paper_2503_08586_amd import binding
+    synth = synth_mod()
+    nreq = nreq or args.serve_requests
+    prec = PREC[mode]
+    lenses = synth.config5_lenses()
+    ctx = binding.LensContext(0, max_inflight=8, autotune=args.autotune)
+    t_load = time.perf_counter()
+    lids = []
+    for sp in lenses:
+        gpu_data(ctx, sp)
+        lids.append(ctx.load(sp, precision=prec))
+    t_load = time.perf_counter() - t_load
+    rng = synth.rng_for_config(5)
+    mean_b = 5050.0
+
+    def make_requests(count):
+        out = []
+        for _ in range(count):
+            j = int(rng.integers(0, len(lids)))
+            b = int(rng.integers(100, 10001))
+            out.append((j, synth.draw_params(rng, b)))
+        return out
+
+    peak_reqs = make_requests(max(40, nreq // 3))
+    peak, _, _ = serve_stream(ctx, lids, peak_reqs, None, rng)
+    out = {"peak_evals_per_s": peak, "precision": mode, "lenses": len(lids), "load_s": t_load, "loads": {}}
+    last = None
+    for rho in loads:
+        reqs = make_requests(nreq)
+        thr, lat, hs = serve_stream(ctx, lids, reqs, rho * peak / mean_b, rng)
+        out["loads"][str(rho)] = {"offered_evals_per_s": rho * peak, "evals_per_s": thr, "requests": len(reqs),
+                                  "p50_ms": float(np.percentile(lat, 50) * 1e3),
+                                  "p99_ms": float(np.percentile(lat, 99) * 1e3)}
+        last = (reqs, hs)
+    st = ctx.stats()
+    out["launches"] = st["launches"]
+    out["requests_done"] = st["requests_done"]
+    if sample_err and last is not None:
+        reqs, hs = last
+        sample = []
+        for (j, P), h in list(zip(reqs, hs))[:8]:
+            sample.append((lenses[j], P[:2], h.out[:2]))
+        res, _, _ = oracle_sample([(sp, P) for sp, P, _ in sample])
+        e = np.concatenate([rel_errors(g, r[0], r[1], r[2]) for (_, _, g), r in zip(sample, res)])
+        out["rel_err_vs_oracle"] = {"max": float(e.max()), "n": int(e.size),
+                                    "sample": "2 proposals of each of the last load's first 8 requests"}
+    ctx.close()
+    return out
+
+
 def run_batch(args):
     import torch
 
@@ -333,7 +624,7 @@ def run_batch(args):
     nnls = args.amplitudes == "nnls" or model != 0
     specs = synth.config3()
     ctx, st = _stream_ctx(binding, torch, autotune=args.autotune)
-    lids, slots, evs = [], 0.0, 0
+    lids, slots, evs, flops = [], 0.0, 0, 0.0
     drng = synth.rng_for_config(3)
     for sp in specs:
         gpu_data(ctx, sp)
@@ -341,8 +632,9 @@ def run_batch(args):
             sp.proposals = synth.double_component_params(drng, sp.proposals)
         lid = ctx.load(sp, precision=prec, amplitudes=1 if nnls else 0, light_model=model, sersic_n=DOUBLE_N)
         lids.append(lid)
-        sl, E = credited_slots(sp, ctx.info(lid), nnls, model)
+        sl, E = credited_slots(sp, ctx.info(lid), nnls, model, prec)
         slots += sl * sp.proposals.shape[0]
+        flops += conv_flops(ctx.info(lid)) * sp.proposals.shape[0]
         evs += E * sp.proposals.shape[0]
     plist = [sp.proposals for sp in specs]
     n = int(sum(p.shape[0] for p in plist))
@@ -381,7 +673,8 @@ def run_batch(args):
         "batched_over_plain": plain_s / step_s,
         "batched_equals_plain_bitwise": bool(same),
         "roofline": {"bound": "alu", "achieved": slots / (gpu_ms * 1e-3) / 1e12, "peak": PEAK_SLOT_PER_S / 1e12,
-                     "unit": "Tslot/s", "frac": slots / (gpu_ms * 1e-3) / PEAK_SLOT_PER_S, "traffic": None,
+                     "unit": "Tslot/s", "frac": roofline_terms(slots, flops, prec, gpu_ms * 1e-3)["frac"],
+                     "terms": roofline_terms(slots, flops, prec, gpu_ms * 1e-3), "traffic": None,
                      "kernel": "k_loglike_batch (graph: H2D, prep, persistent kernel, D2H)", "call_ms": gpu_ms},
         "cpu_baseline": {"value": sum(len(P) for _, P in sample) / tc, "unit": "loglike evals/s", "cores": threads,
                          "kind": "oracle", "sample": "2 proposals of each of 32 lenses (every 8th)"},
@@ -593,8 +886,9 @@ def run_precision(args):
         lids = [ctx.load(sp, precision=PREC[m]) for sp in specs]
         plist = [sp.proposals for sp in specs]
         n = int(sum(p.shape[0] for p in plist))
-        slots = sum(credited_slots(sp, ctx.info(l))[0] * sp.proposals.shape[0]
+        slots = sum(credited_slots(sp, ctx.info(l), prec=PREC[m])[0] * sp.proposals.shape[0]
                     for sp, l in zip(specs, lids))
+        flops = sum(conv_flops(ctx.info(l)) * sp.proposals.shape[0] for sp, l in zip(specs, lids))
         for _ in range(max(1, args.warmup)):
             outs = ctx.loglike_multi(lids, plist)
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -612,7 +906,7 @@ def run_precision(args):
         per[m] = {"tile": [inf["strip_rows"], inf["threads"], inf["blocks_per_cu"], inf["lds_bytes"]],
                   "evals_per_s": n / step_s, "ms_per_step": step_s * 1e3, "max_rel_err": float(errs.max()),
                   "p99_rel_err": float(np.quantile(errs, 0.99)),
-                  "frac_credited_alu": slots / (gpu_ms * 1e-3) / PEAK_SLOT_PER_S}
+                  "roofline": roofline_terms(slots, flops, PREC[m], gpu_ms * 1e-3)}
         for l in lids:
             ctx.unload(l)
     # value: the fastest mode whose sampled lnL error is within 1e-6 (plain BF16, gated at 1e-3, is reported
@@ -632,86 +926,17 @@ def run_precision(args):
 
 
 def run_serving(args):
-    import threading
-
-    import torch
-
-    from paper_2503_08586_amd import binding, synth
-    prec = PREC[args.precision or "split"]
-    lenses = synth.config5_lenses()
-    ctx = binding.LensContext(0, max_inflight=8, autotune=args.autotune)
-    lids = []
-    for sp in lenses:
-        gpu_data(ctx, sp)
-        lids.append(ctx.load(sp, precision=prec))
-    rng = synth.rng_for_config(5)
-    mean_b = 5050.0
-
-    def make_requests(count):
-        out = []
-        for _ in range(count):
-            j = int(rng.integers(0, len(lids)))
-            b = int(rng.integers(100, 10001))
-            out.append((j, synth.draw_params(rng, b)))
-        return out
-
-    def run_stream(reqs, rate):
-        """Open-loop Poisson arrivals at `rate` requests/s (rate None: all at once)."""
-        arr = np.zeros(len(reqs)) if rate is None else synth.poisson_arrivals(rng, rate, len(reqs))
-        t_sub = [0.0] * len(reqs)
-        t_done = [None] * len(reqs)
-        handles = [None] * len(reqs)
-        lock = threading.Lock()
-        stop = [False]
-
-        def poller():
-            pending = set()
-            while True:
-                with lock:
-                    pending.update(i for i, h in enumerate(handles) if h is not None and t_done[i] is None)
-                done = []
-                for i in list(pending):
-                    if ctx.poll(handles[i]) == 0:
-                        t_done[i] = time.perf_counter()
-                        done.append(i)
-                pending.difference_update(done)
-                if stop[0] and not pending and all(t is not None for t in t_done):
-                    return
-                time.sleep(50e-6)
-
-        th = threading.Thread(target=poller)
-        th.start()
-        t0 = time.perf_counter()
-        for i, (j, P) in enumerate(reqs):
-            while time.perf_counter() - t0 < arr[i]:
-                time.sleep(20e-6)
-            t_sub[i] = time.perf_counter()
-            h = ctx.submit(lids[j], P)
-            with lock:
-                handles[i] = h
-        stop[0] = True
-        th.join()
-        t_end = max(t_done)
-        lat = np.array([d - s for d, s in zip(t_done, t_sub)])
-        props = sum(P.shape[0] for _, P in reqs)
-        return props / (t_end - t0), lat
-
-    # peak: a backlog of requests submitted at once
-    peak, _ = run_stream(make_requests(max(60, args.requests // 3)), None)
-    loads = {}
-    for rho in (0.5, 0.6, 0.7, 0.8, 0.9, 1.0):
-        thr, lat = run_stream(make_requests(args.requests), rho * peak / mean_b)
-        loads[str(rho)] = {"offered_evals_per_s": rho * peak, "evals_per_s": thr,
-                           "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3)}
-    rec = {"metric": METRIC, "value": peak, "unit": "loglike evals/s", "n_gpus": 1, "steps": args.requests,
-           "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": path_dtype(args.precision or "split"), "data": "synthetic",
+    """The serving sweep: offered loads of 50-100% of the saturated peak."""
+    mode = args.precision or "split3"
+    out = serving_leg(args, mode, loads=(0.5, 0.6, 0.7, 0.8, 0.9, 1.0), nreq=args.requests)
+    rec = {"metric": METRIC, "value": out["peak_evals_per_s"], "unit": "loglike evals/s", "n_gpus": 1,
+           "steps": args.requests, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": path_dtype(mode), "data": "synthetic",
            "config": {"workload": "serving: 1,000 resident lenses N~U{48..200}, k~U{11..41}, s=4, Gaussian/Moffat "
                                   "PSFs; Poisson requests of U{100..10000} proposals on random lenses; %s convolution"
-                                  % (args.precision or "split"), "requests_per_load": args.requests},
-           "offered_loads": loads, "stats": ctx.stats()}
+                                  % mode, "requests_per_load": args.requests},
+           "serving": out}
     print(json.dumps(rec), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

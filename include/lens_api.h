@@ -257,6 +257,22 @@ lens_status lens_loglike_batch_device(lens_ctx *ctx, lens_id id, const double *d
 lens_status lens_loglike_multi(lens_ctx *ctx, int32_t nlens, const lens_id *ids,
                                const int64_t *counts, const double *params, double *out);
 
+/* Many lenses on device buffers (Sec. 2.2, Eq. 5 for every proposal; the
+ * batched evaluation of Sec. 3.1.4, extended across lenses): ids[i] with
+ * counts[i] proposals (host arrays); d_params [sum counts][20] and d_out
+ * [sum counts] in device memory, lens-major in the order of ids.  Enqueued on
+ * the hipStream_t `stream` (NULL: the default stream) and not waited for: the
+ * prep step over all proposals, then one persistent launch per group of
+ * lenses (as lens_loglike_multi, without the graph and the host copies).  The
+ * caller keeps both buffers alive until the stream passes the call.  Results
+ * equal lens_loglike_multi's and the single-lens results bit for bit.  The
+ * lookup tables of the 8 most recent call shapes are kept; the prepared
+ * constants and work counters use the stream's scratch buffer.  LENS_EINVAL
+ * for null or negative arguments, LENS_ENOENT for an unknown id. */
+lens_status lens_loglike_multi_device(lens_ctx *ctx, int32_t nlens, const lens_id *ids,
+                                      const int64_t *counts, const double *d_params, double *d_out,
+                                      void *stream);
+
 /* Serving.  lens_submit copies params before it returns; out must stay valid
  * until lens_poll / lens_wait report a final status or lens_cancel returns.
  * Requests are batched continuously with others on the device.  When all

@@ -53,6 +53,7 @@ LENS_LIGHT_DOUBLE = 3
 EXPORTED = [
     "lens_init", "lens_shutdown", "lens_load_data", "lens_unload", "lens_get_info",
     "lens_loglike_batch", "lens_loglike_amps", "lens_loglike_batch_device", "lens_loglike_multi",
+    "lens_loglike_multi_device",
     "lens_submit", "lens_poll", "lens_wait", "lens_cancel", "lens_get_stats",
     "lens_model_image", "lens_selftest", "lens_psf_crop", "lens_strerror", "lens_last_error",
     "lens_ensemble_create", "lens_ensemble_run", "lens_ensemble_run_many", "lens_ensemble_get",
@@ -160,6 +161,7 @@ def load():
         "lens_loglike_amps": ([vp, i64, dp, i64, dp, dp], i32),
         "lens_loglike_batch_device": ([vp, i64, vp, i64, vp, vp], i32),
         "lens_loglike_multi": ([vp, i32, i64p, i64p, dp, dp], i32),
+        "lens_loglike_multi_device": ([vp, i32, i64p, i64p, vp, vp, vp], i32),
         "lens_submit": ([vp, i64, dp, i64, dp, i64p], i32),
         "lens_poll": ([vp, i64], i32),
         "lens_wait": ([vp, i64, i64], i32),
@@ -455,6 +457,27 @@ def lens_loglike_multi(ctx, lens_ids: Sequence[int], params_list: Sequence[np.nd
     return np.split(out, np.cumsum(counts)[:-1])
 
 
+def lens_loglike_multi_device(ctx, lens_ids: Sequence[int], counts: Sequence[int], params_dev: "torch.Tensor",
+                              out_dev: "torch.Tensor", stream: Optional["torch.cuda.Stream"] = None):
+    """Many lenses on device buffers: params_dev [sum counts, 20] and out_dev [sum counts]
+    float64 on the GPU, lens-major in the order of lens_ids; enqueued on `stream`."""
+    if params_dev.dtype != torch.float64 or out_dev.dtype != torch.float64:
+        raise TypeError("float64 tensors expected")
+    if not (params_dev.is_cuda and out_dev.is_cuda and params_dev.is_contiguous() and out_dev.is_contiguous()):
+        raise ValueError("contiguous device tensors expected")
+    ids = np.ascontiguousarray(lens_ids, dtype=np.int64)
+    cnt = np.ascontiguousarray(counts, dtype=np.int64)
+    if ids.shape != cnt.shape or ids.ndim != 1:
+        raise ValueError("lens_ids and counts must be 1-d of one length")
+    n = int(cnt.sum())
+    if params_dev.shape != (n, STRIDE) or out_dev.shape != (n,):
+        raise ValueError("shapes must be [sum counts, 20] and [sum counts]")
+    s = stream if stream is not None else torch.cuda.current_stream(params_dev.device)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    _check(ctx, load().lens_loglike_multi_device(ctx, len(ids), ids.ctypes.data_as(i64p), cnt.ctypes.data_as(i64p),
+                                                 params_dev.data_ptr(), out_dev.data_ptr(), s.cuda_stream))
+
+
 class Request:
     """A submitted serving request: keeps its output buffer alive."""
 
@@ -562,6 +585,9 @@ class LensContext:
 
     def loglike_multi(self, lids, params_list):
         return lens_loglike_multi(self.ctx, lids, params_list)
+
+    def loglike_multi_device(self, lids, counts, params_dev, out_dev, stream=None):
+        return lens_loglike_multi_device(self.ctx, lids, counts, params_dev, out_dev, stream)
 
     def model_image(self, lid, params1, stage=1) -> np.ndarray:
         ny, nx = self.geom[lid]

@@ -57,7 +57,12 @@ struct Lens {
     int requests = 0;       // serving requests queued or running
 };
 
-struct Scratch {            // per-stream device scratch of the device-buffer entry point
+// Per-stream device scratch.  Its mutex is held from the moment a call takes
+// the buffer until that call has enqueued every launch that uses it, so that
+// calls sharing a stream neither interleave their launches on one buffer nor
+// free it under each other (a grow drains the stream first).
+struct Scratch {
+    std::mutex mu;
     void *p = nullptr;
     size_t bytes = 0;
 };
@@ -148,6 +153,14 @@ struct Plan {
     hipGraphExec_t exec = nullptr;
     uint64_t used = 0;
 };
+
+// One multi-lens call shape of the device-buffer entry point: the launch
+// groups and their read-only device tables (lens descriptors, item starts,
+// output offsets, and the per-lens prep model table when models differ).  The
+// prepared constants and the work counters live in the caller stream's
+// scratch.  Created and dropped under sync_mu; dropped only after the device
+// has drained, since launches on callers' streams may still read the tables.
+struct DPlan;
 
 // round-to-nearest-even FP32 -> BF16 and back
 uint16_t bf16_rn_host(float f)
@@ -286,7 +299,7 @@ struct lens_ctx {
     std::mutex mu;                        // registry, scratch, budget
     std::map<lens_id, Lens *> lenses;
     lens_id next_id = 1;
-    std::unordered_map<hipStream_t, Scratch> scratch;
+    std::unordered_map<hipStream_t, std::unique_ptr<Scratch>> scratch;
 
     std::mutex sync_mu;                   // staging of the blocking calls
     double *h_params = nullptr, *h_out = nullptr;
@@ -308,6 +321,8 @@ struct lens_ctx {
     // multi-lens plans (graph-captured persistent launches), guarded by sync_mu
     std::map<std::string, struct Plan *> plans;
     uint64_t plan_clock = 0;
+    // multi-lens shapes of the device-buffer entry point, guarded by sync_mu
+    std::map<std::string, struct DPlan *> dplans;
 
     // serving
     int max_inflight = 8;
@@ -433,11 +448,19 @@ lens_status check_ctx(lens_ctx *c)
 }
 
 // Device scratch of at least `bytes` private to `stream` (grown by re-allocation
-// after the stream has drained).
-lens_status stream_scratch(lens_ctx *c, hipStream_t st, size_t bytes, void **out)
+// after the stream has drained).  On return `hold` owns the buffer's lock: keep
+// it until every launch that uses the buffer has been enqueued.
+lens_status stream_scratch(lens_ctx *c, hipStream_t st, size_t bytes, void **out, std::unique_lock<std::mutex> *hold)
 {
-    std::lock_guard<std::mutex> lk(c->mu);
-    Scratch &s = c->scratch[st];
+    Scratch *sp = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(c->mu);
+        std::unique_ptr<Scratch> &e = c->scratch[st];
+        if (!e) e.reset(new Scratch());
+        sp = e.get();
+    }
+    *hold = std::unique_lock<std::mutex>(sp->mu);
+    Scratch &s = *sp;
     if (s.bytes >= bytes) {
         *out = s.p;
         return LENS_OK;
@@ -521,6 +544,9 @@ struct Ensemble {
 void scheduler_main(lens_ctx *c);
 lens_status tune_lens(lens_ctx *c, Lens *L);
 void drop_plan(lens_ctx *c, Plan *pl);
+void drop_dplan(lens_ctx *c, DPlan *pl);
+bool dplan_uses(const DPlan *pl, lens_id id);
+void free_dplan_now(lens_ctx *c, DPlan *pl);
 
 }  // namespace
 
@@ -612,7 +638,9 @@ extern "C" void lens_shutdown(lens_ctx *c)
     c->scv.notify_all();
     if (c->sched.joinable()) c->sched.join();
     DeviceGuard dg(c->device);
-    (void)hipStreamSynchronize(c->stream);
+    // device-buffer calls may still run on callers' streams and read lenses,
+    // plans and scratch freed below
+    (void)hipDeviceSynchronize();
     for (int i = 0; i < kServeStreams; ++i)
         if (c->sstreams[i]) {
             (void)hipStreamSynchronize(c->sstreams[i]);
@@ -632,6 +660,8 @@ extern "C" void lens_shutdown(lens_ctx *c)
         delete pl;
     }
     c->plans.clear();
+    for (auto &kv : c->dplans) free_dplan_now(c, kv.second);
+    c->dplans.clear();
     for (auto &kv : c->reqs) delete kv.second;
     c->reqs.clear();
     for (auto &kv : c->ensembles) {
@@ -644,10 +674,7 @@ extern "C" void lens_shutdown(lens_ctx *c)
         delete kv.second;
     }
     c->lenses.clear();
-    for (auto &kv : c->scratch) {
-        (void)hipStreamSynchronize(kv.first);
-        dev_free(c, kv.second.p);
-    }
+    for (auto &kv : c->scratch) dev_free(c, kv.second->p);
     c->scratch.clear();
     if (c->d_sync) dev_free(c, c->d_sync);
     if (c->d_arena) dev_free(c, c->d_arena);
@@ -725,7 +752,8 @@ lens_status tune_lens(lens_ctx *c, Lens *L)
     std::lock_guard<std::mutex> lk(c->sync_mu);
     void *buf = nullptr;
     const size_t pb = align_up((size_t)n * lensk::kStride * 8, kAlign), cb = align_up((size_t)n * lensk::kPCBytes, kAlign);
-    lens_status rs = stream_scratch(c, c->stream, pb + cb + (size_t)n * 8, &buf);
+    std::unique_lock<std::mutex> hold;
+    lens_status rs = stream_scratch(c, c->stream, pb + cb + (size_t)n * 8, &buf, &hold);
     if (rs != LENS_OK) return rs;
     double *dp = (double *)buf;
     lensk::PropBlock *dpc = (lensk::PropBlock *)((char *)buf + pb);
@@ -1094,6 +1122,14 @@ extern "C" lens_status lens_unload(lens_ctx *c, lens_id id)
             ++it;
         }
     }
+    for (auto it = c->dplans.begin(); it != c->dplans.end();) {
+        if (dplan_uses(it->second, id)) {
+            drop_dplan(c, it->second);
+            it = c->dplans.erase(it);
+        } else {
+            ++it;
+        }
+    }
     log_line(c, "unload lens %lld", (long long)id);
     dev_free(c, L->slab);
     uncharge(c, (int64_t)L->bytes);
@@ -1275,7 +1311,8 @@ extern "C" lens_status lens_loglike_batch_device(lens_ctx *c, lens_id id, const 
     DeviceGuard dg(c->device);
     hipStream_t hs = (hipStream_t)stream;  // NULL: the default stream
     void *scr = nullptr;
-    lens_status rs = stream_scratch(c, hs, scratch_bytes(n, false), &scr);
+    std::unique_lock<std::mutex> hold;   // until both launches are enqueued
+    lens_status rs = stream_scratch(c, hs, scratch_bytes(n, false), &scr, &hold);
     if (rs == LENS_OK) {
         ScratchLayout S = carve(scr, n, false);
         hipError_t e = launch_lens(L, d_params, S.pc, n, d_out, hs);
@@ -1542,6 +1579,164 @@ extern "C" lens_status lens_loglike_multi(lens_ctx *c, int32_t nlens, const lens
     return rs;
 }
 
+namespace {
+
+struct DPlan {
+    std::vector<lens_id> ids;
+    std::vector<int64_t> counts;
+    int64_t tot = 0;
+    BatchGroups bg;
+    bool one_model = true;
+    int model0 = 0;
+    void *dev = nullptr;          // geoms | lstart | lout | pstart | pmodel
+    size_t bytes = 0;
+    LensGeom *d_geom = nullptr;
+    int *d_ls = nullptr, *d_pm = nullptr;
+    int64_t *d_lo = nullptr, *d_ps = nullptr;
+    uint64_t used = 0;
+};
+
+void drop_dplan(lens_ctx *c, DPlan *pl)
+{
+    // sync_mu held, the device drained
+    dev_free(c, pl->dev);
+    uncharge(c, (int64_t)pl->bytes);
+    delete pl;
+}
+
+void free_dplan_now(lens_ctx *c, DPlan *pl)
+{
+    dev_free(c, pl->dev);
+    delete pl;
+}
+
+bool dplan_uses(const DPlan *pl, lens_id id)
+{
+    return std::find(pl->ids.begin(), pl->ids.end(), id) != pl->ids.end();
+}
+
+// Build the tables of one call shape (sync_mu held).
+lens_status build_dplan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int64_t *counts,
+                        const std::vector<Lens *> &Ls, int64_t tot, DPlan **out)
+{
+    auto pl = std::make_unique<DPlan>();
+    pl->ids.assign(ids, ids + nlens);
+    pl->counts.assign(counts, counts + nlens);
+    pl->tot = tot;
+    std::vector<int64_t> off(nlens + 1, 0);
+    for (int i = 0; i < nlens; ++i) off[i + 1] = off[i] + counts[i];
+    group_batch(c, Ls, counts, off.data(), &pl->bg);
+    std::vector<int> hmodel(nlens);
+    for (int i = 0; i < nlens; ++i) {
+        hmodel[i] = Ls[i]->prep_code;
+        pl->one_model = pl->one_model && hmodel[i] == hmodel[0];
+    }
+    pl->model0 = hmodel[0];
+    const BatchGroups &bg = pl->bg;
+    const size_t b_geom = align_up(bg.geom.size() * sizeof(LensGeom), kAlign);
+    const size_t b_ls = align_up(bg.lstart.size() * 4, kAlign), b_lo = align_up(bg.lout.size() * 8, kAlign);
+    const size_t b_ps = align_up((size_t)(nlens + 1) * 8, kAlign), b_pm = align_up((size_t)nlens * 4, kAlign);
+    pl->bytes = b_geom + b_ls + b_lo + b_ps + b_pm;
+    if (!charge(c, (int64_t)pl->bytes)) return fail(c, LENS_ENOMEM, "HBM budget exhausted (batch tables)");
+    pl->dev = dev_alloc(c, pl->bytes);
+    if (!pl->dev) {
+        uncharge(c, (int64_t)pl->bytes);
+        return fail(c, LENS_ENOMEM, "device allocation failed (batch tables)");
+    }
+    char *b = (char *)pl->dev;
+    pl->d_geom = (LensGeom *)b;
+    pl->d_ls = (int *)(b + b_geom);
+    pl->d_lo = (int64_t *)(b + b_geom + b_ls);
+    pl->d_ps = (int64_t *)(b + b_geom + b_ls + b_lo);
+    pl->d_pm = (int *)(b + b_geom + b_ls + b_lo + b_ps);
+    hipError_t e = hipMemcpyAsync(pl->d_geom, bg.geom.data(), bg.geom.size() * sizeof(LensGeom), hipMemcpyHostToDevice,
+                                  c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(pl->d_ls, bg.lstart.data(), bg.lstart.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(pl->d_lo, bg.lout.data(), bg.lout.size() * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(pl->d_ps, off.data(), (size_t)(nlens + 1) * 8, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(pl->d_pm, hmodel.data(), (size_t)nlens * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+        drop_dplan(c, pl.release());
+        return hip_fail(c, e, "batch tables set-up");
+    }
+    log_line(c, "device batch shape: %d lenses, %lld proposals, %zu persistent launches", (int)nlens, (long long)tot,
+             bg.gs.size());
+    *out = pl.release();
+    return LENS_OK;
+}
+
+}  // namespace
+
+extern "C" lens_status lens_loglike_multi_device(lens_ctx *c, int32_t nlens, const lens_id *ids,
+                                                 const int64_t *counts, const double *d_params, double *d_out,
+                                                 void *stream)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (nlens < 0 || (nlens > 0 && (!ids || !counts))) return fail(c, LENS_EINVAL, "bad ids/counts");
+    int64_t tot = 0;
+    for (int i = 0; i < nlens; ++i) {
+        if (counts[i] < 0) return fail(c, LENS_EINVAL, "negative count");
+        tot += counts[i];
+    }
+    if (tot > 0 && (!d_params || !d_out)) return fail(c, LENS_EINVAL, "null params/out");
+    if (tot > INT_MAX) return fail(c, LENS_EINVAL, "too many proposals for one call");
+    if (tot == 0) return LENS_OK;
+    DeviceGuard dg(c->device);
+    hipStream_t hs = (hipStream_t)stream;
+    // sync_mu keeps the shape's tables alive until the launches are enqueued
+    std::lock_guard<std::mutex> lk(c->sync_mu);
+    std::vector<Lens *> Ls;
+    for (int i = 0; i < nlens; ++i) {
+        Lens *L = acquire(c, ids[i]);
+        if (!L) {
+            for (Lens *x : Ls) release(c, x);
+            return fail(c, LENS_ENOENT, "unknown lens id");
+        }
+        Ls.push_back(L);
+    }
+    const std::string key = plan_key(nlens, ids, counts);
+    DPlan *pl = nullptr;
+    lens_status rs = LENS_OK;
+    auto it = c->dplans.find(key);
+    if (it != c->dplans.end()) {
+        pl = it->second;
+    } else {
+        if (c->dplans.size() >= 8) {  // keep the 8 most recently used shapes
+            auto victim = c->dplans.begin();
+            for (auto j = c->dplans.begin(); j != c->dplans.end(); ++j)
+                if (j->second->used < victim->second->used) victim = j;
+            // launches on any stream may still read the victim's tables
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) rs = hip_fail(c, e, "lens_loglike_multi_device");
+            else {
+                drop_dplan(c, victim->second);
+                c->dplans.erase(victim);
+            }
+        }
+        if (rs == LENS_OK) rs = build_dplan(c, nlens, ids, counts, Ls, tot, &pl);
+        if (rs == LENS_OK) c->dplans[key] = pl;
+    }
+    if (rs == LENS_OK) {
+        pl->used = ++c->plan_clock;
+        const size_t b_pc = align_up((size_t)tot * lensk::kPCBytes, kAlign);
+        void *scr = nullptr;
+        std::unique_lock<std::mutex> hold;   // until every launch is enqueued
+        rs = stream_scratch(c, hs, b_pc + align_up(pl->bg.gs.size() * 4 + 4, kAlign), &scr, &hold);
+        if (rs == LENS_OK) {
+            lensk::PropBlock *d_pc = (lensk::PropBlock *)scr;
+            unsigned int *d_cnt = (unsigned int *)((char *)scr + b_pc);
+            hipError_t e = pl->one_model ? lensk::launch_prep(d_params, tot, d_pc, pl->model0, nullptr, nullptr, 0, hs)
+                                         : lensk::launch_prep(d_params, tot, d_pc, 0, pl->d_ps, pl->d_pm, nlens, hs);
+            if (e == hipSuccess) e = launch_groups(pl->bg, hs, pl->d_geom, pl->d_ls, pl->d_lo, d_pc, d_out, d_cnt);
+            if (e != hipSuccess) rs = hip_fail(c, e, "lens_loglike_multi_device");
+        }
+    }
+    for (Lens *x : Ls) release(c, x);
+    return rs;
+}
+
 extern "C" lens_status lens_model_image(lens_ctx *c, lens_id id, const double *params1, int32_t stage,
                                         double *out_img)
 {
@@ -1558,7 +1753,8 @@ extern "C" lens_status lens_model_image(lens_ctx *c, lens_id id, const double *p
         // device: params(20 doubles) | pc | img | tmp
         const size_t bytes = 4096 + 2 * align_up((size_t)npix * 4, kAlign);
         void *dbuf = nullptr;
-        rs = stream_scratch(c, c->stream, bytes, &dbuf);
+        std::unique_lock<std::mutex> hold;
+        rs = stream_scratch(c, c->stream, bytes, &dbuf, &hold);
         if (rs == LENS_OK) {
             char *b = (char *)dbuf;
             double *dp = (double *)b;
@@ -1917,7 +2113,8 @@ extern "C" lens_status lens_selftest(lens_ctx *c, int32_t which, double *result)
             for (int kk = 0; kk < 32; ++kk) ref[i * 16 + j] += (double)bf16_to_float(ha[i * 32 + kk]) * bf16_to_float(hb[kk * 16 + j]);
     std::lock_guard<std::mutex> lk(c->sync_mu);
     void *dbuf = nullptr;
-    lens_status rs = stream_scratch(c, c->stream, 4096, &dbuf);
+    std::unique_lock<std::mutex> hold;
+    lens_status rs = stream_scratch(c, c->stream, 4096, &dbuf, &hold);
     if (rs != LENS_OK) return rs;
     uint16_t *da = (uint16_t *)dbuf, *db = da + 16 * 32;
     float *dd = (float *)((char *)dbuf + 2048);
@@ -1948,7 +2145,8 @@ extern "C" lens_status lens_philox4x32_10(lens_ctx *c, const uint32_t *ctr, cons
     DeviceGuard dg(c->device);
     std::lock_guard<std::mutex> lk(c->sync_mu);
     void *dbuf = nullptr;
-    lens_status rs = stream_scratch(c, c->stream, (size_t)n * 16, &dbuf);
+    std::unique_lock<std::mutex> hold;
+    lens_status rs = stream_scratch(c, c->stream, (size_t)n * 16, &dbuf, &hold);
     if (rs != LENS_OK) return rs;
     hipError_t e = lensk::launch_philox_words(ctr, key, n, (uint32_t *)dbuf, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(out, dbuf, (size_t)n * 16, hipMemcpyDeviceToHost, c->stream);

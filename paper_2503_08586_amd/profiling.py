@@ -1,10 +1,13 @@
-"""HBM traffic of the likelihood kernel from rocprofv3 counters.
+"""HBM traffic of a workload's likelihood kernel from rocprofv3 counters.
 
 Turns two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of bench.py and of its
-1 GiB copy calibration into profiles/traffic_plain_128px_s4_k21.txt (JSON):
+1 GiB copy calibration into the workload's record under profiles/ (JSON):
 
-    python -m paper_2503_08586_amd.profiling <pmc_copy_fetch dir> <pmc_copy_write dir> \\
-        <pmc_plain_fetch dir> <pmc_plain_write dir>
+    python -m paper_2503_08586_amd.profiling <workload> <pmc_copy_fetch dir> <pmc_copy_write dir> \\
+        <pmc_kernel_fetch dir> <pmc_kernel_write dir>
+
+with <workload> one of RECORDS (plain: the one-lens survey-scale launch;
+batched: the persistent multi-lens launch of the default bench line).
 
 The counters are read per dispatch (KiB); each is scaled by what the same
 counter reads for a plain 1 GiB device copy (bytes_known / counter_reading), so
@@ -20,7 +23,23 @@ import os
 import sys
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-RECORD = os.path.join(ROOT, "profiles", "traffic_plain_128px_s4_k21.txt")
+# workload -> (record file, kernel-name part, the bench command the counters were taken on)
+RECORDS = {
+    "plain": ("traffic_plain_128px_s4_k21.txt", "k_loglike_fp32",
+              "python3 bench.py --workload plain --steps 2 --warmup 1 --no-cpu-baseline"),
+    "batched": ("traffic_batched_c4_split3.txt", "k_loglike_batch",
+                "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-serving --no-plain"),
+}
+WORKLOAD_TEXT = {
+    "plain": "plain 128x128 s=4, 21x21 PSF as given, 65,536 proposals/launch",
+    "batched": "64 lenses 200x200 s=4, 41x41 Moffat PSF, split3, 1,048,576 proposals/launch",
+}
+
+
+def record_path(workload):
+    return os.path.join(ROOT, "profiles", RECORDS[workload][0])
+
+
 # everything that decides what the launch does: the kernels, and the runtime
 # that picks the PSF crop and the tile shape
 KERNEL_SOURCES = ["paper_2503_08586_amd/csrc/lens_kernels.hip", "paper_2503_08586_amd/csrc/lens_device.h",
@@ -57,15 +76,16 @@ def rel(d):
 
 
 def main():
-    cf, cw, pf, pw = sys.argv[1:5]
+    workload, cf, cw, pf, pw = sys.argv[1:6]
+    fname, kpart, bench_cmd = RECORDS[workload]
     copy_f, _, _ = read_counter(cf, "FETCH_SIZE", "")
     copy_w, _, _ = read_counter(cw, "WRITE_SIZE", "")
     # a 1 GiB copy reads and writes 1 GiB (2^20 KiB)
     sf, sw = 2.0 ** 20 / copy_f, 2.0 ** 20 / copy_w
-    kf, nf, kname = read_counter(pf, "FETCH_SIZE", "k_loglike_fp32")
-    kw, nw, _ = read_counter(pw, "WRITE_SIZE", "k_loglike_fp32")
+    kf, nf, kname = read_counter(pf, "FETCH_SIZE", kpart)
+    kw, nw, _ = read_counter(pw, "WRITE_SIZE", kpart)
     rec = {"kernel": kname.split("(")[0].replace("void lensk::", ""),
-           "workload": "plain 128x128 s=4, 21x21 PSF as given, 65,536 proposals/launch",
+           "workload": WORKLOAD_TEXT[workload],
            "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw, "dispatches": [nf, nw],
            "copy_fetch_kib": copy_f, "copy_write_kib": copy_w, "scale_fetch": sf, "scale_write": sw,
            "traffic_bytes_per_launch": (kf * sf + kw * sw) * 1024.0, "kernel_src_sha256": kernel_hash(),
@@ -75,12 +95,11 @@ def main():
                % rel(cf),
                "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s -o p -- python3 bench.py --copy-calibration"
                % rel(cw),
-               "rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s -o p -- "
-               "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline" % rel(pf),
-               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s -o p -- "
-               "python3 bench.py --steps 2 --warmup 1 --no-cpu-baseline" % rel(pw),
-               "python -m paper_2503_08586_amd.profiling %s %s %s %s" % tuple(rel(x) for x in (cf, cw, pf, pw))]}
-    with open(RECORD, "w") as f:
+               "rocprofv3 --pmc FETCH_SIZE --output-format csv -d %s -o p -- %s" % (rel(pf), bench_cmd),
+               "rocprofv3 --pmc WRITE_SIZE --output-format csv -d %s -o p -- %s" % (rel(pw), bench_cmd),
+               "python -m paper_2503_08586_amd.profiling %s %s %s %s %s"
+               % ((workload,) + tuple(rel(x) for x in (cf, cw, pf, pw)))]}
+    with open(record_path(workload), "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec))
 

@@ -52,13 +52,36 @@ def test_stale_traffic_record_is_ignored(tmp_path, monkeypatch):
     from paper_2503_08586_amd import profiling
     rec = tmp_path / "traffic.txt"
     rec.write_text(json.dumps({"kernel_src_sha256": profiling.kernel_hash(), "traffic_bytes_per_launch": 123.0}))
-    monkeypatch.setattr(profiling, "RECORD", str(rec))
-    assert bench.measured_traffic(0) == 123.0
-    assert bench.measured_traffic(1) is None        # recorded for the FP32 path only
+    monkeypatch.setattr(profiling, "record_path", lambda w: str(rec))
+    assert bench.measured_traffic("batched") == 123.0
+    assert bench.measured_traffic("precision") is None   # no record for that workload
     rec.write_text(json.dumps({"kernel_src_sha256": "0" * 64, "traffic_bytes_per_launch": 123.0}))
-    assert bench.measured_traffic(0) is None
+    assert bench.measured_traffic("batched") is None
     rec.write_text("not json")
-    assert bench.measured_traffic(0) is None
+    assert bench.measured_traffic("batched") is None
+
+
+@pytest.mark.parametrize("prec", [1, 2, 3])
+def test_matrix_core_modes_credit_the_convolution_to_the_mfma(prec):
+    """In the BF16 matrix-core precisions the PSF taps are not vector-ALU work:
+    E (60 + 4 x 10) + M slots, and 2 M k^2 flops times the products per tap
+    against the dense BF16 peak."""
+    spec = types.SimpleNamespace(s=4)
+    info = {"masked_pixels": 11304, "psf_used": 41, "needed_pixels": 22504}
+    slots, E = bench.credited_slots(spec, info, prec=prec)
+    assert E == 360064
+    assert slots == 360064 * 100 + 11304
+    fl = bench.conv_flops(info)
+    assert fl == 2 * 11304 * 41 * 41
+    t = bench.roofline_terms(slots, fl, prec, 2.0e-6)
+    assert t["t_valu_s"] == pytest.approx(slots / (256 * 4 * 16 * 2.4e9))
+    assert t["t_mfma_s"] == pytest.approx(fl * {1: 3, 2: 1, 3: 6}[prec] / 2.5e15)
+    assert t["frac"] == pytest.approx(max(t["t_valu_s"], t["t_mfma_s"]) / 2.0e-6)
+    assert t["bound"] == "alu"
+    # the FP32 convolution stays on the vector ALU, with no matrix-core term
+    s32, _ = bench.credited_slots(spec, info, prec=0)
+    assert s32 == slots + 11304 * 41 * 41
+    assert bench.roofline_terms(s32, fl, 0, 1.0)["t_mfma_s"] == 0.0
 
 
 def test_epl_series_length():
