@@ -570,7 +570,7 @@ def serving_leg(args, mode, loads=(0.8,), nreq=None, sample_err=True):
     nreq = nreq or args.serve_requests
     prec = PREC[mode]
     lenses = synth.config5_lenses()
-    ctx = binding.LensContext(0, max_inflight=8, autotune=args.autotune)
+    ctx = binding.LensContext(0, autotune=args.autotune)
     t_load = time.perf_counter()
     lids = []
     for sp in lenses:
@@ -590,7 +590,18 @@ def serving_leg(args, mode, loads=(0.8,), nreq=None, sample_err=True):
 
     peak_reqs = make_requests(max(40, nreq // 3))
     peak, _, _ = serve_stream(ctx, lids, peak_reqs, None, rng)
-    out = {"peak_evals_per_s": peak, "precision": mode, "lenses": len(lids), "load_s": t_load, "loads": {}}
+    # the same requests as one batched call on device buffers (no serving): the rate serving is held to
+    import torch
+    dev = torch.device("cuda", 0)
+    st = torch.cuda.Stream()
+    ids = [lids[j] for j, _ in peak_reqs]
+    cnt = [P.shape[0] for _, P in peak_reqs]
+    pd = torch.from_numpy(np.ascontiguousarray(np.concatenate([P for _, P in peak_reqs]))).to(dev)
+    od = torch.empty(int(sum(cnt)), dtype=torch.float64, device=dev)
+    bstep, _ = _timed_steps(lambda: ctx.loglike_multi_device(ids, cnt, pd, od, st), st, 2, 1)
+    batched = sum(cnt) / bstep
+    out = {"peak_evals_per_s": peak, "batched_same_requests_evals_per_s": batched, "peak_over_batched": peak / batched,
+           "precision": mode, "lenses": len(lids), "load_s": t_load, "loads": {}}
     last = None
     for rho in loads:
         reqs = make_requests(nreq)
@@ -599,9 +610,10 @@ def serving_leg(args, mode, loads=(0.8,), nreq=None, sample_err=True):
                                   "p50_ms": float(np.percentile(lat, 50) * 1e3),
                                   "p99_ms": float(np.percentile(lat, 99) * 1e3)}
         last = (reqs, hs)
-    st = ctx.stats()
-    out["launches"] = st["launches"]
-    out["requests_done"] = st["requests_done"]
+    stt = ctx.stats()
+    out["batches"] = stt["launches"]
+    out["requests_done"] = stt["requests_done"]
+    out["request_pieces_per_batch"] = stt["batch_pieces"] / max(1, stt["launches"])
     if sample_err and last is not None:
         reqs, hs = last
         sample = []

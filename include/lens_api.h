@@ -126,7 +126,8 @@ typedef void (*lens_dev_free_fn)(void *ptr, void *stream, void *user);
 typedef struct lens_init_opts {
     int32_t device;             /* HIP device ordinal */
     int64_t hbm_budget_bytes;   /* cap on library-held device memory; <= 0: 90% of free memory at init */
-    int32_t max_inflight;       /* serving: requests resident on the device at once; <= 0: 8 */
+    int32_t max_inflight;       /* serving: requests with work on the device at once (each batch
+                                   mixes pieces of at most this many); <= 0: 64 */
     int32_t nonblocking_submit; /* 1: lens_submit answers LENS_EAGAIN when no slot is free */
     lens_dev_alloc_fn dev_alloc;/* NULL: hipMalloc / hipFree */
     lens_dev_free_fn dev_free;
@@ -190,6 +191,8 @@ typedef struct lens_stats {
      * (at most 4,096) completed requests, the maximum over all of them */
     int64_t latency_count;      /* completed requests in the quantile window */
     double latency_p50_us, latency_p99_us, latency_max_us;
+    int64_t batch_pieces;       /* request pieces placed in serving batches (launches counts the
+                                   batches: batch_pieces / launches requests share a batch on average) */
 } lens_stats;
 
 /* Context.  lens_init creates the context on opts->device (NULL opts: all
@@ -273,10 +276,18 @@ lens_status lens_loglike_multi_device(lens_ctx *ctx, int32_t nlens, const lens_i
                                       const int64_t *counts, const double *d_params, double *d_out,
                                       void *stream);
 
-/* Serving.  lens_submit copies params before it returns; out must stay valid
- * until lens_poll / lens_wait report a final status or lens_cancel returns.
- * Requests are batched continuously with others on the device.  When all
- * max_inflight slots are busy the request queues, or with nonblocking_submit
+/* Serving (the batched likelihood of Sec. 3.1.4, Eq. 5 per proposal, for many
+ * concurrent fits).  lens_submit copies params before it returns; out must
+ * stay valid until lens_poll / lens_wait report a final status or lens_cancel
+ * returns.  Requests are batched continuously: a scheduler thread packs the
+ * waiting proposals of many requests, on any mix of resident lenses, into one
+ * batch (one prep launch and one persistent launch per lens group, as in
+ * lens_loglike_multi), keeps two batches in flight on two streams, and starts
+ * the next batch as soon as one finishes, so requests that arrive while
+ * others run join the next batch.  Batch buffers are fixed and charged to the
+ * HBM budget at the first submit.  Each result equals the result of the same
+ * proposals evaluated alone, bit for bit.  When max_inflight requests already
+ * have work on the device a new request queues, or with nonblocking_submit
  * the call answers LENS_EAGAIN. */
 lens_status lens_submit(lens_ctx *ctx, lens_id id, const double *params, int64_t n,
                         double *out_loglike, lens_req *out_req);

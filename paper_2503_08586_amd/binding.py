@@ -127,7 +127,8 @@ class lens_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "requests_submitted", "requests_done", "requests_failed", "requests_canceled",
         "proposals_done", "queued", "inflight", "hbm_budget_bytes", "hbm_used_bytes", "launches",
-        "latency_count")] + [(n, ctypes.c_double) for n in ("latency_p50_us", "latency_p99_us", "latency_max_us")]
+        "latency_count")] + [(n, ctypes.c_double) for n in ("latency_p50_us", "latency_p99_us", "latency_max_us")] + [
+        ("batch_pieces", ctypes.c_int64)]
 
 
 class LensError(RuntimeError):

@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <deque>
+#include <functional>
 #include <map>
 #include <tuple>
 #include <memory>
@@ -34,10 +35,20 @@ using lensk::LensGeom;
 namespace {
 
 constexpr size_t kAlign = 256;
-constexpr int kServeStreams = 4;
+constexpr int kServeStreams = 2;            // serving batches alternate over these streams
 constexpr size_t kLatencyWindow = 4096;   // completed requests kept for the latency quantiles
-constexpr int64_t kTileMax = 8192;           // proposals per serving launch
-constexpr size_t kBytesPerProposal = lensk::kStride * sizeof(double) + lensk::kPCBytes + sizeof(double);
+// Serving batches: the work of many requests on many lenses in one prep step
+// and one persistent launch per lens group.  At most kServeDepth batches are
+// in flight, so the next one is queued on the device while the last one's
+// tail drains.  A batch holds at most kBatchMax proposals from at most
+// kBatchPieces request pieces, and stops taking work past kBatchWork sub-pixel
+// evaluations (about 10 ms of the device at ~2e11 evaluations/s): large
+// enough that the launch tail is a small share, small enough that a request
+// arriving behind a full batch waits about that long.
+constexpr int kServeDepth = 2;
+constexpr int64_t kBatchMax = 32768;
+constexpr int kBatchPieces = 256;
+constexpr double kBatchWork = 2.0e9;
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
@@ -77,62 +88,29 @@ struct Request {
     double *out = nullptr;        // caller's buffer
     RState state = RState::Queued;
     lens_status status = LENS_PENDING;
-    int64_t next_tile = 0;        // first proposal not yet launched
+    int64_t next_tile = 0;        // first proposal not yet placed in a batch
     int64_t done = 0;             // proposals finished
-    int tiles_running = 0;
+    int tiles_running = 0;        // pieces in batches on the device
+    bool resident = false;        // has had work on the device (counts against max_inflight)
     bool cancel = false;
     std::vector<double> result;   // assembled here, copied to out when complete
     std::chrono::steady_clock::time_point t_submit;
 };
 
-struct Tile {
+// A contiguous range of one request's proposals inside a serving batch.
+struct Piece {
     Request *req = nullptr;
-    int64_t off = 0, n = 0;
-    size_t arena_off = 0, arena_bytes = 0;
-    hipEvent_t ev = nullptr;
-    int stream = 0;
+    int64_t off = 0, n = 0;       // request proposals [off, off + n)
+    int64_t at = 0;               // pooled position in the batch
 };
 
-// First-fit arena over one device slab and one pinned host slab of equal size.
-struct Arena {
-    size_t size = 0;
-    std::map<size_t, size_t> free_;   // offset -> length
-    void reset(size_t s)
-    {
-        size = s;
-        free_.clear();
-        if (s) free_[0] = s;
-    }
-    bool alloc(size_t len, size_t *off)
-    {
-        for (auto it = free_.begin(); it != free_.end(); ++it) {
-            if (it->second >= len) {
-                *off = it->first;
-                size_t rest = it->second - len;
-                size_t noff = it->first + len;
-                free_.erase(it);
-                if (rest) free_[noff] = rest;
-                return true;
-            }
-        }
-        return false;
-    }
-    void release(size_t off, size_t len)
-    {
-        auto it = free_.emplace(off, len).first;
-        auto nx = std::next(it);
-        if (nx != free_.end() && it->first + it->second == nx->first) {
-            it->second += nx->second;
-            free_.erase(nx);
-        }
-        if (it != free_.begin()) {
-            auto pv = std::prev(it);
-            if (pv->first + pv->second == it->first) {
-                pv->second += it->second;
-                free_.erase(it);
-            }
-        }
-    }
+// One serving batch in flight: its pieces, its slot of the serving buffers
+// and the event recorded behind its result copy.
+struct SBatch {
+    std::vector<Piece> pieces;
+    int slot = 0;
+    int64_t n = 0;
+    hipEvent_t ev = nullptr;
 };
 
 thread_local std::unordered_map<const void *, std::string> t_err;
@@ -152,6 +130,9 @@ struct Plan {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t used = 0;
+    // the same sequence without a graph: used when the capture was invalidated
+    // by another thread (an operation on the legacy default stream while it ran)
+    std::function<hipError_t(hipStream_t)> eager;
 };
 
 // One multi-lens call shape of the device-buffer entry point: the launch
@@ -325,7 +306,7 @@ struct lens_ctx {
     std::map<std::string, struct DPlan *> dplans;
 
     // serving
-    int max_inflight = 8;
+    int max_inflight = 64;
     bool nonblocking = false;
     std::mutex smu;
     std::condition_variable scv;          // wakes the scheduler
@@ -333,10 +314,11 @@ struct lens_ctx {
     std::deque<Request *> queue;          // requests with tiles still to launch
     std::map<lens_req, Request *> reqs;
     lens_req next_req = 1;
-    std::vector<Tile> running;
-    Arena arena;
-    void *d_arena = nullptr;
-    char *h_arena = nullptr;
+    std::vector<SBatch> running;          // batches in flight
+    int resident = 0;                     // requests with work placed on the device, not finished
+    bool slot_busy[kServeDepth] = {};
+    void *d_serve = nullptr;              // kServeDepth slots: tables | params | prep | out
+    char *h_serve = nullptr;              // kServeDepth slots: tables | params | out (pinned)
     hipStream_t sstreams[kServeStreams] = {};
     // batch-plan capture, under sync_mu only: no other thread enqueues on a
     // stream while it is being captured
@@ -576,7 +558,7 @@ extern "C" lens_status lens_init(const lens_init_opts *opts, lens_ctx **out)
     size_t fre = 0, tot = 0;
     if (hipMemGetInfo(&fre, &tot) != hipSuccess) return LENS_EDEVICE;
     c->budget = o.hbm_budget_bytes > 0 ? o.hbm_budget_bytes : (int64_t)(fre * 0.9);
-    c->max_inflight = o.max_inflight > 0 ? o.max_inflight : 8;
+    c->max_inflight = o.max_inflight > 0 ? o.max_inflight : 64;
     c->nonblocking = o.nonblocking_submit != 0;
     if (o.stream) {
         c->stream = (hipStream_t)o.stream;
@@ -677,10 +659,10 @@ extern "C" void lens_shutdown(lens_ctx *c)
     for (auto &kv : c->scratch) dev_free(c, kv.second->p);
     c->scratch.clear();
     if (c->d_sync) dev_free(c, c->d_sync);
-    if (c->d_arena) dev_free(c, c->d_arena);
+    if (c->d_serve) dev_free(c, c->d_serve);
     if (c->h_params) (void)hipHostFree(c->h_params);
     if (c->h_out) (void)hipHostFree(c->h_out);
-    if (c->h_arena) (void)hipHostFree(c->h_arena);
+    if (c->h_serve) (void)hipHostFree(c->h_serve);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     t_err.erase(c);
     delete c;
@@ -1501,18 +1483,39 @@ lens_status build_plan(lens_ctx *c, int32_t nlens, const lens_id *ids, const int
     // capture: the graph holds only copies and kernels (the work counters are
     // cleared by a kernel node, never by a memset node)
     // captured on a stream of its own (only this thread, under sync_mu, uses it)
+    const int64_t ntot = tot;
+    double *h_par = pl->h_params, *h_out = pl->h_out;
+    const int m0 = hmodel[0];
+    // the launch sequence, on stream st: params in, prep, persistent launches, results out
+    auto seq = [bg, ntot, one_model, m0, nlens, h_par, h_out, d_par, d_pc, d_out, d_geom, d_ls, d_lo, d_cnt, d_ps,
+                d_pm](hipStream_t st) {
+        hipError_t ce = hipMemcpyAsync(d_par, h_par, (size_t)ntot * lensk::kStride * 8, hipMemcpyHostToDevice, st);
+        if (ce == hipSuccess)
+            ce = one_model ? lensk::launch_prep(d_par, ntot, d_pc, m0, nullptr, nullptr, 0, st)
+                           : lensk::launch_prep(d_par, ntot, d_pc, 0, d_ps, d_pm, nlens, st);
+        if (ce == hipSuccess) ce = launch_groups(bg, st, d_geom, d_ls, d_lo, d_pc, d_out, d_cnt);
+        if (ce == hipSuccess) ce = hipMemcpyAsync(h_out, d_out, (size_t)ntot * 8, hipMemcpyDeviceToHost, st);
+        return ce;
+    };
+    pl->eager = seq;
     hipStream_t cs = c->cap_stream;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bail(e, "hipStreamBeginCapture");
-    hipError_t ce = hipMemcpyAsync(d_par, pl->h_params, (size_t)tot * lensk::kStride * 8, hipMemcpyHostToDevice, cs);
-    if (ce == hipSuccess)
-        ce = one_model ? lensk::launch_prep(d_par, tot, d_pc, hmodel[0], nullptr, nullptr, 0, cs)
-                       : lensk::launch_prep(d_par, tot, d_pc, 0, d_ps, d_pm, nlens, cs);
-    if (ce == hipSuccess) ce = launch_groups(bg, cs, d_geom, d_ls, d_lo, d_pc, d_out, d_cnt);
-    if (ce == hipSuccess) ce = hipMemcpyAsync(pl->h_out, d_out, (size_t)tot * 8, hipMemcpyDeviceToHost, cs);
+    const hipError_t ce = seq(cs);
     hipGraph_t graph = nullptr;
     e = hipStreamEndCapture(cs, &graph);
     pl->graph = graph;
+    if (e == hipErrorStreamCaptureInvalidated || ce == hipErrorStreamCaptureInvalidated ||
+        ce == hipErrorStreamCaptureImplicit) {
+        // another thread's legacy-stream operation broke the capture; nothing
+        // ran and the device is fine: this shape runs without a graph
+        (void)hipGetLastError();
+        if (pl->graph) (void)hipGraphDestroy(pl->graph);
+        pl->graph = nullptr;
+        log_line(c, "batch plan: capture invalidated by another thread; %d lenses run without a graph", (int)nlens);
+        *out = pl.release();
+        return LENS_OK;
+    }
     if (ce != hipSuccess) return bail(ce, "batch plan capture");
     if (e != hipSuccess) return bail(e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&pl->exec, pl->graph, nullptr, nullptr, 0);
@@ -1570,7 +1573,7 @@ extern "C" lens_status lens_loglike_multi(lens_ctx *c, int32_t nlens, const lens
     if (rs == LENS_OK) {
         pl->used = ++c->plan_clock;
         memcpy(pl->h_params, params, (size_t)tot * lensk::kStride * 8);
-        hipError_t e = hipGraphLaunch(pl->exec, c->stream);
+        hipError_t e = pl->exec ? hipGraphLaunch(pl->exec, c->stream) : pl->eager(c->stream);
         if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
         if (e != hipSuccess) rs = hip_fail(c, e, "lens_loglike_multi");
         else memcpy(out, pl->h_out, (size_t)tot * 8);
@@ -1813,141 +1816,251 @@ void finish_request(lens_ctx *c, Request *r)
         c->stats.requests_failed++;
     }
     r->lens->requests--;
+    if (r->resident) {
+        r->resident = false;
+        c->resident--;
+    }
     r->result.clear();
     r->result.shrink_to_fit();
     r->params.clear();
     r->params.shrink_to_fit();
 }
 
-void ensure_arena(lens_ctx *c)
+// Serving slot layout in bytes: tables | params | prep | out on the device,
+// tables | params | out in pinned host memory, so that one copy moves a
+// batch's lookup tables and parameter rows together.
+struct SlotLayout {
+    size_t o_geom, o_ls, o_lo, o_cnt, o_ps, o_pm;   // inside the tables
+    size_t params, pc, out;                         // device offsets
+    size_t h_out;                                   // host offset of out
+    size_t dev_bytes, host_bytes;                   // per slot
+};
+
+SlotLayout slot_layout()
 {
-    if (c->d_arena) return;
-    const size_t want = align_up((size_t)c->max_inflight * kTileMax * kBytesPerProposal + (size_t)c->max_inflight * 3 * kAlign,
-                                 1 << 20);
+    SlotLayout l{};
+    size_t o = 0;
+    l.o_geom = o;
+    o += align_up((size_t)kBatchPieces * sizeof(LensGeom), kAlign);
+    l.o_ls = o;
+    o += align_up((size_t)2 * kBatchPieces * 4, kAlign);   // every piece's start, one end per group
+    l.o_lo = o;
+    o += align_up((size_t)kBatchPieces * 8, kAlign);
+    l.o_cnt = o;
+    o += align_up((size_t)kBatchPieces * 4, kAlign);
+    l.o_ps = o;
+    o += align_up((size_t)(kBatchPieces + 1) * 8, kAlign);
+    l.o_pm = o;
+    o += align_up((size_t)kBatchPieces * 4, kAlign);
+    l.params = o;
+    const size_t pb = align_up((size_t)kBatchMax * lensk::kStride * 8, kAlign);
+    l.pc = l.params + pb;
+    l.out = l.pc + align_up((size_t)kBatchMax * lensk::kPCBytes, kAlign);
+    l.dev_bytes = l.out + align_up((size_t)kBatchMax * 8, kAlign);
+    l.h_out = l.params + pb;
+    l.host_bytes = l.h_out + align_up((size_t)kBatchMax * 8, kAlign);
+    return l;
+}
+
+// The serving buffers: kServeDepth batch slots, charged to the HBM budget at
+// the first submit (never allocated on the scheduler thread).
+void ensure_serving(lens_ctx *c)
+{
+    if (c->d_serve) return;
+    const SlotLayout l = slot_layout();
+    const size_t want = (size_t)kServeDepth * l.dev_bytes;
     if (!charge(c, (int64_t)want)) return;
-    c->d_arena = dev_alloc(c, want);
-    if (!c->d_arena) {
+    c->d_serve = dev_alloc(c, want);
+    if (!c->d_serve) {
         uncharge(c, (int64_t)want);
         return;
     }
-    if (hipHostMalloc((void **)&c->h_arena, want, hipHostMallocDefault) != hipSuccess) {
-        dev_free(c, c->d_arena);
-        c->d_arena = nullptr;
+    if (hipHostMalloc((void **)&c->h_serve, (size_t)kServeDepth * l.host_bytes, hipHostMallocDefault) != hipSuccess) {
+        dev_free(c, c->d_serve);
+        c->d_serve = nullptr;
         uncharge(c, (int64_t)want);
-        return;
     }
-    c->arena.reset(want);
 }
 
-size_t tile_bytes(int64_t n)
+// Gather the next batch (smu held): the queued requests in arrival order, each
+// giving its proposals not yet placed, until the batch holds kBatchMax
+// proposals, kBatchPieces pieces or kBatchWork sub-pixel evaluations.  A
+// request that has no work on the device yet joins only while fewer than
+// max_inflight requests do; a request that does not fit is cut, and its rest
+// goes to the next batch.
+bool form_batch(lens_ctx *c, SBatch *b)
 {
-    return align_up((size_t)n * lensk::kStride * 8, kAlign) + align_up((size_t)n * lensk::kPCBytes, kAlign) +
-           align_up((size_t)n * 8, kAlign);
-}
-
-// Launch as many tiles as slots and arena space allow (smu held).
-void admit(lens_ctx *c)
-{
-    if (c->dev_error.load() || !c->d_arena) return;
-    int stream_rr = (int)c->stats.launches;
-    while ((int)c->running.size() < c->max_inflight && !c->queue.empty()) {
-        Request *r = c->queue.front();
-        if (r->cancel) {
-            c->queue.pop_front();
-            if (r->tiles_running == 0) {
-                finish_request(c, r);
-                c->dcv.notify_all();
-            }
-            continue;
-        }
-        const int64_t n = std::min<int64_t>(kTileMax, r->n - r->next_tile);
-        const size_t bytes = tile_bytes(n);
-        size_t off = 0;
-        if (!c->arena.alloc(bytes, &off)) break;  // wait for memory to free up
-        Tile t;
-        t.req = r;
-        t.off = r->next_tile;
-        t.n = n;
-        t.arena_off = off;
-        t.arena_bytes = bytes;
-        t.stream = stream_rr++ % kServeStreams;
-        hipStream_t hs = c->sstreams[t.stream];
-        char *db = (char *)c->d_arena + off;
-        char *hb = c->h_arena + off;
-        double *dparams = (double *)db;
-        lensk::PropBlock *dpc = (lensk::PropBlock *)(db + align_up((size_t)n * lensk::kStride * 8, kAlign));
-        double *dout = (double *)((char *)dpc + align_up((size_t)n * lensk::kPCBytes, kAlign));
-        double *hparams = (double *)hb;
-        double *hout = (double *)(hb + ((char *)dout - db));
-        memcpy(hparams, r->params.data() + t.off * lensk::kStride, (size_t)n * lensk::kStride * 8);
-        hipError_t e = hipMemcpyAsync(dparams, hparams, (size_t)n * lensk::kStride * 8, hipMemcpyHostToDevice, hs);
-        if (e == hipSuccess) e = launch_lens(r->lens, dparams, dpc, n, dout, hs);
-        if (e == hipSuccess) e = hipMemcpyAsync(hout, dout, (size_t)n * 8, hipMemcpyDeviceToHost, hs);
-        if (e == hipSuccess) e = hipEventCreateWithFlags(&t.ev, hipEventDisableTiming);
-        if (e == hipSuccess) e = hipEventRecord(t.ev, hs);
-        if (e != hipSuccess) {
-            c->dev_error.store(1);
-            c->arena.release(off, bytes);
-            return;
-        }
-        c->stats.launches++;
-        r->state = RState::Running;
+    double work = 0.0;
+    int64_t n = 0;
+    for (size_t qi = 0; qi < c->queue.size(); ++qi) {
+        Request *r = c->queue[qi];
+        if (r->cancel || r->status != LENS_PENDING) continue;
+        if (!r->resident && c->resident >= c->max_inflight) continue;
+        const int64_t rem = r->n - r->next_tile;
+        if (rem <= 0) continue;
+        const Lens *L = r->lens;
+        const double per = std::max(1.0, (double)L->needed * L->g.s * L->g.s);
+        int64_t take = std::min<int64_t>(rem, kBatchMax - n);
+        // the first piece always gets at least one proposal
+        take = std::min<int64_t>(take, std::max<int64_t>(n == 0 ? 1 : 0, (int64_t)((kBatchWork - work) / per)));
+        if (take <= 0) break;
+        b->pieces.push_back(Piece{r, r->next_tile, take, n});
+        r->next_tile += take;
         r->tiles_running++;
-        r->next_tile += n;
-        if (r->next_tile >= r->n) c->queue.pop_front();
-        c->running.push_back(t);
+        r->state = RState::Running;
+        if (!r->resident) {
+            r->resident = true;
+            c->resident++;
+        }
+        n += take;
+        work += per * (double)take;
+        if (n >= kBatchMax || (int)b->pieces.size() >= kBatchPieces || work >= kBatchWork) break;
     }
+    // fully placed requests leave the queue; cancelled ones with nothing on the device finish
+    for (size_t qi = 0; qi < c->queue.size();) {
+        Request *r = c->queue[qi];
+        if (r->cancel && r->tiles_running == 0) {
+            c->queue.erase(c->queue.begin() + (long)qi);
+            finish_request(c, r);
+            c->dcv.notify_all();
+        } else if (r->next_tile >= r->n) {
+            c->queue.erase(c->queue.begin() + (long)qi);
+        } else {
+            ++qi;
+        }
+    }
+    b->n = n;
+    return n > 0;
 }
 
-// Retire finished tiles (smu held).  Returns true if anything finished.
+// Enqueue one batch on its slot's stream (smu held): the tables and parameter
+// rows in one copy, the prep step over the whole batch (per-piece model codes
+// when they differ), one persistent launch per lens group, the results back,
+// and an event.
+hipError_t launch_serving_batch(lens_ctx *c, SBatch &b)
+{
+    const SlotLayout l = slot_layout();
+    char *hb = c->h_serve + (size_t)b.slot * l.host_bytes;
+    char *db = (char *)c->d_serve + (size_t)b.slot * l.dev_bytes;
+    hipStream_t hs = c->sstreams[b.slot % kServeStreams];
+    const int np = (int)b.pieces.size();
+    std::vector<Lens *> Ls(np);
+    std::vector<int64_t> counts(np), off(np + 1, 0);
+    std::vector<int> hmodel(np);
+    bool one_model = true;
+    for (int i = 0; i < np; ++i) {
+        const Piece &pc = b.pieces[i];
+        Ls[i] = pc.req->lens;
+        counts[i] = pc.n;
+        off[i + 1] = off[i] + pc.n;
+        hmodel[i] = Ls[i]->prep_code;
+        one_model = one_model && hmodel[i] == hmodel[0];
+        memcpy(hb + l.params + (size_t)pc.at * lensk::kStride * 8, pc.req->params.data() + pc.off * lensk::kStride,
+               (size_t)pc.n * lensk::kStride * 8);
+    }
+    BatchGroups bg;
+    group_batch(c, Ls, counts.data(), off.data(), &bg);
+    memcpy(hb + l.o_geom, bg.geom.data(), bg.geom.size() * sizeof(LensGeom));
+    memcpy(hb + l.o_ls, bg.lstart.data(), bg.lstart.size() * 4);
+    memcpy(hb + l.o_lo, bg.lout.data(), bg.lout.size() * 8);
+    memcpy(hb + l.o_ps, off.data(), (size_t)(np + 1) * 8);
+    memcpy(hb + l.o_pm, hmodel.data(), (size_t)np * 4);
+    double *d_par = (double *)(db + l.params);
+    lensk::PropBlock *d_pc = (lensk::PropBlock *)(db + l.pc);
+    double *d_out = (double *)(db + l.out);
+    hipError_t e = hipMemcpyAsync(db, hb, l.params + (size_t)b.n * lensk::kStride * 8, hipMemcpyHostToDevice, hs);
+    if (e == hipSuccess)
+        e = one_model ? lensk::launch_prep(d_par, b.n, d_pc, hmodel[0], nullptr, nullptr, 0, hs)
+                      : lensk::launch_prep(d_par, b.n, d_pc, 0, (const int64_t *)(db + l.o_ps),
+                                           (const int *)(db + l.o_pm), np, hs);
+    if (e == hipSuccess)
+        e = launch_groups(bg, hs, (const LensGeom *)(db + l.o_geom), (const int *)(db + l.o_ls),
+                          (const int64_t *)(db + l.o_lo), d_pc, d_out, (unsigned int *)(db + l.o_cnt));
+    if (e == hipSuccess) e = hipMemcpyAsync(hb + l.h_out, d_out, (size_t)b.n * 8, hipMemcpyDeviceToHost, hs);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b.ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(b.ev, hs);
+    return e;
+}
+
+// A batch is done (or failed): results to its requests, finished requests
+// answered (smu held).
+void settle_batch(lens_ctx *c, SBatch &b, bool ok)
+{
+    const SlotLayout l = slot_layout();
+    const double *ho = (const double *)(c->h_serve + (size_t)b.slot * l.host_bytes + l.h_out);
+    for (const Piece &pc : b.pieces) {
+        Request *r = pc.req;
+        if (!ok) r->status = LENS_EDEVICE;
+        else if (!r->cancel && r->status == LENS_PENDING)
+            memcpy(r->result.data() + pc.off, ho + pc.at, (size_t)pc.n * 8);
+        r->tiles_running--;
+        r->done += pc.n;
+        if (r->tiles_running == 0 && (r->done >= r->n || r->cancel || r->status != LENS_PENDING)) {
+            auto it = std::find(c->queue.begin(), c->queue.end(), r);
+            if (it != c->queue.end()) c->queue.erase(it);
+            finish_request(c, r);
+        }
+    }
+    if (b.ev) (void)hipEventDestroy(b.ev);
+    b.ev = nullptr;
+    c->slot_busy[b.slot] = false;
+}
+
+// Retire finished batches (smu held).  Returns true if anything finished.
 bool retire(lens_ctx *c)
 {
     bool any = false;
     for (size_t i = 0; i < c->running.size();) {
-        Tile &t = c->running[i];
-        hipError_t q = hipEventQuery(t.ev);
+        SBatch &b = c->running[i];
+        const hipError_t q = hipEventQuery(b.ev);
         if (q == hipErrorNotReady) {
             ++i;
             continue;
         }
-        Request *r = t.req;
-        if (q != hipSuccess) {
-            c->dev_error.store(1);
-            r->status = LENS_EDEVICE;
-        } else if (!r->cancel) {
-            const char *hb = c->h_arena + t.arena_off;
-            const size_t oo = align_up((size_t)t.n * lensk::kStride * 8, kAlign) + align_up((size_t)t.n * lensk::kPCBytes, kAlign);
-            memcpy(r->result.data() + t.off, hb + oo, (size_t)t.n * 8);
-        }
-        (void)hipEventDestroy(t.ev);
-        c->arena.release(t.arena_off, t.arena_bytes);
-        r->tiles_running--;
-        r->done += t.n;
-        if (r->tiles_running == 0 && (r->done >= r->n || r->cancel || r->status != LENS_PENDING)) {
-            if (r->status != LENS_PENDING || r->cancel) {
-                // drop tiles not yet launched
-                auto it = std::find(c->queue.begin(), c->queue.end(), r);
-                if (it != c->queue.end()) c->queue.erase(it);
-            }
-            finish_request(c, r);
-        }
-        c->running[i] = c->running.back();
+        if (q != hipSuccess) c->dev_error.store(1);
+        settle_batch(c, b, q == hipSuccess);
+        if (i + 1 != c->running.size()) c->running[i] = std::move(c->running.back());
         c->running.pop_back();
         any = true;
     }
     if (c->dev_error.load()) {
-        // sticky failure: every queued request fails
-        while (!c->queue.empty()) {
-            Request *r = c->queue.front();
-            c->queue.pop_front();
-            if (r->tiles_running == 0 && (r->state == RState::Queued || r->state == RState::Running)) {
+        // sticky failure: every request with nothing left on the device fails
+        for (size_t qi = 0; qi < c->queue.size();) {
+            Request *r = c->queue[qi];
+            if (r->tiles_running == 0) {
+                c->queue.erase(c->queue.begin() + (long)qi);
                 r->status = LENS_EDEVICE;
                 finish_request(c, r);
+                any = true;
+            } else {
+                ++qi;
             }
         }
-        any = true;
     }
     return any;
+}
+
+// Launch batches while a slot is free and work is placeable (smu held).
+void admit(lens_ctx *c)
+{
+    while ((int)c->running.size() < kServeDepth && !c->dev_error.load() && c->d_serve && !c->queue.empty()) {
+        int slot = 0;
+        while (slot < kServeDepth && c->slot_busy[slot]) ++slot;
+        if (slot == kServeDepth) return;
+        SBatch b;
+        b.slot = slot;
+        if (!form_batch(c, &b)) return;
+        c->slot_busy[slot] = true;
+        const hipError_t e = launch_serving_batch(c, b);
+        if (e != hipSuccess) {
+            c->dev_error.store(1);
+            settle_batch(c, b, false);
+            return;
+        }
+        c->stats.launches++;
+        c->stats.batch_pieces += (int64_t)b.pieces.size();
+        c->running.push_back(std::move(b));
+    }
 }
 
 void scheduler_main(lens_ctx *c)
@@ -1955,16 +2068,14 @@ void scheduler_main(lens_ctx *c)
     (void)hipSetDevice(c->device);
     std::unique_lock<std::mutex> lk(c->smu);
     while (true) {
+        if (retire(c)) c->dcv.notify_all();
         admit(c);
-        if (retire(c)) {
-            c->dcv.notify_all();
-            admit(c);
-        }
+        if (c->dev_error.load() && retire(c)) c->dcv.notify_all();
         if (c->stop && c->running.empty()) break;
         if (c->running.empty()) {
             c->scv.wait(lk, [&] { return c->stop || (!c->queue.empty() && !c->dev_error.load()); });
         } else {
-            // tiles in flight: poll their events without holding the lock for long
+            // batches in flight: poll their events without holding the lock for long
             lk.unlock();
             std::this_thread::sleep_for(std::chrono::microseconds(20));
             lk.lock();
@@ -1987,10 +2098,13 @@ extern "C" lens_status lens_submit(lens_ctx *c, lens_id id, const double *params
         if (it == c->lenses.end()) return fail(c, LENS_ENOENT, "unknown lens id");
         L = it->second;
         std::lock_guard<std::mutex> sl(c->smu);
-        ensure_arena(c);  // tile buffers are allocated here, never on the scheduler thread
-        if (!c->d_arena) return fail(c, LENS_ENOMEM, "HBM budget exhausted (serving arena)");
-        if (c->nonblocking && (int)c->running.size() >= c->max_inflight)
-            return fail(c, LENS_EAGAIN, "all serving slots busy");
+        ensure_serving(c);  // batch buffers are allocated here, never on the scheduler thread
+        if (!c->d_serve) return fail(c, LENS_ENOMEM, "HBM budget exhausted (serving buffers)");
+        if (c->nonblocking) {
+            int waiting = 0;   // queued requests with nothing on the device yet
+            for (const Request *q : c->queue) waiting += q->resident ? 0 : 1;
+            if (c->resident + waiting >= c->max_inflight) return fail(c, LENS_EAGAIN, "all serving slots busy");
+        }
         Request *r = new Request();
         r->id = c->next_req++;
         r->lens = L;
@@ -2079,7 +2193,7 @@ extern "C" lens_status lens_get_stats(lens_ctx *c, lens_stats *out)
     std::lock_guard<std::mutex> lk(c->smu);
     *out = c->stats;
     out->queued = (int64_t)c->queue.size();
-    out->inflight = (int64_t)c->running.size();
+    out->inflight = (int64_t)c->resident;
     out->hbm_budget_bytes = c->budget;
     out->hbm_used_bytes = c->used.load();
     // nearest-rank quantiles of the latency window

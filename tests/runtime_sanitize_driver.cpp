@@ -174,6 +174,27 @@ int main()
     TRUE(hipDeviceSynchronize() == hipSuccess);
     TRUE(hipMemcpy(out2.data(), dout, (size_t)n * 8, hipMemcpyDeviceToHost) == hipSuccess);
     TRUE(same_bits(out, out2.data(), n));
+    // the multi-lens call on device buffers: lens A's n proposals then lens B's
+    {
+        const lens_id ids2[2] = {A, B};
+        const int64_t cnt2[2] = {n, n};
+        double *mp = nullptr, *mo = nullptr;
+        TRUE(hipMalloc(&mp, (size_t)2 * n * LENS_PARAM_STRIDE * 8) == hipSuccess);
+        TRUE(hipMalloc(&mo, (size_t)2 * n * 8) == hipSuccess);
+        TRUE(hipMemcpy(mp, P.data(), (size_t)n * LENS_PARAM_STRIDE * 8, hipMemcpyHostToDevice) == hipSuccess);
+        TRUE(hipMemcpy(mp + n * LENS_PARAM_STRIDE, P.data(), (size_t)n * LENS_PARAM_STRIDE * 8, hipMemcpyHostToDevice) ==
+             hipSuccess);
+        CK(lens_loglike_multi_device(c, 2, ids2, cnt2, mp, mo, nullptr));
+        TRUE(hipDeviceSynchronize() == hipSuccess);
+        std::vector<double> mh((size_t)2 * n), refB(n);
+        TRUE(hipMemcpy(mh.data(), mo, (size_t)2 * n * 8, hipMemcpyDeviceToHost) == hipSuccess);
+        CK(lens_loglike_batch(c, B, P.data(), n, refB.data()));
+        TRUE(same_bits(out, mh.data(), n));
+        TRUE(same_bits(refB, mh.data() + n, n));
+        EXPECT(lens_loglike_multi_device(c, 2, ids2, cnt2, nullptr, mo, nullptr), LENS_EINVAL);
+        (void)hipFree(mp);
+        (void)hipFree(mo);
+    }
     (void)hipFree(dp);
     (void)hipFree(dout);
 
@@ -362,10 +383,51 @@ int main()
                 if (lens_ensemble_destroy(c, e) != LENS_OK) bad++;
             }
         };
+        // two more threads enqueue device-buffer calls of different sizes on
+        // one shared stream: each result must equal its solo run.  Their
+        // buffers are allocated, and the stream's scratch sized, before the
+        // threads start; they use only the library and that (non-blocking)
+        // stream, never the legacy default stream, while other threads
+        // capture graphs.
+        hipStream_t shared = nullptr;
+        TRUE(hipStreamCreateWithFlags(&shared, hipStreamNonBlocking) == hipSuccess);
+        struct DevBuf {
+            double *p = nullptr, *o = nullptr;
+        } bufA, bufD;
+        TRUE(hipMalloc(&bufA.p, (size_t)700 * LENS_PARAM_STRIDE * 8) == hipSuccess);
+        TRUE(hipMalloc(&bufA.o, (size_t)700 * 8) == hipSuccess);
+        TRUE(hipMalloc(&bufD.p, (size_t)500 * LENS_PARAM_STRIDE * 8) == hipSuccess);
+        TRUE(hipMalloc(&bufD.o, (size_t)500 * 8) == hipSuccess);
+        TRUE(hipMemcpy(bufA.p, Pa.data(), (size_t)700 * LENS_PARAM_STRIDE * 8, hipMemcpyHostToDevice) == hipSuccess);
+        TRUE(hipMemcpy(bufD.p, Pd.data(), (size_t)500 * LENS_PARAM_STRIDE * 8, hipMemcpyHostToDevice) == hipSuccess);
+        {
+            const int64_t c1[1] = {500};
+            CK(lens_loglike_batch_device(c, A, bufA.p, 700, bufA.o, shared));
+            CK(lens_loglike_multi_device(c, 1, &D, c1, bufD.p, bufD.o, shared));
+            TRUE(hipStreamSynchronize(shared) == hipSuccess);
+        }
+        auto on_shared = [&](lens_id id, const DevBuf &db, int64_t np, const std::vector<double> &ref, bool multi) {
+            std::vector<double> o((size_t)np);
+            for (int r = 0; r < 10; ++r) {
+                const int64_t cnt1[1] = {np};
+                const lens_status s = multi ? lens_loglike_multi_device(c, 1, &id, cnt1, db.p, db.o, shared)
+                                            : lens_loglike_batch_device(c, id, db.p, np, db.o, shared);
+                if (s != LENS_OK ||
+                    hipMemcpyAsync(o.data(), db.o, (size_t)np * 8, hipMemcpyDeviceToHost, shared) != hipSuccess ||
+                    hipStreamSynchronize(shared) != hipSuccess || !same_bits(ref, o.data(), (size_t)np))
+                    bad++;
+            }
+        };
         std::thread t1(blocking), t2(serving), t3(sampling);
+        std::thread t4([&] { on_shared(A, bufA, 700, refA, false); });
+        std::thread t5([&] { on_shared(D, bufD, 500, refD, true); });
         t1.join();
         t2.join();
         t3.join();
+        t4.join();
+        t5.join();
+        (void)hipStreamDestroy(shared);
+        for (double *x : {bufA.p, bufA.o, bufD.p, bufD.o}) (void)hipFree(x);
         TRUE(bad.load() == 0);
     }
 

@@ -59,7 +59,7 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(binding.lens_init_opts) == 4 + 4 + 8 + 4 + 4 + 8 * 4 + 8
     assert ctypes.sizeof(binding.lens_data_desc) == 4 + 4 + 8 + 4 + 4 + 8 * 4 + 4 + 4 + 8 + 4 + 4 + 8 * 4 + 4 + 4
     assert ctypes.sizeof(binding.lens_info) == 5 * 4 + 4 + 8 * 4 + 2 * 4 + 8 + 6 * 4
-    assert ctypes.sizeof(binding.lens_stats) == 14 * 8
+    assert ctypes.sizeof(binding.lens_stats) == 15 * 8
 
 
 def test_struct_offsets_match_compiled_header(tmp_path):

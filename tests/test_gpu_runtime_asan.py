@@ -28,13 +28,18 @@ def test_runtime_under_host_asan_ubsan(tmp_path):
         pytest.skip("sanitizer driver not built (paper_2503_08586_amd.build.build_asan_driver)")
     supp = tmp_path / "lsan.supp"
     supp.write_text(LSAN_SUPPRESSIONS)
+    # The quarantine is sized above everything the driver frees, so that ASan
+    # never recycles a freed chunk of HSA-runtime memory while that runtime is
+    # being torn down at process exit (ASan then stops on an internal check of
+    # its device allocator, after the driver has finished).
     env = dict(os.environ,
-               ASAN_OPTIONS="detect_leaks=1:halt_on_error=1:verify_asan_link_order=0",
+               ASAN_OPTIONS="detect_leaks=1:halt_on_error=1:verify_asan_link_order=0:quarantine_size_mb=4096",
                LSAN_OPTIONS="suppressions=%s" % supp,
                UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1",
                LENS_LOG="1")   # the event log's formatting runs under the sanitizers too
     say("case: C-ABI driver under host ASan/UBSan")
     r = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=240)
     out = r.stdout + r.stderr
+    say("driver stdout: %r, exit status %d" % (r.stdout[-200:], r.returncode))
     say(out[-3000:])
     assert r.returncode == 0 and r.stdout.strip().endswith("ok"), out[-6000:]
