@@ -248,6 +248,20 @@ lens_status lens_loglike_amps(lens_ctx *ctx, lens_id id, const double *params, i
 lens_status lens_loglike_batch_device(lens_ctx *ctx, lens_id id, const double *d_params,
                                       int64_t n, double *d_out, void *stream);
 
+/* For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  The same
+ * call as lens_loglike_batch_device (same kernels, same results bit for bit),
+ * except that the prepared constants go to a fixed device array of
+ * LENS_NOALLOC_MAX proposals that the library sets up at lens_init, once per
+ * device, and holds until the process ends; the call itself allocates
+ * nothing.  n > LENS_NOALLOC_MAX answers LENS_EINVAL.  Every call on one GPU
+ * shares that array: calls that overlap on the device (two streams, or two
+ * contexts on the same GPU) race on it, so issue them on one stream or order
+ * them. */
+#define LENS_NOALLOC_MAX 32768
+lens_status lens_loglike_batch_device_noalloc(lens_ctx *ctx, lens_id id, const double *d_params,
+                                              int64_t n, double *d_out, void *stream);
+
 /* Many lenses in one persistent launch.  ids[i] with counts[i] proposals;
  * params holds the proposals of lens 0, then lens 1, ... ([sum counts][20]),
  * out the results in the same order.  Blocking, host buffers.  Workgroups

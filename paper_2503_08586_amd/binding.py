@@ -53,7 +53,7 @@ LENS_LIGHT_DOUBLE = 3
 EXPORTED = [
     "lens_init", "lens_shutdown", "lens_load_data", "lens_unload", "lens_get_info",
     "lens_loglike_batch", "lens_loglike_amps", "lens_loglike_batch_device", "lens_loglike_multi",
-    "lens_loglike_multi_device",
+    "lens_loglike_multi_device", "lens_loglike_batch_device_noalloc",
     "lens_submit", "lens_poll", "lens_wait", "lens_cancel", "lens_get_stats",
     "lens_model_image", "lens_selftest", "lens_psf_crop", "lens_strerror", "lens_last_error",
     "lens_ensemble_create", "lens_ensemble_run", "lens_ensemble_run_many", "lens_ensemble_get",
@@ -163,6 +163,7 @@ def load():
         "lens_loglike_batch_device": ([vp, i64, vp, i64, vp, vp], i32),
         "lens_loglike_multi": ([vp, i32, i64p, i64p, dp, dp], i32),
         "lens_loglike_multi_device": ([vp, i32, i64p, i64p, vp, vp, vp], i32),
+        "lens_loglike_batch_device_noalloc": ([vp, i64, vp, i64, vp, vp], i32),
         "lens_submit": ([vp, i64, dp, i64, dp, i64p], i32),
         "lens_poll": ([vp, i64], i32),
         "lens_wait": ([vp, i64, i64], i32),
@@ -456,6 +457,25 @@ def lens_loglike_multi(ctx, lens_ids: Sequence[int], params_list: Sequence[np.nd
     _check(ctx, load().lens_loglike_multi(ctx, len(ids), ids.ctypes.data_as(i64p), counts.ctypes.data_as(i64p),
                                           _dptr(allp), _dptr(out)))
     return np.split(out, np.cumsum(counts)[:-1])
+
+
+LENS_NOALLOC_MAX = 32768
+
+
+def lens_loglike_batch_device_noalloc(ctx, lens_id, params_dev: "torch.Tensor", out_dev: "torch.Tensor",
+                                      stream: Optional["torch.cuda.Stream"] = None):
+    """The allocation-free device-buffer call: at most LENS_NOALLOC_MAX proposals, prepared
+    constants in the library's fixed per-device array (overlapping calls on one GPU race)."""
+    if params_dev.dtype != torch.float64 or out_dev.dtype != torch.float64:
+        raise TypeError("float64 tensors expected")
+    if not (params_dev.is_cuda and out_dev.is_cuda and params_dev.is_contiguous() and out_dev.is_contiguous()):
+        raise ValueError("contiguous device tensors expected")
+    n = params_dev.shape[0]
+    if params_dev.shape != (n, STRIDE) or out_dev.shape != (n,):
+        raise ValueError("shapes must be [n, 20] and [n]")
+    s = stream if stream is not None else torch.cuda.current_stream(params_dev.device)
+    _check(ctx, load().lens_loglike_batch_device_noalloc(ctx, lens_id, params_dev.data_ptr(), n,
+                                                         out_dev.data_ptr(), s.cuda_stream))
 
 
 def lens_loglike_multi_device(ctx, lens_ids: Sequence[int], counts: Sequence[int], params_dev: "torch.Tensor",

@@ -191,6 +191,14 @@ hipError_t launch_stretch_propose(int W, int half, uint64_t t, uint64_t seed, do
 hipError_t launch_stretch_accept(int W, int half, int d, double *d_walkers, double *d_lnp, const double *d_Y,
                                  const double *d_aux, const double *d_lnl, int64_t *d_accepted, double *d_chain_w,
                                  double *d_chain_lnp, hipStream_t st);
+// The allocation-free entry point's prepared-constant scratch: a fixed device
+// array of kNoAllocMax PropBlocks (lens_kernels.hip).  noalloc_init resolves its
+// address on `device` (which must be current) once; noalloc_scratch returns it,
+// or null before that.
+constexpr int kNoAllocMax = 32768;
+constexpr int kNoAllocDevices = 64;
+hipError_t noalloc_init(int device);
+PropBlock *noalloc_scratch(int device);
 // self-test of the matrix-core operand layout: D = A B for a 16x32 by 32x16 BF16 product
 hipError_t launch_mfma_probe(const uint16_t *d_a, const uint16_t *d_b, float *d_d, hipStream_t st);
 // stage 0: binned image of one proposal into d_img [ny][nx]; stage 1: convolved,

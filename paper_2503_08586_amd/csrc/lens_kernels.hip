@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "lens_device.h"
@@ -910,6 +911,36 @@ __global__ void k_model_conv(const LensGeom g, const float *__restrict__ img, fl
         o += (double)pr;
     }
     out[i] = (float)o;
+}
+
+// ---------------------------------------------------------------------------
+// fixed scratch of the allocation-free entry point
+// ---------------------------------------------------------------------------
+// Prepared constants of up to kNoAllocMax proposals: one array per device,
+// held until the process ends.  In host code the name `scratch` is a host-side
+// stand-in, not a device address; noalloc_init resolves the device address
+// once per device and every launch takes that pointer.
+static __device__ __align__(256) PropBlock scratch[kNoAllocMax];
+static void *g_scratch_dev[kNoAllocDevices];
+static std::mutex g_scratch_mu;
+
+hipError_t noalloc_init(int device)
+{
+    if (device < 0 || device >= kNoAllocDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_dev[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_dev[device] = p;
+    return hipSuccess;
+}
+
+PropBlock *noalloc_scratch(int device)
+{
+    if (device < 0 || device >= kNoAllocDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return static_cast<PropBlock *>(g_scratch_dev[device]);
 }
 
 // ---------------------------------------------------------------------------

@@ -569,6 +569,8 @@ extern "C" lens_status lens_init(const lens_init_opts *opts, lens_ctx **out)
     for (int i = 0; i < kServeStreams; ++i)
         if (hipStreamCreateWithFlags(&c->sstreams[i], hipStreamNonBlocking) != hipSuccess) return LENS_EDEVICE;
     if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) return LENS_EDEVICE;
+    // the allocation-free entry point's fixed scratch on this device
+    if (lensk::noalloc_init(c->device) != hipSuccess) return LENS_EDEVICE;
     c->stats.hbm_budget_bytes = c->budget;
     c->autotune = o.autotune != 0;
     {
@@ -1299,6 +1301,31 @@ extern "C" lens_status lens_loglike_batch_device(lens_ctx *c, lens_id id, const 
         ScratchLayout S = carve(scr, n, false);
         hipError_t e = launch_lens(L, d_params, S.pc, n, d_out, hs);
         if (e != hipSuccess) rs = hip_fail(c, e, "lens_loglike_batch_device");
+    }
+    release(c, L);
+    return rs;
+}
+
+extern "C" lens_status lens_loglike_batch_device_noalloc(lens_ctx *c, lens_id id, const double *d_params,
+                                                         int64_t n, double *d_out, void *stream)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (n < 0 || (n > 0 && (!d_params || !d_out))) return fail(c, LENS_EINVAL, "bad params/out/n");
+    if (n > lensk::kNoAllocMax)
+        return fail(c, LENS_EINVAL, "n above LENS_NOALLOC_MAX, the fixed scratch of the allocation-free call");
+    Lens *L = acquire(c, id);
+    if (!L) return fail(c, LENS_ENOENT, "unknown lens id");
+    lens_status rs = LENS_OK;
+    if (n > 0) {
+        DeviceGuard dg(c->device);
+        lensk::PropBlock *pc = lensk::noalloc_scratch(c->device);   // resolved at lens_init
+        if (!pc) {
+            rs = fail(c, LENS_EDEVICE, "fixed scratch not set up on this device");
+        } else {
+            const hipError_t e = launch_lens(L, d_params, pc, n, d_out, (hipStream_t)stream);
+            if (e != hipSuccess) rs = hip_fail(c, e, "lens_loglike_batch_device_noalloc");
+        }
     }
     release(c, L);
     return rs;

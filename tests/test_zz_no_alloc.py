@@ -1,0 +1,54 @@
+"""The allocation-free entry point (lens_loglike_batch_device_noalloc) through
+the C ABI: two calls in a row, the second smaller, each equal bit for bit to
+lens_loglike_batch_device on the same proposals, with no device memory taken
+by the call; sizes past LENS_NOALLOC_MAX are refused on the host."""
+import numpy as np
+import pytest
+
+from gpu_cases import TOL_FP32, oracle_data, oracle_loglike, rel_err, say
+from paper_2503_08586_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def test_noalloc_matches_device_call():
+    import torch
+
+    from paper_2503_08586_amd import binding
+    say("case: allocation-free entry point, 20000 then 3000 proposals, 128x128 s=4 k=21 and split3 64x64")
+    dev = torch.device("cuda", 0)
+    with binding.LensContext(0) as ctx:
+        specs = [synth.config2(nprop=20000)[0], synth.config1(nprop=3000)[0]]
+        lids = []
+        for sp, prec in zip(specs, (0, 3)):
+            oracle_data(sp)
+            lids.append(ctx.load(sp, precision=prec))
+        st = torch.cuda.Stream()
+        for lid, sp, n in ((lids[0], specs[0], 20000), (lids[1], specs[1], 3000)):
+            P = torch.from_numpy(np.ascontiguousarray(sp.proposals[:n])).to(dev)
+            ref = torch.empty(n, dtype=torch.float64, device=dev)
+            got = torch.full((n,), np.nan, dtype=torch.float64, device=dev)
+            ctx.loglike_device(lid, P, ref, st)
+            st.synchronize()
+            torch.cuda.synchronize()
+            used = ctx.stats()["hbm_used_bytes"]
+            mem = torch.cuda.memory_allocated(dev)
+            binding.lens_loglike_batch_device_noalloc(ctx.ctx, lid, P, got, st)
+            st.synchronize()
+            assert ctx.stats()["hbm_used_bytes"] == used
+            assert torch.cuda.memory_allocated(dev) == mem
+            g, r = got.cpu().numpy(), ref.cpu().numpy()
+            assert np.array_equal(g, r), n
+            o, chi2, C = oracle_loglike(sp, sp.proposals[:6])
+            e = rel_err(g[:6], o, chi2, C)
+            say("n=%d: equal to the device call; max err vs oracle on 6: %.3e" % (n, e.max()))
+            assert e.max() <= TOL_FP32
+        # past the fixed scratch: refused before any launch
+        big = torch.zeros((binding.LENS_NOALLOC_MAX + 1, 20), dtype=torch.float64, device=dev)
+        out = torch.zeros(binding.LENS_NOALLOC_MAX + 1, dtype=torch.float64, device=dev)
+        with pytest.raises(binding.LensError) as ei:
+            binding.lens_loglike_batch_device_noalloc(ctx.ctx, lids[0], big, out, st)
+        assert ei.value.status == binding.LENS_EINVAL
+        assert float(out.abs().sum().cpu()) == 0.0
+        for lid in lids:
+            ctx.unload(lid)
