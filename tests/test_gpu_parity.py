@@ -1,8 +1,9 @@
 """GPU path (through the C ABI) against the FP64 oracle, element by element.
 
-Gate: |lnL_gpu - lnL_oracle| / (chi2/2 + |C|) <= 1e-6 for the FP32 path, with
-C = -1/2 sum_mask ln(2 pi sigma^2).  Out-of-domain proposals must be -inf on
-both sides.
+Gate: |lnL_gpu - lnL_oracle| / (chi2/2 + |C|) <= 1e-6 for the FP32 path and
+the three-plane split, 5e-6 for the two-plane split and 2e-3 for plain BF16
+(the reasons are at MODE_TOL and TOL_BF16), with C = -1/2 sum_mask
+ln(2 pi sigma^2).  Out-of-domain proposals must be -inf on both sides.
 """
 import math
 
@@ -64,13 +65,13 @@ def test_c1_all_proposals(ctx):
 
 
 def test_c2_full_call_sampled(ctx):
-    say("case: 128x128 s=4 k=21, 65536 proposals in one call, 48 sampled")
+    say("case: 128x128 s=4 k=21, 65536 proposals in one call, 1024 sampled")
     spec = synth.config2()[0]
     oracle_data(spec)
     lid = ctx.load(spec)
     got = ctx.loglike(lid, spec.proposals)
     assert got.shape == (65536,) and np.all(np.isfinite(got))
-    idx = np.random.default_rng(0).choice(65536, 48, replace=False)
+    idx = np.random.default_rng(0).choice(np.arange(1, 65535), 1022, replace=False)
     idx = np.concatenate([idx, [0, 65535]])
     _check(spec, got[idx], spec.proposals[idx], label="c2 sampled")
     # the truth itself: chi2 ~ M
