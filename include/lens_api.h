@@ -204,10 +204,13 @@ typedef struct lens_stats {
 lens_status lens_init(const lens_init_opts *opts, lens_ctx **out);
 void lens_shutdown(lens_ctx *ctx);
 
-/* Copy one lens to the device (data, sigma -> weight mask/sigma, PSF, the
- * pixel lists of the mask and of its PSF-dilated footprint).  Charged to the
- * HBM budget: LENS_ENOMEM if it does not fit.  LENS_EINVAL for a bad
- * descriptor (see the field comments). */
+/* Copy one lens to the device: the observed image d_i, its noise sigma_i and
+ * fitting region (Sec. 2.2, Eq. 5; the region of App. A) as FP32 data and
+ * weight mask/sigma, the PSF of Eq. 3 (Sec. 2.1), the supersampling factor of
+ * Sec. 2.1, the pixel lists of the mask and of its PSF-dilated footprint, and
+ * C = -1/2 sum_mask ln(2 pi sigma^2) in FP64.  Charged to the HBM budget:
+ * LENS_ENOMEM if it does not fit.  LENS_EINVAL for a bad descriptor (see the
+ * field comments); nothing is loaded then. */
 lens_status lens_load_data(lens_ctx *ctx, const lens_data_desc *desc, lens_id *out_id);
 /* Free a lens.  LENS_EBUSY while requests on it are queued or running. */
 lens_status lens_unload(lens_ctx *ctx, lens_id id);
@@ -225,8 +228,12 @@ lens_status lens_psf_crop(const double *psf, int32_t k, double psf_tail, int32_t
  * LENS_ENOENT for an unknown id. */
 lens_status lens_get_info(lens_ctx *ctx, lens_id id, lens_info *out);
 
-/* lnL of n proposals (host buffers, params [n][20], out [n]).  Blocks until
- * the results are in out.  n = 0 is a no-op. */
+/* ln P(d | xi) of Sec. 2.2, Eq. 5 for n proposals xi (host buffers, params
+ * [n][20] read, out [n] written): ray trace (Eq. 1), lens and source light
+ * (Eqs. 2, 8-10), supersample and bin (Sec. 2.1), PSF (Eq. 3), masked
+ * Gaussian chi^2.  Blocks until the results are in out.  n = 0 is a no-op.
+ * LENS_EINVAL for null pointers or n < 0, LENS_ENOENT for an unknown id;
+ * out is not written then. */
 lens_status lens_loglike_batch(lens_ctx *ctx, lens_id id, const double *params, int64_t n,
                                double *out_loglike);
 
@@ -240,9 +247,9 @@ lens_status lens_loglike_batch(lens_ctx *ctx, lens_id id, const double *params, 
 lens_status lens_loglike_amps(lens_ctx *ctx, lens_id id, const double *params, int64_t n,
                               double *out_loglike, double *out_amp);
 
-/* Same on device buffers: d_params [n][20] and d_out [n] in device memory,
- * enqueued on the hipStream_t `stream` (NULL: the default stream) and not
- * waited for.  The caller keeps both buffers alive until the stream passes
+/* lnL of Sec. 2.2, Eq. 5 on device buffers: d_params [n][20] and d_out [n]
+ * in device memory, enqueued on the hipStream_t `stream` (NULL: the default
+ * stream) and not waited for.  The caller keeps both buffers alive until the stream passes
  * the call.  Calls on one stream run in order; the library keeps a separate
  * scratch buffer per stream. */
 lens_status lens_loglike_batch_device(lens_ctx *ctx, lens_id id, const double *d_params,
@@ -262,7 +269,8 @@ lens_status lens_loglike_batch_device(lens_ctx *ctx, lens_id id, const double *d
 lens_status lens_loglike_batch_device_noalloc(lens_ctx *ctx, lens_id id, const double *d_params,
                                               int64_t n, double *d_out, void *stream);
 
-/* Many lenses in one persistent launch.  ids[i] with counts[i] proposals;
+/* Many lenses in one persistent launch (Sec. 2.2, Eq. 5 per proposal; the
+ * batched evaluation of Sec. 3.1.4 across lenses).  ids[i] with counts[i] proposals;
  * params holds the proposals of lens 0, then lens 1, ... ([sum counts][20]),
  * out the results in the same order.  Blocking, host buffers.  Workgroups
  * pull (lens, proposal) items, longest first, from a device work counter; the
@@ -305,7 +313,8 @@ lens_status lens_loglike_multi_device(lens_ctx *ctx, int32_t nlens, const lens_i
  * the call answers LENS_EAGAIN. */
 lens_status lens_submit(lens_ctx *ctx, lens_id id, const double *params, int64_t n,
                         double *out_loglike, lens_req *out_req);
-/* LENS_PENDING, LENS_OK when out is written, or the request's error.  A
+/* Non-blocking: LENS_PENDING, LENS_OK when out is written (lnL of Sec. 2.2,
+ * Eq. 5 per proposal, as lens_loglike_batch), or the request's error.  A
  * request id is forgotten after the first final answer (then LENS_ENOENT). */
 lens_status lens_poll(lens_ctx *ctx, lens_req req);
 /* Waits up to timeout_us (< 0: forever); LENS_ETIMEDOUT if still pending. */
