@@ -323,6 +323,10 @@ lens_status lens_wait(lens_ctx *ctx, lens_req req, int64_t timeout_us);
  * and discards it; out is then not written.  The id is forgotten. */
 lens_status lens_cancel(lens_ctx *ctx, lens_req req);
 lens_status lens_get_stats(lens_ctx *ctx, lens_stats *out);
+/* Zero the serving counters and empty the latency window (for per-interval
+ * figures); requests in flight are not affected, and count in the new
+ * interval when they finish. */
+lens_status lens_reset_stats(lens_ctx *ctx);
 
 /* ------------------------------------------------------------------------
  * Sampler loop on the device.  The paper's sampler runs on the host and

@@ -54,7 +54,7 @@ EXPORTED = [
     "lens_init", "lens_shutdown", "lens_load_data", "lens_unload", "lens_get_info",
     "lens_loglike_batch", "lens_loglike_amps", "lens_loglike_batch_device", "lens_loglike_multi",
     "lens_loglike_multi_device", "lens_loglike_batch_device_noalloc",
-    "lens_submit", "lens_poll", "lens_wait", "lens_cancel", "lens_get_stats",
+    "lens_submit", "lens_poll", "lens_wait", "lens_cancel", "lens_get_stats", "lens_reset_stats",
     "lens_model_image", "lens_selftest", "lens_psf_crop", "lens_strerror", "lens_last_error",
     "lens_ensemble_create", "lens_ensemble_run", "lens_ensemble_run_many", "lens_ensemble_get",
     "lens_ensemble_destroy",
@@ -169,6 +169,7 @@ def load():
         "lens_wait": ([vp, i64, i64], i32),
         "lens_cancel": ([vp, i64], i32),
         "lens_get_stats": ([vp, ctypes.POINTER(lens_stats)], i32),
+        "lens_reset_stats": ([vp], i32),
         "lens_model_image": ([vp, i64, dp, i32, dp], i32),
         "lens_selftest": ([vp, i32, dp], i32),
         "lens_psf_crop": ([dp, i32, ctypes.c_double, ctypes.POINTER(i32)], i32),
@@ -528,6 +529,10 @@ def lens_cancel(ctx, req: Request):
     _check(ctx, load().lens_cancel(ctx, req.id))
 
 
+def lens_reset_stats(ctx):
+    _check(ctx, load().lens_reset_stats(ctx))
+
+
 def lens_get_stats(ctx) -> dict:
     s = lens_stats()
     _check(ctx, load().lens_get_stats(ctx, ctypes.byref(s)))
@@ -650,6 +655,9 @@ class LensContext:
 
     def stats(self) -> dict:
         return lens_get_stats(self.ctx)
+
+    def reset_stats(self):
+        lens_reset_stats(self.ctx)
 
     def selftest(self, which=0) -> float:
         return lens_selftest(self.ctx, which)

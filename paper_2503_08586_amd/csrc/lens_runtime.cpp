@@ -2214,6 +2214,16 @@ extern "C" lens_status lens_cancel(lens_ctx *c, lens_req req)
     return LENS_OK;
 }
 
+extern "C" lens_status lens_reset_stats(lens_ctx *c)
+{
+    if (!c) return LENS_EINVAL;
+    std::lock_guard<std::mutex> lk(c->smu);
+    c->stats = lens_stats{};
+    c->lat_ring.clear();
+    c->lat_pos = 0;
+    return LENS_OK;
+}
+
 extern "C" lens_status lens_get_stats(lens_ctx *c, lens_stats *out)
 {
     if (!c || !out) return LENS_EINVAL;

@@ -218,6 +218,16 @@ def test_latency_statistics(b):
         assert 0.0 < st["latency_p50_us"] <= st["latency_p99_us"] <= st["latency_max_us"]
         assert st["latency_p99_us"] == st["latency_max_us"]          # nearest rank of 12: the largest
         assert st["latency_p50_us"] <= walls[5] and st["latency_max_us"] <= walls[-1]
+        # a reset starts a new interval: counters and the window empty, then only new requests
+        c.reset_stats()
+        st = c.stats()
+        assert st["latency_count"] == 0 and st["requests_done"] == 0 and st["launches"] == 0
+        assert st["latency_max_us"] == 0.0 and st["hbm_used_bytes"] > 0
+        for n in (300, 900, 1500):
+            assert c.wait(c.submit(lid, sp.proposals[:n])) == b.LENS_OK
+        st = c.stats()
+        assert st["latency_count"] == 3 and st["requests_done"] == 3 and st["proposals_done"] == 2700
+        assert st["launches"] >= 3 and st["batch_pieces"] >= 3
         c.unload(lid)
 
 
