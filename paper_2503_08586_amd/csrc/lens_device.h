@@ -299,6 +299,7 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
 {
     constexpr bool LENS = LM != LIGHT_SRC, SRC = LM != LIGHT_LENS, DBL = LM == LIGHT_DOUBLE;
     constexpr int IS = DBL ? 2 : LENS ? 1 : 0;   // index of the (first) source channel
+    constexpr int N = LightChannels<LM>::N;
     const int s = g.s;
     const double x0 = ((double)(x * s) - g.cfx) * g.sd;
     const double dx0 = x0 - P.xm;
@@ -307,7 +308,7 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
     double h = g.sd, lead = leading(kExp2_64);
     asm("" : "+v"(h), "+v"(lead));
 #pragma unroll
-    for (int c = 0; c < LightChannels<LM>::N; ++c) acc[c] = 0.0;
+    for (int c = 0; c < N; ++c) acc[c] = 0.0;
     const double el = DBL ? g.fix_e[0] : P.lens.e, Bl = DBL ? g.fix_B[0] : P.lens.B;
     const double es = DBL ? g.fix_e[2] : P.src.e, Bs = DBL ? g.fix_B[2] : P.src.B;
     for (int v = 0; v < s; ++v) {
@@ -318,8 +319,8 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
         const double c1 = P.sm * dy, c2 = P.cm * dy;
         const double cu1 = fma(P.bu1, yy, P.au1), cu2 = fma(P.bu2, yy, P.au2);
         const double rs = P.lens.S * dy, rq = P.lens.Q * (dy * dy);
-        double dx = dx0;
-        for (int u = 0; u < s; ++u) {
+        // the channel values of the sub-pixel at offset dx
+        auto sub = [&](double dx, double (&val)[N]) {
             if constexpr (SRC) {
                 double w1, w2;
                 if constexpr (EPL)
@@ -329,19 +330,41 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
                     ray_trace(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.ku1, dx, cu1), fma(P.ku2, dx, cu2), P, w1,
                               w2);
                 if constexpr (LENS && !DBL) {
-                    acc[0] += sersic_r2(fma(fma(P.lens.P, dx, rs), dx, rq), P.lens, lead);
-                    acc[1] += sersic_r2(ellip_r2(w1, w2, P.src), P.src, lead);
+                    val[0] = sersic_r2(fma(fma(P.lens.P, dx, rs), dx, rq), P.lens, lead);
+                    val[1] = sersic_r2(ellip_r2(w1, w2, P.src), P.src, lead);
                 } else {
                     const double lgs = log2_r2(ellip_r2(w1, w2, P.src));
-                    acc[IS] += sersic_lg(lgs, es, Bs, lead);
-                    if constexpr (DBL) acc[IS + 1] += sersic_lg(lgs + P.dlg_s, g.fix_e[3], g.fix_B[3], lead);
+                    val[IS] = sersic_lg(lgs, es, Bs, lead);
+                    if constexpr (DBL) val[IS + 1] = sersic_lg(lgs + P.dlg_s, g.fix_e[3], g.fix_B[3], lead);
                 }
             }
             if constexpr (LENS && (DBL || !SRC)) {
                 const double lgl = log2_r2(fma(fma(P.lens.P, dx, rs), dx, rq));
-                acc[0] += sersic_lg(lgl, el, Bl, lead);
-                if constexpr (DBL) acc[1] += sersic_lg(lgl + P.dlg_l, g.fix_e[1], g.fix_B[1], lead);
+                val[0] = sersic_lg(lgl, el, Bl, lead);
+                if constexpr (DBL) val[1] = sersic_lg(lgl + P.dlg_l, g.fix_e[1], g.fix_B[1], lead);
             }
+        };
+        double dx = dx0;
+        int u = 0;
+        // two sub-pixels per step (one-component and two-channel models),
+        // with the positions and the order of the additions of one at a time:
+        // measured +2% on the survey-scale lens (four channels would spill)
+        for (; !DBL && u + 2 <= s; u += 2) {
+            const double dxb = dx + h;
+            double va[N], vb[N];
+            sub(dx, va);
+            sub(dxb, vb);
+#pragma unroll
+            for (int c = 0; c < N; ++c) acc[c] += va[c];
+#pragma unroll
+            for (int c = 0; c < N; ++c) acc[c] += vb[c];
+            dx = dxb + h;
+        }
+        for (; u < s; ++u) {
+            double va[N];
+            sub(dx, va);
+#pragma unroll
+            for (int c = 0; c < N; ++c) acc[c] += va[c];
             dx += h;
         }
     }
