@@ -506,69 +506,100 @@ __device__ __forceinline__ f32x4 mfma_products(const bf16x8 (&a)[3], const bf16x
 // 41x41 workload; flushed, each FP32 partial is a short sum.
 constexpr int kFlushChunks = 2;
 
+// NTL tiles of 16 segments starting at segment t (tile j: t + 16 j ..), with
+// one load of each A chunk shared by the tiles: per output the same products
+// in the same order as a tile alone.  Lanes past the strip's last segment s1
+// compute a discarded column.  Returns this lane's chi-square contribution.
+template <int MODE, int NTL>
+__device__ __forceinline__ double conv_tiles(const LensGeom &g, const uint16_t *ring, const uint4 *__restrict__ aop,
+                                             const uint32_t *__restrict__ seg, const float *__restrict__ data,
+                                             const float *__restrict__ wgt, int t, int s0, int s1)
+{
+    constexpr int NPL = mode_planes(MODE);
+    const int lane = threadIdx.x & 63, n = lane & 15, kb = lane >> 4;
+    const int W = g.ring_w, RB = g.ring_rows, L = g.L, nch = g.nchunks, plane = g.plane;
+    int i = 8 * kb, adv = 0;     // window offset of this lane's K elements (K = 8 kb), and the rows it skips
+    while (i >= L) {             // (only for L < 32)
+        i -= L;
+        ++adv;
+    }
+    bool dummy[NTL];
+    int y[NTL], x0[NTL], slot[NTL];
+#pragma unroll
+    for (int j = 0; j < NTL; ++j) {
+        dummy[j] = t + 16 * j + n >= s1;
+        const uint32_t e = dummy[j] ? seg[s0] : seg[t + 16 * j + n];
+        y[j] = (int)(e >> 16);
+        x0[j] = (int)(e & 0xffffu);
+        slot[j] = (y[j] % RB + adv) % RB;   // ring slot of binned row y - r + a
+    }
+    double o[NTL][4] = {};       // outputs 4 kb .. 4 kb + 3 of column n, FP64
+    const uint4 *ap = aop + lane;
+    for (int ch0 = 0; ch0 < nch; ch0 += kFlushChunks) {
+        f32x4 c[NTL];
+#pragma unroll
+        for (int j = 0; j < NTL; ++j) c[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+        const int ch1 = min(ch0 + kFlushChunks, nch);
+        for (int ch = ch0; ch < ch1; ++ch) {
+            bf16x8 av[3];
+#pragma unroll
+            for (int q = 0; q < NPL; ++q) av[q] = __builtin_bit_cast(bf16x8, ap[q * 64]);
+#pragma unroll
+            for (int j = 0; j < NTL; ++j) {
+                bf16x8 bv[3];
+                const uint16_t *bp = ring + (x0[j] - g.xoff) + slot[j] * W + i;
+#pragma unroll
+                for (int q = 0; q < NPL; ++q)
+                    bv[q] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(bp + q * plane));
+                c[j] = mfma_products<MODE>(av, bv, c[j]);
+            }
+            ap += NPL * 64;
+            i += 32;
+            while (i >= L) {
+                i -= L;
+#pragma unroll
+                for (int j = 0; j < NTL; ++j) slot[j] = slot[j] + 1 == RB ? 0 : slot[j] + 1;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NTL; ++j)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[j][v] += (double)c[j][v];
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NTL; ++j) {
+        if (dummy[j]) continue;
+        const int xo = x0[j] + 4 * kb;
+        const float4 d = *reinterpret_cast<const float4 *>(data + (size_t)y[j] * g.pitch + xo);
+        const float4 w = *reinterpret_cast<const float4 *>(wgt + (size_t)y[j] * g.pitch + xo);
+        const double r0 = ((double)d.x - o[j][0]) * (double)w.x;
+        const double r1 = ((double)d.y - o[j][1]) * (double)w.y;
+        const double r2 = ((double)d.z - o[j][2]) * (double)w.z;
+        const double r3 = ((double)d.w - o[j][3]) * (double)w.w;
+        acc = fma(r0, r0, acc);
+        acc = fma(r1, r1, acc);
+        acc = fma(r2, r2, acc);
+        acc = fma(r3, r3, acc);
+    }
+    return acc;
+}
+
+// Chi-square contribution of output rows [ya, yb): each wave takes two tiles
+// of 16 segments at a time (one where only one is left), so that every A
+// chunk loaded from L2 feeds two matrix-core products.
 template <int MODE, int NT>
 __device__ __forceinline__ double conv_mfma(const LensGeom &g, const uint16_t *ring,
                                             const uint4 *__restrict__ aop, const uint32_t *__restrict__ seg,
                                             const int *__restrict__ segpre, const float *__restrict__ data,
                                             const float *__restrict__ wgt, int ya, int yb)
 {
-    constexpr int NPL = mode_planes(MODE);
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int n = lane & 15, kb = lane >> 4;
-    const int W = g.ring_w, RB = g.ring_rows, L = g.L, nch = g.nchunks, plane = g.plane;
+    const int wave = threadIdx.x >> 6;
     double acc = 0.0;
     const int s0 = segpre[ya], s1 = segpre[yb];
-    for (int t = s0 + 16 * wave; t < s1; t += 16 * (NT / 64)) {
-        // a tile of 16 segments; lanes past the strip's last segment compute a discarded column
-        const bool dummy = t + n >= s1;
-        const uint32_t e = dummy ? seg[s0] : seg[t + n];
-        const int y = (int)(e >> 16), x0 = (int)(e & 0xffffu);
-        int slot = y % RB;           // ring slot of binned row y - r + a, a = 0
-        int i = 8 * kb;              // window offset of this lane's K elements, K = 8 kb
-        while (i >= L) {             // (only for L < 32)
-            i -= L;
-            slot = slot + 1 == RB ? 0 : slot + 1;
-        }
-        const uint16_t *rb = ring + (x0 - g.xoff);
-        double o0 = 0.0, o1 = 0.0, o2 = 0.0, o3 = 0.0;   // outputs 4 kb .. 4 kb + 3 of column n, FP64
-        const uint4 *ap = aop + lane;
-        for (int ch0 = 0; ch0 < nch; ch0 += kFlushChunks) {
-            f32x4 c = {0.f, 0.f, 0.f, 0.f};
-            const int ch1 = min(ch0 + kFlushChunks, nch);
-            for (int ch = ch0; ch < ch1; ++ch) {
-                bf16x8 av[3], bv[3];
-                const uint16_t *bp = rb + slot * W + i;
-#pragma unroll
-                for (int q = 0; q < NPL; ++q) {
-                    av[q] = __builtin_bit_cast(bf16x8, ap[q * 64]);
-                    bv[q] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(bp + q * plane));
-                }
-                c = mfma_products<MODE>(av, bv, c);
-                ap += NPL * 64;
-                i += 32;
-                while (i >= L) {
-                    i -= L;
-                    slot = slot + 1 == RB ? 0 : slot + 1;
-                }
-            }
-            o0 += (double)c[0];
-            o1 += (double)c[1];
-            o2 += (double)c[2];
-            o3 += (double)c[3];
-        }
-        if (!dummy) {
-            const int xo = x0 + 4 * kb;
-            const float4 d = *reinterpret_cast<const float4 *>(data + (size_t)y * g.pitch + xo);
-            const float4 w = *reinterpret_cast<const float4 *>(wgt + (size_t)y * g.pitch + xo);
-            const double r0 = ((double)d.x - o0) * (double)w.x;
-            const double r1 = ((double)d.y - o1) * (double)w.y;
-            const double r2 = ((double)d.z - o2) * (double)w.z;
-            const double r3 = ((double)d.w - o3) * (double)w.w;
-            acc = fma(r0, r0, acc);
-            acc = fma(r1, r1, acc);
-            acc = fma(r2, r2, acc);
-            acc = fma(r3, r3, acc);
-        }
+    for (int t = s0 + 32 * wave; t < s1; t += 32 * (NT / 64)) {
+        if (t + 16 < s1) acc += conv_tiles<MODE, 2>(g, ring, aop, seg, data, wgt, t, s0, s1);
+        else acc += conv_tiles<MODE, 1>(g, ring, aop, seg, data, wgt, t, s0, s1);
     }
     return acc;
 }
