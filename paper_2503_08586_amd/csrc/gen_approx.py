@@ -6,6 +6,9 @@ Functions of the FP64 part of the forward model:
   2^f                  on |f| <= 1/2 (2^y = 2^round(y) 2^(y - round(y))), at two degrees
   b_n                  the Sersic constant of Eq. 9, the root b of P(2n, b) = 1/2
                        (P: regularized lower incomplete gamma), piecewise on n
+and the interpolation matrix that turns values at the Chebyshev nodes of
+[-1/2, 1/2] into the coefficients of the interpolating polynomial (the
+per-proposal deflection tables of the SIE).
 F and G are fitted as polynomials in w = t^2, 2^f in f, b_n in the interval's
 own variable u, by least squares in *relative* error on Chebyshev-distributed
 nodes (a near-minimax fit), with the function values taken at 40 significant
@@ -95,6 +98,33 @@ def emit_bn(mids, invh, coefs, err):
     return "\n".join(out)
 
 
+# degree of the per-interval polynomials of the SIE deflection tables
+SIE_DEG = 6
+
+
+def emit_sie_interp():
+    """Nodes t_k = cos((2k + 1) pi / (2 N)) / 2, k < N = SIE_DEG + 1, and the
+    inverse of the Vandermonde matrix V[k][i] = t_k^i, at 40 digits."""
+    n = SIE_DEG + 1
+    nodes = [mp.cos((2 * k + 1) * mp.pi / (2 * n)) / 2 for k in range(n)]
+    V = mp.matrix(n, n)
+    for k in range(n):
+        for i in range(n):
+            V[k, i] = nodes[k] ** i
+    M = V ** -1
+    snap = lambda v: 0.0 if abs(v) < 1e-30 else float(v)   # the middle node is 0: exact zeros
+    out = ["// Interpolation at the %d Chebyshev nodes of [-1/2, 1/2]: the polynomial of" % n,
+           "// degree %d through (kSieNode[k], f_k) is sum_i c_i t^i, c_i = sum_k kSieInterp[i][k] f_k" % SIE_DEG,
+           "constexpr int kSieDeg = %d;" % SIE_DEG,
+           "__device__ static constexpr double kSieNode[%d] = {" % n]
+    out += ["    %.17e," % snap(v) for v in nodes]
+    out += ["};", "__device__ static constexpr double kSieInterp[%d][%d] = {" % (n, n)]
+    for i in range(n):
+        out += ["    {" + ", ".join("%.17e" % snap(M[i, k]) for k in range(n)) + "},"]
+    out += ["};"]
+    return "\n".join(out)
+
+
 def fit(f, a, b, deg, npts=4000):
     k = np.arange(npts)
     x = 0.5 * (a + b) + 0.5 * (b - a) * np.cos(np.pi * (k + 0.5) / npts)
@@ -147,6 +177,7 @@ def main():
     # b_n: degree 10 on quarter octaves reaches the FP64 least-squares floor
     # (~2e-15; degree 8 leaves 3e-13 on the first intervals)
     print(emit_bn(*fit_bn()))
+    print(emit_sie_interp())
 
 
 if __name__ == "__main__":

@@ -203,6 +203,87 @@ __device__ __forceinline__ void ray_trace(double x1, double x2, double u1, doubl
     w2 = u2 - a2;
 }
 
+// The SIE deflection from a per-proposal table.  With s = (x1, x2) / psi,
+// q^2 s1^2 + s2^2 = 1, so alpha' = (s1 H1(u), s2 H2(u)) with u = q |s1| in
+// [0, 1]: the deflection does not change along a ray from the mass centre,
+// and both components are functions of u alone.  H1 and H2 are analytic
+// except at u = +-i q / c; on each of kSieIntervals intervals of u the table
+// holds the polynomial of degree kSieDeg through their values at the
+// interval's Chebyshev nodes (from sie_a1 and sie_a2), which reproduces them to
+// 2e-12 (q = 0.5) and 1.3e-10 (q = 0.3) relative, against 4e-10 and 1.3e-9 of
+// the polynomials behind sie_a1 and sie_a2.  A sub-pixel then takes one
+// interval lookup and two degree-6 Horner sums instead of both deflection
+// functions and, in most waves, a range reduction.  Below q = 0.3 the
+// singularities come too close and the direct functions are used.
+constexpr double kSieTabQ2 = 0.09;   // q^2 from which the table is used
+static_assert(kSieEntry >= 2 * kSieDeg + 3, "SIE table entry");
+
+__device__ __forceinline__ double *sie_table()
+{
+    __shared__ __attribute__((aligned(16))) double t[kSieIntervals * kSieEntry];
+    return t;
+}
+
+__device__ __forceinline__ bool sie_use_table(const PropBlock &P) { return P.q2m >= kSieTabQ2; }
+
+// Entry j of proposal P's table: [j + 1/2, H1 coefficients (t^0 .. t^6), H2
+// coefficients, padding], t = u kSieIntervals - (j + 1/2) in [-1/2, 1/2];
+// threads [0, 2 kSieIntervals) write one interval and one component each.
+// The caller's next barrier publishes the table.
+__device__ inline void sie_setup(const PropBlock &P)
+{
+    if (!sie_use_table(P) || threadIdx.x >= 2 * kSieIntervals) return;
+    const int j = threadIdx.x >> 1, comp = threadIdx.x & 1;
+    const double q = sqrt(P.q2m);
+    double c[kSieDeg + 1] = {};
+    // one node at a time (the kernels' register budget is set by their busiest
+    // point, and seven deflections in flight would be it)
+#pragma unroll 1
+    for (int k = 0; k <= kSieDeg; ++k) {
+        const double u = (j + 0.5 + kSieNode[k]) * (1.0 / kSieIntervals);
+        double f;
+        if (comp == 0) {
+            const double s = u / q;
+            f = sie_a1(s, P.ce, P.bsie, P.bsc) / s;
+        } else {
+            const double s = sqrt((1.0 - u) * (1.0 + u));
+            f = sie_a2(s, P.ce, P.bsie, P.bsc) / s;
+        }
+#pragma unroll
+        for (int i = 0; i <= kSieDeg; ++i) c[i] = fma(kSieInterp[i][k], f, c[i]);
+    }
+    double *e = sie_table() + j * kSieEntry;
+    if (comp == 0) e[0] = j + 0.5;
+#pragma unroll
+    for (int i = 0; i <= kSieDeg; ++i) e[1 + comp * (kSieDeg + 1) + i] = c[i];
+}
+
+// ray_trace with the deflection from the table; qn = q kSieIntervals.
+__device__ __forceinline__ void ray_trace_tab(double x1, double x2, double u1, double u2, const PropBlock &P,
+                                              double qn, double &w1, double &w2)
+{
+    const double psi2 = fma(P.q2m, x1 * x1, x2 * x2);
+    double ir;
+    if (psi2 >= 1e-30) ir = rsq_nr(psi2);
+    else ir = psi2 > 0.0 ? rsq64(psi2) : 0.0;
+    const double s1 = x1 * ir, s2 = x2 * ir;
+    const double un = fabs(s1) * qn;   // u kSieIntervals
+    const int j = min((int)un, kSieIntervals - 1);
+    const double *e = sie_table() + j * kSieEntry;
+    const double t = un - e[0];
+    double h1 = e[kSieDeg + 1];
+#pragma unroll
+    for (int i = kSieDeg - 1; i >= 0; --i) h1 = fma(h1, t, e[1 + i]);
+    // the second set of coefficients is read after the first sum: 14 fewer
+    // registers live at once (other waves hide the LDS latency)
+    asm volatile("" ::: "memory");
+    double h2 = e[2 * kSieDeg + 2];
+#pragma unroll
+    for (int i = kSieDeg - 1; i >= 0; --i) h2 = fma(h2, t, e[kSieDeg + 2 + i]);
+    w1 = u1 - s1 * h1;
+    w2 = u2 - s2 * h2;
+}
+
 // Elliptical power law (Sec. 2.4: kappa = (3 - gamma)/2 (theta_E / R_p)^(gamma - 1)
 // on the SIE's elliptical radius R_p, so gamma = 2 is the SIE).  In the frame
 // of the mass ellipse, with R e^(i phi) = q x1 + i x2, t = gamma - 1,
@@ -293,7 +374,7 @@ struct LightChannels {
 // trace; two components per galaxy share the elliptical radius of their side,
 // whose second component differs only in R_e: log2 (R/R_b)^2 = log2 (R/R_a)^2
 // + 2 log2(R_a/R_b).
-template <int LM, bool EPL = false>
+template <int LM, bool EPL = false, bool TAB = false>
 __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlock &P, int y, int x,
                                                 double (&acc)[LightChannels<LM>::N])
 {
@@ -307,6 +388,7 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
     // pairs they are spilled or rematerialised on every sub-pixel
     double h = g.sd, lead = leading(kExp2_64);
     asm("" : "+v"(h), "+v"(lead));
+    const double qn = TAB ? sqrt(P.q2m) * kSieIntervals : 0.0;
 #pragma unroll
     for (int c = 0; c < N; ++c) acc[c] = 0.0;
     const double el = DBL ? g.fix_e[0] : P.lens.e, Bl = DBL ? g.fix_B[0] : P.lens.B;
@@ -326,6 +408,9 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
                 if constexpr (EPL)
                     ray_trace_epl(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.ku1, dx, cu1), fma(P.ku2, dx, cu2), P,
                                   w1, w2);
+                else if constexpr (TAB)
+                    ray_trace_tab(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.ku1, dx, cu1), fma(P.ku2, dx, cu2), P,
+                                  qn, w1, w2);
                 else
                     ray_trace(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.ku1, dx, cu1), fma(P.ku2, dx, cu2), P, w1,
                               w2);
@@ -349,7 +434,7 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
         // two sub-pixels per step (one-component and two-channel models),
         // with the positions and the order of the additions of one at a time:
         // measured +2% on the survey-scale lens (four channels would spill)
-        for (; !DBL && u + 2 <= s; u += 2) {
+        for (; !DBL && !TAB && u + 2 <= s; u += 2) {
             const double dxb = dx + h;
             double va[N], vb[N];
             sub(dx, va);
@@ -370,32 +455,32 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
     }
 }
 
-template <bool EPL = false>
+template <bool EPL = false, bool TAB = false>
 __device__ __forceinline__ void binned_sums(const LensGeom &g, const PropBlock &P, int y, int x, double &al_out,
                                             double &as_out)
 {
     double acc[2];
-    binned_channels<LIGHT_BOTH, EPL>(g, P, y, x, acc);
+    binned_channels<LIGHT_BOTH, EPL, TAB>(g, P, y, x, acc);
     al_out = acc[0];
     as_out = acc[1];
 }
 
-template <bool EPL = false>
+template <bool EPL = false, bool TAB = false>
 __device__ __forceinline__ float binned_pixel(const LensGeom &g, const PropBlock &P, int y, int x)
 {
     double al, as;
-    binned_sums<EPL>(g, P, y, x, al, as);
+    binned_sums<EPL, TAB>(g, P, y, x, al, as);
     return (float)(fma(P.lens.I, al, P.src.I * as) * g.inv_s2);
 }
 
 // The unit-amplitude channels of pixel (y, x) (binned values, FP32), for
 // amplitudes solved by non-negative least squares (Sec. 2.3).
-template <int LM, bool EPL = false>
+template <int LM, bool EPL = false, bool TAB = false>
 __device__ __forceinline__ void binned_pixel_channels(const LensGeom &g, const PropBlock &P, int y, int x,
                                                       float (&ch)[LightChannels<LM>::N])
 {
     double acc[LightChannels<LM>::N];
-    binned_channels<LM, EPL>(g, P, y, x, acc);
+    binned_channels<LM, EPL, TAB>(g, P, y, x, acc);
 #pragma unroll
     for (int c = 0; c < LightChannels<LM>::N; ++c) ch[c] = (float)(acc[c] * g.inv_s2);
 }

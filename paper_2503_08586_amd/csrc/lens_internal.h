@@ -94,6 +94,9 @@ __host__ __device__ constexpr int mode_light(int mode)
 constexpr int kMassShift = 8;
 constexpr int kEplMaxTerms = 128;   // terms of the power-law deflection series
 constexpr double kGammaMin = 1.05, kGammaMax = 2.95;
+// per-proposal SIE deflection table in LDS: intervals of u = q |x1| / psi and
+// doubles per interval (centre, two sets of 7 coefficients, padding)
+constexpr int kSieIntervals = 16, kSieEntry = 16;
 
 // Everything a likelihood launch needs to know about one resident lens.
 struct LensGeom {
@@ -155,6 +158,9 @@ hipError_t launch_loglike(const LensGeom &g, const PropBlock *d_pc, int64_t n, d
                           hipStream_t st);
 // persistent multi-lens launch (counter reset + kernel) and its occupancy
 int batch_blocks_per_cu(int mode, int nt, size_t lds);
+// static LDS (deflection table, reduction slots) of the multi-lens kernel of a
+// mode and workgroup size; the single-lens kernels hold no more
+size_t batch_static_lds(int mode, int nt);
 int loglike_blocks_per_cu(const LensGeom &g);    // resident single-lens workgroups per CU; 0 if unknown
 hipError_t launch_batch(int mode, int nt, int grid, size_t lds, const LensGeom *d_geoms, const int *d_lstart,
                         const int64_t *d_lout, int nl, int nitems, const PropBlock *d_pc, double *d_out,

@@ -14,6 +14,7 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 #include <vector>
 
 #include "lens_device.h"
@@ -140,6 +141,14 @@ template <> struct RingStore<MODE_FP32N_DBL> : RingStoreN<4> {};
 // the mass model does not change the ring
 template <int MODE> struct RingStoreM : RingStore<mode_base(MODE)> {};
 
+// Modes whose ray trace may take the SIE deflection table: the SIE mass with a
+// lensed source.
+template <int MODE>
+__host__ __device__ constexpr bool sie_tab()
+{
+    return !mode_epl(MODE) && mode_light(MODE) != LIGHT_LENS;
+}
+
 // Binned rows [ya, yb) (all < ny) into their ring slots: every pixel in the
 // row's needed range is evaluated; the rest of the row is cleared when the
 // slot is being reused (clear = true).  Ring column of image column x is
@@ -162,19 +171,26 @@ __device__ __forceinline__ void fill_rows(const LensGeom &g, const PropBlock &P,
         }
     }
     const int fb = evpre[yb];
-    for (int f = evpre[ya] + threadIdx.x; f < fb; f += NT) {
-        const uint32_t e = evl[f];
-        const int y = (int)(e >> 16), x = (int)(e & 0xffffu);
-        int slot = slot_a + (y - ya);
-        if (slot >= RB) slot -= RB;
-        if constexpr (mode_solved(MODE)) {
-            constexpr int NCH = mode_channels(MODE);
-            float ch[NCH];
-            binned_pixel_channels<mode_light(MODE), mode_epl(MODE)>(g, P, y, x, ch);
-            RingStoreM<MODE>::put(ring, g.plane, slot * W + c0 + x, FVec<NCH>::make(ch));
-        } else
-            RingStoreM<MODE>::put(ring, g.plane, slot * W + c0 + x, binned_pixel<mode_epl(MODE)>(g, P, y, x));
-    }
+    // TAB: the SIE deflection from the proposal's table (a uniform branch)
+    auto pixels = [&](auto tab) {
+        constexpr bool TAB = decltype(tab)::value;
+        for (int f = evpre[ya] + threadIdx.x; f < fb; f += NT) {
+            const uint32_t e = evl[f];
+            const int y = (int)(e >> 16), x = (int)(e & 0xffffu);
+            int slot = slot_a + (y - ya);
+            if (slot >= RB) slot -= RB;
+            if constexpr (mode_solved(MODE)) {
+                constexpr int NCH = mode_channels(MODE);
+                float ch[NCH];
+                binned_pixel_channels<mode_light(MODE), mode_epl(MODE), TAB>(g, P, y, x, ch);
+                RingStoreM<MODE>::put(ring, g.plane, slot * W + c0 + x, FVec<NCH>::make(ch));
+            } else
+                RingStoreM<MODE>::put(ring, g.plane, slot * W + c0 + x,
+                                      binned_pixel<mode_epl(MODE), TAB>(g, P, y, x));
+        }
+    };
+    if (sie_tab<MODE>() && sie_use_table(P)) pixels(std::true_type{});
+    else pixels(std::false_type{});
 }
 
 // The strip sweep shared by every kernel: binned rows enter the ring strip by
@@ -224,6 +240,7 @@ __device__ __forceinline__ void strip_loop(const LensGeom &g, const PropBlock &P
 {
     __shared__ double red[NT / 64];
     if constexpr (mode_epl(MODE)) epl_setup(P);   // published by strip_sweep's first barrier
+    if constexpr (sie_tab<MODE>()) sie_setup(P);  // likewise
     double acc = strip_sweep<MODE, NT, double>(g, P, ring, evl, evpre, evr, conv);
     acc = wave_sum(acc);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
@@ -352,6 +369,7 @@ __device__ __forceinline__ void strip_loop_solved(const LensGeom &g, const PropB
     constexpr int NCH = mode_channels(MODE), NM = MomN<NCH>::NM;
     __shared__ double red[NM][NT / 64];
     if constexpr (mode_epl(MODE)) epl_setup(P);   // published by strip_sweep's first barrier
+    if constexpr (sie_tab<MODE>()) sie_setup(P);  // likewise
     if constexpr (NCH >= 2) {
         // each strip's moments are reduced over the wave and added to the
         // wave's LDS slots at once, so that no FP64 accumulators stay live
@@ -1195,6 +1213,17 @@ static const void *batch_kernel(int mode, int nt)
 #undef LENS_M
     default: return nullptr;
     }
+}
+
+size_t batch_static_lds(int mode, int nt)
+{
+    const void *k = batch_kernel(mode, nt);
+    hipFuncAttributes a{};
+    if (!k || hipFuncGetAttributes(&a, k) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0;
+    }
+    return (size_t)a.sharedSizeBytes;
 }
 
 int batch_blocks_per_cu(int mode, int nt, size_t lds)

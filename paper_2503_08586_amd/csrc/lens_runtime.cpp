@@ -245,16 +245,22 @@ bool set_tiles(LensGeom &g, int H, int nt, size_t lds_max)
 //   whose ring lets two workgroups share a CU (powers of two keep the MFMA
 //   convolution's 16-segment tiles spread evenly over the 8 waves);
 // - failing that, the tallest strip that fits one workgroup's LDS.
+// Each resident workgroup also holds its kernel's static LDS (the SIE
+// deflection table and the reduction slots).
 int default_strip(const LensGeom &g, size_t lds_max, size_t lds_cu, int *nt)
 {
     const size_t row_b = lensk::ring_row_bytes(g.mode, g.k, g.span);
     const auto ring = [&](int H) { return (size_t)(H + 2 * g.r) * row_b; };
-    if (lensk::mode_base(g.mode) == lensk::MODE_FP32 && ring(std::min(16, g.ny)) <= std::min(lds_max, lds_cu / 4)) {
+    const auto share = [&](size_t n, int threads) {
+        const size_t st = lensk::batch_static_lds(g.mode, threads);
+        return lds_cu / n > st ? lds_cu / n - st : 0;
+    };
+    if (lensk::mode_base(g.mode) == lensk::MODE_FP32 && ring(std::min(16, g.ny)) <= std::min(lds_max, share(4, 256))) {
         *nt = 256;
         return std::min(16, g.ny);
     }
     *nt = 512;
-    const size_t half = std::min(lds_max, lds_cu / 2);
+    const size_t half = std::min(lds_max, share(2, 512));
     for (int H : {std::min(32, g.ny), 16, 8, 4})
         if (H <= g.ny && ring(H) <= half) return H;
     for (int H = std::min(32, g.ny); H >= 1; --H)

@@ -122,3 +122,83 @@ def test_polynomial_tables_within_stated_error(name, fn, lo, hi, var):
     stated = _stated_error(name)
     # the stated error was measured at 40 digits; FP64 evaluation adds a few ulp
     assert rel.max() <= stated * 1.05 + 4e-16, (name, rel.max(), stated)
+
+
+# --- the per-proposal SIE deflection table (lens_device.h: sie_setup, ray_trace_tab)
+
+def _src_const(fname, name):
+    path = os.path.join(os.path.dirname(HDR), fname)
+    with open(path) as f:
+        m = re.search(r"\b%s\s*=\s*([-+0-9.eE]+)" % name, f.read())
+    assert m, (fname, name)
+    return float(m.group(1))
+
+
+def test_sie_interpolation_matrix():
+    """kSieInterp inverts the Vandermonde matrix of the Chebyshev nodes of
+    [-1/2, 1/2]: it maps the values of any polynomial of degree <= kSieDeg at
+    the nodes to that polynomial's coefficients."""
+    deg = int(_const("kSieDeg"))
+    nodes = _array("kSieNode")
+    M = _array("kSieInterp").reshape(deg + 1, deg + 1)
+    k = np.arange(deg + 1)
+    assert np.allclose(nodes, 0.5 * np.cos((2 * k + 1) * np.pi / (2 * (deg + 1))), rtol=0, atol=4e-16)
+    V = np.vander(nodes, deg + 1, increasing=True)
+    assert np.abs(M @ V - np.eye(deg + 1)).max() < 1e-12
+    rng = np.random.default_rng(3)
+    c = rng.normal(size=deg + 1)
+    assert np.abs(M @ (V @ c) - c).max() < 1e-12
+
+
+class SieTable:
+    """The device's table, built the way sie_setup builds it but from the
+    oracle's SIE deflection (phi = 0, centre 0: the mass frame), and evaluated
+    the way ray_trace_tab evaluates it."""
+
+    def __init__(self, orc, q, theta_e=1.3):
+        self.q, self.te, self.orc = q, theta_e, orc
+        self.NI = int(_src_const("lens_internal.h", "kSieIntervals"))
+        self.deg = int(_const("kSieDeg"))
+        nodes = _array("kSieNode")
+        M = _array("kSieInterp").reshape(self.deg + 1, self.deg + 1)
+        self.c1 = np.zeros((self.NI, self.deg + 1))
+        self.c2 = np.zeros((self.NI, self.deg + 1))
+        for j in range(self.NI):
+            u = (j + 0.5 + nodes) / self.NI
+            f1, f2 = [], []
+            for uk in u:
+                s1, s2 = uk / q, math.sqrt((1 - uk) * (1 + uk))   # on the ellipse q^2 s1^2 + s2^2 = 1
+                a1, a2 = orc.sie_deflection(theta_e, q, 0.0, 0.0, 0.0, s1, s2)
+                f1.append(a1 / s1)
+                f2.append(a2 / s2)
+            self.c1[j] = M @ np.array(f1)
+            self.c2[j] = M @ np.array(f2)
+
+    def deflection(self, x1, x2):
+        ir = 1.0 / math.sqrt(self.q * self.q * x1 * x1 + x2 * x2)
+        s1, s2 = x1 * ir, x2 * ir
+        un = abs(s1) * (math.sqrt(self.q * self.q) * self.NI)
+        j = min(int(un), self.NI - 1)
+        t = un - (j + 0.5)
+        return s1 * _horner(self.c1[j], np.array([t]))[0], s2 * _horner(self.c2[j], np.array([t]))[0]
+
+
+@pytest.mark.parametrize("q,tol", [(0.3, 2e-10), (0.4, 3e-11), (0.5, 5e-12), (0.7, 5e-13), (0.95, 1e-13),
+                                   (1.0 - 1e-9, 1e-13)])
+def test_sie_table_reproduces_the_deflection(orc, q, tol):
+    """The table's deflection at points all around the mass centre, radii
+    1e-3 .. 10 arcsec, against the oracle's closed-form SIE: the deflection
+    depends on the direction alone, so intervals of u = q |x1| / psi cover
+    every point.  The tolerance is the interpolation error for this q."""
+    assert q * q >= _src_const("lens_device.h", "kSieTabQ2") - 1e-12
+    tab = SieTable(orc, q)
+    rng = np.random.default_rng(int(q * 1000))
+    ang = np.concatenate([rng.uniform(0, 2 * np.pi, 400), np.arange(8) * np.pi / 4])
+    rad = np.exp(rng.uniform(np.log(1e-3), np.log(10.0), ang.size))
+    worst = 0.0
+    for a, r in zip(ang, rad):
+        x1, x2 = r * math.cos(a), r * math.sin(a)
+        ref = np.array(orc.sie_deflection(tab.te, q, 0.0, 0.0, 0.0, x1, x2))
+        got = np.array(tab.deflection(x1, x2))
+        worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
+    assert worst < tol, worst
