@@ -42,9 +42,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "loglike evals/s at ≤1e-6 rel err, batched vs plain; p50/p99 req latency"
 PEAK_SLOT_PER_S = 256 * 4 * 16 * 2.4e9        # FP32 VALU lane-slots/s (non-packed)
-PEAK_BF16_FLOP_S = 2.5e15                       # dense BF16 matrix-core peak
+PEAK_BF16_FLOP_S = 2.5e15                       # dense BF16 / FP16 matrix-core peak
 SLOTS_PER_EVAL = 60 + 4 * 10                    # 60 FMA-class ops + 10 quarter-rate transcendentals
-PRODUCTS = {1: 3, 2: 1, 3: 6}                   # BF16 products per PSF tap: split, bf16, split3
+PRODUCTS = {1: 3, 2: 1, 3: 6}                   # matrix-core products per PSF tap: split (FP16), bf16, split3
 DOUBLE_N = (1.0, 4.0, 1.0, 4.0)                 # fixed indices of the two-component model: disc and bulge
 
 
@@ -104,8 +104,8 @@ def gpu_data(ctx, spec):
 
 
 def path_dtype(prec):
-    """Arithmetic types of the path: FP64 ray trace, light and chi2; FP32 or BF16-MFMA convolution."""
-    return "f64+f32" if prec in (None, "fp32") else "f64+bf16"
+    """Arithmetic types of the path: FP64 ray trace, light and chi2; FP32, FP16-MFMA or BF16-MFMA convolution."""
+    return "f64+f32" if prec in (None, "fp32") else "f64+f16" if prec == "split" else "f64+bf16"
 
 
 def credited_slots(spec, info, nnls=False, model=0, prec=0):
@@ -402,7 +402,7 @@ def run_batched(args):
     import torch
 
     from paper_2503_08586_amd import binding, synth
-    mode = args.precision or "split3"
+    mode = args.precision or "split"
     prec = PREC[mode]
     specs = synth.config4()
     dev = torch.device("cuda", 0)
@@ -428,12 +428,12 @@ def run_batched(args):
     terms = roofline_terms(slots, flops, prec, kern_ms * 1e-3)
     roofline = {"bound": terms["bound"], "achieved": slots / (kern_ms * 1e-3) / 1e12,
                 "peak": PEAK_SLOT_PER_S / 1e12, "unit": "Tslot/s", "frac": terms["frac"],
-                "traffic": measured_traffic("batched") if mode == "split3" else None,
+                "traffic": measured_traffic("batched") if mode == "split" else None,
                 "mfma": {"achieved": flops * PRODUCTS.get(prec, 0) / (kern_ms * 1e-3) / 1e12,
                          "peak": PEAK_BF16_FLOP_S / 1e12, "unit": "TFLOP/s",
                          "frac": terms["t_mfma_s"] / (kern_ms * 1e-3),
-                         "note": "2 M k^2 flops per proposal times %d BF16 products per tap"
-                                 % PRODUCTS.get(prec, 0)},
+                         "note": "2 M k^2 flops per proposal times %d %s products per tap"
+                                 % (PRODUCTS.get(prec, 0), "FP16" if prec == 1 else "BF16")},
                 "terms": terms,
                 "kernel": "k_loglike_batch<%d,%d> (+ k_prep, counter reset)" % (prec, infos[0]["threads"]),
                 "kernel_ms": kern_ms, "slots_per_step": slots, "conv_flops_per_step": flops,
@@ -498,8 +498,10 @@ def run_batched(args):
         "scaling": "weak", "vs_baseline": None, "dtype": path_dtype(mode), "data": "synthetic",
         "config": {"workload": "batched precision workload: 64 lenses 200x200 px at 0.05\"/px, 4x4 supersampling, "
                                "41x41 Moffat PSF beta 3 FWHM 0.15\", r=3\" mask, 16,384 proposals per lens per step, "
-                               "one device-buffer multi-lens call (persistent launch), FP64 ray trace, %s BF16 "
-                               "matrix-core PSF convolution, FP64 chi2" % mode,
+                               "one device-buffer multi-lens call (persistent launch), FP64 ray trace, %s "
+                               "matrix-core PSF convolution, FP64 chi2"
+                               % {"split": "FP16 hi+lo split", "split3": "BF16 hi+mid+lo split",
+                                  "bf16": "BF16"}.get(mode, mode),
                    "path": "lens_loglike_multi_device", "proposals_per_step": n, "precision": mode,
                    "subpixel_evals_per_s": evals / step_s},
         "plain": plain,
@@ -909,9 +911,9 @@ def run_precision(args):
                   "roofline": roofline_terms(slots, flops, PREC[m], gpu_ms * 1e-3)}
         for l in lids:
             ctx.unload(l)
-    # value: the fastest mode gated at 1e-6 (fp32, split3); the two-plane split (~2e-6) and plain
-    # BF16 (~1e-3) are reported beside it in "modes" but never as value
-    ok = [m for m in per if m in ("fp32", "split3")] or list(per)
+    # value: the fastest mode gated at 1e-6 (fp32, split, split3); plain BF16 (~1e-3) is
+    # reported beside it in "modes" but never as value
+    ok = [m for m in per if m in ("fp32", "split", "split3")] or list(per)
     best = max(ok, key=lambda m: per[m]["evals_per_s"])
     rec = {"metric": METRIC, "value": per[best]["evals_per_s"], "unit": "loglike evals/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": per[best]["ms_per_step"],
@@ -927,7 +929,7 @@ def run_precision(args):
 
 def run_serving(args):
     """The serving sweep: offered loads of 50-100% of the saturated peak."""
-    mode = args.precision or "split3"
+    mode = args.precision or "split"
     out = serving_leg(args, mode, loads=(0.5, 0.6, 0.7, 0.8, 0.9, 1.0), nreq=args.requests)
     rec = {"metric": METRIC, "value": out["peak_evals_per_s"], "unit": "loglike evals/s", "n_gpus": 1,
            "steps": args.requests, "warmup": 0, "ms_per_step": None, "higher_is_better": True, "scaling": "weak",

@@ -45,8 +45,8 @@
  * Arithmetic: the ray trace and the Sersic exponents in FP64 (FP32 hardware
  * seeds refined by Newton steps, FP32 log2), the binned image rounded to FP32
  * once, the PSF convolution in FP32 on the vector ALU (LENS_PREC_FP32) or as a
- * BF16 matrix-core contraction with FP32 accumulation (the other precisions),
- * the chi-square reduction and the result in FP64.
+ * half-precision matrix-core contraction with FP32 accumulation flushed to FP64
+ * (the other precisions), the chi-square reduction and the result in FP64.
  *
  * Threading: every entry point is thread-safe.  Errors: every call returns a
  * lens_status; on a call error nothing is written to the outputs and
@@ -80,9 +80,10 @@ typedef int32_t lens_status;
 
 /* PSF-convolution arithmetic, chosen per lens at load. */
 #define LENS_PREC_FP32 0          /* FP32 direct convolution on the vector ALUs (lnL error < 1e-6) */
-#define LENS_PREC_BF16_SPLIT 1    /* BF16 MFMA, image and PSF split hi+lo, 3 products (16 significand
-                                     bits: lnL error ~2e-6 on a 200x200 / 41x41 image) */
-#define LENS_PREC_BF16 2          /* BF16 MFMA, single product (lnL error < 1e-3) */
+#define LENS_PREC_F16_SPLIT 1     /* FP16 MFMA, PSF and image split hi+lo, each image row at its own
+                                     power-of-two scale, 3 products (22 significand bits; lnL error
+                                     < 1e-6); the fastest of the < 1e-6 precisions */
+#define LENS_PREC_BF16 2          /* BF16 MFMA, single product (lnL error < 2e-3) */
 #define LENS_PREC_BF16_SPLIT3 3   /* BF16 MFMA, hi+mid+lo split, 6 products (lnL error < 1e-6) */
 
 /* Light amplitudes, chosen per lens at load. */

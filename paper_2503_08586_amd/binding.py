@@ -35,7 +35,7 @@ LENS_ECANCELED = -7
 LENS_ETIMEDOUT = -8
 
 LENS_PREC_FP32 = 0
-LENS_PREC_BF16_SPLIT = 1
+LENS_PREC_F16_SPLIT = 1
 LENS_PREC_BF16 = 2
 LENS_PREC_BF16_SPLIT3 = 3
 

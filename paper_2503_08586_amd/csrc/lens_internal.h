@@ -71,6 +71,16 @@ __host__ __device__ constexpr int mode_planes(int mode)
     return mode_base(mode) == MODE_SPLIT ? 2 : mode_base(mode) == MODE_SPLIT3 ? 3 : 1;
 }
 __host__ __device__ constexpr bool mode_solved(int mode) { return mode_base(mode) >= MODE_FP32N; }
+// Matrix-core window of a 16-wide output segment along one PSF row: 16 + k - 1
+// ring columns, rounded up to 8 (BF16 modes: K-chunks of 32 run on across PSF
+// rows) or to 32 (the FP16 split: every K-chunk within one ring row, whose
+// scale it carries).
+__host__ __device__ constexpr int window_len(int mode, int k)
+{
+    return mode_base(mode) == MODE_SPLIT ? (k + 15 + 31) / 32 * 32 : (k + 15 + 7) / 8 * 8;
+}
+// ring rows the FP16 split's per-row scales are kept for (strip + PSF halo)
+constexpr int kRingRowsMax = 128;
 // binned channels (components at unit amplitude) of a solved-amplitude mode
 __host__ __device__ constexpr int mode_channels(int mode)
 {
@@ -108,7 +118,7 @@ struct LensGeom {
     int ring_rows;         // strip_h + 2r binned rows kept in LDS
     int ring_w;            // elements per LDS row (FP32 ring: floats; MFMA ring: bf16 per plane)
     int plane;             // MFMA ring: elements per bf16 plane (ring_rows * ring_w)
-    int L;                 // MFMA: window length per segment, 16 + k - 1 rounded up to 8
+    int L;                 // MFMA: window length per segment (window_len)
     int nchunks;           // MFMA: K-chunks of 32, ceil(k L / 32)
     int nstrips;           // ceil(ny / strip_h)
     int xoff;              // ring column of image column x is x + r - xoff (a multiple of 16 at or left of
@@ -119,6 +129,7 @@ struct LensGeom {
     float inv_s2;          // 1/s^2
     double norm;           // C = -1/2 sum_mask ln(2 pi sigma^2)
     double dd;             // solved amplitudes: sum_mask (w d)^2 in FP64 of the FP32 w and d
+    double conv_scale;     // FP16 split: 2^-j, undoing the power of two the PSF planes were scaled by
     double fix_e[4];       // MODE_FP32N_DBL: 1/(2n) of the fixed indices (lens a, lens b, source a, source b)
     double fix_B[4];       //   and b_n log2 e
     const float *psf;      // flipped kernel Kf[a][b] = K[k-1-a][k-1-b], [k][k]

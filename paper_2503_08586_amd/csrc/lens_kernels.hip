@@ -54,6 +54,14 @@ __global__ void __launch_bounds__(256) k_prep(const double *__restrict__ params,
 // fused likelihood: shared pieces
 // ---------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+// the matrix-core A operands in the global address space: their loads then
+// count on vmcnt alone, and an LDS wait does not also wait for them
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef const __attribute__((address_space(1))) u32x4 *gptr4;
+// and the B operands' LDS ring, kept in the LDS address space through arrays
+typedef const __attribute__((address_space(3))) uint16_t *lptr16;
+typedef const __attribute__((address_space(3))) u32x4 *lptr4;
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ double wave_sum(double v)
@@ -73,7 +81,9 @@ __device__ __forceinline__ uint16_t bf16_rn(float f)
 __device__ __forceinline__ float bf16_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 // How a binned value is kept in the LDS ring: FP32, or NPL BF16 planes whose
-// sum is the value (hi, hi + lo, hi + mid + lo).
+// sum is the value (hi, hi + lo, hi + mid + lo).  The FP16 split first keeps
+// the FP32 value's upper and lower 16 bits in its two planes; once the row is
+// complete, convert_rows_f16 turns them into half planes at the row's scale.
 template <int MODE>
 struct RingStore {
     static constexpr int NPL = mode_planes(MODE);
@@ -81,6 +91,11 @@ struct RingStore {
     {
         if (MODE == MODE_FP32) {
             static_cast<float *>(ring)[idx] = v;
+        } else if (MODE == MODE_SPLIT) {
+            uint16_t *b = static_cast<uint16_t *>(ring);
+            const uint32_t u = __float_as_uint(v);
+            b[idx] = (uint16_t)(u >> 16);
+            b[plane + idx] = (uint16_t)u;
         } else {
             uint16_t *b = static_cast<uint16_t *>(ring);
             const uint16_t h = bf16_rn(v);
@@ -141,6 +156,57 @@ template <> struct RingStore<MODE_FP32N_DBL> : RingStoreN<4> {};
 // the mass model does not change the ring
 template <int MODE> struct RingStoreM : RingStore<mode_base(MODE)> {};
 
+// FP16 split: per ring slot, the largest |value| of the row being filled (FP32
+// bits, by atomic max) and, once converted, the factor 2^-j that undoes the
+// row's scale.
+__device__ __forceinline__ uint32_t *f16_rowmax()
+{
+    __shared__ uint32_t m[kRingRowsMax];
+    return m;
+}
+__device__ __forceinline__ float *f16_rowscale()
+{
+    __shared__ float sc[kRingRowsMax];
+    return sc;
+}
+
+// Binned rows [ya, yb) of the FP16 split, complete in the ring as FP32 bits:
+// each row scaled by the power of two 2^j that brings its largest |value|
+// into [2^13, 2^14), and split into the nearest half h and the nearest half to
+// the remainder.  The pair keeps 22 significant bits of every value from
+// 2^-3 of the row's largest up; below, the remainder is subnormal and the
+// absolute error stays under 2^-39 of the row's largest value.  One wave per
+// row; the row's maximum is cleared for the slot's next row after the next
+// barrier (clear_rowmax_f16).
+template <int NT>
+__device__ __forceinline__ void convert_rows_f16(const LensGeom &g, uint16_t *ring, int ya, int yb)
+{
+    const int W = g.ring_w, RB = g.ring_rows, lane = threadIdx.x & 63;
+    for (int y = ya + (int)(threadIdx.x >> 6); y < yb; y += NT / 64) {
+        const int slot = (y + g.r) % RB;
+        const float m = __uint_as_float(f16_rowmax()[slot]);
+        int e = 0;
+        (void)frexpf(m, &e);                       // m < 2^e
+        e = m > 0.0f ? max(e, -100) : 14;          // tiny rows: the scale stays finite
+        const float sc = ldexpf(1.0f, 14 - e), inv = ldexpf(1.0f, e - 14);
+        if (lane == 0) f16_rowscale()[slot] = inv;
+        uint16_t *hi = ring + slot * W, *lo = hi + g.plane;
+        for (int x = lane; x < W; x += 64) {
+            const float v = __uint_as_float(((uint32_t)hi[x] << 16) | lo[x]) * sc;
+            const _Float16 h = (_Float16)v;
+            const _Float16 l = (_Float16)(v - (float)h);
+            hi[x] = __builtin_bit_cast(uint16_t, h);
+            lo[x] = __builtin_bit_cast(uint16_t, l);
+        }
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void clear_rowmax_f16(const LensGeom &g, int ya, int yb)
+{
+    for (int y = ya + (int)threadIdx.x; y < yb; y += NT) f16_rowmax()[(y + g.r) % g.ring_rows] = 0u;
+}
+
 // Modes whose ray trace may take the SIE deflection table: the SIE mass with a
 // lensed source.
 template <int MODE>
@@ -184,9 +250,11 @@ __device__ __forceinline__ void fill_rows(const LensGeom &g, const PropBlock &P,
                 float ch[NCH];
                 binned_pixel_channels<mode_light(MODE), mode_epl(MODE), TAB>(g, P, y, x, ch);
                 RingStoreM<MODE>::put(ring, g.plane, slot * W + c0 + x, FVec<NCH>::make(ch));
-            } else
-                RingStoreM<MODE>::put(ring, g.plane, slot * W + c0 + x,
-                                      binned_pixel<mode_epl(MODE), TAB>(g, P, y, x));
+            } else {
+                const float v = binned_pixel<mode_epl(MODE), TAB>(g, P, y, x);
+                RingStoreM<MODE>::put(ring, g.plane, slot * W + c0 + x, v);
+                if constexpr (mode_base(MODE) == MODE_SPLIT) atomicMax(&f16_rowmax()[slot], __float_as_uint(fabsf(v)));
+            }
         }
     };
     if (sie_tab<MODE>() && sie_use_table(P)) pixels(std::true_type{});
@@ -205,8 +273,15 @@ __device__ __forceinline__ Acc strip_sweep(const LensGeom &g, const PropBlock &P
     const int nwords = (mode_base(MODE) == MODE_FP32 ? RB * g.ring_w
                         : mode_solved(MODE)            ? mode_channels(MODE) * RB * g.ring_w
                                                        : RB * g.ring_w * mode_planes(MODE) / 2) / 4;
+    constexpr bool F16 = mode_base(MODE) == MODE_SPLIT;
     float4 *r4 = static_cast<float4 *>(ring);
     for (int i = threadIdx.x; i < nwords; i += NT) r4[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if constexpr (F16) {
+        for (int i = threadIdx.x; i < RB; i += NT) {
+            f16_rowmax()[i] = 0u;
+            f16_rowscale()[i] = 1.0f;   // rows above the image stay zero at scale 1
+        }
+    }
     __syncthreads();
     // binned rows [0, r) precede the first strip
     fill_rows<MODE, NT>(g, P, ring, evl, evpre, evr, 0, min(r, ny), false);
@@ -225,6 +300,13 @@ __device__ __forceinline__ Acc strip_sweep(const LensGeom &g, const PropBlock &P
         }
         if (ya < ny) fill_rows<MODE, NT>(g, P, ring, evl, evpre, evr, ya, min(yb, ny), y0 > 0);
         __syncthreads();
+        if constexpr (F16) {
+            // the rows that entered the ring since the last conversion, as halves
+            const int ca = y0 == 0 ? 0 : ya;
+            convert_rows_f16<NT>(g, static_cast<uint16_t *>(ring), ca, yb);
+            __syncthreads();
+            clear_rowmax_f16<NT>(g, ca, yb);   // read for the last time above
+        }
         acc += conv(y0, min(y0 + H, ny), strip);
     }
     return acc;
@@ -490,18 +572,18 @@ k_loglike_fp32(const LensGeom g, const PropBlock *__restrict__ pc, const float *
 }
 
 // ---------------------------------------------------------------------------
-// PSF convolution as a BF16 matrix-core contraction
+// PSF convolution as a matrix-core contraction
 // ---------------------------------------------------------------------------
 // For a segment of 16 outputs x0..x0+15 of row y,
 //   out[x0 + j] = sum_{a, i} T_a[j, i] w_a[i],  T_a[j, i] = Kf[a][i - j] (0 <= i - j < k),
-//   w_a[i] = binned[y - r + a][x0 - r + i],  i < L = 16 + k - 1 (rounded up to 8),
+//   w_a[i] = binned[y - r + a][x0 - r + i],  i < L (window_len: 16 + k - 1 rounded up),
 // i.e. C = A B with A the banded Toeplitz expansion of the flipped PSF
 // (16 x kL, built once per lens) and the B column of a segment its stacked
-// PSF-row windows.  One v_mfma_f32_16x16x32_bf16 takes 32 of the kL products
-// for 16 segments at once.  Operand layout (wave64): lane l holds A row l%16,
-// B column l%16, K elements 8(l/16)..8(l/16)+7 of the 32; D rows 4(l/16)..+3
-// of column l%16.  Split modes form (a_hi + a_lo)(b_hi + b_lo) without the
-// lo*lo term, or the six products of three planes that reach 2^-24.
+// PSF-row windows.  One v_mfma_f32_16x16x32_{bf16,f16} takes 32 of the kL
+// products for 16 segments at once.  Operand layout (wave64): lane l holds A
+// row l%16, B column l%16, K elements 8(l/16)..8(l/16)+7 of the 32; D rows
+// 4(l/16)..+3 of column l%16.  The BF16 split3 forms the six products of three
+// planes that reach 2^-24; the FP16 split is conv_tiles_f16.
 template <int MODE>
 __device__ __forceinline__ f32x4 mfma_products(const bf16x8 (&a)[3], const bf16x8 (&b)[3], f32x4 c)
 {
@@ -509,8 +591,6 @@ __device__ __forceinline__ f32x4 mfma_products(const bf16x8 (&a)[3], const bf16x
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[2], b[0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[2], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[1], c, 0, 0, 0);
-    }
-    if (mode_base(MODE) == MODE_SPLIT || mode_base(MODE) == MODE_SPLIT3) {
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[1], b[0], c, 0, 0, 0);
         c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[0], b[1], c, 0, 0, 0);
     }
@@ -552,7 +632,7 @@ __device__ __forceinline__ double conv_tiles(const LensGeom &g, const uint16_t *
         slot[j] = (y[j] % RB + adv) % RB;   // ring slot of binned row y - r + a
     }
     double o[NTL][4] = {};       // outputs 4 kb .. 4 kb + 3 of column n, FP64
-    const uint4 *ap = aop + lane;
+    gptr4 ap = (gptr4)aop + lane;
     for (int ch0 = 0; ch0 < nch; ch0 += kFlushChunks) {
         f32x4 c[NTL];
 #pragma unroll
@@ -603,6 +683,99 @@ __device__ __forceinline__ double conv_tiles(const LensGeom &g, const uint16_t *
     return acc;
 }
 
+// The FP16 split: the PSF (scaled by 2^j, conv_scale = 2^-j) and each ring row
+// (at its own scale) as hi + lo halves, three products a_hi b_hi + a_lo b_hi +
+// a_hi b_lo per tap (the dropped a_lo b_lo and both truncations are each below
+// 2^-22 of the tap's product).  A PSF row's window is CPR = L / 32 whole
+// K-chunks of one ring row, so the FP32 partial of each PSF row is flushed to
+// the FP64 output times the two scales, exactly (powers of two).  The A
+// operands stream from L2 two PSF rows ahead of their products (the operand
+// array holds two rows of padding), the B operands of a row are read from LDS
+// before its first product.  Same operand layout and output mapping as
+// conv_tiles.
+template <int NTL, int CPR>
+__device__ __forceinline__ double conv_tiles_f16(const LensGeom &g, const uint16_t *ring,
+                                                 const uint4 *__restrict__ aop, const uint32_t *__restrict__ seg,
+                                                 const float *__restrict__ data, const float *__restrict__ wgt, int t,
+                                                 int s0, int s1)
+{
+    const int lane = threadIdx.x & 63, n = lane & 15, kb = lane >> 4;
+    const int W = g.ring_w, RB = g.ring_rows, plane = g.plane, k = g.k;
+    const float *rs = f16_rowscale();
+    bool dummy[NTL];
+    int y[NTL], x0[NTL], slot[NTL];
+#pragma unroll
+    for (int j = 0; j < NTL; ++j) {
+        dummy[j] = t + 16 * j + n >= s1;
+        const uint32_t e = dummy[j] ? seg[s0] : seg[t + 16 * j + n];
+        y[j] = (int)(e >> 16);
+        x0[j] = (int)(e & 0xffffu);
+        slot[j] = y[j] % RB;   // ring slot of binned row y - r + a at a = 0
+    }
+    double o[NTL][4] = {};     // outputs 4 kb .. 4 kb + 3 of column n, FP64
+    gptr4 ap = (gptr4)aop + lane;
+    for (int a = 0; a < k; ++a) {
+        f32x4 c[NTL];
+        lptr16 bp[NTL];
+#pragma unroll
+        for (int j = 0; j < NTL; ++j) {
+            c[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+            bp[j] = (lptr16)ring + slot[j] * W + (x0[j] - g.xoff) + 8 * kb;
+        }
+#pragma unroll
+        for (int h = 0; h < CPR; ++h) {
+            const f16x8 a0 = __builtin_bit_cast(f16x8, ap[0]), a1 = __builtin_bit_cast(f16x8, ap[64]);
+            ap += 2 * 64;
+#pragma unroll
+            for (int j = 0; j < NTL; ++j) {
+                const f16x8 b0 = __builtin_bit_cast(f16x8, *(lptr4)(bp[j] + 32 * h));
+                const f16x8 b1 = __builtin_bit_cast(f16x8, *(lptr4)(bp[j] + 32 * h + plane));
+                c[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, b1, c[j], 0, 0, 0);
+                c[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1, b0, c[j], 0, 0, 0);
+                c[j] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0, b0, c[j], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < NTL; ++j) {
+            const double sc = (double)rs[slot[j]] * g.conv_scale;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[j][v] = fma((double)c[j][v], sc, o[j][v]);
+            slot[j] = slot[j] + 1 == RB ? 0 : slot[j] + 1;
+        }
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int j = 0; j < NTL; ++j) {
+        if (dummy[j]) continue;
+        const int xo = x0[j] + 4 * kb;
+        const float4 d = *reinterpret_cast<const float4 *>(data + (size_t)y[j] * g.pitch + xo);
+        const float4 w = *reinterpret_cast<const float4 *>(wgt + (size_t)y[j] * g.pitch + xo);
+        const double r0 = ((double)d.x - o[j][0]) * (double)w.x;
+        const double r1 = ((double)d.y - o[j][1]) * (double)w.y;
+        const double r2 = ((double)d.z - o[j][2]) * (double)w.z;
+        const double r3 = ((double)d.w - o[j][3]) * (double)w.w;
+        acc = fma(r0, r0, acc);
+        acc = fma(r1, r1, acc);
+        acc = fma(r2, r2, acc);
+        acc = fma(r3, r3, acc);
+    }
+    return acc;
+}
+
+// Two tiles at a time where two are left (PSF rows of three K-chunks, k > 49:
+// one at a time, which keeps the registers of the prefetched operands at the
+// two-chunk level).
+template <int CPR>
+__device__ __forceinline__ double conv_pair_f16(const LensGeom &g, const uint16_t *ring, const uint4 *__restrict__ aop,
+                                                const uint32_t *__restrict__ seg, const float *__restrict__ data,
+                                                const float *__restrict__ wgt, int t, int s0, int s1)
+{
+    if (CPR <= 2 && t + 16 < s1) return conv_tiles_f16<2, CPR>(g, ring, aop, seg, data, wgt, t, s0, s1);
+    double acc = conv_tiles_f16<1, CPR>(g, ring, aop, seg, data, wgt, t, s0, s1);
+    if (CPR > 2 && t + 16 < s1) acc += conv_tiles_f16<1, CPR>(g, ring, aop, seg, data, wgt, t + 16, s0, s1);
+    return acc;
+}
+
 // Chi-square contribution of output rows [ya, yb): each wave takes two tiles
 // of 16 segments at a time (one where only one is left), so that every A
 // chunk loaded from L2 feeds two matrix-core products.
@@ -616,8 +789,16 @@ __device__ __forceinline__ double conv_mfma(const LensGeom &g, const uint16_t *r
     double acc = 0.0;
     const int s0 = segpre[ya], s1 = segpre[yb];
     for (int t = s0 + 32 * wave; t < s1; t += 32 * (NT / 64)) {
-        if (t + 16 < s1) acc += conv_tiles<MODE, 2>(g, ring, aop, seg, data, wgt, t, s0, s1);
-        else acc += conv_tiles<MODE, 1>(g, ring, aop, seg, data, wgt, t, s0, s1);
+        if constexpr (mode_base(MODE) == MODE_SPLIT) {
+            // K-chunks per PSF row: window_len(k) / 32, at most 3 (k <= 63)
+            const int cpr = g.L >> 5;
+            if (cpr == 2) acc += conv_pair_f16<2>(g, ring, aop, seg, data, wgt, t, s0, s1);
+            else if (cpr == 1) acc += conv_pair_f16<1>(g, ring, aop, seg, data, wgt, t, s0, s1);
+            else acc += conv_pair_f16<3>(g, ring, aop, seg, data, wgt, t, s0, s1);
+        } else {
+            if (t + 16 < s1) acc += conv_tiles<MODE, 2>(g, ring, aop, seg, data, wgt, t, s0, s1);
+            else acc += conv_tiles<MODE, 1>(g, ring, aop, seg, data, wgt, t, s0, s1);
+        }
     }
     return acc;
 }
@@ -1005,8 +1186,7 @@ double host_sersic_bn(double n) { return sersic_bn(n); }
 int ring_width(int mode, int k, int span)
 {
     if (mode_base(mode) == MODE_FP32 || mode_solved(mode)) return (span + 3) / 4 * 4 + 4 * choose_kc(k);
-    const int L = (16 + k - 1 + 7) / 8 * 8;
-    return (span + 15) / 16 * 16 + L;
+    return (span + 15) / 16 * 16 + window_len(mode, k);
 }
 
 size_t ring_row_bytes(int mode, int k, int span)

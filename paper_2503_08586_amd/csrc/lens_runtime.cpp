@@ -160,18 +160,36 @@ float bf16_to_float(uint16_t h)
     return f;
 }
 
-// The flipped PSF Kf[a][b] = K[k-1-a][k-1-b] as npl BF16 planes per tap
-// ([k*k][npl]), each plane the nearest BF16 to what the earlier ones leave of
-// the FP32 tap, except that the last plane of some taps is rounded to its
-// other neighbour so that the planes sum, over the whole kernel, to the FP64
-// sum of K.  The kernel's rounding would otherwise scale every model pixel by
+// round-to-nearest-even FP32 -> IEEE half (subnormals kept) and back
+uint16_t f16_rn_host(float f)
+{
+    const _Float16 h = (_Float16)f;
+    uint16_t u;
+    memcpy(&u, &h, 2);
+    return u;
+}
+
+float f16_to_float(uint16_t u)
+{
+    _Float16 h;
+    memcpy(&h, &u, 2);
+    return (float)h;
+}
+
+// The flipped PSF Kf[a][b] = K[k-1-a][k-1-b], times scale (a power of two),
+// as npl 16-bit planes per tap ([k*k][npl]; BF16, or IEEE half if f16), each
+// plane the nearest value to what the earlier ones leave of the FP32 tap,
+// except that the last plane of some taps is rounded to its other neighbour so
+// that the planes sum, over the whole kernel, to the FP64 sum of scale K.  The kernel's rounding would otherwise scale every model pixel by
 // a common factor 1 + sum(K - planes)/sum(K), off by up to ~2^-17 for two
 // planes, an error that the chi-square does not average away.  Taps are
 // flipped in the order of the least added error, each only when that brings
 // the residual sum closer to zero; no tap's error exceeds one unit of its last
 // plane.
-std::vector<uint16_t> split_psf_planes(const double *psf, int k, int npl)
+std::vector<uint16_t> split_psf_planes(const double *psf, int k, int npl, bool f16 = false, double scale = 1.0)
 {
+    uint16_t (*rn)(float) = f16 ? f16_rn_host : bf16_rn_host;
+    float (*val)(uint16_t) = f16 ? f16_to_float : bf16_to_float;
     const int n = k * k;
     std::vector<uint16_t> out((size_t)n * npl);
     std::vector<double> e(n), ealt(n);
@@ -179,27 +197,27 @@ std::vector<uint16_t> split_psf_planes(const double *psf, int k, int npl)
     double E = 0.0;
     for (int t = 0; t < n; ++t) {
         const int a = t / k, b = t % k;
-        const double K = psf[(size_t)(k - 1 - a) * k + (k - 1 - b)];
+        const double K = scale * psf[(size_t)(k - 1 - a) * k + (k - 1 - b)];
         float v = (float)K;
         double sum = 0.0;
         for (int q = 0; q < npl; ++q) {
-            const uint16_t h = bf16_rn_host(v);
+            const uint16_t h = rn(v);
             out[(size_t)t * npl + q] = h;
-            if (q + 1 < npl) v -= bf16_to_float(h);   // exact: v and its nearest BF16 share the leading bits
-            sum += (double)bf16_to_float(h);
+            if (q + 1 < npl) v -= val(h);   // exact: v and its nearest 16-bit value share the leading bits
+            sum += (double)val(h);
         }
         e[t] = K - sum;
         E += e[t];
-        // the other BF16 neighbour of the last plane's target v
+        // the other 16-bit neighbour of the last plane's target v
         const uint16_t h = out[(size_t)t * npl + npl - 1];
-        const float fh = bf16_to_float(h);
+        const float fh = val(h);
         alt[t] = h;
         ealt[t] = e[t];
         if (v != 0.0f && fh != 0.0f && std::isfinite(fh) && fh != v) {
-            // one BF16 unit towards v: +1 in the magnitude bits moves away from 0
+            // one unit towards v: +1 in the magnitude bits moves away from 0 (both formats)
             const bool up_mag = std::fabs(v) > std::fabs(fh);
             const uint16_t o = up_mag ? (uint16_t)(h + 1) : (uint16_t)(h - 1);
-            const float fo = bf16_to_float(o);
+            const float fo = val(o);
             if (std::isfinite(fo) && (fo > 0.0f) == (fh > 0.0f)) {
                 alt[t] = o;
                 ealt[t] = e[t] + (double)fh - (double)fo;
@@ -230,6 +248,7 @@ bool set_tiles(LensGeom &g, int H, int nt, size_t lds_max)
     H = std::min(H, g.ny);
     const size_t bytes = (size_t)(H + 2 * g.r) * lensk::ring_row_bytes(g.mode, g.k, g.span);
     if (bytes > lds_max) return false;
+    if (lensk::mode_base(g.mode) == lensk::MODE_SPLIT && H + 2 * g.r > lensk::kRingRowsMax) return false;
     g.nt = nt;
     g.strip_h = H;
     g.ring_rows = H + 2 * g.r;
@@ -925,6 +944,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     cvpre[ny] = (int)cvl.size();
     LensGeom g{};
     g.ny = ny; g.nx = nx; g.s = s; g.k = k; g.r = r; g.pitch = pitch; g.mode = mode;
+    g.conv_scale = 1.0;
     // the ring spans the masked columns [xoff, xoff + span) plus the PSF
     // window: xoff is the leftmost masked column rounded down to 16, where
     // every output group and segment starts at or after it
@@ -947,7 +967,7 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
     std::vector<uint16_t> aop;
     if (lensk::mode_base(mode) == lensk::MODE_SPLIT || lensk::mode_base(mode) == lensk::MODE_BF16 ||
         lensk::mode_base(mode) == lensk::MODE_SPLIT3) {
-        g.L = (int)align_up((size_t)(16 + k - 1), 8);
+        g.L = lensk::window_len(mode, k);
         g.nchunks = (int)((k * g.L + 31) / 32);
         for (int y = 0; y < ny; ++y) {
             segpre[y] = (int)seg.size();
@@ -956,7 +976,17 @@ extern "C" lens_status lens_load_data(lens_ctx *c, const lens_data_desc *d, lens
         }
         segpre[ny] = (int)seg.size();
         const int npl = lensk::mode_planes(mode);
-        const std::vector<uint16_t> kpl = split_psf_planes(psf, k, npl);   // [tap of the flipped PSF][plane]
+        // FP16 split: the kernel scaled by 2^j so that its largest tap lies in
+        // [2^13, 2^14), well inside the half range, its faint taps normal or
+        // finely subnormal; the convolution multiplies by 2^-j again
+        const bool f16 = lensk::mode_base(mode) == lensk::MODE_SPLIT;
+        double kmax = 0.0;
+        for (int t = 0; t < k * k; ++t) kmax = std::max(kmax, std::fabs(psf[t]));
+        int kexp = 0;
+        (void)std::frexp(kmax, &kexp);   // kmax < 2^kexp
+        const double kscale = f16 && kmax > 0.0 ? std::ldexp(1.0, 14 - kexp) : 1.0;
+        g.conv_scale = 1.0 / kscale;
+        const std::vector<uint16_t> kpl = split_psf_planes(psf, k, npl, f16, kscale);   // [tap][plane]
         aop.assign((size_t)g.nchunks * npl * 64 * 8, 0);
         for (int ch = 0; ch < g.nchunks; ++ch)
             for (int lane = 0; lane < 64; ++lane)

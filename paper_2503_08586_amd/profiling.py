@@ -27,12 +27,12 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 RECORDS = {
     "plain": ("traffic_plain_128px_s4_k21.txt", "k_loglike_fp32",
               "python3 bench.py --workload plain --steps 2 --warmup 1 --no-cpu-baseline"),
-    "batched": ("traffic_batched_c4_split3.txt", "k_loglike_batch",
+    "batched": ("traffic_batched_c4.txt", "k_loglike_batch",
                 "python3 bench.py --steps 1 --warmup 1 --no-cpu-baseline --no-serving --no-plain"),
 }
 WORKLOAD_TEXT = {
     "plain": "plain 128x128 s=4, 21x21 PSF as given, 65,536 proposals/launch",
-    "batched": "64 lenses 200x200 s=4, 41x41 Moffat PSF, split3, 1,048,576 proposals/launch",
+    "batched": "64 lenses 200x200 s=4, 41x41 Moffat PSF, FP16 split, 1,048,576 proposals/launch",
 }
 
 

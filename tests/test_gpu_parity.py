@@ -1,7 +1,7 @@
 """GPU path (through the C ABI) against the FP64 oracle, element by element.
 
 Gate: |lnL_gpu - lnL_oracle| / (chi2/2 + |C|) <= 1e-6 for the FP32 path and
-the three-plane split, 5e-6 for the two-plane split and 2e-3 for plain BF16
+the two splits and 2e-3 for plain BF16
 (the reasons are at MODE_TOL and TOL_BF16), with C = -1/2 sum_mask
 ln(2 pi sigma^2).  Out-of-domain proposals must be -inf on both sides.
 """
@@ -24,18 +24,11 @@ def ctx():
     c.close()
 
 
-# storage unit of each convolution mode: FP32, hi+lo BF16 (two planes of 8
-# significant bits: 2^-17 relative), plain BF16, hi+mid+lo BF16
-UNIT = {0: 2.0 ** -24, 1: 2.0 ** -17, 2: 2.0 ** -8, 3: 2.0 ** -24}
-# The hi+lo split keeps 16 significand bits of the image and of the PSF.  Its
-# PSF planes are rounded so that they sum to the PSF's sum, and the contraction
-# is summed in FP64 every two K-chunks, but the image's own 2^-17 rounding
-# stays: on bright compact models few pixels carry the chi-square and it does
-# not average out (1.5e-6 measured on the 200x200 / 41x41 workload).  The mode
-# is gated at 5e-6, outside the 1e-6 gate; the hi+mid+lo split (split3) is the
-# mode that meets 1e-6.
-TOL_SPLIT2 = 5e-6
-MODE_TOL = {0: TOL_FP32, 1: TOL_SPLIT2, 2: TOL_BF16, 3: TOL_FP32}
+# storage unit of each convolution mode: FP32, hi+lo FP16 (two planes of 11
+# significant bits at each ring row's own scale: 2^-22 relative), plain BF16,
+# hi+mid+lo BF16
+UNIT = {0: 2.0 ** -24, 1: 2.0 ** -22, 2: 2.0 ** -8, 3: 2.0 ** -24}
+MODE_TOL = {0: TOL_FP32, 1: TOL_FP32, 2: TOL_BF16, 3: TOL_FP32}
 MODES = [("fp32", 0), ("split", 1), ("bf16", 2), ("split3", 3)]
 
 
@@ -468,12 +461,13 @@ def _random_spec(geom, epl):
 
 @pytest.mark.parametrize("geom", RAND_GEOMS, ids=[g[0] for g in RAND_GEOMS])
 def test_random_geometries(ctx, geom):
-    """fp32 and split3 on every random geometry, and the elliptical power law
-    (fp32) on three of them, against the oracle."""
+    """fp32 and both splits on every random geometry (PSF windows of one,
+    two and three K-chunks per row for the FP16 split), and the elliptical
+    power law (fp32) on three of them, against the oracle."""
     name = geom[0]
     say("case: random geometry %s" % name)
     spec = _random_spec(geom, False)
-    for mname, m in (("fp32", 0), ("split3", 3)):
+    for mname, m in (("fp32", 0), ("split", 1), ("split3", 3)):
         lid = ctx.load(spec, precision=m)
         _check(spec, ctx.loglike(lid, spec.proposals), spec.proposals, tol=MODE_TOL[m],
                label="%s/%s" % (name, mname), storage_floor=int(spec.mask.sum()) < 64, unit=UNIT[m])

@@ -269,14 +269,14 @@ def test_env_gated_log(tmp_path):
 
 
 def test_serving_every_lens_kind(ctx, b):
-    """Serving with lenses of every kind at once (FP32 and split3 convolution,
-    amplitudes solved for two light models, the power-law mass with explicit
-    and solved amplitudes): each request's results equal the same proposals
-    evaluated alone, bit for bit."""
+    """Serving with lenses of every kind at once (FP32, FP16-split and split3
+    convolution, amplitudes solved for two light models, the power-law mass
+    with explicit and solved amplitudes): each request's results equal the same
+    proposals evaluated alone, bit for bit."""
     say("case: serving across lens kinds")
-    specs = synth.config3(nlens=6, scale_props=0.0)
+    specs = synth.config3(nlens=7, scale_props=0.0)
     kinds = [dict(), dict(precision=3), dict(amplitudes=1), dict(amplitudes=1, light_model=3, sersic_n=(1, 4, 1, 4)),
-             dict(mass_model=1), dict(mass_model=1, amplitudes=1)]
+             dict(mass_model=1), dict(mass_model=1, amplitudes=1), dict(precision=1)]
     rng = np.random.default_rng(41)
     lids = []
     for sp, kw in zip(specs, kinds):
