@@ -62,7 +62,7 @@ def parse():
                     help="only run a plain device copy of 1 GiB (for HBM counter calibration)")
     ap.add_argument("--workload", default="batched", choices=["batched", "plain", "batch", "precision", "serving",
                                                                "sampler", "sampler_many"])
-    ap.add_argument("--sample-per-lens", type=int, default=64,
+    ap.add_argument("--sample-per-lens", type=int, default=96,
                     help="batched: proposals per sampled lens checked against the oracle (and timing its CPU "
                          "rate: about 10 s of oracle work on 16 host threads at the default)")
     ap.add_argument("--sample-lenses", type=int, default=16,
