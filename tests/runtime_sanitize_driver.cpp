@@ -130,12 +130,12 @@ int main()
     if (!c) return 1;
     const Image small = make_image(40, 2, 7, 0.1), mid = make_image(64, 4, 11, 0.05);
 
-    // lenses: explicit FP32, split3, NNLS, EPL, two components per galaxy
+    // lenses: explicit FP32, FP16 split, NNLS, EPL, two components per galaxy
     lens_id A = 0, B = 0, Cn = 0, D = 0, E = 0;
     lens_data_desc d = desc_of(small);
     CK(lens_load_data(c, &d, &A));
     d = desc_of(mid);
-    d.precision = LENS_PREC_BF16_SPLIT3;
+    d.precision = LENS_PREC_F16_SPLIT;
     CK(lens_load_data(c, &d, &B));
     d = desc_of(small);
     d.amplitudes = LENS_AMP_NNLS;
