@@ -416,9 +416,11 @@ lens_status lens_philox4x32_10(lens_ctx *ctx, const uint32_t *ctr, const uint32_
 lens_status lens_model_image(lens_ctx *ctx, lens_id id, const double *params1, int32_t stage,
                              double *out_img);
 
-/* Self-test of the device (which = 0: the matrix-core operand layout the
- * BF16 convolution relies on, a 16x32 by 32x16 product of small integers).
- * *result = max |device - exact|, 0 when the layout holds. */
+/* Self-test of the device: the matrix-core operand layout the convolution
+ * relies on, a 16x32 by 32x16 product of small integers, in BF16 (which = 0)
+ * or IEEE half (which = 1, the FP16 split's instruction).  *result = max
+ * |device - exact|, 0 when the layout holds; other values of which give
+ * LENS_EINVAL. */
 lens_status lens_selftest(lens_ctx *ctx, int32_t which, double *result);
 
 const char *lens_strerror(lens_status st);

@@ -1093,20 +1093,26 @@ k_loglike_batch(const LensGeom *__restrict__ geoms, const int *__restrict__ lsta
     }
 }
 
+template <bool F16>
 __global__ void k_mfma_probe(const uint16_t *__restrict__ a, const uint16_t *__restrict__ b, float *__restrict__ d)
 {
-    // a: 16 x 32 row-major, b: 32 x 16 row-major, d: 16 x 16 row-major; one wave
+    // a: 16 x 32 row-major, b: 32 x 16 row-major, d: 16 x 16 row-major; one wave;
+    // BF16 or (F16) IEEE-half operands
     const int l = threadIdx.x, n = l & 15, kb = l >> 4;
-    bf16x8 av, bv;
     uint16_t ta[8], tb[8];
     for (int e = 0; e < 8; ++e) {
         ta[e] = a[n * 32 + 8 * kb + e];
         tb[e] = b[(8 * kb + e) * 16 + n];
     }
-    av = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(ta));
-    bv = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(tb));
     f32x4 c = {0.f, 0.f, 0.f, 0.f};
-    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+    if constexpr (F16)
+        c = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(f16x8, *reinterpret_cast<const uint4 *>(ta)),
+                                                   __builtin_bit_cast(f16x8, *reinterpret_cast<const uint4 *>(tb)), c,
+                                                   0, 0, 0);
+    else
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(ta)),
+                                                    __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4 *>(tb)),
+                                                    c, 0, 0, 0);
     for (int v = 0; v < 4; ++v) d[(4 * kb + v) * 16 + n] = c[v];
 }
 
@@ -1430,9 +1436,10 @@ hipError_t launch_batch(int mode, int nt, int grid, size_t lds, const LensGeom *
     return hipLaunchKernel(k, dim3(grid), dim3(nt), args, lds, st);
 }
 
-hipError_t launch_mfma_probe(const uint16_t *d_a, const uint16_t *d_b, float *d_d, hipStream_t st)
+hipError_t launch_mfma_probe(bool f16, const uint16_t *d_a, const uint16_t *d_b, float *d_d, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_mfma_probe, dim3(1), dim3(64), 0, st, d_a, d_b, d_d);
+    if (f16) hipLaunchKernelGGL(k_mfma_probe<true>, dim3(1), dim3(64), 0, st, d_a, d_b, d_d);
+    else hipLaunchKernelGGL(k_mfma_probe<false>, dim3(1), dim3(64), 0, st, d_a, d_b, d_d);
     return hipGetLastError();
 }
 

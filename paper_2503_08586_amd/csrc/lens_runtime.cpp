@@ -2286,18 +2286,21 @@ extern "C" lens_status lens_selftest(lens_ctx *c, int32_t which, double *result)
 {
     lens_status st = check_ctx(c);
     if (st != LENS_OK) return st;
-    if (!result || which != 0) return fail(c, LENS_EINVAL, "unknown self-test");
+    if (!result || (which != 0 && which != 1)) return fail(c, LENS_EINVAL, "unknown self-test");
     DeviceGuard dg(c->device);
-    // D = A B, A 16x32 and B 32x16 with small integers (exact in BF16 and FP32)
+    // D = A B, A 16x32 and B 32x16 with small integers (exact in BF16, FP16 and FP32)
+    const bool f16 = which == 1;
+    uint16_t (*rn)(float) = f16 ? f16_rn_host : bf16_rn_host;
+    float (*val)(uint16_t) = f16 ? f16_to_float : bf16_to_float;
     std::vector<uint16_t> ha(16 * 32), hb(32 * 16);
     std::vector<double> ref(16 * 16, 0.0);
     for (int i = 0; i < 16; ++i)
-        for (int kk = 0; kk < 32; ++kk) ha[i * 32 + kk] = bf16_rn_host((float)((i * 7 + kk * 3) % 11 - 5));
+        for (int kk = 0; kk < 32; ++kk) ha[i * 32 + kk] = rn((float)((i * 7 + kk * 3) % 11 - 5));
     for (int kk = 0; kk < 32; ++kk)
-        for (int j = 0; j < 16; ++j) hb[kk * 16 + j] = bf16_rn_host((float)((kk * 5 + j * 2) % 9 - 4));
+        for (int j = 0; j < 16; ++j) hb[kk * 16 + j] = rn((float)((kk * 5 + j * 2) % 9 - 4));
     for (int i = 0; i < 16; ++i)
         for (int j = 0; j < 16; ++j)
-            for (int kk = 0; kk < 32; ++kk) ref[i * 16 + j] += (double)bf16_to_float(ha[i * 32 + kk]) * bf16_to_float(hb[kk * 16 + j]);
+            for (int kk = 0; kk < 32; ++kk) ref[i * 16 + j] += (double)val(ha[i * 32 + kk]) * val(hb[kk * 16 + j]);
     std::lock_guard<std::mutex> lk(c->sync_mu);
     void *dbuf = nullptr;
     std::unique_lock<std::mutex> hold;
@@ -2308,7 +2311,7 @@ extern "C" lens_status lens_selftest(lens_ctx *c, int32_t which, double *result)
     std::vector<float> hd(256);
     hipError_t e = hipMemcpyAsync(da, ha.data(), ha.size() * 2, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(db, hb.data(), hb.size() * 2, hipMemcpyHostToDevice, c->stream);
-    if (e == hipSuccess) e = lensk::launch_mfma_probe(da, db, dd, c->stream);
+    if (e == hipSuccess) e = lensk::launch_mfma_probe(f16, da, db, dd, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(hd.data(), dd, 256 * 4, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return hip_fail(c, e, "lens_selftest");

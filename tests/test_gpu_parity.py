@@ -154,8 +154,9 @@ def test_geometries(ctx, geom, mode):
 
 
 def test_mfma_operand_layout(ctx):
-    say("case: matrix-core operand layout self-test")
+    say("case: matrix-core operand layout self-test, BF16 and FP16")
     assert ctx.selftest(0) == 0.0
+    assert ctx.selftest(1) == 0.0
 
 
 @pytest.mark.parametrize("mode", MODES, ids=[m[0] for m in MODES])
