@@ -43,7 +43,8 @@ sys.path.insert(0, ROOT)
 METRIC = "loglike evals/s at ≤1e-6 rel err, batched vs plain; p50/p99 req latency"
 PEAK_SLOT_PER_S = 256 * 4 * 16 * 2.4e9        # FP32 VALU lane-slots/s (non-packed)
 PEAK_BF16_FLOP_S = 2.5e15                       # dense BF16 / FP16 matrix-core peak
-SLOTS_PER_EVAL = 60 + 4 * 10                    # 60 FMA-class ops + 10 quarter-rate transcendentals
+TRANS_SLOTS = 2                                 # full-rate slots per FP32 transcendental (measured: 1.9)
+SLOTS_PER_EVAL = 60 + TRANS_SLOTS * 10          # 60 FMA-class ops + 10 half-rate transcendentals
 PRODUCTS = {1: 3, 2: 1, 3: 6}                   # matrix-core products per PSF tap: split (FP16), bf16, split3
 DOUBLE_N = (1.0, 4.0, 1.0, 4.0)                 # fixed indices of the two-component model: disc and bulge
 
@@ -60,7 +61,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target wall time of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of 1 GiB (for HBM counter calibration)")
-    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "batch", "precision", "serving",
+    ap.add_argument("--workload", default="batched", choices=["batched", "plain", "batch", "precision", "serving", "peaks",
                                                                "sampler", "sampler_many"])
     ap.add_argument("--sample-per-lens", type=int, default=96,
                     help="batched: proposals per sampled lens checked against the oracle (and timing its CPU "
@@ -88,11 +89,15 @@ def parse():
 PREC = {"fp32": 0, "split": 1, "bf16": 2, "split3": 3}
 LIGHT = {"both": 0, "lens": 1, "source": 2, "double": 3}
 # credited lane-slots per sub-pixel evaluation of each light model: the ray trace
-# (grid, SIE, shear, lens equation: ~34 FMA-class ops + 4 transcendentals = 50),
-# a Sersic component (~12 FMA + 3 transcendentals = 25 with its elliptical
-# radius), and a second component sharing that radius (~5 FMA + 2
-# transcendentals = 13)
-SLOTS_BY_MODEL = {0: 50 + 2 * 25, 1: 25, 2: 50 + 25, 3: 50 + 2 * (25 + 13)}
+# (grid, SIE, shear, lens equation: ~34 FMA-class ops + 4 transcendentals), a
+# Sersic component (~13 FMA + 3 transcendentals with its elliptical radius), and
+# a second component sharing that radius (~5 FMA + 2 transcendentals); model 0
+# adds up to SLOTS_PER_EVAL
+RAY_SLOTS = 34 + 4 * TRANS_SLOTS
+SERSIC_SLOTS = 13 + 3 * TRANS_SLOTS
+SECOND_SLOTS = 5 + 2 * TRANS_SLOTS
+SLOTS_BY_MODEL = {0: RAY_SLOTS + 2 * SERSIC_SLOTS, 1: SERSIC_SLOTS, 2: RAY_SLOTS + SERSIC_SLOTS,
+                  3: RAY_SLOTS + 2 * (SERSIC_SLOTS + SECOND_SLOTS)}
 CHANNELS = {0: 2, 1: 1, 2: 1, 3: 4}
 
 
@@ -238,6 +243,8 @@ def main():
         return run_sampler(args)
     if args.workload == "sampler_many":
         return run_sampler_many(args)
+    if args.workload == "peaks":
+        return run_peaks(args)
 
     spec = synth.config2(nprop=args.nprop)[0]
     n = spec.proposals.shape[0]
@@ -440,6 +447,12 @@ def run_batched(args):
                 "kernel_ms": kern_ms, "slots_per_step": slots, "conv_flops_per_step": flops,
                 "tile": [infos[0]["strip_rows"], infos[0]["threads"], infos[0]["blocks_per_cu"],
                          infos[0]["lds_bytes"]]}
+
+    # the FP64 FMA issue rate measured on this device, beside the nominal peak
+    fma = ctx.peak_rate("fma_f64")
+    roofline["peak_measured"] = {"fma_f64": fma / 1e12, "unit": "Tslot/s",
+                                 "frac": roofline["achieved"] * 1e12 / fma,
+                                 "note": "lens_peak_rate(LENS_PEAK_FMA_F64) after the timed steps"}
 
     # the plain path: FP32, one lens per call, same proposals, device buffers
     plain = None
@@ -940,6 +953,27 @@ def run_serving(args):
                                   % mode, "requests_per_load": args.requests},
            "serving": out}
     print(json.dumps(rec), flush=True)
+
+
+def run_peaks(args):
+    """Issue rates of the instruction kinds the likelihood kernels are built from
+    (lens_peak_rate), in lane operations/s (vector ALU) or FLOP/s (matrix cores),
+    with each one's cost in full-rate slots at the nominal peak (PEAK_SLOT_PER_S /
+    rate): the credit behind the roofline counts a transcendental as TRANS_SLOTS slots."""
+    from paper_2503_08586_amd import binding
+    ctx = binding.LensContext(0)
+    rates = {}
+    for name in binding.PEAK_OPS:
+        r = ctx.peak_rate(name)
+        if name in ("mfma_f16", "mfma_bf16"):
+            rates[name] = {"tflop_s": r / 1e12, "frac_of_nominal": r / PEAK_BF16_FLOP_S}
+        else:
+            rates[name] = {"t_lane_ops_s": r / 1e12, "slots_per_op": PEAK_SLOT_PER_S / r}
+        print("peak %s: %.4g" % (name, r), file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "instruction issue rates", "n_gpus": 1, "data": "synthetic",
+                      "nominal": {"valu_lane_slots_s": PEAK_SLOT_PER_S, "mfma_flop_s": PEAK_BF16_FLOP_S},
+                      "launch": "8 waves per SIMD, 8 independent chains per lane, best of 3 launches of ~25 ms",
+                      "rates": rates}))
 
 
 if __name__ == "__main__":

@@ -423,6 +423,39 @@ lens_status lens_model_image(lens_ctx *ctx, lens_id id, const double *params1, i
  * LENS_EINVAL. */
 lens_status lens_selftest(lens_ctx *ctx, int32_t which, double *result);
 
+/* Instruction kinds for lens_peak_rate. */
+#define LENS_PEAK_FMA_F64 0         /* v_fma_f64 */
+#define LENS_PEAK_FMA_F32 1         /* v_fma_f32 (not packed) */
+#define LENS_PEAK_MUL_F64 2         /* v_mul_f64 */
+#define LENS_PEAK_ADD_F64 3         /* v_add_f64 */
+#define LENS_PEAK_EXP_F32 4         /* v_exp_f32 (2^x) */
+#define LENS_PEAK_LOG_F32 5         /* v_log_f32 (log2 x) */
+#define LENS_PEAK_RSQ_F32 6         /* v_rsq_f32 */
+#define LENS_PEAK_RCP_F32 7         /* v_rcp_f32 */
+#define LENS_PEAK_CVT_F64_F32 8     /* v_cvt_f32_f64 and v_cvt_f64_f32, alternating */
+#define LENS_PEAK_LDEXP_F64 9       /* v_ldexp_f64 */
+#define LENS_PEAK_FREXP_MANT_F64 10 /* v_frexp_mant_f64 */
+#define LENS_PEAK_RNDNE_F64 11      /* v_rndne_f64 */
+#define LENS_PEAK_RSQ_F64 12        /* v_rsq_f64 */
+#define LENS_PEAK_MFMA_F16 13       /* v_mfma_f32_16x16x32_f16 */
+#define LENS_PEAK_MFMA_BF16 14      /* v_mfma_f32_16x16x32_bf16 */
+#define LENS_PEAK_FMA_F64_EXP_F32 15 /* v_fma_f64 and v_exp_f32, alternating (both counted) */
+#define LENS_PEAK_MFMA_F16_FMA_F64 16 /* four v_fma_f64 after each FP16 product (the FMAs counted) */
+#define LENS_PEAK_COUNT 17
+
+/* Measured peak rate of one instruction kind on this context's device, for
+ * the roofline the likelihood kernels are held against (the operation
+ * counts behind it: ray trace and Sersic profiles of Sec. 2.1 and 2.4, the
+ * PSF contraction of Eq. 4).  A launch of eight waves per SIMD, every lane
+ * running eight independent chains of the instruction, timed with HIP events
+ * on the context's stream, best of three launches of ~25 ms each after a
+ * sizing launch.  *rate = lane operations per second for the vector ALU
+ * kinds (an FMA counts once, so FMA FLOP/s = 2 *rate), FLOP/s for the
+ * matrix-core products (2 x 16 x 16 x 32 per instruction).  An op outside
+ * [0, LENS_PEAK_COUNT) gives LENS_EINVAL.  Holds the context's blocking-call
+ * lock while it runs; meant for characterisation, not for the hot path. */
+lens_status lens_peak_rate(lens_ctx *ctx, int32_t op, double *rate);
+
 const char *lens_strerror(lens_status st);
 /* Last error message of the calling thread on this context ("" if none). */
 const char *lens_last_error(lens_ctx *ctx);

@@ -55,7 +55,7 @@ EXPORTED = [
     "lens_loglike_batch", "lens_loglike_amps", "lens_loglike_batch_device", "lens_loglike_multi",
     "lens_loglike_multi_device", "lens_loglike_batch_device_noalloc",
     "lens_submit", "lens_poll", "lens_wait", "lens_cancel", "lens_get_stats", "lens_reset_stats",
-    "lens_model_image", "lens_selftest", "lens_psf_crop", "lens_strerror", "lens_last_error",
+    "lens_model_image", "lens_selftest", "lens_peak_rate", "lens_psf_crop", "lens_strerror", "lens_last_error",
     "lens_ensemble_create", "lens_ensemble_run", "lens_ensemble_run_many", "lens_ensemble_get",
     "lens_ensemble_destroy",
     "lens_philox4x32_10",
@@ -172,6 +172,7 @@ def load():
         "lens_reset_stats": ([vp], i32),
         "lens_model_image": ([vp, i64, dp, i32, dp], i32),
         "lens_selftest": ([vp, i32, dp], i32),
+        "lens_peak_rate": ([vp, i32, dp], i32),
         "lens_psf_crop": ([dp, i32, ctypes.c_double, ctypes.POINTER(i32)], i32),
         "lens_ensemble_create": ([vp, i64, ctypes.POINTER(lens_ensemble_desc), i64p], i32),
         "lens_ensemble_run": ([vp, i64, i64, i32, dp, dp], i32),
@@ -552,6 +553,18 @@ def lens_selftest(ctx, which: int = 0) -> float:
     return r.value
 
 
+# instruction kinds of lens_peak_rate (LENS_PEAK_* in include/lens_api.h)
+PEAK_OPS = ["fma_f64", "fma_f32", "mul_f64", "add_f64", "exp_f32", "log_f32", "rsq_f32", "rcp_f32",
+            "cvt_f64_f32", "ldexp_f64", "frexp_mant_f64", "rndne_f64", "rsq_f64", "mfma_f16", "mfma_bf16",
+            "fma_f64_exp_f32", "mfma_f16_fma_f64"]
+
+
+def lens_peak_rate(ctx, op: int) -> float:
+    r = ctypes.c_double()
+    _check(ctx, load().lens_peak_rate(ctx, op, ctypes.byref(r)))
+    return r.value
+
+
 def lens_strerror(st: int) -> str:
     return load().lens_strerror(st).decode()
 
@@ -661,3 +674,10 @@ class LensContext:
 
     def selftest(self, which=0) -> float:
         return lens_selftest(self.ctx, which)
+
+    def peak_rate(self, op) -> float:
+        """Measured rate of one instruction kind (index or PEAK_OPS name): lane
+        operations/s for the vector ALU kinds, FLOP/s for the matrix-core products."""
+        if isinstance(op, str):
+            op = PEAK_OPS.index(op)
+        return lens_peak_rate(self.ctx, op)

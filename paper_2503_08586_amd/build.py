@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblens_mi355x.so")
-SOURCES = ["lens_kernels.hip", "lens_sampler.hip", "lens_runtime.cpp"]
+SOURCES = ["lens_kernels.hip", "lens_sampler.hip", "lens_peaks.hip", "lens_runtime.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -162,16 +162,45 @@ __device__ __forceinline__ double log2_r2(double r2)
     return (double)__builtin_amdgcn_frexp_exp(r2) + (double)lm;
 }
 
-// 2^(B (1 - t)) with t = 2^(e lgd), lgd = log2 of (R/R_e)^2 (as above)
+// log2 r2 for a Sersic exponent.  Where every lane of the wave has
+// log2 r2 >= -2 (R >= R_e / 2) it is the FP32 hardware log2 of r2 itself: an
+// absolute error within an ulp of a result of that size (1.2e-7 for |l| < 2,
+// 2.4e-7 for |l| < 4) plus 8.6e-8 from rounding r2 to FP32.  It reaches the
+// brightness scaled by ln2^2 B e t (t = 2^(e l)), which keeps it near 1e-7
+// relative while the profile is within a few R_e and far below the peak
+// beyond.  A wave with a lane nearer a centre (where t is small and the cusp
+// steep, and where r2 = 0 gives -inf) takes log2_r2.  A radius whose FP32
+// value overflows gives l = +inf, t = NaN and, through fmax in sersic_lg,
+// 2^-2000 = 0, as log2_r2's large finite value does.
+__device__ __forceinline__ double log2_r2_sersic(double r2)
+{
+    const float l = hw_log2((float)r2);
+    if (__builtin_amdgcn_ballot_w64(!(l >= -2.0f))) return log2_r2(r2);
+    return (double)l;
+}
+
+// 2^y for y in [-2000, 1023]: 2^round(y) times the FP32 hardware 2^f of the
+// remainder f in [-1/2, 1/2] (relative error ~1 ulp of FP32; f itself is
+// rounded to FP32, 2^-25 absolute).  For the brightness 2^(B (1 - t)), whose
+// relative error is that of this function alone: nothing amplifies it.
+__device__ __forceinline__ double exp2_hw(double y)
+{
+    const double k = rint(y);
+    return ldexp((double)__builtin_amdgcn_exp2f((float)(y - k)), (int)k);
+}
+
+// 2^(B (1 - t)) with t = 2^(e lgd), lgd = log2 of (R/R_e)^2 (as above).  t's
+// relative error is amplified by ln2 B t in the exponent, so it takes the FP64
+// polynomial; the outer power's is not.
 __device__ __forceinline__ double sersic_lg(double lgd, double e, double B, double lead)
 {
     const double t = exp2_64(kExp2_64, e * lgd, lead);
-    return exp2_64(kExp2_64, fmax(fma(-B, t, B), -2000.0), lead);
+    return exp2_hw(fmax(fma(-B, t, B), -2000.0));
 }
 
 __device__ __forceinline__ double sersic_r2(double r2, const LightK &L, double lead)
 {
-    return sersic_lg(log2_r2(r2), L.e, L.B, lead);
+    return sersic_lg(log2_r2_sersic(r2), L.e, L.B, lead);
 }
 
 // (R/R_e)^2 = P dx^2 + Q dy^2 + S dx dy at offset (dx, dy) from a light centre,
@@ -418,13 +447,13 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
                     val[0] = sersic_r2(fma(fma(P.lens.P, dx, rs), dx, rq), P.lens, lead);
                     val[1] = sersic_r2(ellip_r2(w1, w2, P.src), P.src, lead);
                 } else {
-                    const double lgs = log2_r2(ellip_r2(w1, w2, P.src));
+                    const double lgs = log2_r2_sersic(ellip_r2(w1, w2, P.src));
                     val[IS] = sersic_lg(lgs, es, Bs, lead);
                     if constexpr (DBL) val[IS + 1] = sersic_lg(lgs + P.dlg_s, g.fix_e[3], g.fix_B[3], lead);
                 }
             }
             if constexpr (LENS && (DBL || !SRC)) {
-                const double lgl = log2_r2(fma(fma(P.lens.P, dx, rs), dx, rq));
+                const double lgl = log2_r2_sersic(fma(fma(P.lens.P, dx, rs), dx, rq));
                 val[0] = sersic_lg(lgl, el, Bl, lead);
                 if constexpr (DBL) val[1] = sersic_lg(lgl + P.dlg_l, g.fix_e[1], g.fix_B[1], lead);
             }

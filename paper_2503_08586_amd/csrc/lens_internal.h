@@ -218,6 +218,12 @@ hipError_t noalloc_init(int device);
 PropBlock *noalloc_scratch(int device);
 // self-test of the matrix-core operand layout: D = A B for a 16x32 by 32x16 BF16 product
 hipError_t launch_mfma_probe(bool f16, const uint16_t *d_a, const uint16_t *d_b, float *d_d, hipStream_t st);
+// issue-rate probes (lens_peak_rate): `grid` workgroups of peak_threads()
+// threads, n rounds each, one double per thread into out; each lane does
+// peak_ops_per_round(op) operations per round
+int peak_threads();
+double peak_ops_per_round(int op);
+hipError_t launch_peak(int op, int grid, int n, double *out, hipStream_t st);
 // stage 0: binned image of one proposal into d_img [ny][nx]; stage 1: convolved,
 // using d_tmp [ny][nx] for the binned image.
 hipError_t launch_model_image(const LensGeom &g, const PropBlock *d_pc, int stage, float *d_img,

@@ -2321,6 +2321,49 @@ extern "C" lens_status lens_selftest(lens_ctx *c, int32_t which, double *result)
     return LENS_OK;
 }
 
+extern "C" lens_status lens_peak_rate(lens_ctx *c, int32_t op, double *rate)
+{
+    lens_status st = check_ctx(c);
+    if (st != LENS_OK) return st;
+    if (!rate || op < 0 || op >= LENS_PEAK_COUNT) return fail(c, LENS_EINVAL, "unknown instruction kind");
+    DeviceGuard dg(c->device);
+    // eight workgroups of four waves per CU: eight waves per SIMD
+    const int nt = lensk::peak_threads(), grid = 8 * c->num_cus;
+    std::lock_guard<std::mutex> lk(c->sync_mu);
+    void *dbuf = nullptr;
+    std::unique_lock<std::mutex> hold;
+    lens_status rs = stream_scratch(c, c->stream, (size_t)grid * nt * 8, &dbuf, &hold);
+    if (rs != LENS_OK) return rs;
+    double *out = (double *)dbuf;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    // one timed launch of n rounds, in milliseconds
+    auto timed = [&](int n, float *ms) {
+        hipError_t r = hipEventRecord(e0, c->stream);
+        if (r == hipSuccess) r = lensk::launch_peak(op, grid, n, out, c->stream);
+        if (r == hipSuccess) r = hipEventRecord(e1, c->stream);
+        if (r == hipSuccess) r = hipEventSynchronize(e1);
+        if (r == hipSuccess) r = hipEventElapsedTime(ms, e0, e1);
+        return r;
+    };
+    // a sizing launch (0.4-2 ms at the expected rates), then three of ~25 ms
+    const int n0 = 4096;
+    float t0 = 0.f, best = 1e30f;
+    if (e == hipSuccess) e = timed(n0, &t0);
+    const int n = (int)std::min(200.0 * n0, std::max(64.0, n0 * 25.0 / std::max(t0, 1e-3f)));
+    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
+        float ms = 0.f;
+        e = timed(n, &ms);
+        if (e == hipSuccess) best = std::min(best, ms);
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(c, e, "lens_peak_rate");
+    *rate = (double)grid * nt * n * lensk::peak_ops_per_round(op) / (best * 1e-3);
+    return LENS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // sampler loop on the device: Philox4x32-10 words and stretch-move ensembles
 // ---------------------------------------------------------------------------

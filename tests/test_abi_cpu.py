@@ -45,6 +45,16 @@ def test_binding_covers_every_declared_symbol():
         assert callable(getattr(binding, name))
 
 
+def test_peak_kinds_match_header():
+    # binding.PEAK_OPS[i] names LENS_PEAK_<NAME> = i, and LENS_PEAK_COUNT ends the list
+    from paper_2503_08586_amd import binding
+    text = open(HEADER).read()
+    vals = {m.group(1).lower(): int(m.group(2))
+            for m in re.finditer(r"^#define LENS_PEAK_(\w+)\s+(\d+)", text, flags=re.M)}
+    assert vals.pop("count") == len(binding.PEAK_OPS)
+    assert vals == {name: i for i, name in enumerate(binding.PEAK_OPS)}
+
+
 def test_strerror_without_device(lib):
     lib.lens_strerror.restype = ctypes.c_char_p
     lib.lens_strerror.argtypes = [ctypes.c_int32]

@@ -28,19 +28,21 @@ def test_peak_from_unit_counts():
 
 def test_credited_slots_of_the_survey_workload():
     """E = 225,024 sub-pixels (the mask dilated by the 13x13 cropped PSF, at
-    s = 4), M = 11,304 masked pixels: E (60 + 4 x 10) + M k^2 + M."""
+    s = 4), M = 11,304 masked pixels: E (60 + 2 x 10) + M k^2 + M, a
+    transcendental costing two full-rate slots (half rate on CDNA4)."""
+    assert bench.TRANS_SLOTS == 2
     spec = types.SimpleNamespace(s=4)
     info = {"masked_pixels": 11304, "psf_used": 13, "needed_pixels": 225024 // 16}
     slots, E = bench.credited_slots(spec, info)
     assert E == 225024
-    assert slots == 225024 * 100 + 11304 * 169 + 11304 == 24424080
+    assert slots == 225024 * 80 + 11304 * 169 + 11304 == 19923600
 
 
-@pytest.mark.parametrize("model,per_eval,n", [(0, 100, 2), (1, 25, 1), (2, 75, 1), (3, 126, 4)])
+@pytest.mark.parametrize("model,per_eval,n", [(0, 80, 2), (1, 19, 1), (2, 61, 1), (3, 98, 4)])
 def test_credited_slots_of_the_solved_amplitude_models(model, per_eval, n):
-    """Per sub-pixel: ray trace 50, a Sersic with its radius 25, a second
-    component on the same radius 13; per masked pixel N k^2 taps and
-    N(N+1)/2 + N FP64 moments for N components."""
+    """Per sub-pixel: ray trace 34 + 4 x 2, a Sersic with its radius 13 + 3 x 2,
+    a second component on the same radius 5 + 2 x 2; per masked pixel N k^2
+    taps and N(N+1)/2 + N FP64 moments for N components."""
     spec = types.SimpleNamespace(s=2)
     info = {"masked_pixels": 1000, "psf_used": 11, "needed_pixels": 1500}
     slots, E = bench.credited_slots(spec, info, nnls=True, model=model)
@@ -64,13 +66,13 @@ def test_stale_traffic_record_is_ignored(tmp_path, monkeypatch):
 @pytest.mark.parametrize("prec", [1, 2, 3])
 def test_matrix_core_modes_credit_the_convolution_to_the_mfma(prec):
     """In the BF16 matrix-core precisions the PSF taps are not vector-ALU work:
-    E (60 + 4 x 10) + M slots, and 2 M k^2 flops times the products per tap
+    E (60 + 2 x 10) + M slots, and 2 M k^2 flops times the products per tap
     against the dense BF16 peak."""
     spec = types.SimpleNamespace(s=4)
     info = {"masked_pixels": 11304, "psf_used": 41, "needed_pixels": 22504}
     slots, E = bench.credited_slots(spec, info, prec=prec)
     assert E == 360064
-    assert slots == 360064 * 100 + 11304
+    assert slots == 360064 * 80 + 11304
     fl = bench.conv_flops(info)
     assert fl == 2 * 11304 * 41 * 41
     t = bench.roofline_terms(slots, fl, prec, 2.0e-6)
