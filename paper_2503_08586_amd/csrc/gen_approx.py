@@ -99,7 +99,7 @@ def emit_bn(mids, invh, coefs, err):
 
 
 # degree of the per-interval polynomials of the SIE deflection tables
-SIE_DEG = 6
+SIE_DEG = 5
 
 
 def emit_sie_interp():

@@ -238,12 +238,14 @@ __device__ __forceinline__ void ray_trace(double x1, double x2, double u1, doubl
 // and both components are functions of u alone.  H1 and H2 are analytic
 // except at u = +-i q / c; on each of kSieIntervals intervals of u the table
 // holds the polynomial of degree kSieDeg through their values at the
-// interval's Chebyshev nodes (from sie_a1 and sie_a2), which reproduces them to
-// 2e-12 (q = 0.5) and 1.3e-10 (q = 0.3) relative, against 4e-10 and 1.3e-9 of
-// the polynomials behind sie_a1 and sie_a2.  A sub-pixel then takes one
-// interval lookup and two degree-6 Horner sums instead of both deflection
-// functions and, in most waves, a range reduction.  Below q = 0.3 the
-// singularities come too close and the direct functions are used.
+// interval's Chebyshev nodes (from sie_a1 and sie_a2).  With 32 intervals
+// and degree 5 that reproduces them to 1.3e-12 (q = 0.5) and 4e-11 (q = 0.3)
+// relative, against 4e-10 and 1.3e-9 of the polynomials behind sie_a1 and
+// sie_a2 (16 intervals at degree 6 are as accurate at two more FMAs per
+// sub-pixel).  A sub-pixel then takes one interval lookup and two degree-5
+// Horner sums instead of both deflection functions and, in most waves, a
+// range reduction.  Below q = 0.3 the singularities come too close and the
+// direct functions are used.
 constexpr double kSieTabQ2 = 0.09;   // q^2 from which the table is used
 static_assert(kSieEntry >= 2 * kSieDeg + 3, "SIE table entry");
 
@@ -266,7 +268,7 @@ __device__ inline void sie_setup(const PropBlock &P)
     const double q = sqrt(P.q2m);
     double c[kSieDeg + 1] = {};
     // one node at a time (the kernels' register budget is set by their busiest
-    // point, and seven deflections in flight would be it)
+    // point, and all the nodes' deflections in flight would be it)
 #pragma unroll 1
     for (int k = 0; k <= kSieDeg; ++k) {
         const double u = (j + 0.5 + kSieNode[k]) * (1.0 / kSieIntervals);
@@ -303,7 +305,7 @@ __device__ __forceinline__ void ray_trace_tab(double x1, double x2, double u1, d
     double h1 = e[kSieDeg + 1];
 #pragma unroll
     for (int i = kSieDeg - 1; i >= 0; --i) h1 = fma(h1, t, e[1 + i]);
-    // the second set of coefficients is read after the first sum: 14 fewer
+    // the second set of coefficients is read after the first sum: 12 fewer
     // registers live at once (other waves hide the LDS latency)
     asm volatile("" ::: "memory");
     double h2 = e[2 * kSieDeg + 2];

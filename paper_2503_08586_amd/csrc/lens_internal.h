@@ -105,8 +105,8 @@ constexpr int kMassShift = 8;
 constexpr int kEplMaxTerms = 128;   // terms of the power-law deflection series
 constexpr double kGammaMin = 1.05, kGammaMax = 2.95;
 // per-proposal SIE deflection table in LDS: intervals of u = q |x1| / psi and
-// doubles per interval (centre, two sets of 7 coefficients, padding)
-constexpr int kSieIntervals = 16, kSieEntry = 16;
+// doubles per interval (centre, two sets of 6 coefficients, padding to 16 bytes)
+constexpr int kSieIntervals = 32, kSieEntry = 14;
 
 // Everything a likelihood launch needs to know about one resident lens.
 struct LensGeom {
