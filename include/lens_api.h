@@ -449,7 +449,7 @@ lens_status lens_selftest(lens_ctx *ctx, int32_t which, double *result);
  * PSF contraction of Eq. 4).  A launch of eight waves per SIMD, every lane
  * running eight independent chains of the instruction, timed with HIP events
  * on the context's stream, best of three launches of ~25 ms each after a
- * sizing launch.  *rate = lane operations per second for the vector ALU
+ * warm-up and a sizing launch.  *rate = lane operations per second for the vector ALU
  * kinds (an FMA counts once, so FMA FLOP/s = 2 *rate), FLOP/s for the
  * matrix-core products (2 x 16 x 16 x 32 per instruction).  An op outside
  * [0, LENS_PEAK_COUNT) gives LENS_EINVAL.  Holds the context's blocking-call

@@ -2347,9 +2347,11 @@ extern "C" lens_status lens_peak_rate(lens_ctx *c, int32_t op, double *rate)
         if (r == hipSuccess) r = hipEventElapsedTime(ms, e0, e1);
         return r;
     };
-    // a sizing launch (0.4-2 ms at the expected rates), then three of ~25 ms
+    // a warm-up launch (the first one of a kernel also loads its code), a
+    // sizing launch (0.4-2 ms at the expected rates), then three of ~25 ms
     const int n0 = 4096;
     float t0 = 0.f, best = 1e30f;
+    if (e == hipSuccess) e = timed(n0, &t0);
     if (e == hipSuccess) e = timed(n0, &t0);
     const int n = (int)std::min(200.0 * n0, std::max(64.0, n0 * 25.0 / std::max(t0, 1e-3f)));
     for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) {
