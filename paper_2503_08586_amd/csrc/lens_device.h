@@ -162,20 +162,25 @@ __device__ __forceinline__ double log2_r2(double r2)
     return (double)__builtin_amdgcn_frexp_exp(r2) + (double)lm;
 }
 
-// log2 r2 for a Sersic exponent.  Where every lane of the wave has
-// log2 r2 >= -2 (R >= R_e / 2) it is the FP32 hardware log2 of r2 itself: an
-// absolute error within an ulp of a result of that size (1.2e-7 for |l| < 2,
-// 2.4e-7 for |l| < 4) plus 8.6e-8 from rounding r2 to FP32.  It reaches the
-// brightness scaled by ln2^2 B e t (t = 2^(e l)), which keeps it near 1e-7
-// relative while the profile is within a few R_e and far below the peak
-// beyond.  A wave with a lane nearer a centre (where t is small and the cusp
-// steep, and where r2 = 0 gives -inf) takes log2_r2.  A radius whose FP32
-// value overflows gives l = +inf, t = NaN and, through fmax in sersic_lg,
-// 2^-2000 = 0, as log2_r2's large finite value does.
-__device__ __forceinline__ double log2_r2_sersic(double r2)
+// log2 r2 for a Sersic exponent.  For a profile with n >= 1/2 (e <= 1),
+// where every lane of the wave has log2 r2 >= -2 (R >= R_e / 2),
+// it is the FP32 hardware log2 of r2 itself: an absolute error within an ulp
+// of a result of that size (1.2e-7 for |l| < 2, 2.4e-7 for |l| < 4) plus
+// 8.6e-8 from rounding r2 to FP32.  It reaches the brightness scaled by
+// ln2^2 B e t (t = 2^(e l)): with one-ulp errors of this log2 and of exp2_hw
+// aligned, at most 8.4e-7 of the local brightness wherever that is above 1/8
+// of its value at R_e, against 9.2e-7 for the exponent split over the whole
+// index domain (whose worst case is at n = 0.1, where this form would reach
+// 1.7e-6: hence the gate on e).  A wave with a lane nearer a centre (where t
+// is small and the cusp steep, and where r2 = 0 gives -inf) takes log2_r2.
+// A radius whose FP32 value overflows gives l = +inf, t = NaN and, through
+// fmax in sersic_lg, 2^-2000 = 0, as log2_r2's large finite value does.
+// thr (uniform): -2 where the FP32 form is allowed, +inf where it is not (a
+// threshold rather than a flag keeps the sub-pixel loop's code the same).
+__device__ __forceinline__ double log2_r2_sersic(double r2, float thr)
 {
     const float l = hw_log2((float)r2);
-    if (__builtin_amdgcn_ballot_w64(!(l >= -2.0f))) return log2_r2(r2);
+    if (__builtin_amdgcn_ballot_w64(!(l >= thr))) return log2_r2(r2);
     return (double)l;
 }
 
@@ -198,10 +203,6 @@ __device__ __forceinline__ double sersic_lg(double lgd, double e, double B, doub
     return exp2_hw(fmax(fma(-B, t, B), -2000.0));
 }
 
-__device__ __forceinline__ double sersic_r2(double r2, const LightK &L, double lead)
-{
-    return sersic_lg(log2_r2_sersic(r2), L.e, L.B, lead);
-}
 
 // (R/R_e)^2 = P dx^2 + Q dy^2 + S dx dy at offset (dx, dy) from a light centre,
 // the rotation and axis ratio of Eq. 10 folded into P, Q, S.
@@ -424,6 +425,15 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
     for (int c = 0; c < N; ++c) acc[c] = 0.0;
     const double el = DBL ? g.fix_e[0] : P.lens.e, Bl = DBL ? g.fix_B[0] : P.lens.B;
     const double es = DBL ? g.fix_e[2] : P.src.e, Bs = DBL ? g.fix_B[2] : P.src.B;
+    // the FP32 log2 of the Sersic radii only for indices >= 1/2
+    // (log2_r2_sersic), and not for two components per galaxy: the second
+    // one's exponent takes the first one's log2 shifted by 2 log2(R_a/R_b),
+    // so an ulp of a large first log2 can land where the second profile is
+    // still bright
+    float thr_l = !DBL && el <= 1.0 ? -2.0f : __builtin_inff();
+    float thr_s = !DBL && es <= 1.0 ? -2.0f : __builtin_inff();
+    // in VGPRs too: the kernels have no scalar registers to spare
+    asm("" : "+v"(thr_l), "+v"(thr_s));
     for (int v = 0; v < s; ++v) {
         const double yy = ((double)(y * s + v) - g.cfy) * g.sd;
         const double dy = yy - P.ym;
@@ -446,16 +456,16 @@ __device__ __forceinline__ void binned_channels(const LensGeom &g, const PropBlo
                     ray_trace(fma(P.cm, dx, c1), fma(-P.sm, dx, c2), fma(P.ku1, dx, cu1), fma(P.ku2, dx, cu2), P, w1,
                               w2);
                 if constexpr (LENS && !DBL) {
-                    val[0] = sersic_r2(fma(fma(P.lens.P, dx, rs), dx, rq), P.lens, lead);
-                    val[1] = sersic_r2(ellip_r2(w1, w2, P.src), P.src, lead);
+                    val[0] = sersic_lg(log2_r2_sersic(fma(fma(P.lens.P, dx, rs), dx, rq), thr_l), el, Bl, lead);
+                    val[1] = sersic_lg(log2_r2_sersic(ellip_r2(w1, w2, P.src), thr_s), es, Bs, lead);
                 } else {
-                    const double lgs = log2_r2_sersic(ellip_r2(w1, w2, P.src));
+                    const double lgs = log2_r2_sersic(ellip_r2(w1, w2, P.src), thr_s);
                     val[IS] = sersic_lg(lgs, es, Bs, lead);
                     if constexpr (DBL) val[IS + 1] = sersic_lg(lgs + P.dlg_s, g.fix_e[3], g.fix_B[3], lead);
                 }
             }
             if constexpr (LENS && (DBL || !SRC)) {
-                const double lgl = log2_r2_sersic(fma(fma(P.lens.P, dx, rs), dx, rq));
+                const double lgl = log2_r2_sersic(fma(fma(P.lens.P, dx, rs), dx, rq), thr_l);
                 val[0] = sersic_lg(lgl, el, Bl, lead);
                 if constexpr (DBL) val[1] = sersic_lg(lgl + P.dlg_l, g.fix_e[1], g.fix_B[1], lead);
             }

@@ -202,3 +202,70 @@ def test_sie_table_reproduces_the_deflection(orc, q, tol):
         got = np.array(tab.deflection(x1, x2))
         worst = max(worst, np.abs(got - ref).max() / np.abs(ref).max())
     assert worst < tol, worst
+
+
+def _sersic_exact(B, e, l):
+    """exp(-b ((R/R_e)^(1/n) - 1)) = 2^(B (1 - t)), t = 2^(e l), l = log2 (R/R_e)^2."""
+    return 2.0 ** (B * (1.0 - 2.0 ** (e * l)))
+
+
+def _sersic_fp32_log2(B, e, l):
+    """Worst case of the kernels' FP32-hardware form (log2_r2_sersic's fast
+    path and exp2_hw): r2 rounded to FP32, its log2 one FP32 ulp off either
+    way, t in FP64, and the outer 2^f of the FP32-rounded remainder one ulp off
+    either way.  Returns the largest error over the four sign combinations."""
+    r2 = (2.0 ** l).astype(np.float32)
+    l32 = np.log2(r2.astype(np.float64)).astype(np.float32)
+    ulp = np.spacing(np.abs(l32)).astype(np.float64)
+    exact = _sersic_exact(B, e, l)
+    worst = np.zeros_like(l)
+    for sl in (-1.0, 1.0):
+        t = 2.0 ** (e * (l32.astype(np.float64) + sl * ulp))
+        g = np.maximum(B * (1.0 - t), -2000.0)
+        k = np.rint(g)
+        f = (g - k).astype(np.float32).astype(np.float64)
+        for se in (-1.0, 1.0):
+            worst = np.maximum(worst, np.abs(np.ldexp(2.0 ** f * (1.0 + se * 2.0 ** -23), k.astype(int)) - exact))
+    return worst
+
+
+def _sersic_split_log2(B, e, l):
+    """Worst case of the exponent-split form (log2_r2): the binary exponent
+    exact, the FP32 log2 of the mantissa one ulp off either way, both powers
+    of two at the polynomial's 1.9e-9."""
+    m, E = np.frexp(2.0 ** l)
+    lm = np.log2(m.astype(np.float32).astype(np.float64)).astype(np.float32)
+    ulp = np.spacing(np.abs(lm)).astype(np.float64)
+    exact = _sersic_exact(B, e, l)
+    worst = np.zeros_like(l)
+    for sl in (-1.0, 1.0):
+        t = 2.0 ** (e * (E + lm.astype(np.float64) + sl * ulp)) * (1.0 + sl * 1.9e-9)
+        worst = np.maximum(worst, np.abs(2.0 ** np.maximum(B * (1.0 - t), -2000.0) * (1.0 + 1.9e-9) - exact))
+    return worst
+
+
+def _worst_relative(orc, form, n_lo, l_lo, l_hi=16.0):
+    """Largest error of a Sersic form relative to max(local value, 1/8 of the
+    value at R_e), over indices n in [n_lo, 20] and l in [l_lo, l_hi]."""
+    w = 0.0
+    for n in np.geomspace(n_lo, 20.0, 30):
+        B, e = orc.bn(n) / math.log(2.0), 1.0 / (2.0 * n)
+        l = np.linspace(l_lo, l_hi, 4001)
+        err = form(B, e, l)
+        w = max(w, float(np.max(err / np.maximum(_sersic_exact(B, e, l), 0.125))))
+    return w
+
+
+def test_sersic_hardware_log2_error_model(orc):
+    """Why log2_r2_sersic takes the FP32 log2 of r2 only for n >= 1/2 and
+    log2 r2 >= -2: with every one-ulp error aligned, that form stays below
+    9e-7 of the local brightness (wherever it is above 1/8 of its value at
+    R_e), inside the exponent split's own worst case over the whole index
+    domain (below 1e-6, at n = 0.1); at n = 0.1 the FP32 form would reach
+    ~1.7e-6."""
+    fast = _worst_relative(orc, _sersic_fp32_log2, 0.5, -2.0)
+    split = _worst_relative(orc, _sersic_split_log2, 0.1, -40.0)
+    assert fast < 9e-7, fast
+    assert split < 1e-6, split
+    assert fast < split
+    assert _worst_relative(orc, _sersic_fp32_log2, 0.1, -2.0) > 1.2e-6
