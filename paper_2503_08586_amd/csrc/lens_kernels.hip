@@ -690,10 +690,11 @@ __device__ __forceinline__ double conv_tiles(const LensGeom &g, const uint16_t *
 // a_hi b_lo per tap (the dropped a_lo b_lo and both truncations are each below
 // 2^-22 of the tap's product).  A PSF row's window is CPR = L / 32 whole
 // K-chunks of one ring row, so the FP32 partial of each PSF row is flushed to
-// the FP64 output times the two scales, exactly (powers of two).  The A
-// operands stream from L2 two PSF rows ahead of their products (the operand
-// array holds two rows of padding), the B operands of a row are read from LDS
-// before its first product.  Same operand layout and output mapping as
+// the FP64 output times the two scales, exactly (powers of two).  A PSF
+// row's A operands are loaded from L2 and its B operands from LDS at the start
+// of the row (loading the next row's A during this row's products measured
+// slower: a wave per SIMD of registers with two tiles, or without the tiles'
+// shared A loads with one).  Same operand layout and output mapping as
 // conv_tiles.
 template <int NTL, int CPR>
 __device__ __forceinline__ double conv_tiles_f16(const LensGeom &g, const uint16_t *ring,
