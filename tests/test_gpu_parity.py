@@ -157,6 +157,9 @@ def test_mfma_operand_layout(ctx):
     say("case: matrix-core operand layout self-test, BF16 and FP16")
     assert ctx.selftest(0) == 0.0
     assert ctx.selftest(1) == 0.0
+    from paper_2503_08586_amd import binding
+    with pytest.raises(binding.LensError):
+        ctx.selftest(2)
 
 
 @pytest.mark.parametrize("mode", MODES, ids=[m[0] for m in MODES])

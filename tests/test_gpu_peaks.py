@@ -49,3 +49,11 @@ def test_matrix_core_products(rates):
     for name in ("mfma_f16", "mfma_bf16"):
         assert 0.9 <= rates[name] / bench.PEAK_BF16_FLOP_S <= 1.02, name
     assert 0 < rates["mfma_f16_fma_f64"] <= 1.05 * rates["fma_f64"]
+
+
+def test_unknown_instruction_kind():
+    from paper_2503_08586_amd import binding
+    with binding.LensContext(0) as ctx:
+        for op in (-1, len(binding.PEAK_OPS)):
+            with pytest.raises(binding.LensError):
+                binding.lens_peak_rate(ctx.ctx, op)
