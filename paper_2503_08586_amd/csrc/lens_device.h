@@ -47,6 +47,16 @@ __device__ __forceinline__ double rsq64(double x)
     return fma(0.5 * r, fma(-(x * r), r, 1.0), r);
 }
 
+// 1/psi from psi2 = psi^2 >= 0, and 0 at psi = 0: rsq_nr where psi2 lies in
+// FP32's normal range, else rsq64.  The test is wave-uniform and laid out
+// for its usual outcome (no lane of the wave at the mass centre), which then
+// runs without a taken branch; each lane's result is the same either way.
+__device__ __forceinline__ double rsq_psi(double psi2)
+{
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(!(psi2 >= 1e-30)) == 0, 1)) return rsq_nr(psi2);
+    return psi2 >= 1e-30 ? rsq_nr(psi2) : psi2 > 0.0 ? rsq64(psi2) : 0.0;
+}
+
 // a b + c as one VOP3 v_fma_f64 with c taken from an SGPR pair; c must be
 // wave-uniform (here: a polynomial coefficient).  Written out because the
 // compiler otherwise keeps FP64 coefficients in VGPRs and emits v_fmac_f64,
@@ -109,7 +119,7 @@ __device__ __forceinline__ double sie_a1(double u1, double ce, double bsie, doub
     const double t = ce * u1;
     const double z = fabs(t);
     const bool big = z > 1.0;
-    if (__builtin_amdgcn_ballot_w64(big)) {
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(big) != 0, 0)) {
         const double zi = big ? rcp_nr(z) : z;
         const double p = horner(kAtanOverT64, zi * zi);
         return big ? copysign(bsc * fma(-zi, p, kPi2), t) : bsie * u1 * p;
@@ -128,7 +138,7 @@ __device__ __forceinline__ double sie_a2(double u2, double ce, double bsie, doub
     if (z <= 0.9) {
         const bool red = z > 0.5;
         // the reduction on a wave-uniform branch, as in sie_a1
-        if (__builtin_amdgcn_ballot_w64(red)) {
+        if (__builtin_expect(__builtin_amdgcn_ballot_w64(red) != 0, 0)) {
             const double zr = red ? (z - 0.75) * rcp_nr(fma(-0.75, z, 1.0)) : z;
             const double p = horner(kAtanhOverT64, zr * zr);
             return red ? copysign(bsc * fma_c(zr, p, kAtanh075), t) : bsie * u2 * p;
@@ -168,8 +178,8 @@ __device__ __forceinline__ double log2_r2(double r2)
 // of a result of that size (1.2e-7 for |l| < 2, 2.4e-7 for |l| < 4) plus
 // 8.6e-8 from rounding r2 to FP32.  It reaches the brightness scaled by
 // ln2^2 B e t (t = 2^(e l)): with one-ulp errors of this log2 and of exp2_hw
-// aligned, at most 8.4e-7 of the local brightness wherever that is above 1/8
-// of its value at R_e, against 9.2e-7 for the exponent split over the whole
+// aligned, at most 8.8e-7 of the local brightness wherever that is above 1/8
+// of its value at R_e, against 1.1e-6 for the exponent split over the whole
 // index domain (whose worst case is at n = 0.1, where this form would reach
 // 1.7e-6: hence the gate on e).  A wave with a lane nearer a centre (where t
 // is small and the cusp steep, and where r2 = 0 gives -inf) takes log2_r2.
@@ -177,19 +187,31 @@ __device__ __forceinline__ double log2_r2(double r2)
 // fmax in sersic_lg, 2^-2000 = 0, as log2_r2's large finite value does.
 // thr (uniform): -2 where the FP32 form is allowed, +inf where it is not (a
 // threshold rather than a flag keeps the sub-pixel loop's code the same).
+// The test is laid out for the FP32 form, which then runs without a taken
+// branch (most waves take it; two taken branches per Sersic cost 2%).
 __device__ __forceinline__ double log2_r2_sersic(double r2, float thr)
 {
     const float l = hw_log2((float)r2);
-    if (__builtin_amdgcn_ballot_w64(!(l >= thr))) return log2_r2(r2);
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(!(l >= thr)) != 0, 0)) return log2_r2(r2);
     return (double)l;
 }
 
-// 2^y for y in [-2000, 1023]: 2^round(y) times the FP32 hardware 2^f of the
-// remainder f in [-1/2, 1/2] (relative error ~1 ulp of FP32; f itself is
-// rounded to FP32, 2^-25 absolute).  For the brightness 2^(B (1 - t)), whose
-// relative error is that of this function alone: nothing amplifies it.
+// 2^y for y in [-2000, 1023], for the brightness 2^(B (1 - t)), whose
+// relative error is that of this function alone: nothing amplifies it.  The
+// FP32 hardware 2^x is good to about one FP32 ulp of its result.
+// - Where every lane of the wave has y <= 2, it is that 2^x of y rounded to
+//   FP32.  The rounding adds at most ln2 2^-24 = 4.1e-8 relative for y in
+//   [-2, 2], 8.3e-8 down to y = -4 (a sixteenth of the brightness at R_e),
+//   and grows with |y| below, where the brightness shrinks faster.  Below
+//   y = -126 the result is an FP32 subnormal or 0, under 1.2e-38 of the
+//   brightness at R_e.
+// - Otherwise it is 2^round(y) times the 2^x of the remainder f in
+//   [-1/2, 1/2] (f rounded to FP32: 1e-8 relative), as the centre of a steep
+//   profile needs: there y reaches B, up to 57 at n = 20.
+// The test is laid out for the first form, the common one.
 __device__ __forceinline__ double exp2_hw(double y)
 {
+    if (__builtin_expect(__builtin_amdgcn_ballot_w64(!(y <= 2.0)) == 0, 1)) return (double)__builtin_amdgcn_exp2f((float)y);
     const double k = rint(y);
     return ldexp((double)__builtin_amdgcn_exp2f((float)(y - k)), (int)k);
 }
@@ -224,9 +246,7 @@ __device__ __forceinline__ void ray_trace(double x1, double x2, double u1, doubl
                                           double &w1, double &w2)
 {
     const double psi2 = fma(P.q2m, x1 * x1, x2 * x2);
-    double ir;
-    if (psi2 >= 1e-30) ir = rsq_nr(psi2);
-    else ir = psi2 > 0.0 ? rsq64(psi2) : 0.0;
+    const double ir = rsq_psi(psi2);
     const double a1 = sie_a1(x1 * ir, P.ce, P.bsie, P.bsc);
     const double a2 = sie_a2(x2 * ir, P.ce, P.bsie, P.bsc);
     w1 = u1 - a1;
@@ -295,9 +315,7 @@ __device__ __forceinline__ void ray_trace_tab(double x1, double x2, double u1, d
                                               double qn, double &w1, double &w2)
 {
     const double psi2 = fma(P.q2m, x1 * x1, x2 * x2);
-    double ir;
-    if (psi2 >= 1e-30) ir = rsq_nr(psi2);
-    else ir = psi2 > 0.0 ? rsq64(psi2) : 0.0;
+    const double ir = rsq_psi(psi2);
     const double s1 = x1 * ir, s2 = x2 * ir;
     const double un = fabs(s1) * qn;   // u kSieIntervals
     const int j = min((int)un, kSieIntervals - 1);
