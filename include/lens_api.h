@@ -43,7 +43,8 @@
  * gamma in [1.05, 2.95].
  *
  * Arithmetic: the ray trace and the Sersic exponents in FP64 (FP32 hardware
- * seeds refined by Newton steps, FP32 log2), the binned image rounded to FP32
+ * seeds refined by Newton steps; the FP32 hardware log2 and 2^x where their
+ * error is not amplified), the binned image rounded to FP32
  * once, the PSF convolution in FP32 on the vector ALU (LENS_PREC_FP32) or as a
  * half-precision matrix-core contraction with FP32 accumulation flushed to FP64
  * (the other precisions), the chi-square reduction and the result in FP64.
