@@ -54,7 +54,11 @@ __device__ __forceinline__ double rsq64(double x)
 __device__ __forceinline__ double rsq_psi(double psi2)
 {
     if (__builtin_expect(__builtin_amdgcn_ballot_w64(!(psi2 >= 1e-30)) == 0, 1)) return rsq_nr(psi2);
-    return psi2 >= 1e-30 ? rsq_nr(psi2) : psi2 > 0.0 ? rsq64(psi2) : 0.0;
+    // a copy the compiler cannot see through, so that this path's per-lane
+    // test stays inside it instead of being computed on the common path too
+    double p = psi2;
+    asm volatile("" : "+v"(p));
+    return p >= 1e-30 ? rsq_nr(p) : p > 0.0 ? rsq64(p) : 0.0;
 }
 
 // a b + c as one VOP3 v_fma_f64 with c taken from an SGPR pair; c must be
@@ -164,7 +168,7 @@ __device__ __forceinline__ double sie_a2(double u2, double ce, double bsie, doub
 // steep Sersic centre, and the exponent carries that error into the
 // brightness.)  The mantissa's log2 is clamped below at -2048, so the centre
 // (r2 = 0) gives t = 2^-(2048 e) ~ 0 rather than NaN; a radius whose t
-// overflows gives B (1 - t) = -inf, clamped to -2000 (2^-2000 is 0 in FP64).
+// overflows gives B (1 - t) = -inf, whose power of two exp2_hw makes 0.
 // lead: the leading coefficient of kExp2_64 (see horner).
 __device__ __forceinline__ double log2_r2(double r2)
 {
@@ -184,7 +188,7 @@ __device__ __forceinline__ double log2_r2(double r2)
 // 1.7e-6: hence the gate on e).  A wave with a lane nearer a centre (where t
 // is small and the cusp steep, and where r2 = 0 gives -inf) takes log2_r2.
 // A radius whose FP32 value overflows gives l = +inf, t = NaN and, through
-// fmax in sersic_lg, 2^-2000 = 0, as log2_r2's large finite value does.
+// exp2_hw, 0, as log2_r2's large finite value does.
 // thr (uniform): -2 where the FP32 form is allowed, +inf where it is not (a
 // threshold rather than a flag keeps the sub-pixel loop's code the same).
 // The test is laid out for the FP32 form, which then runs without a taken
@@ -196,7 +200,7 @@ __device__ __forceinline__ double log2_r2_sersic(double r2, float thr)
     return (double)l;
 }
 
-// 2^y for y in [-2000, 1023], for the brightness 2^(B (1 - t)), whose
+// 2^y for y <= 1023, -inf and NaN included, for the brightness 2^(B (1 - t)), whose
 // relative error is that of this function alone: nothing amplifies it.  The
 // FP32 hardware 2^x is good to about one FP32 ulp of its result.
 // - Where every lane of the wave has y <= 2, it is that 2^x of y rounded to
@@ -204,14 +208,17 @@ __device__ __forceinline__ double log2_r2_sersic(double r2, float thr)
 //   [-2, 2], 8.3e-8 down to y = -4 (a sixteenth of the brightness at R_e),
 //   and grows with |y| below, where the brightness shrinks faster.  Below
 //   y = -126 the result is an FP32 subnormal or 0, under 1.2e-38 of the
-//   brightness at R_e.
+//   brightness at R_e, and -inf gives 0.
 // - Otherwise it is 2^round(y) times the 2^x of the remainder f in
 //   [-1/2, 1/2] (f rounded to FP32: 1e-8 relative), as the centre of a steep
-//   profile needs: there y reaches B, up to 57 at n = 20.
+//   profile needs: there y reaches B, up to 57 at n = 20.  Here y is first
+//   raised to -2000 (2^-2000 is 0 in FP64), which also maps NaN to 0: a NaN
+//   lane fails the test above and lands here.
 // The test is laid out for the first form, the common one.
 __device__ __forceinline__ double exp2_hw(double y)
 {
     if (__builtin_expect(__builtin_amdgcn_ballot_w64(!(y <= 2.0)) == 0, 1)) return (double)__builtin_amdgcn_exp2f((float)y);
+    y = fmax(y, -2000.0);
     const double k = rint(y);
     return ldexp((double)__builtin_amdgcn_exp2f((float)(y - k)), (int)k);
 }
@@ -222,7 +229,7 @@ __device__ __forceinline__ double exp2_hw(double y)
 __device__ __forceinline__ double sersic_lg(double lgd, double e, double B, double lead)
 {
     const double t = exp2_64(kExp2_64, e * lgd, lead);
-    return exp2_hw(fmax(fma(-B, t, B), -2000.0));
+    return exp2_hw(fma(-B, t, B));
 }
 
 
@@ -318,8 +325,10 @@ __device__ __forceinline__ void ray_trace_tab(double x1, double x2, double u1, d
     const double ir = rsq_psi(psi2);
     const double s1 = x1 * ir, s2 = x2 * ir;
     const double un = fabs(s1) * qn;   // u kSieIntervals
-    const int j = min((int)un, kSieIntervals - 1);
-    const double *e = sie_table() + j * kSieEntry;
+    // the entry's byte offset by a 24-bit multiply (full rate; j <= 31)
+    const unsigned j = min((unsigned)un, (unsigned)(kSieIntervals - 1));
+    const double *e = reinterpret_cast<const double *>(reinterpret_cast<const char *>(sie_table()) +
+                                                       __umul24(j, (unsigned)(kSieEntry * sizeof(double))));
     const double t = un - e[0];
     double h1 = e[kSieDeg + 1];
 #pragma unroll
