@@ -216,7 +216,10 @@ def test_special_proposals(ctx):
     good = [mod(q_m=1.0), mod(q_l=1.0, q_s=1.0), mod(theta_E=0.0), mod(g1=0.0, g2=0.0),
             mod(I_l=0.0), mod(I_s=0.0), mod(n_l=0.1, n_s=20.0), mod(n_l=20.0, n_s=0.1),
             mod(q_m=0.999999), mod(q_m=0.05), mod(x_m=0.0, y_m=0.0), mod(x_s=0.0, y_s=0.0, q_s=1.0),
-            mod(R_s=1e-3), mod(R_l=30.0), mod(theta_E=3.0, q_m=0.3), mod(g1=0.3, g2=-0.3)]
+            mod(R_s=1e-3), mod(R_l=30.0), mod(theta_E=3.0, q_m=0.3), mod(g1=0.3, g2=-0.3),
+            # (R/R_e)^2 beyond FP32's range: an infinite FP32 log2, a NaN
+            # exponent, and a brightness of 0 (the oracle's FP64 gives 0 too)
+            mod(R_s=1e-20), mod(R_l=1e-20)]
     bad = [mod(theta_E=-1e-9), mod(q_m=0.0), mod(q_l=1.0000001), mod(q_s=-0.2), mod(R_l=0.0),
            mod(R_s=-1.0), mod(n_l=0.0999), mod(n_s=20.01), mod(x_s=math.nan), mod(g2=math.inf),
            mod(I_l=-math.inf)]
